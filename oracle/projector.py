@@ -1,0 +1,92 @@
+"""Forward projector A and its transpose (Sec. 2.1, the system matrix A = {a_ij}).
+
+The paper only states that b holds uniform samples of parallel-beam line
+integrals.  This oracle reads A as Joseph's ray-driven model:
+
+* a view whose rays are closer to vertical (|cos theta| >= |sin theta|) steps
+  over the N image rows; at row centre y the ray ``x cos + y sin = r`` crosses
+  ``x = (r - y sin)/cos``; the image is linearly interpolated along that row
+  between its two neighbouring pixel centres, and the step contributes that
+  value times the path length per row, 1/|cos theta|;
+* the other views do the same over columns with weight 1/|sin theta|;
+* interpolation partners outside the image are zero.
+
+The transpose is computed as the literal scatter of those same weights
+(``np.add.at``), i.e. as A^T by definition, not by a separate formula.
+"""
+import numpy as np
+
+from .geometry import angles, row_branch, pixel_centres, bin_centres
+
+
+def _view_samples(n, nb, theta, rowflag):
+    """Fractional interpolation coordinate s[t, u] for step t, ray u, and the
+    per-step path length.  For row views t is the row index and s an x index;
+    for column views t is the column index and s a y index."""
+    c = pixel_centres(n)
+    r = bin_centres(nb)
+    cs, sn = np.cos(theta), np.sin(theta)
+    if rowflag:
+        s = (r[None, :] - c[:, None] * sn) / cs + (n - 1) / 2.0
+        length = 1.0 / abs(cs)
+    else:
+        s = (r[None, :] - c[:, None] * cs) / sn + (n - 1) / 2.0
+        length = 1.0 / abs(sn)
+    return s, length
+
+
+def _pick(plane, t, k):
+    """plane[t, k] with zero outside 0 <= k < n."""
+    n = plane.shape[1]
+    ok = (k >= 0) & (k < n)
+    return np.where(ok, plane[t, np.clip(k, 0, n - 1)], 0.0)
+
+
+def forward_project(x, m, nb):
+    """y = A x, y[v, u] = sum over steps of the interpolated image times the step length."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.shape[0]
+    assert x.shape == (n, n)
+    th = angles(m)
+    rows = row_branch(m)
+    y = np.zeros((m, nb))
+    t = np.arange(n)[:, None]
+    for v in range(m):
+        s, length = _view_samples(n, nb, th[v], rows[v])
+        plane = x if rows[v] else x.T
+        k = np.floor(s).astype(np.int64)
+        f = s - k
+        val = (1.0 - f) * _pick(plane, t, k) + f * _pick(plane, t, k + 1)
+        y[v] = length * val.sum(axis=0)
+    return y
+
+
+def back_project(y, n):
+    """x = A^T y: every weight of ``forward_project`` scattered back onto its pixel."""
+    y = np.asarray(y, dtype=np.float64)
+    m, nb = y.shape
+    th = angles(m)
+    rows = row_branch(m)
+    acc_rows = np.zeros((n, n))   # indexed [iy, ix]
+    acc_cols = np.zeros((n, n))   # indexed [ix, iy]
+    t = np.broadcast_to(np.arange(n)[:, None], (n, nb))
+    for v in range(m):
+        s, length = _view_samples(n, nb, th[v], rows[v])
+        k = np.floor(s).astype(np.int64)
+        f = s - k
+        acc = acc_rows if rows[v] else acc_cols
+        yv = np.broadcast_to(y[v][None, :], (n, nb))
+        for kk, wt in ((k, 1.0 - f), (k + 1, f)):
+            ok = (kk >= 0) & (kk < n)
+            np.add.at(acc, (t[ok], kk[ok]), length * wt[ok] * yv[ok])
+    return acc_rows + acc_cols.T
+
+
+def dense_matrix(n, m, nb):
+    """Dense I x J matrix of A, built column by column as A e_j (small n only)."""
+    a = np.zeros((m * nb, n * n))
+    for j in range(n * n):
+        e = np.zeros(n * n)
+        e[j] = 1.0
+        a[:, j] = forward_project(e.reshape(n, n), m, nb).ravel()
+    return a
