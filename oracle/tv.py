@@ -30,14 +30,19 @@ def grad(x):
 
 
 def div(p1, p2):
-    """Negative adjoint of ``grad``: <grad x, p> = -<x, div p>."""
-    d = np.zeros_like(p1)
-    d[:, 0] += p1[:, 0]
-    d[:, 1:-1] += p1[:, 1:-1] - p1[:, :-2]
-    d[:, -1] += -p1[:, -2]
-    d[0, :] += p2[0, :]
-    d[1:-1, :] += p2[1:-1, :] - p2[:-2, :]
-    d[-1, :] += -p2[-2, :]
+    """Negative adjoint of ``grad``: <grad x, p> = -<x, div p>.
+
+    The last column of p1 and the last row of p2 pair with differences that are
+    identically zero and so never enter; with that, (div p)[i, j] =
+    p1[i, j] - p1[i, j-1] + p2[i, j] - p2[i-1, j] with out-of-range terms zero.
+    """
+    q1 = p1.copy()
+    q1[:, -1] = 0.0
+    q2 = p2.copy()
+    q2[-1, :] = 0.0
+    d = q1 + q2
+    d[:, 1:] -= q1[:, :-1]
+    d[1:, :] -= q2[:-1, :]
     return d
 
 

@@ -33,15 +33,27 @@ def test_tv_of_constant_and_border_pixel():
 
 def test_div_is_negative_adjoint_of_grad():
     rng = np.random.default_rng(0)
-    for shape in ((7, 7), (12, 12), (2, 2)):
+    for shape in ((7, 7), (12, 12), (2, 2), (1, 1)):
         x = rng.standard_normal(shape)
         p1, p2 = rng.standard_normal(shape), rng.standard_normal(shape)
-        p1[:, -1] = 0.0
-        p2[-1, :] = 0.0
         g1, g2 = T.grad(x)
         lhs = float((g1 * p1).sum() + (g2 * p2).sum())
         rhs = -float((x * T.div(p1, p2)).sum())
         assert abs(lhs - rhs) <= 1e-13 * (1 + abs(lhs))
+
+
+def test_div_matches_chambolle_boundary_rule():
+    # Chambolle (2004): (div p)_ij = p1_ij - p1_i,j-1 inside, p1_ij on the first
+    # column, -p1_i,j-1 on the last; likewise for p2 down the rows.
+    rng = np.random.default_rng(6)
+    n = 6
+    p1, p2 = rng.standard_normal((n, n)), rng.standard_normal((n, n))
+    d = T.div(p1, p2)
+    for i in range(n):
+        for j in range(n):
+            a = p1[i, j] if j == 0 else (-p1[i, j - 1] if j == n - 1 else p1[i, j] - p1[i, j - 1])
+            b = p2[i, j] if i == 0 else (-p2[i - 1, j] if i == n - 1 else p2[i, j] - p2[i - 1, j])
+            assert d[i, j] == pytest.approx(a + b, abs=1e-15)
 
 
 def test_prox_with_zero_weight_is_clamp():
