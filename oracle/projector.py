@@ -11,8 +11,8 @@ integrals.  This oracle reads A as Joseph's ray-driven model:
 * the other views do the same over columns with weight 1/|sin theta|;
 * interpolation partners outside the image are zero.
 
-The transpose is computed as the literal scatter of those same weights
-(``np.add.at``), i.e. as A^T by definition, not by a separate formula.
+The transpose is computed as the literal scatter-add of those same weights
+(``np.bincount``), i.e. as A^T by definition, not by a separate formula.
 """
 import numpy as np
 
@@ -42,44 +42,56 @@ def _pick(plane, t, k):
     return np.where(ok, plane[t, np.clip(k, 0, n - 1)], 0.0)
 
 
-def forward_project(x, m, nb):
-    """y = A x, y[v, u] = sum over steps of the interpolated image times the step length."""
+def forward_project(x, m, nb, views=None):
+    """y = A x, y[v, u] = sum over steps of the interpolated image times the step length.
+
+    ``views`` (optional) restricts the output to those view indices of the
+    m-view scan, in that order (rows of the returned array).
+    """
     x = np.asarray(x, dtype=np.float64)
     n = x.shape[0]
     assert x.shape == (n, n)
     th = angles(m)
     rows = row_branch(m)
-    y = np.zeros((m, nb))
+    views = range(m) if views is None else list(views)
+    y = np.zeros((len(views), nb))
     t = np.arange(n)[:, None]
-    for v in range(m):
+    for i, v in enumerate(views):
         s, length = _view_samples(n, nb, th[v], rows[v])
         plane = x if rows[v] else x.T
         k = np.floor(s).astype(np.int64)
         f = s - k
         val = (1.0 - f) * _pick(plane, t, k) + f * _pick(plane, t, k + 1)
-        y[v] = length * val.sum(axis=0)
+        y[i] = length * val.sum(axis=0)
     return y
 
 
-def back_project(y, n):
-    """x = A^T y: every weight of ``forward_project`` scattered back onto its pixel."""
+def back_project(y, n, m=None, views=None):
+    """x = A^T y: every weight of ``forward_project`` scattered back onto its pixel.
+
+    By default y holds all m = y.shape[0] views; with ``m`` and ``views`` given,
+    row i of y is view ``views[i]`` of the m-view scan and the others are zero.
+    """
     y = np.asarray(y, dtype=np.float64)
-    m, nb = y.shape
+    nb = y.shape[1]
+    if views is None:
+        m = y.shape[0]
+        views = range(m)
     th = angles(m)
     rows = row_branch(m)
-    acc_rows = np.zeros((n, n))   # indexed [iy, ix]
-    acc_cols = np.zeros((n, n))   # indexed [ix, iy]
+    acc_rows = np.zeros(n * n)   # indexed [iy, ix]
+    acc_cols = np.zeros(n * n)   # indexed [ix, iy]
     t = np.broadcast_to(np.arange(n)[:, None], (n, nb))
-    for v in range(m):
+    for i, v in enumerate(views):
         s, length = _view_samples(n, nb, th[v], rows[v])
         k = np.floor(s).astype(np.int64)
         f = s - k
         acc = acc_rows if rows[v] else acc_cols
-        yv = np.broadcast_to(y[v][None, :], (n, nb))
+        yv = np.broadcast_to(y[i][None, :], (n, nb))
         for kk, wt in ((k, 1.0 - f), (k + 1, f)):
             ok = (kk >= 0) & (kk < n)
-            np.add.at(acc, (t[ok], kk[ok]), length * wt[ok] * yv[ok])
-    return acc_rows + acc_cols.T
+            acc += np.bincount(t[ok] * n + kk[ok], weights=length * wt[ok] * yv[ok], minlength=n * n)
+    return acc_rows.reshape(n, n) + acc_cols.reshape(n, n).T
 
 
 def dense_matrix(n, m, nb):
