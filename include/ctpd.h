@@ -1,0 +1,147 @@
+/*
+ * ctpd.h -- C ABI of libctpd: FBP-preconditioned primal-dual (APP) TV
+ * reconstruction for parallel-beam CT on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Kudo, Yamazaki, Nemoto, Takaki, "A very fast iterative algorithm
+ * for TV-regularized image reconstruction with applications to low-dose and
+ * few-view CT" (arXiv 1609.06041).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - Image x: n x n float32, row-major x[iy*n + ix], unit pixels, pixel
+ *    centre (ix - (n-1)/2, iy - (n-1)/2).
+ *  - Sinogram: view-major float32 [n_views][n_bins]; view v is at angle
+ *    theta_v = v*pi/n_views (uniform over [0, pi)), bin u at signed distance
+ *    r_u = u - (n_bins-1)/2; the ray of (v, u) is x cos + y sin = r_u.
+ *  - A is Joseph's ray-driven projector: views with |cos| >= |sin| (decided
+ *    from the view index: 4v <= m or 4v >= 3m) step over rows and linearly
+ *    interpolate along x with step length 1/|cos|, the others step over
+ *    columns with 1/|sin|; pixels outside the image are zero.
+ *  - Every array argument is a DEVICE pointer to a densely packed buffer the
+ *    caller allocates and owns, unless marked "host".  Inputs are never
+ *    modified.  Outputs must not alias inputs.
+ *  - Work is queued on the hipStream_t given to ctpd_op_create, in stream
+ *    order.  project / backproject / ramp_filter / tv_prox return without
+ *    waiting; the solvers wait for their own results before returning.
+ *  - Return value: CTPD_OK (0) or a negative error code.  On an argument
+ *    error nothing is launched and no output is written.  ctpd_strerror
+ *    gives a message (for CTPD_EHIP it includes the HIP error of the last
+ *    failure on the calling thread).
+ *  - An op is not thread-safe: calls on one op must not overlap.
+ */
+#ifndef CTPD_H
+#define CTPD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CTPD_OK 0
+#define CTPD_EINVAL (-1)   /* bad argument: null pointer, size, step size, ... */
+#define CTPD_EDOMAIN (-2)  /* data outside the model: w_i <= 0 or non-finite b, w */
+#define CTPD_EHIP (-3)     /* a HIP runtime call failed */
+#define CTPD_ENOMEM (-4)   /* device allocation failed */
+
+/* Maximum n_bins: the filter keeps all 2*n_bins-1 taps in LDS. */
+#define CTPD_MAX_BINS 4096
+
+typedef struct ctpd_op ctpd_op;
+
+/* Scan geometry (Sec. 2.1: parallel-beam, m views over [0, pi)). */
+typedef struct {
+    int32_t n;        /* image side, 1 <= n <= 16384 */
+    int32_t n_views;  /* m >= 1 */
+    int32_t n_bins;   /* 1 <= n_bins <= CTPD_MAX_BINS */
+} ctpd_geometry;
+
+/* Solver knobs.  A zero / negative value selects the default. */
+typedef struct {
+    double tau;          /* primal step; default: low-dose pi*kappa/(2m), few-view
+                            mean|sigma A^T D(1) b| */
+    double sigma;        /* dual step; default: rho times the bound of Eq. 16 /
+                            Algorithm 1 / Algorithm 2 from the operator norms */
+    double tv_step;      /* tau_c of the TV dual iteration, default 1/8 */
+    double safety;       /* rho < 1, default 0.95 */
+    int32_t tv_iters;    /* inner TV steps per outer iteration, default 10 */
+    int32_t norm_steps;  /* max Lanczos steps per operator norm, default 100 */
+    int32_t record_cost; /* 1: fill ctpd_report.cost (Eq. 1 cost, or psi for few-view) */
+    int32_t reserved;
+} ctpd_params;
+
+/* Solver report (host struct filled by the solvers). */
+typedef struct {
+    double tau, sigma;   /* step sizes used */
+    double kappa;        /* mean of diag(W^-1) (low-dose) */
+    double lambda_a;     /* lambda_max(A^T D A) = ||D^1/2 A A^T D^T/2|| at the tau used */
+    double lambda_h;     /* lambda_max(W^-1/2 D W^-1/2) = ||D^1/2 W^-1 D^T/2|| (low-dose) */
+    int32_t norm_steps_a, norm_steps_h;  /* Lanczos steps taken */
+    int32_t iters_done;
+    int32_t reserved;
+    double setup_ms;     /* host wall time of the set-up (norms, taps, defaults) */
+    double loop_ms;      /* host wall time of the iterations */
+    double* cost;        /* host, length >= iters, or NULL */
+    float* mu_out;       /* device [n_views][n_bins] receives mu^K, or NULL */
+    float* p_out;        /* device [2][n][n] receives the TV dual field, or NULL */
+} ctpd_report;
+
+/* Create an operator for geometry *g bound to stream (a hipStream_t; NULL =
+ * the null stream) on the current HIP device.  Allocates the geometry tables
+ * and all iteration workspaces once.  *out receives the handle. */
+int ctpd_op_create(const ctpd_geometry* g, void* stream, ctpd_op** out);
+
+/* Release the op and its device memory (waits for its stream).  NULL is a no-op. */
+void ctpd_op_destroy(ctpd_op* op);
+
+/* y = A x (Sec. 2.1 system matrix; Eqs. 18-20 forward projection).
+ * x: [n][n], y: [n_views][n_bins]. */
+int ctpd_project(ctpd_op* op, const float* x, float* y);
+
+/* x = A^T y, the exact transpose of ctpd_project (Eqs. 19, 30 backprojection).
+ * y: [n_views][n_bins], x: [n][n]. */
+int ctpd_backproject(ctpd_op* op, const float* y, float* x);
+
+/* out = D s, the preconditioner of Eq. 24 (kappa > 0, smoothed ramp
+ * H = |w|/(2 m tau + kappa |w|)) or Eq. 32 (kappa == 0, ramp H = |w|/(2 m tau)),
+ * applied to every view as the linear convolution with the inverse DTFT of H
+ * band-limited to [-pi, pi] rad/bin.  tau > 0, kappa >= 0.
+ * s, out: [n_views][n_bins]. */
+int ctpd_ramp_filter(ctpd_op* op, double tau, double kappa, const float* s, float* out);
+
+/* The 2*n_bins-1 filter taps h[k - (n_bins-1)], k = 0..2n_bins-2, of
+ * ctpd_ramp_filter in float64, copied to the host array taps_host (blocks). */
+int ctpd_filter_taps(ctpd_op* op, double tau, double kappa, double* taps_host);
+
+/* TV prox with non-negativity (Eq. 17): approximately
+ *   x = argmin_{x >= 0} lambda psi(x) + 1/2 ||x - z||^2,  psi of Eq. 2,
+ * by n_iter projected-gradient steps of size tv_step/lambda on the dual field
+ * p, warm-started from p_inout (updated in place), then x = max(0, z - lambda div p).
+ * lambda == 0 gives x = max(0, z).  z, x: [n][n]; p_inout: [2][n][n]
+ * (horizontal then vertical component, |p_j| <= 1). */
+int ctpd_tv_prox(ctpd_op* op, const float* z, double lambda, int32_t n_iter, double tv_step,
+                 float* p_inout, float* x);
+
+/* Low-dose P-WLS TV reconstruction (Eq. 1), Algorithm 1 (beta > 0) or
+ * Algorithm 1' (beta == 0): iters APP iterations (Eqs. 18-20) from x = 0,
+ * mu = 0 with the smoothed-ramp preconditioner of Eq. 24.
+ * b: [n_views][n_bins] log data; w: [n_views][n_bins] weights w_i = 1/var_i > 0;
+ * x_out: [n][n].  p may be NULL (defaults); rep may be NULL.
+ * Synchronises the op's stream before returning. */
+int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double beta, int32_t iters,
+                          const ctpd_params* p, float* x_out, ctpd_report* rep);
+
+/* Few-view reconstruction min psi(x) s.t. Ax = b, x >= 0 (Eq. 25),
+ * Algorithm 2: iters APP iterations (Eqs. 29-31) with the ramp of Eq. 32.
+ * Arguments as for ctpd_pd_lowdose_solve without w and beta. */
+int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd_params* p,
+                          float* x_out, ctpd_report* rep);
+
+/* Static message for an error code. */
+const char* ctpd_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTPD_H */

@@ -1,0 +1,662 @@
+// C ABI of libctpd: operator handle, single operators, and the two APP
+// solvers (Algorithm 1 / 1' for low-dose data, Algorithm 2 for few-view
+// data).  The host code here validates arguments, sets up the geometry and
+// step sizes, and queues kernels; every array operation runs on the GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+using namespace ctpd;
+
+struct ctpd_op {
+    int n = 0, m = 0, nb = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    size_t J = 0, I = 0;   // image / sinogram sizes
+    ViewGeom* views = nullptr;
+    // float32 iteration state
+    float* xT = nullptr;
+    float* x = nullptr;
+    float* z = nullptr;
+    float* p[2] = {nullptr, nullptr};
+    float* mu[3] = {nullptr, nullptr, nullptr};
+    float* mubar = nullptr;
+    float* q = nullptr;
+    float* winv = nullptr;
+    // filter taps for (tap_tau, tap_kappa)
+    double* taps64 = nullptr;
+    float* taps32 = nullptr;
+    double tap_tau = -1.0, tap_kappa = -1.0;
+    // reductions
+    double* partials = nullptr;
+    double* red = nullptr;        // device, 3 * kRedSlots doubles
+    double* red_host = nullptr;   // pinned host mirror
+    // float64 workspaces for the operator norms (allocated on first use)
+    double* img64[4] = {nullptr, nullptr, nullptr, nullptr};
+    double* sino64[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // per-iteration monitor values (device), 2 * cost_cap slots of 3 doubles
+    double* cost_dev = nullptr;
+    int cost_cap = 0;
+};
+
+namespace {
+
+constexpr int kRedSlots = 8;
+thread_local char g_errmsg[512] = "";
+
+int fail_hip(hipError_t e, const char* what) {
+    snprintf(g_errmsg, sizeof g_errmsg, "%s: %s", what, hipGetErrorString(e));
+    return CTPD_EHIP;
+}
+
+#define HIP_TRY(expr)                                         \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) return fail_hip(_e, #expr);     \
+    } while (0)
+
+int alloc_dev(void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+    if (e == hipErrorOutOfMemory) {
+        snprintf(g_errmsg, sizeof g_errmsg, "hipMalloc(%zu bytes): out of memory", bytes);
+        return CTPD_ENOMEM;
+    }
+    if (e != hipSuccess) return fail_hip(e, "hipMalloc");
+    return CTPD_OK;
+}
+
+#define ALLOC(ptr, count)                                                          \
+    do {                                                                           \
+        int _r = alloc_dev((void**)&(ptr), sizeof(*(ptr)) * (size_t)(count));      \
+        if (_r != CTPD_OK) return _r;                                              \
+    } while (0)
+
+int einval(const char* msg) {
+    snprintf(g_errmsg, sizeof g_errmsg, "invalid argument: %s", msg);
+    return CTPD_EINVAL;
+}
+
+// Per-view geometry in float64 (see ViewGeom).
+std::vector<ViewGeom> make_views(int n, int m, int nb) {
+    std::vector<ViewGeom> out(m);
+    const double c = 0.5 * (n - 1), cd = 0.5 * (nb - 1);
+    for (int v = 0; v < m; ++v) {
+        const double th = (double)v * M_PI / (double)m;
+        const double cs = std::cos(th), sn = std::sin(th);
+        ViewGeom g{};
+        g.row = (4 * v <= m || 4 * v >= 3 * m) ? 1 : 0;
+        g.cs = cs;
+        g.sn = sn;
+        // row views:    s = (r_u - Y_t sin)/cos + c,  column views: s = (r_u - X_t cos)/sin + c
+        const double a = g.row ? cs : sn, o = g.row ? sn : cs;
+        g.su = 1.0 / a;
+        g.st = -o / a;
+        g.s0 = (c * o - cd) / a + c;
+        g.len = 1.0 / std::fabs(a);
+        g.len2 = g.len * g.len;
+        out[v] = g;
+    }
+    return out;
+}
+
+int sync(ctpd_op* op) {
+    HIP_TRY(hipStreamSynchronize(op->stream));
+    return CTPD_OK;
+}
+
+int ensure_taps(ctpd_op* op, double tau, double kappa) {
+    if (op->tap_tau == tau && op->tap_kappa == kappa) return CTPD_OK;
+    HIP_TRY(launch_taps(op->taps64, op->taps32, op->nb, op->m, tau, kappa, op->stream));
+    op->tap_tau = tau;
+    op->tap_kappa = kappa;
+    return CTPD_OK;
+}
+
+int ensure_f64(ctpd_op* op) {
+    if (op->img64[0]) return CTPD_OK;
+    for (auto& p : op->img64) ALLOC(p, op->J);
+    for (auto& p : op->sino64) ALLOC(p, op->I);
+    return CTPD_OK;
+}
+
+// Reduction into slot `slot` of op->red (device); read back with read_red.
+int reduce(ctpd_op* op, int kind, const void* a, const void* b, const void* c, size_t len, int slot) {
+    HIP_TRY(launch_reduce(kind, a, b, c, len, op->partials, op->red + 3 * slot, op->stream));
+    return CTPD_OK;
+}
+
+int read_red(ctpd_op* op) {
+    HIP_TRY(hipMemcpyAsync(op->red_host, op->red, sizeof(double) * 3 * kRedSlots, hipMemcpyDeviceToHost,
+                           op->stream));
+    return sync(op);
+}
+
+// Largest eigenvalue of the symmetric operator M (float64) by the Lanczos
+// recurrence without reorthogonalisation: for the extreme eigenvalue the
+// Ritz value converges even after orthogonality is lost (at worst copies of
+// it appear).  Stops when the top Ritz value changes by <= 1e-10 relative.
+double tridiag_max(const std::vector<double>& a, const std::vector<double>& b) {
+    // a: diagonal (k), b: off-diagonal (k-1).  Sturm-sequence bisection.
+    const int k = (int)a.size();
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < k - 1 ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    auto count_below = [&](double x) {
+        int cnt = 0;
+        double d = 1.0;
+        for (int i = 0; i < k; ++i) {
+            d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+            if (d == 0.0) d = -1e-300;
+            if (d < 0.0) ++cnt;
+        }
+        return cnt;
+    };
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (count_below(mid) == k) hi = mid;
+        else lo = mid;
+    }
+    return hi;
+}
+
+template <class Apply>
+int lanczos_max(ctpd_op* op, double* q, double* qp, double* w, size_t len, uint64_t seed, int kmax, Apply apply,
+                double* lam_out, int* steps_out) {
+    HIP_TRY(launch_start_vector(q, len, seed, op->stream));
+    int r = reduce(op, RED_DOT_F64, q, q, nullptr, len, 0);
+    if (r) return r;
+    if ((r = read_red(op))) return r;
+    HIP_TRY(launch_scale_f64(q, q, 1.0 / std::sqrt(op->red_host[0]), len, op->stream));
+    std::vector<double> al, be;
+    double beta = 0.0, theta = 0.0, theta_prev = 0.0;
+    int steps = 0;
+    for (int j = 0; j < kmax; ++j) {
+        if ((r = apply(q, w))) return r;
+        if ((r = reduce(op, RED_DOT_F64, q, w, nullptr, len, 0))) return r;
+        if ((r = read_red(op))) return r;
+        const double alpha = op->red_host[0];
+        // w = w - alpha q - beta qp
+        HIP_TRY(launch_axpby_f64(w, q, -alpha, 1.0, j ? qp : nullptr, -beta, len, op->stream));
+        if ((r = reduce(op, RED_DOT_F64, w, w, nullptr, len, 0))) return r;
+        if ((r = read_red(op))) return r;
+        const double bn = std::sqrt(std::max(op->red_host[0], 0.0));
+        al.push_back(alpha);
+        theta = tridiag_max(al, be);
+        steps = j + 1;
+        if (j > 0 && std::fabs(theta - theta_prev) <= 1e-10 * std::fabs(theta)) break;
+        if (!(bn > 1e-300 * std::max(1.0, std::fabs(theta)))) break;
+        be.push_back(bn);
+        theta_prev = theta;
+        beta = bn;
+        HIP_TRY(launch_scale_f64(w, w, 1.0 / bn, len, op->stream));
+        double* t = qp;
+        qp = q;
+        q = w;
+        w = t;
+    }
+    *lam_out = theta;
+    *steps_out = steps;
+    return CTPD_OK;
+}
+
+// lambda_max(A^T D A) with the float64 operators and the taps in op->taps64.
+int lambda_a(ctpd_op* op, int kmax, double* lam, int* steps) {
+    int r = ensure_f64(op);
+    if (r) return r;
+    double *s1 = op->sino64[3], *s2 = op->sino64[4], *vT = op->img64[3];
+    auto apply = [&](const double* in, double* out) -> int {
+        HIP_TRY(launch_transpose<double>(in, vT, op->n, op->stream));
+        HIP_TRY(launch_forward<double>(in, vT, s1, op->views, op->n, op->m, op->nb, op->stream));
+        HIP_TRY(launch_filter_f64(s1, s2, op->taps64, nullptr, nullptr, op->m, op->nb, op->stream));
+        HIP_TRY(launch_adjoint<double>(s2, nullptr, 1.0, 0.0, nullptr, 0.0, 1.0, out, op->views, op->n, op->m,
+                                       op->nb, op->stream));
+        return CTPD_OK;
+    };
+    return lanczos_max(op, op->img64[0], op->img64[1], op->img64[2], op->J, 1, kmax, apply, lam, steps);
+}
+
+// lambda_max(W^-1/2 D W^-1/2); needs op->sino64[3] = sqrt(1/w).
+int lambda_h(ctpd_op* op, int kmax, double* lam, int* steps) {
+    const double* rs = op->sino64[3];
+    auto apply = [&](const double* in, double* out) -> int {
+        HIP_TRY(launch_filter_f64(in, out, op->taps64, rs, rs, op->m, op->nb, op->stream));
+        return CTPD_OK;
+    };
+    return lanczos_max(op, op->sino64[0], op->sino64[1], op->sino64[2], op->I, 2, kmax, apply, lam, steps);
+}
+
+int filter(ctpd_op* op, int mode, const float* in0, const float* in1, const float* in2, const float* in3,
+           const float* E0, float e0, const float* E1, float e1, float c, float* out) {
+    FilterArgs a{};
+    a.in0 = in0;
+    a.in1 = in1;
+    a.in2 = in2;
+    a.in3 = in3;
+    a.E0 = E0;
+    a.E1 = E1;
+    a.e0 = e0;
+    a.e1 = e1;
+    a.c = c;
+    a.mode = mode;
+    a.out = out;
+    HIP_TRY(launch_filter_f32(a, op->taps32, op->m, op->nb, op->stream));
+    return CTPD_OK;
+}
+
+int project(ctpd_op* op, const float* x, float* y) {
+    HIP_TRY(launch_transpose<float>(x, op->xT, op->n, op->stream));
+    HIP_TRY(launch_forward<float>(x, op->xT, y, op->views, op->n, op->m, op->nb, op->stream));
+    return CTPD_OK;
+}
+
+// n_iter dual steps on p (warm start in pin; result pointer returned in *pout,
+// which is either pin or op->p scratch), then x = max(0, z - lam div p).
+int tv_prox(ctpd_op* op, const float* z, float lam, int n_iter, float step, float* pin, float* scratch, float* x,
+            float** pout) {
+    float* src = pin;
+    float* dst = scratch;
+    if (lam > 0.0f) {
+        for (int i = 0; i < n_iter; ++i) {
+            HIP_TRY(launch_tv_step(z, src, dst, op->n, lam, step, op->stream));
+            std::swap(src, dst);
+        }
+    }
+    HIP_TRY(launch_tv_finalize(z, src, x, op->n, lam, op->stream));
+    if (pout) *pout = src;
+    return CTPD_OK;
+}
+
+struct Knobs {
+    double tau, sigma, tv_step, rho;
+    int tv_iters, norm_steps, record;
+};
+
+int read_params(const ctpd_params* p, Knobs* k) {
+    k->tau = 0.0;
+    k->sigma = 0.0;
+    k->tv_step = 0.125;
+    k->rho = 0.95;
+    k->tv_iters = 10;
+    k->norm_steps = 100;
+    k->record = 0;
+    if (!p) return CTPD_OK;
+    if (!(std::isfinite(p->tau) && std::isfinite(p->sigma) && std::isfinite(p->tv_step) &&
+          std::isfinite(p->safety)))
+        return einval("non-finite parameter");
+    if (p->tau > 0) k->tau = p->tau;
+    if (p->sigma > 0) k->sigma = p->sigma;
+    if (p->tv_step > 0) k->tv_step = p->tv_step;
+    if (p->safety > 0) {
+        if (p->safety >= 1.0) return einval("safety must be < 1");
+        k->rho = p->safety;
+    }
+    if (p->tv_iters > 0) k->tv_iters = p->tv_iters;
+    if (p->norm_steps > 0) k->norm_steps = p->norm_steps;
+    k->record = p->record_cost ? 1 : 0;
+    return CTPD_OK;
+}
+
+int ensure_cost(ctpd_op* op, int iters) {
+    if (op->cost_cap >= iters) return CTPD_OK;
+    if (op->cost_dev) hipFree(op->cost_dev);
+    op->cost_dev = nullptr;
+    op->cost_cap = 0;
+    ALLOC(op->cost_dev, (size_t)6 * std::max(iters, 1));
+    op->cost_cap = iters;
+    return CTPD_OK;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+int finish(ctpd_op* op, int iters, bool lowdose, double beta, float* p_final, ctpd_report* rep, float* x_out,
+           bool recorded) {
+    const size_t J = op->J, I = op->I;
+    HIP_TRY(launch_copy_f32(x_out, op->x, J, op->stream));
+    if (rep && rep->mu_out) HIP_TRY(launch_copy_f32(rep->mu_out, op->mu[0], I, op->stream));
+    if (rep && rep->p_out) HIP_TRY(launch_copy_f32(rep->p_out, p_final, 2 * J, op->stream));
+    if (rep && rep->cost && recorded && iters > 0) {
+        std::vector<double> h((size_t)6 * iters);
+        HIP_TRY(hipMemcpyAsync(h.data(), op->cost_dev, sizeof(double) * h.size(), hipMemcpyDeviceToHost,
+                               op->stream));
+        int r = sync(op);
+        if (r) return r;
+        for (int k = 0; k < iters; ++k) {
+            const double tv = h[6 * k + 0], res = h[6 * k + 3];
+            rep->cost[k] = lowdose ? beta * tv + 0.5 * res : tv;
+        }
+    }
+    return sync(op);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ctpd_strerror(int code) {
+    switch (code) {
+        case CTPD_OK: return "ok";
+        case CTPD_EINVAL: return g_errmsg[0] ? g_errmsg : "invalid argument";
+        case CTPD_EDOMAIN: return g_errmsg[0] ? g_errmsg : "data outside the model";
+        case CTPD_EHIP: return g_errmsg[0] ? g_errmsg : "HIP runtime error";
+        case CTPD_ENOMEM: return g_errmsg[0] ? g_errmsg : "out of device memory";
+        default: return "unknown error code";
+    }
+}
+
+int ctpd_op_create(const ctpd_geometry* g, void* stream, ctpd_op** out) {
+    g_errmsg[0] = 0;
+    if (!g || !out) return einval("null pointer");
+    if (g->n < 1 || g->n > 16384) return einval("n out of range [1, 16384]");
+    if (g->n_views < 1 || g->n_views > 1000000) return einval("n_views out of range");
+    if (g->n_bins < 1 || g->n_bins > CTPD_MAX_BINS) return einval("n_bins out of range");
+    *out = nullptr;
+    ctpd_op* op = new ctpd_op();
+    op->n = g->n;
+    op->m = g->n_views;
+    op->nb = g->n_bins;
+    op->stream = (hipStream_t)stream;
+    op->J = (size_t)op->n * op->n;
+    op->I = (size_t)op->m * op->nb;
+    auto init = [&]() -> int {
+        HIP_TRY(hipGetDevice(&op->device));
+        ALLOC(op->views, op->m);
+        std::vector<ViewGeom> hv = make_views(op->n, op->m, op->nb);
+        HIP_TRY(hipMemcpy(op->views, hv.data(), sizeof(ViewGeom) * op->m, hipMemcpyHostToDevice));
+        ALLOC(op->xT, op->J);
+        ALLOC(op->x, op->J);
+        ALLOC(op->z, op->J);
+        for (auto& p : op->p) ALLOC(p, 2 * op->J);
+        for (auto& p : op->mu) ALLOC(p, op->I);
+        ALLOC(op->mubar, op->I);
+        ALLOC(op->q, op->I);
+        ALLOC(op->winv, op->I);
+        ALLOC(op->taps64, 2 * op->nb - 1);
+        ALLOC(op->taps32, 2 * op->nb - 1);
+        ALLOC(op->partials, 3 * kReduceBlocks);
+        ALLOC(op->red, 3 * kRedSlots);
+        HIP_TRY(hipHostMalloc((void**)&op->red_host, sizeof(double) * 3 * kRedSlots, hipHostMallocDefault));
+        return CTPD_OK;
+    };
+    int r = init();
+    if (r != CTPD_OK) {
+        ctpd_op_destroy(op);
+        return r;
+    }
+    *out = op;
+    return CTPD_OK;
+}
+
+void ctpd_op_destroy(ctpd_op* op) {
+    if (!op) return;
+    if (op->stream || op->views) hipStreamSynchronize(op->stream);
+    void* ptrs[] = {op->views, op->xT, op->x, op->z, op->p[0], op->p[1], op->mu[0], op->mu[1], op->mu[2],
+                    op->mubar, op->q, op->winv, op->taps64, op->taps32, op->partials, op->red, op->cost_dev,
+                    op->img64[0], op->img64[1], op->img64[2], op->img64[3], op->sino64[0], op->sino64[1],
+                    op->sino64[2], op->sino64[3], op->sino64[4]};
+    for (void* p : ptrs)
+        if (p) hipFree(p);
+    if (op->red_host) hipHostFree(op->red_host);
+    delete op;
+}
+
+int ctpd_project(ctpd_op* op, const float* x, float* y) {
+    g_errmsg[0] = 0;
+    if (!op || !x || !y) return einval("null pointer");
+    return project(op, x, y);
+}
+
+int ctpd_backproject(ctpd_op* op, const float* y, float* x) {
+    g_errmsg[0] = 0;
+    if (!op || !x || !y) return einval("null pointer");
+    HIP_TRY(launch_adjoint<float>(y, nullptr, 1.0f, 0.0f, nullptr, 0.0f, 1.0f, x, op->views, op->n, op->m, op->nb,
+                                  op->stream));
+    return CTPD_OK;
+}
+
+int ctpd_ramp_filter(ctpd_op* op, double tau, double kappa, const float* s, float* out) {
+    g_errmsg[0] = 0;
+    if (!op || !s || !out) return einval("null pointer");
+    if (!(tau > 0.0) || !std::isfinite(tau)) return einval("tau must be finite and > 0");
+    if (!(kappa >= 0.0) || !std::isfinite(kappa)) return einval("kappa must be finite and >= 0");
+    int r = ensure_taps(op, tau, kappa);
+    if (r) return r;
+    return filter(op, FILT_PLAIN, s, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, 1.0f, out);
+}
+
+int ctpd_filter_taps(ctpd_op* op, double tau, double kappa, double* taps_host) {
+    g_errmsg[0] = 0;
+    if (!op || !taps_host) return einval("null pointer");
+    if (!(tau > 0.0) || !std::isfinite(tau)) return einval("tau must be finite and > 0");
+    if (!(kappa >= 0.0) || !std::isfinite(kappa)) return einval("kappa must be finite and >= 0");
+    int r = ensure_taps(op, tau, kappa);
+    if (r) return r;
+    HIP_TRY(hipMemcpyAsync(taps_host, op->taps64, sizeof(double) * (2 * op->nb - 1), hipMemcpyDeviceToHost,
+                           op->stream));
+    return sync(op);
+}
+
+int ctpd_tv_prox(ctpd_op* op, const float* z, double lambda, int32_t n_iter, double tv_step, float* p_inout,
+                 float* x) {
+    g_errmsg[0] = 0;
+    if (!op || !z || !p_inout || !x) return einval("null pointer");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return einval("lambda must be finite and >= 0");
+    if (n_iter < 0) return einval("n_iter < 0");
+    if (!(tv_step > 0.0) || !std::isfinite(tv_step)) return einval("tv_step must be finite and > 0");
+    float* pf = nullptr;
+    const float lam = (float)lambda;
+    int r = tv_prox(op, z, lam, n_iter, (float)(tv_step / lambda), p_inout, op->p[0], x, &pf);
+    if (r) return r;
+    if (pf != p_inout) HIP_TRY(launch_copy_f32(p_inout, pf, 2 * op->J, op->stream));
+    return CTPD_OK;
+}
+
+int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double beta, int32_t iters,
+                          const ctpd_params* p, float* x_out, ctpd_report* rep) {
+    g_errmsg[0] = 0;
+    if (!op || !b || !w || !x_out) return einval("null pointer");
+    if (!(beta >= 0.0) || !std::isfinite(beta)) return einval("beta must be finite and >= 0");
+    if (iters < 0) return einval("iters < 0");
+    Knobs k;
+    int r = read_params(p, &k);
+    if (r) return r;
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t I = op->I, J = op->J;
+    hipStream_t s = op->stream;
+    // a1: kappa = mean(1/w) with a validity scan of w and b
+    if ((r = reduce(op, RED_INVW_CHECK, w, b, nullptr, I, 0))) return r;
+    if ((r = read_red(op))) return r;
+    if (op->red_host[1] > 0 || op->red_host[2] > 0) {
+        snprintf(g_errmsg, sizeof g_errmsg, "%.0f weights <= 0 or non-finite, %.0f non-finite data",
+                 op->red_host[1], op->red_host[2]);
+        return CTPD_EDOMAIN;
+    }
+    const double kappa = op->red_host[0] / (double)I;
+    const double tau = k.tau > 0 ? k.tau : M_PI * kappa / (2.0 * op->m);
+    HIP_TRY(launch_inverse_f32(op->winv, w, I, s));
+    if ((r = ensure_taps(op, tau, kappa))) return r;
+    // a2: step sizes
+    double sigma = k.sigma, lam_a = 0.0, lam_h = 0.0;
+    int steps_a = 0, steps_h = 0;
+    if (!(sigma > 0)) {
+        if ((r = lambda_a(op, k.norm_steps, &lam_a, &steps_a))) return r;
+        HIP_TRY(launch_rsqrt_f64(op->sino64[3], w, I, s));
+        if ((r = lambda_h(op, k.norm_steps, &lam_h, &steps_h))) return r;
+        sigma = k.rho * std::min(2.0 / lam_h, 1.0 / (tau * lam_a));
+    }
+    if ((r = sync(op))) return r;
+    const double setup_ms = ms_since(t0);
+    const auto t1 = std::chrono::steady_clock::now();
+    if (k.record && (r = ensure_cost(op, iters))) return r;
+    // x^0 = 0, mu^0 = 0, p = 0
+    HIP_TRY(launch_fill_f32(op->x, 0.f, J, s));
+    HIP_TRY(launch_fill_f32(op->p[0], 0.f, 2 * J, s));
+    HIP_TRY(launch_fill_f32(op->mu[0], 0.f, I, s));
+    HIP_TRY(launch_fill_f32(op->mu[1], 0.f, I, s));
+    float *mu = op->mu[0], *mup = op->mu[1], *mun = op->mu[2];
+    float* pcur = op->p[0];
+    const float fs = (float)sigma, ft = (float)tau, lam = (float)(tau * beta);
+    const float tvstep = lam > 0 ? (float)(k.tv_step / (tau * beta)) : 0.f;
+    for (int it = 0; it < iters; ++it) {
+        // Step 1: extrapolation (Eq. 18 / Algorithm 1)
+        if (it == 0)
+            r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, -fs, op->mubar);
+        else
+            r = filter(op, FILT_EXTRAP, op->winv, mu, mup, nullptr, mu, 2.f, mup, -1.f, -fs, op->mubar);
+        if (r) return r;
+        // Step 2: z = x - tau A^T mubar, x = prox(z; tau beta)
+        HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, op->x, 1.f, -ft, op->z, op->views, op->n,
+                                      op->m, op->nb, s));
+        float* pnew = nullptr;
+        if ((r = tv_prox(op, op->z, lam, k.tv_iters, tvstep, pcur, pcur == op->p[0] ? op->p[1] : op->p[0], op->x,
+                         &pnew)))
+            return r;
+        pcur = pnew;
+        // Step 3: mu^{k+1} = mu^k + sigma D (A x^{k+1} - b - W^-1 mu^k)
+        if ((r = project(op, op->x, op->q))) return r;
+        if ((r = filter(op, FILT_DUAL_LD, op->q, b, op->winv, mu, mu, 1.f, nullptr, 0.f, fs, mun))) return r;
+        if (k.record) {
+            if ((r = reduce(op, RED_WRES_F32, op->q, b, w, I, 0))) return r;
+            HIP_TRY(launch_tv_norm(op->x, op->n, op->partials, op->cost_dev + 6 * it, s));
+            HIP_TRY(hipMemcpyAsync(op->cost_dev + 6 * it + 3, op->red, sizeof(double) * 3,
+                                   hipMemcpyDeviceToDevice, s));
+        }
+        float* t = mup;
+        mup = mu;
+        mu = mun;
+        mun = t;
+    }
+    op->mu[0] = mu;
+    op->mu[1] = mup;
+    op->mu[2] = mun;
+    if ((r = finish(op, iters, true, beta, pcur, rep, x_out, k.record != 0))) return r;
+    if (rep) {
+        rep->tau = tau;
+        rep->sigma = sigma;
+        rep->kappa = kappa;
+        rep->lambda_a = lam_a;
+        rep->lambda_h = lam_h;
+        rep->norm_steps_a = steps_a;
+        rep->norm_steps_h = steps_h;
+        rep->iters_done = iters;
+        rep->setup_ms = setup_ms;
+        rep->loop_ms = ms_since(t1);
+    }
+    return CTPD_OK;
+}
+
+int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd_params* p, float* x_out,
+                          ctpd_report* rep) {
+    g_errmsg[0] = 0;
+    if (!op || !b || !x_out) return einval("null pointer");
+    if (iters < 0) return einval("iters < 0");
+    Knobs k;
+    int r = read_params(p, &k);
+    if (r) return r;
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t I = op->I, J = op->J;
+    hipStream_t s = op->stream;
+    if ((r = reduce(op, RED_SQ_F32, b, nullptr, nullptr, I, 0))) return r;
+    if ((r = read_red(op))) return r;
+    if (op->red_host[1] > 0) {
+        snprintf(g_errmsg, sizeof g_errmsg, "%.0f non-finite data values", op->red_host[1]);
+        return CTPD_EDOMAIN;
+    }
+    // a2: sigma tau < 1/lambda_max(A^T D(tau) A) with D(tau) = D(1)/tau, so
+    // sigma = rho / lambda_max(A^T D(1) A) whatever tau is.
+    double sigma = k.sigma, lam1 = 0.0;
+    int steps_a = 0;
+    if (!(sigma > 0) || !(k.tau > 0)) {
+        if ((r = ensure_taps(op, 1.0, 0.0))) return r;
+        if (!(sigma > 0)) {
+            if ((r = lambda_a(op, k.norm_steps, &lam1, &steps_a))) return r;
+            sigma = k.rho / lam1;
+        }
+    }
+    double tau = k.tau;
+    if (!(tau > 0)) {
+        // tau = mean |sigma A^T D(1) b|
+        if ((r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, 1.f, op->q)))
+            return r;
+        HIP_TRY(launch_adjoint<float>(op->q, nullptr, 1.f, 0.f, nullptr, 0.f, 1.f, op->z, op->views, op->n, op->m,
+                                      op->nb, s));
+        if ((r = reduce(op, RED_ABS_F32, op->z, nullptr, nullptr, J, 0))) return r;
+        if ((r = read_red(op))) return r;
+        tau = sigma * op->red_host[0] / (double)J;
+        if (!(tau > 0)) tau = 1.0;   // all-zero data: any tau works
+    }
+    if ((r = ensure_taps(op, tau, 0.0))) return r;
+    if ((r = sync(op))) return r;
+    const double setup_ms = ms_since(t0);
+    const auto t1 = std::chrono::steady_clock::now();
+    if (k.record && (r = ensure_cost(op, iters))) return r;
+    HIP_TRY(launch_fill_f32(op->x, 0.f, J, s));
+    HIP_TRY(launch_fill_f32(op->p[0], 0.f, 2 * J, s));
+    HIP_TRY(launch_fill_f32(op->mu[0], 0.f, I, s));
+    HIP_TRY(launch_fill_f32(op->mu[1], 0.f, I, s));
+    float *mu = op->mu[0], *mup = op->mu[1], *mun = op->mu[2];
+    float* pcur = op->p[0];
+    const float fs = (float)sigma, ft = (float)tau, lam = (float)tau;
+    const float tvstep = (float)(k.tv_step / tau);
+    for (int it = 0; it < iters; ++it) {
+        // Steps 1-2: z = x - tau A^T mubar, mubar = -sigma D b (k = 0) or 2 mu - mu_prev
+        if (it == 0) {
+            if ((r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, -fs,
+                            op->mubar)))
+                return r;
+            HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, op->x, 1.f, -ft, op->z, op->views, op->n,
+                                          op->m, op->nb, s));
+        } else {
+            HIP_TRY(launch_adjoint<float>(mu, mup, 2.f, -1.f, op->x, 1.f, -ft, op->z, op->views, op->n, op->m,
+                                          op->nb, s));
+        }
+        float* pnew = nullptr;
+        if ((r = tv_prox(op, op->z, lam, k.tv_iters, tvstep, pcur, pcur == op->p[0] ? op->p[1] : op->p[0], op->x,
+                         &pnew)))
+            return r;
+        pcur = pnew;
+        // Step 3: mu^{k+1} = mu^k + sigma D (A x^{k+1} - b)
+        if ((r = project(op, op->x, op->q))) return r;
+        if ((r = filter(op, FILT_DUAL_FV, op->q, b, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun))) return r;
+        if (k.record) {
+            if ((r = reduce(op, RED_SQDIFF_F32, op->q, b, nullptr, I, 0))) return r;
+            HIP_TRY(launch_tv_norm(op->x, op->n, op->partials, op->cost_dev + 6 * it, s));
+            HIP_TRY(hipMemcpyAsync(op->cost_dev + 6 * it + 3, op->red, sizeof(double) * 3,
+                                   hipMemcpyDeviceToDevice, s));
+        }
+        float* t = mup;
+        mup = mu;
+        mu = mun;
+        mun = t;
+    }
+    op->mu[0] = mu;
+    op->mu[1] = mup;
+    op->mu[2] = mun;
+    if ((r = finish(op, iters, false, 1.0, pcur, rep, x_out, k.record != 0))) return r;
+    if (rep) {
+        rep->tau = tau;
+        rep->sigma = sigma;
+        rep->kappa = 0.0;
+        rep->lambda_a = lam1 > 0 ? lam1 / tau : 0.0;
+        rep->lambda_h = 0.0;
+        rep->norm_steps_a = steps_a;
+        rep->norm_steps_h = 0;
+        rep->iters_done = iters;
+        rep->setup_ms = setup_ms;
+        rep->loop_ms = ms_since(t1);
+    }
+    return CTPD_OK;
+}
+
+}  // extern "C"

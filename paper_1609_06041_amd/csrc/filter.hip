@@ -1,0 +1,248 @@
+// The preconditioner D of Eqs. 24 and 32: per view, the linear convolution of
+// the detector bins with the taps h[k] = (1/pi) int_0^pi H(w) cos(k w) dw of
+// the band-limited filter response H.  Every view shares one symmetric
+// Toeplitz matrix T[j][i] = h[i - j], so D over all views is the dense
+// contraction OUT[v][i] = sum_j S[v][j] T[j][i]  (M = views, N = K = bins),
+// which runs on the matrix cores (v_mfma_f32_16x16x4_f32).  T is never
+// stored: its tiles are read straight out of the 2nb-1 taps kept in LDS.
+//
+// The float32 kernel fuses the dual-variable algebra around D
+// (Eqs. 18, 20, 31): the prologue forms the filter input from up to four
+// sinograms while staging it in LDS, the epilogue combines the result with up
+// to two sinograms.  A float64 VALU variant serves the operator-norm
+// computation.
+#include "internal.h"
+
+namespace ctpd {
+
+// ---------------------------------------------------------------------------
+// Taps.  Ramp (kappa == 0, Eq. 32): h[0] = pi/2, h[k] = -2/(pi k^2) for odd k,
+// 0 for even k != 0, all over 2 m tau.  Smoothed ramp (Eq. 24): composite
+// 16-point Gauss-Legendre quadrature of w cos(k w)/(2 m tau + kappa w) over
+// [0, pi] with at least two panels per period of cos(k w).
+struct GaussLegendre16 {
+    double x[16];   // nodes on [-1, 1]
+    double w[16];   // weights
+};
+
+__global__ __launch_bounds__(256) void taps_kernel(double* __restrict__ taps64, float* __restrict__ taps32,
+                                                   int nb, double c0, double kappa, int panels,
+                                                   GaussLegendre16 gl) {
+    const int k = blockIdx.x;   // offset 0..nb-1
+    double h;
+    if (kappa == 0.0) {
+        const double pi = 3.14159265358979323846;
+        h = (k == 0) ? pi / 2.0 : ((k & 1) ? -2.0 / (pi * (double)k * (double)k) : 0.0);
+        h /= c0;
+    } else {
+        const double pi = 3.14159265358979323846;
+        const double width = pi / panels;
+        double acc = 0.0;
+        for (int p = threadIdx.x; p < panels; p += 256) {
+            const double mid = (p + 0.5) * width, half = 0.5 * width;
+            double ps = 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const double w = fma(half, gl.x[q], mid);
+                ps = fma(gl.w[q], w * cos((double)k * w) / fma(kappa, w, c0), ps);
+            }
+            acc += ps * half;
+        }
+        // fixed-order block reduction
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        __shared__ double red[4];
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        h = (red[0] + red[1] + red[2] + red[3]) / pi;
+    }
+    if (threadIdx.x == 0) {
+        taps64[nb - 1 + k] = h;
+        taps64[nb - 1 - k] = h;
+        taps32[nb - 1 + k] = (float)h;
+        taps32[nb - 1 - k] = (float)h;
+    }
+}
+
+static GaussLegendre16 make_gl16() {
+    // Roots of P_16 by Newton's method from Chebyshev guesses; w = 2/((1-x^2) P'(x)^2).
+    GaussLegendre16 g;
+    const int n = 16;
+    for (int i = 0; i < n / 2; ++i) {
+        double x = cos(3.14159265358979323846 * (i + 0.75) / (n + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+            const double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+        }
+        const double w = 2.0 / ((1.0 - x * x) * dp * dp);
+        g.x[i] = -x;
+        g.w[i] = w;
+        g.x[n - 1 - i] = x;
+        g.w[n - 1 - i] = w;
+    }
+    return g;
+}
+
+hipError_t launch_taps(double* taps64, float* taps32, int nb, int m, double tau, double kappa, hipStream_t s) {
+    static const GaussLegendre16 gl = make_gl16();
+    const int panels = nb < 32 ? 64 : 2 * nb;
+    taps_kernel<<<nb, 256, 0, s>>>(taps64, taps32, nb, 2.0 * m * tau, kappa, panels, gl);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// float32 matrix-core filter.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int FBM = 32;   // views per workgroup
+constexpr int FBN = 64;   // output bins per workgroup
+constexpr int FBK = 32;   // input bins per LDS stage
+constexpr int FSTRIDE = FBK + 1;
+
+__device__ __forceinline__ float filter_input(const FilterArgs& a, size_t i) {
+    switch (a.mode) {
+        case FILT_EXTRAP: return a.in0[i] * (a.in1[i] - a.in2[i]);
+        case FILT_DUAL_LD: return a.in0[i] - a.in1[i] - a.in2[i] * a.in3[i];
+        case FILT_DUAL_FV: return a.in0[i] - a.in1[i];
+        default: return a.in0[i];
+    }
+}
+
+// Workgroup: 4 waves, a 32 x 64 output tile; wave w owns rows 16*(w/2) and
+// columns 32*(w%2) as two 16 x 16 MFMA accumulators.  MFMA 16x16x4 f32
+// operand layout: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k,
+// D[i][j] in lane j + 16*(i/4), element i%4.
+__global__ __launch_bounds__(256) void filter_mfma_kernel(FilterArgs a, const float* __restrict__ taps, int m,
+                                                          int nb) {
+    extern __shared__ float smem[];
+    const int ntap = 2 * nb - 1;
+    const int tlen = ntap + FBK + FBN;
+    float* htap = smem;                 // htap[FBK + k] = taps[k], zero padded
+    float* stile = smem + tlen;         // [FBM][FSTRIDE]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n0 = blockIdx.x * FBN, v0 = blockIdx.y * FBM;
+    for (int i = tid; i < tlen; i += 256) {
+        const int k = i - FBK;
+        htap[i] = (k >= 0 && k < ntap) ? taps[k] : 0.0f;
+    }
+    const int wr = (wave >> 1) * 16, wc = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < nb; k0 += FBK) {
+        __syncthreads();
+        for (int e = tid; e < FBM * FBK; e += 256) {
+            const int r = e / FBK, cc = e - r * FBK;
+            const int v = v0 + r, j = k0 + cc;
+            stile[r * FSTRIDE + cc] = (v < m && j < nb) ? filter_input(a, (size_t)v * nb + j) : 0.0f;
+        }
+        __syncthreads();
+        // T[krow][col] = h[col - krow] sits at htap[col - krow + nb - 1 + FBK].
+        const int hb = n0 + wc + li - (k0 + lk) + nb - 1 + FBK;
+#pragma unroll
+        for (int kk = 0; kk < FBK; kk += 4) {
+            const float av = stile[(wr + li) * FSTRIDE + kk + lk];
+            const float b0 = htap[hb - kk];
+            const float b1 = htap[hb - kk + 16];
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b1, acc1, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+        const v4f acc = blk ? acc1 : acc0;
+        const int col = n0 + wc + 16 * blk + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int v = v0 + wr + 4 * lk + r;
+            if (v < m && col < nb) {
+                const size_t idx = (size_t)v * nb + col;
+                float val = a.c * acc[r];
+                if (a.E0) val = fmaf(a.e0, a.E0[idx], val);
+                if (a.E1) val = fmaf(a.e1, a.E1[idx], val);
+                a.out[idx] = val;
+            }
+        }
+    }
+}
+
+hipError_t launch_filter_f32(const FilterArgs& a, const float* taps32, int m, int nb, hipStream_t s) {
+    dim3 grid((nb + FBN - 1) / FBN, (m + FBM - 1) / FBM);
+    const size_t lds = sizeof(float) * ((size_t)(2 * nb - 1 + FBK + FBN) + FBM * FSTRIDE);
+    filter_mfma_kernel<<<grid, 256, lds, s>>>(a, taps32, m, nb);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// float64 filter on the vector ALUs: out = post .* D (pre .* in).  Block =
+// (1024-output chunk, view); the input is streamed in 1024-bin chunks with
+// the matching 2047-tap window in LDS.  Lane l computes outputs l + 256 r.
+constexpr int F64_CH = 1024;
+
+__global__ __launch_bounds__(256) void filter_f64_kernel(const double* __restrict__ in, double* __restrict__ out,
+                                                         const double* __restrict__ taps,
+                                                         const double* __restrict__ pre,
+                                                         const double* __restrict__ post, int nb) {
+    __shared__ double sv[F64_CH];
+    __shared__ double hw[2 * F64_CH - 1];
+    const int v = blockIdx.y, i0 = blockIdx.x * F64_CH, tid = threadIdx.x;
+    const size_t rb = (size_t)v * nb;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j0 = 0; j0 < nb; j0 += F64_CH) {
+        __syncthreads();
+        for (int j = tid; j < F64_CH; j += 256) {
+            const int jj = j0 + j;
+            double val = 0.0;
+            if (jj < nb) {
+                val = in[rb + jj];
+                if (pre) val *= pre[rb + jj];
+            }
+            sv[j] = val;
+        }
+        // window: offset d = i - j in [i0 - j0 - (CH-1), i0 - j0 + (CH-1)]
+        for (int e = tid; e < 2 * F64_CH - 1; e += 256) {
+            const int d = i0 - j0 - (F64_CH - 1) + e;
+            hw[e] = (d > -nb && d < nb) ? taps[nb - 1 + d] : 0.0;
+        }
+        __syncthreads();
+        for (int j = 0; j < F64_CH; ++j) {
+            const double sj = sv[j];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] = fma(hw[tid + 256 * r - j + F64_CH - 1], sj, acc[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = i0 + tid + 256 * r;
+        if (i < nb) {
+            double val = acc[r];
+            if (post) val *= post[rb + i];
+            out[rb + i] = val;
+        }
+    }
+}
+
+hipError_t launch_filter_f64(const double* in, double* out, const double* taps64, const double* pre,
+                             const double* post, int m, int nb, hipStream_t s) {
+    dim3 grid((nb + F64_CH - 1) / F64_CH, m);
+    filter_f64_kernel<<<grid, 256, 0, s>>>(in, out, taps64, pre, post, nb);
+    return hipGetLastError();
+}
+
+}  // namespace ctpd

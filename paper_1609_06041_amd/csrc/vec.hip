@@ -1,0 +1,225 @@
+// Vector utilities: deterministic float64 reductions (wave shuffles, then the
+// block, then one final block in fixed order), the counter-based start
+// vector of the norm computation, and small elementwise kernels.
+#include "internal.h"
+
+namespace ctpd {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Sum of three per-thread values over the 256-thread block; result valid in thread 0.
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c) {
+    __shared__ double red[3][4];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = a;
+        red[1][w] = b;
+        red[2][w] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        b = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        c = (red[2][0] + red[2][1]) + (red[2][2] + red[2][3]);
+    }
+}
+
+template <int OP>
+__global__ __launch_bounds__(256) void reduce_partial_kernel(const void* __restrict__ pa, const void* __restrict__ pb,
+                                                             const void* __restrict__ pc, size_t len,
+                                                             double* __restrict__ partials) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < len; i += stride) {
+        if constexpr (OP == RED_DOT_F64) {
+            s0 = fma(((const double*)pa)[i], ((const double*)pb)[i], s0);
+        } else if constexpr (OP == RED_INVW_CHECK) {
+            const float w = ((const float*)pa)[i];
+            if (w > 0.0f && isfinite(w)) s0 += 1.0 / (double)w;
+            else s1 += 1.0;
+            if (pb && !isfinite(((const float*)pb)[i])) s2 += 1.0;
+        } else if constexpr (OP == RED_ABS_F32) {
+            s0 += fabs((double)((const float*)pa)[i]);
+        } else if constexpr (OP == RED_WRES_F32) {
+            const double r = (double)((const float*)pa)[i] - (double)((const float*)pb)[i];
+            s0 = fma((double)((const float*)pc)[i] * r, r, s0);
+        } else if constexpr (OP == RED_SQDIFF_F32) {
+            const double r = (double)((const float*)pa)[i] - (double)((const float*)pb)[i];
+            s0 = fma(r, r, s0);
+        } else {   // RED_SQ_F32, counting non-finite entries
+            const float v = ((const float*)pa)[i];
+            if (isfinite(v)) s0 = fma((double)v, (double)v, s0);
+            else s1 += 1.0;
+        }
+    }
+    block_sum3(s0, s1, s2);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x + 0] = s0;
+        partials[3 * blockIdx.x + 1] = s1;
+        partials[3 * blockIdx.x + 2] = s2;
+    }
+}
+
+__global__ __launch_bounds__(256) void reduce_final_kernel(const double* __restrict__ partials, int nblocks,
+                                                           double* __restrict__ out) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+        s0 += partials[3 * b + 0];
+        s1 += partials[3 * b + 1];
+        s2 += partials[3 * b + 2];
+    }
+    block_sum3(s0, s1, s2);
+    if (threadIdx.x == 0) {
+        out[0] = s0;
+        out[1] = s1;
+        out[2] = s2;
+    }
+}
+
+static int reduce_blocks(size_t len) {
+    const size_t b = (len + 255) / 256;
+    return (int)(b < (size_t)kReduceBlocks ? (b ? b : 1) : kReduceBlocks);
+}
+
+hipError_t launch_reduce(int op, const void* a, const void* b, const void* c, size_t len, double* partials,
+                         double* dev_out, hipStream_t s) {
+    const int nb = reduce_blocks(len);
+    switch (op) {
+        case RED_DOT_F64: reduce_partial_kernel<RED_DOT_F64><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
+        case RED_INVW_CHECK: reduce_partial_kernel<RED_INVW_CHECK><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
+        case RED_ABS_F32: reduce_partial_kernel<RED_ABS_F32><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
+        case RED_WRES_F32: reduce_partial_kernel<RED_WRES_F32><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
+        case RED_SQDIFF_F32: reduce_partial_kernel<RED_SQDIFF_F32><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
+        default: reduce_partial_kernel<RED_SQ_F32><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    reduce_final_kernel<<<1, 256, 0, s>>>(partials, nb, dev_out);
+    return hipGetLastError();
+}
+
+// TV norm (Eq. 2) of a float32 image in float64.
+__global__ __launch_bounds__(256) void tv_norm_partial_kernel(const float* __restrict__ x, int n,
+                                                              double* __restrict__ partials) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    const size_t len = (size_t)n * n, stride = (size_t)gridDim.x * 256;
+    for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < len; idx += stride) {
+        const int i = (int)(idx / n), j = (int)(idx - (size_t)i * n);
+        const double xc = x[idx];
+        const double g1 = (j < n - 1) ? (double)x[idx + 1] - xc : 0.0;
+        const double g2 = (i < n - 1) ? (double)x[idx + n] - xc : 0.0;
+        s0 += sqrt(g1 * g1 + g2 * g2);
+    }
+    block_sum3(s0, s1, s2);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x + 0] = s0;
+        partials[3 * blockIdx.x + 1] = 0.0;
+        partials[3 * blockIdx.x + 2] = 0.0;
+    }
+}
+
+hipError_t launch_tv_norm(const float* x, int n, double* partials, double* dev_out, hipStream_t s) {
+    const int nb = reduce_blocks((size_t)n * n);
+    tv_norm_partial_kernel<<<nb, 256, 0, s>>>(x, n, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    reduce_final_kernel<<<1, 256, 0, s>>>(partials, nb, dev_out);
+    return hipGetLastError();
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014) as a counter-based generator:
+// v[i] = top 53 bits of mix(seed + (i+1) * golden) in [0, 1), minus 1/2.
+__global__ __launch_bounds__(256) void start_vector_kernel(double* __restrict__ v, size_t len, uint64_t seed) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= len) return;
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    v[i] = (double)(z >> 11) * 0x1.0p-53 - 0.5;
+}
+
+hipError_t launch_start_vector(double* v, size_t len, uint64_t seed, hipStream_t s) {
+    start_vector_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(v, len, seed);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void axpby_kernel(double* __restrict__ y, const double* __restrict__ x, double a,
+                                                    double b, const double* __restrict__ z, double c, size_t len) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= len) return;
+    double r = a * x[i] + b * y[i];
+    if (z) r += c * z[i];
+    y[i] = r;
+}
+
+hipError_t launch_axpby_f64(double* y, const double* x, double a, double b, const double* z, double c,
+                            size_t len, hipStream_t s) {
+    axpby_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(y, x, a, b, z, c, len);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void scale_kernel(double* __restrict__ y, const double* __restrict__ x, double a,
+                                                    size_t len) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < len) y[i] = a * x[i];
+}
+
+hipError_t launch_scale_f64(double* y, const double* x, double a, size_t len, hipStream_t s) {
+    scale_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(y, x, a, len);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void inverse_kernel(float* __restrict__ out, const float* __restrict__ w,
+                                                      size_t len) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < len) out[i] = (float)(1.0 / (double)w[i]);
+}
+
+hipError_t launch_inverse_f32(float* out, const float* w, size_t len, hipStream_t s) {
+    inverse_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(out, w, len);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void rsqrt_kernel(double* __restrict__ out, const float* __restrict__ w,
+                                                    size_t len) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < len) out[i] = sqrt(1.0 / (double)w[i]);
+}
+
+hipError_t launch_rsqrt_f64(double* out, const float* w, size_t len, hipStream_t s) {
+    rsqrt_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(out, w, len);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void copy_kernel(float* __restrict__ dst, const float* __restrict__ src,
+                                                   size_t len) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < len) dst[i] = src[i];
+}
+
+hipError_t launch_copy_f32(float* dst, const float* src, size_t len, hipStream_t s) {
+    if (len == 0) return hipSuccess;
+    copy_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(dst, src, len);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(float* __restrict__ dst, float v, size_t len) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < len) dst[i] = v;
+}
+
+hipError_t launch_fill_f32(float* dst, float v, size_t len, hipStream_t s) {
+    if (len == 0) return hipSuccess;
+    fill_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(dst, v, len);
+    return hipGetLastError();
+}
+
+}  // namespace ctpd

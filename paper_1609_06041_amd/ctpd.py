@@ -1,0 +1,222 @@
+"""Python binding of libctpd (the C ABI declared in include/ctpd.h).
+
+Argument marshalling only: tensors are checked for dtype, device, shape and
+contiguity, and their device pointers go straight to the library; every step
+of the computation runs in the HIP kernels.  The library is required -- if
+``libctpd.so`` is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_int, c_int32, c_void_p
+
+import numpy as np
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libctpd.so")
+
+CTPD_OK, CTPD_EINVAL, CTPD_EDOMAIN, CTPD_EHIP, CTPD_ENOMEM = 0, -1, -2, -3, -4
+MAX_BINS = 4096
+
+# Every symbol the header declares, with its ctypes signature.
+_SIGNATURES = {
+    "ctpd_op_create": (c_int, [c_void_p, c_void_p, POINTER(c_void_p)]),
+    "ctpd_op_destroy": (None, [c_void_p]),
+    "ctpd_project": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "ctpd_backproject": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "ctpd_ramp_filter": (c_int, [c_void_p, c_double, c_double, c_void_p, c_void_p]),
+    "ctpd_filter_taps": (c_int, [c_void_p, c_double, c_double, POINTER(c_double)]),
+    "ctpd_tv_prox": (c_int, [c_void_p, c_void_p, c_double, c_int32, c_double, c_void_p, c_void_p]),
+    "ctpd_pd_lowdose_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p,
+                                      c_void_p]),
+    "ctpd_pd_fewview_solve": (c_int, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "ctpd_strerror": (ctypes.c_char_p, [c_int]),
+}
+
+
+class CtpdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ctpd error {code}: {msg}")
+        self.code = code
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("n_views", c_int32), ("n_bins", c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("tau", c_double), ("sigma", c_double), ("tv_step", c_double), ("safety", c_double),
+                ("tv_iters", c_int32), ("norm_steps", c_int32), ("record_cost", c_int32), ("reserved", c_int32)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("tau", c_double), ("sigma", c_double), ("kappa", c_double), ("lambda_a", c_double),
+                ("lambda_h", c_double), ("norm_steps_a", c_int32), ("norm_steps_h", c_int32),
+                ("iters_done", c_int32), ("reserved", c_int32), ("setup_ms", c_double), ("loop_ms", c_double),
+                ("cost", POINTER(c_double)), ("mu_out", c_void_p), ("p_out", c_void_p)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libctpd.so (raises CtpdError if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise CtpdError(CTPD_EHIP, f"{LIB_PATH} is not built; run `python -m paper_1609_06041_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(code: int) -> None:
+    if code != CTPD_OK:
+        msg = load().ctpd_strerror(code)
+        raise CtpdError(code, msg.decode() if msg else "?")
+
+
+def _ptr(t: torch.Tensor, shape, name: str) -> c_void_p:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return c_void_p(t.data_ptr())
+
+
+def _params(tau, sigma, tv_iters, tv_step, safety, norm_steps, record_cost) -> Params:
+    return Params(tau=float(tau or 0.0), sigma=float(sigma or 0.0), tv_step=float(tv_step or 0.0),
+                  safety=float(safety or 0.0), tv_iters=int(tv_iters or 0), norm_steps=int(norm_steps or 0),
+                  record_cost=1 if record_cost else 0, reserved=0)
+
+
+class Operator:
+    """A scan geometry (n x n image, n_views x n_bins sinogram) bound to a stream."""
+
+    def __init__(self, n: int, n_views: int, n_bins: int, stream: torch.cuda.Stream | None = None):
+        self.n, self.m, self.nb = int(n), int(n_views), int(n_bins)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.device = self.stream.device
+        h = c_void_p()
+        with torch.cuda.device(self.device):
+            _check(load().ctpd_op_create(byref(Geometry(self.n, self.m, self.nb)),
+                                         c_void_p(self.stream.cuda_stream), byref(h)))
+        self._h = h
+
+    # -- lifetime --------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().ctpd_op_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- helpers ---------------------------------------------------------
+    def _img(self):
+        return torch.empty((self.n, self.n), dtype=torch.float32, device=self.device)
+
+    def _sino(self):
+        return torch.empty((self.m, self.nb), dtype=torch.float32, device=self.device)
+
+    # -- single operators --------------------------------------------------
+    def project(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = self._sino() if out is None else out
+        _check(load().ctpd_project(self._h, _ptr(x, (self.n, self.n), "x"), _ptr(out, (self.m, self.nb), "out")))
+        return out
+
+    def backproject(self, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = self._img() if out is None else out
+        _check(load().ctpd_backproject(self._h, _ptr(y, (self.m, self.nb), "y"), _ptr(out, (self.n, self.n), "out")))
+        return out
+
+    def ramp_filter(self, s: torch.Tensor, tau: float, kappa: float = 0.0,
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+        out = self._sino() if out is None else out
+        _check(load().ctpd_ramp_filter(self._h, float(tau), float(kappa), _ptr(s, (self.m, self.nb), "s"),
+                                       _ptr(out, (self.m, self.nb), "out")))
+        return out
+
+    def filter_taps(self, tau: float, kappa: float = 0.0) -> np.ndarray:
+        taps = np.zeros(2 * self.nb - 1, dtype=np.float64)
+        _check(load().ctpd_filter_taps(self._h, float(tau), float(kappa),
+                                       taps.ctypes.data_as(POINTER(c_double))))
+        return taps
+
+    def tv_prox(self, z: torch.Tensor, lam: float, p: torch.Tensor | None = None, n_iter: int = 10,
+                tv_step: float = 0.125, out: torch.Tensor | None = None):
+        """Returns (x, p); p (shape [2, n, n]) is updated in place when given."""
+        if p is None:
+            p = torch.zeros((2, self.n, self.n), dtype=torch.float32, device=self.device)
+        out = self._img() if out is None else out
+        _check(load().ctpd_tv_prox(self._h, _ptr(z, (self.n, self.n), "z"), float(lam), int(n_iter),
+                                   float(tv_step), _ptr(p, (2, self.n, self.n), "p"),
+                                   _ptr(out, (self.n, self.n), "out")))
+        return out, p
+
+    # -- solvers -------------------------------------------------------------
+    def _report(self, iters, record_cost, return_state):
+        rep = Report()
+        cost = None
+        if record_cost and iters > 0:
+            cost = np.zeros(iters, dtype=np.float64)
+            rep.cost = cost.ctypes.data_as(POINTER(c_double))
+        state = {}
+        if return_state:
+            state["mu"] = self._sino()
+            state["p"] = torch.empty((2, self.n, self.n), dtype=torch.float32, device=self.device)
+            rep.mu_out = c_void_p(state["mu"].data_ptr())
+            rep.p_out = c_void_p(state["p"].data_ptr())
+        return rep, cost, state
+
+    @staticmethod
+    def _info(rep: Report, cost, state) -> dict:
+        info = {k: getattr(rep, k) for k in ("tau", "sigma", "kappa", "lambda_a", "lambda_h", "norm_steps_a",
+                                            "norm_steps_h", "iters_done", "setup_ms", "loop_ms")}
+        if cost is not None:
+            info["cost"] = cost
+        info.update(state)
+        return info
+
+    def lowdose_solve(self, b: torch.Tensor, w: torch.Tensor, beta: float, iters: int, *, tau=None, sigma=None,
+                      tv_iters=10, tv_step=0.125, safety=0.95, norm_steps=100, record_cost=False,
+                      return_state=False, out: torch.Tensor | None = None):
+        """Algorithm 1 (beta > 0) / 1' (beta = 0).  Returns (x, info)."""
+        out = self._img() if out is None else out
+        prm = _params(tau, sigma, tv_iters, tv_step, safety, norm_steps, record_cost)
+        rep, cost, state = self._report(iters, record_cost, return_state)
+        _check(load().ctpd_pd_lowdose_solve(self._h, _ptr(b, (self.m, self.nb), "b"),
+                                            _ptr(w, (self.m, self.nb), "w"), float(beta), int(iters),
+                                            byref(prm), _ptr(out, (self.n, self.n), "out"), byref(rep)))
+        return out, self._info(rep, cost, state)
+
+    def fewview_solve(self, b: torch.Tensor, iters: int, *, tau=None, sigma=None, tv_iters=10, tv_step=0.125,
+                      safety=0.95, norm_steps=100, record_cost=False, return_state=False,
+                      out: torch.Tensor | None = None):
+        """Algorithm 2.  Returns (x, info)."""
+        out = self._img() if out is None else out
+        prm = _params(tau, sigma, tv_iters, tv_step, safety, norm_steps, record_cost)
+        rep, cost, state = self._report(iters, record_cost, return_state)
+        _check(load().ctpd_pd_fewview_solve(self._h, _ptr(b, (self.m, self.nb), "b"), int(iters), byref(prm),
+                                            _ptr(out, (self.n, self.n), "out"), byref(rep)))
+        return out, self._info(rep, cost, state)

@@ -1,0 +1,66 @@
+"""The C ABI library loads, exports every symbol include/ctpd.h declares, and
+rejects bad arguments before touching the GPU (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1609_06041_amd import ctpd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ctpd.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ctpd_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("ctpd_project", "ctpd_backproject", "ctpd_ramp_filter", "ctpd_pd_lowdose_solve",
+                     "ctpd_pd_fewview_solve", "ctpd_op_create", "ctpd_op_destroy", "ctpd_strerror"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(libctpd):
+    for name in declared_functions():
+        assert hasattr(libctpd, name), name
+        assert name in ctpd._SIGNATURES, f"binding lacks a signature for {name}"
+
+
+def test_binding_struct_layouts_match_header():
+    # field order / sizes as declared (ctypes follows the C ABI layout rules)
+    assert ctypes.sizeof(ctpd.Geometry) == 12
+    assert ctypes.sizeof(ctpd.Params) == 4 * 8 + 4 * 4
+    assert ctypes.sizeof(ctpd.Report) == 5 * 8 + 4 * 4 + 2 * 8 + 3 * 8
+    text = open(HEADER).read()
+    assert f"#define CTPD_MAX_BINS {ctpd.MAX_BINS}" in text
+
+
+@pytest.mark.parametrize("n,m,nb", [(0, 10, 10), (10, 0, 10), (10, 10, 0), (-3, 1, 1), (8, 8, 4097)])
+def test_op_create_rejects_bad_geometry(libctpd, n, m, nb):
+    h = ctypes.c_void_p()
+    g = ctpd.Geometry(n, m, nb)
+    assert libctpd.ctpd_op_create(ctypes.byref(g), None, ctypes.byref(h)) == ctpd.CTPD_EINVAL
+    assert not h.value
+    assert b"invalid argument" in libctpd.ctpd_strerror(ctpd.CTPD_EINVAL)
+
+
+def test_null_arguments_are_rejected(libctpd):
+    assert libctpd.ctpd_op_create(None, None, None) == ctpd.CTPD_EINVAL
+    assert libctpd.ctpd_project(None, None, None) == ctpd.CTPD_EINVAL
+    assert libctpd.ctpd_backproject(None, None, None) == ctpd.CTPD_EINVAL
+    assert libctpd.ctpd_ramp_filter(None, 1.0, 0.0, None, None) == ctpd.CTPD_EINVAL
+    assert libctpd.ctpd_filter_taps(None, 1.0, 0.0, None) == ctpd.CTPD_EINVAL
+    assert libctpd.ctpd_tv_prox(None, None, 0.1, 1, 0.125, None, None) == ctpd.CTPD_EINVAL
+    assert libctpd.ctpd_pd_lowdose_solve(None, None, None, 0.1, 1, None, None, None) == ctpd.CTPD_EINVAL
+    assert libctpd.ctpd_pd_fewview_solve(None, None, 1, None, None, None) == ctpd.CTPD_EINVAL
+    libctpd.ctpd_op_destroy(None)   # no-op
+
+
+def test_error_strings(libctpd):
+    for code in (0, -1, -2, -3, -4, -99):
+        assert libctpd.ctpd_strerror(code)
