@@ -109,6 +109,10 @@ int ctpd_backproject(ctpd_op* op, const float* y, float* x);
  * s, out: [n_views][n_bins]. */
 int ctpd_ramp_filter(ctpd_op* op, double tau, double kappa, const float* s, float* out);
 
+/* The same D in float64 (the precision the operator norms are computed in):
+ * out = D s for float64 s, out: [n_views][n_bins]. */
+int ctpd_ramp_filter_f64(ctpd_op* op, double tau, double kappa, const double* s, double* out);
+
 /* The 2*n_bins-1 filter taps h[k - (n_bins-1)], k = 0..2n_bins-2, of
  * ctpd_ramp_filter in float64, copied to the host array taps_host (blocks). */
 int ctpd_filter_taps(ctpd_op* op, double tau, double kappa, double* taps_host);

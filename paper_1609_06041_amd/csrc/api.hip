@@ -20,9 +20,11 @@ struct ctpd_op {
     hipStream_t stream = nullptr;
     int device = 0;
     size_t J = 0, I = 0;   // image / sinogram sizes
+    size_t Jp = 0;         // padded plane size n * (n + 4)
     ViewGeom* views = nullptr;
     // float32 iteration state
-    float* xT = nullptr;
+    float* xp = nullptr;    // padded image planes for the forward projector, [n][n+4] each
+    float* xTp = nullptr;
     float* x = nullptr;
     float* z = nullptr;
     float* p[2] = {nullptr, nullptr};
@@ -39,8 +41,13 @@ struct ctpd_op {
     double* red = nullptr;        // device, 3 * kRedSlots doubles
     double* red_host = nullptr;   // pinned host mirror
     // float64 workspaces for the operator norms (allocated on first use)
-    double* img64[4] = {nullptr, nullptr, nullptr, nullptr};
+    double* img64[3] = {nullptr, nullptr, nullptr};
+    double* pad64[2] = {nullptr, nullptr};
     double* sino64[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // Lanczos recurrence scalars (device + pinned host mirror)
+    double* lz = nullptr;
+    double* lz_host = nullptr;
+    int lz_cap = 0;
     // per-iteration monitor values (device), 2 * cost_cap slots of 3 doubles
     double* cost_dev = nullptr;
     int cost_cap = 0;
@@ -122,6 +129,7 @@ int ensure_taps(ctpd_op* op, double tau, double kappa) {
 int ensure_f64(ctpd_op* op) {
     if (op->img64[0]) return CTPD_OK;
     for (auto& p : op->img64) ALLOC(p, op->J);
+    for (auto& p : op->pad64) ALLOC(p, op->Jp);
     for (auto& p : op->sino64) ALLOC(p, op->I);
     return CTPD_OK;
 }
@@ -138,10 +146,11 @@ int read_red(ctpd_op* op) {
     return sync(op);
 }
 
-// Largest eigenvalue of the symmetric operator M (float64) by the Lanczos
+// Largest eigenvalue of a symmetric operator M (float64) by the Lanczos
 // recurrence without reorthogonalisation: for the extreme eigenvalue the
 // Ritz value converges even after orthogonality is lost (at worst copies of
 // it appear).  Stops when the top Ritz value changes by <= 1e-10 relative.
+// The Ritz value is the top eigenvalue of the tridiagonal matrix (alpha, beta).
 double tridiag_max(const std::vector<double>& a, const std::vector<double>& b) {
     // a: diagonal (k), b: off-diagonal (k-1).  Sturm-sequence bisection.
     const int k = (int)a.size();
@@ -169,40 +178,72 @@ double tridiag_max(const std::vector<double>& a, const std::vector<double>& b) {
     return hi;
 }
 
+// Lanczos with the recurrence scalars kept on the device: the kernels read
+// alpha_j and beta_j from device memory, and the host only copies them back
+// every kCheck steps to evaluate the top Ritz value (so the queue never
+// drains between steps).  Device slots (3 doubles each): [0] start norm^2,
+// [1 + j] alpha_j, [1 + cap + j] beta_{j+1}^2.
+constexpr int kCheck = 8;
+
+int ensure_lz(ctpd_op* op, int kmax) {
+    if (op->lz_cap >= kmax) return CTPD_OK;
+    if (op->lz) hipFree(op->lz);
+    if (op->lz_host) hipHostFree(op->lz_host);
+    op->lz = nullptr;
+    op->lz_host = nullptr;
+    op->lz_cap = 0;
+    const size_t cnt = (size_t)3 * (2 * kmax + 1);
+    ALLOC(op->lz, cnt);
+    HIP_TRY(hipHostMalloc((void**)&op->lz_host, sizeof(double) * cnt, hipHostMallocDefault));
+    op->lz_cap = kmax;
+    return CTPD_OK;
+}
+
 template <class Apply>
-int lanczos_max(ctpd_op* op, double* q, double* qp, double* w, size_t len, uint64_t seed, int kmax, Apply apply,
-                double* lam_out, int* steps_out) {
-    HIP_TRY(launch_start_vector(q, len, seed, op->stream));
-    int r = reduce(op, RED_DOT_F64, q, q, nullptr, len, 0);
+int lanczos_max(ctpd_op* op, double* q, double* qp, double* w, int rows, int cols, uint64_t seed,
+                const float* wgt, double inv_kappa, int kmax, Apply apply, double* lam_out, int* steps_out) {
+    int r = ensure_lz(op, kmax);
     if (r) return r;
-    if ((r = read_red(op))) return r;
-    HIP_TRY(launch_scale_f64(q, q, 1.0 / std::sqrt(op->red_host[0]), len, op->stream));
+    const size_t len = (size_t)rows * cols;
+    const int cap = op->lz_cap;
+    double* s0 = op->lz;
+    auto AL = [&](int j) { return op->lz + 3 * (1 + j); };
+    auto B2 = [&](int j) { return op->lz + 3 * (1 + cap + j); };
+    hipStream_t s = op->stream;
+    HIP_TRY(launch_start_vector(q, rows, cols, seed, wgt, inv_kappa, s));
+    HIP_TRY(launch_reduce(RED_DOT_F64, q, q, nullptr, len, op->partials, s0, s));
+    HIP_TRY(launch_normalize(q, q, s0, len, s));
     std::vector<double> al, be;
-    double beta = 0.0, theta = 0.0, theta_prev = 0.0;
-    int steps = 0;
-    for (int j = 0; j < kmax; ++j) {
+    double theta = 0.0, theta_prev = 0.0;
+    int done = 0, steps = 0;
+    bool converged = false;
+    for (int j = 0; j < kmax && !converged; ++j) {
         if ((r = apply(q, w))) return r;
-        if ((r = reduce(op, RED_DOT_F64, q, w, nullptr, len, 0))) return r;
-        if ((r = read_red(op))) return r;
-        const double alpha = op->red_host[0];
-        // w = w - alpha q - beta qp
-        HIP_TRY(launch_axpby_f64(w, q, -alpha, 1.0, j ? qp : nullptr, -beta, len, op->stream));
-        if ((r = reduce(op, RED_DOT_F64, w, w, nullptr, len, 0))) return r;
-        if ((r = read_red(op))) return r;
-        const double bn = std::sqrt(std::max(op->red_host[0], 0.0));
-        al.push_back(alpha);
-        theta = tridiag_max(al, be);
-        steps = j + 1;
-        if (j > 0 && std::fabs(theta - theta_prev) <= 1e-10 * std::fabs(theta)) break;
-        if (!(bn > 1e-300 * std::max(1.0, std::fabs(theta)))) break;
-        be.push_back(bn);
-        theta_prev = theta;
-        beta = bn;
-        HIP_TRY(launch_scale_f64(w, w, 1.0 / bn, len, op->stream));
+        HIP_TRY(launch_reduce(RED_DOT_F64, q, w, nullptr, len, op->partials, AL(j), s));
+        HIP_TRY(launch_lanczos_update(w, q, j ? qp : nullptr, AL(j), j ? B2(j - 1) : nullptr, len, op->partials,
+                                      B2(j), s));
+        HIP_TRY(launch_normalize(w, w, B2(j), len, s));
         double* t = qp;
         qp = q;
         q = w;
         w = t;
+        if ((j + 1) % kCheck != 0 && j + 1 != kmax) continue;
+        HIP_TRY(hipMemcpyAsync(op->lz_host, op->lz, sizeof(double) * 3 * (2 * cap + 1), hipMemcpyDeviceToHost, s));
+        if ((r = sync(op))) return r;
+        for (int i = done; i <= j; ++i) {
+            al.push_back(op->lz_host[3 * (1 + i)]);
+            theta = tridiag_max(al, be);
+            steps = i + 1;
+            const double bn = std::sqrt(std::max(op->lz_host[3 * (1 + cap + i)], 0.0));
+            if ((i > 0 && std::fabs(theta - theta_prev) <= 1e-10 * std::fabs(theta)) ||
+                !(bn > 1e-300 * std::max(1.0, std::fabs(theta)))) {
+                converged = true;
+                break;
+            }
+            be.push_back(bn);
+            theta_prev = theta;
+        }
+        done = j + 1;
     }
     *lam_out = theta;
     *steps_out = steps;
@@ -213,26 +254,29 @@ int lanczos_max(ctpd_op* op, double* q, double* qp, double* w, size_t len, uint6
 int lambda_a(ctpd_op* op, int kmax, double* lam, int* steps) {
     int r = ensure_f64(op);
     if (r) return r;
-    double *s1 = op->sino64[3], *s2 = op->sino64[4], *vT = op->img64[3];
+    double *s1 = op->sino64[3], *s2 = op->sino64[4];
     auto apply = [&](const double* in, double* out) -> int {
-        HIP_TRY(launch_transpose<double>(in, vT, op->n, op->stream));
-        HIP_TRY(launch_forward<double>(in, vT, s1, op->views, op->n, op->m, op->nb, op->stream));
+        HIP_TRY(launch_pad_planes<double>(in, op->pad64[0], op->pad64[1], op->n, op->stream));
+        HIP_TRY(launch_forward<double>(op->pad64[0], op->pad64[1], s1, op->views, op->n, op->m, op->nb,
+                                       op->stream));
         HIP_TRY(launch_filter_f64(s1, s2, op->taps64, nullptr, nullptr, op->m, op->nb, op->stream));
         HIP_TRY(launch_adjoint<double>(s2, nullptr, 1.0, 0.0, nullptr, 0.0, 1.0, out, op->views, op->n, op->m,
                                        op->nb, op->stream));
         return CTPD_OK;
     };
-    return lanczos_max(op, op->img64[0], op->img64[1], op->img64[2], op->J, 1, kmax, apply, lam, steps);
+    return lanczos_max(op, op->img64[0], op->img64[1], op->img64[2], op->n, op->n, 1, nullptr, 0.0, kmax, apply,
+                       lam, steps);
 }
 
 // lambda_max(W^-1/2 D W^-1/2); needs op->sino64[3] = sqrt(1/w).
-int lambda_h(ctpd_op* op, int kmax, double* lam, int* steps) {
+int lambda_h(ctpd_op* op, const float* w, double kappa, int kmax, double* lam, int* steps) {
     const double* rs = op->sino64[3];
     auto apply = [&](const double* in, double* out) -> int {
         HIP_TRY(launch_filter_f64(in, out, op->taps64, rs, rs, op->m, op->nb, op->stream));
         return CTPD_OK;
     };
-    return lanczos_max(op, op->sino64[0], op->sino64[1], op->sino64[2], op->I, 2, kmax, apply, lam, steps);
+    return lanczos_max(op, op->sino64[0], op->sino64[1], op->sino64[2], op->m, op->nb, 2, w, 1.0 / kappa, kmax,
+                       apply, lam, steps);
 }
 
 int filter(ctpd_op* op, int mode, const float* in0, const float* in1, const float* in2, const float* in3,
@@ -254,8 +298,8 @@ int filter(ctpd_op* op, int mode, const float* in0, const float* in1, const floa
 }
 
 int project(ctpd_op* op, const float* x, float* y) {
-    HIP_TRY(launch_transpose<float>(x, op->xT, op->n, op->stream));
-    HIP_TRY(launch_forward<float>(x, op->xT, y, op->views, op->n, op->m, op->nb, op->stream));
+    HIP_TRY(launch_pad_planes<float>(x, op->xp, op->xTp, op->n, op->stream));
+    HIP_TRY(launch_forward<float>(op->xp, op->xTp, y, op->views, op->n, op->m, op->nb, op->stream));
     return CTPD_OK;
 }
 
@@ -368,13 +412,15 @@ int ctpd_op_create(const ctpd_geometry* g, void* stream, ctpd_op** out) {
     op->nb = g->n_bins;
     op->stream = (hipStream_t)stream;
     op->J = (size_t)op->n * op->n;
+    op->Jp = (size_t)op->n * (op->n + 4);
     op->I = (size_t)op->m * op->nb;
     auto init = [&]() -> int {
         HIP_TRY(hipGetDevice(&op->device));
         ALLOC(op->views, op->m);
         std::vector<ViewGeom> hv = make_views(op->n, op->m, op->nb);
         HIP_TRY(hipMemcpy(op->views, hv.data(), sizeof(ViewGeom) * op->m, hipMemcpyHostToDevice));
-        ALLOC(op->xT, op->J);
+        ALLOC(op->xp, op->Jp);
+        ALLOC(op->xTp, op->Jp);
         ALLOC(op->x, op->J);
         ALLOC(op->z, op->J);
         for (auto& p : op->p) ALLOC(p, 2 * op->J);
@@ -401,13 +447,15 @@ int ctpd_op_create(const ctpd_geometry* g, void* stream, ctpd_op** out) {
 void ctpd_op_destroy(ctpd_op* op) {
     if (!op) return;
     if (op->stream || op->views) hipStreamSynchronize(op->stream);
-    void* ptrs[] = {op->views, op->xT, op->x, op->z, op->p[0], op->p[1], op->mu[0], op->mu[1], op->mu[2],
+    void* ptrs[] = {op->views, op->xp, op->xTp, op->x, op->z, op->p[0], op->p[1], op->mu[0], op->mu[1], op->mu[2],
                     op->mubar, op->q, op->winv, op->taps64, op->taps32, op->partials, op->red, op->cost_dev,
-                    op->img64[0], op->img64[1], op->img64[2], op->img64[3], op->sino64[0], op->sino64[1],
+                    op->img64[0], op->img64[1], op->img64[2], op->pad64[0], op->pad64[1], op->sino64[0], op->sino64[1],
                     op->sino64[2], op->sino64[3], op->sino64[4]};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (op->red_host) hipHostFree(op->red_host);
+    if (op->lz) hipFree(op->lz);
+    if (op->lz_host) hipHostFree(op->lz_host);
     delete op;
 }
 
@@ -433,6 +481,17 @@ int ctpd_ramp_filter(ctpd_op* op, double tau, double kappa, const float* s, floa
     int r = ensure_taps(op, tau, kappa);
     if (r) return r;
     return filter(op, FILT_PLAIN, s, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, 1.0f, out);
+}
+
+int ctpd_ramp_filter_f64(ctpd_op* op, double tau, double kappa, const double* s, double* out) {
+    g_errmsg[0] = 0;
+    if (!op || !s || !out) return einval("null pointer");
+    if (!(tau > 0.0) || !std::isfinite(tau)) return einval("tau must be finite and > 0");
+    if (!(kappa >= 0.0) || !std::isfinite(kappa)) return einval("kappa must be finite and >= 0");
+    int r = ensure_taps(op, tau, kappa);
+    if (r) return r;
+    HIP_TRY(launch_filter_f64(s, out, op->taps64, nullptr, nullptr, op->m, op->nb, op->stream));
+    return CTPD_OK;
 }
 
 int ctpd_filter_taps(ctpd_op* op, double tau, double kappa, double* taps_host) {
@@ -492,7 +551,7 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
     if (!(sigma > 0)) {
         if ((r = lambda_a(op, k.norm_steps, &lam_a, &steps_a))) return r;
         HIP_TRY(launch_rsqrt_f64(op->sino64[3], w, I, s));
-        if ((r = lambda_h(op, k.norm_steps, &lam_h, &steps_h))) return r;
+        if ((r = lambda_h(op, w, kappa, k.norm_steps, &lam_h, &steps_h))) return r;
         sigma = k.rho * std::min(2.0 / lam_h, 1.0 / (tau * lam_a));
     }
     if ((r = sync(op))) return r;

@@ -9,8 +9,8 @@
 // The float32 kernel fuses the dual-variable algebra around D
 // (Eqs. 18, 20, 31): the prologue forms the filter input from up to four
 // sinograms while staging it in LDS, the epilogue combines the result with up
-// to two sinograms.  A float64 VALU variant serves the operator-norm
-// computation.
+// to two sinograms.  A float64 variant (v_mfma_f64_16x16x4_f64) serves the
+// operator-norm computation.
 #include "internal.h"
 
 namespace ctpd {
@@ -190,58 +190,80 @@ hipError_t launch_filter_f32(const FilterArgs& a, const float* taps32, int m, in
 }
 
 // ---------------------------------------------------------------------------
-// float64 filter on the vector ALUs: out = post .* D (pre .* in).  Block =
-// (1024-output chunk, view); the input is streamed in 1024-bin chunks with
-// the matching 2047-tap window in LDS.  Lane l computes outputs l + 256 r.
-constexpr int F64_CH = 1024;
+// float64 filter on the matrix cores (v_mfma_f64_16x16x4_f64), for the
+// operator norms: out = post .* D (pre .* in)  (pre / post optional).
+// Same tiling as the float32 kernel (32 views x 64 bins per workgroup, wave w
+// owns rows 16*(w/2), columns 32*(w%2)); per 16-bin stage of the input the
+// workgroup keeps only the 79 taps that stage touches.  The A and B operand
+// layouts match the f32 instruction; the result differs: D[i][j] sits in lane
+// j + 16*(i%4), element i/4.
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int DBK = 16;
+constexpr int DSTRIDE = DBK + 1;
+constexpr int DTW = FBN + DBK - 1;   // taps per stage
 
 __global__ __launch_bounds__(256) void filter_f64_kernel(const double* __restrict__ in, double* __restrict__ out,
                                                          const double* __restrict__ taps,
                                                          const double* __restrict__ pre,
-                                                         const double* __restrict__ post, int nb) {
-    __shared__ double sv[F64_CH];
-    __shared__ double hw[2 * F64_CH - 1];
-    const int v = blockIdx.y, i0 = blockIdx.x * F64_CH, tid = threadIdx.x;
-    const size_t rb = (size_t)v * nb;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int j0 = 0; j0 < nb; j0 += F64_CH) {
+                                                         const double* __restrict__ post, int m, int nb) {
+    __shared__ double stile[FBM * DSTRIDE];
+    __shared__ double hw[DTW + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n0 = blockIdx.x * FBN, v0 = blockIdx.y * FBM;
+    const int wr = (wave >> 1) * 16, wc = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < nb; k0 += DBK) {
         __syncthreads();
-        for (int j = tid; j < F64_CH; j += 256) {
-            const int jj = j0 + j;
+        for (int e = tid; e < FBM * DBK; e += 256) {
+            const int r = e / DBK, cc = e - r * DBK;
+            const int v = v0 + r, j = k0 + cc;
             double val = 0.0;
-            if (jj < nb) {
-                val = in[rb + jj];
-                if (pre) val *= pre[rb + jj];
+            if (v < m && j < nb) {
+                const size_t idx = (size_t)v * nb + j;
+                val = in[idx];
+                if (pre) val *= pre[idx];
             }
-            sv[j] = val;
+            stile[r * DSTRIDE + cc] = val;
         }
-        // window: offset d = i - j in [i0 - j0 - (CH-1), i0 - j0 + (CH-1)]
-        for (int e = tid; e < 2 * F64_CH - 1; e += 256) {
-            const int d = i0 - j0 - (F64_CH - 1) + e;
+        // offsets d = col - krow in [n0 - k0 - (DBK-1), n0 - k0 + FBN - 1]
+        for (int e = tid; e < DTW; e += 256) {
+            const int d = n0 - k0 - (DBK - 1) + e;
             hw[e] = (d > -nb && d < nb) ? taps[nb - 1 + d] : 0.0;
         }
         __syncthreads();
-        for (int j = 0; j < F64_CH; ++j) {
-            const double sj = sv[j];
+        // T[krow][col] = h[col - krow] at hw[(col - n0) - (krow - k0) + DBK - 1]
+        const int hb = wc + li - lk + DBK - 1;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[r] = fma(hw[tid + 256 * r - j + F64_CH - 1], sj, acc[r]);
+        for (int kk = 0; kk < DBK; kk += 4) {
+            const double av = stile[(wr + li) * DSTRIDE + kk + lk];
+            const double b0 = hw[hb - kk];
+            const double b1 = hw[hb - kk + 16];
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, acc1, 0, 0, 0);
         }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = i0 + tid + 256 * r;
-        if (i < nb) {
-            double val = acc[r];
-            if (post) val *= post[rb + i];
-            out[rb + i] = val;
+    for (int blk = 0; blk < 2; ++blk) {
+        const v4d acc = blk ? acc1 : acc0;
+        const int col = n0 + wc + 16 * blk + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int v = v0 + wr + lk + 4 * r;   // f64 16x16x4: D[i][j] in lane j + 16*(i%4), element i/4
+            if (v < m && col < nb) {
+                const size_t idx = (size_t)v * nb + col;
+                double val = acc[r];
+                if (post) val *= post[idx];
+                out[idx] = val;
+            }
         }
     }
 }
 
 hipError_t launch_filter_f64(const double* in, double* out, const double* taps64, const double* pre,
                              const double* post, int m, int nb, hipStream_t s) {
-    dim3 grid((nb + F64_CH - 1) / F64_CH, m);
-    filter_f64_kernel<<<grid, 256, 0, s>>>(in, out, taps64, pre, post, nb);
+    dim3 grid((nb + FBN - 1) / FBN, (m + FBM - 1) / FBM);
+    filter_f64_kernel<<<grid, 256, 0, s>>>(in, out, taps64, pre, post, m, nb);
     return hipGetLastError();
 }
 

@@ -48,11 +48,13 @@ struct FilterArgs {
 };
 
 // ---- projector.hip -------------------------------------------------------
+// xp / xTp: [n][n+4] row-major copies of x and its transpose with two zero
+// pixels on each side of every row
 template <typename T>
-hipError_t launch_transpose(const T* in, T* out, int n, hipStream_t s);
-// y = len * sum_t interp(plane_t, s(t,u)); plane = x for row views, xT for column views
+hipError_t launch_pad_planes(const T* x, T* xp, T* xTp, int n, hipStream_t s);
+// y = len * sum_t interp(plane_t, s(t,u)); plane = xp for row views, xTp for column views
 template <typename T>
-hipError_t launch_forward(const T* x, const T* xT, T* y, const ViewGeom* views, int n, int m, int nb,
+hipError_t launch_forward(const T* xp, const T* xTp, T* y, const ViewGeom* views, int n, int m, int nb,
                           hipStream_t s);
 // out = alpha * xin + beta * A^T (c1 * y1 + c2 * y2)   (xin, y2 may be null)
 template <typename T>
@@ -91,7 +93,16 @@ hipError_t launch_reduce(int op, const void* a, const void* b, const void* c, si
 hipError_t launch_tv_norm(const float* x, int n, double* partials, double* dev_out, hipStream_t s);
 constexpr int kReduceBlocks = 512;
 
-hipError_t launch_start_vector(double* v, size_t len, uint64_t seed, hipStream_t s);
+// Lanczos start vector over [rows][cols]: image bump (w null) or the sinogram
+// pattern (-1)^col / (w kappa), plus counter-based noise.
+hipError_t launch_start_vector(double* v, int rows, int cols, uint64_t seed, const float* w, double inv_kappa,
+                               hipStream_t s);
+// w <- w - alpha[0] q - sqrt(beta2[0]) qp, and beta2_out[0] = ||w||^2 (device scalars)
+hipError_t launch_lanczos_update(double* w, const double* q, const double* qp, const double* alpha,
+                                 const double* beta2, size_t len, double* partials, double* beta2_out,
+                                 hipStream_t s);
+// y = x / sqrt(sumsq[0])
+hipError_t launch_normalize(double* y, const double* x, const double* sumsq, size_t len, hipStream_t s);
 // y = a*x + b*y + c*z (double; z may be null)
 hipError_t launch_axpby_f64(double* y, const double* x, double a, double b, const double* z, double c,
                             size_t len, hipStream_t s);

@@ -12,47 +12,66 @@
 namespace ctpd {
 
 // ---------------------------------------------------------------------------
-// Transpose (column views read the image along columns; keeping a transposed
-// copy makes their taps contiguous and the wave's loads coalesced).
+// Padded planes.  Row views read image rows, column views read image columns;
+// the forward projector reads both from row-major copies padded with two zero
+// pixels on each side of every row, so taps outside the image need no test:
+//   xp [t][k + 2] = x[t][k],   xTp[t][k + 2] = x[k][t],   pitch n + 4.
 template <typename T>
-__global__ __launch_bounds__(256) void transpose_kernel(const T* __restrict__ in, T* __restrict__ out, int n) {
+__global__ __launch_bounds__(256) void pad_planes_kernel(const T* __restrict__ in, T* __restrict__ xp,
+                                                         T* __restrict__ xTp, int n) {
     __shared__ T tile[32][33];
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    const int P = n + 4;
     for (int r = ty; r < 32; r += 8) {
         const int iy = by + r, ix = bx + tx;
-        if (iy < n && ix < n) tile[r][tx] = in[(size_t)iy * n + ix];
+        T val = T(0);
+        if (iy < n && ix < n) val = in[(size_t)iy * n + ix];
+        tile[r][tx] = val;
+        if (iy < n && ix < n) xp[(size_t)iy * P + ix + 2] = val;
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
-        const int ox = bx + r, oy = by + tx;   // out[ox][oy] = in[oy][ox]
-        if (ox < n && oy < n) out[(size_t)ox * n + oy] = tile[tx][r];
+        const int ox = bx + r, oy = by + tx;   // xT[ox][oy] = x[oy][ox]
+        if (ox < n && oy < n) xTp[(size_t)ox * P + oy + 2] = tile[tx][r];
+    }
+    // zero pads: block column 0 writes columns 0, 1, n+2, n+3 of its 32 rows
+    if (blockIdx.x == 0) {
+        for (int e = threadIdx.x; e < 32 * 4; e += 256) {
+            const int r = by + (e >> 2), q = e & 3;
+            const int col = q < 2 ? q : n + q;
+            if (r < n) {
+                xp[(size_t)r * P + col] = T(0);
+                xTp[(size_t)r * P + col] = T(0);
+            }
+        }
     }
 }
 
 template <typename T>
-hipError_t launch_transpose(const T* in, T* out, int n, hipStream_t s) {
+hipError_t launch_pad_planes(const T* x, T* xp, T* xTp, int n, hipStream_t s) {
     dim3 grid((n + 31) / 32, (n + 31) / 32);
-    transpose_kernel<T><<<grid, 256, 0, s>>>(in, out, n);
+    pad_planes_kernel<T><<<grid, 256, 0, s>>>(x, xp, xTp, n);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Forward projection: one lane per ray (v, u).  Consecutive lanes are
 // consecutive bins of one view, so at each step the wave reads a short
-// contiguous run of one image row (row views) or one row of the transposed
-// image (column views).
+// contiguous run of one padded row (row views) or one padded column (column
+// views).  The lane's steps are limited to those whose sample lies in (-1, n);
+// a sample index clamped to [-2, n] then always reads real or zero pixels.
 template <typename T>
-__global__ __launch_bounds__(256) void forward_kernel(const T* __restrict__ x, const T* __restrict__ xT,
+__global__ __launch_bounds__(256) void forward_kernel(const T* __restrict__ xp, const T* __restrict__ xTp,
                                                       T* __restrict__ y, const ViewGeom* __restrict__ views,
                                                       int n, int nb) {
     const int v = blockIdx.y;
     const int u = blockIdx.x * 256 + threadIdx.x;
     if (u >= nb) return;
     const ViewGeom g = views[v];
-    const T* __restrict__ plane = g.row ? x : xT;
+    const int P = n + 4;
+    const T* __restrict__ plane = (g.row ? xp : xTp) + 2;
     const double base = fma((double)u, g.su, g.s0);
-    // Steps whose sample lies in (-1, n) touch the image; outside both taps are zero.
     int t0 = 0, t1 = n - 1;
     if (g.st != 0.0) {
         const double ta = (-1.0 - base) / g.st, tb = ((double)n - base) / g.st;
@@ -64,24 +83,24 @@ __global__ __launch_bounds__(256) void forward_kernel(const T* __restrict__ x, c
         t1 = -1;
     }
     T acc = T(0);
+#pragma unroll 16
     for (int t = t0; t <= t1; ++t) {
         const double s = fma((double)t, g.st, base);
         const double fl = floor(s);
-        const int k = (int)fl;
+        const int k = min(max((int)fl, -2), n);
         const T f = (T)(s - fl);
-        const T* __restrict__ row = plane + (size_t)t * n;
-        const T a = (k >= 0 && k < n) ? row[k] : T(0);
-        const T b = (k >= -1 && k < n - 1) ? row[k + 1] : T(0);
+        const T* __restrict__ row = plane + (size_t)t * P;
+        const T a = row[k], b = row[k + 1];
         acc += a + f * (b - a);
     }
     y[(size_t)v * nb + u] = acc * (T)g.len;
 }
 
 template <typename T>
-hipError_t launch_forward(const T* x, const T* xT, T* y, const ViewGeom* views, int n, int m, int nb,
+hipError_t launch_forward(const T* xp, const T* xTp, T* y, const ViewGeom* views, int n, int m, int nb,
                           hipStream_t s) {
     dim3 grid((nb + 255) / 256, m);
-    forward_kernel<T><<<grid, 256, 0, s>>>(x, xT, y, views, n, nb);
+    forward_kernel<T><<<grid, 256, 0, s>>>(xp, xTp, y, views, n, nb);
     return hipGetLastError();
 }
 
@@ -90,53 +109,183 @@ hipError_t launch_forward(const T* x, const T* xT, T* y, const ViewGeom* views, 
 // (X, Y) and view v the Joseph weights of A are the hat function
 // max(0, 1 - |u - t|/s_v)/s_v of the distance between bin u and the pixel's
 // bin coordinate t = X cos + Y sin + (nb-1)/2, with s_v = |cos| (row views)
-// or |sin| (column views) <= 1, so at most the bins floor(t), floor(t)+1 carry
+// or |sin| (column views) <= 1, so only bins floor(t), floor(t)+1 carry
 // weight.  out = alpha * xin + beta * A^T (c1 y1 + c2 y2).
+//
+// Workgroup: a 32 x 32 pixel tile, 512 lanes in two halves; half h takes the
+// view chunks h, h+2, ... and its lane (tx, ty) owns pixels
+// (x0 + tx, y0 + ty + 8j), j = 0..3.  For each chunk of 16 views the half
+// stages, per view, the 48 bins starting one below the tile's lowest bin
+// coordinate (the tile spans at most 31 sqrt(2) + 2 bins), zero outside the
+// detector, so the inner loop reads LDS without bounds tests.  The next
+// chunk's bins are loaded into registers while the current chunk is used.
+// The halves are summed through LDS at the end (deterministic).
+constexpr int AT_T = 32;
+constexpr int AT_VC = 16;
+constexpr int AT_W = 48;
+constexpr int AT_PER = AT_VC * AT_W / 256;
+
+struct TileBox {
+    double xlo, xhi, ylo, yhi, cd;
+};
+
+// First staged bin of view g for the tile (one below floor of the lowest t).
+__device__ __forceinline__ int window_base(const ViewGeom& g, const TileBox& b) {
+    const double tmin = b.cd + (g.cs >= 0.0 ? b.xlo * g.cs : b.xhi * g.cs) + (g.sn >= 0.0 ? b.ylo * g.sn : b.yhi * g.sn);
+    return (int)floor(tmin) - 1;
+}
+
 template <typename T, bool TWO>
-__global__ __launch_bounds__(256) void adjoint_kernel(const T* __restrict__ y1, const T* __restrict__ y2, T c1,
+__global__ __launch_bounds__(512) void adjoint_kernel(const T* __restrict__ y1, const T* __restrict__ y2, T c1,
                                                       T c2, const T* __restrict__ xin, T alpha, T beta,
                                                       T* __restrict__ out, const ViewGeom* __restrict__ views,
                                                       int n, int m, int nb) {
-    const int ix = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int iy = blockIdx.y * 16 + (threadIdx.x >> 4);
-    if (ix >= n || iy >= n) return;
-    const double c = 0.5 * (double)(n - 1), cd = 0.5 * (double)(nb - 1);
-    const double X = (double)ix - c, Y = (double)iy - c;
-    T acc = T(0);
-    for (int v = 0; v < m; ++v) {
-        const ViewGeom g = views[v];
-        const double t = fma(X, g.cs, fma(Y, g.sn, cd));
-        const double fl = floor(t);
-        const int u0 = (int)fl;
-        const T f = (T)(t - fl);
-        const T len = (T)g.len, len2 = (T)g.len2;
-        const T w0 = fmax(T(0), len - f * len2);
-        const T w1 = fmax(T(0), len - (T(1) - f) * len2);
-        const size_t rb = (size_t)v * nb;
-        T a = T(0), b = T(0);
-        if (u0 >= 0 && u0 < nb) a = TWO ? c1 * y1[rb + u0] + c2 * y2[rb + u0] : y1[rb + u0];
-        if (u0 >= -1 && u0 < nb - 1) b = TWO ? c1 * y1[rb + u0 + 1] + c2 * y2[rb + u0 + 1] : y1[rb + u0 + 1];
-        acc += w0 * a + w1 * b;
+    __shared__ T win[2][AT_VC][AT_W];
+    __shared__ double pt0[2][AT_VC], pcs[2][AT_VC], psn[2][AT_VC];
+    __shared__ T plen[2][AT_VC], plen2[2][AT_VC];
+    const int tid = threadIdx.x, h = tid >> 8, l = tid & 255;
+    const int tx = l & 31, ty = l >> 5;
+    const int x0 = blockIdx.x * AT_T, y0 = blockIdx.y * AT_T;
+    const double c = 0.5 * (double)(n - 1);
+    const TileBox box{x0 - c, x0 + (AT_T - 1) - c, y0 - c, y0 + (AT_T - 1) - c, 0.5 * (double)(nb - 1)};
+    const int nchunk = (m + AT_VC - 1) / AT_VC;
+    const int nsteps = (nchunk + 1) / 2;
+
+    T stg[AT_PER];
+    auto fetch = [&](int ch) {
+#pragma unroll
+        for (int r = 0; r < AT_PER; ++r) {
+            const int e = l + 256 * r;
+            const int i = e / AT_W, k = e - i * AT_W;
+            const int v = ch * AT_VC + i;
+            T val = T(0);
+            if (ch < nchunk && v < m) {
+                const int u = window_base(views[v], box) + k;
+                if (u >= 0 && u < nb) {
+                    const size_t idx = (size_t)v * nb + u;
+                    val = TWO ? c1 * y1[idx] + c2 * y2[idx] : y1[idx];
+                }
+            }
+            stg[r] = val;
+        }
+    };
+    auto commit = [&](int ch) {
+#pragma unroll
+        for (int r = 0; r < AT_PER; ++r) {
+            const int e = l + 256 * r;
+            const int i = e / AT_W;
+            win[h][i][e - i * AT_W] = stg[r];
+        }
+        if (l < AT_VC) {
+            const int v = ch * AT_VC + l;
+            if (ch < nchunk && v < m) {
+                const ViewGeom g = views[v];
+                const int ub = window_base(g, box);
+                pt0[h][l] = fma(box.xlo, g.cs, fma(box.ylo, g.sn, box.cd)) - (double)ub;
+                pcs[h][l] = g.cs;
+                psn[h][l] = g.sn;
+                plen[h][l] = (T)g.len;
+                plen2[h][l] = (T)g.len2;
+            } else {   // past the last view: zero weights on a zero window
+                pt0[h][l] = 1.5;
+                pcs[h][l] = 0.0;
+                psn[h][l] = 0.0;
+                plen[h][l] = T(0);
+                plen2[h][l] = T(0);
+            }
+        }
+    };
+
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+    fetch(h);
+    commit(h);
+    __syncthreads();
+    for (int st = 0; st < nsteps; ++st) {
+        const int ch = h + 2 * st;
+        fetch(ch + 2);
+        if (ch < nchunk) {
+            // two views x four pixels per pass: all eight LDS reads are independent
+#pragma unroll 1
+            for (int i = 0; i < AT_VC; i += 2) {
+                double t[2][4];
+                int k[2][4];
+                T f[2][4], a[2][4], b[2][4], len[2], len2[2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const double cs = pcs[h][i + q], sn = psn[h][i + q];
+                    const double tb = fma((double)tx, cs, fma((double)ty, sn, pt0[h][i + q]));
+                    len[q] = plen[h][i + q];
+                    len2[q] = plen2[h][i + q];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) t[q][j] = fma((double)(8 * j), sn, tb);
+                }
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        k[q][j] = (int)t[q][j];                       // t >= 1 - rounding: trunc == floor
+                        f[q][j] = (T)(t[q][j] - (double)k[q][j]);
+                    }
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        a[q][j] = win[h][i + q][k[q][j]];
+                        b[q][j] = win[h][i + q][k[q][j] + 1];
+                    }
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const T cc = len[q] - len2[q];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const T w0 = fmax(T(0), len[q] - f[q][j] * len2[q]);
+                        const T w1 = fmax(T(0), cc + f[q][j] * len2[q]);
+                        acc[j] = fma(w0, a[q][j], fma(w1, b[q][j], acc[j]));
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        commit(ch + 2);
+        __syncthreads();
     }
-    const size_t idx = (size_t)iy * n + ix;
-    T r = beta * acc;
-    if (xin) r += alpha * xin[idx];
-    out[idx] = r;
+    // sum the halves through LDS (reusing the staging buffer)
+    T* red = &win[0][0][0];
+    static_assert(2 * AT_VC * AT_W >= AT_T * AT_T, "reduction buffer");
+    if (h == 1) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) red[(ty + 8 * j) * AT_T + tx] = acc[j];
+    }
+    __syncthreads();
+    if (h == 0) {
+        const int ix = x0 + tx;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int iy = y0 + ty + 8 * j;
+            if (ix < n && iy < n) {
+                const T sum = acc[j] + red[(ty + 8 * j) * AT_T + tx];
+                const size_t idx = (size_t)iy * n + ix;
+                T r = beta * sum;
+                if (xin) r += alpha * xin[idx];
+                out[idx] = r;
+            }
+        }
+    }
 }
 
 template <typename T>
 hipError_t launch_adjoint(const T* y1, const T* y2, T c1, T c2, const T* xin, T alpha, T beta, T* out,
                           const ViewGeom* views, int n, int m, int nb, hipStream_t s) {
-    dim3 grid((n + 15) / 16, (n + 15) / 16);
+    dim3 grid((n + AT_T - 1) / AT_T, (n + AT_T - 1) / AT_T);
     if (y2)
-        adjoint_kernel<T, true><<<grid, 256, 0, s>>>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb);
+        adjoint_kernel<T, true><<<grid, 512, 0, s>>>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb);
     else
-        adjoint_kernel<T, false><<<grid, 256, 0, s>>>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb);
+        adjoint_kernel<T, false><<<grid, 512, 0, s>>>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb);
     return hipGetLastError();
 }
 
-template hipError_t launch_transpose<float>(const float*, float*, int, hipStream_t);
-template hipError_t launch_transpose<double>(const double*, double*, int, hipStream_t);
+template hipError_t launch_pad_planes<float>(const float*, float*, float*, int, hipStream_t);
+template hipError_t launch_pad_planes<double>(const double*, double*, double*, int, hipStream_t);
 template hipError_t launch_forward<float>(const float*, const float*, float*, const ViewGeom*, int, int, int,
                                           hipStream_t);
 template hipError_t launch_forward<double>(const double*, const double*, double*, const ViewGeom*, int, int,

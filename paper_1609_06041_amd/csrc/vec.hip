@@ -134,20 +134,92 @@ hipError_t launch_tv_norm(const float* x, int n, double* partials, double* dev_o
     return hipGetLastError();
 }
 
-// SplitMix64 (Steele, Lea, Flood 2014) as a counter-based generator:
-// v[i] = top 53 bits of mix(seed + (i+1) * golden) in [0, 1), minus 1/2.
-__global__ __launch_bounds__(256) void start_vector_kernel(double* __restrict__ v, size_t len, uint64_t seed) {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= len) return;
-    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+// SplitMix64 (Steele, Lea, Flood 2014) as a counter-based generator.
+__device__ __forceinline__ double splitmix_unit(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
-    v[i] = (double)(z >> 11) * 0x1.0p-53 - 0.5;
+    return (double)(z >> 11) * 0x1.0p-53;   // [0, 1)
 }
 
-hipError_t launch_start_vector(double* v, size_t len, uint64_t seed, hipStream_t s) {
-    start_vector_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(v, len, seed);
+// Lanczos start vectors: a shape close to the expected top eigenvector plus
+// 5% counter-based noise (so no eigenvector is missed).
+//   image space (n x n): Gaussian bump of width n/4 at the centre -- the
+//     ramp-preconditioned A^T D A has its largest eigenvalues at the lowest
+//     spatial frequencies;
+//   sinogram space ([rows][cols], weights w): (-1)^u / (w kappa) -- the filter
+//     response peaks at the Nyquist frequency and W^-1 favours low counts.
+__global__ __launch_bounds__(256) void start_vector_kernel(double* __restrict__ v, int rows, int cols, uint64_t seed,
+                                                           const float* __restrict__ w, double inv_kappa) {
+    const size_t len = (size_t)rows * cols;
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= len) return;
+    const int r = (int)(i / cols), c = (int)(i - (size_t)r * cols);
+    double shape;
+    if (w) {
+        shape = ((c & 1) ? -1.0 : 1.0) * inv_kappa / (double)w[i];
+    } else {
+        const double h = 0.5 * (cols - 1), s = 0.25 * cols;
+        const double dx = c - h, dy = r - h;
+        shape = exp(-(dx * dx + dy * dy) / (2.0 * s * s));
+    }
+    v[i] = shape + 0.05 * (splitmix_unit(seed, i) - 0.5);
+}
+
+hipError_t launch_start_vector(double* v, int rows, int cols, uint64_t seed, const float* w, double inv_kappa,
+                               hipStream_t s) {
+    const size_t len = (size_t)rows * cols;
+    start_vector_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(v, rows, cols, seed, w, inv_kappa);
+    return hipGetLastError();
+}
+
+// One Lanczos orthogonalisation with device-resident scalars:
+//   w <- w - alpha q - beta qp,  beta = sqrt(beta2[0]) (qp, beta2 may be null),
+// with block partial sums of w'^2 for the next beta.
+__global__ __launch_bounds__(256) void lanczos_update_kernel(double* __restrict__ w, const double* __restrict__ q,
+                                                             const double* __restrict__ qp,
+                                                             const double* __restrict__ alpha,
+                                                             const double* __restrict__ beta2, size_t len,
+                                                             double* __restrict__ partials) {
+    const double a = alpha[0];
+    const double b = (qp && beta2) ? sqrt(beta2[0]) : 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < len; i += stride) {
+        double r = w[i] - a * q[i];
+        if (qp) r -= b * qp[i];
+        w[i] = r;
+        s0 = fma(r, r, s0);
+    }
+    block_sum3(s0, s1, s2);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x + 0] = s0;
+        partials[3 * blockIdx.x + 1] = 0.0;
+        partials[3 * blockIdx.x + 2] = 0.0;
+    }
+}
+
+hipError_t launch_lanczos_update(double* w, const double* q, const double* qp, const double* alpha,
+                                 const double* beta2, size_t len, double* partials, double* beta2_out,
+                                 hipStream_t s) {
+    const int nb = reduce_blocks(len);
+    lanczos_update_kernel<<<nb, 256, 0, s>>>(w, q, qp, alpha, beta2, len, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    reduce_final_kernel<<<1, 256, 0, s>>>(partials, nb, beta2_out);
+    return hipGetLastError();
+}
+
+// y = x / sqrt(sumsq[0])
+__global__ __launch_bounds__(256) void normalize_kernel(double* __restrict__ y, const double* __restrict__ x,
+                                                        const double* __restrict__ sumsq, size_t len) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < len) y[i] = x[i] / sqrt(sumsq[0]);
+}
+
+hipError_t launch_normalize(double* y, const double* x, const double* sumsq, size_t len, hipStream_t s) {
+    normalize_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(y, x, sumsq, len);
     return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ _SIGNATURES = {
     "ctpd_project": (c_int, [c_void_p, c_void_p, c_void_p]),
     "ctpd_backproject": (c_int, [c_void_p, c_void_p, c_void_p]),
     "ctpd_ramp_filter": (c_int, [c_void_p, c_double, c_double, c_void_p, c_void_p]),
+    "ctpd_ramp_filter_f64": (c_int, [c_void_p, c_double, c_double, c_void_p, c_void_p]),
     "ctpd_filter_taps": (c_int, [c_void_p, c_double, c_double, POINTER(c_double)]),
     "ctpd_tv_prox": (c_int, [c_void_p, c_void_p, c_double, c_int32, c_double, c_void_p, c_void_p]),
     "ctpd_pd_lowdose_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p,
@@ -95,6 +96,14 @@ def _ptr(t: torch.Tensor, shape, name: str) -> c_void_p:
     return c_void_p(t.data_ptr())
 
 
+def _ptr64(t: torch.Tensor, shape, name: str) -> c_void_p:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 torch.Tensor")
+    if t.device.type != "cuda" or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous GPU tensor of shape {tuple(shape)}")
+    return c_void_p(t.data_ptr())
+
+
 def _params(tau, sigma, tv_iters, tv_step, safety, norm_steps, record_cost) -> Params:
     return Params(tau=float(tau or 0.0), sigma=float(sigma or 0.0), tv_step=float(tv_step or 0.0),
                   safety=float(safety or 0.0), tv_iters=int(tv_iters or 0), norm_steps=int(norm_steps or 0),
@@ -155,6 +164,13 @@ class Operator:
         out = self._sino() if out is None else out
         _check(load().ctpd_ramp_filter(self._h, float(tau), float(kappa), _ptr(s, (self.m, self.nb), "s"),
                                        _ptr(out, (self.m, self.nb), "out")))
+        return out
+
+    def ramp_filter_f64(self, s: torch.Tensor, tau: float, kappa: float = 0.0,
+                        out: torch.Tensor | None = None) -> torch.Tensor:
+        out = torch.empty((self.m, self.nb), dtype=torch.float64, device=self.device) if out is None else out
+        _check(load().ctpd_ramp_filter_f64(self._h, float(tau), float(kappa), _ptr64(s, (self.m, self.nb), "s"),
+                                           _ptr64(out, (self.m, self.nb), "out")))
         return out
 
     def filter_taps(self, tau: float, kappa: float = 0.0) -> np.ndarray:

@@ -55,6 +55,7 @@ def test_null_arguments_are_rejected(libctpd):
     assert libctpd.ctpd_backproject(None, None, None) == ctpd.CTPD_EINVAL
     assert libctpd.ctpd_ramp_filter(None, 1.0, 0.0, None, None) == ctpd.CTPD_EINVAL
     assert libctpd.ctpd_filter_taps(None, 1.0, 0.0, None) == ctpd.CTPD_EINVAL
+    assert libctpd.ctpd_ramp_filter_f64(None, 1.0, 0.0, None, None) == ctpd.CTPD_EINVAL
     assert libctpd.ctpd_tv_prox(None, None, 0.1, 1, 0.125, None, None) == ctpd.CTPD_EINVAL
     assert libctpd.ctpd_pd_lowdose_solve(None, None, None, 0.1, 1, None, None, None) == ctpd.CTPD_EINVAL
     assert libctpd.ctpd_pd_fewview_solve(None, None, 1, None, None, None) == ctpd.CTPD_EINVAL

@@ -110,6 +110,20 @@ def test_ramp_filter_matches_oracle(gpu, m, nb, kappa):
     assert rel(out, ref) <= TOL, rel(out, ref)
 
 
+@pytest.mark.parametrize("m,nb,kappa", [(90, 96, 1.6e-4), (720, 736, 0.0), (5, 37, 0.02), (33, 65, 0.0),
+                                        (1, 1, 0.1), (47, 130, 0.3)])
+def test_ramp_filter_f64_matches_oracle(gpu, m, nb, kappa):
+    rng = np.random.default_rng(m * nb + 1)
+    s = rng.standard_normal((m, nb))
+    tau = 0.7 if kappa == 0.0 else math.pi * kappa / (2 * m)
+    with ctpd.Operator(8, m, nb) as op:
+        out = op.ramp_filter_f64(torch.from_numpy(s).cuda(), tau, kappa)
+        torch.cuda.synchronize()
+        out = out.cpu().numpy()
+    ref = OF.apply_filter(s, OF.smoothed_ramp_taps(nb, m, tau, kappa))
+    assert rel(out, ref) <= 1e-12, rel(out, ref)
+
+
 def test_ramp_filter_on_phantom_sinogram(gpu):
     n, m, nb = 512, 720, 736
     prob = S.make_problem(1, 0, n, m, nb, 20, 5e4, with_x_true=False)
