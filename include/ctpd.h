@@ -51,7 +51,7 @@ typedef struct ctpd_op ctpd_op;
 
 /* Scan geometry (Sec. 2.1: parallel-beam, m views over [0, pi)). */
 typedef struct {
-    int32_t n;        /* image side, 1 <= n <= 16384 */
+    int32_t n;        /* image side, 1 <= n <= 8192 */
     int32_t n_views;  /* m >= 1 */
     int32_t n_bins;   /* 1 <= n_bins <= CTPD_MAX_BINS */
 } ctpd_geometry;

@@ -20,10 +20,10 @@ struct ctpd_op {
     hipStream_t stream = nullptr;
     int device = 0;
     size_t J = 0, I = 0;   // image / sinogram sizes
-    size_t Jp = 0;         // padded plane size n * (n + 4)
+    size_t Jp = 0;         // padded plane size n * (n + 6)
     ViewGeom* views = nullptr;
     // float32 iteration state
-    float* xp = nullptr;    // padded image planes for the forward projector, [n][n+4] each
+    float* xp = nullptr;    // padded image planes for the forward projector, [n][n+6] each
     float* xTp = nullptr;
     float* x = nullptr;
     float* z = nullptr;
@@ -402,7 +402,7 @@ const char* ctpd_strerror(int code) {
 int ctpd_op_create(const ctpd_geometry* g, void* stream, ctpd_op** out) {
     g_errmsg[0] = 0;
     if (!g || !out) return einval("null pointer");
-    if (g->n < 1 || g->n > 16384) return einval("n out of range [1, 16384]");
+    if (g->n < 1 || g->n > 8192) return einval("n out of range [1, 8192]");
     if (g->n_views < 1 || g->n_views > 1000000) return einval("n_views out of range");
     if (g->n_bins < 1 || g->n_bins > CTPD_MAX_BINS) return einval("n_bins out of range");
     *out = nullptr;
@@ -412,7 +412,7 @@ int ctpd_op_create(const ctpd_geometry* g, void* stream, ctpd_op** out) {
     op->nb = g->n_bins;
     op->stream = (hipStream_t)stream;
     op->J = (size_t)op->n * op->n;
-    op->Jp = (size_t)op->n * (op->n + 4);
+    op->Jp = (size_t)op->n * (op->n + 6);
     op->I = (size_t)op->m * op->nb;
     auto init = [&]() -> int {
         HIP_TRY(hipGetDevice(&op->device));

@@ -48,7 +48,7 @@ struct FilterArgs {
 };
 
 // ---- projector.hip -------------------------------------------------------
-// xp / xTp: [n][n+4] row-major copies of x and its transpose with two zero
+// xp / xTp: [n][n+6] row-major copies of x and its transpose with three zero
 // pixels on each side of every row
 template <typename T>
 hipError_t launch_pad_planes(const T* x, T* xp, T* xTp, int n, hipStream_t s);

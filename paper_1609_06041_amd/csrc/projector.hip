@@ -13,33 +13,36 @@ namespace ctpd {
 
 // ---------------------------------------------------------------------------
 // Padded planes.  Row views read image rows, column views read image columns;
-// the forward projector reads both from row-major copies padded with two zero
-// pixels on each side of every row, so taps outside the image need no test:
-//   xp [t][k + 2] = x[t][k],   xTp[t][k + 2] = x[k][t],   pitch n + 4.
+// the forward projector reads both from row-major copies padded with FP_PAD
+// zero pixels on each side of every row, so taps outside the image need no
+// test:  xp[t][k + FP_PAD] = x[t][k],  xTp[t][k + FP_PAD] = x[k][t],
+// pitch n + 2 FP_PAD.
+constexpr int FP_PAD = 3;
+
 template <typename T>
 __global__ __launch_bounds__(256) void pad_planes_kernel(const T* __restrict__ in, T* __restrict__ xp,
                                                          T* __restrict__ xTp, int n) {
     __shared__ T tile[32][33];
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
-    const int P = n + 4;
+    const int P = n + 2 * FP_PAD;
     for (int r = ty; r < 32; r += 8) {
         const int iy = by + r, ix = bx + tx;
         T val = T(0);
         if (iy < n && ix < n) val = in[(size_t)iy * n + ix];
         tile[r][tx] = val;
-        if (iy < n && ix < n) xp[(size_t)iy * P + ix + 2] = val;
+        if (iy < n && ix < n) xp[(size_t)iy * P + ix + FP_PAD] = val;
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
         const int ox = bx + r, oy = by + tx;   // xT[ox][oy] = x[oy][ox]
-        if (ox < n && oy < n) xTp[(size_t)ox * P + oy + 2] = tile[tx][r];
+        if (ox < n && oy < n) xTp[(size_t)ox * P + oy + FP_PAD] = tile[tx][r];
     }
-    // zero pads: block column 0 writes columns 0, 1, n+2, n+3 of its 32 rows
+    // zero pads: the blocks of the first block column write the pad columns of their rows
     if (blockIdx.x == 0) {
-        for (int e = threadIdx.x; e < 32 * 4; e += 256) {
-            const int r = by + (e >> 2), q = e & 3;
-            const int col = q < 2 ? q : n + q;
+        for (int e = threadIdx.x; e < 32 * 2 * FP_PAD; e += 256) {
+            const int r = by + e / (2 * FP_PAD), q = e % (2 * FP_PAD);
+            const int col = q < FP_PAD ? q : n + q;
             if (r < n) {
                 xp[(size_t)r * P + col] = T(0);
                 xTp[(size_t)r * P + col] = T(0);
@@ -56,44 +59,107 @@ hipError_t launch_pad_planes(const T* x, T* xp, T* xTp, int n, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Forward projection: one lane per ray (v, u).  Consecutive lanes are
-// consecutive bins of one view, so at each step the wave reads a short
-// contiguous run of one padded row (row views) or one padded column (column
-// views).  The lane's steps are limited to those whose sample lies in (-1, n);
-// a sample index clamped to [-2, n] then always reads real or zero pixels.
+// Forward projection: one lane per ray (v, u), 256 consecutive bins of one
+// view per workgroup, so at each step a wave reads a short contiguous run of
+// one padded row (row views) or padded column (column views).
+//
+// The wave steps through the union of its rays' step ranges together (the
+// row offset is then a scalar), and each lane carries its sample position in
+// 32.32 fixed point, biased by FP_PAD so that the integer part is the padded
+// column: one 64-bit add per step, the fraction converted straight from the
+// low word.  The per-step increment is rounded to 2^-32 pixel, so after n
+// steps the position is off by at most n * 2^-33 -- far below float32
+// resolution.  A lane outside its own range clamps its column into the zero
+// pad (one unsigned min: negative columns wrap to the right pad), so it adds
+// exact zeros.  Taps are fetched with raw buffer loads: 32-bit lane offset,
+// scalar row offset, both taps in one 8-byte (16-byte for float64) load.
+typedef float v2f_t __attribute__((ext_vector_type(2)));
+typedef double v2d_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void load_taps(const __amdgpu_buffer_rsrc_t& rs, unsigned voff, int soff, float& a,
+                                          float& b) {
+    const v2f_t ab = __builtin_bit_cast(v2f_t, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+    a = ab.x;
+    b = ab.y;
+}
+
+__device__ __forceinline__ void load_taps(const __amdgpu_buffer_rsrc_t& rs, unsigned voff, int soff, double& a,
+                                          double& b) {
+    const v2d_t ab = __builtin_bit_cast(v2d_t, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
+    a = ab.x;
+    b = ab.y;
+}
+
+// Buffer resource word 3 for raw (untyped) buffers on CDNA.
+constexpr int kBufferRsrcWord3 = 0x00020000;
+constexpr int FW_BATCH = 8;
+
 template <typename T>
 __global__ __launch_bounds__(256) void forward_kernel(const T* __restrict__ xp, const T* __restrict__ xTp,
                                                       T* __restrict__ y, const ViewGeom* __restrict__ views,
                                                       int n, int nb) {
     const int v = blockIdx.y;
     const int u = blockIdx.x * 256 + threadIdx.x;
-    if (u >= nb) return;
     const ViewGeom g = views[v];
-    const int P = n + 4;
-    const T* __restrict__ plane = (g.row ? xp : xTp) + 2;
-    const double base = fma((double)u, g.su, g.s0);
-    int t0 = 0, t1 = n - 1;
-    if (g.st != 0.0) {
-        const double ta = (-1.0 - base) / g.st, tb = ((double)n - base) / g.st;
-        const double lo = fmin(fmax(fmin(ta, tb) - 1.0, 0.0), (double)n);
-        const double hi = fmax(fmin(fmax(ta, tb) + 1.0, (double)(n - 1)), -1.0);
-        t0 = (int)floor(lo);
-        t1 = (int)ceil(hi);
-    } else if (!(base > -1.0 && base < (double)n)) {
-        t1 = -1;
+    const int P = n + 2 * FP_PAD;
+    const double base = fma((double)min(u, nb - 1), g.su, g.s0);
+    // this ray's steps whose sample lies within one step of (-1, n)
+    int t0 = n, t1 = -1;
+    if (u < nb) {
+        if (g.st != 0.0) {
+            const double ta = (-1.0 - base) / g.st, tb = ((double)n - base) / g.st;
+            const double lo = fmin(fmax(fmin(ta, tb), -1.0), (double)n);
+            const double hi = fmin(fmax(fmax(ta, tb), -1.0), (double)n);
+            t0 = max(0, (int)floor(lo));
+            t1 = min(n - 1, (int)ceil(hi));
+        } else if (base > -1.0 && base < (double)n) {
+            t0 = 0;
+            t1 = n - 1;
+        }
     }
-    T acc = T(0);
-#pragma unroll 16
-    for (int t = t0; t <= t1; ++t) {
-        const double s = fma((double)t, g.st, base);
-        const double fl = floor(s);
-        const int k = min(max((int)fl, -2), n);
-        const T f = (T)(s - fl);
-        const T* __restrict__ row = plane + (size_t)t * P;
-        const T a = row[k], b = row[k + 1];
-        acc += a + f * (b - a);
+    for (int off = 32; off > 0; off >>= 1) {
+        t0 = min(t0, __shfl_xor(t0, off));
+        t1 = max(t1, __shfl_xor(t1, off));
     }
-    y[(size_t)v * nb + u] = acc * (T)g.len;
+    t0 = __builtin_amdgcn_readfirstlane(t0);
+    t1 = __builtin_amdgcn_readfirstlane(t1);
+    const double two32 = 4294967296.0;
+    unsigned long long sfix = (unsigned long long)llrint((fma((double)t0, g.st, base) + FP_PAD) * two32);
+    const unsigned long long dfix = (unsigned long long)llrint(g.st * two32);
+    const unsigned cmax = (unsigned)(P - 2);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(g.row ? xp : xTp), (short)0, (int)((size_t)n * P * sizeof(T)), kBufferRsrcWord3);
+    const int rowstride = P * (int)sizeof(T);
+    int rowb = t0 * rowstride;
+    T acc_a = T(0), acc_d = T(0);   // sum of left taps, sum of low-word * (right - left)
+    int t = t0;
+    for (; t + FW_BATCH - 1 <= t1; t += FW_BATCH) {
+        unsigned off[FW_BATCH];
+        T lf[FW_BATCH], a[FW_BATCH], b[FW_BATCH];
+#pragma unroll
+        for (int q = 0; q < FW_BATCH; ++q) {
+            off[q] = min((unsigned)(sfix >> 32), cmax) * (unsigned)sizeof(T);
+            lf[q] = (T)(unsigned)sfix;
+            sfix += dfix;
+        }
+#pragma unroll
+        for (int q = 0; q < FW_BATCH; ++q) load_taps(rs, off[q], rowb + q * rowstride, a[q], b[q]);
+#pragma unroll
+        for (int q = 0; q < FW_BATCH; ++q) {
+            acc_a += a[q];
+            acc_d = fma(lf[q], b[q] - a[q], acc_d);
+        }
+        rowb += FW_BATCH * rowstride;
+    }
+    for (; t <= t1; ++t) {
+        T a, b;
+        load_taps(rs, min((unsigned)(sfix >> 32), cmax) * (unsigned)sizeof(T), rowb, a, b);
+        acc_a += a;
+        acc_d = fma((T)(unsigned)sfix, b - a, acc_d);
+        sfix += dfix;
+        rowb += rowstride;
+    }
+    if (u < nb) y[(size_t)v * nb + u] = (acc_a + acc_d * (T)2.3283064365386962890625e-10) * (T)g.len;
 }
 
 template <typename T>
@@ -141,7 +207,7 @@ __global__ __launch_bounds__(512) void adjoint_kernel(const T* __restrict__ y1, 
                                                       T* __restrict__ out, const ViewGeom* __restrict__ views,
                                                       int n, int m, int nb) {
     __shared__ T win[2][AT_VC][AT_W];
-    __shared__ double pt0[2][AT_VC], pcs[2][AT_VC], psn[2][AT_VC];
+    __shared__ long long pt0[2][AT_VC], pcs[2][AT_VC], psn[2][AT_VC];
     __shared__ T plen[2][AT_VC], plen2[2][AT_VC];
     const int tid = threadIdx.x, h = tid >> 8, l = tid & 255;
     const int tx = l & 31, ty = l >> 5;
@@ -150,6 +216,7 @@ __global__ __launch_bounds__(512) void adjoint_kernel(const T* __restrict__ y1, 
     const TileBox box{x0 - c, x0 + (AT_T - 1) - c, y0 - c, y0 + (AT_T - 1) - c, 0.5 * (double)(nb - 1)};
     const int nchunk = (m + AT_VC - 1) / AT_VC;
     const int nsteps = (nchunk + 1) / 2;
+    const double two32 = 4294967296.0;
 
     T stg[AT_PER];
     auto fetch = [&](int ch) {
@@ -169,6 +236,9 @@ __global__ __launch_bounds__(512) void adjoint_kernel(const T* __restrict__ y1, 
             stg[r] = val;
         }
     };
+    // Per view: the tile origin's bin coordinate relative to the window, and
+    // the per-pixel increments, in 32.32 fixed point (the weights absorb the
+    // 2^-32 of the fraction through plen2).
     auto commit = [&](int ch) {
 #pragma unroll
         for (int r = 0; r < AT_PER; ++r) {
@@ -181,15 +251,16 @@ __global__ __launch_bounds__(512) void adjoint_kernel(const T* __restrict__ y1, 
             if (ch < nchunk && v < m) {
                 const ViewGeom g = views[v];
                 const int ub = window_base(g, box);
-                pt0[h][l] = fma(box.xlo, g.cs, fma(box.ylo, g.sn, box.cd)) - (double)ub;
-                pcs[h][l] = g.cs;
-                psn[h][l] = g.sn;
+                const double t0 = fma(box.xlo, g.cs, fma(box.ylo, g.sn, box.cd)) - (double)ub;
+                pt0[h][l] = llrint(t0 * two32);
+                pcs[h][l] = llrint(g.cs * two32);
+                psn[h][l] = llrint(g.sn * two32);
                 plen[h][l] = (T)g.len;
-                plen2[h][l] = (T)g.len2;
+                plen2[h][l] = (T)(g.len2 / two32);
             } else {   // past the last view: zero weights on a zero window
-                pt0[h][l] = 1.5;
-                pcs[h][l] = 0.0;
-                psn[h][l] = 0.0;
+                pt0[h][l] = 3ll << 31;
+                pcs[h][l] = 0;
+                psn[h][l] = 0;
                 plen[h][l] = T(0);
                 plen2[h][l] = T(0);
             }
@@ -207,25 +278,23 @@ __global__ __launch_bounds__(512) void adjoint_kernel(const T* __restrict__ y1, 
             // two views x four pixels per pass: all eight LDS reads are independent
 #pragma unroll 1
             for (int i = 0; i < AT_VC; i += 2) {
-                double t[2][4];
-                int k[2][4];
+                unsigned k[2][4];
                 T f[2][4], a[2][4], b[2][4], len[2], len2[2];
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    const double cs = pcs[h][i + q], sn = psn[h][i + q];
-                    const double tb = fma((double)tx, cs, fma((double)ty, sn, pt0[h][i + q]));
+                    const long long sn = psn[h][i + q];
+                    const unsigned long long tb =
+                        (unsigned long long)(pt0[h][i + q] + (long long)tx * pcs[h][i + q] + (long long)ty * sn);
                     len[q] = plen[h][i + q];
                     len2[q] = plen2[h][i + q];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) t[q][j] = fma((double)(8 * j), sn, tb);
-                }
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-#pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        k[q][j] = (int)t[q][j];                       // t >= 1 - rounding: trunc == floor
-                        f[q][j] = (T)(t[q][j] - (double)k[q][j]);
+                        // t >= 1 - rounding > 0, so the high word is floor(t)
+                        const unsigned long long tj = tb + (unsigned long long)((long long)(8 * j) * sn);
+                        k[q][j] = (unsigned)(tj >> 32);
+                        f[q][j] = (T)(unsigned)tj;
                     }
+                }
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
 #pragma unroll
@@ -235,7 +304,7 @@ __global__ __launch_bounds__(512) void adjoint_kernel(const T* __restrict__ y1, 
                     }
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    const T cc = len[q] - len2[q];
+                    const T cc = len[q] - len2[q] * (T)two32;
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const T w0 = fmax(T(0), len[q] - f[q][j] * len2[q]);
