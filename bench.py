@@ -132,6 +132,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--op-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counters", action="store_true",
+                    help="short run for rocprofv3 --pmc: a plain 256 MiB device copy (counter calibration) "
+                         "followed by 5 A^T launches on the workload; prints nothing else")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -154,6 +157,17 @@ def main() -> int:
     w = torch.from_numpy(w32).to(dev)
     op = ctpd.Operator(n, m, nb)
     stream = op.stream
+    if args.counters:
+        src = torch.ones(64 * 1024 * 1024, device=dev, dtype=torch.float32)   # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        img_out = torch.empty((n, n), device=dev, dtype=torch.float32)
+        for _ in range(5):
+            op.backproject(b, out=img_out)
+        torch.cuda.synchronize()
+        op.close()
+        log("counter run done")
+        return 0
 
     log(f"warmup: {args.warmup} solve(s)")
     for _ in range(args.warmup):

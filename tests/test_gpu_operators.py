@@ -41,7 +41,7 @@ def f32(a):
     return np.asarray(a, dtype=np.float32).astype(np.float64)
 
 
-GEOMS = [(1, 1, 1), (7, 5, 11), (64, 90, 96), (100, 36, 143), (129, 33, 200), (64, 32, 96)]
+GEOMS = [(1, 1, 1), (7, 5, 11), (64, 90, 96), (100, 36, 143), (129, 33, 200), (64, 32, 96), (384, 720, 546)]
 
 
 @pytest.mark.parametrize("n,m,nb", GEOMS)
