@@ -125,6 +125,147 @@ def cpu_baseline(b64, w64, beta, n, m, nb, tau, sigma, stride: int = 4) -> dict:
     }
 
 
+def compare(dev) -> int:
+    """Iterations of the preconditioned solvers needed to match 1000 iterations of
+    the unpreconditioned comparators (the paper's Sec. 4 comparison)."""
+    import numpy as np
+    import torch
+
+    from paper_1609_06041_amd import ctpd, synth
+
+    out = {"kind": "iterations_to_match", "data": "synthetic", "dtype": "f32"}
+    # low-dose: Eq. 1 cost per iteration
+    prob, spec = synth.workload_problem("lowdose_512", with_x_true=True)
+    n, m, nb, beta = spec["n"], spec["m"], spec["nb"], spec["beta"]
+    b32, w32 = synth.as_f32_inputs(prob)
+    b, w = torch.from_numpy(b32).to(dev), torch.from_numpy(w32).to(dev)
+    xt = prob.x_true
+    with ctpd.Operator(n, m, nb) as op:
+        log("Algorithm 1, 20 iterations, cost recorded")
+        xa, ia = op.lowdose_solve(b, w, beta, 20, record_cost=True)
+        xa = xa.cpu().numpy()
+        log("GIST, 1000 iterations, cost recorded")
+        xg, ig = op.gist_lowdose_solve(b, w, beta, 1000, record_cost=True)
+        xg = xg.cpu().numpy()
+        _, ig_t = op.gist_lowdose_solve(b, w, beta, 1000)
+        _, ia_t = op.lowdose_solve(b, w, beta, 20)
+    fa, fg = ia["cost"], ig["cost"]
+    k_match = next((k + 1 for k in range(len(fa)) if fa[k] <= fg[-1]), None)
+    out["lowdose_512"] = {
+        "algorithm1_cost": [float(v) for v in fa],
+        "gist_cost_at": {str(k): float(fg[k - 1]) for k in (1, 10, 100, 300, 1000)},
+        "algorithm1_iters_to_reach_gist1000_cost": k_match,
+        "gist_iters_to_reach_algorithm1_k10_cost": next((k + 1 for k in range(len(fg)) if fg[k] <= fa[9]), None),
+        "rmse_algorithm1_20": float(np.sqrt(((xa - xt) ** 2).mean())),
+        "rmse_gist_1000": float(np.sqrt(((xg - xt) ** 2).mean())),
+        "rel_diff_algorithm1_20_vs_gist_1000": float(np.linalg.norm(xa - xg) / np.linalg.norm(xg)),
+        "gist_step": ig_t["tau"], "gist_lipschitz": ig_t["lambda_a"],
+        "ms": {"algorithm1_20_loop": ia_t["loop_ms"], "algorithm1_setup": ia_t["setup_ms"],
+               "gist_1000_loop": ig_t["loop_ms"], "gist_setup": ig_t["setup_ms"]},
+    }
+    # few-view: RMSE against the phantom and distance to the CP-1000 image
+    prob, spec = synth.workload_problem("fewview_512", with_x_true=True)
+    n, m, nb = spec["n"], spec["m"], spec["nb"]
+    bf = torch.from_numpy(np.asarray(prob.b, np.float32)).to(dev)
+    xt = prob.x_true
+    with ctpd.Operator(n, m, nb) as op:
+        log("Chambolle-Pock, 1000 iterations")
+        xc, ic = op.cp_fewview_solve(bf, 1000)
+        xc = xc.cpu().numpy()
+        rows = []
+        for k in (1, 2, 3, 5, 10, 20):
+            xk, ik = op.fewview_solve(bf, k)
+            xk = xk.cpu().numpy()
+            rows.append({"k": k, "rmse": float(np.sqrt(((xk - xt) ** 2).mean())),
+                         "rel_diff_vs_cp1000": float(np.linalg.norm(xk - xc) / np.linalg.norm(xc)),
+                         "loop_ms": ik["loop_ms"]})
+        cp_rmse = {}
+        for k in (3, 10, 100, 300):
+            xk, _ = op.cp_fewview_solve(bf, k)
+            cp_rmse[str(k)] = float(np.sqrt(((xk.cpu().numpy() - xt) ** 2).mean()))
+    cp_rmse["1000"] = float(np.sqrt(((xc - xt) ** 2).mean()))
+    out["fewview_512"] = {"algorithm2": rows, "cp_rmse_at": cp_rmse,
+                          "algorithm2_iters_to_reach_cp1000_rmse":
+                              next((r["k"] for r in rows if r["rmse"] <= cp_rmse["1000"]), None),
+                          "ms": {"cp_1000_loop": ic["loop_ms"], "cp_setup": ic["setup_ms"]}}
+    out["paper_context"] = ("paper (hardware not stated): ~10 Algorithm-1 iterations match GIST at 1000; "
+                            "3 Algorithm-2 iterations match Chambolle-Pock at 1000")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def batch_speedup(dev, count: int, steps: int, warmup: int) -> int:
+    """Batched uneven workload: one batched solve (set-up of every problem, then
+    the 20-iteration loop of all problems as one graph replay) against the
+    per-problem solver called once per problem."""
+    import numpy as np
+    import torch
+
+    from paper_1609_06041_amd import ctpd, synth
+
+    log(f"generating {count} seeded problems of the batched uneven workload")
+    specs, bs, ws, betas = [], [], [], []
+    for p in range(count):
+        prob, spec = synth.batch_problem(p)
+        b32, w32 = synth.as_f32_inputs(prob)
+        specs.append(spec)
+        bs.append(torch.from_numpy(b32).to(dev))
+        ws.append(torch.from_numpy(w32).to(dev))
+        betas.append(spec["beta"])
+    geoms = [(sp["n"], sp["m"], sp["nb"]) for sp in specs]
+    iters = specs[0]["iters"]
+    outs = [torch.empty((n, n), device=dev) for n, _, _ in geoms]
+    log("per-problem solves")
+    ops = [ctpd.Operator(*g) for g in geoms]
+    for op, b, w, beta, x in zip(ops, bs, ws, betas, outs):   # warm-up
+        op.lowdose_solve(b, w, beta, iters, out=x)
+    seq_total, seq_loop, seq_setup = [], [], []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loops = setups = 0.0
+        for op, b, w, beta, x in zip(ops, bs, ws, betas, outs):
+            _, info = op.lowdose_solve(b, w, beta, iters, out=x)
+            loops += info["loop_ms"]
+            setups += info["setup_ms"]
+        torch.cuda.synchronize()
+        seq_total.append(1e3 * (time.perf_counter() - t0))
+        seq_loop.append(loops)
+        seq_setup.append(setups)
+    ref = [x.clone() for x in outs]
+    for op in ops:
+        op.close()
+    log("batched solves")
+    bouts = [torch.empty((n, n), device=dev) for n, _, _ in geoms]
+    with ctpd.Batch(geoms) as bt:
+        for _ in range(warmup):
+            bt.lowdose_solve(bs, ws, betas, iters, outs=bouts)
+        bat_total, bat_loop, bat_setup = [], [], []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, infos = bt.lowdose_solve(bs, ws, betas, iters, outs=bouts)
+            torch.cuda.synchronize()
+            bat_total.append(1e3 * (time.perf_counter() - t0))
+            bat_loop.append(infos[0]["loop_ms"])
+            bat_setup.append(infos[0]["setup_ms"])
+    identical = all(bool(torch.equal(a, b)) for a, b in zip(ref, bouts))
+    med = lambda v: float(np.median(v))
+    work = sum(m * n * n for n, m, _ in geoms)
+    out = {
+        "kind": "batched_uneven", "problems": count, "iterations": iters, "data": "synthetic", "dtype": "f32",
+        "sizes": {f"{n}x{m}": sum(1 for g in geoms if g[0] == n and g[1] == m) for n, m, _ in sorted(set(geoms))},
+        "sequential_ms": {"total": med(seq_total), "loop_sum": med(seq_loop), "setup_sum": med(seq_setup)},
+        "batched_ms": {"total": med(bat_total), "loop": med(bat_loop), "setup": med(bat_setup)},
+        "speedup_total": med(seq_total) / med(bat_total),
+        "speedup_loop": med(seq_loop) / med(bat_loop),
+        "batched_loop_gupdates_per_s": 2 * iters * work / (med(bat_loop) * 1e-3) / 1e9,
+        "results_identical_to_sequential": identical,
+    }
+    print(json.dumps(out), flush=True)
+    return 0 if identical else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +273,12 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--op-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare", action="store_true",
+                    help="instead of the throughput line: Algorithm 1 vs 1000 GIST iterations (lowdose_512) and "
+                         "Algorithm 2 vs 1000 Chambolle-Pock iterations (fewview_512), iterations to match")
+    ap.add_argument("--batch", type=int, default=0, metavar="P",
+                    help="instead of the throughput line: P problems of the batched uneven workload solved as one "
+                         "batch (graph replay) vs the same problems solved one after another")
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 --pmc: a plain 256 MiB device copy (counter calibration) "
                          "followed by 5 A^T launches on the workload; prints nothing else")
@@ -149,6 +296,10 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.compare:
+        return compare(dev)
+    if args.batch:
+        return batch_speedup(dev, args.batch, args.steps, args.warmup)
     log("generating the seeded lowdose_512 inputs")
     prob, spec = synth.workload_problem("lowdose_512", with_x_true=False)
     n, m, nb, beta, iters = spec["n"], spec["m"], spec["nb"], spec["beta"], spec["iters"]

@@ -46,8 +46,11 @@ extern "C" {
 
 /* Maximum n_bins: the filter keeps all 2*n_bins-1 taps in LDS. */
 #define CTPD_MAX_BINS 4096
+/* Maximum number of problems in one batch. */
+#define CTPD_MAX_BATCH 4096
 
 typedef struct ctpd_op ctpd_op;
+typedef struct ctpd_batch ctpd_batch;
 
 /* Scan geometry (Sec. 2.1: parallel-beam, m views over [0, pi)). */
 typedef struct {
@@ -140,6 +143,61 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
  * Arguments as for ctpd_pd_lowdose_solve without w and beta. */
 int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd_params* p,
                           float* x_out, ctpd_report* rep);
+
+/* ---- batched solves ------------------------------------------------------
+ * Many independent low-dose problems (Eq. 1) of uneven image sizes and view
+ * counts solved together by Algorithm 1, each with its own set-up exactly as
+ * in ctpd_pd_lowdose_solve (its own kappa, tau, taps and sigma), iterated in
+ * lockstep: one launch per kernel and step covers every problem, and the
+ * whole iters-iteration loop is captured once as a HIP graph and replayed on
+ * later calls with the same iters / tv_iters. */
+
+/* Create a batch of count problems with geometries geoms[0..count-1] (host
+ * array), bound to stream (the caller's hipStream_t; inputs are read after
+ * the work queued on it so far).  Allocates every problem's workspaces.
+ * CTPD_EINVAL for count outside [1, CTPD_MAX_BATCH] or a bad geometry. */
+int ctpd_batch_create(const ctpd_geometry* geoms, int32_t count, void* stream, ctpd_batch** out);
+
+/* Release the batch (waits for its work).  NULL is a no-op. */
+void ctpd_batch_destroy(ctpd_batch* batch);
+
+/* iters iterations of Algorithm 1 on every problem.  b, w, x_out: host arrays
+ * of count device pointers (problem i: b[i], w[i] [n_views][n_bins],
+ * x_out[i] [n][n]); beta: host array of count values >= 0.  p applies to
+ * every problem (record_cost is ignored).  reps: NULL or a host array of
+ * count reports (tau, sigma, kappa, norms and step counts per problem;
+ * setup_ms / loop_ms are the batch's; cost, mu_out, p_out are not used).
+ * Synchronous.  Errors as for ctpd_pd_lowdose_solve (the first failing
+ * problem decides). */
+int ctpd_batch_lowdose_solve(ctpd_batch* batch, const float* const* b, const float* const* w,
+                             const double* beta, int32_t iters, const ctpd_params* p, float* const* x_out,
+                             ctpd_report* reps);
+
+/* Comparator for the low-dose problem of Eq. 1 (Sec. 4 compares Algorithm 1
+ * with it; Table 1 lists it): GIST, the Loris-Verhoeven iteration -- a
+ * gradient step on the weighted data term, a projection step on the dual of
+ * the TV penalty -- with x >= 0 entering as the projection of the
+ * Chen-Huang-Zhang primal-dual fixed-point form.  Per iteration from x = 0,
+ * v = 0:  u = x - gamma A^T W (A x - b);  y = P+(u + lam div v);
+ * v = projection of (v + grad y) onto {|v_j| <= gamma beta / lam};
+ * x = P+(u + lam div v).  No preconditioner.
+ * Arguments as for ctpd_pd_lowdose_solve.  ctpd_params.tau is gamma (default
+ * rho * 2 / lambda_max(A^T W A)), ctpd_params.sigma is lam (default and
+ * maximum 1/8); the report's lambda_a is lambda_max(A^T W A) (0 when gamma
+ * was given) and p_out receives v. */
+int ctpd_gist_lowdose_solve(ctpd_op* op, const float* b, const float* w, double beta, int32_t iters,
+                            const ctpd_params* p, float* x_out, ctpd_report* rep);
+
+/* Comparator for the few-view problem of Eq. 25 (Sec. 4 compares Algorithm 2
+ * with it; Table 1 lists it): Chambolle-Pock (theta = 1) with K = [A; grad].
+ * Per iteration from zero:  y1 += s (A xbar - b);  y2 = projection of
+ * (y2 + s grad xbar) onto the unit ball;  x' = P+(x - t (A^T y1 - div y2));
+ * xbar = 2 x' - x.  No preconditioner.  ctpd_params.tau is t and
+ * ctpd_params.sigma is s (default both rho / sqrt(lambda_max(A^T A) + 8));
+ * the report's lambda_a is lambda_max(A^T A) (0 when both were given);
+ * mu_out receives y1 and p_out y2.  Arguments as for ctpd_pd_fewview_solve. */
+int ctpd_cp_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd_params* p, float* x_out,
+                          ctpd_report* rep);
 
 /* Static message for an error code. */
 const char* ctpd_strerror(int code);

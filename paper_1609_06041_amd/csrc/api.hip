@@ -9,53 +9,16 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <vector>
 
-#include "internal.h"
+#include "op.h"
 
 using namespace ctpd;
 
-struct ctpd_op {
-    int n = 0, m = 0, nb = 0;
-    hipStream_t stream = nullptr;
-    int device = 0;
-    size_t J = 0, I = 0;   // image / sinogram sizes
-    size_t Jp = 0;         // padded plane size n * (n + 6)
-    ViewGeom* views = nullptr;
-    // float32 iteration state
-    float* xp = nullptr;    // padded image planes for the forward projector, [n][n+6] each
-    float* xTp = nullptr;
-    float* x = nullptr;
-    float* z = nullptr;
-    float* p[2] = {nullptr, nullptr};
-    float* mu[3] = {nullptr, nullptr, nullptr};
-    float* mubar = nullptr;
-    float* q = nullptr;
-    float* winv = nullptr;
-    // filter taps for (tap_tau, tap_kappa)
-    double* taps64 = nullptr;
-    float* taps32 = nullptr;
-    double tap_tau = -1.0, tap_kappa = -1.0;
-    // reductions
-    double* partials = nullptr;
-    double* red = nullptr;        // device, 3 * kRedSlots doubles
-    double* red_host = nullptr;   // pinned host mirror
-    // float64 workspaces for the operator norms (allocated on first use)
-    double* img64[3] = {nullptr, nullptr, nullptr};
-    double* pad64[2] = {nullptr, nullptr};
-    double* sino64[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    // Lanczos recurrence scalars (device + pinned host mirror)
-    double* lz = nullptr;
-    double* lz_host = nullptr;
-    int lz_cap = 0;
-    // per-iteration monitor values (device), 2 * cost_cap slots of 3 doubles
-    double* cost_dev = nullptr;
-    int cost_cap = 0;
-};
 
-namespace {
+namespace ctpd_host {
 
-constexpr int kRedSlots = 8;
 thread_local char g_errmsg[512] = "";
 
 int fail_hip(hipError_t e, const char* what) {
@@ -63,11 +26,6 @@ int fail_hip(hipError_t e, const char* what) {
     return CTPD_EHIP;
 }
 
-#define HIP_TRY(expr)                                         \
-    do {                                                      \
-        hipError_t _e = (expr);                               \
-        if (_e != hipSuccess) return fail_hip(_e, #expr);     \
-    } while (0)
 
 int alloc_dev(void** p, size_t bytes) {
     hipError_t e = hipMalloc(p, bytes ? bytes : 1);
@@ -79,11 +37,6 @@ int alloc_dev(void** p, size_t bytes) {
     return CTPD_OK;
 }
 
-#define ALLOC(ptr, count)                                                          \
-    do {                                                                           \
-        int _r = alloc_dev((void**)&(ptr), sizeof(*(ptr)) * (size_t)(count));      \
-        if (_r != CTPD_OK) return _r;                                              \
-    } while (0)
 
 int einval(const char* msg) {
     snprintf(g_errmsg, sizeof g_errmsg, "invalid argument: %s", msg);
@@ -180,103 +133,105 @@ double tridiag_max(const std::vector<double>& a, const std::vector<double>& b) {
 
 // Lanczos with the recurrence scalars kept on the device: the kernels read
 // alpha_j and beta_j from device memory, and the host only copies them back
-// every kCheck steps to evaluate the top Ritz value (so the queue never
-// drains between steps).  Device slots (3 doubles each): [0] start norm^2,
-// [1 + j] alpha_j, [1 + cap + j] beta_{j+1}^2.
-constexpr int kCheck = 8;
-
+// every few steps to evaluate the top Ritz value (so the queue never drains
+// between steps).  Device slots (3 doubles each): [0] start norm^2,
+// [1 + j] alpha_j, [1 + cap + j] beta_{j+1}^2.  Two chains (the two operator
+// norms of the low-dose solve) can run at once, each on its own stream with
+// its own scalar and partial-sum buffers.
 int ensure_lz(ctpd_op* op, int kmax) {
     if (op->lz_cap >= kmax) return CTPD_OK;
-    if (op->lz) hipFree(op->lz);
-    if (op->lz_host) hipHostFree(op->lz_host);
-    op->lz = nullptr;
-    op->lz_host = nullptr;
+    for (int c = 0; c < 2; ++c) {
+        if (op->lz[c]) hipFree(op->lz[c]);
+        if (op->lz_host[c]) hipHostFree(op->lz_host[c]);
+        op->lz[c] = nullptr;
+        op->lz_host[c] = nullptr;
+    }
     op->lz_cap = 0;
     const size_t cnt = (size_t)3 * (2 * kmax + 1);
-    ALLOC(op->lz, cnt);
-    HIP_TRY(hipHostMalloc((void**)&op->lz_host, sizeof(double) * cnt, hipHostMallocDefault));
+    for (int c = 0; c < 2; ++c) {
+        ALLOC(op->lz[c], cnt);
+        HIP_TRY(hipHostMalloc((void**)&op->lz_host[c], sizeof(double) * cnt, hipHostMallocDefault));
+        if (!op->lz_partials[c]) ALLOC(op->lz_partials[c], 3 * kReduceBlocks);
+    }
     op->lz_cap = kmax;
     return CTPD_OK;
 }
 
-template <class Apply>
-int lanczos_max(ctpd_op* op, double* q, double* qp, double* w, int rows, int cols, uint64_t seed,
-                const float* wgt, double inv_kappa, int kmax, Apply apply, double* lam_out, int* steps_out) {
-    int r = ensure_lz(op, kmax);
-    if (r) return r;
-    const size_t len = (size_t)rows * cols;
-    const int cap = op->lz_cap;
-    double* s0 = op->lz;
-    auto AL = [&](int j) { return op->lz + 3 * (1 + j); };
-    auto B2 = [&](int j) { return op->lz + 3 * (1 + cap + j); };
-    hipStream_t s = op->stream;
-    HIP_TRY(launch_start_vector(q, rows, cols, seed, wgt, inv_kappa, s));
-    HIP_TRY(launch_reduce(RED_DOT_F64, q, q, nullptr, len, op->partials, s0, s));
-    HIP_TRY(launch_normalize(q, q, s0, len, s));
-    std::vector<double> al, be;
-    double theta = 0.0, theta_prev = 0.0;
-    int done = 0, steps = 0;
-    bool converged = false;
-    for (int j = 0; j < kmax && !converged; ++j) {
-        if ((r = apply(q, w))) return r;
-        HIP_TRY(launch_reduce(RED_DOT_F64, q, w, nullptr, len, op->partials, AL(j), s));
-        HIP_TRY(launch_lanczos_update(w, q, j ? qp : nullptr, AL(j), j ? B2(j - 1) : nullptr, len, op->partials,
-                                      B2(j), s));
-        HIP_TRY(launch_normalize(w, w, B2(j), len, s));
-        double* t = qp;
-        qp = q;
-        q = w;
-        w = t;
-        if ((j + 1) % kCheck != 0 && j + 1 != kmax) continue;
-        HIP_TRY(hipMemcpyAsync(op->lz_host, op->lz, sizeof(double) * 3 * (2 * cap + 1), hipMemcpyDeviceToHost, s));
-        if ((r = sync(op))) return r;
-        for (int i = done; i <= j; ++i) {
-            al.push_back(op->lz_host[3 * (1 + i)]);
-            theta = tridiag_max(al, be);
-            steps = i + 1;
-            const double bn = std::sqrt(std::max(op->lz_host[3 * (1 + cap + i)], 0.0));
-            if ((i > 0 && std::fabs(theta - theta_prev) <= 1e-10 * std::fabs(theta)) ||
-                !(bn > 1e-300 * std::max(1.0, std::fabs(theta)))) {
-                converged = true;
-                break;
+
+// Run Lanczos chains to convergence together: each round queues
+// `per_round` steps of every unfinished chain on its own stream, then
+// synchronises and checks them all.
+int run_lanczos(const std::vector<Lanczos*>& chains) {
+    for (;;) {
+        bool any = false;
+        for (Lanczos* c : chains)
+            if (!c->finished()) {
+                int r = c->enqueue(c->per_round);
+                if (r) return r;
+                any = true;
             }
-            be.push_back(bn);
-            theta_prev = theta;
-        }
-        done = j + 1;
+        if (!any) return CTPD_OK;
+        for (Lanczos* c : chains) HIP_TRY(hipStreamSynchronize(c->s));
+        for (Lanczos* c : chains)
+            if (!c->finished()) c->absorb();
     }
-    *lam_out = theta;
-    *steps_out = steps;
-    return CTPD_OK;
 }
 
-// lambda_max(A^T D A) with the float64 operators and the taps in op->taps64.
-int lambda_a(ctpd_op* op, int kmax, double* lam, int* steps) {
+// lambda_max(A^T D A) with the float64 operators and the taps in op->taps64,
+// on op->stream; with filt == false the middle factor is W = diag(wgt)
+// (wgt given) or the identity instead of D.
+int setup_lambda_a(ctpd_op* op, int kmax, Lanczos* L, bool filt, const float* wgt) {
     int r = ensure_f64(op);
     if (r) return r;
-    double *s1 = op->sino64[3], *s2 = op->sino64[4];
-    auto apply = [&](const double* in, double* out) -> int {
-        HIP_TRY(launch_pad_planes<double>(in, op->pad64[0], op->pad64[1], op->n, op->stream));
-        HIP_TRY(launch_forward<double>(op->pad64[0], op->pad64[1], s1, op->views, op->n, op->m, op->nb,
-                                       op->stream));
-        HIP_TRY(launch_filter_f64(s1, s2, op->taps64, nullptr, nullptr, op->m, op->nb, op->stream));
+    if ((r = ensure_lz(op, kmax))) return r;
+    double *s1 = op->sino64[4], *s2 = op->sino64[5];
+    hipStream_t s = op->stream;
+    L->op = op;
+    L->chain = 0;
+    L->per_round = 8;
+    L->s = s;
+    L->q = op->img64[0];
+    L->qp = op->img64[1];
+    L->w = op->img64[2];
+    L->kmax = kmax;
+    L->apply = [op, s1, s2, s, filt, wgt](const double* in, double* out) -> int {
+        HIP_TRY(launch_pad_planes<double>(in, op->pad64[0], op->pad64[1], op->n, s));
+        HIP_TRY(launch_forward<double>(op->pad64[0], op->pad64[1], filt || wgt ? s1 : s2, op->views, op->n, op->m,
+                                       op->nb, s));
+        if (filt)
+            HIP_TRY(launch_filter_f64(s1, s2, op->taps64, nullptr, nullptr, op->m, op->nb, s));
+        else if (wgt)
+            HIP_TRY(launch_mul_w_f64(s2, s1, wgt, op->I, s));
         HIP_TRY(launch_adjoint<double>(s2, nullptr, 1.0, 0.0, nullptr, 0.0, 1.0, out, op->views, op->n, op->m,
-                                       op->nb, op->stream));
+                                       op->nb, s));
         return CTPD_OK;
     };
-    return lanczos_max(op, op->img64[0], op->img64[1], op->img64[2], op->n, op->n, 1, nullptr, 0.0, kmax, apply,
-                       lam, steps);
+    return L->start(op->n, op->n, 1, nullptr, 0.0);
 }
 
-// lambda_max(W^-1/2 D W^-1/2); needs op->sino64[3] = sqrt(1/w).
-int lambda_h(ctpd_op* op, const float* w, double kappa, int kmax, double* lam, int* steps) {
+// lambda_max(W^-1/2 D W^-1/2) on the aux stream (after everything queued on
+// op->stream so far); needs op->sino64[3] = sqrt(1/w).
+int setup_lambda_h(ctpd_op* op, const float* w, double kappa, int kmax, Lanczos* L) {
+    int r = ensure_f64(op);
+    if (r) return r;
+    if ((r = ensure_lz(op, kmax))) return r;
+    HIP_TRY(hipEventRecord(op->fork, op->stream));
+    HIP_TRY(hipStreamWaitEvent(op->aux, op->fork, 0));
     const double* rs = op->sino64[3];
-    auto apply = [&](const double* in, double* out) -> int {
-        HIP_TRY(launch_filter_f64(in, out, op->taps64, rs, rs, op->m, op->nb, op->stream));
+    hipStream_t s = op->aux;
+    L->op = op;
+    L->chain = 1;
+    L->per_round = 16;   // one step of the A chain costs several of the H chain
+    L->s = s;
+    L->q = op->sino64[0];
+    L->qp = op->sino64[1];
+    L->w = op->sino64[2];
+    L->kmax = kmax;
+    L->apply = [op, rs, s](const double* in, double* out) -> int {
+        HIP_TRY(launch_filter_f64(in, out, op->taps64, rs, rs, op->m, op->nb, s));
         return CTPD_OK;
     };
-    return lanczos_max(op, op->sino64[0], op->sino64[1], op->sino64[2], op->m, op->nb, 2, w, 1.0 / kappa, kmax,
-                       apply, lam, steps);
+    return L->start(op->m, op->nb, 2, w, 1.0 / kappa);
 }
 
 int filter(ctpd_op* op, int mode, const float* in0, const float* in1, const float* in2, const float* in3,
@@ -304,26 +259,19 @@ int project(ctpd_op* op, const float* x, float* y) {
 }
 
 // n_iter dual steps on p (warm start in pin; result pointer returned in *pout,
-// which is either pin or op->p scratch), then x = max(0, z - lam div p).
+// which is either pin or scratch, both used as ping-pong buffers), then
+// x = max(0, z - lam div p).  lam == 0 gives x = max(0, z) and leaves p alone.
 int tv_prox(ctpd_op* op, const float* z, float lam, int n_iter, float step, float* pin, float* scratch, float* x,
             float** pout) {
-    float* src = pin;
-    float* dst = scratch;
-    if (lam > 0.0f) {
-        for (int i = 0; i < n_iter; ++i) {
-            HIP_TRY(launch_tv_step(z, src, dst, op->n, lam, step, op->stream));
-            std::swap(src, dst);
-        }
-    }
-    HIP_TRY(launch_tv_finalize(z, src, x, op->n, lam, op->stream));
-    if (pout) *pout = src;
+    float* pf = pin;
+    if (lam > 0.0f)
+        HIP_TRY(launch_tv_prox(z, pin, scratch, x, op->n, lam, step, n_iter, &pf, op->stream));
+    else
+        HIP_TRY(launch_tv_finalize(z, pin, x, op->n, 0.0f, op->stream));
+    if (pout) *pout = pf;
     return CTPD_OK;
 }
 
-struct Knobs {
-    double tau, sigma, tv_step, rho;
-    int tv_iters, norm_steps, record;
-};
 
 int read_params(const ctpd_params* p, Knobs* k) {
     k->tau = 0.0;
@@ -384,7 +332,47 @@ int finish(ctpd_op* op, int iters, bool lowdose, double beta, float* p_final, ct
     return sync(op);
 }
 
-}  // namespace
+// a1 and the start of a2 for Algorithm 1: validity scan of w and b, kappa =
+// mean(1/w), tau, W^-1, the taps of Eq. 24; when sigma is not given, the two
+// operator-norm chains are started (run them with run_lanczos, then call
+// lowdose_setup_end).
+int lowdose_setup_begin(ctpd_op* op, const float* b, const float* w, const Knobs& k, LowdoseSetup* S) {
+    const size_t I = op->I;
+    int r;
+    if ((r = reduce(op, RED_INVW_CHECK, w, b, nullptr, I, 0))) return r;
+    if ((r = read_red(op))) return r;
+    if (op->red_host[1] > 0 || op->red_host[2] > 0) {
+        snprintf(g_errmsg, sizeof g_errmsg, "%.0f weights <= 0 or non-finite, %.0f non-finite data",
+                 op->red_host[1], op->red_host[2]);
+        return CTPD_EDOMAIN;
+    }
+    S->kappa = op->red_host[0] / (double)I;
+    S->tau = k.tau > 0 ? k.tau : M_PI * S->kappa / (2.0 * op->m);
+    HIP_TRY(launch_inverse_f32(op->winv, w, I, op->stream));
+    if ((r = ensure_taps(op, S->tau, S->kappa))) return r;
+    S->sigma = k.sigma;
+    S->norms = !(S->sigma > 0);
+    if (S->norms) {
+        if ((r = ensure_f64(op))) return r;
+        HIP_TRY(launch_rsqrt_f64(op->sino64[3], w, I, op->stream));
+        if ((r = setup_lambda_a(op, k.norm_steps, &S->La))) return r;
+        if ((r = setup_lambda_h(op, w, S->kappa, k.norm_steps, &S->Lh))) return r;
+    }
+    return CTPD_OK;
+}
+
+void lowdose_setup_end(const Knobs& k, LowdoseSetup* S) {
+    if (!S->norms) return;
+    S->lam_a = S->La.theta;
+    S->steps_a = S->La.steps;
+    S->lam_h = S->Lh.theta;
+    S->steps_h = S->Lh.steps;
+    S->sigma = k.rho * std::min(2.0 / S->lam_h, 1.0 / (S->tau * S->lam_a));
+}
+
+}  // namespace ctpd_host
+
+using namespace ctpd_host;
 
 extern "C" {
 
@@ -433,6 +421,8 @@ int ctpd_op_create(const ctpd_geometry* g, void* stream, ctpd_op** out) {
         ALLOC(op->partials, 3 * kReduceBlocks);
         ALLOC(op->red, 3 * kRedSlots);
         HIP_TRY(hipHostMalloc((void**)&op->red_host, sizeof(double) * 3 * kRedSlots, hipHostMallocDefault));
+        HIP_TRY(hipStreamCreateWithFlags(&op->aux, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&op->fork, hipEventDisableTiming));
         return CTPD_OK;
     };
     int r = init();
@@ -450,12 +440,18 @@ void ctpd_op_destroy(ctpd_op* op) {
     void* ptrs[] = {op->views, op->xp, op->xTp, op->x, op->z, op->p[0], op->p[1], op->mu[0], op->mu[1], op->mu[2],
                     op->mubar, op->q, op->winv, op->taps64, op->taps32, op->partials, op->red, op->cost_dev,
                     op->img64[0], op->img64[1], op->img64[2], op->pad64[0], op->pad64[1], op->sino64[0], op->sino64[1],
-                    op->sino64[2], op->sino64[3], op->sino64[4]};
+                    op->sino64[2], op->sino64[3], op->sino64[4], op->sino64[5], op->lz[0], op->lz[1],
+                    op->lz_partials[0], op->lz_partials[1], op->xbar};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (op->red_host) hipHostFree(op->red_host);
-    if (op->lz) hipFree(op->lz);
-    if (op->lz_host) hipHostFree(op->lz_host);
+    for (double* h : op->lz_host)
+        if (h) hipHostFree(h);
+    if (op->aux) {
+        hipStreamSynchronize(op->aux);
+        hipStreamDestroy(op->aux);
+    }
+    if (op->fork) hipEventDestroy(op->fork);
     delete op;
 }
 
@@ -533,27 +529,12 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
     const auto t0 = std::chrono::steady_clock::now();
     const size_t I = op->I, J = op->J;
     hipStream_t s = op->stream;
-    // a1: kappa = mean(1/w) with a validity scan of w and b
-    if ((r = reduce(op, RED_INVW_CHECK, w, b, nullptr, I, 0))) return r;
-    if ((r = read_red(op))) return r;
-    if (op->red_host[1] > 0 || op->red_host[2] > 0) {
-        snprintf(g_errmsg, sizeof g_errmsg, "%.0f weights <= 0 or non-finite, %.0f non-finite data",
-                 op->red_host[1], op->red_host[2]);
-        return CTPD_EDOMAIN;
-    }
-    const double kappa = op->red_host[0] / (double)I;
-    const double tau = k.tau > 0 ? k.tau : M_PI * kappa / (2.0 * op->m);
-    HIP_TRY(launch_inverse_f32(op->winv, w, I, s));
-    if ((r = ensure_taps(op, tau, kappa))) return r;
-    // a2: step sizes
-    double sigma = k.sigma, lam_a = 0.0, lam_h = 0.0;
-    int steps_a = 0, steps_h = 0;
-    if (!(sigma > 0)) {
-        if ((r = lambda_a(op, k.norm_steps, &lam_a, &steps_a))) return r;
-        HIP_TRY(launch_rsqrt_f64(op->sino64[3], w, I, s));
-        if ((r = lambda_h(op, w, kappa, k.norm_steps, &lam_h, &steps_h))) return r;
-        sigma = k.rho * std::min(2.0 / lam_h, 1.0 / (tau * lam_a));
-    }
+    LowdoseSetup S;
+    if ((r = lowdose_setup_begin(op, b, w, k, &S))) return r;
+    if (S.norms && (r = run_lanczos({&S.La, &S.Lh}))) return r;
+    lowdose_setup_end(k, &S);
+    const double kappa = S.kappa, tau = S.tau, sigma = S.sigma, lam_a = S.lam_a, lam_h = S.lam_h;
+    const int steps_a = S.steps_a, steps_h = S.steps_h;
     if ((r = sync(op))) return r;
     const double setup_ms = ms_since(t0);
     const auto t1 = std::chrono::steady_clock::now();
@@ -639,7 +620,11 @@ int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
     if (!(sigma > 0) || !(k.tau > 0)) {
         if ((r = ensure_taps(op, 1.0, 0.0))) return r;
         if (!(sigma > 0)) {
-            if ((r = lambda_a(op, k.norm_steps, &lam1, &steps_a))) return r;
+            Lanczos La;
+            if ((r = setup_lambda_a(op, k.norm_steps, &La))) return r;
+            if ((r = run_lanczos({&La}))) return r;
+            lam1 = La.theta;
+            steps_a = La.steps;
             sigma = k.rho / lam1;
         }
     }
@@ -708,6 +693,169 @@ int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
         rep->sigma = sigma;
         rep->kappa = 0.0;
         rep->lambda_a = lam1 > 0 ? lam1 / tau : 0.0;
+        rep->lambda_h = 0.0;
+        rep->norm_steps_a = steps_a;
+        rep->norm_steps_h = 0;
+        rep->iters_done = iters;
+        rep->setup_ms = setup_ms;
+        rep->loop_ms = ms_since(t1);
+    }
+    return CTPD_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Comparators (unpreconditioned first-order primal-dual methods of Sec. 4).
+
+int ctpd_gist_lowdose_solve(ctpd_op* op, const float* b, const float* w, double beta, int32_t iters,
+                            const ctpd_params* p, float* x_out, ctpd_report* rep) {
+    g_errmsg[0] = 0;
+    if (!op || !b || !w || !x_out) return einval("null pointer");
+    if (!(beta >= 0.0) || !std::isfinite(beta)) return einval("beta must be finite and >= 0");
+    if (iters < 0) return einval("iters < 0");
+    Knobs k;
+    int r = read_params(p, &k);
+    if (r) return r;
+    if (k.sigma > 0.125) return einval("GIST dual step must be <= 1/8 (||grad||^2 <= 8)");
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t I = op->I, J = op->J;
+    hipStream_t s = op->stream;
+    if ((r = reduce(op, RED_INVW_CHECK, w, b, nullptr, I, 0))) return r;
+    if ((r = read_red(op))) return r;
+    if (op->red_host[1] > 0 || op->red_host[2] > 0) {
+        snprintf(g_errmsg, sizeof g_errmsg, "%.0f weights <= 0 or non-finite, %.0f non-finite data",
+                 op->red_host[1], op->red_host[2]);
+        return CTPD_EDOMAIN;
+    }
+    const double kappa = op->red_host[0] / (double)I;
+    double gamma = k.tau, lip = 0.0;
+    int steps_a = 0;
+    if (!(gamma > 0)) {
+        Lanczos L;
+        if ((r = setup_lambda_a(op, k.norm_steps, &L, false, w))) return r;
+        if ((r = run_lanczos({&L}))) return r;
+        lip = L.theta;
+        steps_a = L.steps;
+        gamma = k.rho * 2.0 / lip;
+    }
+    const double lam = k.sigma > 0 ? k.sigma : 0.125;
+    const double radius = gamma * beta / lam;
+    if ((r = sync(op))) return r;
+    const double setup_ms = ms_since(t0);
+    const auto t1 = std::chrono::steady_clock::now();
+    if (k.record && (r = ensure_cost(op, iters))) return r;
+    HIP_TRY(launch_fill_f32(op->x, 0.f, J, s));
+    HIP_TRY(launch_fill_f32(op->p[0], 0.f, 2 * J, s));
+    float* pcur = op->p[0];
+    // the dual field is kept scaled to the unit ball: v = radius * p
+    const float tl = (float)(-lam * radius), ts = radius > 0 ? (float)(-1.0 / radius) : 0.f;
+    for (int it = 0; it < iters; ++it) {
+        // u = x - gamma A^T W (A x - b)
+        if ((r = project(op, op->x, op->q))) return r;
+        HIP_TRY(launch_lin3_f32(op->mubar, op->q, 1.f, b, -1.f, nullptr, 0.f, w, I, s));
+        HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, op->x, 1.f, (float)-gamma, op->z, op->views,
+                                      op->n, op->m, op->nb, s));
+        // y = P+(u + lam div v); v <- ball(v + grad y); x = P+(u + lam div v)
+        if (radius > 0) {
+            float* pf = nullptr;
+            HIP_TRY(launch_tv_prox(op->z, pcur, pcur == op->p[0] ? op->p[1] : op->p[0], op->x, op->n, tl, ts, 1,
+                                   &pf, s));
+            pcur = pf;
+        } else {
+            HIP_TRY(launch_tv_finalize(op->z, pcur, op->x, op->n, 0.f, s));
+        }
+        if (k.record) {
+            if ((r = project(op, op->x, op->q))) return r;
+            if ((r = reduce(op, RED_WRES_F32, op->q, b, w, I, 0))) return r;
+            HIP_TRY(launch_tv_norm(op->x, op->n, op->partials, op->cost_dev + 6 * it, s));
+            HIP_TRY(hipMemcpyAsync(op->cost_dev + 6 * it + 3, op->red, sizeof(double) * 3,
+                                   hipMemcpyDeviceToDevice, s));
+        }
+    }
+    if (rep && rep->p_out && radius > 0)   // report v itself
+        HIP_TRY(launch_lin3_f32(pcur, pcur, (float)radius, nullptr, 0.f, nullptr, 0.f, nullptr, 2 * J, s));
+    if ((r = finish(op, iters, true, beta, pcur, rep, x_out, k.record != 0))) return r;
+    if (rep) {
+        rep->tau = gamma;
+        rep->sigma = lam;
+        rep->kappa = kappa;
+        rep->lambda_a = lip;
+        rep->lambda_h = 0.0;
+        rep->norm_steps_a = steps_a;
+        rep->norm_steps_h = 0;
+        rep->iters_done = iters;
+        rep->setup_ms = setup_ms;
+        rep->loop_ms = ms_since(t1);
+    }
+    return CTPD_OK;
+}
+
+int ctpd_cp_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd_params* p, float* x_out,
+                          ctpd_report* rep) {
+    g_errmsg[0] = 0;
+    if (!op || !b || !x_out) return einval("null pointer");
+    if (iters < 0) return einval("iters < 0");
+    Knobs k;
+    int r = read_params(p, &k);
+    if (r) return r;
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t I = op->I, J = op->J;
+    hipStream_t s = op->stream;
+    if ((r = reduce(op, RED_SQ_F32, b, nullptr, nullptr, I, 0))) return r;
+    if ((r = read_red(op))) return r;
+    if (op->red_host[1] > 0) {
+        snprintf(g_errmsg, sizeof g_errmsg, "%.0f non-finite data values", op->red_host[1]);
+        return CTPD_EDOMAIN;
+    }
+    if (!op->xbar) ALLOC(op->xbar, J);
+    double t = k.tau, sg = k.sigma, lata = 0.0;
+    int steps_a = 0;
+    if (!(t > 0) || !(sg > 0)) {
+        Lanczos L;
+        if ((r = setup_lambda_a(op, k.norm_steps, &L, false, nullptr))) return r;
+        if ((r = run_lanczos({&L}))) return r;
+        lata = L.theta;
+        steps_a = L.steps;
+        const double st = k.rho / std::sqrt(lata + 8.0);
+        if (!(t > 0)) t = st;
+        if (!(sg > 0)) sg = st;
+    }
+    if ((r = sync(op))) return r;
+    const double setup_ms = ms_since(t0);
+    const auto t1 = std::chrono::steady_clock::now();
+    if (k.record && (r = ensure_cost(op, iters))) return r;
+    float *x = op->x, *xn = op->z, *y1 = op->mu[0];
+    HIP_TRY(launch_fill_f32(x, 0.f, J, s));
+    HIP_TRY(launch_fill_f32(op->xbar, 0.f, J, s));
+    HIP_TRY(launch_fill_f32(op->p[0], 0.f, 2 * J, s));
+    HIP_TRY(launch_fill_f32(y1, 0.f, I, s));
+    const float fs = (float)sg, ft = (float)t;
+    for (int it = 0; it < iters; ++it) {
+        // y1 <- y1 + s (A xbar - b);  y2 <- ball(y2 + s grad xbar)
+        if ((r = project(op, op->xbar, op->q))) return r;
+        HIP_TRY(launch_lin3_f32(y1, y1, 1.f, op->q, fs, b, -fs, nullptr, I, s));
+        HIP_TRY(launch_grad_ball(op->xbar, op->p[0], op->n, fs, s));
+        // x_new = P+(x - t (A^T y1 - div y2)),  xbar = 2 x_new - x
+        HIP_TRY(launch_adjoint<float>(y1, nullptr, 1.f, 0.f, x, 1.f, -ft, xn, op->views, op->n, op->m, op->nb, s));
+        HIP_TRY(launch_tv_finalize(xn, op->p[0], xn, op->n, -ft, s));
+        HIP_TRY(launch_lin3_f32(op->xbar, xn, 2.f, x, -1.f, nullptr, 0.f, nullptr, J, s));
+        std::swap(x, xn);
+        if (k.record) {
+            if ((r = project(op, x, op->q))) return r;
+            if ((r = reduce(op, RED_SQDIFF_F32, op->q, b, nullptr, I, 0))) return r;
+            HIP_TRY(launch_tv_norm(x, op->n, op->partials, op->cost_dev + 6 * it, s));
+            HIP_TRY(hipMemcpyAsync(op->cost_dev + 6 * it + 3, op->red, sizeof(double) * 3,
+                                   hipMemcpyDeviceToDevice, s));
+        }
+    }
+    op->x = x;
+    op->z = xn;
+    if ((r = finish(op, iters, false, 1.0, op->p[0], rep, x_out, k.record != 0))) return r;
+    if (rep) {
+        rep->tau = t;
+        rep->sigma = sg;
+        rep->kappa = 0.0;
+        rep->lambda_a = lata;
         rep->lambda_h = 0.0;
         rep->norm_steps_a = steps_a;
         rep->norm_steps_h = 0;

@@ -1,0 +1,284 @@
+// Batched low-dose solves: many independent problems of uneven image sizes
+// and view counts (Algorithm 1 on each), set up together and iterated
+// together.  Each problem keeps its own operator handle (geometry tables,
+// taps, workspaces); the iteration runs one flattened launch per kernel and
+// step for the whole batch, and the whole K-iteration loop is captured once
+// in a HIP graph and replayed.
+//
+// Workgroup placement: consecutive workgroups of a launch go to the eight
+// XCDs in turn, and each XCD has its own L2.  Problems are assigned to XCDs
+// (largest first, onto the least-loaded XCD, weighted by m * n^2, the work of
+// A and A^T), and a problem's workgroups are placed only at grid positions of
+// its XCD, so its image, sinogram and views stay in one L2 across kernels.
+#include <algorithm>
+#include <numeric>
+
+#include "op.h"
+
+using namespace ctpd;
+using namespace ctpd_host;
+
+namespace {
+
+constexpr int kXcds = 8;
+
+enum Kind { K_INIT, K_FILT, K_ADJ, K_TV, K_PAD, K_FWD, K_COPY, K_COUNT };
+
+}  // namespace
+
+struct ctpd_batch {
+    int count = 0;
+    hipStream_t user = nullptr;   // caller's stream
+    hipStream_t gs = nullptr;     // internal stream: set-up joins here, the loop graph runs here
+    hipEvent_t ev = nullptr;
+    std::vector<ctpd_op*> ops;
+    std::vector<hipStream_t> streams;   // one per problem for the set-up
+    std::vector<int> xcd;               // XCD of each problem
+    int max_nb = 0;
+    BatchItem* items = nullptr;         // device table
+    BatchItem* items_host = nullptr;    // pinned mirror
+    BlockRef* map[K_COUNT] = {};
+    int nblk[K_COUNT] = {};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int g_iters = -1, g_tv = -1;
+};
+
+namespace {
+
+int blocks_of(const ctpd_op* op, int kind) {
+    const size_t J = op->J, I = op->I;
+    switch (kind) {
+        case K_INIT: return (int)((3 * J + 2 * I + 2047) / 2048);
+        case K_FILT: return filter_blocks_x(op->nb) * filter_blocks_y(op->m);
+        case K_ADJ: return adjoint_tiles(op->n) * adjoint_tiles(op->n);
+        case K_TV: return tv_tiles(op->n) * tv_tiles(op->n);
+        case K_PAD: return pad_tiles(op->n) * pad_tiles(op->n);
+        case K_FWD: return forward_blocks_x(op->nb) * op->m;
+        default: return (int)((J + 2047) / 2048);
+    }
+}
+
+int build_maps(ctpd_batch* bt) {
+    const int P = bt->count;
+    // XCD assignment: longest processing time first
+    std::vector<int> order(P);
+    std::iota(order.begin(), order.end(), 0);
+    auto work = [&](int p) { return (double)bt->ops[p]->m * bt->ops[p]->n * bt->ops[p]->n; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+    std::vector<double> load(kXcds, 0.0);
+    bt->xcd.assign(P, 0);
+    for (int p : order) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        bt->xcd[p] = x;
+        load[x] += work(p);
+    }
+    for (int kind = 0; kind < K_COUNT; ++kind) {
+        std::vector<std::vector<BlockRef>> bins(kXcds);
+        for (int p : order) {
+            const int nb = blocks_of(bt->ops[p], kind);
+            for (int l = 0; l < nb; ++l) bins[bt->xcd[p]].push_back(BlockRef{p, l});
+        }
+        size_t len = 0;
+        for (auto& b : bins) len = std::max(len, b.size());
+        std::vector<BlockRef> flat(len * kXcds, BlockRef{-1, 0});
+        for (int x = 0; x < kXcds; ++x)
+            for (size_t i = 0; i < bins[x].size(); ++i) flat[i * kXcds + x] = bins[x][i];
+        ALLOC(bt->map[kind], flat.size());
+        HIP_TRY(hipMemcpy(bt->map[kind], flat.data(), sizeof(BlockRef) * flat.size(), hipMemcpyHostToDevice));
+        bt->nblk[kind] = (int)flat.size();
+    }
+    return CTPD_OK;
+}
+
+// The K-iteration loop of Algorithm 1 over the whole batch (queued on bt->gs).
+int queue_loop(ctpd_batch* bt, int iters, int tv_iters) {
+    hipStream_t s = bt->gs;
+    const BatchItem* it = bt->items;
+    HIP_TRY(launch_batch_init(it, bt->map[K_INIT], bt->nblk[K_INIT], s));
+    int pc = 0;
+    const int chunk = tv_chunk_max();
+    for (int k = 0; k < iters; ++k) {
+        const int rot = (3 - k % 3) % 3;
+        // Step 1: mubar = -sigma D b (k = 0) / 2 mu - mu_prev - sigma D W^-1 (mu - mu_prev)
+        HIP_TRY(launch_filter_batched(it, bt->map[K_FILT], bt->nblk[K_FILT], k == 0 ? FILT_PLAIN : FILT_EXTRAP,
+                                      rot, bt->max_nb, s));
+        // Step 2: z = x - tau A^T mubar; x = prox(z)
+        HIP_TRY(launch_adjoint_batched(it, bt->map[K_ADJ], bt->nblk[K_ADJ], false, rot, s));
+        int left = tv_iters;
+        do {
+            const int st = std::min(left, chunk);
+            left -= st;
+            HIP_TRY(launch_tv_prox_batched(it, bt->map[K_TV], bt->nblk[K_TV], pc, st, left == 0, s));
+            pc = 1 - pc;
+        } while (left > 0);
+        // Step 3: mu^{k+1} = mu + sigma D (A x - b - W^-1 mu)
+        HIP_TRY(launch_pad_planes_batched(it, bt->map[K_PAD], bt->nblk[K_PAD], s));
+        HIP_TRY(launch_forward_batched(it, bt->map[K_FWD], bt->nblk[K_FWD], s));
+        HIP_TRY(launch_filter_batched(it, bt->map[K_FILT], bt->nblk[K_FILT], FILT_DUAL_LD, rot, bt->max_nb, s));
+    }
+    HIP_TRY(launch_batch_copy_out(it, bt->map[K_COPY], bt->nblk[K_COPY], s));
+    return CTPD_OK;
+}
+
+int capture_loop(ctpd_batch* bt, int iters, int tv_iters) {
+    if (bt->exec && bt->g_iters == iters && bt->g_tv == tv_iters) return CTPD_OK;
+    if (bt->exec) hipGraphExecDestroy(bt->exec);
+    if (bt->graph) hipGraphDestroy(bt->graph);
+    bt->exec = nullptr;
+    bt->graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(bt->gs, hipStreamCaptureModeThreadLocal));
+    const int r = queue_loop(bt, iters, tv_iters);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(bt->gs, &g);
+    if (r) {
+        if (g) hipGraphDestroy(g);
+        return r;
+    }
+    HIP_TRY(e);
+    bt->graph = g;
+    HIP_TRY(hipGraphInstantiate(&bt->exec, g, nullptr, nullptr, 0));
+    bt->g_iters = iters;
+    bt->g_tv = tv_iters;
+    return CTPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ctpd_batch_create(const ctpd_geometry* geoms, int32_t count, void* stream, ctpd_batch** out) {
+    g_errmsg[0] = 0;
+    if (!geoms || !out) return einval("null pointer");
+    if (count < 1 || count > CTPD_MAX_BATCH) return einval("count out of range [1, CTPD_MAX_BATCH]");
+    *out = nullptr;
+    ctpd_batch* bt = new ctpd_batch();
+    bt->count = count;
+    bt->user = (hipStream_t)stream;
+    auto init = [&]() -> int {
+        HIP_TRY(hipStreamCreateWithFlags(&bt->gs, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&bt->ev, hipEventDisableTiming));
+        for (int p = 0; p < count; ++p) {
+            hipStream_t st = nullptr;
+            HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            bt->streams.push_back(st);
+            ctpd_op* op = nullptr;
+            const int r = ctpd_op_create(&geoms[p], st, &op);
+            if (r) return r;
+            bt->ops.push_back(op);
+            bt->max_nb = std::max(bt->max_nb, geoms[p].n_bins);
+        }
+        ALLOC(bt->items, count);
+        HIP_TRY(hipHostMalloc((void**)&bt->items_host, sizeof(BatchItem) * count, hipHostMallocDefault));
+        return build_maps(bt);
+    };
+    const int r = init();
+    if (r) {
+        ctpd_batch_destroy(bt);
+        return r;
+    }
+    *out = bt;
+    return CTPD_OK;
+}
+
+void ctpd_batch_destroy(ctpd_batch* bt) {
+    if (!bt) return;
+    if (bt->gs) hipStreamSynchronize(bt->gs);
+    if (bt->exec) hipGraphExecDestroy(bt->exec);
+    if (bt->graph) hipGraphDestroy(bt->graph);
+    for (ctpd_op* op : bt->ops) ctpd_op_destroy(op);
+    for (hipStream_t st : bt->streams) hipStreamDestroy(st);
+    for (BlockRef* m : bt->map)
+        if (m) hipFree(m);
+    if (bt->items) hipFree(bt->items);
+    if (bt->items_host) hipHostFree(bt->items_host);
+    if (bt->ev) hipEventDestroy(bt->ev);
+    if (bt->gs) hipStreamDestroy(bt->gs);
+    delete bt;
+}
+
+int ctpd_batch_lowdose_solve(ctpd_batch* bt, const float* const* b, const float* const* w, const double* beta,
+                             int32_t iters, const ctpd_params* p, float* const* x_out, ctpd_report* reps) {
+    g_errmsg[0] = 0;
+    if (!bt || !b || !w || !beta || !x_out) return einval("null pointer");
+    if (iters < 0) return einval("iters < 0");
+    const int P = bt->count;
+    for (int i = 0; i < P; ++i) {
+        if (!b[i] || !w[i] || !x_out[i]) return einval("null problem pointer");
+        if (!(beta[i] >= 0.0) || !std::isfinite(beta[i])) return einval("beta must be finite and >= 0");
+    }
+    Knobs k;
+    int r = read_params(p, &k);
+    if (r) return r;
+    const auto t0 = std::chrono::steady_clock::now();
+    // inputs are ready on the caller's stream: every problem stream waits for it
+    HIP_TRY(hipEventRecord(bt->ev, bt->user));
+    for (hipStream_t st : bt->streams) HIP_TRY(hipStreamWaitEvent(st, bt->ev, 0));
+    HIP_TRY(hipStreamWaitEvent(bt->gs, bt->ev, 0));
+    // a1 / a2 for every problem; the operator-norm chains of all problems run together
+    std::vector<LowdoseSetup> S(P);
+    std::vector<Lanczos*> chains;
+    for (int i = 0; i < P; ++i) {
+        if ((r = lowdose_setup_begin(bt->ops[i], b[i], w[i], k, &S[i]))) return r;
+        if (S[i].norms) {
+            chains.push_back(&S[i].La);
+            chains.push_back(&S[i].Lh);
+        }
+    }
+    if ((r = run_lanczos(chains))) return r;
+    for (int i = 0; i < P; ++i) {
+        lowdose_setup_end(k, &S[i]);
+        if ((r = sync(bt->ops[i]))) return r;
+    }
+    const double setup_ms = ms_since(t0);
+    const auto t1 = std::chrono::steady_clock::now();
+    for (int i = 0; i < P; ++i) {
+        const ctpd_op* op = bt->ops[i];
+        BatchItem& it = bt->items_host[i];
+        it = BatchItem{};
+        it.n = op->n;
+        it.m = op->m;
+        it.nb = op->nb;
+        it.lowdose = 1;
+        it.views = op->views;
+        it.taps = op->taps32;
+        it.b = b[i];
+        it.winv = op->winv;
+        it.x = op->x;
+        it.z = op->z;
+        it.q = op->q;
+        it.mubar = op->mubar;
+        for (int j = 0; j < 3; ++j) it.mu[j] = op->mu[j];
+        for (int j = 0; j < 2; ++j) it.p[j] = op->p[j];
+        it.xp = op->xp;
+        it.xTp = op->xTp;
+        it.x_out = x_out[i];
+        it.sigma = (float)S[i].sigma;
+        it.tau = (float)S[i].tau;
+        it.lam = (float)(S[i].tau * beta[i]);
+        it.tvstep = it.lam > 0 ? (float)(k.tv_step / (S[i].tau * beta[i])) : 0.f;
+    }
+    HIP_TRY(hipMemcpyAsync(bt->items, bt->items_host, sizeof(BatchItem) * P, hipMemcpyHostToDevice, bt->gs));
+    if ((r = capture_loop(bt, iters, k.tv_iters))) return r;
+    HIP_TRY(hipGraphLaunch(bt->exec, bt->gs));
+    HIP_TRY(hipStreamSynchronize(bt->gs));
+    const double loop_ms = ms_since(t1);
+    if (reps) {
+        for (int i = 0; i < P; ++i) {
+            ctpd_report& rp = reps[i];
+            rp.tau = S[i].tau;
+            rp.sigma = S[i].sigma;
+            rp.kappa = S[i].kappa;
+            rp.lambda_a = S[i].lam_a;
+            rp.lambda_h = S[i].lam_h;
+            rp.norm_steps_a = S[i].steps_a;
+            rp.norm_steps_h = S[i].steps_h;
+            rp.iters_done = iters;
+            rp.setup_ms = setup_ms;
+            rp.loop_ms = loop_ms;
+        }
+    }
+    return CTPD_OK;
+}
+
+}  // extern "C"

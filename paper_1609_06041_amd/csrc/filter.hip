@@ -111,51 +111,87 @@ hipError_t launch_taps(double* taps64, float* taps32, int nb, int m, double tau,
 // float32 matrix-core filter.
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int FBM = 32;   // views per workgroup
-constexpr int FBN = 64;   // output bins per workgroup
-constexpr int FBK = 32;   // input bins per LDS stage
-constexpr int FSTRIDE = FBK + 1;
+constexpr int FBM = 32;    // views per workgroup
+constexpr int FBN = 64;    // output bins per workgroup
+constexpr int FBK = 128;   // input bins per LDS stage
+constexpr int FSTRIDE = FBK + 2;   // row pitch = 2 mod 32 banks: the 32 lanes of a half-wave hit 32 banks
+constexpr int FPER = FBM * FBK / 256;
 
-__device__ __forceinline__ float filter_input(const FilterArgs& a, size_t i) {
-    switch (a.mode) {
-        case FILT_EXTRAP: return a.in0[i] * (a.in1[i] - a.in2[i]);
-        case FILT_DUAL_LD: return a.in0[i] - a.in1[i] - a.in2[i] * a.in3[i];
-        case FILT_DUAL_FV: return a.in0[i] - a.in1[i];
-        default: return a.in0[i];
+// Number of sinogram arrays the prologue of each mode reads, and the input of
+// D formed from their raw values (a compile-time mode, and the raw values are
+// combined only at the LDS store, so the loads of a whole stage stay in flight
+// while the previous stage runs on the matrix cores).
+template <int MODE>
+struct FilterIn {
+    static constexpr int N = MODE == FILT_DUAL_LD ? 4 : MODE == FILT_EXTRAP ? 3 : MODE == FILT_DUAL_FV ? 2 : 1;
+    __device__ static __forceinline__ float combine(const float* r) {
+        if (MODE == FILT_EXTRAP) return r[0] * (r[1] - r[2]);
+        if (MODE == FILT_DUAL_LD) return r[0] - r[1] - r[2] * r[3];
+        if (MODE == FILT_DUAL_FV) return r[0] - r[1];
+        return r[0];
     }
-}
+};
 
 // Workgroup: 4 waves, a 32 x 64 output tile; wave w owns rows 16*(w/2) and
 // columns 32*(w%2) as two 16 x 16 MFMA accumulators.  MFMA 16x16x4 f32
 // operand layout: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k,
-// D[i][j] in lane j + 16*(i/4), element i%4.
-__global__ __launch_bounds__(256) void filter_mfma_kernel(FilterArgs a, const float* __restrict__ taps, int m,
-                                                          int nb) {
-    extern __shared__ float smem[];
+// D[i][j] in lane j + 16*(i/4), element i%4.  The filter input of the next
+// 128-bin stage is loaded into registers while the current stage runs.
+template <int MODE>
+__device__ __forceinline__ void filter_body(const FilterArgs& a, const float* __restrict__ taps, int m, int nb,
+                                            float* smem, int bxi, int byi) {
     const int ntap = 2 * nb - 1;
     const int tlen = ntap + FBK + FBN;
     float* htap = smem;                 // htap[FBK + k] = taps[k], zero padded
     float* stile = smem + tlen;         // [FBM][FSTRIDE]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n0 = blockIdx.x * FBN, v0 = blockIdx.y * FBM;
-    for (int i = tid; i < tlen; i += 256) {
-        const int k = i - FBK;
-        htap[i] = (k >= 0 && k < ntap) ? taps[k] : 0.0f;
+    const int n0 = bxi * FBN, v0 = byi * FBM;
+    for (int i0 = 0; i0 < tlen; i0 += 256 * 8) {   // 8 loads in flight per thread
+        float tv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = i0 + tid + 256 * u - FBK;
+            tv[u] = taps[(k >= 0 && k < ntap) ? k : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + tid + 256 * u, k = i - FBK;
+            if (i < tlen) htap[i] = (k >= 0 && k < ntap) ? tv[u] : 0.0f;
+        }
     }
     const int wr = (wave >> 1) * 16, wc = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
+    constexpr int NIN = FilterIn<MODE>::N;
+    const float* src[4] = {a.in0, a.in1, a.in2, a.in3};
+    float stg[FPER][NIN];
+    bool okk[FPER];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < FPER; ++r) {
+            const int e = tid + 256 * r;
+            const int row = e / FBK, cc = e - row * FBK;
+            const int v = v0 + row, j = k0 + cc;
+            okk[r] = v < m && j < nb;
+            const size_t idx = okk[r] ? (size_t)v * nb + j : 0;   // clamped, unconditional loads
+#pragma unroll
+            for (int q = 0; q < NIN; ++q) stg[r][q] = src[q][idx];
+        }
+    };
     v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    fetch(0);
     for (int k0 = 0; k0 < nb; k0 += FBK) {
         __syncthreads();
-        for (int e = tid; e < FBM * FBK; e += 256) {
-            const int r = e / FBK, cc = e - r * FBK;
-            const int v = v0 + r, j = k0 + cc;
-            stile[r * FSTRIDE + cc] = (v < m && j < nb) ? filter_input(a, (size_t)v * nb + j) : 0.0f;
+#pragma unroll
+        for (int r = 0; r < FPER; ++r) {
+            const int e = tid + 256 * r;
+            const int row = e / FBK;
+            stile[row * FSTRIDE + (e - row * FBK)] = okk[r] ? FilterIn<MODE>::combine(stg[r]) : 0.0f;
         }
         __syncthreads();
+        if (k0 + FBK < nb) fetch(k0 + FBK);
         // T[krow][col] = h[col - krow] sits at htap[col - krow + nb - 1 + FBK].
         const int hb = n0 + wc + li - (k0 + lk) + nb - 1 + FBK;
-#pragma unroll
+#pragma unroll 8
         for (int kk = 0; kk < FBK; kk += 4) {
             const float av = stile[(wr + li) * FSTRIDE + kk + lk];
             const float b0 = htap[hb - kk];
@@ -182,26 +218,103 @@ __global__ __launch_bounds__(256) void filter_mfma_kernel(FilterArgs a, const fl
     }
 }
 
+template <int MODE>
+__global__ __launch_bounds__(256) void filter_mfma_kernel(FilterArgs a, const float* __restrict__ taps, int m,
+                                                          int nb) {
+    extern __shared__ float smem[];
+    filter_body<MODE>(a, taps, m, nb, smem, blockIdx.x, blockIdx.y);
+}
+
+size_t filter_lds_bytes(int nb) {
+    return sizeof(float) * ((size_t)(2 * nb - 1 + FBK + FBN) + FBM * FSTRIDE);
+}
+
 hipError_t launch_filter_f32(const FilterArgs& a, const float* taps32, int m, int nb, hipStream_t s) {
     dim3 grid((nb + FBN - 1) / FBN, (m + FBM - 1) / FBM);
-    const size_t lds = sizeof(float) * ((size_t)(2 * nb - 1 + FBK + FBN) + FBM * FSTRIDE);
-    filter_mfma_kernel<<<grid, 256, lds, s>>>(a, taps32, m, nb);
+    const size_t lds = filter_lds_bytes(nb);
+    switch (a.mode) {
+        case FILT_EXTRAP: filter_mfma_kernel<FILT_EXTRAP><<<grid, 256, lds, s>>>(a, taps32, m, nb); break;
+        case FILT_DUAL_LD: filter_mfma_kernel<FILT_DUAL_LD><<<grid, 256, lds, s>>>(a, taps32, m, nb); break;
+        case FILT_DUAL_FV: filter_mfma_kernel<FILT_DUAL_FV><<<grid, 256, lds, s>>>(a, taps32, m, nb); break;
+        default: filter_mfma_kernel<FILT_PLAIN><<<grid, 256, lds, s>>>(a, taps32, m, nb); break;
+    }
     return hipGetLastError();
 }
+
+// Batched filter: the solver's two uses of D per iteration, with the
+// prologue / epilogue operands taken from each problem's workspaces
+// (mu^k = mu[rot], mu^{k-1} = mu[(rot+1)%3], mu^{k+1} -> mu[(rot+2)%3]).
+template <int MODE>
+__global__ __launch_bounds__(256) void filter_batched(const BatchItem* __restrict__ items,
+                                                      const BlockRef* __restrict__ map, int rot) {
+    extern __shared__ float smem[];
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const BatchItem& it = items[e.prob];
+    float* mu = it.mu[rot];
+    float* mup = it.mu[(rot + 1) % 3];
+    FilterArgs a{};
+    a.mode = MODE;
+    if (MODE == FILT_PLAIN) {   // k = 0: mubar = -sigma D b
+        a.in0 = it.b;
+        a.c = -it.sigma;
+        a.out = it.mubar;
+    } else if (MODE == FILT_EXTRAP) {   // mubar = 2 mu - mu_prev - sigma D W^-1 (mu - mu_prev)
+        a.in0 = it.winv;
+        a.in1 = mu;
+        a.in2 = mup;
+        a.E0 = mu;
+        a.e0 = 2.f;
+        a.E1 = mup;
+        a.e1 = -1.f;
+        a.c = -it.sigma;
+        a.out = it.mubar;
+    } else {   // mu^{k+1} = mu + sigma D (A x - b [- W^-1 mu])
+        a.in0 = it.q;
+        a.in1 = it.b;
+        a.in2 = it.winv;
+        a.in3 = mu;
+        a.E0 = mu;
+        a.e0 = 1.f;
+        a.c = it.sigma;
+        a.out = it.mu[(rot + 2) % 3];
+    }
+    const int gx = (it.nb + FBN - 1) / FBN;
+    filter_body<MODE>(a, it.taps, it.m, it.nb, smem, e.local % gx, e.local / gx);
+}
+
+hipError_t launch_filter_batched(const BatchItem* items, const BlockRef* map, int nblocks, int mode, int rot,
+                                 int max_nb, hipStream_t s) {
+    const size_t lds = filter_lds_bytes(max_nb);
+    switch (mode) {
+        case FILT_EXTRAP: filter_batched<FILT_EXTRAP><<<nblocks, 256, lds, s>>>(items, map, rot); break;
+        case FILT_DUAL_LD: filter_batched<FILT_DUAL_LD><<<nblocks, 256, lds, s>>>(items, map, rot); break;
+        case FILT_DUAL_FV: filter_batched<FILT_DUAL_FV><<<nblocks, 256, lds, s>>>(items, map, rot); break;
+        default: filter_batched<FILT_PLAIN><<<nblocks, 256, lds, s>>>(items, map, rot); break;
+    }
+    return hipGetLastError();
+}
+
+// filter work decomposition (for batched block maps)
+int filter_blocks_x(int nb) { return (nb + FBN - 1) / FBN; }
+int filter_blocks_y(int m) { return (m + FBM - 1) / FBM; }
 
 // ---------------------------------------------------------------------------
 // float64 filter on the matrix cores (v_mfma_f64_16x16x4_f64), for the
 // operator norms: out = post .* D (pre .* in)  (pre / post optional).
 // Same tiling as the float32 kernel (32 views x 64 bins per workgroup, wave w
-// owns rows 16*(w/2), columns 32*(w%2)); per 16-bin stage of the input the
-// workgroup keeps only the 79 taps that stage touches.  The A and B operand
+// owns rows 16*(w/2), columns 32*(w%2)); per 64-bin stage of the input the
+// workgroup keeps only the 127 taps that stage touches, and the next stage is
+// loaded into registers while the current one runs.  The A and B operand
 // layouts match the f32 instruction; the result differs: D[i][j] sits in lane
 // j + 16*(i%4), element i/4.
 typedef double v4d __attribute__((ext_vector_type(4)));
-constexpr int DBK = 16;
-constexpr int DSTRIDE = DBK + 1;
+constexpr int DBK = 64;
+constexpr int DSTRIDE = DBK + 1;     // odd pitch: 16 lanes x 8 bytes cover all 32 banks
 constexpr int DTW = FBN + DBK - 1;   // taps per stage
+constexpr int DPER = FBM * DBK / 256;
 
+template <bool PRE, bool POST>
 __global__ __launch_bounds__(256) void filter_f64_kernel(const double* __restrict__ in, double* __restrict__ out,
                                                          const double* __restrict__ taps,
                                                          const double* __restrict__ pre,
@@ -212,29 +325,41 @@ __global__ __launch_bounds__(256) void filter_f64_kernel(const double* __restric
     const int n0 = blockIdx.x * FBN, v0 = blockIdx.y * FBM;
     const int wr = (wave >> 1) * 16, wc = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
-    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < nb; k0 += DBK) {
-        __syncthreads();
-        for (int e = tid; e < FBM * DBK; e += 256) {
-            const int r = e / DBK, cc = e - r * DBK;
-            const int v = v0 + r, j = k0 + cc;
-            double val = 0.0;
-            if (v < m && j < nb) {
-                const size_t idx = (size_t)v * nb + j;
-                val = in[idx];
-                if (pre) val *= pre[idx];
-            }
-            stile[r * DSTRIDE + cc] = val;
+    double stg[DPER], stp[DPER];
+    double tstg = 0.0;
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < DPER; ++r) {
+            const int e = tid + 256 * r;
+            const int row = e / DBK, cc = e - row * DBK;
+            const int v = v0 + row, j = k0 + cc;
+            const bool ok = v < m && j < nb;
+            const size_t idx = ok ? (size_t)v * nb + j : 0;   // clamped, unconditional load
+            stg[r] = ok ? in[idx] : 0.0;
+            if (PRE) stp[r] = pre[idx];   // multiplied in at the LDS store, so all loads stay in flight
         }
         // offsets d = col - krow in [n0 - k0 - (DBK-1), n0 - k0 + FBN - 1]
-        for (int e = tid; e < DTW; e += 256) {
-            const int d = n0 - k0 - (DBK - 1) + e;
-            hw[e] = (d > -nb && d < nb) ? taps[nb - 1 + d] : 0.0;
-        }
+        const int d = n0 - k0 - (DBK - 1) + tid;
+        const bool tok = tid < DTW && d > -nb && d < nb;
+        const double tv = taps[tok ? nb - 1 + d : 0];
+        tstg = tok ? tv : 0.0;
+    };
+    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    fetch(0);
+    for (int k0 = 0; k0 < nb; k0 += DBK) {
         __syncthreads();
+#pragma unroll
+        for (int r = 0; r < DPER; ++r) {
+            const int e = tid + 256 * r;
+            const int row = e / DBK;
+            stile[row * DSTRIDE + (e - row * DBK)] = PRE ? stg[r] * stp[r] : stg[r];
+        }
+        if (tid < DTW) hw[tid] = tstg;
+        __syncthreads();
+        if (k0 + DBK < nb) fetch(k0 + DBK);
         // T[krow][col] = h[col - krow] at hw[(col - n0) - (krow - k0) + DBK - 1]
         const int hb = wc + li - lk + DBK - 1;
-#pragma unroll
+#pragma unroll 4
         for (int kk = 0; kk < DBK; kk += 4) {
             const double av = stile[(wr + li) * DSTRIDE + kk + lk];
             const double b0 = hw[hb - kk];
@@ -253,7 +378,7 @@ __global__ __launch_bounds__(256) void filter_f64_kernel(const double* __restric
             if (v < m && col < nb) {
                 const size_t idx = (size_t)v * nb + col;
                 double val = acc[r];
-                if (post) val *= post[idx];
+                if (POST) val *= post[idx];
                 out[idx] = val;
             }
         }
@@ -263,7 +388,14 @@ __global__ __launch_bounds__(256) void filter_f64_kernel(const double* __restric
 hipError_t launch_filter_f64(const double* in, double* out, const double* taps64, const double* pre,
                              const double* post, int m, int nb, hipStream_t s) {
     dim3 grid((nb + FBN - 1) / FBN, (m + FBM - 1) / FBM);
-    filter_f64_kernel<<<grid, 256, 0, s>>>(in, out, taps64, pre, post, m, nb);
+    if (pre && post)
+        filter_f64_kernel<true, true><<<grid, 256, 0, s>>>(in, out, taps64, pre, post, m, nb);
+    else if (pre)
+        filter_f64_kernel<true, false><<<grid, 256, 0, s>>>(in, out, taps64, pre, post, m, nb);
+    else if (post)
+        filter_f64_kernel<false, true><<<grid, 256, 0, s>>>(in, out, taps64, pre, post, m, nb);
+    else
+        filter_f64_kernel<false, false><<<grid, 256, 0, s>>>(in, out, taps64, pre, post, m, nb);
     return hipGetLastError();
 }
 

@@ -47,6 +47,34 @@ struct FilterArgs {
     float* out;
 };
 
+// One problem of a batched solve: its geometry, its workspaces (the buffers of
+// the problem's own operator handle), its inputs and step sizes.  Buffers with
+// rotating roles are indexed by the launch's rotation argument: mu[rot] is
+// mu^k, mu[(rot+1)%3] mu^{k-1}, mu[(rot+2)%3] receives mu^{k+1}.
+struct BatchItem {
+    int n, m, nb, lowdose;
+    const ViewGeom* views;
+    const float* taps;
+    const float* b;
+    const float* winv;
+    float* x;
+    float* z;
+    float* q;
+    float* mubar;
+    float* mu[3];
+    float* p[2];
+    float* xp;
+    float* xTp;
+    float* x_out;
+    float sigma, tau, lam, tvstep;
+};
+
+// The problem and the block within it of one workgroup of a batched launch
+// (prob < 0: an idle workgroup).
+struct BlockRef {
+    int prob, local;
+};
+
 // ---- projector.hip -------------------------------------------------------
 // xp / xTp: [n][n+6] row-major copies of x and its transpose with three zero
 // pixels on each side of every row
@@ -61,6 +89,17 @@ template <typename T>
 hipError_t launch_adjoint(const T* y1, const T* y2, T c1, T c2, const T* xin, T alpha, T beta, T* out,
                           const ViewGeom* views, int n, int m, int nb, hipStream_t s);
 
+// batched forms (grids of nblocks workgroups described by map):
+//   pad planes of x, q = A x, z = x - tau A^T mubar (two: z = x - tau A^T (2 mu^k - mu^{k-1}))
+hipError_t launch_pad_planes_batched(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s);
+hipError_t launch_forward_batched(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s);
+hipError_t launch_adjoint_batched(const BatchItem* items, const BlockRef* map, int nblocks, bool two, int rot,
+                                  hipStream_t s);
+
+int adjoint_tiles(int n);       // A^T tiles per image side
+int pad_tiles(int n);           // pad-plane tiles per image side
+int forward_blocks_x(int nb);   // forward-projector workgroups per view
+
 // ---- filter.hip ----------------------------------------------------------
 // taps64[k], k = 0..2nb-2, for offset k - (nb-1); also written rounded to taps32.
 hipError_t launch_taps(double* taps64, float* taps32, int nb, int m, double tau, double kappa,
@@ -71,9 +110,27 @@ hipError_t launch_filter_f32(const FilterArgs& a, const float* taps32, int m, in
 hipError_t launch_filter_f64(const double* in, double* out, const double* taps64, const double* pre,
                              const double* post, int m, int nb, hipStream_t s);
 
+// batched filter for the solver's two uses of D (mode FILT_PLAIN: k = 0
+// extrapolation; FILT_EXTRAP; FILT_DUAL_LD / FILT_DUAL_FV: dual update)
+hipError_t launch_filter_batched(const BatchItem* items, const BlockRef* map, int nblocks, int mode, int rot,
+                                 int max_nb, hipStream_t s);
+int filter_blocks_x(int nb);
+int filter_blocks_y(int m);
+
 // ---- tv.hip --------------------------------------------------------------
-hipError_t launch_tv_step(const float* z, const float* p_in, float* p_out, int n, float lam, float step,
-                          hipStream_t s);
+// The TV prox: n_iter dual steps on p starting from p_a (warm start), then
+// x = max(0, z - lam div p).  lam > 0.  p_a and p_b are both overwritten as
+// ping-pong buffers; *p_final receives the one holding the final p.
+hipError_t launch_tv_prox(const float* z, float* p_a, float* p_b, float* x, int n, float lam, float step,
+                          int n_iter, float** p_final, hipStream_t s);
+// p <- projection of (p + s grad xb) onto the unit ball, pointwise (the dual
+// step of Chambolle-Pock on the TV term).
+hipError_t launch_grad_ball(const float* xb, float* p, int n, float s, hipStream_t st);
+// batched TV prox chunk (p[src] -> p[1-src]; x written when last)
+hipError_t launch_tv_prox_batched(const BatchItem* items, const BlockRef* map, int nblocks, int src, int steps,
+                                  bool last, hipStream_t s);
+int tv_tiles(int n);      // TV tiles per image side
+int tv_chunk_max();       // dual steps per TV launch at most
 hipError_t launch_tv_finalize(const float* z, const float* p, float* x, int n, float lam, hipStream_t s);
 
 // ---- vec.hip -------------------------------------------------------------
@@ -109,6 +166,13 @@ hipError_t launch_axpby_f64(double* y, const double* x, double a, double b, cons
 // y = a*x (double)
 hipError_t launch_scale_f64(double* y, const double* x, double a, size_t len, hipStream_t s);
 // out[i] = f(x[i]): inverse (1/x) or sqrt(1/x)   (float in, float / double out)
+hipError_t launch_lin3_f32(float* out, const float* a, float c0, const float* b, float c1, const float* c, float c2,
+                           const float* w, size_t len, hipStream_t s);
+hipError_t launch_mul_w_f64(double* out, const double* a, const float* w, size_t len, hipStream_t s);
+// batched solve: zero x, p[0], mu[0], mu[1] of every problem / copy x to x_out
+// (2048 elements per workgroup)
+hipError_t launch_batch_init(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s);
+hipError_t launch_batch_copy_out(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s);
 hipError_t launch_inverse_f32(float* out, const float* w, size_t len, hipStream_t s);
 hipError_t launch_rsqrt_f64(double* out, const float* w, size_t len, hipStream_t s);
 hipError_t launch_copy_f32(float* dst, const float* src, size_t len, hipStream_t s);

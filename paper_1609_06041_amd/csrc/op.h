@@ -1,0 +1,191 @@
+// Host-side internals of libctpd shared by the translation units that hold
+// the C ABI (api.hip: operator handle, single operators, solvers; batch.hip:
+// batched solves): the operator handle, error helpers, step-size set-up.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <functional>
+#include <vector>
+
+#include "internal.h"
+
+using ctpd::ViewGeom;
+
+// The operator handle: geometry tables and every workspace of a solve,
+// allocated once per geometry.
+struct ctpd_op {
+    int n = 0, m = 0, nb = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    size_t J = 0, I = 0;   // image / sinogram sizes
+    size_t Jp = 0;         // padded plane size n * (n + 6)
+    ViewGeom* views = nullptr;
+    // float32 iteration state
+    float* xp = nullptr;    // padded image planes for the forward projector, [n][n+6] each
+    float* xTp = nullptr;
+    float* x = nullptr;
+    float* z = nullptr;
+    float* p[2] = {nullptr, nullptr};
+    float* mu[3] = {nullptr, nullptr, nullptr};
+    float* mubar = nullptr;
+    float* q = nullptr;
+    float* winv = nullptr;
+    float* xbar = nullptr;   // Chambolle-Pock extrapolated image (allocated on first use)
+    // filter taps for (tap_tau, tap_kappa)
+    double* taps64 = nullptr;
+    float* taps32 = nullptr;
+    double tap_tau = -1.0, tap_kappa = -1.0;
+    // reductions
+    double* partials = nullptr;
+    double* red = nullptr;        // device, 3 * kRedSlots doubles
+    double* red_host = nullptr;   // pinned host mirror
+    // float64 workspaces for the operator norms (allocated on first use)
+    double* img64[3] = {nullptr, nullptr, nullptr};
+    double* pad64[2] = {nullptr, nullptr};
+    double* sino64[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // Lanczos recurrence scalars (device + pinned host mirror) and reduction
+    // partials, one set per concurrent chain; chain 1 runs on the aux stream
+    double* lz[2] = {nullptr, nullptr};
+    double* lz_host[2] = {nullptr, nullptr};
+    double* lz_partials[2] = {nullptr, nullptr};
+    int lz_cap = 0;
+    hipStream_t aux = nullptr;
+    hipEvent_t fork = nullptr;
+    // per-iteration monitor values (device), 2 * cost_cap slots of 3 doubles
+    double* cost_dev = nullptr;
+    int cost_cap = 0;
+};
+
+namespace ctpd_host {
+
+using namespace ctpd;
+
+constexpr int kRedSlots = 8;
+extern thread_local char g_errmsg[512];
+
+int fail_hip(hipError_t e, const char* what);
+int alloc_dev(void** p, size_t bytes);
+int einval(const char* msg);
+
+#define HIP_TRY(expr)                                         \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) return fail_hip(_e, #expr);     \
+    } while (0)
+
+#define ALLOC(ptr, count)                                                          \
+    do {                                                                           \
+        int _r = alloc_dev((void**)&(ptr), sizeof(*(ptr)) * (size_t)(count));      \
+        if (_r != CTPD_OK) return _r;                                              \
+    } while (0)
+
+std::vector<ViewGeom> make_views(int n, int m, int nb);
+int sync(ctpd_op* op);
+int ensure_taps(ctpd_op* op, double tau, double kappa);
+int ensure_f64(ctpd_op* op);
+int reduce(ctpd_op* op, int kind, const void* a, const void* b, const void* c, size_t len, int slot);
+int read_red(ctpd_op* op);
+double tridiag_max(const std::vector<double>& a, const std::vector<double>& b);
+int ensure_lz(ctpd_op* op, int kmax);
+
+using ApplyFn = std::function<int(const double*, double*)>;
+
+struct Lanczos {
+    ctpd_op* op = nullptr;
+    int chain = 0;
+    int per_round = 8;
+    hipStream_t s = nullptr;
+    double *q = nullptr, *qp = nullptr, *w = nullptr;
+    size_t len = 0;
+    int kmax = 0, j = 0, done = 0, steps = 0;
+    bool converged = false;
+    double theta = 0.0, theta_prev = 0.0;
+    std::vector<double> al, be;
+    ApplyFn apply;
+
+    double* AL(int i) const { return op->lz[chain] + 3 * (1 + i); }
+    double* B2(int i) const { return op->lz[chain] + 3 * (1 + op->lz_cap + i); }
+    bool finished() const { return converged || done >= kmax; }
+
+    int start(int rows, int cols, uint64_t seed, const float* wgt, double inv_kappa) {
+        len = (size_t)rows * cols;
+        double* s0 = op->lz[chain];
+        HIP_TRY(launch_start_vector(q, rows, cols, seed, wgt, inv_kappa, s));
+        HIP_TRY(launch_reduce(RED_DOT_F64, q, q, nullptr, len, op->lz_partials[chain], s0, s));
+        HIP_TRY(launch_normalize(q, q, s0, len, s));
+        return CTPD_OK;
+    }
+    // queue up to n more steps and the copy-back of the scalars
+    int enqueue(int n) {
+        const int end = std::min(kmax, j + n);
+        for (; j < end; ++j) {
+            int r = apply(q, w);
+            if (r) return r;
+            HIP_TRY(launch_reduce(RED_DOT_F64, q, w, nullptr, len, op->lz_partials[chain], AL(j), s));
+            HIP_TRY(launch_lanczos_update(w, q, j ? qp : nullptr, AL(j), j ? B2(j - 1) : nullptr, len,
+                                          op->lz_partials[chain], B2(j), s));
+            HIP_TRY(launch_normalize(w, w, B2(j), len, s));
+            double* t = qp;
+            qp = q;
+            q = w;
+            w = t;
+        }
+        HIP_TRY(hipMemcpyAsync(op->lz_host[chain], op->lz[chain], sizeof(double) * 3 * (2 * op->lz_cap + 1),
+                               hipMemcpyDeviceToHost, s));
+        return CTPD_OK;
+    }
+    // after the stream is synchronised: extend the tridiagonal matrix and test
+    // the top Ritz value (relative change <= 1e-10, or an invariant subspace)
+    void absorb() {
+        const double* h = op->lz_host[chain];
+        for (int i = done; i < j && !converged; ++i) {
+            al.push_back(h[3 * (1 + i)]);
+            theta = tridiag_max(al, be);
+            steps = i + 1;
+            const double bn = std::sqrt(std::max(h[3 * (1 + op->lz_cap + i)], 0.0));
+            if ((i > 0 && std::fabs(theta - theta_prev) <= 1e-10 * std::fabs(theta)) ||
+                !(bn > 1e-300 * std::max(1.0, std::fabs(theta))))
+                converged = true;
+            be.push_back(bn);
+            theta_prev = theta;
+        }
+        done = j;
+    }
+};
+
+int run_lanczos(const std::vector<Lanczos*>& chains);
+int setup_lambda_a(ctpd_op* op, int kmax, Lanczos* L, bool filt = true, const float* wgt = nullptr);
+int setup_lambda_h(ctpd_op* op, const float* w, double kappa, int kmax, Lanczos* L);
+
+int filter(ctpd_op* op, int mode, const float* in0, const float* in1, const float* in2, const float* in3,
+           const float* E0, float e0, const float* E1, float e1, float c, float* out);
+int project(ctpd_op* op, const float* x, float* y);
+int tv_prox(ctpd_op* op, const float* z, float lam, int n_iter, float step, float* pin, float* scratch, float* x,
+            float** pout);
+
+struct Knobs {
+    double tau, sigma, tv_step, rho;
+    int tv_iters, norm_steps, record;
+};
+
+int read_params(const ctpd_params* p, Knobs* k);
+int ensure_cost(ctpd_op* op, int iters);
+double ms_since(std::chrono::steady_clock::time_point t0);
+int finish(ctpd_op* op, int iters, bool lowdose, double beta, float* p_final, ctpd_report* rep, float* x_out,
+           bool recorded);
+
+// Set-up of Algorithm 1 (see api.hip).
+struct LowdoseSetup {
+    double kappa = 0.0, tau = 0.0, sigma = 0.0, lam_a = 0.0, lam_h = 0.0;
+    int steps_a = 0, steps_h = 0;
+    bool norms = false;
+    Lanczos La, Lh;
+};
+int lowdose_setup_begin(ctpd_op* op, const float* b, const float* w, const Knobs& k, LowdoseSetup* S);
+void lowdose_setup_end(const Knobs& k, LowdoseSetup* S);
+
+}  // namespace ctpd_host

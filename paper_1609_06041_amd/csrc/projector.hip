@@ -19,11 +19,14 @@ namespace ctpd {
 // pitch n + 2 FP_PAD.
 constexpr int FP_PAD = 3;
 
+// Kernel bodies take their block coordinates as arguments so that the single
+// launches and the batched launches (one flattened grid over many problems)
+// share them.
 template <typename T>
-__global__ __launch_bounds__(256) void pad_planes_kernel(const T* __restrict__ in, T* __restrict__ xp,
-                                                         T* __restrict__ xTp, int n) {
+__device__ __forceinline__ void pad_planes_body(const T* __restrict__ in, T* __restrict__ xp, T* __restrict__ xTp,
+                                                int n, int bxi, int byi) {
     __shared__ T tile[32][33];
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int bx = bxi * 32, by = byi * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
     const int P = n + 2 * FP_PAD;
     for (int r = ty; r < 32; r += 8) {
@@ -39,7 +42,7 @@ __global__ __launch_bounds__(256) void pad_planes_kernel(const T* __restrict__ i
         if (ox < n && oy < n) xTp[(size_t)ox * P + oy + FP_PAD] = tile[tx][r];
     }
     // zero pads: the blocks of the first block column write the pad columns of their rows
-    if (blockIdx.x == 0) {
+    if (bxi == 0) {
         for (int e = threadIdx.x; e < 32 * 2 * FP_PAD; e += 256) {
             const int r = by + e / (2 * FP_PAD), q = e % (2 * FP_PAD);
             const int col = q < FP_PAD ? q : n + q;
@@ -49,6 +52,12 @@ __global__ __launch_bounds__(256) void pad_planes_kernel(const T* __restrict__ i
             }
         }
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void pad_planes_kernel(const T* __restrict__ in, T* __restrict__ xp,
+                                                         T* __restrict__ xTp, int n) {
+    pad_planes_body<T>(in, xp, xTp, n, blockIdx.x, blockIdx.y);
 }
 
 template <typename T>
@@ -95,11 +104,9 @@ constexpr int kBufferRsrcWord3 = 0x00020000;
 constexpr int FW_BATCH = 8;
 
 template <typename T>
-__global__ __launch_bounds__(256) void forward_kernel(const T* __restrict__ xp, const T* __restrict__ xTp,
-                                                      T* __restrict__ y, const ViewGeom* __restrict__ views,
-                                                      int n, int nb) {
-    const int v = blockIdx.y;
-    const int u = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void forward_body(const T* __restrict__ xp, const T* __restrict__ xTp, T* __restrict__ y,
+                                             const ViewGeom* __restrict__ views, int n, int nb, int bxi, int v) {
+    const int u = bxi * 256 + threadIdx.x;
     const ViewGeom g = views[v];
     const int P = n + 2 * FP_PAD;
     const double base = fma((double)min(u, nb - 1), g.su, g.s0);
@@ -163,6 +170,13 @@ __global__ __launch_bounds__(256) void forward_kernel(const T* __restrict__ xp, 
 }
 
 template <typename T>
+__global__ __launch_bounds__(256) void forward_kernel(const T* __restrict__ xp, const T* __restrict__ xTp,
+                                                      T* __restrict__ y, const ViewGeom* __restrict__ views,
+                                                      int n, int nb) {
+    forward_body<T>(xp, xTp, y, views, n, nb, blockIdx.x, blockIdx.y);
+}
+
+template <typename T>
 hipError_t launch_forward(const T* xp, const T* xTp, T* y, const ViewGeom* views, int n, int m, int nb,
                           hipStream_t s) {
     dim3 grid((nb + 255) / 256, m);
@@ -202,16 +216,16 @@ __device__ __forceinline__ int window_base(const ViewGeom& g, const TileBox& b) 
 }
 
 template <typename T, bool TWO>
-__global__ __launch_bounds__(512) void adjoint_kernel(const T* __restrict__ y1, const T* __restrict__ y2, T c1,
-                                                      T c2, const T* __restrict__ xin, T alpha, T beta,
-                                                      T* __restrict__ out, const ViewGeom* __restrict__ views,
-                                                      int n, int m, int nb) {
+__device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* __restrict__ y2, T c1, T c2,
+                                             const T* __restrict__ xin, T alpha, T beta, T* __restrict__ out,
+                                             const ViewGeom* __restrict__ views, int n, int m, int nb, int bxi,
+                                             int byi) {
     __shared__ T win[2][AT_VC][AT_W];
     __shared__ long long pt0[2][AT_VC], pcs[2][AT_VC], psn[2][AT_VC];
     __shared__ T plen[2][AT_VC], plen2[2][AT_VC];
     const int tid = threadIdx.x, h = tid >> 8, l = tid & 255;
     const int tx = l & 31, ty = l >> 5;
-    const int x0 = blockIdx.x * AT_T, y0 = blockIdx.y * AT_T;
+    const int x0 = bxi * AT_T, y0 = byi * AT_T;
     const double c = 0.5 * (double)(n - 1);
     const TileBox box{x0 - c, x0 + (AT_T - 1) - c, y0 - c, y0 + (AT_T - 1) - c, 0.5 * (double)(nb - 1)};
     const int nchunk = (m + AT_VC - 1) / AT_VC;
@@ -342,6 +356,14 @@ __global__ __launch_bounds__(512) void adjoint_kernel(const T* __restrict__ y1, 
     }
 }
 
+template <typename T, bool TWO>
+__global__ __launch_bounds__(512) void adjoint_kernel(const T* __restrict__ y1, const T* __restrict__ y2, T c1,
+                                                      T c2, const T* __restrict__ xin, T alpha, T beta,
+                                                      T* __restrict__ out, const ViewGeom* __restrict__ views,
+                                                      int n, int m, int nb) {
+    adjoint_body<T, TWO>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb, blockIdx.x, blockIdx.y);
+}
+
 template <typename T>
 hipError_t launch_adjoint(const T* y1, const T* y2, T c1, T c2, const T* xin, T alpha, T beta, T* out,
                           const ViewGeom* views, int n, int m, int nb, hipStream_t s) {
@@ -352,6 +374,64 @@ hipError_t launch_adjoint(const T* y1, const T* y2, T c1, T c2, const T* xin, T 
         adjoint_kernel<T, false><<<grid, 512, 0, s>>>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb);
     return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// Batched launches: one flattened grid over all problems of a batch; the
+// block map gives each workgroup its problem and its block within it.
+__global__ __launch_bounds__(256) void pad_planes_batched(const BatchItem* __restrict__ items,
+                                                          const BlockRef* __restrict__ map) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const BatchItem& it = items[e.prob];
+    const int gx = (it.n + 31) / 32;
+    pad_planes_body<float>(it.x, it.xp, it.xTp, it.n, e.local % gx, e.local / gx);
+}
+
+__global__ __launch_bounds__(256) void forward_batched(const BatchItem* __restrict__ items,
+                                                       const BlockRef* __restrict__ map) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const BatchItem& it = items[e.prob];
+    const int gx = (it.nb + 255) / 256;
+    forward_body<float>(it.xp, it.xTp, it.q, it.views, it.n, it.nb, e.local % gx, e.local / gx);
+}
+
+// z = x - tau A^T mubar  (mode 0), or z = x - tau A^T (2 mu - mu_prev)  (mode 1, few-view k >= 1)
+template <bool TWO>
+__global__ __launch_bounds__(512) void adjoint_batched(const BatchItem* __restrict__ items,
+                                                       const BlockRef* __restrict__ map, int rot) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const BatchItem& it = items[e.prob];
+    const int gx = (it.n + AT_T - 1) / AT_T;
+    const float* y1 = TWO ? it.mu[rot] : it.mubar;
+    const float* y2 = TWO ? it.mu[(rot + 1) % 3] : nullptr;
+    adjoint_body<float, TWO>(y1, y2, 2.f, -1.f, it.x, 1.f, -it.tau, it.z, it.views, it.n, it.m, it.nb,
+                             e.local % gx, e.local / gx);
+}
+
+hipError_t launch_pad_planes_batched(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s) {
+    pad_planes_batched<<<nblocks, 256, 0, s>>>(items, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_batched(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s) {
+    forward_batched<<<nblocks, 256, 0, s>>>(items, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_batched(const BatchItem* items, const BlockRef* map, int nblocks, bool two, int rot,
+                                  hipStream_t s) {
+    if (two)
+        adjoint_batched<true><<<nblocks, 512, 0, s>>>(items, map, rot);
+    else
+        adjoint_batched<false><<<nblocks, 512, 0, s>>>(items, map, rot);
+    return hipGetLastError();
+}
+
+int adjoint_tiles(int n) { return (n + AT_T - 1) / AT_T; }
+int pad_tiles(int n) { return (n + 31) / 32; }
+int forward_blocks_x(int nb) { return (nb + 255) / 256; }
 
 template hipError_t launch_pad_planes<float>(const float*, float*, float*, int, hipStream_t);
 template hipError_t launch_pad_planes<double>(const double*, double*, double*, int, hipStream_t);

@@ -6,9 +6,14 @@
 // and finally x = max(0, z - lam div p).  grad is the forward difference of
 // Eq. 2's h_j, v_j (zero on the last column / row), div its negative adjoint.
 //
-// The step kernel is a 5-point stencil: every lane forms x~ at its pixel and
-// at its right and lower neighbours directly from z and p (reads hit L1/L2),
-// so one launch is one dual step, with p double-buffered.
+// The prox kernel blocks the dual steps in time: a workgroup owns a 32 x 32
+// tile, stages z and p on the tile plus a halo of (steps + 1) pixels in LDS,
+// and runs up to kTvChunk steps there (one step reads p one pixel away in
+// each direction, so the valid region shrinks by one pixel per step and the
+// halo is what is used up), then writes p and, on the last chunk, x for the
+// tile.  Chunks ping-pong p between two global buffers.
+#include <utility>
+
 #include "internal.h"
 
 namespace ctpd {
@@ -29,27 +34,88 @@ __device__ __forceinline__ float xtilde(const float* __restrict__ z, const float
     return fmaxf(0.0f, z[(size_t)i * n + j] - lam * div_p(p1, p2, i, j, n));
 }
 
-__global__ __launch_bounds__(256) void tv_step_kernel(const float* __restrict__ z, const float* __restrict__ p_in,
-                                                      float* __restrict__ p_out, int n, float lam, float step) {
-    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (i >= n || j >= n) return;
+constexpr int kTvTile = 32;
+constexpr int kTvChunk = 10;
+constexpr int kTvMaxW = kTvTile + 2 * (kTvChunk + 1);
+
+// One workgroup = 16 waves (four per SIMD, to hide the LDS latency of the
+// dependent stencil reads); a wave sweeps one 64-wide LDS row at a time.
+constexpr int kTvThreads = 1024;
+constexpr int kTvRows = kTvThreads / 64;
+
+__device__ __forceinline__ void tv_prox_body(const float* __restrict__ z, const float* __restrict__ p_in,
+                                             float* __restrict__ p_out, float* __restrict__ x, int n, float lam,
+                                             float step, int steps, int bxi, int byi) {
+    __shared__ float sz[kTvMaxW * kTvMaxW], sx[kTvMaxW * kTvMaxW];
+    __shared__ float s1[kTvMaxW * kTvMaxW], s2[kTvMaxW * kTvMaxW];
+    const int H = steps + 1, W = kTvTile + 2 * H;
+    const int i0 = byi * kTvTile - H, j0 = bxi * kTvTile - H;
+    const int c = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const size_t nn = (size_t)n * n;
-    const float* __restrict__ p1 = p_in;
-    const float* __restrict__ p2 = p_in + nn;
-    const float xc = xtilde(z, p1, p2, i, j, n, lam);
-    const float g1 = (j < n - 1) ? xtilde(z, p1, p2, i, j + 1, n, lam) - xc : 0.0f;
-    const float g2 = (i < n - 1) ? xtilde(z, p1, p2, i + 1, j, n, lam) - xc : 0.0f;
-    const size_t idx = (size_t)i * n + j;
-    const float q1 = p1[idx] - step * g1;
-    const float q2 = p2[idx] - step * g2;
-    const float s = fmaxf(1.0f, sqrtf(q1 * q1 + q2 * q2));
-    p_out[idx] = q1 / s;
-    p_out[nn + idx] = q2 / s;
+    const int j = j0 + c;
+    const bool colin = c < W;
+    const bool jin = colin && j >= 0 && j < n;
+    for (int r = ty; r < W; r += kTvRows) {
+        const int i = i0 + r;
+        if (!colin) continue;
+        const int o = r * W + c;
+        float zz = 0.f, a1 = 0.f, a2 = 0.f;
+        if (jin && i >= 0 && i < n) {
+            const size_t g = (size_t)i * n + j;
+            zz = z[g];
+            a1 = p_in[g];
+            a2 = p_in[nn + g];
+        }
+        sz[o] = zz;
+        s1[o] = a1;
+        s2[o] = a2;
+    }
+    __syncthreads();
+    // x~ at LDS cell (r, c) with the masked divergence of the global pixel (i, j)
+    auto xt_at = [&](int r, int i) -> float {
+        const int o = r * W + c;
+        float d = 0.f;
+        if (j < n - 1) d += s1[o];
+        if (j > 0 && c > 0) d -= s1[o - 1];
+        if (i < n - 1) d += s2[o];
+        if (i > 0 && r > 0) d -= s2[o - W];
+        return fmaxf(0.f, sz[o] - lam * d);
+    };
+    for (int t = 1; t <= steps; ++t) {
+        // cells whose new p is still needed: rows / columns [t, W - t)
+        for (int r = t - 1 + ty; r < W - t + 1; r += kTvRows) {
+            if (!colin) continue;
+            sx[r * W + c] = xt_at(r, i0 + r);
+        }
+        __syncthreads();
+        for (int r = t + ty; r < W - t; r += kTvRows) {
+            const int i = i0 + r;
+            if (!(jin && c >= t && c < W - t && i >= 0 && i < n)) continue;
+            const int o = r * W + c;
+            const float xc = sx[o];
+            const float g1 = (j < n - 1) ? sx[o + 1] - xc : 0.f;
+            const float g2 = (i < n - 1) ? sx[o + W] - xc : 0.f;
+            const float q1 = s1[o] - step * g1, q2 = s2[o] - step * g2;
+            const float sc = fmaxf(1.f, sqrtf(q1 * q1 + q2 * q2));
+            s1[o] = q1 / sc;
+            s2[o] = q2 / sc;
+        }
+        __syncthreads();
+    }
+    for (int r = H + ty; r < H + kTvTile; r += kTvRows) {
+        const int i = i0 + r;
+        if (!(jin && c >= H && c < H + kTvTile && i < n)) continue;
+        const int o = r * W + c;
+        const size_t g = (size_t)i * n + j;
+        p_out[g] = s1[o];
+        p_out[nn + g] = s2[o];
+        if (x) x[g] = xt_at(r, i);
+    }
 }
 
-__global__ __launch_bounds__(256) void tv_finalize_kernel(const float* __restrict__ z, const float* __restrict__ p,
-                                                          float* __restrict__ x, int n, float lam) {
+// x may alias z (each pixel reads only its own z)
+__global__ __launch_bounds__(256) void tv_finalize_kernel(const float* z, const float* __restrict__ p, float* x, int n,
+                                                          float lam) {
     const int j = blockIdx.x * 64 + (threadIdx.x & 63);
     const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (i >= n || j >= n) return;
@@ -57,10 +123,82 @@ __global__ __launch_bounds__(256) void tv_finalize_kernel(const float* __restric
     x[(size_t)i * n + j] = (lam == 0.0f) ? fmaxf(0.0f, z[(size_t)i * n + j]) : xtilde(z, p, p + nn, i, j, n, lam);
 }
 
-hipError_t launch_tv_step(const float* z, const float* p_in, float* p_out, int n, float lam, float step,
-                          hipStream_t s) {
+__global__ __launch_bounds__(kTvThreads) void tv_prox_kernel(const float* __restrict__ z,
+                                                             const float* __restrict__ p_in,
+                                                             float* __restrict__ p_out, float* __restrict__ x, int n,
+                                                             float lam, float step, int steps) {
+    tv_prox_body(z, p_in, p_out, x, n, lam, step, steps, blockIdx.x, blockIdx.y);
+}
+
+// Batched TV prox chunk: p[src] -> p[1 - src] for every problem, x written on
+// the last chunk; a problem with lam == 0 (beta = 0) takes x = max(0, z).
+__global__ __launch_bounds__(kTvThreads) void tv_prox_batched(const BatchItem* __restrict__ items,
+                                                              const BlockRef* __restrict__ map, int src, int steps,
+                                                              int last) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const BatchItem& it = items[e.prob];
+    const int gx = (it.n + kTvTile - 1) / kTvTile;
+    const int bxi = e.local % gx, byi = e.local / gx;
+    if (it.lam > 0.f) {
+        tv_prox_body(it.z, it.p[src], it.p[1 - src], last ? it.x : nullptr, it.n, it.lam, it.tvstep, steps, bxi,
+                     byi);
+    } else if (last) {
+        const int c = threadIdx.x & 63, ty = threadIdx.x >> 6;
+        const int j = bxi * kTvTile + c;
+        for (int r = ty; r < kTvTile; r += kTvRows) {
+            const int i = byi * kTvTile + r;
+            if (c < kTvTile && i < it.n && j < it.n) {
+                const size_t g = (size_t)i * it.n + j;
+                it.x[g] = fmaxf(0.f, it.z[g]);
+            }
+        }
+    }
+}
+
+hipError_t launch_tv_prox_batched(const BatchItem* items, const BlockRef* map, int nblocks, int src, int steps,
+                                  bool last, hipStream_t s) {
+    tv_prox_batched<<<nblocks, kTvThreads, 0, s>>>(items, map, src, steps, last ? 1 : 0);
+    return hipGetLastError();
+}
+
+int tv_tiles(int n) { return (n + kTvTile - 1) / kTvTile; }
+int tv_chunk_max() { return kTvChunk; }
+
+__global__ __launch_bounds__(256) void grad_ball_kernel(const float* __restrict__ xb, float* __restrict__ p, int n,
+                                                        float sg) {
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= n || j >= n) return;
+    const size_t nn = (size_t)n * n, idx = (size_t)i * n + j;
+    const float xc = xb[idx];
+    const float g1 = (j < n - 1) ? xb[idx + 1] - xc : 0.f;
+    const float g2 = (i < n - 1) ? xb[idx + n] - xc : 0.f;
+    const float q1 = fmaf(sg, g1, p[idx]), q2 = fmaf(sg, g2, p[nn + idx]);
+    const float sc = fmaxf(1.f, sqrtf(q1 * q1 + q2 * q2));
+    p[idx] = q1 / sc;
+    p[nn + idx] = q2 / sc;
+}
+
+hipError_t launch_grad_ball(const float* xb, float* p, int n, float sg, hipStream_t s) {
     dim3 grid((n + 63) / 64, (n + 3) / 4);
-    tv_step_kernel<<<grid, 256, 0, s>>>(z, p_in, p_out, n, lam, step);
+    grad_ball_kernel<<<grid, 256, 0, s>>>(xb, p, n, sg);
+    return hipGetLastError();
+}
+
+hipError_t launch_tv_prox(const float* z, float* p_a, float* p_b, float* x, int n, float lam, float step,
+                          int n_iter, float** p_final, hipStream_t s) {
+    dim3 grid((n + kTvTile - 1) / kTvTile, (n + kTvTile - 1) / kTvTile);
+    float* src = p_a;
+    float* dst = p_b;
+    int left = n_iter;
+    do {
+        const int k = left < kTvChunk ? left : kTvChunk;
+        left -= k;
+        tv_prox_kernel<<<grid, kTvThreads, 0, s>>>(z, src, dst, left == 0 ? x : nullptr, n, lam, step, k);
+        std::swap(src, dst);
+    } while (left > 0);
+    *p_final = src;
     return hipGetLastError();
 }
 

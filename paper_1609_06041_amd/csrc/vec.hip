@@ -223,6 +223,88 @@ hipError_t launch_normalize(double* y, const double* x, const double* sumsq, siz
     return hipGetLastError();
 }
 
+// out = (c0 a + c1 b + c2 c) .* w   (b, c, w may be null; out may alias a, b or c)
+__global__ __launch_bounds__(256) void lin3_kernel(float* out, const float* a, float c0, const float* b, float c1,
+                                                   const float* c, float c2, const float* __restrict__ w,
+                                                   size_t len) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= len) return;
+    float r = c0 * a[i];
+    if (b) r = fmaf(c1, b[i], r);
+    if (c) r = fmaf(c2, c[i], r);
+    if (w) r *= w[i];
+    out[i] = r;
+}
+
+hipError_t launch_lin3_f32(float* out, const float* a, float c0, const float* b, float c1, const float* c, float c2,
+                           const float* w, size_t len, hipStream_t s) {
+    lin3_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(out, a, c0, b, c1, c, c2, w, len);
+    return hipGetLastError();
+}
+
+// out = a .* w with float weights (float64 operator applications)
+__global__ __launch_bounds__(256) void mul_w_kernel(double* __restrict__ out, const double* __restrict__ a,
+                                                    const float* __restrict__ w, size_t len) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < len) out[i] = a[i] * (double)w[i];
+}
+
+hipError_t launch_mul_w_f64(double* out, const double* a, const float* w, size_t len, hipStream_t s) {
+    mul_w_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(out, a, w, len);
+    return hipGetLastError();
+}
+
+// Batched solve start / end, 2048 elements per workgroup of the problem's
+// virtual concatenation [x | p0 | mu0 | mu1] (init: zeroed) or [x] (copy-out).
+__global__ __launch_bounds__(256) void batch_init_kernel(const BatchItem* __restrict__ items,
+                                                         const BlockRef* __restrict__ map) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const BatchItem& it = items[e.prob];
+    const size_t J = (size_t)it.n * it.n, I = (size_t)it.m * it.nb;
+    for (int r = 0; r < 8; ++r) {
+        size_t i = (size_t)e.local * 2048 + r * 256 + threadIdx.x;
+        if (i < J) {
+            it.x[i] = 0.f;
+            continue;
+        }
+        i -= J;
+        if (i < 2 * J) {
+            it.p[0][i] = 0.f;
+            continue;
+        }
+        i -= 2 * J;
+        if (i < I) {
+            it.mu[0][i] = 0.f;
+            continue;
+        }
+        i -= I;
+        if (i < I) it.mu[1][i] = 0.f;
+    }
+}
+
+__global__ __launch_bounds__(256) void batch_copy_out_kernel(const BatchItem* __restrict__ items,
+                                                             const BlockRef* __restrict__ map) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const BatchItem& it = items[e.prob];
+    const size_t J = (size_t)it.n * it.n;
+    for (int r = 0; r < 8; ++r) {
+        const size_t i = (size_t)e.local * 2048 + r * 256 + threadIdx.x;
+        if (i < J) it.x_out[i] = it.x[i];
+    }
+}
+
+hipError_t launch_batch_init(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s) {
+    batch_init_kernel<<<nblocks, 256, 0, s>>>(items, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_copy_out(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s) {
+    batch_copy_out_kernel<<<nblocks, 256, 0, s>>>(items, map);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void axpby_kernel(double* __restrict__ y, const double* __restrict__ x, double a,
                                                     double b, const double* __restrict__ z, double c, size_t len) {
     const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;

@@ -32,6 +32,13 @@ _SIGNATURES = {
     "ctpd_pd_lowdose_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p,
                                       c_void_p]),
     "ctpd_pd_fewview_solve": (c_int, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "ctpd_gist_lowdose_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p,
+                                        c_void_p]),
+    "ctpd_cp_fewview_solve": (c_int, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "ctpd_batch_create": (c_int, [c_void_p, c_int32, c_void_p, POINTER(c_void_p)]),
+    "ctpd_batch_destroy": (None, [c_void_p]),
+    "ctpd_batch_lowdose_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
+                                         c_void_p]),
     "ctpd_strerror": (ctypes.c_char_p, [c_int]),
 }
 
@@ -236,3 +243,73 @@ class Operator:
         _check(load().ctpd_pd_fewview_solve(self._h, _ptr(b, (self.m, self.nb), "b"), int(iters), byref(prm),
                                             _ptr(out, (self.n, self.n), "out"), byref(rep)))
         return out, self._info(rep, cost, state)
+
+    def gist_lowdose_solve(self, b: torch.Tensor, w: torch.Tensor, beta: float, iters: int, *, gamma=None,
+                           lam=None, safety=0.95, norm_steps=100, record_cost=False, return_state=False,
+                           out: torch.Tensor | None = None):
+        """GIST comparator for Eq. 1 (no preconditioner).  Returns (x, info); info['tau'] is gamma."""
+        out = self._img() if out is None else out
+        prm = _params(gamma, lam, 0, 0, safety, norm_steps, record_cost)
+        rep, cost, state = self._report(iters, record_cost, return_state)
+        _check(load().ctpd_gist_lowdose_solve(self._h, _ptr(b, (self.m, self.nb), "b"),
+                                              _ptr(w, (self.m, self.nb), "w"), float(beta), int(iters),
+                                              byref(prm), _ptr(out, (self.n, self.n), "out"), byref(rep)))
+        return out, self._info(rep, cost, state)
+
+    def cp_fewview_solve(self, b: torch.Tensor, iters: int, *, t=None, s=None, safety=0.95, norm_steps=100,
+                         record_cost=False, return_state=False, out: torch.Tensor | None = None):
+        """Chambolle-Pock comparator for the few-view problem.  Returns (x, info)."""
+        out = self._img() if out is None else out
+        prm = _params(t, s, 0, 0, safety, norm_steps, record_cost)
+        rep, cost, state = self._report(iters, record_cost, return_state)
+        _check(load().ctpd_cp_fewview_solve(self._h, _ptr(b, (self.m, self.nb), "b"), int(iters), byref(prm),
+                                            _ptr(out, (self.n, self.n), "out"), byref(rep)))
+        return out, self._info(rep, cost, state)
+
+
+class Batch:
+    """Independent low-dose problems of uneven sizes, solved together (Algorithm 1 on each)."""
+
+    def __init__(self, geoms, stream: torch.cuda.Stream | None = None):
+        self.geoms = [(int(n), int(m), int(nb)) for n, m, nb in geoms]
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.device = self.stream.device
+        arr = (Geometry * len(self.geoms))(*[Geometry(*g) for g in self.geoms])
+        h = c_void_p()
+        with torch.cuda.device(self.device):
+            _check(load().ctpd_batch_create(arr, len(self.geoms), c_void_p(self.stream.cuda_stream), byref(h)))
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().ctpd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def lowdose_solve(self, bs, ws, betas, iters: int, *, tau=None, sigma=None, tv_iters=10, tv_step=0.125,
+                      safety=0.95, norm_steps=100, outs=None):
+        """Returns (list of x, list of info dicts)."""
+        P = len(self.geoms)
+        if not (len(bs) == len(ws) == len(betas) == P):
+            raise ValueError(f"need {P} sinograms, weights and betas")
+        if outs is None:
+            outs = [torch.empty((n, n), dtype=torch.float32, device=self.device) for n, _, _ in self.geoms]
+        pb = (c_void_p * P)(*[_ptr(b, (m, nb), "b") for b, (_, m, nb) in zip(bs, self.geoms)])
+        pw = (c_void_p * P)(*[_ptr(w, (m, nb), "w") for w, (_, m, nb) in zip(ws, self.geoms)])
+        px = (c_void_p * P)(*[_ptr(x, (n, n), "out") for x, (n, _, _) in zip(outs, self.geoms)])
+        pbeta = (c_double * P)(*[float(v) for v in betas])
+        prm = _params(tau, sigma, tv_iters, tv_step, safety, norm_steps, False)
+        reps = (Report * P)()
+        _check(load().ctpd_batch_lowdose_solve(self._h, pb, pw, pbeta, int(iters), byref(prm), px, reps))
+        return outs, [Operator._info(r, None, {}) for r in reps]

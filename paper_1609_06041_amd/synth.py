@@ -155,6 +155,28 @@ WORKLOADS = {
 }
 
 
+# The batched uneven workload: independent low-dose problems whose image side
+# N, view count m, phantom size and dose are drawn per problem; nb = ceil(1.42 N)
+# so the detector covers the image diagonal.
+BATCH_SIDES = (256, 384, 512)
+BATCH_VIEWS = (32, 90, 360, 720)
+
+
+def batch_spec(problem_id: int, config_id: int = 3) -> dict:
+    rng = rng_for(config_id, problem_id, 2)
+    n = int(BATCH_SIDES[rng.integers(len(BATCH_SIDES))])
+    m = int(BATCH_VIEWS[rng.integers(len(BATCH_VIEWS))])
+    return dict(config_id=config_id, problem_id=problem_id, n=n, m=m, nb=int(math.ceil(1.42 * n)),
+                n_ellipses=int(rng.integers(10, 21)), i0=float(rng.uniform(1e4, 1e5)), beta=0.005, iters=20)
+
+
+def batch_problem(problem_id: int, config_id: int = 3, with_x_true: bool = False) -> tuple[Problem, dict]:
+    spec = batch_spec(problem_id, config_id)
+    prob = make_problem(config_id, problem_id, spec["n"], spec["m"], spec["nb"], spec["n_ellipses"], spec["i0"],
+                        with_x_true=with_x_true)
+    return prob, spec
+
+
 def workload_problem(name: str, problem_id: int = 0, with_x_true: bool = True) -> tuple[Problem, dict]:
     spec = dict(WORKLOADS[name])
     prob = make_problem(spec["config_id"], problem_id, spec["n"], spec["m"], spec["nb"],
