@@ -26,6 +26,9 @@ readability against the paper rather than speed:
                   cost (Eq. 1), partial primal-dual gap, RMSE (Eq. 34)
 * ``comparators`` - the unpreconditioned comparators of Sec. 4: GIST for
                   Eq. 1 and Chambolle-Pock for the few-view problem
+* ``unrolled``  - Algorithm 1 unrolled for a fixed number of iterations as a
+                  function of (b, beta, tau, sigma), and its float64
+                  central-difference gradient
 
 Pins (tests/test_oracle_*.py) tie each function to something other than
 itself: closed-form chord integrals and Gaussian projections, exact column
@@ -40,4 +43,4 @@ Parity unpinned: the iterates x^k at the exact iteration counts used for
 GPU parity have no printed values in the paper (its figures are missing);
 they are pinned only through the limits above.
 """
-from . import geometry, projector, filters, tv, app, comparators  # noqa: F401
+from . import geometry, projector, filters, tv, app, comparators, unrolled  # noqa: F401
