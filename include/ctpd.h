@@ -173,6 +173,34 @@ int ctpd_batch_lowdose_solve(ctpd_batch* batch, const float* const* b, const flo
                              const double* beta, int32_t iters, const ctpd_params* p, float* const* x_out,
                              ctpd_report* reps);
 
+/* ---- unrolled, differentiable Algorithm 1 --------------------------------
+ * x^K as a function of (b, beta, tau, sigma): exactly iters iterations of
+ * Eqs. 18-20 from zero with the given step sizes (no operator norms) and
+ * D = D(tau), the smoothed ramp of Eq. 24 at kappa = mean(1/w).  The forward
+ * pass keeps every iteration's state in a caller-owned checkpoint buffer; the
+ * reverse pass returns the gradient of <x_grad, x^K> with respect to b and
+ * the three scalars. */
+
+/* Number of floats of the checkpoint buffer for iters iterations:
+ * (iters + 1) * (3 n^2 + n_views n_bins) (x^k, mu^k, p^k per iteration). */
+int ctpd_unrolled_ckpt_floats(const ctpd_op* op, int32_t iters, size_t* count);
+
+/* Forward pass.  b, w: [n_views][n_bins] (as ctpd_pd_lowdose_solve); beta >= 0,
+ * tau > 0, sigma > 0, iters >= 1; p: NULL or knobs (tv_iters, tv_step are
+ * used); ckpt: device buffer of ctpd_unrolled_ckpt_floats floats, written;
+ * x_out: [n][n] receives x^iters.  Same arithmetic as ctpd_pd_lowdose_solve at
+ * these step sizes.  Stream-ordered after one host synchronisation (kappa). */
+int ctpd_unrolled_lowdose_forward(ctpd_op* op, const float* b, const float* w, double beta, double tau,
+                                  double sigma, int32_t iters, const ctpd_params* p, float* ckpt, float* x_out);
+
+/* Reverse pass for the same arguments and the checkpoints of the forward
+ * pass.  x_grad: [n][n] adjoint of x^iters; b_grad: [n_views][n_bins]
+ * receives d<x_grad, x^K>/db; grads (host, 3 doubles) receives the
+ * derivatives with respect to beta, tau, sigma.  Synchronises the stream. */
+int ctpd_unrolled_lowdose_backward(ctpd_op* op, const float* b, const float* w, double beta, double tau,
+                                   double sigma, int32_t iters, const ctpd_params* p, const float* ckpt,
+                                   const float* x_grad, float* b_grad, double* grads);
+
 /* Comparator for the low-dose problem of Eq. 1 (Sec. 4 compares Algorithm 1
  * with it; Table 1 lists it): GIST, the Loris-Verhoeven iteration -- a
  * gradient step on the weighted data term, a projection step on the dual of

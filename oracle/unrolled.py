@@ -43,6 +43,9 @@ def fd_gradients(b, w, beta, tau, sigma, n, iters, x_true, directions=(), h=1e-6
                                              a.get("sigma", sigma), n, iters, **kw), x_true)
     out = {}
     for name, val in (("beta", beta), ("tau", tau), ("sigma", sigma)):
+        if rel_h and val == 0.0:   # no relative step at zero (and beta = 0 is a kink of the prox)
+            out[name] = None
+            continue
         hh = h * val if rel_h else h
         out[name] = central_difference(lambda v: L(**{name: v}), val, hh)
     out["b_dir"] = [central_difference(lambda t: L(b=b + t * v), 0.0, h) for v in directions]

@@ -452,6 +452,7 @@ void ctpd_op_destroy(ctpd_op* op) {
         hipStreamDestroy(op->aux);
     }
     if (op->fork) hipEventDestroy(op->fork);
+    free_unrolled(op->uw);
     delete op;
 }
 

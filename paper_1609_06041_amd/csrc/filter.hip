@@ -25,15 +25,18 @@ struct GaussLegendre16 {
     double w[16];   // weights
 };
 
+// With d_tau, the taps of dH/dtau = -2m w / (2 m tau + kappa w)^2 (c1 = 2m):
+// for the ramp that is -h / tau.
 __global__ __launch_bounds__(256) void taps_kernel(double* __restrict__ taps64, float* __restrict__ taps32,
                                                    int nb, double c0, double kappa, int panels,
-                                                   GaussLegendre16 gl) {
+                                                   GaussLegendre16 gl, double c1, int d_tau) {
     const int k = blockIdx.x;   // offset 0..nb-1
     double h;
     if (kappa == 0.0) {
         const double pi = 3.14159265358979323846;
         h = (k == 0) ? pi / 2.0 : ((k & 1) ? -2.0 / (pi * (double)k * (double)k) : 0.0);
         h /= c0;
+        if (d_tau) h *= -c1 / c0;
     } else {
         const double pi = 3.14159265358979323846;
         const double width = pi / panels;
@@ -44,7 +47,9 @@ __global__ __launch_bounds__(256) void taps_kernel(double* __restrict__ taps64, 
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const double w = fma(half, gl.x[q], mid);
-                ps = fma(gl.w[q], w * cos((double)k * w) / fma(kappa, w, c0), ps);
+                const double den = fma(kappa, w, c0);
+                const double hw = d_tau ? -c1 * w / (den * den) : w / den;
+                ps = fma(gl.w[q], hw * cos((double)k * w), ps);
             }
             acc += ps * half;
         }
@@ -100,10 +105,11 @@ static GaussLegendre16 make_gl16() {
     return g;
 }
 
-hipError_t launch_taps(double* taps64, float* taps32, int nb, int m, double tau, double kappa, hipStream_t s) {
+hipError_t launch_taps(double* taps64, float* taps32, int nb, int m, double tau, double kappa, hipStream_t s,
+                       bool d_tau) {
     static const GaussLegendre16 gl = make_gl16();
     const int panels = nb < 32 ? 64 : 2 * nb;
-    taps_kernel<<<nb, 256, 0, s>>>(taps64, taps32, nb, 2.0 * m * tau, kappa, panels, gl);
+    taps_kernel<<<nb, 256, 0, s>>>(taps64, taps32, nb, 2.0 * m * tau, kappa, panels, gl, 2.0 * m, d_tau ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -102,8 +102,9 @@ int forward_blocks_x(int nb);   // forward-projector workgroups per view
 
 // ---- filter.hip ----------------------------------------------------------
 // taps64[k], k = 0..2nb-2, for offset k - (nb-1); also written rounded to taps32.
+// d_tau: the taps of dH/dtau instead of H (the filter's derivative in tau).
 hipError_t launch_taps(double* taps64, float* taps32, int nb, int m, double tau, double kappa,
-                       hipStream_t s);
+                       hipStream_t s, bool d_tau = false);
 hipError_t launch_filter_f32(const FilterArgs& a, const float* taps32, int m, int nb, hipStream_t s);
 // out = scale_in * D (scale_in .* in), elementwise scale optional (null = 1), then
 // out *= scale_out (optional)
@@ -131,6 +132,20 @@ hipError_t launch_tv_prox_batched(const BatchItem* items, const BlockRef* map, i
                                   bool last, hipStream_t s);
 int tv_tiles(int n);      // TV tiles per image side
 int tv_chunk_max();       // dual steps per TV launch at most
+// steps (<= tv_chunk_max()) dual steps from p_in into p_out without touching
+// p_in; x = max(0, z - lam div p_out) written when x is not null.
+hipError_t launch_tv_steps(const float* z, const float* p_in, float* p_out, float* x, int n, float lam, float step,
+                           int steps, hipStream_t s);
+// Reverse pass of the TV prox (one dual step = three kernels, in reverse order
+// of use), see tv.hip.
+hipError_t launch_tv_bwd_final(const float* z, const float* p, const float* xbar, int n, float lam, float* tbar,
+                               float* zbar, float* prod, hipStream_t s);
+hipError_t launch_tv_bwd_proj(const float* z, const float* p_prev, const float* pbar, int n, float lam, float step,
+                              float* qbar, float* prod, hipStream_t s);
+hipError_t launch_tv_bwd_mask(const float* z, const float* p_prev, const float* qbar, int n, float lam, float step,
+                              float* tbar, float* zbar, float* prod, hipStream_t s);
+hipError_t launch_tv_bwd_grad(const float* qbar, const float* tbar, int n, float lam, float* pbar,
+                              hipStream_t s);
 hipError_t launch_tv_finalize(const float* z, const float* p, float* x, int n, float lam, hipStream_t s);
 
 // ---- vec.hip -------------------------------------------------------------
@@ -142,6 +157,8 @@ enum ReduceOp : int {
     RED_WRES_F32 = 3,      // sum w*(q-b)^2                     (float)
     RED_SQDIFF_F32 = 4,    // sum (q-b)^2                       (float)
     RED_SQ_F32 = 5,        // sum b^2                           (float)
+    RED_DOT_F32 = 6,       // sum a[i]*b[i]                    (float)
+    RED_SUM_F32 = 7,       // sum a[i]                          (float)
 };
 // Result (3 doubles: value, count1, count2) written to dev_out[0..2].
 hipError_t launch_reduce(int op, const void* a, const void* b, const void* c, size_t len,
@@ -168,6 +185,9 @@ hipError_t launch_scale_f64(double* y, const double* x, double a, size_t len, hi
 // out[i] = f(x[i]): inverse (1/x) or sqrt(1/x)   (float in, float / double out)
 hipError_t launch_lin3_f32(float* out, const float* a, float c0, const float* b, float c1, const float* c, float c2,
                            const float* w, size_t len, hipStream_t s);
+// out = c0 a + c1 b + c2 (c .* d)   (b, c may be null; d null = ones; out may alias a or b)
+hipError_t launch_lin_mix_f32(float* out, const float* a, float c0, const float* b, float c1, const float* c,
+                              const float* d, float c2, size_t len, hipStream_t s);
 hipError_t launch_mul_w_f64(double* out, const double* a, const float* w, size_t len, hipStream_t s);
 // batched solve: zero x, p[0], mu[0], mu[1] of every problem / copy x to x_out
 // (2048 elements per workgroup)

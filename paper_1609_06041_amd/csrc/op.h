@@ -15,6 +15,11 @@
 
 using ctpd::ViewGeom;
 
+namespace ctpd_host {
+struct UnrolledWs;
+void free_unrolled(UnrolledWs* u);
+}  // namespace ctpd_host
+
 // The operator handle: geometry tables and every workspace of a solve,
 // allocated once per geometry.
 struct ctpd_op {
@@ -58,6 +63,8 @@ struct ctpd_op {
     // per-iteration monitor values (device), 2 * cost_cap slots of 3 doubles
     double* cost_dev = nullptr;
     int cost_cap = 0;
+    // workspaces of the unrolled solve's reverse pass (allocated on first use)
+    ctpd_host::UnrolledWs* uw = nullptr;
 };
 
 namespace ctpd_host {

@@ -186,6 +186,133 @@ hipError_t launch_grad_ball(const float* xb, float* p, int n, float sg, hipStrea
     return hipGetLastError();
 }
 
+hipError_t launch_tv_steps(const float* z, const float* p_in, float* p_out, float* x, int n, float lam, float step,
+                           int steps, hipStream_t s) {
+    if (steps > kTvChunk) return hipErrorInvalidValue;
+    dim3 grid((n + kTvTile - 1) / kTvTile, (n + kTvTile - 1) / kTvTile);
+    tv_prox_kernel<<<grid, kTvThreads, 0, s>>>(z, p_in, p_out, x, n, lam, step, steps);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Reverse pass of the prox (for the unrolled solve's gradient).  One forward
+// dual step maps p to p' = P(q), q = p - step grad x~, x~ = max(0, z - lam div p),
+// P the pointwise projection onto the unit ball.  Given the adjoint pbar of
+// p', the reverse step is
+//   qbar = J_P(q) pbar        (J_P = I inside the ball, (I - q^ q^T)/|q| outside)
+//   t    = [z - lam div p > 0] * step * div qbar      (adjoint of x~ through grad)
+//   pbar_prev = qbar + lam grad t,   zbar += t,
+// and the scalar adjoints collect -t . div p (for lam) and -qbar . grad x~ (for
+// step).  Each kernel recomputes what it needs from z and the stored p.
+__device__ __forceinline__ float tv_div(const float* __restrict__ p1, const float* __restrict__ p2, int i, int j,
+                                        int n, size_t idx) {
+    float d = 0.0f;
+    if (j < n - 1) d += p1[idx];
+    if (j > 0) d -= p1[idx - 1];
+    if (i < n - 1) d += p2[idx];
+    if (i > 0) d -= p2[idx - n];
+    return d;
+}
+
+#define TV_PIXEL                                              \
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63);       \
+    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);        \
+    if (i >= n || j >= n) return;                             \
+    const size_t nn = (size_t)n * n, idx = (size_t)i * n + j;
+
+__global__ __launch_bounds__(256) void tv_bwd_final_kernel(const float* __restrict__ z, const float* __restrict__ p,
+                                                           const float* __restrict__ xbar, int n, float lam,
+                                                           float* __restrict__ tbar, float* __restrict__ zbar,
+                                                           float* __restrict__ prod) {
+    TV_PIXEL
+    const float d = tv_div(p, p + nn, i, j, n, idx);
+    const float t = (z[idx] - lam * d > 0.0f) ? xbar[idx] : 0.0f;
+    tbar[idx] = t;
+    zbar[idx] = t;
+    prod[idx] = -t * d;
+}
+
+__global__ __launch_bounds__(256) void tv_bwd_proj_kernel(const float* __restrict__ z,
+                                                          const float* __restrict__ pp,
+                                                          const float* __restrict__ pbar, int n, float lam,
+                                                          float step, float* __restrict__ qbar,
+                                                          float* __restrict__ prod) {
+    TV_PIXEL
+    const float* p1 = pp;
+    const float* p2 = pp + nn;
+    const float xc = fmaxf(0.0f, z[idx] - lam * tv_div(p1, p2, i, j, n, idx));
+    const float g1 = (j < n - 1) ? fmaxf(0.0f, z[idx + 1] - lam * tv_div(p1, p2, i, j + 1, n, idx + 1)) - xc : 0.0f;
+    const float g2 = (i < n - 1) ? fmaxf(0.0f, z[idx + n] - lam * tv_div(p1, p2, i + 1, j, n, idx + n)) - xc : 0.0f;
+    const float q1 = p1[idx] - step * g1, q2 = p2[idx] - step * g2;
+    const float b1 = pbar[idx], b2 = pbar[nn + idx];
+    const float nq = sqrtf(q1 * q1 + q2 * q2);
+    float r1 = b1, r2 = b2;
+    if (nq > 1.0f) {
+        const float u1 = q1 / nq, u2 = q2 / nq;
+        const float dp = u1 * b1 + u2 * b2;
+        r1 = (b1 - u1 * dp) / nq;
+        r2 = (b2 - u2 * dp) / nq;
+    }
+    qbar[idx] = r1;
+    qbar[nn + idx] = r2;
+    prod[idx] = -(r1 * g1 + r2 * g2);
+}
+
+__global__ __launch_bounds__(256) void tv_bwd_mask_kernel(const float* __restrict__ z,
+                                                          const float* __restrict__ pp,
+                                                          const float* __restrict__ qbar, int n, float lam,
+                                                          float step, float* __restrict__ tbar,
+                                                          float* __restrict__ zbar, float* __restrict__ prod) {
+    TV_PIXEL
+    const float d = tv_div(pp, pp + nn, i, j, n, idx);
+    const float xtb = step * tv_div(qbar, qbar + nn, i, j, n, idx);
+    const float t = (z[idx] - lam * d > 0.0f) ? xtb : 0.0f;
+    tbar[idx] = t;
+    zbar[idx] += t;
+    prod[idx] = -t * d;
+}
+
+__global__ __launch_bounds__(256) void tv_bwd_grad_kernel(const float* __restrict__ qbar,
+                                                          const float* __restrict__ tbar, int n, float lam,
+                                                          float* __restrict__ pbar) {
+    TV_PIXEL
+    const float tc = tbar[idx];
+    const float g1 = (j < n - 1) ? tbar[idx + 1] - tc : 0.0f;
+    const float g2 = (i < n - 1) ? tbar[idx + n] - tc : 0.0f;
+    pbar[idx] = qbar[idx] + lam * g1;
+    pbar[nn + idx] = qbar[nn + idx] + lam * g2;
+}
+
+#undef TV_PIXEL
+
+hipError_t launch_tv_bwd_final(const float* z, const float* p, const float* xbar, int n, float lam, float* tbar,
+                               float* zbar, float* prod, hipStream_t s) {
+    dim3 grid((n + 63) / 64, (n + 3) / 4);
+    tv_bwd_final_kernel<<<grid, 256, 0, s>>>(z, p, xbar, n, lam, tbar, zbar, prod);
+    return hipGetLastError();
+}
+
+hipError_t launch_tv_bwd_proj(const float* z, const float* p_prev, const float* pbar, int n, float lam, float step,
+                              float* qbar, float* prod, hipStream_t s) {
+    dim3 grid((n + 63) / 64, (n + 3) / 4);
+    tv_bwd_proj_kernel<<<grid, 256, 0, s>>>(z, p_prev, pbar, n, lam, step, qbar, prod);
+    return hipGetLastError();
+}
+
+hipError_t launch_tv_bwd_mask(const float* z, const float* p_prev, const float* qbar, int n, float lam, float step,
+                              float* tbar, float* zbar, float* prod, hipStream_t s) {
+    dim3 grid((n + 63) / 64, (n + 3) / 4);
+    tv_bwd_mask_kernel<<<grid, 256, 0, s>>>(z, p_prev, qbar, n, lam, step, tbar, zbar, prod);
+    return hipGetLastError();
+}
+
+hipError_t launch_tv_bwd_grad(const float* qbar, const float* tbar, int n, float lam, float* pbar,
+                              hipStream_t s) {
+    dim3 grid((n + 63) / 64, (n + 3) / 4);
+    tv_bwd_grad_kernel<<<grid, 256, 0, s>>>(qbar, tbar, n, lam, pbar);
+    return hipGetLastError();
+}
+
 hipError_t launch_tv_prox(const float* z, float* p_a, float* p_b, float* x, int n, float lam, float step,
                           int n_iter, float** p_final, hipStream_t s) {
     dim3 grid((n + kTvTile - 1) / kTvTile, (n + kTvTile - 1) / kTvTile);

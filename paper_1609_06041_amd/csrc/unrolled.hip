@@ -1,0 +1,324 @@
+// Algorithm 1 unrolled for a fixed number of iterations with given step sizes,
+// as a differentiable function of the data b, the TV weight beta and the steps
+// tau, sigma (the filter D = D(tau) of Eq. 24 depends on tau too).  The
+// forward pass runs exactly the solver's kernels and keeps the state
+// (x^k, mu^k, p^k) of every iteration in a caller-owned checkpoint buffer; the
+// reverse pass walks the iterations backwards, recomputing each iteration's
+// intermediates (the extrapolated dual variable, z, the inner TV dual fields)
+// from its checkpoint, and applies the transposed operators: A^T for A, A for
+// A^T, D and dD/dtau for themselves (symmetric Toeplitz), and the TV reverse
+// kernels for the prox.  Scalar adjoints are float64 sums gathered into
+// separate device slots and added on the host in a fixed order.
+#include "op.h"
+
+using namespace ctpd;
+
+namespace ctpd_host {
+
+struct UnrolledWs {
+    int tv_cap = -1;
+    int slot_cap = 0;
+    double* dtaps64 = nullptr;
+    float* dtaps32 = nullptr;
+    double dtap_tau = -1.0, dtap_kappa = -1.0;
+    float *ax = nullptr, *axt = nullptr, *zbar = nullptr, *tbar = nullptr, *prod = nullptr;
+    float *amu = nullptr, *amu2 = nullptr, *amup = nullptr, *amup2 = nullptr;
+    float *ap = nullptr, *pba = nullptr, *pbb = nullptr, *qbar = nullptr;
+    float *e = nullptr, *r = nullptr, *dr = nullptr, *dm = nullptr, *rbar = nullptr, *az = nullptr, *daz = nullptr,
+          *dpaz = nullptr;
+    float* ps = nullptr;   // (tv_cap + 1) dual fields of one outer iteration
+    double* slots = nullptr;
+    std::vector<double> slots_host;
+};
+
+void free_unrolled(UnrolledWs* u) {
+    if (!u) return;
+    void* ptrs[] = {u->dtaps64, u->dtaps32, u->ax,   u->axt, u->zbar, u->tbar, u->prod, u->amu,  u->amu2,
+                    u->amup,    u->amup2,   u->ap,   u->pba, u->pbb,  u->qbar, u->e,    u->r,    u->dr,
+                    u->dm,      u->rbar,    u->az,   u->daz, u->dpaz, u->ps,   u->slots};
+    for (void* p : ptrs)
+        if (p) hipFree(p);
+    delete u;
+}
+
+}  // namespace ctpd_host
+
+using namespace ctpd_host;
+
+namespace {
+
+int ensure_unrolled(ctpd_op* op, int tv_iters, int nslots) {
+    if (!op->uw) {
+        op->uw = new UnrolledWs();
+        UnrolledWs* u = op->uw;
+        const size_t J = op->J, I = op->I, T = 2 * (size_t)op->nb - 1;
+        ALLOC(u->dtaps64, T);
+        ALLOC(u->dtaps32, T);
+        for (float** p : {&u->ax, &u->axt, &u->zbar, &u->tbar, &u->prod}) ALLOC(*p, J);
+        for (float** p : {&u->amu, &u->amu2, &u->amup, &u->amup2, &u->e, &u->r, &u->dr, &u->dm, &u->rbar, &u->az,
+                          &u->daz, &u->dpaz})
+            ALLOC(*p, I);
+        for (float** p : {&u->ap, &u->pba, &u->pbb, &u->qbar}) ALLOC(*p, 2 * J);
+    }
+    UnrolledWs* u = op->uw;
+    if (u->tv_cap < tv_iters) {
+        if (u->ps) hipFree(u->ps);
+        u->ps = nullptr;
+        u->tv_cap = -1;
+        ALLOC(u->ps, (size_t)(tv_iters + 1) * 2 * op->J);
+        u->tv_cap = tv_iters;
+    }
+    if (u->slot_cap < nslots) {
+        if (u->slots) hipFree(u->slots);
+        u->slots = nullptr;
+        u->slot_cap = 0;
+        ALLOC(u->slots, (size_t)3 * nslots);
+        u->slot_cap = nslots;
+    }
+    return CTPD_OK;
+}
+
+// kappa = mean(1/w) with the validity scan, W^-1 and the taps of D(tau).
+int prepare(ctpd_op* op, const float* b, const float* w, double tau, double* kappa) {
+    int r;
+    if ((r = reduce(op, RED_INVW_CHECK, w, b, nullptr, op->I, 0))) return r;
+    if ((r = read_red(op))) return r;
+    if (op->red_host[1] > 0 || op->red_host[2] > 0) {
+        snprintf(g_errmsg, sizeof g_errmsg, "%.0f weights <= 0 or non-finite, %.0f non-finite data",
+                 op->red_host[1], op->red_host[2]);
+        return CTPD_EDOMAIN;
+    }
+    *kappa = op->red_host[0] / (double)op->I;
+    HIP_TRY(launch_inverse_f32(op->winv, w, op->I, op->stream));
+    return ensure_taps(op, tau, *kappa);
+}
+
+int check_args(ctpd_op* op, const float* b, const float* w, double beta, double tau, double sigma, int iters) {
+    if (!op || !b || !w) return einval("null pointer");
+    if (!(beta >= 0.0) || !std::isfinite(beta)) return einval("beta must be finite and >= 0");
+    if (!(tau > 0.0) || !std::isfinite(tau)) return einval("tau must be finite and > 0");
+    if (!(sigma > 0.0) || !std::isfinite(sigma)) return einval("sigma must be finite and > 0");
+    if (iters < 1) return einval("iters must be >= 1");
+    return CTPD_OK;
+}
+
+struct Slots {
+    size_t x, mu, p, stride;
+};
+
+Slots layout(const ctpd_op* op) {
+    const size_t J = op->J, I = op->I;
+    return Slots{0, J, J + I, 3 * J + I};
+}
+
+// out = c * D s with the given float32 taps
+int filt(ctpd_op* op, const float* taps, const float* in, float c, float* out, const float* E0 = nullptr,
+         float e0 = 0.f) {
+    FilterArgs a{};
+    a.in0 = in;
+    a.E0 = E0;
+    a.e0 = e0;
+    a.c = c;
+    a.mode = FILT_PLAIN;
+    a.out = out;
+    HIP_TRY(launch_filter_f32(a, taps, op->m, op->nb, op->stream));
+    return CTPD_OK;
+}
+
+enum Cat { C_SIGMA, C_TAU, C_LAM, C_STEP };
+
+}  // namespace
+
+extern "C" {
+
+int ctpd_unrolled_ckpt_floats(const ctpd_op* op, int32_t iters, size_t* count) {
+    g_errmsg[0] = 0;
+    if (!op || !count) return einval("null pointer");
+    if (iters < 1) return einval("iters must be >= 1");
+    *count = (size_t)(iters + 1) * layout(op).stride;
+    return CTPD_OK;
+}
+
+int ctpd_unrolled_lowdose_forward(ctpd_op* op, const float* b, const float* w, double beta, double tau,
+                                  double sigma, int32_t iters, const ctpd_params* p, float* ckpt, float* x_out) {
+    g_errmsg[0] = 0;
+    int r = check_args(op, b, w, beta, tau, sigma, iters);
+    if (r) return r;
+    if (!ckpt || !x_out) return einval("null pointer");
+    Knobs k;
+    if ((r = read_params(p, &k))) return r;
+    double kappa = 0.0;
+    if ((r = prepare(op, b, w, tau, &kappa))) return r;
+    const size_t J = op->J;
+    const Slots L = layout(op);
+    hipStream_t s = op->stream;
+    auto X = [&](int i) { return ckpt + (size_t)i * L.stride + L.x; };
+    auto MU = [&](int i) { return ckpt + (size_t)i * L.stride + L.mu; };
+    auto P = [&](int i) { return ckpt + (size_t)i * L.stride + L.p; };
+    HIP_TRY(launch_fill_f32(ckpt, 0.f, L.stride, s));
+    const float fs = (float)sigma, ft = (float)tau, lam = (float)(tau * beta);
+    const float tvstep = lam > 0 ? (float)(k.tv_step / (tau * beta)) : 0.f;
+    for (int it = 0; it < iters; ++it) {
+        float *x = X(it), *mu = MU(it), *mup = MU(it > 0 ? it - 1 : 0);
+        if (it == 0)
+            r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, -fs, op->mubar);
+        else
+            r = filter(op, FILT_EXTRAP, op->winv, mu, mup, nullptr, mu, 2.f, mup, -1.f, -fs, op->mubar);
+        if (r) return r;
+        HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, x, 1.f, -ft, op->z, op->views, op->n, op->m,
+                                      op->nb, s));
+        HIP_TRY(launch_copy_f32(op->p[0], P(it), 2 * J, s));
+        float* pf = nullptr;
+        if ((r = tv_prox(op, op->z, lam, k.tv_iters, tvstep, op->p[0], op->p[1], X(it + 1), &pf))) return r;
+        HIP_TRY(launch_copy_f32(P(it + 1), pf, 2 * J, s));
+        if ((r = project(op, X(it + 1), op->q))) return r;
+        if ((r = filter(op, FILT_DUAL_LD, op->q, b, op->winv, mu, mu, 1.f, nullptr, 0.f, fs, MU(it + 1)))) return r;
+    }
+    HIP_TRY(launch_copy_f32(x_out, X(iters), J, s));
+    return CTPD_OK;
+}
+
+int ctpd_unrolled_lowdose_backward(ctpd_op* op, const float* b, const float* w, double beta, double tau,
+                                   double sigma, int32_t iters, const ctpd_params* p, const float* ckpt,
+                                   const float* x_grad, float* b_grad, double* grads) {
+    g_errmsg[0] = 0;
+    int r = check_args(op, b, w, beta, tau, sigma, iters);
+    if (r) return r;
+    if (!ckpt || !x_grad || !b_grad || !grads) return einval("null pointer");
+    Knobs k;
+    if ((r = read_params(p, &k))) return r;
+    const int nt = k.tv_iters;
+    const int per_iter = 2 * nt + 8;
+    if ((r = ensure_unrolled(op, nt, iters * per_iter))) return r;
+    double kappa = 0.0;
+    if ((r = prepare(op, b, w, tau, &kappa))) return r;
+    UnrolledWs* u = op->uw;
+    if (u->dtap_tau != tau || u->dtap_kappa != kappa) {
+        HIP_TRY(launch_taps(u->dtaps64, u->dtaps32, op->nb, op->m, tau, kappa, op->stream, true));
+        u->dtap_tau = tau;
+        u->dtap_kappa = kappa;
+    }
+    const size_t J = op->J, I = op->I;
+    const Slots L = layout(op);
+    hipStream_t s = op->stream;
+    auto X = [&](int i) { return ckpt + (size_t)i * L.stride + L.x; };
+    auto MU = [&](int i) { return ckpt + (size_t)i * L.stride + L.mu; };
+    auto P = [&](int i) { return ckpt + (size_t)i * L.stride + L.p; };
+    auto PS = [&](int i) { return u->ps + (size_t)i * 2 * J; };
+    const float fs = (float)sigma, ft = (float)tau, lam = (float)(tau * beta);
+    const float tvstep = lam > 0 ? (float)(k.tv_step / (tau * beta)) : 0.f;
+    const float* taps = op->taps32;
+    const float* dtaps = u->dtaps32;
+    // scalar adjoint terms: (category, factor) per device slot
+    std::vector<std::pair<int, double>> terms;
+    auto dot = [&](int cat, double factor, const float* a, const float* bb, size_t len) -> int {
+        const int slot = (int)terms.size();
+        terms.emplace_back(cat, factor);
+        HIP_TRY(launch_reduce(RED_DOT_F32, a, bb, nullptr, len, op->partials, u->slots + 3 * slot, s));
+        return CTPD_OK;
+    };
+    auto sum = [&](int cat, const float* a, size_t len) -> int {
+        const int slot = (int)terms.size();
+        terms.emplace_back(cat, 1.0);
+        HIP_TRY(launch_reduce(RED_SUM_F32, a, nullptr, nullptr, len, op->partials, u->slots + 3 * slot, s));
+        return CTPD_OK;
+    };
+    // adjoint state of (x^{k+1}, mu^{k+1}, mu^k as the next iteration's mu_prev, p^{k+1})
+    HIP_TRY(launch_copy_f32(u->ax, x_grad, J, s));
+    HIP_TRY(launch_fill_f32(u->amu, 0.f, I, s));
+    HIP_TRY(launch_fill_f32(u->amup, 0.f, I, s));
+    HIP_TRY(launch_fill_f32(u->ap, 0.f, 2 * J, s));
+    HIP_TRY(launch_fill_f32(b_grad, 0.f, I, s));
+    for (int it = iters - 1; it >= 0; --it) {
+        const float *x = X(it), *mu = MU(it), *mup = MU(it > 0 ? it - 1 : 0), *x1 = X(it + 1);
+        // recompute the extrapolated dual variable, z and the inner dual fields
+        const float* e = b;
+        if (it == 0) {
+            r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, -fs, op->mubar);
+        } else {
+            HIP_TRY(launch_lin3_f32(u->e, mu, 1.f, mup, -1.f, nullptr, 0.f, op->winv, I, s));
+            e = u->e;
+            r = filter(op, FILT_EXTRAP, op->winv, mu, mup, nullptr, mu, 2.f, mup, -1.f, -fs, op->mubar);
+        }
+        if (r) return r;
+        HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, x, 1.f, -ft, op->z, op->views, op->n, op->m,
+                                      op->nb, s));
+        HIP_TRY(launch_copy_f32(PS(0), P(it), 2 * J, s));
+        if (lam > 0)
+            for (int i = 1; i <= nt; ++i)
+                HIP_TRY(launch_tv_steps(op->z, PS(i - 1), PS(i), nullptr, op->n, lam, tvstep, 1, s));
+        if ((r = project(op, x1, op->q))) return r;
+        HIP_TRY(launch_lin_mix_f32(u->r, op->q, 1.f, b, -1.f, op->winv, mu, -1.f, I, s));
+        // mu^{k+1} = mu + sigma D r
+        if ((r = filt(op, taps, u->r, 1.f, u->dr))) return r;
+        if ((r = dot(C_SIGMA, 1.0, u->amu, u->dr, I))) return r;
+        if ((r = filt(op, dtaps, u->amu, 1.f, u->dm))) return r;
+        if ((r = dot(C_TAU, sigma, u->dm, u->r, I))) return r;
+        if ((r = filt(op, taps, u->amu, fs, u->rbar))) return r;
+        // r = A x^{k+1} - b - W^-1 mu
+        HIP_TRY(launch_lin_mix_f32(u->amu2, u->amu, 1.f, u->amup, 1.f, op->winv, u->rbar, -1.f, I, s));
+        HIP_TRY(launch_adjoint<float>(u->rbar, nullptr, 1.f, 0.f, u->ax, 1.f, 1.f, u->axt, op->views, op->n, op->m,
+                                      op->nb, s));
+        HIP_TRY(launch_lin_mix_f32(b_grad, b_grad, 1.f, u->rbar, -1.f, nullptr, nullptr, 0.f, I, s));
+        // x^{k+1}, p^{k+1} = prox(z, p^k)
+        if (lam > 0) {
+            HIP_TRY(launch_tv_bwd_final(op->z, PS(nt), u->axt, op->n, lam, u->tbar, u->zbar, u->prod, s));
+            if ((r = sum(C_LAM, u->prod, J))) return r;
+            HIP_TRY(launch_tv_bwd_grad(u->ap, u->tbar, op->n, lam, u->pba, s));
+            float *cur = u->pba, *nxt = u->pbb;
+            for (int i = nt; i >= 1; --i) {
+                HIP_TRY(launch_tv_bwd_proj(op->z, PS(i - 1), cur, op->n, lam, tvstep, u->qbar, u->prod, s));
+                if ((r = sum(C_STEP, u->prod, J))) return r;
+                HIP_TRY(launch_tv_bwd_mask(op->z, PS(i - 1), u->qbar, op->n, lam, tvstep, u->tbar, u->zbar, u->prod,
+                                           s));
+                if ((r = sum(C_LAM, u->prod, J))) return r;
+                HIP_TRY(launch_tv_bwd_grad(u->qbar, u->tbar, op->n, lam, nxt, s));
+                std::swap(cur, nxt);
+            }
+            std::swap(u->ap, cur == u->pba ? u->pba : u->pbb);
+        } else {
+            // x^{k+1} = max(0, z), p passes through unchanged
+            HIP_TRY(launch_tv_bwd_final(op->z, PS(0), u->axt, op->n, 0.f, u->tbar, u->zbar, u->prod, s));
+        }
+        // z = x^k - tau A^T mubar
+        if ((r = project(op, u->zbar, u->az))) return r;
+        if ((r = dot(C_TAU, -1.0, u->az, op->mubar, I))) return r;
+        if ((r = filt(op, taps, u->az, 1.f, u->daz))) return r;
+        if ((r = filt(op, dtaps, u->az, 1.f, u->dpaz))) return r;
+        if ((r = dot(C_SIGMA, tau, u->daz, e, I))) return r;
+        if ((r = dot(C_TAU, sigma * tau, u->dpaz, e, I))) return r;
+        if (it == 0) {
+            HIP_TRY(launch_lin_mix_f32(b_grad, b_grad, 1.f, u->daz, (float)(sigma * tau), nullptr, nullptr, 0.f, I,
+                                       s));
+        } else {
+            HIP_TRY(launch_lin_mix_f32(u->amu2, u->amu2, 1.f, u->az, (float)(-2.0 * tau), op->winv, u->daz,
+                                       (float)(sigma * tau), I, s));
+            HIP_TRY(launch_lin_mix_f32(u->amup2, u->az, ft, nullptr, 0.f, op->winv, u->daz, (float)(-sigma * tau),
+                                       I, s));
+        }
+        std::swap(u->ax, u->zbar);
+        std::swap(u->amu, u->amu2);
+        std::swap(u->amup, u->amup2);
+    }
+    const int ns = (int)terms.size();
+    u->slots_host.assign((size_t)3 * ns, 0.0);
+    HIP_TRY(hipMemcpyAsync(u->slots_host.data(), u->slots, sizeof(double) * 3 * ns, hipMemcpyDeviceToHost, s));
+    if ((r = sync(op))) return r;
+    double g_sigma = 0.0, g_tau = 0.0, g_lam = 0.0, g_step = 0.0;
+    for (int i = 0; i < ns; ++i) {
+        const double v = terms[i].second * u->slots_host[3 * i];
+        switch (terms[i].first) {
+            case C_SIGMA: g_sigma += v; break;
+            case C_TAU: g_tau += v; break;
+            case C_LAM: g_lam += v; break;
+            default: g_step += v; break;
+        }
+    }
+    if (lam > 0) g_lam += g_step * (-k.tv_step / ((tau * beta) * (tau * beta)));
+    grads[0] = tau * g_lam;            // d/dbeta  (lam = tau beta)
+    grads[1] = g_tau + beta * g_lam;   // d/dtau
+    grads[2] = g_sigma;                // d/dsigma
+    return CTPD_OK;
+}
+
+}  // extern "C"

@@ -53,6 +53,10 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(const void* __restr
         } else if constexpr (OP == RED_SQDIFF_F32) {
             const double r = (double)((const float*)pa)[i] - (double)((const float*)pb)[i];
             s0 = fma(r, r, s0);
+        } else if constexpr (OP == RED_DOT_F32) {
+            s0 = fma((double)((const float*)pa)[i], (double)((const float*)pb)[i], s0);
+        } else if constexpr (OP == RED_SUM_F32) {
+            s0 += (double)((const float*)pa)[i];
         } else {   // RED_SQ_F32, counting non-finite entries
             const float v = ((const float*)pa)[i];
             if (isfinite(v)) s0 = fma((double)v, (double)v, s0);
@@ -97,6 +101,8 @@ hipError_t launch_reduce(int op, const void* a, const void* b, const void* c, si
         case RED_ABS_F32: reduce_partial_kernel<RED_ABS_F32><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
         case RED_WRES_F32: reduce_partial_kernel<RED_WRES_F32><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
         case RED_SQDIFF_F32: reduce_partial_kernel<RED_SQDIFF_F32><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
+        case RED_DOT_F32: reduce_partial_kernel<RED_DOT_F32><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
+        case RED_SUM_F32: reduce_partial_kernel<RED_SUM_F32><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
         default: reduce_partial_kernel<RED_SQ_F32><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
     }
     hipError_t e = hipGetLastError();
@@ -239,6 +245,23 @@ __global__ __launch_bounds__(256) void lin3_kernel(float* out, const float* a, f
 hipError_t launch_lin3_f32(float* out, const float* a, float c0, const float* b, float c1, const float* c, float c2,
                            const float* w, size_t len, hipStream_t s) {
     lin3_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(out, a, c0, b, c1, c, c2, w, len);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void lin_mix_kernel(float* out, const float* a, float c0, const float* b, float c1,
+                                                      const float* __restrict__ c, const float* __restrict__ d,
+                                                      float c2, size_t len) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= len) return;
+    float r = c0 * a[i];
+    if (b) r = fmaf(c1, b[i], r);
+    if (c) r = fmaf(c2, d ? c[i] * d[i] : c[i], r);
+    out[i] = r;
+}
+
+hipError_t launch_lin_mix_f32(float* out, const float* a, float c0, const float* b, float c1, const float* c,
+                              const float* d, float c2, size_t len, hipStream_t s) {
+    lin_mix_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(out, a, c0, b, c1, c, d, c2, len);
     return hipGetLastError();
 }
 

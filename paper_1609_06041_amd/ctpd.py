@@ -39,6 +39,11 @@ _SIGNATURES = {
     "ctpd_batch_destroy": (None, [c_void_p]),
     "ctpd_batch_lowdose_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
                                          c_void_p]),
+    "ctpd_unrolled_ckpt_floats": (c_int, [c_void_p, c_int32, POINTER(ctypes.c_size_t)]),
+    "ctpd_unrolled_lowdose_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double, c_double, c_int32,
+                                              c_void_p, c_void_p, c_void_p]),
+    "ctpd_unrolled_lowdose_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double, c_double, c_int32,
+                                               c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double)]),
     "ctpd_strerror": (ctypes.c_char_p, [c_int]),
 }
 
@@ -265,6 +270,37 @@ class Operator:
         _check(load().ctpd_cp_fewview_solve(self._h, _ptr(b, (self.m, self.nb), "b"), int(iters), byref(prm),
                                             _ptr(out, (self.n, self.n), "out"), byref(rep)))
         return out, self._info(rep, cost, state)
+
+
+    # -- unrolled Algorithm 1 (forward with checkpoints, reverse pass) -------------
+    def ckpt_floats(self, iters: int) -> int:
+        cnt = ctypes.c_size_t()
+        _check(load().ctpd_unrolled_ckpt_floats(self._h, int(iters), byref(cnt)))
+        return int(cnt.value)
+
+    def unrolled_forward(self, b, w, beta, tau, sigma, iters, ckpt, *, tv_iters=10, tv_step=0.125, out=None):
+        out = self._img() if out is None else out
+        prm = _params(None, None, tv_iters, tv_step, None, None, False)
+        if ckpt.dtype != torch.float32 or ckpt.numel() < self.ckpt_floats(iters) or not ckpt.is_contiguous():
+            raise ValueError("checkpoint buffer too small or not contiguous float32")
+        _check(load().ctpd_unrolled_lowdose_forward(self._h, _ptr(b, (self.m, self.nb), "b"),
+                                                    _ptr(w, (self.m, self.nb), "w"), float(beta), float(tau),
+                                                    float(sigma), int(iters), byref(prm), c_void_p(ckpt.data_ptr()),
+                                                    _ptr(out, (self.n, self.n), "out")))
+        return out
+
+    def unrolled_backward(self, b, w, beta, tau, sigma, iters, ckpt, x_grad, *, tv_iters=10, tv_step=0.125,
+                          b_grad=None):
+        b_grad = self._sino() if b_grad is None else b_grad
+        prm = _params(None, None, tv_iters, tv_step, None, None, False)
+        g = (c_double * 3)()
+        _check(load().ctpd_unrolled_lowdose_backward(self._h, _ptr(b, (self.m, self.nb), "b"),
+                                                     _ptr(w, (self.m, self.nb), "w"), float(beta), float(tau),
+                                                     float(sigma), int(iters), byref(prm),
+                                                     c_void_p(ckpt.data_ptr()),
+                                                     _ptr(x_grad, (self.n, self.n), "x_grad"),
+                                                     _ptr(b_grad, (self.m, self.nb), "b_grad"), g))
+        return b_grad, (g[0], g[1], g[2])
 
 
 class Batch:

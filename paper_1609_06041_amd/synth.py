@@ -66,6 +66,8 @@ def draw_ellipses(n: int, count: int, rng: np.random.Generator) -> list:
     the disk of radius n/2 - 1 is redrawn, so every ray meeting the object
     also meets the pixel grid.
     """
+    if n < 3:   # the smallest ellipse (semi-axis 3n/64) only fits inside radius n/2 - 1 from n = 3 on
+        raise ValueError(f"ellipse phantoms need n >= 3, got {n}")
     s = n / 64.0
     out = []
     while len(out) < count:

@@ -2,6 +2,7 @@
 import math
 
 import numpy as np
+import pytest
 
 from paper_1609_06041_amd import synth as S
 
@@ -42,3 +43,8 @@ def test_rasterised_phantom_matches_density_scale():
     x = S.rasterise(e, 32)
     assert x.max() == 1.0 / 32
     assert abs(x.sum() - math.pi * 100 / 32) < 0.01 * math.pi * 100 / 32
+
+
+def test_too_small_image_is_rejected_not_looped():
+    with pytest.raises(ValueError):
+        S.draw_ellipses(2, 3, S.rng_for(0, 0, 0))
