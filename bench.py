@@ -235,9 +235,12 @@ def batch_speedup(dev, count: int, steps: int, warmup: int) -> int:
     ref = [x.clone() for x in outs]
     for op in ops:
         op.close()
-    log("batched solves")
+    log("batched solves: autotuning tile shapes")
+    from paper_1609_06041_amd import autotune
     bouts = [torch.empty((n, n), device=dev) for n, _, _ in geoms]
     with ctpd.Batch(geoms) as bt:
+        tuned = autotune.autotune(bt, bs, ws, betas, iters)
+        log(f"chosen tiles {tuned['tiles']}")
         for _ in range(warmup):
             bt.lowdose_solve(bs, ws, betas, iters, outs=bouts)
         bat_total, bat_loop, bat_setup = [], [], []
@@ -249,6 +252,7 @@ def batch_speedup(dev, count: int, steps: int, warmup: int) -> int:
             bat_total.append(1e3 * (time.perf_counter() - t0))
             bat_loop.append(infos[0]["loop_ms"])
             bat_setup.append(infos[0]["setup_ms"])
+        graph_ms = bt.time_loop(iters, 10, 5)
     identical = all(bool(torch.equal(a, b)) for a, b in zip(ref, bouts))
     med = lambda v: float(np.median(v))
     work = sum(m * n * n for n, m, _ in geoms)
@@ -259,7 +263,10 @@ def batch_speedup(dev, count: int, steps: int, warmup: int) -> int:
         "batched_ms": {"total": med(bat_total), "loop": med(bat_loop), "setup": med(bat_setup)},
         "speedup_total": med(seq_total) / med(bat_total),
         "speedup_loop": med(seq_loop) / med(bat_loop),
-        "batched_loop_gupdates_per_s": 2 * iters * work / (med(bat_loop) * 1e-3) / 1e9,
+        "batched_graph_replay_ms": graph_ms,
+        "speedup_loop_graph_replay": med(seq_loop) / graph_ms,
+        "batched_loop_gupdates_per_s": 2 * iters * work / (graph_ms * 1e-3) / 1e9,
+        "tiles": tuned["tiles"], "autotune_ms": tuned.get("timings_ms"),
         "results_identical_to_sequential": identical,
     }
     print(json.dumps(out), flush=True)

@@ -201,6 +201,26 @@ int ctpd_unrolled_lowdose_backward(ctpd_op* op, const float* b, const float* w, 
                                    double sigma, int32_t iters, const ctpd_params* p, const float* ckpt,
                                    const float* x_grad, float* b_grad, double* grads);
 
+/* Tile shapes and workgroup placement of the batched kernels (chosen by an
+ * autotuner that times ctpd_batch_time_loop over the candidates). */
+typedef struct {
+    int32_t placement;   /* 0: each problem's workgroups on one XCD (default); 1: problem-major order */
+    int32_t tv_threads;  /* threads per 32 x 32 TV tile: 512 or 1024 (default) */
+    int32_t fwd_batch;   /* taps in flight per forward-projector lane: 4 or 8 (default) */
+    int32_t reserved;
+} ctpd_batch_tiles;
+
+/* Set / read the batch's tile choices (CTPD_EINVAL for values outside the
+ * lists above).  Setting recaptures the loop graph on the next call. */
+int ctpd_batch_set_tiles(ctpd_batch* batch, const ctpd_batch_tiles* tiles);
+int ctpd_batch_get_tiles(const ctpd_batch* batch, ctpd_batch_tiles* tiles);
+
+/* Replay the iters-iteration loop of the last solve's set-up reps times and
+ * return the median device time per replay in *ms (HIP events).  The inputs
+ * of the last solve must still be valid; results are overwritten with the
+ * same values.  CTPD_EINVAL before the first solve. */
+int ctpd_batch_time_loop(ctpd_batch* batch, int32_t iters, int32_t tv_iters, int32_t reps, double* ms);
+
 /* Comparator for the low-dose problem of Eq. 1 (Sec. 4 compares Algorithm 1
  * with it; Table 1 lists it): GIST, the Loris-Verhoeven iteration -- a
  * gradient step on the weighted data term, a projection step on the dual of

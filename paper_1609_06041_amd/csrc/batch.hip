@@ -42,6 +42,8 @@ struct ctpd_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int g_iters = -1, g_tv = -1;
+    ctpd_batch_tiles tiles{0, 1024, 8, 0};
+    bool solved = false;   // items hold a valid set-up (a solve has run)
 };
 
 namespace {
@@ -74,16 +76,26 @@ int build_maps(ctpd_batch* bt) {
         load[x] += work(p);
     }
     for (int kind = 0; kind < K_COUNT; ++kind) {
-        std::vector<std::vector<BlockRef>> bins(kXcds);
-        for (int p : order) {
-            const int nb = blocks_of(bt->ops[p], kind);
-            for (int l = 0; l < nb; ++l) bins[bt->xcd[p]].push_back(BlockRef{p, l});
+        std::vector<BlockRef> flat;
+        if (bt->tiles.placement == 0) {   // XCD-binned
+            std::vector<std::vector<BlockRef>> bins(kXcds);
+            for (int p : order) {
+                const int nb = blocks_of(bt->ops[p], kind);
+                for (int l = 0; l < nb; ++l) bins[bt->xcd[p]].push_back(BlockRef{p, l});
+            }
+            size_t len = 0;
+            for (auto& b : bins) len = std::max(len, b.size());
+            flat.assign(len * kXcds, BlockRef{-1, 0});
+            for (int x = 0; x < kXcds; ++x)
+                for (size_t i = 0; i < bins[x].size(); ++i) flat[i * kXcds + x] = bins[x][i];
+        } else {   // problem-major, largest first: consecutive workgroups of a problem spread over all XCDs
+            for (int p : order) {
+                const int nb = blocks_of(bt->ops[p], kind);
+                for (int l = 0; l < nb; ++l) flat.push_back(BlockRef{p, l});
+            }
         }
-        size_t len = 0;
-        for (auto& b : bins) len = std::max(len, b.size());
-        std::vector<BlockRef> flat(len * kXcds, BlockRef{-1, 0});
-        for (int x = 0; x < kXcds; ++x)
-            for (size_t i = 0; i < bins[x].size(); ++i) flat[i * kXcds + x] = bins[x][i];
+        if (bt->map[kind]) hipFree(bt->map[kind]);
+        bt->map[kind] = nullptr;
         ALLOC(bt->map[kind], flat.size());
         HIP_TRY(hipMemcpy(bt->map[kind], flat.data(), sizeof(BlockRef) * flat.size(), hipMemcpyHostToDevice));
         bt->nblk[kind] = (int)flat.size();
@@ -109,12 +121,13 @@ int queue_loop(ctpd_batch* bt, int iters, int tv_iters) {
         do {
             const int st = std::min(left, chunk);
             left -= st;
-            HIP_TRY(launch_tv_prox_batched(it, bt->map[K_TV], bt->nblk[K_TV], pc, st, left == 0, s));
+            HIP_TRY(launch_tv_prox_batched(it, bt->map[K_TV], bt->nblk[K_TV], pc, st, left == 0,
+                                           bt->tiles.tv_threads, s));
             pc = 1 - pc;
         } while (left > 0);
         // Step 3: mu^{k+1} = mu + sigma D (A x - b - W^-1 mu)
         HIP_TRY(launch_pad_planes_batched(it, bt->map[K_PAD], bt->nblk[K_PAD], s));
-        HIP_TRY(launch_forward_batched(it, bt->map[K_FWD], bt->nblk[K_FWD], s));
+        HIP_TRY(launch_forward_batched(it, bt->map[K_FWD], bt->nblk[K_FWD], bt->tiles.fwd_batch, s));
         HIP_TRY(launch_filter_batched(it, bt->map[K_FILT], bt->nblk[K_FILT], FILT_DUAL_LD, rot, bt->max_nb, s));
     }
     HIP_TRY(launch_batch_copy_out(it, bt->map[K_COPY], bt->nblk[K_COPY], s));
@@ -263,6 +276,7 @@ int ctpd_batch_lowdose_solve(ctpd_batch* bt, const float* const* b, const float*
     HIP_TRY(hipGraphLaunch(bt->exec, bt->gs));
     HIP_TRY(hipStreamSynchronize(bt->gs));
     const double loop_ms = ms_since(t1);
+    bt->solved = true;
     if (reps) {
         for (int i = 0; i < P; ++i) {
             ctpd_report& rp = reps[i];
@@ -278,6 +292,58 @@ int ctpd_batch_lowdose_solve(ctpd_batch* bt, const float* const* b, const float*
             rp.loop_ms = loop_ms;
         }
     }
+    return CTPD_OK;
+}
+
+int ctpd_batch_set_tiles(ctpd_batch* bt, const ctpd_batch_tiles* t) {
+    g_errmsg[0] = 0;
+    if (!bt || !t) return einval("null pointer");
+    if (t->placement != 0 && t->placement != 1) return einval("placement must be 0 or 1");
+    if (t->tv_threads != 512 && t->tv_threads != 1024) return einval("tv_threads must be 512 or 1024");
+    if (t->fwd_batch != 4 && t->fwd_batch != 8) return einval("fwd_batch must be 4 or 8");
+    const bool remap = t->placement != bt->tiles.placement;
+    bt->tiles = *t;
+    bt->tiles.reserved = 0;
+    bt->g_iters = -1;   // recapture the loop with the new choices
+    if (remap) {
+        HIP_TRY(hipStreamSynchronize(bt->gs));
+        return build_maps(bt);
+    }
+    return CTPD_OK;
+}
+
+int ctpd_batch_get_tiles(const ctpd_batch* bt, ctpd_batch_tiles* t) {
+    g_errmsg[0] = 0;
+    if (!bt || !t) return einval("null pointer");
+    *t = bt->tiles;
+    return CTPD_OK;
+}
+
+int ctpd_batch_time_loop(ctpd_batch* bt, int32_t iters, int32_t tv_iters, int32_t reps, double* ms) {
+    g_errmsg[0] = 0;
+    if (!bt || !ms) return einval("null pointer");
+    if (!bt->solved) return einval("no solve has set the batch up yet");
+    if (iters < 1 || tv_iters < 1 || reps < 1) return einval("iters, tv_iters and reps must be >= 1");
+    int r = capture_loop(bt, iters, tv_iters);
+    if (r) return r;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    std::vector<float> t(reps);
+    int rc = CTPD_OK;
+    for (int i = 0; i < reps && rc == CTPD_OK; ++i) {
+        hipError_t e = hipEventRecord(e0, bt->gs);
+        if (e == hipSuccess) e = hipGraphLaunch(bt->exec, bt->gs);
+        if (e == hipSuccess) e = hipEventRecord(e1, bt->gs);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t[i], e0, e1);
+        if (e != hipSuccess) rc = fail_hip(e, "timing the batched loop");
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    std::sort(t.begin(), t.end());
+    *ms = t[reps / 2];
     return CTPD_OK;
 }
 

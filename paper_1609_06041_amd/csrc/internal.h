@@ -92,7 +92,9 @@ hipError_t launch_adjoint(const T* y1, const T* y2, T c1, T c2, const T* xin, T 
 // batched forms (grids of nblocks workgroups described by map):
 //   pad planes of x, q = A x, z = x - tau A^T mubar (two: z = x - tau A^T (2 mu^k - mu^{k-1}))
 hipError_t launch_pad_planes_batched(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s);
-hipError_t launch_forward_batched(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s);
+// fb: taps in flight per lane (4 or 8), a tuning choice of the batch
+hipError_t launch_forward_batched(const BatchItem* items, const BlockRef* map, int nblocks, int fb,
+                                  hipStream_t s);
 hipError_t launch_adjoint_batched(const BatchItem* items, const BlockRef* map, int nblocks, bool two, int rot,
                                   hipStream_t s);
 
@@ -127,9 +129,10 @@ hipError_t launch_tv_prox(const float* z, float* p_a, float* p_b, float* x, int 
 // p <- projection of (p + s grad xb) onto the unit ball, pointwise (the dual
 // step of Chambolle-Pock on the TV term).
 hipError_t launch_grad_ball(const float* xb, float* p, int n, float s, hipStream_t st);
-// batched TV prox chunk (p[src] -> p[1-src]; x written when last)
+// batched TV prox chunk (p[src] -> p[1-src]; x written when last); threads
+// per 32 x 32 tile: 512 or 1024, a tuning choice of the batch
 hipError_t launch_tv_prox_batched(const BatchItem* items, const BlockRef* map, int nblocks, int src, int steps,
-                                  bool last, hipStream_t s);
+                                  bool last, int threads, hipStream_t s);
 int tv_tiles(int n);      // TV tiles per image side
 int tv_chunk_max();       // dual steps per TV launch at most
 // steps (<= tv_chunk_max()) dual steps from p_in into p_out without touching

@@ -146,7 +146,7 @@ struct Lanczos {
         return CTPD_OK;
     }
     // after the stream is synchronised: extend the tridiagonal matrix and test
-    // the top Ritz value (relative change <= 1e-10, or an invariant subspace)
+    // the top Ritz value (relative change <= 1e-9, or an invariant subspace)
     void absorb() {
         const double* h = op->lz_host[chain];
         for (int i = done; i < j && !converged; ++i) {
@@ -154,7 +154,7 @@ struct Lanczos {
             theta = tridiag_max(al, be);
             steps = i + 1;
             const double bn = std::sqrt(std::max(h[3 * (1 + op->lz_cap + i)], 0.0));
-            if ((i > 0 && std::fabs(theta - theta_prev) <= 1e-10 * std::fabs(theta)) ||
+            if ((i > 0 && std::fabs(theta - theta_prev) <= 1e-9 * std::fabs(theta)) ||
                 !(bn > 1e-300 * std::max(1.0, std::fabs(theta))))
                 converged = true;
             be.push_back(bn);

@@ -103,7 +103,7 @@ __device__ __forceinline__ void load_taps(const __amdgpu_buffer_rsrc_t& rs, unsi
 constexpr int kBufferRsrcWord3 = 0x00020000;
 constexpr int FW_BATCH = 8;
 
-template <typename T>
+template <typename T, int FB = FW_BATCH>
 __device__ __forceinline__ void forward_body(const T* __restrict__ xp, const T* __restrict__ xTp, T* __restrict__ y,
                                              const ViewGeom* __restrict__ views, int n, int nb, int bxi, int v) {
     const int u = bxi * 256 + threadIdx.x;
@@ -140,23 +140,23 @@ __device__ __forceinline__ void forward_body(const T* __restrict__ xp, const T* 
     int rowb = t0 * rowstride;
     T acc_a = T(0), acc_d = T(0);   // sum of left taps, sum of low-word * (right - left)
     int t = t0;
-    for (; t + FW_BATCH - 1 <= t1; t += FW_BATCH) {
-        unsigned off[FW_BATCH];
-        T lf[FW_BATCH], a[FW_BATCH], b[FW_BATCH];
+    for (; t + FB - 1 <= t1; t += FB) {
+        unsigned off[FB];
+        T lf[FB], a[FB], b[FB];
 #pragma unroll
-        for (int q = 0; q < FW_BATCH; ++q) {
+        for (int q = 0; q < FB; ++q) {
             off[q] = min((unsigned)(sfix >> 32), cmax) * (unsigned)sizeof(T);
             lf[q] = (T)(unsigned)sfix;
             sfix += dfix;
         }
 #pragma unroll
-        for (int q = 0; q < FW_BATCH; ++q) load_taps(rs, off[q], rowb + q * rowstride, a[q], b[q]);
+        for (int q = 0; q < FB; ++q) load_taps(rs, off[q], rowb + q * rowstride, a[q], b[q]);
 #pragma unroll
-        for (int q = 0; q < FW_BATCH; ++q) {
+        for (int q = 0; q < FB; ++q) {
             acc_a += a[q];
             acc_d = fma(lf[q], b[q] - a[q], acc_d);
         }
-        rowb += FW_BATCH * rowstride;
+        rowb += FB * rowstride;
     }
     for (; t <= t1; ++t) {
         T a, b;
@@ -387,13 +387,14 @@ __global__ __launch_bounds__(256) void pad_planes_batched(const BatchItem* __res
     pad_planes_body<float>(it.x, it.xp, it.xTp, it.n, e.local % gx, e.local / gx);
 }
 
+template <int FB>
 __global__ __launch_bounds__(256) void forward_batched(const BatchItem* __restrict__ items,
                                                        const BlockRef* __restrict__ map) {
     const BlockRef e = map[blockIdx.x];
     if (e.prob < 0) return;
     const BatchItem& it = items[e.prob];
     const int gx = (it.nb + 255) / 256;
-    forward_body<float>(it.xp, it.xTp, it.q, it.views, it.n, it.nb, e.local % gx, e.local / gx);
+    forward_body<float, FB>(it.xp, it.xTp, it.q, it.views, it.n, it.nb, e.local % gx, e.local / gx);
 }
 
 // z = x - tau A^T mubar  (mode 0), or z = x - tau A^T (2 mu - mu_prev)  (mode 1, few-view k >= 1)
@@ -415,8 +416,12 @@ hipError_t launch_pad_planes_batched(const BatchItem* items, const BlockRef* map
     return hipGetLastError();
 }
 
-hipError_t launch_forward_batched(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s) {
-    forward_batched<<<nblocks, 256, 0, s>>>(items, map);
+hipError_t launch_forward_batched(const BatchItem* items, const BlockRef* map, int nblocks, int fb,
+                                  hipStream_t s) {
+    if (fb == 4)
+        forward_batched<4><<<nblocks, 256, 0, s>>>(items, map);
+    else
+        forward_batched<8><<<nblocks, 256, 0, s>>>(items, map);
     return hipGetLastError();
 }
 

@@ -41,8 +41,8 @@ constexpr int kTvMaxW = kTvTile + 2 * (kTvChunk + 1);
 // One workgroup = 16 waves (four per SIMD, to hide the LDS latency of the
 // dependent stencil reads); a wave sweeps one 64-wide LDS row at a time.
 constexpr int kTvThreads = 1024;
-constexpr int kTvRows = kTvThreads / 64;
 
+template <int THREADS>
 __device__ __forceinline__ void tv_prox_body(const float* __restrict__ z, const float* __restrict__ p_in,
                                              float* __restrict__ p_out, float* __restrict__ x, int n, float lam,
                                              float step, int steps, int bxi, int byi) {
@@ -55,7 +55,7 @@ __device__ __forceinline__ void tv_prox_body(const float* __restrict__ z, const 
     const int j = j0 + c;
     const bool colin = c < W;
     const bool jin = colin && j >= 0 && j < n;
-    for (int r = ty; r < W; r += kTvRows) {
+    for (int r = ty; r < W; r += (THREADS / 64)) {
         const int i = i0 + r;
         if (!colin) continue;
         const int o = r * W + c;
@@ -83,12 +83,12 @@ __device__ __forceinline__ void tv_prox_body(const float* __restrict__ z, const 
     };
     for (int t = 1; t <= steps; ++t) {
         // cells whose new p is still needed: rows / columns [t, W - t)
-        for (int r = t - 1 + ty; r < W - t + 1; r += kTvRows) {
+        for (int r = t - 1 + ty; r < W - t + 1; r += (THREADS / 64)) {
             if (!colin) continue;
             sx[r * W + c] = xt_at(r, i0 + r);
         }
         __syncthreads();
-        for (int r = t + ty; r < W - t; r += kTvRows) {
+        for (int r = t + ty; r < W - t; r += (THREADS / 64)) {
             const int i = i0 + r;
             if (!(jin && c >= t && c < W - t && i >= 0 && i < n)) continue;
             const int o = r * W + c;
@@ -102,7 +102,7 @@ __device__ __forceinline__ void tv_prox_body(const float* __restrict__ z, const 
         }
         __syncthreads();
     }
-    for (int r = H + ty; r < H + kTvTile; r += kTvRows) {
+    for (int r = H + ty; r < H + kTvTile; r += (THREADS / 64)) {
         const int i = i0 + r;
         if (!(jin && c >= H && c < H + kTvTile && i < n)) continue;
         const int o = r * W + c;
@@ -127,26 +127,28 @@ __global__ __launch_bounds__(kTvThreads) void tv_prox_kernel(const float* __rest
                                                              const float* __restrict__ p_in,
                                                              float* __restrict__ p_out, float* __restrict__ x, int n,
                                                              float lam, float step, int steps) {
-    tv_prox_body(z, p_in, p_out, x, n, lam, step, steps, blockIdx.x, blockIdx.y);
+    tv_prox_body<kTvThreads>(z, p_in, p_out, x, n, lam, step, steps, blockIdx.x, blockIdx.y);
 }
 
 // Batched TV prox chunk: p[src] -> p[1 - src] for every problem, x written on
 // the last chunk; a problem with lam == 0 (beta = 0) takes x = max(0, z).
-__global__ __launch_bounds__(kTvThreads) void tv_prox_batched(const BatchItem* __restrict__ items,
-                                                              const BlockRef* __restrict__ map, int src, int steps,
-                                                              int last) {
+// THREADS (512 or 1024 per 32 x 32 tile) is a tuning choice of the batch.
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void tv_prox_batched(const BatchItem* __restrict__ items,
+                                                           const BlockRef* __restrict__ map, int src, int steps,
+                                                           int last) {
     const BlockRef e = map[blockIdx.x];
     if (e.prob < 0) return;
     const BatchItem& it = items[e.prob];
     const int gx = (it.n + kTvTile - 1) / kTvTile;
     const int bxi = e.local % gx, byi = e.local / gx;
     if (it.lam > 0.f) {
-        tv_prox_body(it.z, it.p[src], it.p[1 - src], last ? it.x : nullptr, it.n, it.lam, it.tvstep, steps, bxi,
-                     byi);
+        tv_prox_body<THREADS>(it.z, it.p[src], it.p[1 - src], last ? it.x : nullptr, it.n, it.lam, it.tvstep, steps,
+                              bxi, byi);
     } else if (last) {
         const int c = threadIdx.x & 63, ty = threadIdx.x >> 6;
         const int j = bxi * kTvTile + c;
-        for (int r = ty; r < kTvTile; r += kTvRows) {
+        for (int r = ty; r < kTvTile; r += THREADS / 64) {
             const int i = byi * kTvTile + r;
             if (c < kTvTile && i < it.n && j < it.n) {
                 const size_t g = (size_t)i * it.n + j;
@@ -157,8 +159,11 @@ __global__ __launch_bounds__(kTvThreads) void tv_prox_batched(const BatchItem* _
 }
 
 hipError_t launch_tv_prox_batched(const BatchItem* items, const BlockRef* map, int nblocks, int src, int steps,
-                                  bool last, hipStream_t s) {
-    tv_prox_batched<<<nblocks, kTvThreads, 0, s>>>(items, map, src, steps, last ? 1 : 0);
+                                  bool last, int threads, hipStream_t s) {
+    if (threads == 512)
+        tv_prox_batched<512><<<nblocks, 512, 0, s>>>(items, map, src, steps, last ? 1 : 0);
+    else
+        tv_prox_batched<1024><<<nblocks, 1024, 0, s>>>(items, map, src, steps, last ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -44,6 +44,9 @@ _SIGNATURES = {
                                               c_void_p, c_void_p, c_void_p]),
     "ctpd_unrolled_lowdose_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double, c_double, c_int32,
                                                c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double)]),
+    "ctpd_batch_set_tiles": (c_int, [c_void_p, c_void_p]),
+    "ctpd_batch_get_tiles": (c_int, [c_void_p, c_void_p]),
+    "ctpd_batch_time_loop": (c_int, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_double)]),
     "ctpd_strerror": (ctypes.c_char_p, [c_int]),
 }
 
@@ -61,6 +64,10 @@ class Geometry(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("tau", c_double), ("sigma", c_double), ("tv_step", c_double), ("safety", c_double),
                 ("tv_iters", c_int32), ("norm_steps", c_int32), ("record_cost", c_int32), ("reserved", c_int32)]
+
+
+class BatchTiles(ctypes.Structure):
+    _fields_ = [("placement", c_int32), ("tv_threads", c_int32), ("fwd_batch", c_int32), ("reserved", c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -349,3 +356,17 @@ class Batch:
         reps = (Report * P)()
         _check(load().ctpd_batch_lowdose_solve(self._h, pb, pw, pbeta, int(iters), byref(prm), px, reps))
         return outs, [Operator._info(r, None, {}) for r in reps]
+
+    def set_tiles(self, placement: int, tv_threads: int, fwd_batch: int) -> None:
+        _check(load().ctpd_batch_set_tiles(self._h, byref(BatchTiles(placement, tv_threads, fwd_batch, 0))))
+
+    def get_tiles(self) -> dict:
+        t = BatchTiles()
+        _check(load().ctpd_batch_get_tiles(self._h, byref(t)))
+        return {"placement": t.placement, "tv_threads": t.tv_threads, "fwd_batch": t.fwd_batch}
+
+    def time_loop(self, iters: int, tv_iters: int = 10, reps: int = 3) -> float:
+        """Median device ms of one replay of the loop graph (needs a previous solve)."""
+        ms = c_double()
+        _check(load().ctpd_batch_time_loop(self._h, int(iters), int(tv_iters), int(reps), byref(ms)))
+        return ms.value

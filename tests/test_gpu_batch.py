@@ -119,3 +119,23 @@ def test_batch_rejects_bad_arguments(gpu):
         with pytest.raises(ctpd.CtpdError) as e:
             bt.lowdose_solve([dev(b) for b, _ in data], [dev(w) for _, w in data], [0.1, -1.0], 3)
         assert e.value.code == ctpd.CTPD_EINVAL
+
+
+def test_every_tile_choice_gives_the_same_result(gpu):
+    from paper_1609_06041_amd import autotune
+    geoms = [(48, 33, 70), (64, 90, 96), (40, 16, 57)]
+    data = _inputs(geoms, 40)
+    betas = [0.01, 0.02, 0.03]
+    bs, ws = [dev(b) for b, _ in data], [dev(w) for _, w in data]
+    with ctpd.Batch(geoms) as bt:
+        ref, _ = bt.lowdose_solve(bs, ws, betas, 5)
+        ref = [host(x) for x in ref]
+        for cand in autotune.CANDIDATES:
+            bt.set_tiles(**cand)
+            assert bt.get_tiles() == cand
+            xs, _ = bt.lowdose_solve(bs, ws, betas, 5)
+            for x, r in zip(xs, ref):
+                np.testing.assert_array_equal(host(x), r)
+        assert bt.time_loop(5, 10, 2) > 0.0
+        with pytest.raises(ctpd.CtpdError):
+            bt.set_tiles(placement=0, tv_threads=256, fwd_batch=8)
