@@ -61,10 +61,14 @@ typedef struct {
 
 /* Solver knobs.  A zero / negative value selects the default. */
 typedef struct {
-    double tau;          /* primal step; default: low-dose pi*kappa/(2m), few-view
+    double tau;          /* primal step; default: low-dose 0.3*pi*kappa/(2m), few-view
                             mean|sigma A^T D(1) b| */
     double sigma;        /* dual step; default: rho times the bound of Eq. 16 /
-                            Algorithm 1 / Algorithm 2 from the operator norms */
+                            Algorithm 1 / Algorithm 2 from the operator norms.
+                            lambda_max(A^T D A) depends on the geometry only when
+                            tau is the default (D then scales as 1/kappa; for the
+                            few-view ramp, D(tau) = D(1)/tau): the handle computes
+                            it at its first such solve and reuses it after. */
     double tv_step;      /* tau_c of the TV dual iteration, default 1/8 */
     double safety;       /* rho < 1, default 0.95 */
     int32_t tv_iters;    /* inner TV steps per outer iteration, default 10 */
@@ -79,7 +83,7 @@ typedef struct {
     double kappa;        /* mean of diag(W^-1) (low-dose) */
     double lambda_a;     /* lambda_max(A^T D A) = ||D^1/2 A A^T D^T/2|| at the tau used */
     double lambda_h;     /* lambda_max(W^-1/2 D W^-1/2) = ||D^1/2 W^-1 D^T/2|| (low-dose) */
-    int32_t norm_steps_a, norm_steps_h;  /* Lanczos steps taken */
+    int32_t norm_steps_a, norm_steps_h;  /* Lanczos steps taken (0: lambda_a from the handle's cache) */
     int32_t iters_done;
     int32_t reserved;
     double setup_ms;     /* host wall time of the set-up (norms, taps, defaults) */

@@ -347,24 +347,41 @@ int lowdose_setup_begin(ctpd_op* op, const float* b, const float* w, const Knobs
         return CTPD_EDOMAIN;
     }
     S->kappa = op->red_host[0] / (double)I;
-    S->tau = k.tau > 0 ? k.tau : M_PI * S->kappa / (2.0 * op->m);
+    S->tau = k.tau > 0 ? k.tau : kTauMultLowdose * M_PI * S->kappa / (2.0 * op->m);
     HIP_TRY(launch_inverse_f32(op->winv, w, I, op->stream));
     if ((r = ensure_taps(op, S->tau, S->kappa))) return r;
     S->sigma = k.sigma;
     S->norms = !(S->sigma > 0);
     if (S->norms) {
+        // with the default tau, H of Eq. 24 is |w| / (kappa (0.3 pi + |w|)), so
+        // D = D1 / kappa and kappa * lambda_max(A^T D A) depends on the geometry only
+        S->cacheable = !(k.tau > 0);
+        S->run_a = !(S->cacheable && op->norm_ld > 0.0 && op->norm_ld_kmax == k.norm_steps);
         if ((r = ensure_f64(op))) return r;
         HIP_TRY(launch_rsqrt_f64(op->sino64[3], w, I, op->stream));
-        if ((r = setup_lambda_a(op, k.norm_steps, &S->La))) return r;
-        if ((r = setup_lambda_h(op, w, S->kappa, k.norm_steps, &S->Lh))) return r;
+        if (S->run_a && (r = setup_lambda_a(op, k.norm_steps, &S->La))) return r;
+        if (S->defer_h) {
+            if ((r = ensure_lz(op, k.norm_steps))) return r;
+        } else if ((r = setup_lambda_h(op, w, S->kappa, k.norm_steps, &S->Lh))) {
+            return r;
+        }
     }
     return CTPD_OK;
 }
 
-void lowdose_setup_end(const Knobs& k, LowdoseSetup* S) {
+void lowdose_setup_end(ctpd_op* op, const Knobs& k, LowdoseSetup* S) {
     if (!S->norms) return;
-    S->lam_a = S->La.theta;
-    S->steps_a = S->La.steps;
+    if (S->run_a) {
+        S->lam_a = S->La.theta;
+        S->steps_a = S->La.steps;
+        if (S->cacheable) {
+            op->norm_ld = S->lam_a * S->kappa;
+            op->norm_ld_kmax = k.norm_steps;
+        }
+    } else {
+        S->lam_a = op->norm_ld / S->kappa;
+        S->steps_a = 0;
+    }
     S->lam_h = S->Lh.theta;
     S->steps_h = S->Lh.steps;
     S->sigma = k.rho * std::min(2.0 / S->lam_h, 1.0 / (S->tau * S->lam_a));
@@ -532,8 +549,9 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
     hipStream_t s = op->stream;
     LowdoseSetup S;
     if ((r = lowdose_setup_begin(op, b, w, k, &S))) return r;
-    if (S.norms && (r = run_lanczos({&S.La, &S.Lh}))) return r;
-    lowdose_setup_end(k, &S);
+    if (S.norms && (r = run_lanczos(S.run_a ? std::vector<Lanczos*>{&S.La, &S.Lh} : std::vector<Lanczos*>{&S.Lh})))
+        return r;
+    lowdose_setup_end(op, k, &S);
     const double kappa = S.kappa, tau = S.tau, sigma = S.sigma, lam_a = S.lam_a, lam_h = S.lam_h;
     const int steps_a = S.steps_a, steps_h = S.steps_h;
     if ((r = sync(op))) return r;
@@ -621,11 +639,17 @@ int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
     if (!(sigma > 0) || !(k.tau > 0)) {
         if ((r = ensure_taps(op, 1.0, 0.0))) return r;
         if (!(sigma > 0)) {
-            Lanczos La;
-            if ((r = setup_lambda_a(op, k.norm_steps, &La))) return r;
-            if ((r = run_lanczos({&La}))) return r;
-            lam1 = La.theta;
-            steps_a = La.steps;
+            if (op->norm_fv > 0.0 && op->norm_fv_kmax == k.norm_steps) {   // D(1) depends on the geometry only
+                lam1 = op->norm_fv;
+            } else {
+                Lanczos La;
+                if ((r = setup_lambda_a(op, k.norm_steps, &La))) return r;
+                if ((r = run_lanczos({&La}))) return r;
+                lam1 = La.theta;
+                steps_a = La.steps;
+                op->norm_fv = lam1;
+                op->norm_fv_kmax = k.norm_steps;
+            }
             sigma = k.rho / lam1;
         }
     }
@@ -812,11 +836,17 @@ int ctpd_cp_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
     double t = k.tau, sg = k.sigma, lata = 0.0;
     int steps_a = 0;
     if (!(t > 0) || !(sg > 0)) {
-        Lanczos L;
-        if ((r = setup_lambda_a(op, k.norm_steps, &L, false, nullptr))) return r;
-        if ((r = run_lanczos({&L}))) return r;
-        lata = L.theta;
-        steps_a = L.steps;
+        if (op->norm_ata > 0.0 && op->norm_ata_kmax == k.norm_steps) {   // a property of the geometry
+            lata = op->norm_ata;
+        } else {
+            Lanczos L;
+            if ((r = setup_lambda_a(op, k.norm_steps, &L, false, nullptr))) return r;
+            if ((r = run_lanczos({&L}))) return r;
+            lata = L.theta;
+            steps_a = L.steps;
+            op->norm_ata = lata;
+            op->norm_ata_kmax = k.norm_steps;
+        }
         const double st = k.rho / std::sqrt(lata + 8.0);
         if (!(t > 0)) t = st;
         if (!(sg > 0)) sg = st;

@@ -321,14 +321,14 @@ constexpr int DTW = FBN + DBK - 1;   // taps per stage
 constexpr int DPER = FBM * DBK / 256;
 
 template <bool PRE, bool POST>
-__global__ __launch_bounds__(256) void filter_f64_kernel(const double* __restrict__ in, double* __restrict__ out,
-                                                         const double* __restrict__ taps,
-                                                         const double* __restrict__ pre,
-                                                         const double* __restrict__ post, int m, int nb) {
+__device__ __forceinline__ void filter_f64_body(const double* __restrict__ in, double* __restrict__ out,
+                                                const double* __restrict__ taps, const double* __restrict__ pre,
+                                                const double* __restrict__ post, int m, int nb, int bxi,
+                                                int byi) {
     __shared__ double stile[FBM * DSTRIDE];
     __shared__ double hw[DTW + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n0 = blockIdx.x * FBN, v0 = blockIdx.y * FBM;
+    const int n0 = bxi * FBN, v0 = byi * FBM;
     const int wr = (wave >> 1) * 16, wc = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
     double stg[DPER], stp[DPER];
@@ -389,6 +389,30 @@ __global__ __launch_bounds__(256) void filter_f64_kernel(const double* __restric
             }
         }
     }
+}
+
+template <bool PRE, bool POST>
+__global__ __launch_bounds__(256) void filter_f64_kernel(const double* __restrict__ in, double* __restrict__ out,
+                                                         const double* __restrict__ taps,
+                                                         const double* __restrict__ pre,
+                                                         const double* __restrict__ post, int m, int nb) {
+    filter_f64_body<PRE, POST>(in, out, taps, pre, post, m, nb, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void norm_filter_batched(const NormItem* __restrict__ items,
+                                                           const BlockRef* __restrict__ map, int rot) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const NormItem& it = items[e.prob];
+    const int gx = (it.nb + FBN - 1) / FBN;
+    filter_f64_body<true, true>(it.v[rot], it.v[(rot + 2) % 3], it.taps64, it.rs, it.rs, it.m, it.nb, e.local % gx,
+                                e.local / gx);
+}
+
+hipError_t launch_norm_filter_batched(const NormItem* it, const BlockRef* map, int nblocks, int rot,
+                                      hipStream_t s) {
+    norm_filter_batched<<<nblocks, 256, 0, s>>>(it, map, rot);
+    return hipGetLastError();
 }
 
 hipError_t launch_filter_f64(const double* in, double* out, const double* taps64, const double* pre,

@@ -69,6 +69,22 @@ struct BatchItem {
     float sigma, tau, lam, tvstep;
 };
 
+// One problem's lambda_h = lambda_max(W^-1/2 D W^-1/2) Lanczos chain in a
+// batched set-up (float64).  The three Lanczos vectors rotate: v[rot] is q_j,
+// v[(rot+1)%3] q_{j-1}, v[(rot+2)%3] receives the next one.  lz holds the
+// recurrence scalars as in the single chain: [0] start norm^2, [1 + j]
+// alpha_j, [1 + cap + j] beta_{j+1}^2 (3 doubles each).
+struct NormItem {
+    int m, nb, cap, pad_;
+    const double* taps64;
+    const double* rs;        // sqrt(1/w)
+    const float* w;          // weights (start vector)
+    double inv_kappa;
+    double* v[3];
+    double* partials;        // 3 * kReduceBlocks doubles
+    double* lz;
+};
+
 // The problem and the block within it of one workgroup of a batched launch
 // (prob < 0: an idle workgroup).
 struct BlockRef {
@@ -119,6 +135,10 @@ hipError_t launch_filter_batched(const BatchItem* items, const BlockRef* map, in
                                  int max_nb, hipStream_t s);
 int filter_blocks_x(int nb);
 int filter_blocks_y(int m);
+
+// batched W^-1/2 D W^-1/2 applied to v[rot] into v[(rot+2)%3] (float64)
+hipError_t launch_norm_filter_batched(const NormItem* it, const BlockRef* map, int nblocks, int rot,
+                                      hipStream_t s);
 
 // ---- tv.hip --------------------------------------------------------------
 // The TV prox: n_iter dual steps on p starting from p_a (warm start), then
@@ -196,6 +216,18 @@ hipError_t launch_mul_w_f64(double* out, const double* a, const float* w, size_t
 // (2048 elements per workgroup)
 hipError_t launch_batch_init(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s);
 hipError_t launch_batch_copy_out(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s);
+// batched lambda_h chain steps (NormItem tables; map entries index reduction
+// blocks (K_RED: reduce_blocks_for(m nb) per problem), elementwise blocks of
+// 256 (K_ELEM), or filter tiles (K_FILT))
+int reduce_blocks_for(size_t len);
+hipError_t launch_norm_start_batched(const NormItem* it, const BlockRef* elem, int nelem, const BlockRef* red,
+                                     int nred, int count, uint64_t seed, hipStream_t s);
+hipError_t launch_norm_dot_batched(const NormItem* it, const BlockRef* red, int nred, int count, int rot, int j,
+                                   hipStream_t s);
+hipError_t launch_norm_update_batched(const NormItem* it, const BlockRef* red, int nred, int count, int rot, int j,
+                                      hipStream_t s);
+hipError_t launch_norm_normalize_batched(const NormItem* it, const BlockRef* elem, int nelem, int rot, int j,
+                                         hipStream_t s);
 hipError_t launch_inverse_f32(float* out, const float* w, size_t len, hipStream_t s);
 hipError_t launch_rsqrt_f64(double* out, const float* w, size_t len, hipStream_t s);
 hipError_t launch_copy_f32(float* dst, const float* src, size_t len, hipStream_t s);

@@ -63,6 +63,10 @@ struct ctpd_op {
     // per-iteration monitor values (device), 2 * cost_cap slots of 3 doubles
     double* cost_dev = nullptr;
     int cost_cap = 0;
+    // geometry-only operator norms (see ctpd_params.sigma): kappa * lambda_max(A^T D A)
+    // for the default low-dose tau, lambda_max(A^T D(1) A) for few-view; 0 = not yet
+    double norm_ld = 0.0, norm_fv = 0.0, norm_ata = 0.0;   // norm_ata: lambda_max(A^T A) (Chambolle-Pock)
+    int norm_ld_kmax = 0, norm_fv_kmax = 0, norm_ata_kmax = 0;
     // workspaces of the unrolled solve's reverse pass (allocated on first use)
     ctpd_host::UnrolledWs* uw = nullptr;
 };
@@ -186,13 +190,18 @@ int finish(ctpd_op* op, int iters, bool lowdose, double beta, float* p_final, ct
            bool recorded);
 
 // Set-up of Algorithm 1 (see api.hip).
+constexpr double kTauMultLowdose = 0.3;   // default tau = 0.3 pi kappa / (2m)
+
 struct LowdoseSetup {
     double kappa = 0.0, tau = 0.0, sigma = 0.0, lam_a = 0.0, lam_h = 0.0;
     int steps_a = 0, steps_h = 0;
-    bool norms = false;
+    bool norms = false;     // sigma from the norms
+    bool run_a = false;     // lambda_a from the chain (else from the handle's cache)
+    bool cacheable = false; // default tau: kappa * lambda_a is a property of the geometry
+    bool defer_h = false;   // the caller runs the lambda_h chain itself (batched set-up)
     Lanczos La, Lh;
 };
 int lowdose_setup_begin(ctpd_op* op, const float* b, const float* w, const Knobs& k, LowdoseSetup* S);
-void lowdose_setup_end(const Knobs& k, LowdoseSetup* S);
+void lowdose_setup_end(ctpd_op* op, const Knobs& k, LowdoseSetup* S);
 
 }  // namespace ctpd_host

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void reduce_final_kernel(const double* __restr
     }
 }
 
-static int reduce_blocks(size_t len) {
+__host__ __device__ static inline int reduce_blocks(size_t len) {
     const size_t b = (len + 255) / 256;
     return (int)(b < (size_t)kReduceBlocks ? (b ? b : 1) : kReduceBlocks);
 }
@@ -274,6 +274,131 @@ __global__ __launch_bounds__(256) void mul_w_kernel(double* __restrict__ out, co
 
 hipError_t launch_mul_w_f64(double* out, const double* a, const float* w, size_t len, hipStream_t s) {
     mul_w_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(out, a, w, len);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched lambda_h Lanczos chains: the same per-element arithmetic and the same
+// reduction trees as the single chain (reduce_blocks_for(len) grid-stride
+// blocks, then one fixed-order final block), so every problem's recurrence
+// scalars are bit-identical to its single chain's.
+int reduce_blocks_for(size_t len) { return reduce_blocks(len); }
+
+__device__ __forceinline__ double norm_start_value(const NormItem& it, size_t i, uint64_t seed) {
+    const int c = (int)(i % (size_t)it.nb);
+    const double shape = ((c & 1) ? -1.0 : 1.0) * it.inv_kappa / (double)it.w[i];
+    return shape + 0.05 * (splitmix_unit(seed, i) - 0.5);
+}
+
+__global__ __launch_bounds__(256) void norm_start_batched(const NormItem* __restrict__ items,
+                                                          const BlockRef* __restrict__ map, uint64_t seed) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const NormItem& it = items[e.prob];
+    const size_t len = (size_t)it.m * it.nb;
+    const size_t i = (size_t)e.local * 256 + threadIdx.x;
+    if (i < len) it.v[0][i] = norm_start_value(it, i, seed);
+}
+
+// kind 0: sum v0^2 (start), 1: sum q.w (alpha_j), 2: Lanczos update of w (beta_{j+1}^2 partials)
+template <int KIND>
+__global__ __launch_bounds__(256) void norm_partial_batched(const NormItem* __restrict__ items,
+                                                            const BlockRef* __restrict__ map, int rot, int j) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const NormItem& it = items[e.prob];
+    const size_t len = (size_t)it.m * it.nb;
+    const int nb = reduce_blocks(len);
+    const size_t stride = (size_t)nb * 256;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (KIND == 0) {
+        const double* q = it.v[0];
+        for (size_t i = (size_t)e.local * 256 + threadIdx.x; i < len; i += stride) s0 = fma(q[i], q[i], s0);
+    } else if (KIND == 1) {
+        const double* q = it.v[rot];
+        const double* w = it.v[(rot + 2) % 3];
+        for (size_t i = (size_t)e.local * 256 + threadIdx.x; i < len; i += stride) s0 = fma(q[i], w[i], s0);
+    } else {
+        const double* q = it.v[rot];
+        const double* qp = j ? it.v[(rot + 1) % 3] : nullptr;
+        double* w = it.v[(rot + 2) % 3];
+        const double a = it.lz[3 * (1 + j)];
+        const double b = qp ? sqrt(it.lz[3 * (1 + it.cap + j - 1)]) : 0.0;
+        for (size_t i = (size_t)e.local * 256 + threadIdx.x; i < len; i += stride) {
+            double r = w[i] - a * q[i];
+            if (qp) r -= b * qp[i];
+            w[i] = r;
+            s0 = fma(r, r, s0);
+        }
+    }
+    block_sum3(s0, s1, s2);
+    if (threadIdx.x == 0) {
+        it.partials[3 * e.local + 0] = s0;
+        it.partials[3 * e.local + 1] = 0.0;
+        it.partials[3 * e.local + 2] = 0.0;
+    }
+}
+
+// one workgroup per problem: slot = sum of its partials (fixed order)
+__global__ __launch_bounds__(256) void norm_final_batched(const NormItem* __restrict__ items, int slot_kind,
+                                                          int j) {
+    const NormItem& it = items[blockIdx.x];
+    const int nblocks = reduce_blocks((size_t)it.m * it.nb);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+        s0 += it.partials[3 * b + 0];
+        s1 += it.partials[3 * b + 1];
+        s2 += it.partials[3 * b + 2];
+    }
+    block_sum3(s0, s1, s2);
+    if (threadIdx.x == 0) {
+        double* out = slot_kind == 0 ? it.lz : slot_kind == 1 ? it.lz + 3 * (1 + j) : it.lz + 3 * (1 + it.cap + j);
+        out[0] = s0;
+        out[1] = s1;
+        out[2] = s2;
+    }
+}
+
+// v[dst] = v[src] / sqrt(slot)  (start: v0 / sqrt(lz[0]); step j: w / sqrt(beta_{j+1}^2))
+__global__ __launch_bounds__(256) void norm_scale_batched(const NormItem* __restrict__ items,
+                                                          const BlockRef* __restrict__ map, int rot, int j) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const NormItem& it = items[e.prob];
+    const size_t len = (size_t)it.m * it.nb;
+    const size_t i = (size_t)e.local * 256 + threadIdx.x;
+    if (i >= len) return;
+    double* v = j < 0 ? it.v[0] : it.v[(rot + 2) % 3];
+    const double* ss = j < 0 ? it.lz : it.lz + 3 * (1 + it.cap + j);
+    v[i] = v[i] / sqrt(ss[0]);
+}
+
+hipError_t launch_norm_start_batched(const NormItem* it, const BlockRef* elem, int nelem, const BlockRef* red,
+                                     int nred, int count, uint64_t seed, hipStream_t s) {
+    norm_start_batched<<<nelem, 256, 0, s>>>(it, elem, seed);
+    norm_partial_batched<0><<<nred, 256, 0, s>>>(it, red, 0, 0);
+    norm_final_batched<<<count, 256, 0, s>>>(it, 0, 0);
+    norm_scale_batched<<<nelem, 256, 0, s>>>(it, elem, 0, -1);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_dot_batched(const NormItem* it, const BlockRef* red, int nred, int count, int rot, int j,
+                                   hipStream_t s) {
+    norm_partial_batched<1><<<nred, 256, 0, s>>>(it, red, rot, j);
+    norm_final_batched<<<count, 256, 0, s>>>(it, 1, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_update_batched(const NormItem* it, const BlockRef* red, int nred, int count, int rot, int j,
+                                      hipStream_t s) {
+    norm_partial_batched<2><<<nred, 256, 0, s>>>(it, red, rot, j);
+    norm_final_batched<<<count, 256, 0, s>>>(it, 2, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_normalize_batched(const NormItem* it, const BlockRef* elem, int nelem, int rot, int j,
+                                         hipStream_t s) {
+    norm_scale_batched<<<nelem, 256, 0, s>>>(it, elem, rot, j);
     return hipGetLastError();
 }
 

@@ -79,6 +79,24 @@ def test_lowdose_default_steps_match_oracle(gpu):
     assert rel(x, ref.x) <= 1e-4
 
 
+def test_second_solve_reuses_the_geometry_norm(gpu):
+    # with the default tau, kappa * lambda_max(A^T D A) depends on the geometry only
+    n, m, nb = 64, 90, 96
+    b1, w1 = lowdose_inputs(n, m, nb, seed=11)
+    b2, w2 = lowdose_inputs(n, m, nb, seed=12, i0=3e4)
+    st2 = OA.steps_lowdose(w2, n)
+    with ctpd.Operator(n, m, nb) as op:
+        _, i1 = op.lowdose_solve(dev(b1), dev(w1), 0.01, 2)
+        x, i2 = op.lowdose_solve(dev(b2), dev(w2), 0.01, 10)
+        x = host(x)
+    assert i1["norm_steps_a"] > 0 and i2["norm_steps_a"] == 0
+    assert i2["lambda_a"] == pytest.approx(st2.lambda_a, rel=1e-6)
+    assert i2["lambda_h"] == pytest.approx(st2.lambda_h, rel=1e-6)
+    assert i2["sigma"] == pytest.approx(st2.sigma, rel=1e-6)
+    ref, _ = OA.lowdose_solve(b2, w2, 0.01, n, 10, tau=st2.tau, sigma=st2.sigma)
+    assert rel(x, ref.x) <= 1e-4
+
+
 @pytest.mark.parametrize("n,m,nb,iters", [(64, 32, 96, 20), (50, 12, 75, 10)])
 def test_fewview_solve_matches_oracle(gpu, n, m, nb, iters):
     prob = S.make_problem(91, n, n, m, nb, 8, None, with_x_true=False)

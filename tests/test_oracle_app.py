@@ -40,7 +40,7 @@ def test_wls_solve_converges_to_nnls():
     sw = np.sqrt(w).ravel()
     ref, _ = nnls(sw[:, None] * a, sw * b.ravel())
     kappa = float((1.0 / w).mean())
-    res, st = AP.lowdose_solve(b, w, 0.0, n, 1500, tau=3 * AP.default_tau_lowdose(kappa, m))
+    res, st = AP.lowdose_solve(b, w, 0.0, n, 1500, tau=3 * np.pi * kappa / (2.0 * m))
     assert st.sigma > 0 and st.tau > 0
     np.testing.assert_allclose(res.x.ravel(), ref, atol=1e-9)
 
