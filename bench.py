@@ -277,6 +277,88 @@ def batch_speedup(dev, count: int, steps: int, warmup: int) -> int:
     return 0 if identical else 1
 
 
+def unrolled_speedup(dev, steps: int) -> int:
+    """16 independent 256^2 / 180-view problems, 10 unrolled iterations: forward
+    and forward + reverse pass (each problem on its own stream) against 16 plain
+    solves of the same 10 iterations, all at the same fixed step sizes."""
+    import numpy as np
+    import torch
+
+    from paper_1609_06041_amd import ctpd, synth
+    from paper_1609_06041_amd.unrolled import unrolled_lowdose
+
+    B, n, m, nb, K, beta = 16, 256, 180, 368, 10, 0.005
+    log(f"generating {B} seeded 256^2 problems")
+    probs = [synth.make_problem(4, p, n, m, nb, 15, 2e4, with_x_true=True) for p in range(B)]
+    bs = [torch.from_numpy(np.asarray(pr.b, np.float32)).to(dev) for pr in probs]
+    ws = [torch.from_numpy(np.asarray(pr.w, np.float32)).to(dev) for pr in probs]
+    xts = [torch.from_numpy(np.asarray(pr.x_true, np.float32)).to(dev) for pr in probs]
+    streams = [torch.cuda.Stream(device=dev) for _ in range(B)]
+    ops = [ctpd.Operator(n, m, nb, stream=s) for s in streams]
+    steps_ = []
+    for op, b, w in zip(ops, bs, ws):
+        _, info = op.lowdose_solve(b, w, beta, 0)
+        steps_.append((info["tau"], info["sigma"]))
+    torch.cuda.synchronize()
+
+    def plain():
+        for op, b, w, (ta, si) in zip(ops, bs, ws, steps_):
+            op.lowdose_solve(b, w, beta, K, tau=ta, sigma=si)
+
+    def forward():
+        xs = []
+        for op, st, b, w, (ta, si) in zip(ops, streams, bs, ws, steps_):
+            with torch.cuda.stream(st):
+                xs.append(unrolled_lowdose(op, b, w, beta, ta, si, K))
+        return xs
+
+    def fwd_bwd():
+        main = torch.cuda.current_stream()
+        bts = [b.clone().requires_grad_(True) for b in bs]
+        pars = [[torch.tensor(v, dtype=torch.float64, requires_grad=True) for v in (beta, ta, si)]
+                for ta, si in steps_]
+        losses = []
+        for op, st, b, w, xt, (pb, pt, ps) in zip(ops, streams, bts, ws, xts, pars):
+            st.wait_stream(main)
+            with torch.cuda.stream(st):
+                x = unrolled_lowdose(op, b, w, pb, pt, ps, K)
+                losses.append(((x - xt) ** 2).sum())
+        for st in streams:
+            main.wait_stream(st)
+        torch.stack(losses).sum().backward()
+        return bts, pars
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(max(steps, 3)):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(1e3 * (time.perf_counter() - t0))
+        return float(np.median(ts))
+
+    log("timing plain solves, forward passes, forward + reverse passes")
+    t_plain = timed(plain)
+    t_fwd = timed(forward)
+    t_fb = timed(fwd_bwd)
+    bts, pars = fwd_bwd()
+    torch.cuda.synchronize()
+    finite = all(bool(torch.isfinite(b.grad).all()) for b in bts) and all(
+        all(p.grad is not None and np.isfinite(float(p.grad)) for p in ps) for ps in pars)
+    out = {"kind": "unrolled_gradient", "problems": B, "image": f"{n}x{n}", "views": m, "bins": nb, "iterations": K,
+           "data": "synthetic", "dtype": "f32", "plain_solves_ms": t_plain, "forward_ms": t_fwd,
+           "forward_backward_ms": t_fb, "backward_over_forward": (t_fb - t_fwd) / t_fwd,
+           "forward_backward_over_plain": t_fb / t_plain, "gradients_finite": finite,
+           "accuracy": "reverse pass vs float64 central differences of the oracle, 1e-3 relative on 32^2 "
+                       "(tests/test_gpu_unrolled.py)"}
+    for op in ops:
+        op.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,6 +372,9 @@ def main() -> int:
     ap.add_argument("--batch", type=int, default=0, metavar="P",
                     help="instead of the throughput line: P problems of the batched uneven workload solved as one "
                          "batch (graph replay) vs the same problems solved one after another")
+    ap.add_argument("--unrolled", action="store_true",
+                    help="instead of the throughput line: 16 unrolled 10-iteration solves (256^2, 180 views) forward "
+                         "and reverse pass vs 16 plain solves")
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 --pmc: a plain 256 MiB device copy (counter calibration) "
                          "followed by 5 A^T launches on the workload; prints nothing else")
@@ -311,6 +396,8 @@ def main() -> int:
         return compare(dev)
     if args.batch:
         return batch_speedup(dev, args.batch, args.steps, args.warmup)
+    if args.unrolled:
+        return unrolled_speedup(dev, args.steps)
     log("generating the seeded lowdose_512 inputs (3 independent phantoms / noise draws)")
     insts = []
     for pid in range(N_INSTANCES):

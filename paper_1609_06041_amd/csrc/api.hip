@@ -209,30 +209,6 @@ int setup_lambda_a(ctpd_op* op, int kmax, Lanczos* L, bool filt, const float* wg
     return L->start(op->n, op->n, 1, nullptr, 0.0);
 }
 
-// lambda_max(W^-1/2 D W^-1/2) on the aux stream (after everything queued on
-// op->stream so far); needs op->sino64[3] = sqrt(1/w).
-int setup_lambda_h(ctpd_op* op, const float* w, double kappa, int kmax, Lanczos* L) {
-    int r = ensure_f64(op);
-    if (r) return r;
-    if ((r = ensure_lz(op, kmax))) return r;
-    HIP_TRY(hipEventRecord(op->fork, op->stream));
-    HIP_TRY(hipStreamWaitEvent(op->aux, op->fork, 0));
-    const double* rs = op->sino64[3];
-    hipStream_t s = op->aux;
-    L->op = op;
-    L->chain = 1;
-    L->per_round = 16;   // one step of the A chain costs several of the H chain
-    L->s = s;
-    L->q = op->sino64[0];
-    L->qp = op->sino64[1];
-    L->w = op->sino64[2];
-    L->kmax = kmax;
-    L->apply = [op, rs, s](const double* in, double* out) -> int {
-        HIP_TRY(launch_filter_f64(in, out, op->taps64, rs, rs, op->m, op->nb, s));
-        return CTPD_OK;
-    };
-    return L->start(op->m, op->nb, 2, w, 1.0 / kappa);
-}
 
 int filter(ctpd_op* op, int mode, const float* in0, const float* in1, const float* in2, const float* in3,
            const float* E0, float e0, const float* E1, float e1, float c, float* out) {
@@ -332,6 +308,87 @@ int finish(ctpd_op* op, int iters, bool lowdose, double beta, float* p_final, ct
     return sync(op);
 }
 
+int ensure_hv(ctpd_op* op, int kmax) {
+    if (!op->hv_item) {
+        ALLOC(op->hv_item, 1);
+        HIP_TRY(hipHostMalloc((void**)&op->hv_item_host, sizeof(NormItem), hipHostMallocDefault));
+        ALLOC(op->hv_sum, 3);
+        HIP_TRY(hipHostMalloc((void**)&op->hv_sum_host, sizeof(double) * 3, hipHostMallocDefault));
+        std::vector<RowRef> rows(op->m);
+        for (int v = 0; v < op->m; ++v) rows[v] = RowRef{0, v};
+        ALLOC(op->hv_rows, op->m);
+        HIP_TRY(hipMemcpy(op->hv_rows, rows.data(), sizeof(RowRef) * op->m, hipMemcpyHostToDevice));
+        const int gx = filter_blocks_x(op->nb), gy = filter_blocks_y(op->m);
+        std::vector<BlockRef> f(gx * gy);
+        for (int l = 0; l < gx * gy; ++l) f[l] = BlockRef{0, l};
+        ALLOC(op->hv_filt, f.size());
+        HIP_TRY(hipMemcpy(op->hv_filt, f.data(), sizeof(BlockRef) * f.size(), hipMemcpyHostToDevice));
+        op->hv_nfilt = (int)f.size();
+        ALLOC(op->hv_b0, op->m);
+        ALLOC(op->hv_theta, op->m);
+        ALLOC(op->hv_done, op->m);
+    }
+    if (op->hv_cap < kmax) {
+        if (op->hv_al) hipFree(op->hv_al);
+        if (op->hv_b2) hipFree(op->hv_b2);
+        op->hv_al = op->hv_b2 = nullptr;
+        op->hv_cap = 0;
+        ALLOC(op->hv_al, (size_t)kmax * op->m);
+        ALLOC(op->hv_b2, (size_t)kmax * op->m);
+        op->hv_cap = kmax;
+    }
+    return CTPD_OK;
+}
+
+int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, const double* kappa, int kmax,
+                   hipStream_t s, NormItem* items, NormItem* items_host, const RowRef* rows, int nrows,
+                   const BlockRef* filt, int nfilt, double* summary, double* summary_host, double* lam,
+                   int* steps) {
+    const int P = (int)ops.size();
+    for (int i = 0; i < P; ++i) {
+        ctpd_op* op = ops[i];
+        int r = ensure_hv(op, kmax);
+        if (r) return r;
+        NormItem& it = items_host[i];
+        it = NormItem{};
+        it.m = op->m;
+        it.nb = op->nb;
+        it.taps64 = op->taps64;
+        it.rs = op->sino64[3];
+        it.w = w[i];
+        it.inv_kappa = 1.0 / kappa[i];
+        for (int q = 0; q < 3; ++q) it.v[q] = op->sino64[q];
+        it.al = op->hv_al;
+        it.b2 = op->hv_b2;
+        it.b0 = op->hv_b0;
+        it.theta = op->hv_theta;
+        it.done = op->hv_done;
+        it.summary = summary + 3 * i;
+    }
+    HIP_TRY(hipMemcpyAsync(items, items_host, sizeof(NormItem) * P, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_rows_start(items, rows, nrows, 2, s));
+    constexpr int kRound = 8;
+    int j = 0;
+    for (bool running = true; running && j < kmax;) {
+        const int j1 = std::min(kmax, j + kRound);
+        for (; j < j1; ++j) {
+            const int rot = (3 - j % 3) % 3;
+            HIP_TRY(launch_norm_filter_batched(items, filt, nfilt, rot, s));
+            HIP_TRY(launch_rows_step(items, rows, nrows, rot, j, s));
+        }
+        HIP_TRY(launch_rows_ritz(items, rows, nrows, P, j, 1e-9, s));
+        HIP_TRY(hipMemcpyAsync(summary_host, summary, sizeof(double) * 3 * P, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        running = false;
+        for (int i = 0; i < P; ++i) running = running || summary_host[3 * i + 1] > 0.0;
+    }
+    for (int i = 0; i < P; ++i) {
+        lam[i] = summary_host[3 * i + 0];
+        steps[i] = summary_host[3 * i + 1] > 0.0 ? j : (int)summary_host[3 * i + 2];
+    }
+    return CTPD_OK;
+}
+
 // a1 and the start of a2 for Algorithm 1: validity scan of w and b, kappa =
 // mean(1/w), tau, W^-1, the taps of Eq. 24; when sigma is not given, the two
 // operator-norm chains are started (run them with run_lanczos, then call
@@ -360,11 +417,7 @@ int lowdose_setup_begin(ctpd_op* op, const float* b, const float* w, const Knobs
         if ((r = ensure_f64(op))) return r;
         HIP_TRY(launch_rsqrt_f64(op->sino64[3], w, I, op->stream));
         if (S->run_a && (r = setup_lambda_a(op, k.norm_steps, &S->La))) return r;
-        if (S->defer_h) {
-            if ((r = ensure_lz(op, k.norm_steps))) return r;
-        } else if ((r = setup_lambda_h(op, w, S->kappa, k.norm_steps, &S->Lh))) {
-            return r;
-        }
+        (void)w;
     }
     return CTPD_OK;
 }
@@ -382,8 +435,6 @@ void lowdose_setup_end(ctpd_op* op, const Knobs& k, LowdoseSetup* S) {
         S->lam_a = op->norm_ld / S->kappa;
         S->steps_a = 0;
     }
-    S->lam_h = S->Lh.theta;
-    S->steps_h = S->Lh.steps;
     S->sigma = k.rho * std::min(2.0 / S->lam_h, 1.0 / (S->tau * S->lam_a));
 }
 
@@ -470,6 +521,12 @@ void ctpd_op_destroy(ctpd_op* op) {
     }
     if (op->fork) hipEventDestroy(op->fork);
     free_unrolled(op->uw);
+    void* hv[] = {op->hv_al, op->hv_b2, op->hv_b0, op->hv_theta, op->hv_done, op->hv_item, op->hv_rows, op->hv_filt,
+                  op->hv_sum};
+    for (void* p : hv)
+        if (p) hipFree(p);
+    if (op->hv_item_host) hipHostFree(op->hv_item_host);
+    if (op->hv_sum_host) hipHostFree(op->hv_sum_host);
     delete op;
 }
 
@@ -549,8 +606,27 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
     hipStream_t s = op->stream;
     LowdoseSetup S;
     if ((r = lowdose_setup_begin(op, b, w, k, &S))) return r;
-    if (S.norms && (r = run_lanczos(S.run_a ? std::vector<Lanczos*>{&S.La, &S.Lh} : std::vector<Lanczos*>{&S.Lh})))
-        return r;
+    if (S.norms) {
+        // the lambda_A chain (first solve on the handle) runs on op->stream while the
+        // per-view lambda_h chains run on op->aux
+        if ((r = ensure_hv(op, k.norm_steps))) return r;
+        HIP_TRY(hipEventRecord(op->fork, op->stream));
+        HIP_TRY(hipStreamWaitEvent(op->aux, op->fork, 0));
+        if (S.run_a) {
+            for (int q = 0; q < 4 && !S.La.finished(); ++q)   // queue the first rounds before the h chains block
+                if ((r = S.La.enqueue(S.La.per_round))) return r;
+        }
+        const float* wp[1] = {w};
+        if ((r = lambda_h_views({op}, wp, &S.kappa, k.norm_steps, op->aux, op->hv_item, op->hv_item_host,
+                                op->hv_rows, op->m, op->hv_filt, op->hv_nfilt, op->hv_sum, op->hv_sum_host,
+                                &S.lam_h, &S.steps_h)))
+            return r;
+        if (S.run_a) {
+            HIP_TRY(hipStreamSynchronize(op->stream));
+            S.La.absorb();
+            if ((r = run_lanczos({&S.La}))) return r;
+        }
+    }
     lowdose_setup_end(op, k, &S);
     const double kappa = S.kappa, tau = S.tau, sigma = S.sigma, lam_a = S.lam_a, lam_h = S.lam_h;
     const int steps_a = S.steps_a, steps_h = S.steps_h;

@@ -22,7 +22,7 @@ namespace {
 
 constexpr int kXcds = 8;
 
-enum Kind { K_INIT, K_FILT, K_ADJ, K_TV, K_PAD, K_FWD, K_COPY, K_RED, K_ELEM, K_COUNT };
+enum Kind { K_INIT, K_FILT, K_ADJ, K_TV, K_PAD, K_FWD, K_COPY, K_COUNT };
 
 }  // namespace
 
@@ -39,6 +39,10 @@ struct ctpd_batch {
     BatchItem* items_host = nullptr;    // pinned mirror
     NormItem* nitems = nullptr;         // lambda_h chains: device table
     NormItem* nitems_host = nullptr;    // pinned mirror
+    RowRef* rows = nullptr;             // every (problem, view)
+    int nrows = 0;
+    double* hsum = nullptr;             // lambda_h chain summaries, 3 per problem (device)
+    double* hsum_host = nullptr;        // pinned mirror
     BlockRef* map[K_COUNT] = {};
     int nblk[K_COUNT] = {};
     hipGraph_t graph = nullptr;
@@ -59,8 +63,6 @@ int blocks_of(const ctpd_op* op, int kind) {
         case K_TV: return tv_tiles(op->n) * tv_tiles(op->n);
         case K_PAD: return pad_tiles(op->n) * pad_tiles(op->n);
         case K_FWD: return forward_blocks_x(op->nb) * op->m;
-        case K_RED: return reduce_blocks_for(I);
-        case K_ELEM: return (int)((I + 255) / 256);
         default: return (int)((J + 2047) / 2048);
     }
 }
@@ -160,67 +162,6 @@ int capture_loop(ctpd_batch* bt, int iters, int tv_iters) {
     return CTPD_OK;
 }
 
-// lambda_h = lambda_max(W^-1/2 D W^-1/2) of every problem by Lanczos chains run
-// in lockstep, one launch per kernel and step for the whole batch (on bt->gs);
-// each problem's chain stops (its Ritz value freezes) at its own convergence
-// step, exactly as its single chain would.
-int batched_lambda_h(ctpd_batch* bt, const float* const* w, std::vector<LowdoseSetup>& S, int kmax) {
-    const int P = bt->count;
-    hipStream_t s = bt->gs;
-    for (int i = 0; i < P; ++i) {
-        ctpd_op* op = bt->ops[i];
-        NormItem& it = bt->nitems_host[i];
-        it = NormItem{};
-        it.m = op->m;
-        it.nb = op->nb;
-        it.cap = op->lz_cap;
-        it.taps64 = op->taps64;
-        it.rs = op->sino64[3];
-        it.w = w[i];
-        it.inv_kappa = 1.0 / S[i].kappa;
-        for (int q = 0; q < 3; ++q) it.v[q] = op->sino64[q];
-        it.partials = op->lz_partials[1];
-        it.lz = op->lz[1];
-        Lanczos& L = S[i].Lh;
-        L = Lanczos{};
-        L.op = op;
-        L.chain = 1;
-        L.kmax = kmax;
-    }
-    HIP_TRY(hipMemcpyAsync(bt->nitems, bt->nitems_host, sizeof(NormItem) * P, hipMemcpyHostToDevice, s));
-    const NormItem* it = bt->nitems;
-    HIP_TRY(launch_norm_start_batched(it, bt->map[K_ELEM], bt->nblk[K_ELEM], bt->map[K_RED], bt->nblk[K_RED], P, 2,
-                                      s));
-    constexpr int kRound = 16;
-    for (int j0 = 0; j0 < kmax; j0 += kRound) {
-        const int j1 = std::min(kmax, j0 + kRound);
-        for (int j = j0; j < j1; ++j) {
-            const int rot = (3 - j % 3) % 3;
-            HIP_TRY(launch_norm_filter_batched(it, bt->map[K_FILT], bt->nblk[K_FILT], rot, s));
-            HIP_TRY(launch_norm_dot_batched(it, bt->map[K_RED], bt->nblk[K_RED], P, rot, j, s));
-            HIP_TRY(launch_norm_update_batched(it, bt->map[K_RED], bt->nblk[K_RED], P, rot, j, s));
-            HIP_TRY(launch_norm_normalize_batched(it, bt->map[K_ELEM], bt->nblk[K_ELEM], rot, j, s));
-        }
-        for (int i = 0; i < P; ++i) {
-            ctpd_op* op = bt->ops[i];
-            if (S[i].Lh.finished()) continue;
-            HIP_TRY(hipMemcpyAsync(op->lz_host[1], op->lz[1], sizeof(double) * 3 * (2 * op->lz_cap + 1),
-                                   hipMemcpyDeviceToHost, s));
-        }
-        HIP_TRY(hipStreamSynchronize(s));
-        bool all = true;
-        for (int i = 0; i < P; ++i) {
-            Lanczos& L = S[i].Lh;
-            if (L.finished()) continue;
-            L.j = j1;
-            L.absorb();
-            all = all && L.finished();
-        }
-        if (all) break;
-    }
-    return CTPD_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -250,6 +191,14 @@ int ctpd_batch_create(const ctpd_geometry* geoms, int32_t count, void* stream, c
         HIP_TRY(hipHostMalloc((void**)&bt->items_host, sizeof(BatchItem) * count, hipHostMallocDefault));
         ALLOC(bt->nitems, count);
         HIP_TRY(hipHostMalloc((void**)&bt->nitems_host, sizeof(NormItem) * count, hipHostMallocDefault));
+        std::vector<RowRef> rows;
+        for (int p = 0; p < count; ++p)
+            for (int v = 0; v < geoms[p].n_views; ++v) rows.push_back(RowRef{p, v});
+        bt->nrows = (int)rows.size();
+        ALLOC(bt->rows, rows.size());
+        HIP_TRY(hipMemcpy(bt->rows, rows.data(), sizeof(RowRef) * rows.size(), hipMemcpyHostToDevice));
+        ALLOC(bt->hsum, 3 * count);
+        HIP_TRY(hipHostMalloc((void**)&bt->hsum_host, sizeof(double) * 3 * count, hipHostMallocDefault));
         return build_maps(bt);
     };
     const int r = init();
@@ -274,6 +223,9 @@ void ctpd_batch_destroy(ctpd_batch* bt) {
     if (bt->items_host) hipHostFree(bt->items_host);
     if (bt->nitems) hipFree(bt->nitems);
     if (bt->nitems_host) hipHostFree(bt->nitems_host);
+    if (bt->rows) hipFree(bt->rows);
+    if (bt->hsum) hipFree(bt->hsum);
+    if (bt->hsum_host) hipHostFree(bt->hsum_host);
     if (bt->ev) hipEventDestroy(bt->ev);
     if (bt->gs) hipStreamDestroy(bt->gs);
     delete bt;
@@ -302,17 +254,28 @@ int ctpd_batch_lowdose_solve(ctpd_batch* bt, const float* const* b, const float*
     std::vector<Lanczos*> chains;
     bool norms = false;
     for (int i = 0; i < P; ++i) {
-        S[i].defer_h = true;
         if ((r = lowdose_setup_begin(bt->ops[i], b[i], w[i], k, &S[i]))) return r;
         norms = norms || S[i].norms;
         if (S[i].norms && S[i].run_a) chains.push_back(&S[i].La);
     }
     // lambda_A chains (first solve on the geometry only), one stream per problem
     if ((r = run_lanczos(chains))) return r;
-    // lambda_h chains of all problems together, on the batch stream
+    // per-view lambda_h chains of all problems together, on the batch stream
     for (int i = 0; i < P; ++i)
         if ((r = sync(bt->ops[i]))) return r;
-    if (norms && (r = batched_lambda_h(bt, w, S, k.norm_steps))) return r;
+    if (norms) {
+        std::vector<double> kap(P), lam(P);
+        std::vector<int> st(P);
+        for (int i = 0; i < P; ++i) kap[i] = S[i].kappa;
+        if ((r = lambda_h_views(bt->ops, w, kap.data(), k.norm_steps, bt->gs, bt->nitems, bt->nitems_host, bt->rows,
+                                bt->nrows, bt->map[K_FILT], bt->nblk[K_FILT], bt->hsum, bt->hsum_host, lam.data(),
+                                st.data())))
+            return r;
+        for (int i = 0; i < P; ++i) {
+            S[i].lam_h = lam[i];
+            S[i].steps_h = st[i];
+        }
+    }
     for (int i = 0; i < P; ++i) {
         lowdose_setup_end(bt->ops[i], k, &S[i]);
         if ((r = sync(bt->ops[i]))) return r;

@@ -69,20 +69,32 @@ struct BatchItem {
     float sigma, tau, lam, tvstep;
 };
 
-// One problem's lambda_h = lambda_max(W^-1/2 D W^-1/2) Lanczos chain in a
-// batched set-up (float64).  The three Lanczos vectors rotate: v[rot] is q_j,
-// v[(rot+1)%3] q_{j-1}, v[(rot+2)%3] receives the next one.  lz holds the
-// recurrence scalars as in the single chain: [0] start norm^2, [1 + j]
-// alpha_j, [1 + cap + j] beta_{j+1}^2 (3 doubles each).
+// One problem of the per-view lambda_h = lambda_max(W^-1/2 D W^-1/2) chains
+// (float64).  W^-1/2 D W^-1/2 is block diagonal over views, so every view runs
+// its own chain on its n_bins-vector.  The three Lanczos vectors (whole
+// sinograms) rotate: v[rot] is q_j, v[(rot+1)%3] q_{j-1}, v[(rot+2)%3] receives
+// the next one.  The scalars of view v at step j are al[j m + v] (alpha) and
+// b2[j m + v] (beta_{j+1}^2); b0[v] is the start norm^2; theta[v] the view's top
+// Ritz value; done[v] = steps once its chain has stopped (0 while running);
+// summary = {max theta, views still running, max steps}.
 struct NormItem {
-    int m, nb, cap, pad_;
+    int m, nb;
     const double* taps64;
     const double* rs;        // sqrt(1/w)
     const float* w;          // weights (start vector)
     double inv_kappa;
     double* v[3];
-    double* partials;        // 3 * kReduceBlocks doubles
-    double* lz;
+    double* al;
+    double* b2;
+    double* b0;
+    double* theta;
+    int* done;
+    double* summary;
+};
+
+// One view (row) of one problem in the per-view chains.
+struct RowRef {
+    int prob, view;
 };
 
 // The problem and the block within it of one workgroup of a batched launch
@@ -216,18 +228,11 @@ hipError_t launch_mul_w_f64(double* out, const double* a, const float* w, size_t
 // (2048 elements per workgroup)
 hipError_t launch_batch_init(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s);
 hipError_t launch_batch_copy_out(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s);
-// batched lambda_h chain steps (NormItem tables; map entries index reduction
-// blocks (K_RED: reduce_blocks_for(m nb) per problem), elementwise blocks of
-// 256 (K_ELEM), or filter tiles (K_FILT))
-int reduce_blocks_for(size_t len);
-hipError_t launch_norm_start_batched(const NormItem* it, const BlockRef* elem, int nelem, const BlockRef* red,
-                                     int nred, int count, uint64_t seed, hipStream_t s);
-hipError_t launch_norm_dot_batched(const NormItem* it, const BlockRef* red, int nred, int count, int rot, int j,
-                                   hipStream_t s);
-hipError_t launch_norm_update_batched(const NormItem* it, const BlockRef* red, int nred, int count, int rot, int j,
-                                      hipStream_t s);
-hipError_t launch_norm_normalize_batched(const NormItem* it, const BlockRef* elem, int nelem, int rot, int j,
-                                         hipStream_t s);
+// per-view lambda_h chains over the rows of a NormItem table (one wave per row)
+hipError_t launch_rows_start(const NormItem* it, const RowRef* rows, int nrows, uint64_t seed, hipStream_t s);
+hipError_t launch_rows_step(const NormItem* it, const RowRef* rows, int nrows, int rot, int j, hipStream_t s);
+hipError_t launch_rows_ritz(const NormItem* it, const RowRef* rows, int nrows, int count, int steps, double tol,
+                            hipStream_t s);
 hipError_t launch_inverse_f32(float* out, const float* w, size_t len, hipStream_t s);
 hipError_t launch_rsqrt_f64(double* out, const float* w, size_t len, hipStream_t s);
 hipError_t launch_copy_f32(float* dst, const float* src, size_t len, hipStream_t s);

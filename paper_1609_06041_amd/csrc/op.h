@@ -67,6 +67,18 @@ struct ctpd_op {
     // for the default low-dose tau, lambda_max(A^T D(1) A) for few-view; 0 = not yet
     double norm_ld = 0.0, norm_fv = 0.0, norm_ata = 0.0;   // norm_ata: lambda_max(A^T A) (Chambolle-Pock)
     int norm_ld_kmax = 0, norm_fv_kmax = 0, norm_ata_kmax = 0;
+    // per-view lambda_h chains (allocated on first use): scalars per view and
+    // step, and the one-problem tables the shared routine runs on
+    double *hv_al = nullptr, *hv_b2 = nullptr, *hv_b0 = nullptr, *hv_theta = nullptr;
+    int* hv_done = nullptr;
+    int hv_cap = 0;
+    ctpd::NormItem* hv_item = nullptr;        // device, 1 entry
+    ctpd::NormItem* hv_item_host = nullptr;   // pinned
+    ctpd::RowRef* hv_rows = nullptr;          // device, m entries
+    ctpd::BlockRef* hv_filt = nullptr;        // device, filter tiles
+    int hv_nfilt = 0;
+    double* hv_sum = nullptr;                 // device, 3 doubles
+    double* hv_sum_host = nullptr;            // pinned
     // workspaces of the unrolled solve's reverse pass (allocated on first use)
     ctpd_host::UnrolledWs* uw = nullptr;
 };
@@ -170,7 +182,6 @@ struct Lanczos {
 
 int run_lanczos(const std::vector<Lanczos*>& chains);
 int setup_lambda_a(ctpd_op* op, int kmax, Lanczos* L, bool filt = true, const float* wgt = nullptr);
-int setup_lambda_h(ctpd_op* op, const float* w, double kappa, int kmax, Lanczos* L);
 
 int filter(ctpd_op* op, int mode, const float* in0, const float* in1, const float* in2, const float* in3,
            const float* E0, float e0, const float* E1, float e1, float c, float* out);
@@ -198,10 +209,20 @@ struct LowdoseSetup {
     bool norms = false;     // sigma from the norms
     bool run_a = false;     // lambda_a from the chain (else from the handle's cache)
     bool cacheable = false; // default tau: kappa * lambda_a is a property of the geometry
-    bool defer_h = false;   // the caller runs the lambda_h chain itself (batched set-up)
-    Lanczos La, Lh;
+    Lanczos La;
 };
 int lowdose_setup_begin(ctpd_op* op, const float* b, const float* w, const Knobs& k, LowdoseSetup* S);
+
+// lambda_max(W^-1/2 D W^-1/2) of each handle by per-view Lanczos chains run in
+// lockstep on stream s (needs op->sino64[3] = sqrt(1/w) and the taps).  items:
+// device / pinned tables of ops.size() entries; rows: every (problem, view);
+// filt: the filter tiles of all problems; summary: 3 doubles per problem
+// (device and pinned).  lam[i], steps[i] receive the results.
+int ensure_hv(ctpd_op* op, int kmax);
+int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, const double* kappa, int kmax,
+                   hipStream_t s, ctpd::NormItem* items, ctpd::NormItem* items_host, const ctpd::RowRef* rows,
+                   int nrows, const ctpd::BlockRef* filt, int nfilt, double* summary, double* summary_host,
+                   double* lam, int* steps);
 void lowdose_setup_end(ctpd_op* op, const Knobs& k, LowdoseSetup* S);
 
 }  // namespace ctpd_host

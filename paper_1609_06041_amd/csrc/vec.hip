@@ -278,127 +278,193 @@ hipError_t launch_mul_w_f64(double* out, const double* a, const float* w, size_t
 }
 
 // ---------------------------------------------------------------------------
-// Batched lambda_h Lanczos chains: the same per-element arithmetic and the same
-// reduction trees as the single chain (reduce_blocks_for(len) grid-stride
-// blocks, then one fixed-order final block), so every problem's recurrence
-// scalars are bit-identical to its single chain's.
-int reduce_blocks_for(size_t len) { return reduce_blocks(len); }
-
-__device__ __forceinline__ double norm_start_value(const NormItem& it, size_t i, uint64_t seed) {
-    const int c = (int)(i % (size_t)it.nb);
-    const double shape = ((c & 1) ? -1.0 : 1.0) * it.inv_kappa / (double)it.w[i];
-    return shape + 0.05 * (splitmix_unit(seed, i) - 0.5);
+// Per-view Lanczos chains for lambda_max(W^-1/2 D W^-1/2).  D acts on every
+// view (row) separately and W is diagonal, so the operator is block diagonal
+// and its largest eigenvalue is the largest over views: every view runs its
+// own chain on its nb-vector, all views (of all problems of a table) in
+// lockstep.  One wave per row for the row reductions (fixed-order shuffles)
+// and for the Ritz values (Sturm-sequence multisection on the view's
+// tridiagonal matrix).  A stopped view's vectors are left untouched.
+__device__ __forceinline__ double wave_sum_all(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
 }
 
-__global__ __launch_bounds__(256) void norm_start_batched(const NormItem* __restrict__ items,
-                                                          const BlockRef* __restrict__ map, uint64_t seed) {
-    const BlockRef e = map[blockIdx.x];
-    if (e.prob < 0) return;
-    const NormItem& it = items[e.prob];
-    const size_t len = (size_t)it.m * it.nb;
-    const size_t i = (size_t)e.local * 256 + threadIdx.x;
-    if (i < len) it.v[0][i] = norm_start_value(it, i, seed);
+#define ROW_PROLOGUE                                                   \
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);               \
+    const int lane = threadIdx.x & 63;                                 \
+    if (row >= nrows) return;                                          \
+    const RowRef rr = rows[row];                                       \
+    const NormItem& it = items[rr.prob];                               \
+    const int m = it.m, nb = it.nb, v = rr.view;                       \
+    const size_t base = (size_t)v * nb;
+
+__global__ __launch_bounds__(256) void rows_start_kernel(const NormItem* __restrict__ items,
+                                                         const RowRef* __restrict__ rows, int nrows,
+                                                         uint64_t seed) {
+    ROW_PROLOGUE
+    double* q = it.v[0] + base;
+    double ss = 0.0;
+    for (int u = lane; u < nb; u += 64) {
+        const size_t i = base + u;
+        const double shape = ((u & 1) ? -1.0 : 1.0) * it.inv_kappa / (double)it.w[i];
+        const double val = shape + 0.05 * (splitmix_unit(seed, i) - 0.5);
+        q[u] = val;
+        ss = fma(val, val, ss);
+    }
+    ss = wave_sum_all(ss);
+    const double inv = 1.0 / sqrt(ss);
+    for (int u = lane; u < nb; u += 64) q[u] *= inv;
+    if (lane == 0) {
+        it.b0[v] = ss;
+        it.done[v] = 0;
+        it.theta[v] = 0.0;
+    }
+    (void)m;
 }
 
-// kind 0: sum v0^2 (start), 1: sum q.w (alpha_j), 2: Lanczos update of w (beta_{j+1}^2 partials)
-template <int KIND>
-__global__ __launch_bounds__(256) void norm_partial_batched(const NormItem* __restrict__ items,
-                                                            const BlockRef* __restrict__ map, int rot, int j) {
-    const BlockRef e = map[blockIdx.x];
-    if (e.prob < 0) return;
-    const NormItem& it = items[e.prob];
-    const size_t len = (size_t)it.m * it.nb;
-    const int nb = reduce_blocks(len);
-    const size_t stride = (size_t)nb * 256;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    if (KIND == 0) {
-        const double* q = it.v[0];
-        for (size_t i = (size_t)e.local * 256 + threadIdx.x; i < len; i += stride) s0 = fma(q[i], q[i], s0);
-    } else if (KIND == 1) {
-        const double* q = it.v[rot];
-        const double* w = it.v[(rot + 2) % 3];
-        for (size_t i = (size_t)e.local * 256 + threadIdx.x; i < len; i += stride) s0 = fma(q[i], w[i], s0);
-    } else {
-        const double* q = it.v[rot];
-        const double* qp = j ? it.v[(rot + 1) % 3] : nullptr;
-        double* w = it.v[(rot + 2) % 3];
-        const double a = it.lz[3 * (1 + j)];
-        const double b = qp ? sqrt(it.lz[3 * (1 + it.cap + j - 1)]) : 0.0;
-        for (size_t i = (size_t)e.local * 256 + threadIdx.x; i < len; i += stride) {
-            double r = w[i] - a * q[i];
-            if (qp) r -= b * qp[i];
-            w[i] = r;
-            s0 = fma(r, r, s0);
+// Step j after the filter has put M q into w:  alpha = q.w;
+// w <- w - alpha q - beta qp;  beta'^2 = |w|^2;  w <- w / beta'.
+__global__ __launch_bounds__(256) void rows_step_kernel(const NormItem* __restrict__ items,
+                                                        const RowRef* __restrict__ rows, int nrows, int rot, int j) {
+    ROW_PROLOGUE
+    if (it.done[v]) return;
+    const double* q = it.v[rot] + base;
+    const double* qp = it.v[(rot + 1) % 3] + base;
+    double* w = it.v[(rot + 2) % 3] + base;
+    double a = 0.0;
+    for (int u = lane; u < nb; u += 64) a = fma(q[u], w[u], a);
+    a = wave_sum_all(a);
+    const double b = j ? sqrt(it.b2[(size_t)(j - 1) * m + v]) : 0.0;
+    double ss = 0.0;
+    for (int u = lane; u < nb; u += 64) {
+        double r = w[u] - a * q[u];
+        if (j) r -= b * qp[u];
+        w[u] = r;
+        ss = fma(r, r, ss);
+    }
+    ss = wave_sum_all(ss);
+    if (ss > 0.0) {
+        const double inv = 1.0 / sqrt(ss);
+        for (int u = lane; u < nb; u += 64) w[u] *= inv;
+    }
+    if (lane == 0) {
+        it.al[(size_t)j * m + v] = a;
+        it.b2[(size_t)j * m + v] = ss;
+    }
+}
+
+// Largest eigenvalue of the k x k tridiagonal matrix (alpha_i, sqrt(b2_i)) of
+// view v by multisection over one wave: each round every lane counts (Sturm
+// sequence) the eigenvalues below its own shift of the bracket, and the
+// bracket shrinks to the interval between the last shift with fewer than k
+// eigenvalues below and the first with all k (65x per round).
+__device__ double rows_tridiag_max(const NormItem& it, int v, int k, int lane) {
+    const int m = it.m;
+    auto al = [&](int i) { return it.al[(size_t)i * m + v]; };
+    auto bb = [&](int i) { return it.b2[(size_t)i * m + v]; };   // beta_{i+1}^2, couples i and i+1
+    double lo = al(0), hi = al(0);
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? sqrt(bb(i - 1)) : 0.0) + (i < k - 1 ? sqrt(bb(i)) : 0.0);
+        lo = fmin(lo, al(i) - r);
+        hi = fmax(hi, al(i) + r);
+    }
+    if (!isfinite(lo) || !isfinite(hi)) return hi;
+    for (int round = 0; round < 40 && hi - lo > 1e-15 * fmax(fabs(lo), fabs(hi)); ++round) {
+        const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+        int cnt = 0;
+        double d = 1.0;
+        for (int i = 0; i < k; ++i) {
+            d = al(i) - x - (i > 0 ? bb(i - 1) / d : 0.0);
+            if (d == 0.0) d = -1e-300;
+            if (d < 0.0) ++cnt;
         }
+        // first lane whose shift lies above every eigenvalue
+        const unsigned long long above = __ballot(cnt == k);
+        const int f = above ? __ffsll((long long)above) - 1 : 64;
+        const double nhi = f < 64 ? lo + (hi - lo) * (double)(f + 1) / 65.0 : hi;
+        const double nlo = f > 0 ? lo + (hi - lo) * (double)f / 65.0 : lo;
+        lo = nlo;
+        hi = nhi;
     }
-    block_sum3(s0, s1, s2);
-    if (threadIdx.x == 0) {
-        it.partials[3 * e.local + 0] = s0;
-        it.partials[3 * e.local + 1] = 0.0;
-        it.partials[3 * e.local + 2] = 0.0;
+    return hi;
+}
+
+// After `steps` steps: each running view's top Ritz value (one wave per view);
+// the view stops when it changed by <= tol relative over the last step or its
+// Krylov space is exhausted (beta ~ 0).
+__global__ __launch_bounds__(256) void rows_ritz_kernel(const NormItem* __restrict__ items,
+                                                        const RowRef* __restrict__ rows, int nrows, int steps,
+                                                        double tol) {
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= nrows) return;
+    const RowRef rr = rows[row];
+    const NormItem& it = items[rr.prob];
+    const int v = rr.view, m = it.m;
+    if (it.done[v]) return;
+    const double th = rows_tridiag_max(it, v, steps, lane);
+    const double bn = sqrt(fmax(it.b2[(size_t)(steps - 1) * m + v], 0.0));
+    bool stop = !(bn > 1e-300 * fmax(1.0, fabs(th))) || !isfinite(th);
+    if (!stop && steps > 1) {
+        const double th1 = rows_tridiag_max(it, v, steps - 1, lane);
+        stop = fabs(th - th1) <= tol * fabs(th);
+    }
+    if (lane == 0) {
+        it.theta[v] = th;
+        if (stop) it.done[v] = steps;
     }
 }
 
-// one workgroup per problem: slot = sum of its partials (fixed order)
-__global__ __launch_bounds__(256) void norm_final_batched(const NormItem* __restrict__ items, int slot_kind,
-                                                          int j) {
+// one workgroup per problem: {max theta, running views, max steps}
+__global__ __launch_bounds__(256) void rows_summary_kernel(const NormItem* __restrict__ items) {
     const NormItem& it = items[blockIdx.x];
-    const int nblocks = reduce_blocks((size_t)it.m * it.nb);
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += 256) {
-        s0 += it.partials[3 * b + 0];
-        s1 += it.partials[3 * b + 1];
-        s2 += it.partials[3 * b + 2];
+    double mx = -1e300, run = 0.0, st = 0.0;
+    for (int v = threadIdx.x; v < it.m; v += 256) {
+        const double th = it.theta[v];
+        if (isfinite(th)) mx = fmax(mx, th);
+        if (!it.done[v]) run += 1.0;
+        st = fmax(st, (double)it.done[v]);
     }
-    block_sum3(s0, s1, s2);
+    __shared__ double r0[256], r1[256], r2[256];
+    r0[threadIdx.x] = mx;
+    r1[threadIdx.x] = run;
+    r2[threadIdx.x] = st;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            r0[threadIdx.x] = fmax(r0[threadIdx.x], r0[threadIdx.x + off]);
+            r1[threadIdx.x] += r1[threadIdx.x + off];
+            r2[threadIdx.x] = fmax(r2[threadIdx.x], r2[threadIdx.x + off]);
+        }
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
-        double* out = slot_kind == 0 ? it.lz : slot_kind == 1 ? it.lz + 3 * (1 + j) : it.lz + 3 * (1 + it.cap + j);
-        out[0] = s0;
-        out[1] = s1;
-        out[2] = s2;
+        it.summary[0] = r0[0];
+        it.summary[1] = r1[0];
+        it.summary[2] = r2[0];
     }
 }
 
-// v[dst] = v[src] / sqrt(slot)  (start: v0 / sqrt(lz[0]); step j: w / sqrt(beta_{j+1}^2))
-__global__ __launch_bounds__(256) void norm_scale_batched(const NormItem* __restrict__ items,
-                                                          const BlockRef* __restrict__ map, int rot, int j) {
-    const BlockRef e = map[blockIdx.x];
-    if (e.prob < 0) return;
-    const NormItem& it = items[e.prob];
-    const size_t len = (size_t)it.m * it.nb;
-    const size_t i = (size_t)e.local * 256 + threadIdx.x;
-    if (i >= len) return;
-    double* v = j < 0 ? it.v[0] : it.v[(rot + 2) % 3];
-    const double* ss = j < 0 ? it.lz : it.lz + 3 * (1 + it.cap + j);
-    v[i] = v[i] / sqrt(ss[0]);
-}
+#undef ROW_PROLOGUE
 
-hipError_t launch_norm_start_batched(const NormItem* it, const BlockRef* elem, int nelem, const BlockRef* red,
-                                     int nred, int count, uint64_t seed, hipStream_t s) {
-    norm_start_batched<<<nelem, 256, 0, s>>>(it, elem, seed);
-    norm_partial_batched<0><<<nred, 256, 0, s>>>(it, red, 0, 0);
-    norm_final_batched<<<count, 256, 0, s>>>(it, 0, 0);
-    norm_scale_batched<<<nelem, 256, 0, s>>>(it, elem, 0, -1);
+hipError_t launch_rows_start(const NormItem* it, const RowRef* rows, int nrows, uint64_t seed, hipStream_t s) {
+    rows_start_kernel<<<(nrows + 3) / 4, 256, 0, s>>>(it, rows, nrows, seed);
     return hipGetLastError();
 }
 
-hipError_t launch_norm_dot_batched(const NormItem* it, const BlockRef* red, int nred, int count, int rot, int j,
-                                   hipStream_t s) {
-    norm_partial_batched<1><<<nred, 256, 0, s>>>(it, red, rot, j);
-    norm_final_batched<<<count, 256, 0, s>>>(it, 1, j);
+hipError_t launch_rows_step(const NormItem* it, const RowRef* rows, int nrows, int rot, int j, hipStream_t s) {
+    rows_step_kernel<<<(nrows + 3) / 4, 256, 0, s>>>(it, rows, nrows, rot, j);
     return hipGetLastError();
 }
 
-hipError_t launch_norm_update_batched(const NormItem* it, const BlockRef* red, int nred, int count, int rot, int j,
-                                      hipStream_t s) {
-    norm_partial_batched<2><<<nred, 256, 0, s>>>(it, red, rot, j);
-    norm_final_batched<<<count, 256, 0, s>>>(it, 2, j);
-    return hipGetLastError();
-}
-
-hipError_t launch_norm_normalize_batched(const NormItem* it, const BlockRef* elem, int nelem, int rot, int j,
-                                         hipStream_t s) {
-    norm_scale_batched<<<nelem, 256, 0, s>>>(it, elem, rot, j);
+hipError_t launch_rows_ritz(const NormItem* it, const RowRef* rows, int nrows, int count, int steps, double tol,
+                            hipStream_t s) {
+    rows_ritz_kernel<<<(nrows + 3) / 4, 256, 0, s>>>(it, rows, nrows, steps, tol);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    rows_summary_kernel<<<count, 256, 0, s>>>(it);
     return hipGetLastError();
 }
 
