@@ -48,6 +48,8 @@ extern "C" {
 #define CTPD_MAX_BINS 4096
 /* Maximum number of problems in one batch. */
 #define CTPD_MAX_BATCH 4096
+/* Maximum ctpd_params.norm_steps. */
+#define CTPD_MAX_NORM_STEPS 512
 
 typedef struct ctpd_op ctpd_op;
 typedef struct ctpd_batch ctpd_batch;
@@ -72,7 +74,8 @@ typedef struct {
     double tv_step;      /* tau_c of the TV dual iteration, default 1/8 */
     double safety;       /* rho < 1, default 0.95 */
     int32_t tv_iters;    /* inner TV steps per outer iteration, default 10 */
-    int32_t norm_steps;  /* max Lanczos steps per operator norm, default 100 */
+    int32_t norm_steps;  /* max Lanczos steps per operator norm, default 100,
+                            at most CTPD_MAX_NORM_STEPS */
     int32_t record_cost; /* 1: fill ctpd_report.cost (Eq. 1 cost, or psi for few-view) */
     int32_t reserved;
 } ctpd_params;

@@ -269,6 +269,7 @@ int read_params(const ctpd_params* p, Knobs* k) {
         k->rho = p->safety;
     }
     if (p->tv_iters > 0) k->tv_iters = p->tv_iters;
+    if (p->norm_steps > CTPD_MAX_NORM_STEPS) return einval("norm_steps above CTPD_MAX_NORM_STEPS");
     if (p->norm_steps > 0) k->norm_steps = p->norm_steps;
     k->record = p->record_cost ? 1 : 0;
     return CTPD_OK;

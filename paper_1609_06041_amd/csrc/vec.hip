@@ -282,9 +282,10 @@ hipError_t launch_mul_w_f64(double* out, const double* a, const float* w, size_t
 // view (row) separately and W is diagonal, so the operator is block diagonal
 // and its largest eigenvalue is the largest over views: every view runs its
 // own chain on its nb-vector, all views (of all problems of a table) in
-// lockstep.  One wave per row for the row reductions (fixed-order shuffles)
-// and for the Ritz values (Sturm-sequence multisection on the view's
-// tridiagonal matrix).  A stopped view's vectors are left untouched.
+// lockstep.  One workgroup per row for the Lanczos step (fixed-order
+// reductions), one wave per row for the Ritz values (Sturm-sequence
+// multisection on the view's tridiagonal matrix, scalars staged in LDS).  A
+// stopped view's vectors are left untouched.
 __device__ __forceinline__ double wave_sum_all(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -324,32 +325,47 @@ __global__ __launch_bounds__(256) void rows_start_kernel(const NormItem* __restr
     (void)m;
 }
 
-// Step j after the filter has put M q into w:  alpha = q.w;
-// w <- w - alpha q - beta qp;  beta'^2 = |w|^2;  w <- w / beta'.
+// Sum over the 256-thread block, returned to every thread (fixed order).
+__device__ __forceinline__ double block_allsum(double v, double* red4) {
+    v = wave_sum_all(v);
+    __syncthreads();   // red4 free from any previous use
+    if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (red4[0] + red4[1]) + (red4[2] + red4[3]);
+}
+
+// Step j after the filter has put M q into w (one workgroup per view):
+// alpha = q.w;  w <- w - alpha q - beta qp;  beta'^2 = |w|^2;  w <- w / beta'.
 __global__ __launch_bounds__(256) void rows_step_kernel(const NormItem* __restrict__ items,
                                                         const RowRef* __restrict__ rows, int nrows, int rot, int j) {
-    ROW_PROLOGUE
+    __shared__ double red4[4];
+    const int row = blockIdx.x;
+    if (row >= nrows) return;
+    const RowRef rr = rows[row];
+    const NormItem& it = items[rr.prob];
+    const int m = it.m, nb = it.nb, v = rr.view;
     if (it.done[v]) return;
+    const size_t base = (size_t)v * nb;
     const double* q = it.v[rot] + base;
     const double* qp = it.v[(rot + 1) % 3] + base;
     double* w = it.v[(rot + 2) % 3] + base;
     double a = 0.0;
-    for (int u = lane; u < nb; u += 64) a = fma(q[u], w[u], a);
-    a = wave_sum_all(a);
+    for (int u = threadIdx.x; u < nb; u += 256) a = fma(q[u], w[u], a);
+    a = block_allsum(a, red4);
     const double b = j ? sqrt(it.b2[(size_t)(j - 1) * m + v]) : 0.0;
     double ss = 0.0;
-    for (int u = lane; u < nb; u += 64) {
+    for (int u = threadIdx.x; u < nb; u += 256) {
         double r = w[u] - a * q[u];
         if (j) r -= b * qp[u];
         w[u] = r;
         ss = fma(r, r, ss);
     }
-    ss = wave_sum_all(ss);
+    ss = block_allsum(ss, red4);
     if (ss > 0.0) {
         const double inv = 1.0 / sqrt(ss);
-        for (int u = lane; u < nb; u += 64) w[u] *= inv;
+        for (int u = threadIdx.x; u < nb; u += 256) w[u] *= inv;
     }
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
         it.al[(size_t)j * m + v] = a;
         it.b2[(size_t)j * m + v] = ss;
     }
@@ -360,15 +376,13 @@ __global__ __launch_bounds__(256) void rows_step_kernel(const NormItem* __restri
 // sequence) the eigenvalues below its own shift of the bracket, and the
 // bracket shrinks to the interval between the last shift with fewer than k
 // eigenvalues below and the first with all k (65x per round).
-__device__ double rows_tridiag_max(const NormItem& it, int v, int k, int lane) {
-    const int m = it.m;
-    auto al = [&](int i) { return it.al[(size_t)i * m + v]; };
-    auto bb = [&](int i) { return it.b2[(size_t)i * m + v]; };   // beta_{i+1}^2, couples i and i+1
-    double lo = al(0), hi = al(0);
+__device__ double rows_tridiag_max(const double* __restrict__ al, const double* __restrict__ bb, int k, int lane) {
+    // al[i]: alpha_i; bb[i]: beta_{i+1}^2 (couples i and i+1); both in LDS
+    double lo = al[0], hi = al[0];
     for (int i = 0; i < k; ++i) {
-        const double r = (i > 0 ? sqrt(bb(i - 1)) : 0.0) + (i < k - 1 ? sqrt(bb(i)) : 0.0);
-        lo = fmin(lo, al(i) - r);
-        hi = fmax(hi, al(i) + r);
+        const double r = (i > 0 ? sqrt(bb[i - 1]) : 0.0) + (i < k - 1 ? sqrt(bb[i]) : 0.0);
+        lo = fmin(lo, al[i] - r);
+        hi = fmax(hi, al[i] + r);
     }
     if (!isfinite(lo) || !isfinite(hi)) return hi;
     for (int round = 0; round < 40 && hi - lo > 1e-15 * fmax(fabs(lo), fabs(hi)); ++round) {
@@ -376,7 +390,7 @@ __device__ double rows_tridiag_max(const NormItem& it, int v, int k, int lane) {
         int cnt = 0;
         double d = 1.0;
         for (int i = 0; i < k; ++i) {
-            d = al(i) - x - (i > 0 ? bb(i - 1) / d : 0.0);
+            d = al[i] - x - (i > 0 ? bb[i - 1] / d : 0.0);
             if (d == 0.0) d = -1e-300;
             if (d < 0.0) ++cnt;
         }
@@ -391,24 +405,36 @@ __device__ double rows_tridiag_max(const NormItem& it, int v, int k, int lane) {
     return hi;
 }
 
+constexpr int kRitzMax = CTPD_MAX_NORM_STEPS;   // steps a per-view chain can take
+
 // After `steps` steps: each running view's top Ritz value (one wave per view);
 // the view stops when it changed by <= tol relative over the last step or its
 // Krylov space is exhausted (beta ~ 0).
 __global__ __launch_bounds__(256) void rows_ritz_kernel(const NormItem* __restrict__ items,
                                                         const RowRef* __restrict__ rows, int nrows, int steps,
                                                         double tol) {
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    __shared__ double sal[4][kRitzMax], sbb[4][kRitzMax];
+    const int wv = threadIdx.x >> 6;
+    const int row = blockIdx.x * 4 + wv;
     const int lane = threadIdx.x & 63;
     if (row >= nrows) return;
     const RowRef rr = rows[row];
     const NormItem& it = items[rr.prob];
     const int v = rr.view, m = it.m;
     if (it.done[v]) return;
-    const double th = rows_tridiag_max(it, v, steps, lane);
-    const double bn = sqrt(fmax(it.b2[(size_t)(steps - 1) * m + v], 0.0));
+    // the view's recurrence scalars into LDS (strided by m in HBM; read once)
+    for (int i = lane; i < steps; i += 64) {
+        sal[wv][i] = it.al[(size_t)i * m + v];
+        sbb[wv][i] = it.b2[(size_t)i * m + v];
+    }
+    // the wave's own LDS writes are complete and visible to its lanes before the reads
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    const double th = rows_tridiag_max(sal[wv], sbb[wv], steps, lane);
+    const double bn = sqrt(fmax(sbb[wv][steps - 1], 0.0));
     bool stop = !(bn > 1e-300 * fmax(1.0, fabs(th))) || !isfinite(th);
     if (!stop && steps > 1) {
-        const double th1 = rows_tridiag_max(it, v, steps - 1, lane);
+        const double th1 = rows_tridiag_max(sal[wv], sbb[wv], steps - 1, lane);
         stop = fabs(th - th1) <= tol * fabs(th);
     }
     if (lane == 0) {
@@ -455,7 +481,7 @@ hipError_t launch_rows_start(const NormItem* it, const RowRef* rows, int nrows, 
 }
 
 hipError_t launch_rows_step(const NormItem* it, const RowRef* rows, int nrows, int rot, int j, hipStream_t s) {
-    rows_step_kernel<<<(nrows + 3) / 4, 256, 0, s>>>(it, rows, nrows, rot, j);
+    rows_step_kernel<<<nrows, 256, 0, s>>>(it, rows, nrows, rot, j);
     return hipGetLastError();
 }
 

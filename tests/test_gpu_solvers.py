@@ -170,3 +170,6 @@ def test_invalid_weights_and_data_are_rejected(gpu):
         with pytest.raises(ctpd.CtpdError) as e:
             op.lowdose_solve(dev(b), dev(w), -1.0, 3)
         assert e.value.code == ctpd.CTPD_EINVAL
+        with pytest.raises(ctpd.CtpdError) as e:
+            op.lowdose_solve(dev(b), dev(w), 0.1, 3, norm_steps=513)
+        assert e.value.code == ctpd.CTPD_EINVAL
