@@ -141,8 +141,8 @@ double tridiag_max(const std::vector<double>& a, const std::vector<double>& b) {
 int ensure_lz(ctpd_op* op, int kmax) {
     if (op->lz_cap >= kmax) return CTPD_OK;
     for (int c = 0; c < 2; ++c) {
-        if (op->lz[c]) hipFree(op->lz[c]);
-        if (op->lz_host[c]) hipHostFree(op->lz_host[c]);
+        if (op->lz[c]) (void)hipFree(op->lz[c]);
+        if (op->lz_host[c]) (void)hipHostFree(op->lz_host[c]);
         op->lz[c] = nullptr;
         op->lz_host[c] = nullptr;
     }
@@ -277,7 +277,7 @@ int read_params(const ctpd_params* p, Knobs* k) {
 
 int ensure_cost(ctpd_op* op, int iters) {
     if (op->cost_cap >= iters) return CTPD_OK;
-    if (op->cost_dev) hipFree(op->cost_dev);
+    if (op->cost_dev) (void)hipFree(op->cost_dev);
     op->cost_dev = nullptr;
     op->cost_cap = 0;
     ALLOC(op->cost_dev, (size_t)6 * std::max(iters, 1));
@@ -330,8 +330,8 @@ int ensure_hv(ctpd_op* op, int kmax) {
         ALLOC(op->hv_done, op->m);
     }
     if (op->hv_cap < kmax) {
-        if (op->hv_al) hipFree(op->hv_al);
-        if (op->hv_b2) hipFree(op->hv_b2);
+        if (op->hv_al) (void)hipFree(op->hv_al);
+        if (op->hv_b2) (void)hipFree(op->hv_b2);
         op->hv_al = op->hv_b2 = nullptr;
         op->hv_cap = 0;
         ALLOC(op->hv_al, (size_t)kmax * op->m);
@@ -505,29 +505,29 @@ int ctpd_op_create(const ctpd_geometry* g, void* stream, ctpd_op** out) {
 
 void ctpd_op_destroy(ctpd_op* op) {
     if (!op) return;
-    if (op->stream || op->views) hipStreamSynchronize(op->stream);
+    if (op->stream || op->views) (void)hipStreamSynchronize(op->stream);
     void* ptrs[] = {op->views, op->xp, op->xTp, op->x, op->z, op->p[0], op->p[1], op->mu[0], op->mu[1], op->mu[2],
                     op->mubar, op->q, op->winv, op->taps64, op->taps32, op->partials, op->red, op->cost_dev,
                     op->img64[0], op->img64[1], op->img64[2], op->pad64[0], op->pad64[1], op->sino64[0], op->sino64[1],
                     op->sino64[2], op->sino64[3], op->sino64[4], op->sino64[5], op->lz[0], op->lz[1],
                     op->lz_partials[0], op->lz_partials[1], op->xbar};
     for (void* p : ptrs)
-        if (p) hipFree(p);
-    if (op->red_host) hipHostFree(op->red_host);
+        if (p) (void)hipFree(p);
+    if (op->red_host) (void)hipHostFree(op->red_host);
     for (double* h : op->lz_host)
-        if (h) hipHostFree(h);
+        if (h) (void)hipHostFree(h);
     if (op->aux) {
-        hipStreamSynchronize(op->aux);
-        hipStreamDestroy(op->aux);
+        (void)hipStreamSynchronize(op->aux);
+        (void)hipStreamDestroy(op->aux);
     }
-    if (op->fork) hipEventDestroy(op->fork);
+    if (op->fork) (void)hipEventDestroy(op->fork);
     free_unrolled(op->uw);
     void* hv[] = {op->hv_al, op->hv_b2, op->hv_b0, op->hv_theta, op->hv_done, op->hv_item, op->hv_rows, op->hv_filt,
                   op->hv_sum};
     for (void* p : hv)
-        if (p) hipFree(p);
-    if (op->hv_item_host) hipHostFree(op->hv_item_host);
-    if (op->hv_sum_host) hipHostFree(op->hv_sum_host);
+        if (p) (void)hipFree(p);
+    if (op->hv_item_host) (void)hipHostFree(op->hv_item_host);
+    if (op->hv_sum_host) (void)hipHostFree(op->hv_sum_host);
     delete op;
 }
 

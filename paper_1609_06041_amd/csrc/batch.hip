@@ -100,7 +100,7 @@ int build_maps(ctpd_batch* bt) {
                 for (int l = 0; l < nb; ++l) flat.push_back(BlockRef{p, l});
             }
         }
-        if (bt->map[kind]) hipFree(bt->map[kind]);
+        if (bt->map[kind]) (void)hipFree(bt->map[kind]);
         bt->map[kind] = nullptr;
         ALLOC(bt->map[kind], flat.size());
         HIP_TRY(hipMemcpy(bt->map[kind], flat.data(), sizeof(BlockRef) * flat.size(), hipMemcpyHostToDevice));
@@ -142,8 +142,8 @@ int queue_loop(ctpd_batch* bt, int iters, int tv_iters) {
 
 int capture_loop(ctpd_batch* bt, int iters, int tv_iters) {
     if (bt->exec && bt->g_iters == iters && bt->g_tv == tv_iters) return CTPD_OK;
-    if (bt->exec) hipGraphExecDestroy(bt->exec);
-    if (bt->graph) hipGraphDestroy(bt->graph);
+    if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+    if (bt->graph) (void)hipGraphDestroy(bt->graph);
     bt->exec = nullptr;
     bt->graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(bt->gs, hipStreamCaptureModeThreadLocal));
@@ -151,7 +151,7 @@ int capture_loop(ctpd_batch* bt, int iters, int tv_iters) {
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(bt->gs, &g);
     if (r) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return r;
     }
     HIP_TRY(e);
@@ -212,22 +212,22 @@ int ctpd_batch_create(const ctpd_geometry* geoms, int32_t count, void* stream, c
 
 void ctpd_batch_destroy(ctpd_batch* bt) {
     if (!bt) return;
-    if (bt->gs) hipStreamSynchronize(bt->gs);
-    if (bt->exec) hipGraphExecDestroy(bt->exec);
-    if (bt->graph) hipGraphDestroy(bt->graph);
+    if (bt->gs) (void)hipStreamSynchronize(bt->gs);
+    if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+    if (bt->graph) (void)hipGraphDestroy(bt->graph);
     for (ctpd_op* op : bt->ops) ctpd_op_destroy(op);
-    for (hipStream_t st : bt->streams) hipStreamDestroy(st);
+    for (hipStream_t st : bt->streams) (void)hipStreamDestroy(st);
     for (BlockRef* m : bt->map)
-        if (m) hipFree(m);
-    if (bt->items) hipFree(bt->items);
-    if (bt->items_host) hipHostFree(bt->items_host);
-    if (bt->nitems) hipFree(bt->nitems);
-    if (bt->nitems_host) hipHostFree(bt->nitems_host);
-    if (bt->rows) hipFree(bt->rows);
-    if (bt->hsum) hipFree(bt->hsum);
-    if (bt->hsum_host) hipHostFree(bt->hsum_host);
-    if (bt->ev) hipEventDestroy(bt->ev);
-    if (bt->gs) hipStreamDestroy(bt->gs);
+        if (m) (void)hipFree(m);
+    if (bt->items) (void)hipFree(bt->items);
+    if (bt->items_host) (void)hipHostFree(bt->items_host);
+    if (bt->nitems) (void)hipFree(bt->nitems);
+    if (bt->nitems_host) (void)hipHostFree(bt->nitems_host);
+    if (bt->rows) (void)hipFree(bt->rows);
+    if (bt->hsum) (void)hipFree(bt->hsum);
+    if (bt->hsum_host) (void)hipHostFree(bt->hsum_host);
+    if (bt->ev) (void)hipEventDestroy(bt->ev);
+    if (bt->gs) (void)hipStreamDestroy(bt->gs);
     delete bt;
 }
 
@@ -376,8 +376,8 @@ int ctpd_batch_time_loop(ctpd_batch* bt, int32_t iters, int32_t tv_iters, int32_
         if (e == hipSuccess) e = hipEventElapsedTime(&t[i], e0, e1);
         if (e != hipSuccess) rc = fail_hip(e, "timing the batched loop");
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc) return rc;
     std::sort(t.begin(), t.end());
     *ms = t[reps / 2];

@@ -171,14 +171,19 @@ int tv_chunk_max();       // dual steps per TV launch at most
 // p_in; x = max(0, z - lam div p_out) written when x is not null.
 hipError_t launch_tv_steps(const float* z, const float* p_in, float* p_out, float* x, int n, float lam, float step,
                            int steps, hipStream_t s);
-// Reverse pass of the TV prox (one dual step = three kernels, in reverse order
-// of use), see tv.hip.
+// the steps (<= tv_chunk_max()) from p_in, every intermediate dual field stored:
+// step t's at ps + (t - 1) 2 n^2
+hipError_t launch_tv_steps_store(const float* z, const float* p_in, float* ps, int n, float lam, float step,
+                                 int steps, hipStream_t s);
+// Reverse pass of the TV prox (tv.hip).  Each kernel writes one block sum of
+// its scalar-adjoint term per workgroup to partial[0 .. tv_bwd_blocks(n)).
+int tv_bwd_blocks(int n);
 hipError_t launch_tv_bwd_final(const float* z, const float* p, const float* xbar, int n, float lam, float* tbar,
-                               float* zbar, float* prod, hipStream_t s);
-hipError_t launch_tv_bwd_proj(const float* z, const float* p_prev, const float* pbar, int n, float lam, float step,
-                              float* qbar, float* prod, hipStream_t s);
+                               float* zbar, double* partial, hipStream_t s);
+hipError_t launch_tv_bwd_gradproj(const float* z, const float* p_prev, float* qn, const float* tn, int n, float lam,
+                                  float step, double* partial, hipStream_t s);
 hipError_t launch_tv_bwd_mask(const float* z, const float* p_prev, const float* qbar, int n, float lam, float step,
-                              float* tbar, float* zbar, float* prod, hipStream_t s);
+                              float* tbar, float* zbar, double* partial, hipStream_t s);
 hipError_t launch_tv_bwd_grad(const float* qbar, const float* tbar, int n, float lam, float* pbar,
                               hipStream_t s);
 hipError_t launch_tv_finalize(const float* z, const float* p, float* x, int n, float lam, hipStream_t s);
@@ -233,6 +238,12 @@ hipError_t launch_rows_start(const NormItem* it, const RowRef* rows, int nrows, 
 hipError_t launch_rows_step(const NormItem* it, const RowRef* rows, int nrows, int rot, int j, hipStream_t s);
 hipError_t launch_rows_ritz(const NormItem* it, const RowRef* rows, int nrows, int count, int steps, double tol,
                             hipStream_t s);
+// per-block float64 partial sums of a . b into partial[0 .. reduce_blocks_for(len));
+// slot sums: out[k] = sum(partial[k cap .. (k+1) cap)); fill for float64 buffers
+hipError_t launch_dot_partials(const float* a, const float* b, size_t len, double* partial, hipStream_t s);
+hipError_t launch_slot_reduce(const double* partial, int cap, int nslots, double* out, hipStream_t s);
+hipError_t launch_fill_f64(double* dst, double v, size_t len, hipStream_t s);
+int reduce_blocks_for(size_t len);
 hipError_t launch_inverse_f32(float* out, const float* w, size_t len, hipStream_t s);
 hipError_t launch_rsqrt_f64(double* out, const float* w, size_t len, hipStream_t s);
 hipError_t launch_copy_f32(float* dst, const float* src, size_t len, hipStream_t s);

@@ -42,10 +42,14 @@ constexpr int kTvMaxW = kTvTile + 2 * (kTvChunk + 1);
 // dependent stencil reads); a wave sweeps one 64-wide LDS row at a time.
 constexpr int kTvThreads = 1024;
 
+// ps_store (optional): the dual field after every step t = 1..steps is also
+// written to ps_store + (t - 1) * 2 n^2 (the interior stays valid: the halo
+// is one pixel wider than the steps taken).
 template <int THREADS>
 __device__ __forceinline__ void tv_prox_body(const float* __restrict__ z, const float* __restrict__ p_in,
                                              float* __restrict__ p_out, float* __restrict__ x, int n, float lam,
-                                             float step, int steps, int bxi, int byi) {
+                                             float step, int steps, int bxi, int byi,
+                                             float* __restrict__ ps_store = nullptr) {
     __shared__ float sz[kTvMaxW * kTvMaxW], sx[kTvMaxW * kTvMaxW];
     __shared__ float s1[kTvMaxW * kTvMaxW], s2[kTvMaxW * kTvMaxW];
     const int H = steps + 1, W = kTvTile + 2 * H;
@@ -101,6 +105,16 @@ __device__ __forceinline__ void tv_prox_body(const float* __restrict__ z, const 
             s2[o] = q2 / sc;
         }
         __syncthreads();
+        if (ps_store) {
+            float* dst = ps_store + (size_t)(t - 1) * 2 * nn;
+            for (int r = H + ty; r < H + kTvTile; r += (THREADS / 64)) {
+                const int i = i0 + r;
+                if (!(jin && c >= H && c < H + kTvTile && i < n)) continue;
+                const size_t g = (size_t)i * n + j;
+                dst[g] = s1[r * W + c];
+                dst[nn + g] = s2[r * W + c];
+            }
+        }
     }
     for (int r = H + ty; r < H + kTvTile; r += (THREADS / 64)) {
         const int i = i0 + r;
@@ -191,6 +205,23 @@ hipError_t launch_grad_ball(const float* xb, float* p, int n, float sg, hipStrea
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(kTvThreads) void tv_steps_store_kernel(const float* __restrict__ z,
+                                                                    const float* __restrict__ p_in,
+                                                                    float* __restrict__ ps, int n, float lam,
+                                                                    float step, int steps) {
+    // final p of the launch goes to the last stored slot as well
+    tv_prox_body<kTvThreads>(z, p_in, ps + (size_t)(steps - 1) * 2 * n * n, nullptr, n, lam, step, steps, blockIdx.x,
+                             blockIdx.y, ps);
+}
+
+hipError_t launch_tv_steps_store(const float* z, const float* p_in, float* ps, int n, float lam, float step,
+                                 int steps, hipStream_t s) {
+    if (steps < 1 || steps > kTvChunk) return hipErrorInvalidValue;
+    dim3 grid((n + kTvTile - 1) / kTvTile, (n + kTvTile - 1) / kTvTile);
+    tv_steps_store_kernel<<<grid, kTvThreads, 0, s>>>(z, p_in, ps, n, lam, step, steps);
+    return hipGetLastError();
+}
+
 hipError_t launch_tv_steps(const float* z, const float* p_in, float* p_out, float* x, int n, float lam, float step,
                            int steps, hipStream_t s) {
     if (steps > kTvChunk) return hipErrorInvalidValue;
@@ -219,68 +250,104 @@ __device__ __forceinline__ float tv_div(const float* __restrict__ p1, const floa
     return d;
 }
 
+// Sum of one value per thread over the 256-thread block, written by thread 0
+// to out (fixed order).
+__device__ __forceinline__ void block_sum_to(float v, double* out) {
+    __shared__ double red[4];
+    double d = (double)v;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// One pixel per thread, 64 x 4 per workgroup; out-of-range threads take part
+// in the block sums with zero.
 #define TV_PIXEL                                              \
     const int j = blockIdx.x * 64 + (threadIdx.x & 63);       \
     const int i = blockIdx.y * 4 + (threadIdx.x >> 6);        \
-    if (i >= n || j >= n) return;                             \
-    const size_t nn = (size_t)n * n, idx = (size_t)i * n + j;
+    const bool in = i < n && j < n;                           \
+    const size_t nn = (size_t)n * n, idx = in ? (size_t)i * n + j : 0;
+#define TV_SLOT (partial + blockIdx.y * gridDim.x + blockIdx.x)
 
+// x = max(0, z - lam div p): t = mask * xbar; tbar = t, zbar = t; sum -t.div p
 __global__ __launch_bounds__(256) void tv_bwd_final_kernel(const float* __restrict__ z, const float* __restrict__ p,
                                                            const float* __restrict__ xbar, int n, float lam,
                                                            float* __restrict__ tbar, float* __restrict__ zbar,
-                                                           float* __restrict__ prod) {
+                                                           double* __restrict__ partial) {
     TV_PIXEL
-    const float d = tv_div(p, p + nn, i, j, n, idx);
-    const float t = (z[idx] - lam * d > 0.0f) ? xbar[idx] : 0.0f;
-    tbar[idx] = t;
-    zbar[idx] = t;
-    prod[idx] = -t * d;
-}
-
-__global__ __launch_bounds__(256) void tv_bwd_proj_kernel(const float* __restrict__ z,
-                                                          const float* __restrict__ pp,
-                                                          const float* __restrict__ pbar, int n, float lam,
-                                                          float step, float* __restrict__ qbar,
-                                                          float* __restrict__ prod) {
-    TV_PIXEL
-    const float* p1 = pp;
-    const float* p2 = pp + nn;
-    const float xc = fmaxf(0.0f, z[idx] - lam * tv_div(p1, p2, i, j, n, idx));
-    const float g1 = (j < n - 1) ? fmaxf(0.0f, z[idx + 1] - lam * tv_div(p1, p2, i, j + 1, n, idx + 1)) - xc : 0.0f;
-    const float g2 = (i < n - 1) ? fmaxf(0.0f, z[idx + n] - lam * tv_div(p1, p2, i + 1, j, n, idx + n)) - xc : 0.0f;
-    const float q1 = p1[idx] - step * g1, q2 = p2[idx] - step * g2;
-    const float b1 = pbar[idx], b2 = pbar[nn + idx];
-    const float nq = sqrtf(q1 * q1 + q2 * q2);
-    float r1 = b1, r2 = b2;
-    if (nq > 1.0f) {
-        const float u1 = q1 / nq, u2 = q2 / nq;
-        const float dp = u1 * b1 + u2 * b2;
-        r1 = (b1 - u1 * dp) / nq;
-        r2 = (b2 - u2 * dp) / nq;
+    float v = 0.0f;
+    if (in) {
+        const float d = tv_div(p, p + nn, i, j, n, idx);
+        const float t = (z[idx] - lam * d > 0.0f) ? xbar[idx] : 0.0f;
+        tbar[idx] = t;
+        zbar[idx] = t;
+        v = -t * d;
     }
-    qbar[idx] = r1;
-    qbar[nn + idx] = r2;
-    prod[idx] = -(r1 * g1 + r2 * g2);
+    block_sum_to(v, TV_SLOT);
 }
 
+// Reverse of one dual step, first half: pbar = qn + lam grad tn (the adjoint of
+// the step's output p), then qbar = J_P(q) pbar written over qn; sum -qbar.grad x~.
+__global__ __launch_bounds__(256) void tv_bwd_gradproj_kernel(const float* __restrict__ z,
+                                                              const float* __restrict__ pp, float* qn,
+                                                              const float* __restrict__ tn, int n, float lam,
+                                                              float step, double* __restrict__ partial) {
+    TV_PIXEL
+    float v = 0.0f;
+    if (in) {
+        const float tc = tn[idx];
+        const float b1 = qn[idx] + lam * ((j < n - 1) ? tn[idx + 1] - tc : 0.0f);
+        const float b2 = qn[nn + idx] + lam * ((i < n - 1) ? tn[idx + n] - tc : 0.0f);
+        const float* p1 = pp;
+        const float* p2 = pp + nn;
+        const float xc = fmaxf(0.0f, z[idx] - lam * tv_div(p1, p2, i, j, n, idx));
+        const float g1 =
+            (j < n - 1) ? fmaxf(0.0f, z[idx + 1] - lam * tv_div(p1, p2, i, j + 1, n, idx + 1)) - xc : 0.0f;
+        const float g2 =
+            (i < n - 1) ? fmaxf(0.0f, z[idx + n] - lam * tv_div(p1, p2, i + 1, j, n, idx + n)) - xc : 0.0f;
+        const float q1 = p1[idx] - step * g1, q2 = p2[idx] - step * g2;
+        const float nq = sqrtf(q1 * q1 + q2 * q2);
+        float r1 = b1, r2 = b2;
+        if (nq > 1.0f) {
+            const float u1 = q1 / nq, u2 = q2 / nq;
+            const float dp = u1 * b1 + u2 * b2;
+            r1 = (b1 - u1 * dp) / nq;
+            r2 = (b2 - u2 * dp) / nq;
+        }
+        qn[idx] = r1;
+        qn[nn + idx] = r2;
+        v = -(r1 * g1 + r2 * g2);
+    }
+    block_sum_to(v, TV_SLOT);
+}
+
+// Second half: t = mask * step * div qbar; tbar = t, zbar += t; sum -t.div p.
 __global__ __launch_bounds__(256) void tv_bwd_mask_kernel(const float* __restrict__ z,
                                                           const float* __restrict__ pp,
                                                           const float* __restrict__ qbar, int n, float lam,
                                                           float step, float* __restrict__ tbar,
-                                                          float* __restrict__ zbar, float* __restrict__ prod) {
+                                                          float* __restrict__ zbar, double* __restrict__ partial) {
     TV_PIXEL
-    const float d = tv_div(pp, pp + nn, i, j, n, idx);
-    const float xtb = step * tv_div(qbar, qbar + nn, i, j, n, idx);
-    const float t = (z[idx] - lam * d > 0.0f) ? xtb : 0.0f;
-    tbar[idx] = t;
-    zbar[idx] += t;
-    prod[idx] = -t * d;
+    float v = 0.0f;
+    if (in) {
+        const float d = tv_div(pp, pp + nn, i, j, n, idx);
+        const float xtb = step * tv_div(qbar, qbar + nn, i, j, n, idx);
+        const float t = (z[idx] - lam * d > 0.0f) ? xtb : 0.0f;
+        tbar[idx] = t;
+        zbar[idx] += t;
+        v = -t * d;
+    }
+    block_sum_to(v, TV_SLOT);
 }
 
+// pbar = qbar + lam grad tbar (the adjoint of the warm-start dual field)
 __global__ __launch_bounds__(256) void tv_bwd_grad_kernel(const float* __restrict__ qbar,
                                                           const float* __restrict__ tbar, int n, float lam,
                                                           float* __restrict__ pbar) {
     TV_PIXEL
+    if (!in) return;
     const float tc = tbar[idx];
     const float g1 = (j < n - 1) ? tbar[idx + 1] - tc : 0.0f;
     const float g2 = (i < n - 1) ? tbar[idx + n] - tc : 0.0f;
@@ -288,26 +355,29 @@ __global__ __launch_bounds__(256) void tv_bwd_grad_kernel(const float* __restric
     pbar[nn + idx] = qbar[nn + idx] + lam * g2;
 }
 
+#undef TV_SLOT
 #undef TV_PIXEL
 
+int tv_bwd_blocks(int n) { return ((n + 63) / 64) * ((n + 3) / 4); }
+
 hipError_t launch_tv_bwd_final(const float* z, const float* p, const float* xbar, int n, float lam, float* tbar,
-                               float* zbar, float* prod, hipStream_t s) {
+                               float* zbar, double* partial, hipStream_t s) {
     dim3 grid((n + 63) / 64, (n + 3) / 4);
-    tv_bwd_final_kernel<<<grid, 256, 0, s>>>(z, p, xbar, n, lam, tbar, zbar, prod);
+    tv_bwd_final_kernel<<<grid, 256, 0, s>>>(z, p, xbar, n, lam, tbar, zbar, partial);
     return hipGetLastError();
 }
 
-hipError_t launch_tv_bwd_proj(const float* z, const float* p_prev, const float* pbar, int n, float lam, float step,
-                              float* qbar, float* prod, hipStream_t s) {
+hipError_t launch_tv_bwd_gradproj(const float* z, const float* p_prev, float* qn, const float* tn, int n, float lam,
+                                  float step, double* partial, hipStream_t s) {
     dim3 grid((n + 63) / 64, (n + 3) / 4);
-    tv_bwd_proj_kernel<<<grid, 256, 0, s>>>(z, p_prev, pbar, n, lam, step, qbar, prod);
+    tv_bwd_gradproj_kernel<<<grid, 256, 0, s>>>(z, p_prev, qn, tn, n, lam, step, partial);
     return hipGetLastError();
 }
 
 hipError_t launch_tv_bwd_mask(const float* z, const float* p_prev, const float* qbar, int n, float lam, float step,
-                              float* tbar, float* zbar, float* prod, hipStream_t s) {
+                              float* tbar, float* zbar, double* partial, hipStream_t s) {
     dim3 grid((n + 63) / 64, (n + 3) / 4);
-    tv_bwd_mask_kernel<<<grid, 256, 0, s>>>(z, p_prev, qbar, n, lam, step, tbar, zbar, prod);
+    tv_bwd_mask_kernel<<<grid, 256, 0, s>>>(z, p_prev, qbar, n, lam, step, tbar, zbar, partial);
     return hipGetLastError();
 }
 

@@ -26,18 +26,20 @@ struct UnrolledWs {
     float *ap = nullptr, *pba = nullptr, *pbb = nullptr, *qbar = nullptr;
     float *e = nullptr, *r = nullptr, *dr = nullptr, *dm = nullptr, *rbar = nullptr, *az = nullptr, *daz = nullptr,
           *dpaz = nullptr;
-    float* ps = nullptr;   // (tv_cap + 1) dual fields of one outer iteration
-    double* slots = nullptr;
-    std::vector<double> slots_host;
+    float* ps = nullptr;   // tv_cap dual fields of one outer iteration (after steps 1..n_tv)
+    double* part = nullptr;    // scalar-adjoint terms: slot_cap block sums per slot
+    double* sums = nullptr;    // one total per slot
+    int part_cap = 0;          // block sums per slot
+    std::vector<double> sums_host;
 };
 
 void free_unrolled(UnrolledWs* u) {
     if (!u) return;
     void* ptrs[] = {u->dtaps64, u->dtaps32, u->ax,   u->axt, u->zbar, u->tbar, u->prod, u->amu,  u->amu2,
                     u->amup,    u->amup2,   u->ap,   u->pba, u->pbb,  u->qbar, u->e,    u->r,    u->dr,
-                    u->dm,      u->rbar,    u->az,   u->daz, u->dpaz, u->ps,   u->slots};
+                    u->dm,      u->rbar,    u->az,   u->daz, u->dpaz, u->ps,   u->part, u->sums};
     for (void* p : ptrs)
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
     delete u;
 }
 
@@ -62,18 +64,22 @@ int ensure_unrolled(ctpd_op* op, int tv_iters, int nslots) {
     }
     UnrolledWs* u = op->uw;
     if (u->tv_cap < tv_iters) {
-        if (u->ps) hipFree(u->ps);
+        if (u->ps) (void)hipFree(u->ps);
         u->ps = nullptr;
         u->tv_cap = -1;
-        ALLOC(u->ps, (size_t)(tv_iters + 1) * 2 * op->J);
+        ALLOC(u->ps, (size_t)std::max(tv_iters, 1) * 2 * op->J);
         u->tv_cap = tv_iters;
     }
-    if (u->slot_cap < nslots) {
-        if (u->slots) hipFree(u->slots);
-        u->slots = nullptr;
+    const int cap = std::max(tv_bwd_blocks(op->n), reduce_blocks_for(std::max(op->I, op->J)));
+    if (u->slot_cap < nslots || u->part_cap != cap) {
+        if (u->part) (void)hipFree(u->part);
+        if (u->sums) (void)hipFree(u->sums);
+        u->part = u->sums = nullptr;
         u->slot_cap = 0;
-        ALLOC(u->slots, (size_t)3 * nslots);
+        ALLOC(u->part, (size_t)cap * nslots);
+        ALLOC(u->sums, nslots);
         u->slot_cap = nslots;
+        u->part_cap = cap;
     }
     return CTPD_OK;
 }
@@ -188,7 +194,7 @@ int ctpd_unrolled_lowdose_backward(ctpd_op* op, const float* b, const float* w, 
     Knobs k;
     if ((r = read_params(p, &k))) return r;
     const int nt = k.tv_iters;
-    const int per_iter = 2 * nt + 8;
+    const int per_iter = 2 * nt + 6;
     if ((r = ensure_unrolled(op, nt, iters * per_iter))) return r;
     double kappa = 0.0;
     if ((r = prepare(op, b, w, tau, &kappa))) return r;
@@ -204,25 +210,23 @@ int ctpd_unrolled_lowdose_backward(ctpd_op* op, const float* b, const float* w, 
     auto X = [&](int i) { return ckpt + (size_t)i * L.stride + L.x; };
     auto MU = [&](int i) { return ckpt + (size_t)i * L.stride + L.mu; };
     auto P = [&](int i) { return ckpt + (size_t)i * L.stride + L.p; };
-    auto PS = [&](int i) { return u->ps + (size_t)i * 2 * J; };
     const float fs = (float)sigma, ft = (float)tau, lam = (float)(tau * beta);
     const float tvstep = lam > 0 ? (float)(k.tv_step / (tau * beta)) : 0.f;
     const float* taps = op->taps32;
     const float* dtaps = u->dtaps32;
-    // scalar adjoint terms: (category, factor) per device slot
+    // Scalar-adjoint terms: every term gets a slot of part_cap block sums
+    // (written by the kernels that produce it), reduced once at the end and
+    // added up on the host by category in a fixed order.
     std::vector<std::pair<int, double>> terms;
-    auto dot = [&](int cat, double factor, const float* a, const float* bb, size_t len) -> int {
-        const int slot = (int)terms.size();
+    auto slot = [&](int cat, double factor) -> double* {
         terms.emplace_back(cat, factor);
-        HIP_TRY(launch_reduce(RED_DOT_F32, a, bb, nullptr, len, op->partials, u->slots + 3 * slot, s));
+        return u->part + (size_t)(terms.size() - 1) * u->part_cap;
+    };
+    auto dot = [&](int cat, double factor, const float* a, const float* bb, size_t len) -> int {
+        HIP_TRY(launch_dot_partials(a, bb, len, slot(cat, factor), s));
         return CTPD_OK;
     };
-    auto sum = [&](int cat, const float* a, size_t len) -> int {
-        const int slot = (int)terms.size();
-        terms.emplace_back(cat, 1.0);
-        HIP_TRY(launch_reduce(RED_SUM_F32, a, nullptr, nullptr, len, op->partials, u->slots + 3 * slot, s));
-        return CTPD_OK;
-    };
+    HIP_TRY(launch_fill_f64(u->part, 0.0, (size_t)u->part_cap * iters * per_iter, s));
     // adjoint state of (x^{k+1}, mu^{k+1}, mu^k as the next iteration's mu_prev, p^{k+1})
     HIP_TRY(launch_copy_f32(u->ax, x_grad, J, s));
     HIP_TRY(launch_fill_f32(u->amu, 0.f, I, s));
@@ -243,10 +247,17 @@ int ctpd_unrolled_lowdose_backward(ctpd_op* op, const float* b, const float* w, 
         if (r) return r;
         HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, x, 1.f, -ft, op->z, op->views, op->n, op->m,
                                       op->nb, s));
-        HIP_TRY(launch_copy_f32(PS(0), P(it), 2 * J, s));
-        if (lam > 0)
-            for (int i = 1; i <= nt; ++i)
-                HIP_TRY(launch_tv_steps(op->z, PS(i - 1), PS(i), nullptr, op->n, lam, tvstep, 1, s));
+        // PS(i): dual field after inner step i (PS(0) = p^k from the checkpoint)
+        auto PS = [&](int i) -> const float* { return i == 0 ? P(it) : u->ps + (size_t)(i - 1) * 2 * J; };
+        if (lam > 0 && nt > 0) {
+            if (nt <= tv_chunk_max()) {
+                HIP_TRY(launch_tv_steps_store(op->z, P(it), u->ps, op->n, lam, tvstep, nt, s));
+            } else {
+                for (int i = 1; i <= nt; ++i)
+                    HIP_TRY(launch_tv_steps(op->z, PS(i - 1), u->ps + (size_t)(i - 1) * 2 * J, nullptr, op->n, lam,
+                                            tvstep, 1, s));
+            }
+        }
         if ((r = project(op, x1, op->q))) return r;
         HIP_TRY(launch_lin_mix_f32(u->r, op->q, 1.f, b, -1.f, op->winv, mu, -1.f, I, s));
         // mu^{k+1} = mu + sigma D r
@@ -262,23 +273,19 @@ int ctpd_unrolled_lowdose_backward(ctpd_op* op, const float* b, const float* w, 
         HIP_TRY(launch_lin_mix_f32(b_grad, b_grad, 1.f, u->rbar, -1.f, nullptr, nullptr, 0.f, I, s));
         // x^{k+1}, p^{k+1} = prox(z, p^k)
         if (lam > 0) {
-            HIP_TRY(launch_tv_bwd_final(op->z, PS(nt), u->axt, op->n, lam, u->tbar, u->zbar, u->prod, s));
-            if ((r = sum(C_LAM, u->prod, J))) return r;
-            HIP_TRY(launch_tv_bwd_grad(u->ap, u->tbar, op->n, lam, u->pba, s));
-            float *cur = u->pba, *nxt = u->pbb;
+            HIP_TRY(launch_tv_bwd_final(op->z, PS(nt), u->axt, op->n, lam, u->tbar, u->zbar, slot(C_LAM, 1.0), s));
+            // the adjoint of p^{k+1} (u->ap) becomes the first qbar buffer
             for (int i = nt; i >= 1; --i) {
-                HIP_TRY(launch_tv_bwd_proj(op->z, PS(i - 1), cur, op->n, lam, tvstep, u->qbar, u->prod, s));
-                if ((r = sum(C_STEP, u->prod, J))) return r;
-                HIP_TRY(launch_tv_bwd_mask(op->z, PS(i - 1), u->qbar, op->n, lam, tvstep, u->tbar, u->zbar, u->prod,
-                                           s));
-                if ((r = sum(C_LAM, u->prod, J))) return r;
-                HIP_TRY(launch_tv_bwd_grad(u->qbar, u->tbar, op->n, lam, nxt, s));
-                std::swap(cur, nxt);
+                HIP_TRY(launch_tv_bwd_gradproj(op->z, PS(i - 1), u->ap, u->tbar, op->n, lam, tvstep,
+                                               slot(C_STEP, 1.0), s));
+                HIP_TRY(launch_tv_bwd_mask(op->z, PS(i - 1), u->ap, op->n, lam, tvstep, u->tbar, u->zbar,
+                                           slot(C_LAM, 1.0), s));
             }
-            std::swap(u->ap, cur == u->pba ? u->pba : u->pbb);
+            HIP_TRY(launch_tv_bwd_grad(u->ap, u->tbar, op->n, lam, u->pba, s));
+            std::swap(u->ap, u->pba);
         } else {
             // x^{k+1} = max(0, z), p passes through unchanged
-            HIP_TRY(launch_tv_bwd_final(op->z, PS(0), u->axt, op->n, 0.f, u->tbar, u->zbar, u->prod, s));
+            HIP_TRY(launch_tv_bwd_final(op->z, P(it), u->axt, op->n, 0.f, u->tbar, u->zbar, slot(C_LAM, 0.0), s));
         }
         // z = x^k - tau A^T mubar
         if ((r = project(op, u->zbar, u->az))) return r;
@@ -301,12 +308,13 @@ int ctpd_unrolled_lowdose_backward(ctpd_op* op, const float* b, const float* w, 
         std::swap(u->amup, u->amup2);
     }
     const int ns = (int)terms.size();
-    u->slots_host.assign((size_t)3 * ns, 0.0);
-    HIP_TRY(hipMemcpyAsync(u->slots_host.data(), u->slots, sizeof(double) * 3 * ns, hipMemcpyDeviceToHost, s));
+    HIP_TRY(launch_slot_reduce(u->part, u->part_cap, ns, u->sums, s));
+    u->sums_host.assign(ns, 0.0);
+    HIP_TRY(hipMemcpyAsync(u->sums_host.data(), u->sums, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
     if ((r = sync(op))) return r;
     double g_sigma = 0.0, g_tau = 0.0, g_lam = 0.0, g_step = 0.0;
     for (int i = 0; i < ns; ++i) {
-        const double v = terms[i].second * u->slots_host[3 * i];
+        const double v = terms[i].second * u->sums_host[i];
         switch (terms[i].first) {
             case C_SIGMA: g_sigma += v; break;
             case C_TAU: g_tau += v; break;

@@ -265,6 +265,51 @@ hipError_t launch_lin_mix_f32(float* out, const float* a, float c0, const float*
     return hipGetLastError();
 }
 
+// Block partial sums of a . b (float inputs, float64 sums) into partial[0 .. nb),
+// nb = reduce_blocks(len); the rest of a slot is left as it is (zeroed by the caller).
+__global__ __launch_bounds__(256) void dot_partials_kernel(const float* __restrict__ a, const float* __restrict__ b,
+                                                           size_t len, double* __restrict__ partial) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < len; i += stride)
+        s0 = fma((double)a[i], (double)b[i], s0);
+    block_sum3(s0, s1, s2);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s0;
+}
+
+int reduce_blocks_for(size_t len) { return reduce_blocks(len); }
+
+hipError_t launch_dot_partials(const float* a, const float* b, size_t len, double* partial, hipStream_t s) {
+    dot_partials_kernel<<<reduce_blocks(len), 256, 0, s>>>(a, b, len, partial);
+    return hipGetLastError();
+}
+
+// out[k] = sum of partial[k cap .. (k + 1) cap), one workgroup per slot, fixed order.
+__global__ __launch_bounds__(256) void slot_reduce_kernel(const double* __restrict__ partial, int cap,
+                                                          double* __restrict__ out) {
+    const double* p = partial + (size_t)blockIdx.x * cap;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int b = threadIdx.x; b < cap; b += 256) s0 += p[b];
+    block_sum3(s0, s1, s2);
+    if (threadIdx.x == 0) out[blockIdx.x] = s0;
+}
+
+hipError_t launch_slot_reduce(const double* partial, int cap, int nslots, double* out, hipStream_t s) {
+    if (nslots <= 0) return hipSuccess;
+    slot_reduce_kernel<<<nslots, 256, 0, s>>>(partial, cap, out);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void fill_f64_kernel(double* __restrict__ dst, double v, size_t len) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < len) dst[i] = v;
+}
+
+hipError_t launch_fill_f64(double* dst, double v, size_t len, hipStream_t s) {
+    fill_f64_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(dst, v, len);
+    return hipGetLastError();
+}
+
 // out = a .* w with float weights (float64 operator applications)
 __global__ __launch_bounds__(256) void mul_w_kernel(double* __restrict__ out, const double* __restrict__ a,
                                                     const float* __restrict__ w, size_t len) {
