@@ -286,13 +286,15 @@ def batch_speedup(dev, count: int, steps: int, warmup: int) -> int:
 
 def unrolled_speedup(dev, steps: int) -> int:
     """16 independent 256^2 / 180-view problems, 10 unrolled iterations: forward
-    and forward + reverse pass (each problem on its own stream) against 16 plain
-    solves of the same 10 iterations, all at the same fixed step sizes."""
+    and forward + reverse pass (the many-problem calls, each problem on its own
+    stream) against 16 plain solves of the same 10 iterations and against the
+    same forward + reverse passes one problem at a time, all at the same fixed
+    step sizes."""
     import numpy as np
     import torch
 
     from paper_1609_06041_amd import ctpd, synth
-    from paper_1609_06041_amd.unrolled import unrolled_lowdose
+    from paper_1609_06041_amd.unrolled import unrolled_lowdose, unrolled_lowdose_batch
 
     B, n, m, nb, K, beta = 16, 256, 180, 368, 10, 0.005
     log(f"generating {B} seeded 256^2 problems")
@@ -313,26 +315,15 @@ def unrolled_speedup(dev, steps: int) -> int:
             op.lowdose_solve(b, w, beta, K, tau=ta, sigma=si)
 
     def forward():
-        xs = []
-        for op, st, b, w, (ta, si) in zip(ops, streams, bs, ws, steps_):
-            with torch.cuda.stream(st):
-                xs.append(unrolled_lowdose(op, b, w, beta, ta, si, K))
-        return xs
+        return unrolled_lowdose_batch(ops, bs, ws, [beta] * B, [ta for ta, _ in steps_], [si for _, si in steps_], K)
 
     def fwd_bwd():
-        main = torch.cuda.current_stream()
         bts = [b.clone().requires_grad_(True) for b in bs]
         pars = [[torch.tensor(v, dtype=torch.float64, requires_grad=True) for v in (beta, ta, si)]
                 for ta, si in steps_]
-        losses = []
-        for op, st, b, w, xt, (pb, pt, ps) in zip(ops, streams, bts, ws, xts, pars):
-            st.wait_stream(main)
-            with torch.cuda.stream(st):
-                x = unrolled_lowdose(op, b, w, pb, pt, ps, K)
-                losses.append(((x - xt) ** 2).sum())
-        for st in streams:
-            main.wait_stream(st)
-        torch.stack(losses).sum().backward()
+        xs = unrolled_lowdose_batch(ops, bts, ws, [p[0] for p in pars], [p[1] for p in pars], [p[2] for p in pars],
+                                    K)
+        torch.stack([((x - xt) ** 2).sum() for x, xt in zip(xs, xts)]).sum().backward()
         return bts, pars
 
     def timed(fn):

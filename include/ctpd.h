@@ -208,6 +208,24 @@ int ctpd_unrolled_lowdose_backward(ctpd_op* op, const float* b, const float* w, 
                                    double sigma, int32_t iters, const ctpd_params* p, const float* ckpt,
                                    const float* x_grad, float* b_grad, double* grads);
 
+/* The forward / reverse passes of count independent problems in one call
+ * (1 <= count <= CTPD_MAX_BATCH; every pointer array holds count entries,
+ * scalars count doubles, grads 3 * count doubles laid out as (beta, tau,
+ * sigma) per problem).  Each problem runs on its own operator's stream with
+ * the arithmetic of the single calls above; the library synchronises once
+ * for all the kappa reductions before queueing the loops, and the reverse
+ * pass once more at the end for the scalar gradients, so problems on distinct
+ * streams overlap.  The operators must be distinct (CTPD_EINVAL otherwise). */
+int ctpd_unrolled_lowdose_forward_many(int32_t count, ctpd_op* const* ops, const float* const* b,
+                                       const float* const* w, const double* beta, const double* tau,
+                                       const double* sigma, int32_t iters, const ctpd_params* p,
+                                       float* const* ckpt, float* const* x_out);
+int ctpd_unrolled_lowdose_backward_many(int32_t count, ctpd_op* const* ops, const float* const* b,
+                                        const float* const* w, const double* beta, const double* tau,
+                                        const double* sigma, int32_t iters, const ctpd_params* p,
+                                        const float* const* ckpt, const float* const* x_grad, float* const* b_grad,
+                                        double* grads);
+
 /* Tile shapes and workgroup placement of the batched kernels (chosen by an
  * autotuner that times ctpd_batch_time_loop over the candidates). */
 typedef struct {

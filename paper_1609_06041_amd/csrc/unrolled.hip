@@ -9,6 +9,9 @@
 // A^T, D and dD/dtau for themselves (symmetric Toeplitz), and the TV reverse
 // kernels for the prox.  Scalar adjoints are float64 sums gathered into
 // separate device slots and added on the host in a fixed order.
+#include <algorithm>
+#include <vector>
+
 #include "op.h"
 
 using namespace ctpd;
@@ -84,11 +87,15 @@ int ensure_unrolled(ctpd_op* op, int tv_iters, int nslots) {
     return CTPD_OK;
 }
 
-// kappa = mean(1/w) with the validity scan, W^-1 and the taps of D(tau).
-int prepare(ctpd_op* op, const float* b, const float* w, double tau, double* kappa) {
-    int r;
-    if ((r = reduce(op, RED_INVW_CHECK, w, b, nullptr, op->I, 0))) return r;
-    if ((r = read_red(op))) return r;
+// kappa = mean(1/w) with the validity scan (queued; read back after the
+// stream is synchronised), then W^-1 and the taps of D(tau).
+int prepare_begin(ctpd_op* op, const float* b, const float* w) {
+    HIP_TRY(launch_reduce(RED_INVW_CHECK, w, b, nullptr, op->I, op->partials, op->red, op->stream));
+    HIP_TRY(hipMemcpyAsync(op->red_host, op->red, sizeof(double) * 3, hipMemcpyDeviceToHost, op->stream));
+    return CTPD_OK;
+}
+
+int prepare_end(ctpd_op* op, const float* w, double tau, double* kappa) {
     if (op->red_host[1] > 0 || op->red_host[2] > 0) {
         snprintf(g_errmsg, sizeof g_errmsg, "%.0f weights <= 0 or non-finite, %.0f non-finite data",
                  op->red_host[1], op->red_host[2]);
@@ -131,30 +138,19 @@ int filt(ctpd_op* op, const float* taps, const float* in, float c, float* out, c
     return CTPD_OK;
 }
 
-enum Cat { C_SIGMA, C_TAU, C_LAM, C_STEP };
-
-}  // namespace
-
-extern "C" {
-
-int ctpd_unrolled_ckpt_floats(const ctpd_op* op, int32_t iters, size_t* count) {
-    g_errmsg[0] = 0;
-    if (!op || !count) return einval("null pointer");
-    if (iters < 1) return einval("iters must be >= 1");
-    *count = (size_t)(iters + 1) * layout(op).stride;
+// Each problem keeps its set-up readback in its operator, so an operator may
+// appear once per call.
+int check_distinct(ctpd_op* const* ops, int count) {
+    std::vector<ctpd_op*> v(ops, ops + count);
+    std::sort(v.begin(), v.end());
+    if (std::adjacent_find(v.begin(), v.end()) != v.end()) return einval("an operator appears twice");
     return CTPD_OK;
 }
 
-int ctpd_unrolled_lowdose_forward(ctpd_op* op, const float* b, const float* w, double beta, double tau,
-                                  double sigma, int32_t iters, const ctpd_params* p, float* ckpt, float* x_out) {
-    g_errmsg[0] = 0;
-    int r = check_args(op, b, w, beta, tau, sigma, iters);
-    if (r) return r;
-    if (!ckpt || !x_out) return einval("null pointer");
-    Knobs k;
-    if ((r = read_params(p, &k))) return r;
-    double kappa = 0.0;
-    if ((r = prepare(op, b, w, tau, &kappa))) return r;
+// The forward iterations of one problem (after prepare_end), queued on its stream.
+int forward_loop(ctpd_op* op, const float* b, double beta, double tau, double sigma, int iters, const Knobs& k,
+                 float* ckpt, float* x_out) {
+    int r = CTPD_OK;
     const size_t J = op->J;
     const Slots L = layout(op);
     hipStream_t s = op->stream;
@@ -184,20 +180,17 @@ int ctpd_unrolled_lowdose_forward(ctpd_op* op, const float* b, const float* w, d
     return CTPD_OK;
 }
 
-int ctpd_unrolled_lowdose_backward(ctpd_op* op, const float* b, const float* w, double beta, double tau,
-                                   double sigma, int32_t iters, const ctpd_params* p, const float* ckpt,
-                                   const float* x_grad, float* b_grad, double* grads) {
-    g_errmsg[0] = 0;
-    int r = check_args(op, b, w, beta, tau, sigma, iters);
-    if (r) return r;
-    if (!ckpt || !x_grad || !b_grad || !grads) return einval("null pointer");
-    Knobs k;
-    if ((r = read_params(p, &k))) return r;
+enum Cat { C_SIGMA, C_TAU, C_LAM, C_STEP };
+
+// The reverse pass of one problem (after prepare_end), queued on its stream,
+// ending with the copy of the scalar terms to the host (terms: their
+// categories and factors, to be combined by combine_terms after a sync).
+int backward_queue(ctpd_op* op, const float* b, double beta, double tau, double sigma, double kappa, int iters,
+                   const Knobs& k, const float* ckpt, const float* x_grad, float* b_grad,
+                   std::vector<std::pair<int, double>>& terms) {
+    int r = CTPD_OK;
     const int nt = k.tv_iters;
     const int per_iter = 2 * nt + 6;
-    if ((r = ensure_unrolled(op, nt, iters * per_iter))) return r;
-    double kappa = 0.0;
-    if ((r = prepare(op, b, w, tau, &kappa))) return r;
     UnrolledWs* u = op->uw;
     if (u->dtap_tau != tau || u->dtap_kappa != kappa) {
         HIP_TRY(launch_taps(u->dtaps64, u->dtaps32, op->nb, op->m, tau, kappa, op->stream, true));
@@ -217,7 +210,7 @@ int ctpd_unrolled_lowdose_backward(ctpd_op* op, const float* b, const float* w, 
     // Scalar-adjoint terms: every term gets a slot of part_cap block sums
     // (written by the kernels that produce it), reduced once at the end and
     // added up on the host by category in a fixed order.
-    std::vector<std::pair<int, double>> terms;
+    terms.clear();
     auto slot = [&](int cat, double factor) -> double* {
         terms.emplace_back(cat, factor);
         return u->part + (size_t)(terms.size() - 1) * u->part_cap;
@@ -311,9 +304,14 @@ int ctpd_unrolled_lowdose_backward(ctpd_op* op, const float* b, const float* w, 
     HIP_TRY(launch_slot_reduce(u->part, u->part_cap, ns, u->sums, s));
     u->sums_host.assign(ns, 0.0);
     HIP_TRY(hipMemcpyAsync(u->sums_host.data(), u->sums, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
-    if ((r = sync(op))) return r;
+    return CTPD_OK;
+}
+
+// d/dbeta, d/dtau, d/dsigma from the scalar terms (after the sync).
+void combine_terms(const UnrolledWs* u, const std::vector<std::pair<int, double>>& terms, double beta, double tau,
+                   double tv_step, double* grads) {
     double g_sigma = 0.0, g_tau = 0.0, g_lam = 0.0, g_step = 0.0;
-    for (int i = 0; i < ns; ++i) {
+    for (size_t i = 0; i < terms.size(); ++i) {
         const double v = terms[i].second * u->sums_host[i];
         switch (terms[i].first) {
             case C_SIGMA: g_sigma += v; break;
@@ -322,11 +320,106 @@ int ctpd_unrolled_lowdose_backward(ctpd_op* op, const float* b, const float* w, 
             default: g_step += v; break;
         }
     }
-    if (lam > 0) g_lam += g_step * (-k.tv_step / ((tau * beta) * (tau * beta)));
+    if (tau * beta > 0) g_lam += g_step * (-tv_step / ((tau * beta) * (tau * beta)));
     grads[0] = tau * g_lam;            // d/dbeta  (lam = tau beta)
     grads[1] = g_tau + beta * g_lam;   // d/dtau
     grads[2] = g_sigma;                // d/dsigma
+}
+
+
+}  // namespace
+
+extern "C" {
+
+int ctpd_unrolled_ckpt_floats(const ctpd_op* op, int32_t iters, size_t* count) {
+    g_errmsg[0] = 0;
+    if (!op || !count) return einval("null pointer");
+    if (iters < 1) return einval("iters must be >= 1");
+    *count = (size_t)(iters + 1) * layout(op).stride;
     return CTPD_OK;
+}
+
+int ctpd_unrolled_lowdose_forward_many(int32_t count, ctpd_op* const* ops, const float* const* b,
+                                       const float* const* w, const double* beta, const double* tau,
+                                       const double* sigma, int32_t iters, const ctpd_params* p,
+                                       float* const* ckpt, float* const* x_out) {
+    g_errmsg[0] = 0;
+    if (count < 1 || count > CTPD_MAX_BATCH) return einval("count must be in 1..CTPD_MAX_BATCH");
+    if (!ops || !b || !w || !beta || !tau || !sigma || !ckpt || !x_out) return einval("null pointer");
+    int r;
+    if ((r = check_distinct(ops, count))) return r;
+    for (int i = 0; i < count; ++i) {
+        if ((r = check_args(ops[i], b[i], w[i], beta[i], tau[i], sigma[i], iters))) return r;
+        if (!ckpt[i] || !x_out[i]) return einval("null pointer");
+    }
+    Knobs k;
+    if ((r = read_params(p, &k))) return r;
+    for (int i = 0; i < count; ++i)
+        if ((r = prepare_begin(ops[i], b[i], w[i]))) return r;
+    for (int i = 0; i < count; ++i) {
+        if ((r = sync(ops[i]))) return r;
+        double kappa = 0.0;
+        if ((r = prepare_end(ops[i], w[i], tau[i], &kappa))) return r;
+        if ((r = forward_loop(ops[i], b[i], beta[i], tau[i], sigma[i], iters, k, ckpt[i], x_out[i]))) return r;
+    }
+    return CTPD_OK;
+}
+
+int ctpd_unrolled_lowdose_forward(ctpd_op* op, const float* b, const float* w, double beta, double tau,
+                                  double sigma, int32_t iters, const ctpd_params* p, float* ckpt, float* x_out) {
+    return ctpd_unrolled_lowdose_forward_many(1, &op, &b, &w, &beta, &tau, &sigma, iters, p, &ckpt, &x_out);
+}
+
+int ctpd_unrolled_lowdose_backward_many(int32_t count, ctpd_op* const* ops, const float* const* b,
+                                        const float* const* w, const double* beta, const double* tau,
+                                        const double* sigma, int32_t iters, const ctpd_params* p,
+                                        const float* const* ckpt, const float* const* x_grad, float* const* b_grad,
+                                        double* grads) {
+    g_errmsg[0] = 0;
+    if (count < 1 || count > CTPD_MAX_BATCH) return einval("count must be in 1..CTPD_MAX_BATCH");
+    if (!ops || !b || !w || !beta || !tau || !sigma || !ckpt || !x_grad || !b_grad || !grads)
+        return einval("null pointer");
+    int r;
+    if ((r = check_distinct(ops, count))) return r;
+    for (int i = 0; i < count; ++i) {
+        if ((r = check_args(ops[i], b[i], w[i], beta[i], tau[i], sigma[i], iters))) return r;
+        if (!ckpt[i] || !x_grad[i] || !b_grad[i]) return einval("null pointer");
+    }
+    Knobs k;
+    if ((r = read_params(p, &k))) return r;
+    const int per_iter = 2 * k.tv_iters + 6;
+    for (int i = 0; i < count; ++i) {
+        if ((r = ensure_unrolled(ops[i], k.tv_iters, iters * per_iter))) return r;
+        if ((r = prepare_begin(ops[i], b[i], w[i]))) return r;
+    }
+    std::vector<std::vector<std::pair<int, double>>> terms(count);
+    for (int i = 0; i < count; ++i) {
+        ctpd_op* op = ops[i];
+        if ((r = sync(op))) return r;
+        double kappa = 0.0;
+        if ((r = prepare_end(op, w[i], tau[i], &kappa))) return r;
+        UnrolledWs* u = op->uw;
+        if (u->dtap_tau != tau[i] || u->dtap_kappa != kappa) {
+            HIP_TRY(launch_taps(u->dtaps64, u->dtaps32, op->nb, op->m, tau[i], kappa, op->stream, true));
+            u->dtap_tau = tau[i];
+            u->dtap_kappa = kappa;
+        }
+        if ((r = backward_queue(op, b[i], beta[i], tau[i], sigma[i], kappa, iters, k, ckpt[i], x_grad[i], b_grad[i],
+                                terms[i])))
+            return r;
+    }
+    for (int i = 0; i < count; ++i) {
+        if ((r = sync(ops[i]))) return r;
+        combine_terms(ops[i]->uw, terms[i], beta[i], tau[i], k.tv_step, grads + 3 * i);
+    }
+    return CTPD_OK;
+}
+
+int ctpd_unrolled_lowdose_backward(ctpd_op* op, const float* b, const float* w, double beta, double tau,
+                                   double sigma, int32_t iters, const ctpd_params* p, const float* ckpt,
+                                   const float* x_grad, float* b_grad, double* grads) {
+    return ctpd_unrolled_lowdose_backward_many(1, &op, &b, &w, &beta, &tau, &sigma, iters, p, &ckpt, &x_grad,
+                                               &b_grad, grads);
 }
 
 }  // extern "C"

@@ -44,6 +44,12 @@ _SIGNATURES = {
                                               c_void_p, c_void_p, c_void_p]),
     "ctpd_unrolled_lowdose_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double, c_double, c_int32,
                                                c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double)]),
+    "ctpd_unrolled_lowdose_forward_many": (c_int, [c_int32, c_void_p, c_void_p, c_void_p, POINTER(c_double),
+                                                   POINTER(c_double), POINTER(c_double), c_int32, c_void_p, c_void_p,
+                                                   c_void_p]),
+    "ctpd_unrolled_lowdose_backward_many": (c_int, [c_int32, c_void_p, c_void_p, c_void_p, POINTER(c_double),
+                                                    POINTER(c_double), POINTER(c_double), c_int32, c_void_p,
+                                                    c_void_p, c_void_p, c_void_p, POINTER(c_double)]),
     "ctpd_batch_set_tiles": (c_int, [c_void_p, c_void_p]),
     "ctpd_batch_get_tiles": (c_int, [c_void_p, c_void_p]),
     "ctpd_batch_time_loop": (c_int, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_double)]),
@@ -308,6 +314,63 @@ class Operator:
                                                      _ptr(x_grad, (self.n, self.n), "x_grad"),
                                                      _ptr(b_grad, (self.m, self.nb), "b_grad"), g))
         return b_grad, (g[0], g[1], g[2])
+
+
+def _ptr_array(ptrs):
+    return (c_void_p * len(ptrs))(*[p.value for p in ptrs])
+
+
+def _f64_array(vals):
+    return (c_double * len(vals))(*[float(v) for v in vals])
+
+
+def _check_ckpt(op: "Operator", ckpt: torch.Tensor, iters: int) -> c_void_p:
+    if ckpt.dtype != torch.float32 or ckpt.numel() < op.ckpt_floats(iters) or not ckpt.is_contiguous():
+        raise ValueError("checkpoint buffer too small or not contiguous float32")
+    return c_void_p(ckpt.data_ptr())
+
+
+def unrolled_forward_many(ops, bs, ws, betas, taus, sigmas, iters, ckpts, *, tv_iters=10, tv_step=0.125,
+                          outs=None):
+    """The unrolled forward pass of several independent problems in one call,
+    each on its operator's stream (the library synchronises once for all the
+    kappa reductions, then queues every loop).  Returns the list of x."""
+    P = len(ops)
+    if not (len(bs) == len(ws) == len(betas) == len(taus) == len(sigmas) == len(ckpts) == P) or P == 0:
+        raise ValueError("one b, w, beta, tau, sigma and checkpoint buffer per operator")
+    outs = [op._img() for op in ops] if outs is None else outs
+    prm = _params(None, None, tv_iters, tv_step, None, None, False)
+    _check(load().ctpd_unrolled_lowdose_forward_many(
+        P, _ptr_array([op._h for op in ops]),
+        _ptr_array([_ptr(b, (op.m, op.nb), "b") for op, b in zip(ops, bs)]),
+        _ptr_array([_ptr(w, (op.m, op.nb), "w") for op, w in zip(ops, ws)]),
+        _f64_array(betas), _f64_array(taus), _f64_array(sigmas), int(iters), byref(prm),
+        _ptr_array([_check_ckpt(op, c, iters) for op, c in zip(ops, ckpts)]),
+        _ptr_array([_ptr(x, (op.n, op.n), "out") for op, x in zip(ops, outs)])))
+    return outs
+
+
+def unrolled_backward_many(ops, bs, ws, betas, taus, sigmas, iters, ckpts, x_grads, *, tv_iters=10,
+                           tv_step=0.125, b_grads=None):
+    """The reverse passes of several independent problems in one call (one
+    host synchronisation at the end for all the scalar gradients).  Returns
+    (list of dL/db, list of (dL/dbeta, dL/dtau, dL/dsigma))."""
+    P = len(ops)
+    if not (len(bs) == len(ws) == len(betas) == len(taus) == len(sigmas) == len(ckpts) == len(x_grads) == P) \
+            or P == 0:
+        raise ValueError("one b, w, beta, tau, sigma, checkpoint buffer and x gradient per operator")
+    b_grads = [op._sino() for op in ops] if b_grads is None else b_grads
+    prm = _params(None, None, tv_iters, tv_step, None, None, False)
+    g = (c_double * (3 * P))()
+    _check(load().ctpd_unrolled_lowdose_backward_many(
+        P, _ptr_array([op._h for op in ops]),
+        _ptr_array([_ptr(b, (op.m, op.nb), "b") for op, b in zip(ops, bs)]),
+        _ptr_array([_ptr(w, (op.m, op.nb), "w") for op, w in zip(ops, ws)]),
+        _f64_array(betas), _f64_array(taus), _f64_array(sigmas), int(iters), byref(prm),
+        _ptr_array([_check_ckpt(op, c, iters) for op, c in zip(ops, ckpts)]),
+        _ptr_array([_ptr(x, (op.n, op.n), "x_grad") for op, x in zip(ops, x_grads)]),
+        _ptr_array([_ptr(x, (op.m, op.nb), "b_grad") for op, x in zip(ops, b_grads)]), g))
+    return b_grads, [(g[3 * i], g[3 * i + 1], g[3 * i + 2]) for i in range(P)]
 
 
 class Batch:

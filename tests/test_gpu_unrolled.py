@@ -3,6 +3,9 @@ solver, and the GPU reverse pass against float64 central differences of the
 oracle's unrolled solve (h = 1e-6 relative for the scalars, 1e-6 along unit
 sinogram directions), on 32 x 32 instances away from kinks.
 
+The many-problem calls (several problems, one operator and stream each) give
+the single calls' results bit for bit.
+
 Bars: forward x^K bit-identical to ``ctpd_pd_lowdose_solve`` at the same step
 sizes; gradients (d/dbeta, d/dtau, d/dsigma and <dL/db, v> for random v)
 within 1e-3 relative of the finite differences -- float32 forward and reverse
@@ -83,3 +86,49 @@ def test_backward_rejects_bad_arguments(gpu):
         assert e.value.code == ctpd.CTPD_EINVAL
         with pytest.raises(ValueError):
             op.unrolled_forward(dev(b), dev(w), 0.1, 0.1, 0.5, 3, ck)   # buffer sized for 2 iterations
+
+
+def test_many_problem_calls_equal_single_calls(gpu):
+    # three uneven problems on their own streams through the many-problem
+    # calls: every output bit-identical to the single calls
+    from paper_1609_06041_amd.unrolled import unrolled_lowdose_batch
+    geoms = [(32, 24, 48), (40, 17, 61), (24, 30, 40)]
+    iters, betas = 4, [0.02, 0.0, 0.05]
+    data = [_instance(10 + i, *g) for i, g in enumerate(geoms)]
+    steps = [OA.steps_lowdose(w, g[0]) for g, (_, _, w) in zip(geoms, data)]
+    streams = [torch.cuda.Stream() for _ in geoms]
+    ops = [ctpd.Operator(*g, stream=s) for g, s in zip(geoms, streams)]
+    try:
+        ref = []
+        for op, (xt, b, w), st, beta in zip(ops, data, steps, betas):
+            bt = dev(b).requires_grad_(True)
+            pars = [torch.tensor(v, dtype=torch.float64, requires_grad=True) for v in (beta, st.tau, st.sigma)]
+            op.stream.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(op.stream):
+                x = unrolled_lowdose(op, bt, dev(w), *pars, iters)
+                ((x - dev(xt)) ** 2).sum().backward()
+            torch.cuda.synchronize()
+            ref.append((host(x), host(bt.grad), [float(p.grad) for p in pars]))
+        bts = [dev(b).requires_grad_(True) for _, b, _ in data]
+        pars = [[torch.tensor(v, dtype=torch.float64, requires_grad=True) for v in (beta, st.tau, st.sigma)]
+                for beta, st in zip(betas, steps)]
+        xs = unrolled_lowdose_batch(ops, bts, [dev(w) for _, _, w in data], [p[0] for p in pars],
+                                    [p[1] for p in pars], [p[2] for p in pars], iters)
+        sum(((x - dev(xt)) ** 2).sum() for x, (xt, _, _) in zip(xs, data)).backward()
+        for i, (x_r, gb_r, gs_r) in enumerate(ref):
+            np.testing.assert_array_equal(host(xs[i]), x_r)
+            np.testing.assert_array_equal(host(bts[i].grad), gb_r)
+            assert [float(p.grad) for p in pars[i]] == gs_r
+    finally:
+        for op in ops:
+            op.close()
+
+
+def test_many_problem_calls_reject_a_repeated_operator(gpu):
+    n, m, nb = 16, 8, 24
+    _, b, w = _instance(6, n, m, nb)
+    with ctpd.Operator(n, m, nb) as op:
+        cks = [torch.empty(op.ckpt_floats(2), device="cuda") for _ in range(2)]
+        with pytest.raises(ctpd.CtpdError) as e:
+            ctpd.unrolled_forward_many([op, op], [dev(b)] * 2, [dev(w)] * 2, [0.1] * 2, [0.1] * 2, [0.5] * 2, 2, cks)
+        assert e.value.code == ctpd.CTPD_EINVAL
