@@ -211,11 +211,14 @@ int ctpd_unrolled_lowdose_backward(ctpd_op* op, const float* b, const float* w, 
 /* The forward / reverse passes of count independent problems in one call
  * (1 <= count <= CTPD_MAX_BATCH; every pointer array holds count entries,
  * scalars count doubles, grads 3 * count doubles laid out as (beta, tau,
- * sigma) per problem).  Each problem runs on its own operator's stream with
- * the arithmetic of the single calls above; the library synchronises once
- * for all the kappa reductions before queueing the loops, and the reverse
- * pass once more at the end for the scalar gradients, so problems on distinct
- * streams overlap.  The operators must be distinct (CTPD_EINVAL otherwise). */
+ * sigma) per problem), with the arithmetic of the single calls above (which
+ * are this call with count = 1).  The whole call runs on the first operator's
+ * stream: every problem's pass is recorded as a list of kernel steps and each
+ * step runs as one launch over all the problems, so small problems fill the
+ * GPU together.  The call first synchronises the other operators' streams and
+ * then once more for all the kappa reductions; the reverse pass synchronises
+ * again at the end for the scalar gradients.  The operators must be distinct
+ * (CTPD_EINVAL otherwise). */
 int ctpd_unrolled_lowdose_forward_many(int32_t count, ctpd_op* const* ops, const float* const* b,
                                        const float* const* w, const double* beta, const double* tau,
                                        const double* sigma, int32_t iters, const ctpd_params* p,

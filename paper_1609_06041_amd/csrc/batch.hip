@@ -20,11 +20,47 @@ using namespace ctpd_host;
 
 namespace {
 
-constexpr int kXcds = 8;
-
 enum Kind { K_INIT, K_FILT, K_ADJ, K_TV, K_PAD, K_FWD, K_COPY, K_COUNT };
 
 }  // namespace
+
+namespace ctpd_host {
+
+Placement plan_xcds(const std::vector<double>& work) {
+    const int P = (int)work.size();
+    Placement pl;
+    pl.order.resize(P);
+    std::iota(pl.order.begin(), pl.order.end(), 0);
+    std::stable_sort(pl.order.begin(), pl.order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    std::vector<double> load(kXcds, 0.0);
+    pl.xcd.assign(P, 0);
+    for (int p : pl.order) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        pl.xcd[p] = x;
+        load[x] += work[p];
+    }
+    return pl;
+}
+
+std::vector<BlockRef> place_blocks(const Placement& pl, const std::vector<int>& counts, int placement) {
+    std::vector<BlockRef> flat;
+    if (placement == 0) {   // XCD-binned
+        std::vector<std::vector<BlockRef>> bins(kXcds);
+        for (int p : pl.order)
+            for (int l = 0; l < counts[p]; ++l) bins[pl.xcd[p]].push_back(BlockRef{p, l});
+        size_t len = 0;
+        for (auto& b : bins) len = std::max(len, b.size());
+        flat.assign(len * kXcds, BlockRef{-1, 0});
+        for (int x = 0; x < kXcds; ++x)
+            for (size_t i = 0; i < bins[x].size(); ++i) flat[i * kXcds + x] = bins[x][i];
+    } else {   // problem-major, largest first: consecutive workgroups of a problem spread over all XCDs
+        for (int p : pl.order)
+            for (int l = 0; l < counts[p]; ++l) flat.push_back(BlockRef{p, l});
+    }
+    return flat;
+}
+
+}  // namespace ctpd_host
 
 struct ctpd_batch {
     int count = 0;
@@ -69,37 +105,14 @@ int blocks_of(const ctpd_op* op, int kind) {
 
 int build_maps(ctpd_batch* bt) {
     const int P = bt->count;
-    // XCD assignment: longest processing time first
-    std::vector<int> order(P);
-    std::iota(order.begin(), order.end(), 0);
-    auto work = [&](int p) { return (double)bt->ops[p]->m * bt->ops[p]->n * bt->ops[p]->n; };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
-    std::vector<double> load(kXcds, 0.0);
-    bt->xcd.assign(P, 0);
-    for (int p : order) {
-        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        bt->xcd[p] = x;
-        load[x] += work(p);
-    }
+    std::vector<double> work(P);
+    for (int p = 0; p < P; ++p) work[p] = (double)bt->ops[p]->m * bt->ops[p]->n * bt->ops[p]->n;
+    const Placement pl = plan_xcds(work);
+    bt->xcd = pl.xcd;
     for (int kind = 0; kind < K_COUNT; ++kind) {
-        std::vector<BlockRef> flat;
-        if (bt->tiles.placement == 0) {   // XCD-binned
-            std::vector<std::vector<BlockRef>> bins(kXcds);
-            for (int p : order) {
-                const int nb = blocks_of(bt->ops[p], kind);
-                for (int l = 0; l < nb; ++l) bins[bt->xcd[p]].push_back(BlockRef{p, l});
-            }
-            size_t len = 0;
-            for (auto& b : bins) len = std::max(len, b.size());
-            flat.assign(len * kXcds, BlockRef{-1, 0});
-            for (int x = 0; x < kXcds; ++x)
-                for (size_t i = 0; i < bins[x].size(); ++i) flat[i * kXcds + x] = bins[x][i];
-        } else {   // problem-major, largest first: consecutive workgroups of a problem spread over all XCDs
-            for (int p : order) {
-                const int nb = blocks_of(bt->ops[p], kind);
-                for (int l = 0; l < nb; ++l) flat.push_back(BlockRef{p, l});
-            }
-        }
+        std::vector<int> counts(P);
+        for (int p = 0; p < P; ++p) counts[p] = blocks_of(bt->ops[p], kind);
+        const std::vector<BlockRef> flat = place_blocks(pl, counts, bt->tiles.placement);
         if (bt->map[kind]) (void)hipFree(bt->map[kind]);
         bt->map[kind] = nullptr;
         ALLOC(bt->map[kind], flat.size());

@@ -301,6 +301,31 @@ hipError_t launch_filter_batched(const BatchItem* items, const BlockRef* map, in
     return hipGetLastError();
 }
 
+// One recorded filter step per problem (the unrolled passes).
+template <int MODE>
+__global__ __launch_bounds__(256) void step_filter_kernel(const UStep* __restrict__ steps,
+                                                          const BlockRef* __restrict__ map) {
+    extern __shared__ float smem[];
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const UStep& st = steps[e.prob];
+    if (!st.active) return;
+    const int gx = (st.nb + FBN - 1) / FBN;
+    filter_body<MODE>(st.fa, st.taps, st.m, st.nb, smem, e.local % gx, e.local / gx);
+}
+
+hipError_t launch_step_filter(const UStep* steps, const BlockRef* map, int nblocks, int mode, int max_nb,
+                              hipStream_t s) {
+    const size_t lds = filter_lds_bytes(max_nb);
+    switch (mode) {
+        case FILT_EXTRAP: step_filter_kernel<FILT_EXTRAP><<<nblocks, 256, lds, s>>>(steps, map); break;
+        case FILT_DUAL_LD: step_filter_kernel<FILT_DUAL_LD><<<nblocks, 256, lds, s>>>(steps, map); break;
+        case FILT_DUAL_FV: step_filter_kernel<FILT_DUAL_FV><<<nblocks, 256, lds, s>>>(steps, map); break;
+        default: step_filter_kernel<FILT_PLAIN><<<nblocks, 256, lds, s>>>(steps, map); break;
+    }
+    return hipGetLastError();
+}
+
 // filter work decomposition (for batched block maps)
 int filter_blocks_x(int nb) { return (nb + FBN - 1) / FBN; }
 int filter_blocks_y(int m) { return (m + FBM - 1) / FBM; }

@@ -103,6 +103,53 @@ struct BlockRef {
     int prob, local;
 };
 
+// One launch of a recorded schedule for one problem (the unrolled passes):
+// the step kernels read entry [prob] of a table of these through the block
+// map of the step's map class, so one launch serves every problem of a call.
+// active == 0 makes the problem skip the launch (the TV steps of a problem
+// with beta = 0).  The fields each kind reads:
+enum StepKind : int {
+    SK_FILTER,     // out = fa (FilterArgs, mode fa.mode) with taps over m x nb
+    SK_ADJOINT,    // out[0] = in[1] + c0 A^T in[0]
+    SK_PAD,        // pad planes of in[0] into out[0] (x), out[1] (x^T)
+    SK_FORWARD,    // out[0] = A x from the planes in[0], in[1]
+    SK_TV,         // `steps` dual steps on in[1] (z = in[0]) into out[0]; out[1] (if set) = x;
+                   // out[2] (if set) = every step's field; lam == 0: out[1] = max(0, z) only
+    SK_BWD_FINAL,     // reverse of x = max(0, z - lam div p): in z, p, xbar; out tbar, zbar
+    SK_BWD_GRADPROJ,  // reverse dual step, first half: in z, p_prev, tn; out[0] = qn (in place)
+    SK_BWD_MASK,      // reverse dual step, second half: in z, p_prev, qbar; out tbar, zbar (+=)
+    SK_BWD_GRAD,      // out[0] = in[0] + lam grad in[1]
+    SK_LIN3,       // out[0] = (c0 in[0] + c1 in[1] + c2 in[2]) .* in[3]   (null operands skipped)
+    SK_LINMIX,     // out[0] = c0 in[0] + c1 in[1] + c2 (in[2] .* in[3])
+    SK_COPY,       // out[0] = in[0]
+    SK_FILL,       // out[0] = c0
+    SK_INV,        // out[0] = 1 / in[0]
+    SK_DOT,        // part[block] = partial sums of in[0] . in[1] over reduce_blocks_for(len) blocks
+    SK_FILL64,     // part[0 .. len) = 0
+    SK_SLOTS,      // dout[k] = sum of part[k steps .. (k + 1) steps), k < len  (steps = the slot width)
+};
+struct UStep {
+    int kind, active;
+    int n, m, nb, steps;
+    size_t len;
+    float lam, step, c0, c1, c2;
+    const float* in[4];
+    float* out[3];
+    double* part;
+    double* dout;
+    const ViewGeom* views;
+    const float* taps;
+    FilterArgs fa;
+};
+// Step launchers: one launch of kind `kind` over the table entries
+// steps[0 .. P) (one per problem), nblocks workgroups described by map.
+// max_nb sizes the filter's LDS.
+hipError_t launch_step_filter(const UStep* steps, const BlockRef* map, int nblocks, int mode, int max_nb,
+                              hipStream_t s);
+hipError_t launch_step_projector(int kind, const UStep* steps, const BlockRef* map, int nblocks, hipStream_t s);
+hipError_t launch_step_tv(int kind, const UStep* steps, const BlockRef* map, int nblocks, hipStream_t s);
+hipError_t launch_step_vec(int kind, const UStep* steps, const BlockRef* map, int nblocks, hipStream_t s);
+
 // ---- projector.hip -------------------------------------------------------
 // xp / xTp: [n][n+6] row-major copies of x and its transpose with three zero
 // pixels on each side of every row
@@ -167,25 +214,9 @@ hipError_t launch_tv_prox_batched(const BatchItem* items, const BlockRef* map, i
                                   bool last, int threads, hipStream_t s);
 int tv_tiles(int n);      // TV tiles per image side
 int tv_chunk_max();       // dual steps per TV launch at most
-// steps (<= tv_chunk_max()) dual steps from p_in into p_out without touching
-// p_in; x = max(0, z - lam div p_out) written when x is not null.
-hipError_t launch_tv_steps(const float* z, const float* p_in, float* p_out, float* x, int n, float lam, float step,
-                           int steps, hipStream_t s);
-// the steps (<= tv_chunk_max()) from p_in, every intermediate dual field stored:
-// step t's at ps + (t - 1) 2 n^2
-hipError_t launch_tv_steps_store(const float* z, const float* p_in, float* ps, int n, float lam, float step,
-                                 int steps, hipStream_t s);
-// Reverse pass of the TV prox (tv.hip).  Each kernel writes one block sum of
-// its scalar-adjoint term per workgroup to partial[0 .. tv_bwd_blocks(n)).
+// Reverse pass of the prox: one workgroup per 64 x 4 pixels, tv_bwd_blocks(n)
+// per image (each writes one block sum of its scalar-adjoint term).
 int tv_bwd_blocks(int n);
-hipError_t launch_tv_bwd_final(const float* z, const float* p, const float* xbar, int n, float lam, float* tbar,
-                               float* zbar, double* partial, hipStream_t s);
-hipError_t launch_tv_bwd_gradproj(const float* z, const float* p_prev, float* qn, const float* tn, int n, float lam,
-                                  float step, double* partial, hipStream_t s);
-hipError_t launch_tv_bwd_mask(const float* z, const float* p_prev, const float* qbar, int n, float lam, float step,
-                              float* tbar, float* zbar, double* partial, hipStream_t s);
-hipError_t launch_tv_bwd_grad(const float* qbar, const float* tbar, int n, float lam, float* pbar,
-                              hipStream_t s);
 hipError_t launch_tv_finalize(const float* z, const float* p, float* x, int n, float lam, hipStream_t s);
 
 // ---- vec.hip -------------------------------------------------------------
@@ -222,12 +253,9 @@ hipError_t launch_axpby_f64(double* y, const double* x, double a, double b, cons
                             size_t len, hipStream_t s);
 // y = a*x (double)
 hipError_t launch_scale_f64(double* y, const double* x, double a, size_t len, hipStream_t s);
-// out[i] = f(x[i]): inverse (1/x) or sqrt(1/x)   (float in, float / double out)
+// out = (c0 a + c1 b + c2 c) .* w   (b, c, w may be null; out may alias a, b or c)
 hipError_t launch_lin3_f32(float* out, const float* a, float c0, const float* b, float c1, const float* c, float c2,
                            const float* w, size_t len, hipStream_t s);
-// out = c0 a + c1 b + c2 (c .* d)   (b, c may be null; d null = ones; out may alias a or b)
-hipError_t launch_lin_mix_f32(float* out, const float* a, float c0, const float* b, float c1, const float* c,
-                              const float* d, float c2, size_t len, hipStream_t s);
 hipError_t launch_mul_w_f64(double* out, const double* a, const float* w, size_t len, hipStream_t s);
 // batched solve: zero x, p[0], mu[0], mu[1] of every problem / copy x to x_out
 // (2048 elements per workgroup)
@@ -238,12 +266,9 @@ hipError_t launch_rows_start(const NormItem* it, const RowRef* rows, int nrows, 
 hipError_t launch_rows_step(const NormItem* it, const RowRef* rows, int nrows, int rot, int j, hipStream_t s);
 hipError_t launch_rows_ritz(const NormItem* it, const RowRef* rows, int nrows, int count, int steps, double tol,
                             hipStream_t s);
-// per-block float64 partial sums of a . b into partial[0 .. reduce_blocks_for(len));
-// slot sums: out[k] = sum(partial[k cap .. (k+1) cap)); fill for float64 buffers
-hipError_t launch_dot_partials(const float* a, const float* b, size_t len, double* partial, hipStream_t s);
-hipError_t launch_slot_reduce(const double* partial, int cap, int nslots, double* out, hipStream_t s);
-hipError_t launch_fill_f64(double* dst, double v, size_t len, hipStream_t s);
+// workgroups of a float64 reduction over len elements
 int reduce_blocks_for(size_t len);
+// out[i] = 1/w[i] (float) or sqrt(1/w[i]) (double), computed in float64
 hipError_t launch_inverse_f32(float* out, const float* w, size_t len, hipStream_t s);
 hipError_t launch_rsqrt_f64(double* out, const float* w, size_t len, hipStream_t s);
 hipError_t launch_copy_f32(float* dst, const float* src, size_t len, hipStream_t s);

@@ -225,4 +225,16 @@ int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, cons
                    double* lam, int* steps);
 void lowdose_setup_end(ctpd_op* op, const Knobs& k, LowdoseSetup* S);
 
+// Workgroup placement of batched launches: problems go to XCDs by work
+// (largest first onto the least-loaded XCD); placement 0 interleaves the XCD
+// bins so that consecutive workgroups of a problem land on its own XCD (each
+// XCD has its own L2), placement 1 lays the problems out one after another,
+// largest first.  counts[p]: workgroups of problem p in the launch.
+constexpr int kXcds = 8;
+struct Placement {
+    std::vector<int> order, xcd;
+};
+Placement plan_xcds(const std::vector<double>& work);
+std::vector<ctpd::BlockRef> place_blocks(const Placement& pl, const std::vector<int>& counts, int placement);
+
 }  // namespace ctpd_host

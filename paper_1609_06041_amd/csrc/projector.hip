@@ -434,6 +434,48 @@ hipError_t launch_adjoint_batched(const BatchItem* items, const BlockRef* map, i
     return hipGetLastError();
 }
 
+// Recorded steps (one table entry per problem): pad planes, A, A^T.
+__global__ __launch_bounds__(256) void step_pad_kernel(const UStep* __restrict__ steps,
+                                                       const BlockRef* __restrict__ map) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const UStep& st = steps[e.prob];
+    if (!st.active) return;
+    const int gx = (st.n + 31) / 32;
+    pad_planes_body<float>(st.in[0], st.out[0], st.out[1], st.n, e.local % gx, e.local / gx);
+}
+
+__global__ __launch_bounds__(256) void step_forward_kernel(const UStep* __restrict__ steps,
+                                                           const BlockRef* __restrict__ map) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const UStep& st = steps[e.prob];
+    if (!st.active) return;
+    const int gx = (st.nb + 255) / 256;
+    forward_body<float>(st.in[0], st.in[1], st.out[0], st.views, st.n, st.nb, e.local % gx, e.local / gx);
+}
+
+__global__ __launch_bounds__(512) void step_adjoint_kernel(const UStep* __restrict__ steps,
+                                                           const BlockRef* __restrict__ map) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const UStep& st = steps[e.prob];
+    if (!st.active) return;
+    const int gx = (st.n + AT_T - 1) / AT_T;
+    adjoint_body<float, false>(st.in[0], nullptr, 1.f, 0.f, st.in[1], 1.f, st.c0, st.out[0], st.views, st.n, st.m,
+                               st.nb, e.local % gx, e.local / gx);
+}
+
+hipError_t launch_step_projector(int kind, const UStep* steps, const BlockRef* map, int nblocks, hipStream_t s) {
+    switch (kind) {
+        case SK_PAD: step_pad_kernel<<<nblocks, 256, 0, s>>>(steps, map); break;
+        case SK_FORWARD: step_forward_kernel<<<nblocks, 256, 0, s>>>(steps, map); break;
+        case SK_ADJOINT: step_adjoint_kernel<<<nblocks, 512, 0, s>>>(steps, map); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 int adjoint_tiles(int n) { return (n + AT_T - 1) / AT_T; }
 int pad_tiles(int n) { return (n + 31) / 32; }
 int forward_blocks_x(int nb) { return (nb + 255) / 256; }

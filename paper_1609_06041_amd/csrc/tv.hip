@@ -205,31 +205,6 @@ hipError_t launch_grad_ball(const float* xb, float* p, int n, float sg, hipStrea
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kTvThreads) void tv_steps_store_kernel(const float* __restrict__ z,
-                                                                    const float* __restrict__ p_in,
-                                                                    float* __restrict__ ps, int n, float lam,
-                                                                    float step, int steps) {
-    // final p of the launch goes to the last stored slot as well
-    tv_prox_body<kTvThreads>(z, p_in, ps + (size_t)(steps - 1) * 2 * n * n, nullptr, n, lam, step, steps, blockIdx.x,
-                             blockIdx.y, ps);
-}
-
-hipError_t launch_tv_steps_store(const float* z, const float* p_in, float* ps, int n, float lam, float step,
-                                 int steps, hipStream_t s) {
-    if (steps < 1 || steps > kTvChunk) return hipErrorInvalidValue;
-    dim3 grid((n + kTvTile - 1) / kTvTile, (n + kTvTile - 1) / kTvTile);
-    tv_steps_store_kernel<<<grid, kTvThreads, 0, s>>>(z, p_in, ps, n, lam, step, steps);
-    return hipGetLastError();
-}
-
-hipError_t launch_tv_steps(const float* z, const float* p_in, float* p_out, float* x, int n, float lam, float step,
-                           int steps, hipStream_t s) {
-    if (steps > kTvChunk) return hipErrorInvalidValue;
-    dim3 grid((n + kTvTile - 1) / kTvTile, (n + kTvTile - 1) / kTvTile);
-    tv_prox_kernel<<<grid, kTvThreads, 0, s>>>(z, p_in, p_out, x, n, lam, step, steps);
-    return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
 // Reverse pass of the prox (for the unrolled solve's gradient).  One forward
 // dual step maps p to p' = P(q), q = p - step grad x~, x~ = max(0, z - lam div p),
@@ -262,20 +237,20 @@ __device__ __forceinline__ void block_sum_to(float v, double* out) {
     if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// One pixel per thread, 64 x 4 per workgroup; out-of-range threads take part
-// in the block sums with zero.
+// One pixel per thread, 64 x 4 per workgroup (block (bx, by) of a grid gx
+// blocks wide); out-of-range threads take part in the block sums with zero.
 #define TV_PIXEL                                              \
-    const int j = blockIdx.x * 64 + (threadIdx.x & 63);       \
-    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);        \
+    const int j = bx * 64 + (threadIdx.x & 63);               \
+    const int i = by * 4 + (threadIdx.x >> 6);                \
     const bool in = i < n && j < n;                           \
     const size_t nn = (size_t)n * n, idx = in ? (size_t)i * n + j : 0;
-#define TV_SLOT (partial + blockIdx.y * gridDim.x + blockIdx.x)
+#define TV_SLOT (partial + by * gx + bx)
 
 // x = max(0, z - lam div p): t = mask * xbar; tbar = t, zbar = t; sum -t.div p
-__global__ __launch_bounds__(256) void tv_bwd_final_kernel(const float* __restrict__ z, const float* __restrict__ p,
-                                                           const float* __restrict__ xbar, int n, float lam,
-                                                           float* __restrict__ tbar, float* __restrict__ zbar,
-                                                           double* __restrict__ partial) {
+__device__ __forceinline__ void tv_bwd_final_body(const float* __restrict__ z, const float* __restrict__ p,
+                                                  const float* __restrict__ xbar, int n, float lam,
+                                                  float* __restrict__ tbar, float* __restrict__ zbar,
+                                                  double* __restrict__ partial, int bx, int by, int gx) {
     TV_PIXEL
     float v = 0.0f;
     if (in) {
@@ -290,10 +265,10 @@ __global__ __launch_bounds__(256) void tv_bwd_final_kernel(const float* __restri
 
 // Reverse of one dual step, first half: pbar = qn + lam grad tn (the adjoint of
 // the step's output p), then qbar = J_P(q) pbar written over qn; sum -qbar.grad x~.
-__global__ __launch_bounds__(256) void tv_bwd_gradproj_kernel(const float* __restrict__ z,
-                                                              const float* __restrict__ pp, float* qn,
-                                                              const float* __restrict__ tn, int n, float lam,
-                                                              float step, double* __restrict__ partial) {
+__device__ __forceinline__ void tv_bwd_gradproj_body(const float* __restrict__ z, const float* __restrict__ pp,
+                                                     float* qn, const float* __restrict__ tn, int n, float lam,
+                                                     float step, double* __restrict__ partial, int bx, int by,
+                                                     int gx) {
     TV_PIXEL
     float v = 0.0f;
     if (in) {
@@ -324,11 +299,10 @@ __global__ __launch_bounds__(256) void tv_bwd_gradproj_kernel(const float* __res
 }
 
 // Second half: t = mask * step * div qbar; tbar = t, zbar += t; sum -t.div p.
-__global__ __launch_bounds__(256) void tv_bwd_mask_kernel(const float* __restrict__ z,
-                                                          const float* __restrict__ pp,
-                                                          const float* __restrict__ qbar, int n, float lam,
-                                                          float step, float* __restrict__ tbar,
-                                                          float* __restrict__ zbar, double* __restrict__ partial) {
+__device__ __forceinline__ void tv_bwd_mask_body(const float* __restrict__ z, const float* __restrict__ pp,
+                                                 const float* __restrict__ qbar, int n, float lam, float step,
+                                                 float* __restrict__ tbar, float* __restrict__ zbar,
+                                                 double* __restrict__ partial, int bx, int by, int gx) {
     TV_PIXEL
     float v = 0.0f;
     if (in) {
@@ -343,9 +317,8 @@ __global__ __launch_bounds__(256) void tv_bwd_mask_kernel(const float* __restric
 }
 
 // pbar = qbar + lam grad tbar (the adjoint of the warm-start dual field)
-__global__ __launch_bounds__(256) void tv_bwd_grad_kernel(const float* __restrict__ qbar,
-                                                          const float* __restrict__ tbar, int n, float lam,
-                                                          float* __restrict__ pbar) {
+__device__ __forceinline__ void tv_bwd_grad_body(const float* __restrict__ qbar, const float* __restrict__ tbar,
+                                                 int n, float lam, float* __restrict__ pbar, int bx, int by) {
     TV_PIXEL
     if (!in) return;
     const float tc = tbar[idx];
@@ -358,35 +331,70 @@ __global__ __launch_bounds__(256) void tv_bwd_grad_kernel(const float* __restric
 #undef TV_SLOT
 #undef TV_PIXEL
 
+// Recorded steps (one table entry per problem): TV prox chunks and the
+// reverse kernels.  A TV step of a problem with lam == 0 only writes
+// x = max(0, z) (when out[1] is set) and leaves the dual field alone.
+__global__ __launch_bounds__(kTvThreads) void step_tv_kernel(const UStep* __restrict__ steps,
+                                                             const BlockRef* __restrict__ map) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const UStep& st = steps[e.prob];
+    if (!st.active) return;
+    const int gx = (st.n + kTvTile - 1) / kTvTile;
+    const int bxi = e.local % gx, byi = e.local / gx;
+    if (st.lam > 0.f) {
+        tv_prox_body<kTvThreads>(st.in[0], st.in[1], st.out[0], st.out[1], st.n, st.lam, st.step, st.steps, bxi, byi,
+                                 st.out[2]);
+    } else if (st.out[1]) {
+        const int c = threadIdx.x & 63, ty = threadIdx.x >> 6;
+        const int j = bxi * kTvTile + c;
+        for (int r = ty; r < kTvTile; r += kTvThreads / 64) {
+            const int i = byi * kTvTile + r;
+            if (c < kTvTile && i < st.n && j < st.n) {
+                const size_t g = (size_t)i * st.n + j;
+                st.out[1][g] = fmaxf(0.f, st.in[0][g]);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void step_tv_bwd_kernel(const UStep* __restrict__ steps,
+                                                          const BlockRef* __restrict__ map) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const UStep& st = steps[e.prob];
+    if (!st.active) return;
+    const int gx = (st.n + 63) / 64;
+    const int bx = e.local % gx, by = e.local / gx;
+    switch (st.kind) {
+        case SK_BWD_FINAL:
+            tv_bwd_final_body(st.in[0], st.in[1], st.in[2], st.n, st.lam, st.out[0], st.out[1], st.part, bx, by, gx);
+            break;
+        case SK_BWD_GRADPROJ:
+            tv_bwd_gradproj_body(st.in[0], st.in[1], st.out[0], st.in[2], st.n, st.lam, st.step, st.part, bx, by,
+                                 gx);
+            break;
+        case SK_BWD_MASK:
+            tv_bwd_mask_body(st.in[0], st.in[1], st.in[2], st.n, st.lam, st.step, st.out[0], st.out[1], st.part, bx,
+                             by, gx);
+            break;
+        default: tv_bwd_grad_body(st.in[0], st.in[1], st.n, st.lam, st.out[0], bx, by); break;
+    }
+}
+
+hipError_t launch_step_tv(int kind, const UStep* steps, const BlockRef* map, int nblocks, hipStream_t s) {
+    switch (kind) {
+        case SK_TV: step_tv_kernel<<<nblocks, kTvThreads, 0, s>>>(steps, map); break;
+        case SK_BWD_FINAL:
+        case SK_BWD_GRADPROJ:
+        case SK_BWD_MASK:
+        case SK_BWD_GRAD: step_tv_bwd_kernel<<<nblocks, 256, 0, s>>>(steps, map); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 int tv_bwd_blocks(int n) { return ((n + 63) / 64) * ((n + 3) / 4); }
-
-hipError_t launch_tv_bwd_final(const float* z, const float* p, const float* xbar, int n, float lam, float* tbar,
-                               float* zbar, double* partial, hipStream_t s) {
-    dim3 grid((n + 63) / 64, (n + 3) / 4);
-    tv_bwd_final_kernel<<<grid, 256, 0, s>>>(z, p, xbar, n, lam, tbar, zbar, partial);
-    return hipGetLastError();
-}
-
-hipError_t launch_tv_bwd_gradproj(const float* z, const float* p_prev, float* qn, const float* tn, int n, float lam,
-                                  float step, double* partial, hipStream_t s) {
-    dim3 grid((n + 63) / 64, (n + 3) / 4);
-    tv_bwd_gradproj_kernel<<<grid, 256, 0, s>>>(z, p_prev, qn, tn, n, lam, step, partial);
-    return hipGetLastError();
-}
-
-hipError_t launch_tv_bwd_mask(const float* z, const float* p_prev, const float* qbar, int n, float lam, float step,
-                              float* tbar, float* zbar, double* partial, hipStream_t s) {
-    dim3 grid((n + 63) / 64, (n + 3) / 4);
-    tv_bwd_mask_kernel<<<grid, 256, 0, s>>>(z, p_prev, qbar, n, lam, step, tbar, zbar, partial);
-    return hipGetLastError();
-}
-
-hipError_t launch_tv_bwd_grad(const float* qbar, const float* tbar, int n, float lam, float* pbar,
-                              hipStream_t s) {
-    dim3 grid((n + 63) / 64, (n + 3) / 4);
-    tv_bwd_grad_kernel<<<grid, 256, 0, s>>>(qbar, tbar, n, lam, pbar);
-    return hipGetLastError();
-}
 
 hipError_t launch_tv_prox(const float* z, float* p_a, float* p_b, float* x, int n, float lam, float step,
                           int n_iter, float** p_final, hipStream_t s) {

@@ -248,67 +248,7 @@ hipError_t launch_lin3_f32(float* out, const float* a, float c0, const float* b,
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void lin_mix_kernel(float* out, const float* a, float c0, const float* b, float c1,
-                                                      const float* __restrict__ c, const float* __restrict__ d,
-                                                      float c2, size_t len) {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= len) return;
-    float r = c0 * a[i];
-    if (b) r = fmaf(c1, b[i], r);
-    if (c) r = fmaf(c2, d ? c[i] * d[i] : c[i], r);
-    out[i] = r;
-}
-
-hipError_t launch_lin_mix_f32(float* out, const float* a, float c0, const float* b, float c1, const float* c,
-                              const float* d, float c2, size_t len, hipStream_t s) {
-    lin_mix_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(out, a, c0, b, c1, c, d, c2, len);
-    return hipGetLastError();
-}
-
-// Block partial sums of a . b (float inputs, float64 sums) into partial[0 .. nb),
-// nb = reduce_blocks(len); the rest of a slot is left as it is (zeroed by the caller).
-__global__ __launch_bounds__(256) void dot_partials_kernel(const float* __restrict__ a, const float* __restrict__ b,
-                                                           size_t len, double* __restrict__ partial) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    const size_t stride = (size_t)gridDim.x * 256;
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < len; i += stride)
-        s0 = fma((double)a[i], (double)b[i], s0);
-    block_sum3(s0, s1, s2);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s0;
-}
-
 int reduce_blocks_for(size_t len) { return reduce_blocks(len); }
-
-hipError_t launch_dot_partials(const float* a, const float* b, size_t len, double* partial, hipStream_t s) {
-    dot_partials_kernel<<<reduce_blocks(len), 256, 0, s>>>(a, b, len, partial);
-    return hipGetLastError();
-}
-
-// out[k] = sum of partial[k cap .. (k + 1) cap), one workgroup per slot, fixed order.
-__global__ __launch_bounds__(256) void slot_reduce_kernel(const double* __restrict__ partial, int cap,
-                                                          double* __restrict__ out) {
-    const double* p = partial + (size_t)blockIdx.x * cap;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int b = threadIdx.x; b < cap; b += 256) s0 += p[b];
-    block_sum3(s0, s1, s2);
-    if (threadIdx.x == 0) out[blockIdx.x] = s0;
-}
-
-hipError_t launch_slot_reduce(const double* partial, int cap, int nslots, double* out, hipStream_t s) {
-    if (nslots <= 0) return hipSuccess;
-    slot_reduce_kernel<<<nslots, 256, 0, s>>>(partial, cap, out);
-    return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void fill_f64_kernel(double* __restrict__ dst, double v, size_t len) {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < len) dst[i] = v;
-}
-
-hipError_t launch_fill_f64(double* dst, double v, size_t len, hipStream_t s) {
-    fill_f64_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(dst, v, len);
-    return hipGetLastError();
-}
 
 // out = a .* w with float weights (float64 operator applications)
 __global__ __launch_bounds__(256) void mul_w_kernel(double* __restrict__ out, const double* __restrict__ a,
@@ -658,6 +598,66 @@ __global__ __launch_bounds__(256) void fill_kernel(float* __restrict__ dst, floa
 hipError_t launch_fill_f32(float* dst, float v, size_t len, hipStream_t s) {
     if (len == 0) return hipSuccess;
     fill_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(dst, v, len);
+    return hipGetLastError();
+}
+
+// Recorded elementwise / reduction steps (one table entry per problem).
+// Elementwise kinds: 256 elements per workgroup.  SK_DOT: the problem's
+// reduce_blocks(len) workgroups stride over len, as launch_dot_partials.
+// SK_SLOTS: one workgroup per slot.
+__global__ __launch_bounds__(256) void step_vec_kernel(const UStep* __restrict__ steps,
+                                                       const BlockRef* __restrict__ map) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const UStep& st = steps[e.prob];
+    if (!st.active) return;
+    const int kind = st.kind;
+    if (kind == SK_DOT) {
+        const size_t stride = (size_t)reduce_blocks(st.len) * 256;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (size_t i = (size_t)e.local * 256 + threadIdx.x; i < st.len; i += stride)
+            s0 = fma((double)st.in[0][i], (double)st.in[1][i], s0);
+        block_sum3(s0, s1, s2);
+        if (threadIdx.x == 0) st.part[e.local] = s0;
+        return;
+    }
+    if (kind == SK_SLOTS) {
+        const double* p = st.part + (size_t)e.local * st.steps;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int b = threadIdx.x; b < st.steps; b += 256) s0 += p[b];
+        block_sum3(s0, s1, s2);
+        if (threadIdx.x == 0) st.dout[e.local] = s0;
+        return;
+    }
+    const size_t i = (size_t)e.local * 256 + threadIdx.x;
+    if (i >= st.len) return;
+    switch (kind) {
+        case SK_LIN3: {
+            float r = st.c0 * st.in[0][i];
+            if (st.in[1]) r = fmaf(st.c1, st.in[1][i], r);
+            if (st.in[2]) r = fmaf(st.c2, st.in[2][i], r);
+            if (st.in[3]) r *= st.in[3][i];
+            st.out[0][i] = r;
+            break;
+        }
+        case SK_LINMIX: {
+            float r = st.c0 * st.in[0][i];
+            if (st.in[1]) r = fmaf(st.c1, st.in[1][i], r);
+            if (st.in[2]) r = fmaf(st.c2, st.in[3] ? st.in[2][i] * st.in[3][i] : st.in[2][i], r);
+            st.out[0][i] = r;
+            break;
+        }
+        case SK_COPY: st.out[0][i] = st.in[0][i]; break;
+        case SK_FILL: st.out[0][i] = st.c0; break;
+        case SK_INV: st.out[0][i] = (float)(1.0 / (double)st.in[0][i]); break;
+        case SK_FILL64: st.part[i] = 0.0; break;
+        default: break;
+    }
+}
+
+hipError_t launch_step_vec(int kind, const UStep* steps, const BlockRef* map, int nblocks, hipStream_t s) {
+    (void)kind;
+    step_vec_kernel<<<nblocks, 256, 0, s>>>(steps, map);
     return hipGetLastError();
 }
 
