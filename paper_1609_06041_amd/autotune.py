@@ -21,7 +21,7 @@ CANDIDATES = [dict(placement=p, tv_threads=t, fwd_batch=f) for p in (0, 1) for t
 
 def signature(geoms, iters: int, tv_iters: int) -> str:
     key = json.dumps({"device": torch.cuda.get_device_name(), "geoms": sorted(map(list, geoms)),
-                      "iters": int(iters), "tv_iters": int(tv_iters)})
+                      "iters": int(iters), "tv_iters": int(tv_iters), "knobs": sorted(CANDIDATES[0])})
     return hashlib.sha1(key.encode()).hexdigest()[:16]
 
 

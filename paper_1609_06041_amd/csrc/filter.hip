@@ -430,6 +430,11 @@ __global__ __launch_bounds__(256) void norm_filter_batched(const NormItem* __res
     if (e.prob < 0) return;
     const NormItem& it = items[e.prob];
     const int gx = (it.nb + FBN - 1) / FBN;
+    // views whose chain has stopped are neither stepped nor read again: a
+    // workgroup whose views have all stopped has nothing to do
+    const int v = (e.local / gx) * FBM + (int)threadIdx.x;
+    const int live = threadIdx.x < FBM && v < it.m && !it.done[v];
+    if (!__syncthreads_or(live)) return;
     filter_f64_body<true, true>(it.v[rot], it.v[(rot + 2) % 3], it.taps64, it.rs, it.rs, it.m, it.nb, e.local % gx,
                                 e.local / gx);
 }

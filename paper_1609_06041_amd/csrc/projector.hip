@@ -192,16 +192,21 @@ hipError_t launch_forward(const T* xp, const T* xTp, T* y, const ViewGeom* views
 // or |sin| (column views) <= 1, so only bins floor(t), floor(t)+1 carry
 // weight.  out = alpha * xin + beta * A^T (c1 y1 + c2 y2).
 //
-// Workgroup: a 32 x 32 pixel tile, 512 lanes in two halves; half h takes the
-// view chunks h, h+2, ... and its lane (tx, ty) owns pixels
-// (x0 + tx, y0 + ty + 8j), j = 0..3.  For each chunk of 16 views the half
+// Workgroup: a 32 x 32 pixel tile, AT_G view streams of 256 lanes; stream h
+// takes the view chunks h, h+AT_G, ... and its lane (tx, ty) owns pixels
+// (x0 + tx, y0 + ty + 8j), j = 0..3.  For each chunk of 16 views the stream
 // stages, per view, the 48 bins starting one below the tile's lowest bin
 // coordinate (the tile spans at most 31 sqrt(2) + 2 bins), zero outside the
 // detector, so the inner loop reads LDS without bounds tests.  The next
 // chunk's bins are loaded into registers while the current chunk is used.
-// The halves are summed through LDS at the end (deterministic).
+// The streams are summed through LDS at the end in a fixed order
+// (deterministic).  Per view the stream also tabulates the bin positions of
+// the tile's first row and the row increments, so a lane's positions take
+// only 64-bit adds.
 constexpr int AT_T = 32;
 constexpr int AT_VC = 16;
+constexpr int AT_G = 4;   // view streams per tile (16 waves: a 512^2 image has one tile per CU)
+constexpr int AT_THREADS = 256 * AT_G;
 constexpr int AT_W = 48;
 constexpr int AT_PER = AT_VC * AT_W / 256;
 
@@ -220,16 +225,21 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
                                              const T* __restrict__ xin, T alpha, T beta, T* __restrict__ out,
                                              const ViewGeom* __restrict__ views, int n, int m, int nb, int bxi,
                                              int byi) {
-    __shared__ T win[2][AT_VC][AT_W];
-    __shared__ long long pt0[2][AT_VC], pcs[2][AT_VC], psn[2][AT_VC];
-    __shared__ T plen[2][AT_VC], plen2[2][AT_VC];
+    __shared__ T win[AT_G][AT_VC][AT_W];
+    // per view of the staged chunk, in 32.32 fixed point relative to the
+    // window: colt[i][tx] = t of pixel (x0 + tx, y0), rowt[i][r] = r * (the
+    // per-row increment), r = 0..8 -- so a lane's four positions are
+    // colt[tx] + rowt[ty] + j rowt[8] (adds only)
+    __shared__ long long colt[AT_G][AT_VC][AT_T];
+    __shared__ long long rowt[AT_G][AT_VC][9];
+    __shared__ T plen[AT_G][AT_VC], plen2[AT_G][AT_VC];
     const int tid = threadIdx.x, h = tid >> 8, l = tid & 255;
     const int tx = l & 31, ty = l >> 5;
     const int x0 = bxi * AT_T, y0 = byi * AT_T;
     const double c = 0.5 * (double)(n - 1);
     const TileBox box{x0 - c, x0 + (AT_T - 1) - c, y0 - c, y0 + (AT_T - 1) - c, 0.5 * (double)(nb - 1)};
     const int nchunk = (m + AT_VC - 1) / AT_VC;
-    const int nsteps = (nchunk + 1) / 2;
+    const int nsteps = (nchunk + AT_G - 1) / AT_G;
     const double two32 = 4294967296.0;
 
     T stg[AT_PER];
@@ -250,9 +260,9 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
             stg[r] = val;
         }
     };
-    // Per view: the tile origin's bin coordinate relative to the window, and
-    // the per-pixel increments, in 32.32 fixed point (the weights absorb the
-    // 2^-32 of the fraction through plen2).
+    // The tables of the chunk's views (the weights absorb the 2^-32 of the
+    // fraction through plen2).  Past the last view: position 1.5 in a zero
+    // window with zero weights.
     auto commit = [&](int ch) {
 #pragma unroll
         for (int r = 0; r < AT_PER; ++r) {
@@ -260,24 +270,29 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
             const int i = e / AT_W;
             win[h][i][e - i * AT_W] = stg[r];
         }
-        if (l < AT_VC) {
-            const int v = ch * AT_VC + l;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = l + 256 * q;
+            const int i = e >> 5, cx = e & 31;
+            const int v = ch * AT_VC + i;
+            long long a = 3ll << 31;
             if (ch < nchunk && v < m) {
                 const ViewGeom g = views[v];
-                const int ub = window_base(g, box);
-                const double t0 = fma(box.xlo, g.cs, fma(box.ylo, g.sn, box.cd)) - (double)ub;
-                pt0[h][l] = llrint(t0 * two32);
-                pcs[h][l] = llrint(g.cs * two32);
-                psn[h][l] = llrint(g.sn * two32);
-                plen[h][l] = (T)g.len;
-                plen2[h][l] = (T)(g.len2 / two32);
-            } else {   // past the last view: zero weights on a zero window
-                pt0[h][l] = 3ll << 31;
-                pcs[h][l] = 0;
-                psn[h][l] = 0;
-                plen[h][l] = T(0);
-                plen2[h][l] = T(0);
+                const double t0 = fma(box.xlo, g.cs, fma(box.ylo, g.sn, box.cd)) - (double)window_base(g, box);
+                a = llrint(t0 * two32) + (long long)cx * llrint(g.cs * two32);
             }
+            colt[h][i][cx] = a;
+        }
+        if (l < AT_VC * 9) {
+            const int i = l / 9, r = l - 9 * i;
+            const int v = ch * AT_VC + i;
+            rowt[h][i][r] = (ch < nchunk && v < m) ? (long long)r * llrint(views[v].sn * two32) : 0ll;
+        } else if (l < AT_VC * 10) {
+            const int i = l - AT_VC * 9;
+            const int v = ch * AT_VC + i;
+            const bool live = ch < nchunk && v < m;
+            plen[h][i] = live ? (T)views[v].len : T(0);
+            plen2[h][i] = live ? (T)(views[v].len2 / two32) : T(0);
         }
     };
 
@@ -286,8 +301,8 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
     commit(h);
     __syncthreads();
     for (int st = 0; st < nsteps; ++st) {
-        const int ch = h + 2 * st;
-        fetch(ch + 2);
+        const int ch = h + AT_G * st;
+        fetch(ch + AT_G);
         if (ch < nchunk) {
             // two views x four pixels per pass: all eight LDS reads are independent
 #pragma unroll 1
@@ -296,17 +311,16 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
                 T f[2][4], a[2][4], b[2][4], len[2], len2[2];
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    const long long sn = psn[h][i + q];
-                    const unsigned long long tb =
-                        (unsigned long long)(pt0[h][i + q] + (long long)tx * pcs[h][i + q] + (long long)ty * sn);
+                    unsigned long long tj = (unsigned long long)(colt[h][i + q][tx] + rowt[h][i + q][ty]);
+                    const unsigned long long d8 = (unsigned long long)rowt[h][i + q][8];
                     len[q] = plen[h][i + q];
                     len2[q] = plen2[h][i + q];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         // t >= 1 - rounding > 0, so the high word is floor(t)
-                        const unsigned long long tj = tb + (unsigned long long)((long long)(8 * j) * sn);
                         k[q][j] = (unsigned)(tj >> 32);
                         f[q][j] = (T)(unsigned)tj;
+                        tj += d8;
                     }
                 }
 #pragma unroll
@@ -329,15 +343,15 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
             }
         }
         __syncthreads();
-        commit(ch + 2);
+        commit(ch + AT_G);
         __syncthreads();
     }
-    // sum the halves through LDS (reusing the staging buffer)
+    // sum the streams through LDS (reusing the staging buffer), in a fixed order
     T* red = &win[0][0][0];
-    static_assert(2 * AT_VC * AT_W >= AT_T * AT_T, "reduction buffer");
-    if (h == 1) {
+    static_assert((AT_G - 1) * AT_T * AT_T <= AT_G * AT_VC * AT_W, "reduction buffer");
+    if (h > 0) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) red[(ty + 8 * j) * AT_T + tx] = acc[j];
+        for (int j = 0; j < 4; ++j) red[(h - 1) * AT_T * AT_T + (ty + 8 * j) * AT_T + tx] = acc[j];
     }
     __syncthreads();
     if (h == 0) {
@@ -346,7 +360,9 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
         for (int j = 0; j < 4; ++j) {
             const int iy = y0 + ty + 8 * j;
             if (ix < n && iy < n) {
-                const T sum = acc[j] + red[(ty + 8 * j) * AT_T + tx];
+                T sum = acc[j];
+#pragma unroll
+                for (int g = 0; g < AT_G - 1; ++g) sum += red[g * AT_T * AT_T + (ty + 8 * j) * AT_T + tx];
                 const size_t idx = (size_t)iy * n + ix;
                 T r = beta * sum;
                 if (xin) r += alpha * xin[idx];
@@ -357,7 +373,7 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
 }
 
 template <typename T, bool TWO>
-__global__ __launch_bounds__(512) void adjoint_kernel(const T* __restrict__ y1, const T* __restrict__ y2, T c1,
+__global__ __launch_bounds__(AT_THREADS) void adjoint_kernel(const T* __restrict__ y1, const T* __restrict__ y2, T c1,
                                                       T c2, const T* __restrict__ xin, T alpha, T beta,
                                                       T* __restrict__ out, const ViewGeom* __restrict__ views,
                                                       int n, int m, int nb) {
@@ -369,9 +385,9 @@ hipError_t launch_adjoint(const T* y1, const T* y2, T c1, T c2, const T* xin, T 
                           const ViewGeom* views, int n, int m, int nb, hipStream_t s) {
     dim3 grid((n + AT_T - 1) / AT_T, (n + AT_T - 1) / AT_T);
     if (y2)
-        adjoint_kernel<T, true><<<grid, 512, 0, s>>>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb);
+        adjoint_kernel<T, true><<<grid, AT_THREADS, 0, s>>>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb);
     else
-        adjoint_kernel<T, false><<<grid, 512, 0, s>>>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb);
+        adjoint_kernel<T, false><<<grid, AT_THREADS, 0, s>>>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb);
     return hipGetLastError();
 }
 
@@ -399,7 +415,7 @@ __global__ __launch_bounds__(256) void forward_batched(const BatchItem* __restri
 
 // z = x - tau A^T mubar  (mode 0), or z = x - tau A^T (2 mu - mu_prev)  (mode 1, few-view k >= 1)
 template <bool TWO>
-__global__ __launch_bounds__(512) void adjoint_batched(const BatchItem* __restrict__ items,
+__global__ __launch_bounds__(AT_THREADS) void adjoint_batched(const BatchItem* __restrict__ items,
                                                        const BlockRef* __restrict__ map, int rot) {
     const BlockRef e = map[blockIdx.x];
     if (e.prob < 0) return;
@@ -428,9 +444,9 @@ hipError_t launch_forward_batched(const BatchItem* items, const BlockRef* map, i
 hipError_t launch_adjoint_batched(const BatchItem* items, const BlockRef* map, int nblocks, bool two, int rot,
                                   hipStream_t s) {
     if (two)
-        adjoint_batched<true><<<nblocks, 512, 0, s>>>(items, map, rot);
+        adjoint_batched<true><<<nblocks, AT_THREADS, 0, s>>>(items, map, rot);
     else
-        adjoint_batched<false><<<nblocks, 512, 0, s>>>(items, map, rot);
+        adjoint_batched<false><<<nblocks, AT_THREADS, 0, s>>>(items, map, rot);
     return hipGetLastError();
 }
 
@@ -455,7 +471,7 @@ __global__ __launch_bounds__(256) void step_forward_kernel(const UStep* __restri
     forward_body<float>(st.in[0], st.in[1], st.out[0], st.views, st.n, st.nb, e.local % gx, e.local / gx);
 }
 
-__global__ __launch_bounds__(512) void step_adjoint_kernel(const UStep* __restrict__ steps,
+__global__ __launch_bounds__(AT_THREADS) void step_adjoint_kernel(const UStep* __restrict__ steps,
                                                            const BlockRef* __restrict__ map) {
     const BlockRef e = map[blockIdx.x];
     if (e.prob < 0) return;
@@ -470,7 +486,7 @@ hipError_t launch_step_projector(int kind, const UStep* steps, const BlockRef* m
     switch (kind) {
         case SK_PAD: step_pad_kernel<<<nblocks, 256, 0, s>>>(steps, map); break;
         case SK_FORWARD: step_forward_kernel<<<nblocks, 256, 0, s>>>(steps, map); break;
-        case SK_ADJOINT: step_adjoint_kernel<<<nblocks, 512, 0, s>>>(steps, map); break;
+        case SK_ADJOINT: step_adjoint_kernel<<<nblocks, AT_THREADS, 0, s>>>(steps, map); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
