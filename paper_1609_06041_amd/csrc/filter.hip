@@ -326,6 +326,66 @@ hipError_t launch_step_filter(const UStep* steps, const BlockRef* map, int nbloc
     return hipGetLastError();
 }
 
+// Upper bound of the largest eigenvalue of the nb x nb Toeplitz section of
+// the taps: its eigenvalues lie between the extremes of the generating
+// function f(w) = h_0 + 2 sum_{k=1}^{nb-1} h_k cos(k w) (symmetric taps), and
+// f is evaluated on kSymGrid equispaced points of [0, pi] (the cosines by
+// their three-term recurrence) plus the Lipschitz margin (spacing / 2) *
+// 2 sum_k k |h_k|, so the result is not below the true maximum.
+constexpr int kSymGrid = kSymBlocks * 256;
+
+__global__ __launch_bounds__(256) void symbol_grid_kernel(const double* __restrict__ taps64, int nb,
+                                                          double* __restrict__ partial) {
+    __shared__ double red[4];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const double w = M_PI * (double)i / (double)(kSymGrid - 1);
+    const double* h = taps64 + (nb - 1);
+    const double c1 = cos(w);
+    double cprev = 1.0, c = c1, f = 0.0;
+    for (int k = 1; k < nb; ++k) {
+        f = fma(h[k], c, f);
+        const double cn = fma(2.0 * c1, c, -cprev);
+        cprev = c;
+        c = cn;
+    }
+    double v = fma(2.0, f, h[0]);
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void symbol_final_kernel(const double* __restrict__ taps64, int nb,
+                                                           double* __restrict__ out) {
+    __shared__ double rl[4], rm[4];
+    const double* h = taps64 + (nb - 1);
+    double lip = 0.0;
+    for (int k = 1 + threadIdx.x; k < nb; k += 256) lip = fma((double)k, fabs(h[k]), lip);
+    double mx = threadIdx.x < kSymBlocks ? out[1 + threadIdx.x] : -1e300;
+    for (int off = 32; off > 0; off >>= 1) {
+        lip += __shfl_xor(lip, off);
+        mx = fmax(mx, __shfl_xor(mx, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        rl[threadIdx.x >> 6] = lip;
+        rm[threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double L = 2.0 * ((rl[0] + rl[1]) + (rl[2] + rl[3]));
+        const double m = fmax(fmax(rm[0], rm[1]), fmax(rm[2], rm[3]));
+        out[0] = m + 0.5 * (M_PI / (double)(kSymGrid - 1)) * L;
+    }
+}
+
+hipError_t launch_symbol_max(const double* taps64, int nb, double* out, hipStream_t s) {
+    symbol_grid_kernel<<<kSymBlocks, 256, 0, s>>>(taps64, nb, out + 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    symbol_final_kernel<<<1, 256, 0, s>>>(taps64, nb, out);
+    return hipGetLastError();
+}
+
 // filter work decomposition (for batched block maps)
 int filter_blocks_x(int nb) { return (nb + FBN - 1) / FBN; }
 int filter_blocks_y(int m) { return (m + FBM - 1) / FBM; }

@@ -76,7 +76,10 @@ struct BatchItem {
 // the next one.  The scalars of view v at step j are al[j m + v] (alpha) and
 // b2[j m + v] (beta_{j+1}^2); b0[v] is the start norm^2; theta[v] the view's top
 // Ritz value; done[v] = steps once its chain has stopped (0 while running);
-// summary = {max theta, views still running, max steps}.
+// summary = {max theta, views still running, max steps}.  A view also stops
+// once fsym[0] * maxinv[v] -- an upper bound of its eigenvalue: the largest
+// value of the filter's symbol times the view's largest 1/w -- is below the
+// largest Ritz value of the problem (fsym null: no such pruning).
 struct NormItem {
     int m, nb;
     const double* taps64;
@@ -90,6 +93,8 @@ struct NormItem {
     double* theta;
     int* done;
     double* summary;
+    const double* fsym;
+    double* maxinv;
 };
 
 // One view (row) of one problem in the per-view chains.
@@ -264,6 +269,10 @@ hipError_t launch_batch_copy_out(const BatchItem* items, const BlockRef* map, in
 // per-view lambda_h chains over the rows of a NormItem table (one wave per row)
 hipError_t launch_rows_start(const NormItem* it, const RowRef* rows, int nrows, uint64_t seed, hipStream_t s);
 hipError_t launch_rows_step(const NormItem* it, const RowRef* rows, int nrows, int rot, int j, hipStream_t s);
+// upper bound of max over omega of h0 + 2 sum_k h_k cos(k omega) (taps64 as
+// launch_taps writes them) into out[0]; out[1 ..] is scratch (kSymBlocks doubles)
+constexpr int kSymBlocks = 64;
+hipError_t launch_symbol_max(const double* taps64, int nb, double* out, hipStream_t s);
 hipError_t launch_rows_ritz(const NormItem* it, const RowRef* rows, int nrows, int count, int steps, double tol,
                             hipStream_t s);
 // workgroups of a float64 reduction over len elements

@@ -71,6 +71,9 @@ struct ctpd_op {
     // step, and the one-problem tables the shared routine runs on
     double *hv_al = nullptr, *hv_b2 = nullptr, *hv_b0 = nullptr, *hv_theta = nullptr;
     int* hv_done = nullptr;
+    double* hv_maxinv = nullptr;               // device, m doubles: max 1/w per view
+    double* hv_sym = nullptr;                  // device, 1 + kSymBlocks doubles: bound of the filter's symbol
+    double hv_sym_tau = -1.0, hv_sym_kappa = -1.0;   // the taps hv_sym was computed for
     int hv_cap = 0;
     ctpd::NormItem* hv_item = nullptr;        // device, 1 entry
     ctpd::NormItem* hv_item_host = nullptr;   // pinned

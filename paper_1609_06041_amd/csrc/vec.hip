@@ -291,14 +291,17 @@ __global__ __launch_bounds__(256) void rows_start_kernel(const NormItem* __restr
                                                          uint64_t seed) {
     ROW_PROLOGUE
     double* q = it.v[0] + base;
-    double ss = 0.0;
+    double ss = 0.0, mi = 0.0;
     for (int u = lane; u < nb; u += 64) {
         const size_t i = base + u;
-        const double shape = ((u & 1) ? -1.0 : 1.0) * it.inv_kappa / (double)it.w[i];
+        const double iw = 1.0 / (double)it.w[i];
+        const double shape = ((u & 1) ? -1.0 : 1.0) * it.inv_kappa * iw;
         const double val = shape + 0.05 * (splitmix_unit(seed, i) - 0.5);
         q[u] = val;
         ss = fma(val, val, ss);
+        mi = fmax(mi, iw);
     }
+    for (int off = 32; off > 0; off >>= 1) mi = fmax(mi, __shfl_xor(mi, off));
     ss = wave_sum_all(ss);
     const double inv = 1.0 / sqrt(ss);
     for (int u = lane; u < nb; u += 64) q[u] *= inv;
@@ -306,6 +309,7 @@ __global__ __launch_bounds__(256) void rows_start_kernel(const NormItem* __restr
         it.b0[v] = ss;
         it.done[v] = 0;
         it.theta[v] = 0.0;
+        it.maxinv[v] = mi;
     }
     (void)m;
 }
@@ -428,17 +432,33 @@ __global__ __launch_bounds__(256) void rows_ritz_kernel(const NormItem* __restri
     }
 }
 
-// one workgroup per problem: {max theta, running views, max steps}
-__global__ __launch_bounds__(256) void rows_summary_kernel(const NormItem* __restrict__ items) {
+// one workgroup per problem: {max theta, running views, max steps}, after
+// stopping the views whose eigenvalue bound is below the largest Ritz value
+// (a lower bound of the problem's lambda_h; the margin covers the rounding of
+// the Ritz values)
+__global__ __launch_bounds__(256) void rows_summary_kernel(const NormItem* __restrict__ items, int steps) {
     const NormItem& it = items[blockIdx.x];
-    double mx = -1e300, run = 0.0, st = 0.0;
+    __shared__ double r0[256], r1[256], r2[256];
+    double mx = -1e300;
     for (int v = threadIdx.x; v < it.m; v += 256) {
         const double th = it.theta[v];
         if (isfinite(th)) mx = fmax(mx, th);
+    }
+    r0[threadIdx.x] = mx;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) r0[threadIdx.x] = fmax(r0[threadIdx.x], r0[threadIdx.x + off]);
+        __syncthreads();
+    }
+    mx = r0[0];
+    __syncthreads();
+    const double cut = it.fsym ? mx * (1.0 - 1e-9) : -1e300;
+    double run = 0.0, st = 0.0;
+    for (int v = threadIdx.x; v < it.m; v += 256) {
+        if (!it.done[v] && it.fsym && it.fsym[0] * it.maxinv[v] < cut) it.done[v] = steps;
         if (!it.done[v]) run += 1.0;
         st = fmax(st, (double)it.done[v]);
     }
-    __shared__ double r0[256], r1[256], r2[256];
     r0[threadIdx.x] = mx;
     r1[threadIdx.x] = run;
     r2[threadIdx.x] = st;
@@ -475,7 +495,7 @@ hipError_t launch_rows_ritz(const NormItem* it, const RowRef* rows, int nrows, i
     rows_ritz_kernel<<<(nrows + 3) / 4, 256, 0, s>>>(it, rows, nrows, steps, tol);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    rows_summary_kernel<<<count, 256, 0, s>>>(it);
+    rows_summary_kernel<<<count, 256, 0, s>>>(it, steps);
     return hipGetLastError();
 }
 

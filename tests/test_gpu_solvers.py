@@ -173,3 +173,22 @@ def test_invalid_weights_and_data_are_rejected(gpu):
         with pytest.raises(ctpd.CtpdError) as e:
             op.lowdose_solve(dev(b), dev(w), 0.1, 3, norm_steps=513)
         assert e.value.code == ctpd.CTPD_EINVAL
+
+
+def test_lambda_h_equals_the_largest_per_view_eigenvalue(gpu):
+    # W^-1/2 D W^-1/2 is block diagonal over views: lambda_h is the largest
+    # eigenvalue of the m dense nb x nb blocks (brute force here).  The GPU
+    # stops the chains of views whose bound (symbol maximum x max 1/w) falls
+    # below the best Ritz value, which must not change the result.
+    from scipy.linalg import eigh, toeplitz
+    from oracle.filters import smoothed_ramp_taps
+    n, m, nb = 128, 180, 184
+    b, w = lowdose_inputs(n, m, nb, seed=21, n_ell=12, i0=2e4)
+    with ctpd.Operator(n, m, nb) as op:
+        _, info = op.lowdose_solve(dev(b), dev(w), 0.01, 1)
+    h = smoothed_ramp_taps(nb, m, info["tau"], info["kappa"])
+    T = toeplitz(h[nb - 1:])
+    rs = np.sqrt(1.0 / w)
+    lam = max(eigh(rs[v][:, None] * T * rs[v][None, :], eigvals_only=True, subset_by_index=[nb - 1, nb - 1])[0]
+              for v in range(m))
+    assert info["lambda_h"] == pytest.approx(lam, rel=1e-6)
