@@ -319,7 +319,7 @@ int ensure_hv(ctpd_op* op, int kmax) {
         for (int v = 0; v < op->m; ++v) rows[v] = RowRef{0, v};
         ALLOC(op->hv_rows, op->m);
         HIP_TRY(hipMemcpy(op->hv_rows, rows.data(), sizeof(RowRef) * op->m, hipMemcpyHostToDevice));
-        const int gx = filter_blocks_x(op->nb), gy = filter_blocks_y(op->m);
+        const int gx = norm_blocks_x(op->nb), gy = norm_blocks_y(op->m);
         std::vector<BlockRef> f(gx * gy);
         for (int l = 0; l < gx * gy; ++l) f[l] = BlockRef{0, l};
         ALLOC(op->hv_filt, f.size());

@@ -20,7 +20,7 @@ using namespace ctpd_host;
 
 namespace {
 
-enum Kind { K_INIT, K_FILT, K_ADJ, K_TV, K_PAD, K_FWD, K_COPY, K_COUNT };
+enum Kind { K_INIT, K_FILT, K_NFILT, K_ADJ, K_TV, K_PAD, K_FWD, K_COPY, K_COUNT };
 
 }  // namespace
 
@@ -95,6 +95,7 @@ int blocks_of(const ctpd_op* op, int kind) {
     switch (kind) {
         case K_INIT: return (int)((3 * J + 2 * I + 2047) / 2048);
         case K_FILT: return filter_blocks_x(op->nb) * filter_blocks_y(op->m);
+        case K_NFILT: return norm_blocks_x(op->nb) * norm_blocks_y(op->m);
         case K_ADJ: return adjoint_tiles(op->n) * adjoint_tiles(op->n);
         case K_TV: return tv_tiles(op->n) * tv_tiles(op->n);
         case K_PAD: return pad_tiles(op->n) * pad_tiles(op->n);
@@ -281,7 +282,7 @@ int ctpd_batch_lowdose_solve(ctpd_batch* bt, const float* const* b, const float*
         std::vector<int> st(P);
         for (int i = 0; i < P; ++i) kap[i] = S[i].kappa;
         if ((r = lambda_h_views(bt->ops, w, kap.data(), k.norm_steps, bt->gs, bt->nitems, bt->nitems_host, bt->rows,
-                                bt->nrows, bt->map[K_FILT], bt->nblk[K_FILT], bt->hsum, bt->hsum_host, lam.data(),
+                                bt->nrows, bt->map[K_NFILT], bt->nblk[K_NFILT], bt->hsum, bt->hsum_host, lam.data(),
                                 st.data())))
             return r;
         for (int i = 0; i < P; ++i) {

@@ -117,8 +117,11 @@ hipError_t launch_taps(double* taps64, float* taps32, int nb, int m, double tau,
 // float32 matrix-core filter.
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int FBM = 32;    // views per workgroup
+constexpr int FBM = 16;    // views per workgroup
 constexpr int FBN = 64;    // output bins per workgroup
+constexpr int FTPR = FBN / 16;            // 16 x 16 output tiles per tile row
+constexpr int FACC = FBM * FBN / 1024;    // 16 x 16 accumulators per wave (4 waves)
+static_assert(FACC >= 1 && FTPR % FACC == 0, "a wave's tiles lie in one tile row");
 constexpr int FBK = 128;   // input bins per LDS stage
 constexpr int FSTRIDE = FBK + 2;   // row pitch = 2 mod 32 banks: the 32 lanes of a half-wave hit 32 banks
 constexpr int FPER = FBM * FBK / 256;
@@ -138,8 +141,8 @@ struct FilterIn {
     }
 };
 
-// Workgroup: 4 waves, a 32 x 64 output tile; wave w owns rows 16*(w/2) and
-// columns 32*(w%2) as two 16 x 16 MFMA accumulators.  MFMA 16x16x4 f32
+// Workgroup: 4 waves, an FBM x FBN output tile cut into 16 x 16 MFMA tiles;
+// wave w owns FACC consecutive tiles of one tile row.  MFMA 16x16x4 f32
 // operand layout: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k,
 // D[i][j] in lane j + 16*(i/4), element i%4.  The filter input of the next
 // 128-bin stage is loaded into registers while the current stage runs.
@@ -165,7 +168,7 @@ __device__ __forceinline__ void filter_body(const FilterArgs& a, const float* __
             if (i < tlen) htap[i] = (k >= 0 && k < ntap) ? tv[u] : 0.0f;
         }
     }
-    const int wr = (wave >> 1) * 16, wc = (wave & 1) * 32;
+    const int wr = (wave * FACC / FTPR) * 16, wc = (wave * FACC % FTPR) * 16;
     const int li = lane & 15, lk = lane >> 4;
     constexpr int NIN = FilterIn<MODE>::N;
     const float* src[4] = {a.in0, a.in1, a.in2, a.in3};
@@ -183,7 +186,9 @@ __device__ __forceinline__ void filter_body(const FilterArgs& a, const float* __
             for (int q = 0; q < NIN; ++q) stg[r][q] = src[q][idx];
         }
     };
-    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    v4f acc[FACC];
+#pragma unroll
+    for (int q = 0; q < FACC; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
     fetch(0);
     for (int k0 = 0; k0 < nb; k0 += FBK) {
         __syncthreads();
@@ -200,22 +205,20 @@ __device__ __forceinline__ void filter_body(const FilterArgs& a, const float* __
 #pragma unroll 8
         for (int kk = 0; kk < FBK; kk += 4) {
             const float av = stile[(wr + li) * FSTRIDE + kk + lk];
-            const float b0 = htap[hb - kk];
-            const float b1 = htap[hb - kk + 16];
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b1, acc1, 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < FACC; ++q)
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, htap[hb - kk + 16 * q], acc[q], 0, 0, 0);
         }
     }
 #pragma unroll
-    for (int blk = 0; blk < 2; ++blk) {
-        const v4f acc = blk ? acc1 : acc0;
+    for (int blk = 0; blk < FACC; ++blk) {
         const int col = n0 + wc + 16 * blk + li;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int v = v0 + wr + 4 * lk + r;
             if (v < m && col < nb) {
                 const size_t idx = (size_t)v * nb + col;
-                float val = a.c * acc[r];
+                float val = a.c * acc[blk][r];
                 if (a.E0) val = fmaf(a.e0, a.E0[idx], val);
                 if (a.E1) val = fmaf(a.e1, a.E1[idx], val);
                 a.out[idx] = val;
@@ -390,6 +393,7 @@ hipError_t launch_symbol_max(const double* taps64, int nb, double* out, hipStrea
 int filter_blocks_x(int nb) { return (nb + FBN - 1) / FBN; }
 int filter_blocks_y(int m) { return (m + FBM - 1) / FBM; }
 
+
 // ---------------------------------------------------------------------------
 // float64 filter on the matrix cores (v_mfma_f64_16x16x4_f64), for the
 // operator norms: out = post .* D (pre .* in)  (pre / post optional).
@@ -400,20 +404,22 @@ int filter_blocks_y(int m) { return (m + FBM - 1) / FBM; }
 // layouts match the f32 instruction; the result differs: D[i][j] sits in lane
 // j + 16*(i%4), element i/4.
 typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int DBM = 32;    // views per workgroup (float64 filter)
+constexpr int DBN = 64;    // output bins per workgroup (float64 filter)
 constexpr int DBK = 64;
 constexpr int DSTRIDE = DBK + 1;     // odd pitch: 16 lanes x 8 bytes cover all 32 banks
-constexpr int DTW = FBN + DBK - 1;   // taps per stage
-constexpr int DPER = FBM * DBK / 256;
+constexpr int DTW = DBN + DBK - 1;   // taps per stage
+constexpr int DPER = DBM * DBK / 256;
 
 template <bool PRE, bool POST>
 __device__ __forceinline__ void filter_f64_body(const double* __restrict__ in, double* __restrict__ out,
                                                 const double* __restrict__ taps, const double* __restrict__ pre,
                                                 const double* __restrict__ post, int m, int nb, int bxi,
                                                 int byi) {
-    __shared__ double stile[FBM * DSTRIDE];
+    __shared__ double stile[DBM * DSTRIDE];
     __shared__ double hw[DTW + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n0 = bxi * FBN, v0 = byi * FBM;
+    const int n0 = bxi * DBN, v0 = byi * DBM;
     const int wr = (wave >> 1) * 16, wc = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
     double stg[DPER], stp[DPER];
@@ -429,7 +435,7 @@ __device__ __forceinline__ void filter_f64_body(const double* __restrict__ in, d
             stg[r] = ok ? in[idx] : 0.0;
             if (PRE) stp[r] = pre[idx];   // multiplied in at the LDS store, so all loads stay in flight
         }
-        // offsets d = col - krow in [n0 - k0 - (DBK-1), n0 - k0 + FBN - 1]
+        // offsets d = col - krow in [n0 - k0 - (DBK-1), n0 - k0 + DBN - 1]
         const int d = n0 - k0 - (DBK - 1) + tid;
         const bool tok = tid < DTW && d > -nb && d < nb;
         const double tv = taps[tok ? nb - 1 + d : 0];
@@ -489,11 +495,11 @@ __global__ __launch_bounds__(256) void norm_filter_batched(const NormItem* __res
     const BlockRef e = map[blockIdx.x];
     if (e.prob < 0) return;
     const NormItem& it = items[e.prob];
-    const int gx = (it.nb + FBN - 1) / FBN;
+    const int gx = (it.nb + DBN - 1) / DBN;
     // views whose chain has stopped are neither stepped nor read again: a
     // workgroup whose views have all stopped has nothing to do
-    const int v = (e.local / gx) * FBM + (int)threadIdx.x;
-    const int live = threadIdx.x < FBM && v < it.m && !it.done[v];
+    const int v = (e.local / gx) * DBM + (int)threadIdx.x;
+    const int live = threadIdx.x < DBM && v < it.m && !it.done[v];
     if (!__syncthreads_or(live)) return;
     filter_f64_body<true, true>(it.v[rot], it.v[(rot + 2) % 3], it.taps64, it.rs, it.rs, it.m, it.nb, e.local % gx,
                                 e.local / gx);
@@ -507,7 +513,7 @@ hipError_t launch_norm_filter_batched(const NormItem* it, const BlockRef* map, i
 
 hipError_t launch_filter_f64(const double* in, double* out, const double* taps64, const double* pre,
                              const double* post, int m, int nb, hipStream_t s) {
-    dim3 grid((nb + FBN - 1) / FBN, (m + FBM - 1) / FBM);
+    dim3 grid((nb + DBN - 1) / DBN, (m + DBM - 1) / DBM);
     if (pre && post)
         filter_f64_kernel<true, true><<<grid, 256, 0, s>>>(in, out, taps64, pre, post, m, nb);
     else if (pre)
@@ -518,5 +524,8 @@ hipError_t launch_filter_f64(const double* in, double* out, const double* taps64
         filter_f64_kernel<false, false><<<grid, 256, 0, s>>>(in, out, taps64, pre, post, m, nb);
     return hipGetLastError();
 }
+
+int norm_blocks_x(int nb) { return (nb + DBN - 1) / DBN; }
+int norm_blocks_y(int m) { return (m + DBM - 1) / DBM; }
 
 }  // namespace ctpd

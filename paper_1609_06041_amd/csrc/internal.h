@@ -199,6 +199,9 @@ hipError_t launch_filter_batched(const BatchItem* items, const BlockRef* map, in
                                  int max_nb, hipStream_t s);
 int filter_blocks_x(int nb);
 int filter_blocks_y(int m);
+// float64 (norm) filter work decomposition
+int norm_blocks_x(int nb);
+int norm_blocks_y(int m);
 
 // batched W^-1/2 D W^-1/2 applied to v[rot] into v[(rot+2)%3] (float64)
 hipError_t launch_norm_filter_batched(const NormItem* it, const BlockRef* map, int nblocks, int rot,
