@@ -13,8 +13,9 @@ default tau; the handle computes it at its first solve (reported as
 ``setup_ms_cold``, in the warm-up) and reuses it.  ``value`` = PD iterations
 per second over the whole job (20 * steps / elapsed).  Also reported: the iteration loop alone, A and A^T
 throughput in G(pixel, view) updates/s, the filter's matrix-core rate, the
-TV step's bandwidth, the roofline of the dominant kernel (A^T), and the FP64
-oracle timed on the host on a bounded sample of the same workload.
+TV step's bandwidth, the roofline of the dominant kernel (A, the forward
+projector; A^T's is reported beside it), and the FP64 oracle timed on the host
+on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline]
 """
@@ -39,10 +40,14 @@ PEAK_FP32_VECTOR_TFLOPS = 78.6
 # max(0, len -+ f len2 ...) (2 x (FMA + max) = 6), the two weighted taps
 # accumulated (2 FMA = 4).
 AT_FLOP_PER_UPDATE = 15.0
+# Algorithmic FLOP per in-image ray step of A: sample position
+# s = s0 + u su + t st (2 FMA = 4), its fraction (1), the interpolation
+# a + f (b - a) (sub + FMA = 3), the accumulation (1).
+A_FLOP_PER_STEP = 9.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 N_INSTANCES = 3   # independent inputs cycled through by the timed solves
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "adjoint_kernel_lowdose512_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "projector_kernels_lowdose512_traffic.md")
 
 
 def log(msg: str) -> None:
@@ -54,9 +59,35 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per A^T launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
+def forward_ray_steps(n: int, m: int, nb: int) -> int:
+    """In-image (ray, step) pairs of the Joseph forward projector: the steps t of
+    ray (v, u) whose sample s(t, u) = s0 + u su + t st lies in (-1, n), i.e. that
+    have a nonzero tap (views at v pi / m; row views step over rows)."""
+    import numpy as np
+    c, cd = 0.5 * (n - 1), 0.5 * (nb - 1)
+    u = np.arange(nb, dtype=np.float64)
+    total = 0
+    for v in range(m):
+        th = v * np.pi / m
+        cs, sn = np.cos(th), np.sin(th)
+        row = 4 * v <= m or 4 * v >= 3 * m
+        a, o = (cs, sn) if row else (sn, cs)
+        base = (c * o - cd) / a + c + u / a
+        st = -o / a
+        if st == 0.0:
+            total += int(np.count_nonzero((base > -1.0) & (base < n))) * n
+            continue
+        t1, t2 = (-1.0 - base) / st, (n - base) / st
+        lo, hi = np.minimum(t1, t2), np.maximum(t1, t2)
+        first = np.maximum(np.floor(lo) + 1, 0)
+        last = np.minimum(np.ceil(hi) - 1, n - 1)
+        total += int(np.clip(last - first + 1, 0, None).sum())
+    return total
+
+
+def read_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` ("forward" or "adjoint") from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -67,7 +98,7 @@ def read_traffic():
     if vals.get("source_sha256_16") != kernel_source_hash():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[f"{kernel}_hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
@@ -392,7 +423,7 @@ def main() -> int:
                          "and reverse pass vs 16 plain solves")
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 --pmc: a plain 256 MiB device copy (counter calibration) "
-                         "followed by 5 A^T launches on the workload; prints nothing else")
+                         "followed by 5 A and 5 A^T launches on the workload; prints nothing else")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -430,6 +461,10 @@ def main() -> int:
         dst = torch.empty_like(src)
         dst.copy_(src)
         img_out = torch.empty((n, n), device=dev, dtype=torch.float32)
+        sino = torch.empty((m, nb), device=dev, dtype=torch.float32)
+        img = torch.rand((n, n), device=dev, dtype=torch.float32)
+        for _ in range(5):
+            op.project(img, out=sino)
         for _ in range(5):
             op.backproject(b, out=img_out)
         torch.cuda.synchronize()
@@ -469,8 +504,10 @@ def main() -> int:
     pz = torch.zeros((2, n, n), device=dev, dtype=torch.float32)
     t_tv10 = time_op(lambda: op.tv_prox(img, 1e-3, pz, n_iter=10, out=img_out), stream, max(reps // 5, 5))
     updates = float(m) * n * n
+    ray_steps = float(forward_ray_steps(n, m, nb))
+    a_tflops = A_FLOP_PER_STEP * ray_steps / (t_a * 1e-3) / 1e12
     at_tflops = AT_FLOP_PER_UPDATE * updates / (t_at * 1e-3) / 1e12
-    traffic = read_traffic()
+    peak_note = "FP32 vector FMA rate without packed instructions: 256 CU x 64 lanes x 2.4 GHz x 2"
     rec = {
         "metric": "512x512/720-view PD iters/s (Algorithm 1, set-up included) + A, A^T Gupdates/s",
         "value": value,
@@ -503,12 +540,16 @@ def main() -> int:
         "op_ms": {"A": t_a, "AT": t_at, "D": t_d, "tv_step": t_tv10 / 10.0},
         "filter_mfma_tflops": 2.0 * m * nb * nb / (t_d * 1e-3) / 1e12,
         "tv_step_gbs": 20.0 * n * n / (t_tv10 / 10.0 * 1e-3) / 1e9,
-        "roofline": {"kernel": "adjoint_kernel (A^T, one launch per ctpd_backproject)", "bound": "alu",
-                     "achieved": at_tflops, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": at_tflops / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
-                     "work_per_launch": f"{updates:.4g} (pixel, view) updates x {AT_FLOP_PER_UPDATE:.0f} FLOP",
-                     "peak_note": "FP32 vector FMA rate without packed instructions: 256 CU x 64 lanes x "
-                                  "2.4 GHz x 2"},
+        "roofline": {"kernel": "forward_kernel (A, one launch per ctpd_project)", "bound": "alu",
+                     "achieved": a_tflops, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": a_tflops / PEAK_FP32_VECTOR_TFLOPS, "traffic": read_traffic("forward"),
+                     "work_per_launch": f"{ray_steps:.4g} in-image ray steps x {A_FLOP_PER_STEP:.0f} FLOP",
+                     "peak_note": peak_note},
+        "roofline_at": {"kernel": "adjoint_kernel (A^T, one launch per ctpd_backproject)", "bound": "alu",
+                        "achieved": at_tflops, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                        "frac": at_tflops / PEAK_FP32_VECTOR_TFLOPS, "traffic": read_traffic("adjoint"),
+                        "work_per_launch": f"{updates:.4g} (pixel, view) updates x {AT_FLOP_PER_UPDATE:.0f} FLOP",
+                        "peak_note": peak_note},
         "accuracy": "parity-tested vs the FP64 oracle: A, A^T, D rel l2 <= 1e-5; x^k rel l2 <= 1e-4; "
                     "cost rel <= 1e-5 (tests/test_gpu_*.py)",
         "paper_context": "paper (no hardware stated): ~10 Algorithm-1 iterations match GIST at 1000; "
