@@ -211,8 +211,11 @@ int setup_lambda_a(ctpd_op* op, int kmax, Lanczos* L, bool filt, const float* wg
 
 
 int filter(ctpd_op* op, int mode, const float* in0, const float* in1, const float* in2, const float* in3,
-           const float* E0, float e0, const float* E1, float e1, float c, float* out) {
+           const float* E0, float e0, const float* E1, float e1, float c, float* out, const float* Sw,
+           float* Sout) {
     FilterArgs a{};
+    a.Sw = Sw;
+    a.Sout = Sout;
     a.in0 = in0;
     a.in1 = in1;
     a.in2 = in2;
@@ -225,6 +228,14 @@ int filter(ctpd_op* op, int mode, const float* in0, const float* in1, const floa
     a.mode = mode;
     a.out = out;
     HIP_TRY(launch_filter_f32(a, op->taps32, op->m, op->nb, op->stream));
+    return CTPD_OK;
+}
+
+// y = A x - rb - rw .* rm (rw null: A x - rb): the dual update's filter input
+// written by the projector itself
+int project_resid(ctpd_op* op, const float* x, const float* rb, const float* rw, const float* rm, float* y) {
+    HIP_TRY(launch_pad_planes<float>(x, op->xp, op->xTp, op->n, op->stream));
+    HIP_TRY(launch_forward_resid(op->xp, op->xTp, y, op->views, op->n, op->m, op->nb, rb, rw, rm, op->stream));
     return CTPD_OK;
 }
 
@@ -493,6 +504,7 @@ int ctpd_op_create(const ctpd_geometry* g, void* stream, ctpd_op** out) {
         for (auto& p : op->mu) ALLOC(p, op->I);
         ALLOC(op->mubar, op->I);
         ALLOC(op->q, op->I);
+        ALLOC(op->sx, op->I);
         ALLOC(op->winv, op->I);
         ALLOC(op->taps64, 2 * op->nb - 1);
         ALLOC(op->taps32, 2 * op->nb - 1);
@@ -516,7 +528,7 @@ void ctpd_op_destroy(ctpd_op* op) {
     if (!op) return;
     if (op->stream || op->views) (void)hipStreamSynchronize(op->stream);
     void* ptrs[] = {op->views, op->xp, op->xTp, op->x, op->z, op->p[0], op->p[1], op->mu[0], op->mu[1], op->mu[2],
-                    op->mubar, op->q, op->winv, op->taps64, op->taps32, op->partials, op->red, op->cost_dev,
+                    op->mubar, op->q, op->sx, op->winv, op->taps64, op->taps32, op->partials, op->red, op->cost_dev,
                     op->img64[0], op->img64[1], op->img64[2], op->pad64[0], op->pad64[1], op->sino64[0], op->sino64[1],
                     op->sino64[2], op->sino64[3], op->sino64[4], op->sino64[5], op->lz[0], op->lz[1],
                     op->lz_partials[0], op->lz_partials[1], op->xbar};
@@ -653,10 +665,17 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
     float* pcur = op->p[0];
     const float fs = (float)sigma, ft = (float)tau, lam = (float)(tau * beta);
     const float tvstep = lam > 0 ? (float)(k.tv_step / (tau * beta)) : 0.f;
+    // Without the cost monitor the two filters run on inputs written by the
+    // kernels before them (same arithmetic as the fused prologues): the
+    // projector writes r = A x - b - W^-1 mu, and the dual update writes
+    // W^-1 (mu^{k+1} - mu^k) for the next extrapolation.
+    const bool fused = !k.record;
     for (int it = 0; it < iters; ++it) {
         // Step 1: extrapolation (Eq. 18 / Algorithm 1)
         if (it == 0)
             r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, -fs, op->mubar);
+        else if (fused)
+            r = filter(op, FILT_PLAIN, op->sx, nullptr, nullptr, nullptr, mu, 2.f, mup, -1.f, -fs, op->mubar);
         else
             r = filter(op, FILT_EXTRAP, op->winv, mu, mup, nullptr, mu, 2.f, mup, -1.f, -fs, op->mubar);
         if (r) return r;
@@ -669,8 +688,15 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
             return r;
         pcur = pnew;
         // Step 3: mu^{k+1} = mu^k + sigma D (A x^{k+1} - b - W^-1 mu^k)
-        if ((r = project(op, op->x, op->q))) return r;
-        if ((r = filter(op, FILT_DUAL_LD, op->q, b, op->winv, mu, mu, 1.f, nullptr, 0.f, fs, mun))) return r;
+        if (fused) {
+            if ((r = project_resid(op, op->x, b, op->winv, mu, op->q))) return r;
+            if ((r = filter(op, FILT_PLAIN, op->q, nullptr, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun,
+                            op->winv, op->sx)))
+                return r;
+        } else {
+            if ((r = project(op, op->x, op->q))) return r;
+            if ((r = filter(op, FILT_DUAL_LD, op->q, b, op->winv, mu, mu, 1.f, nullptr, 0.f, fs, mun))) return r;
+        }
         if (k.record) {
             if ((r = reduce(op, RED_WRES_F32, op->q, b, w, I, 0))) return r;
             HIP_TRY(launch_tv_norm(op->x, op->n, op->partials, op->cost_dev + 6 * it, s));
@@ -781,9 +807,17 @@ int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
                          &pnew)))
             return r;
         pcur = pnew;
-        // Step 3: mu^{k+1} = mu^k + sigma D (A x^{k+1} - b)
-        if ((r = project(op, op->x, op->q))) return r;
-        if ((r = filter(op, FILT_DUAL_FV, op->q, b, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun))) return r;
+        // Step 3: mu^{k+1} = mu^k + sigma D (A x^{k+1} - b); without the cost
+        // monitor the projector writes the residual itself
+        if (!k.record) {
+            if ((r = project_resid(op, op->x, b, nullptr, nullptr, op->q))) return r;
+            if ((r = filter(op, FILT_PLAIN, op->q, nullptr, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun)))
+                return r;
+        } else {
+            if ((r = project(op, op->x, op->q))) return r;
+            if ((r = filter(op, FILT_DUAL_FV, op->q, b, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun)))
+                return r;
+        }
         if (k.record) {
             if ((r = reduce(op, RED_SQDIFF_F32, op->q, b, nullptr, I, 0))) return r;
             HIP_TRY(launch_tv_norm(op->x, op->n, op->partials, op->cost_dev + 6 * it, s));

@@ -135,7 +135,7 @@ struct FilterIn {
     static constexpr int N = MODE == FILT_DUAL_LD ? 4 : MODE == FILT_EXTRAP ? 3 : MODE == FILT_DUAL_FV ? 2 : 1;
     __device__ static __forceinline__ float combine(const float* r) {
         if (MODE == FILT_EXTRAP) return r[0] * (r[1] - r[2]);
-        if (MODE == FILT_DUAL_LD) return r[0] - r[1] - r[2] * r[3];
+        if (MODE == FILT_DUAL_LD) return fmaf(-r[2], r[3], r[0] - r[1]);
         if (MODE == FILT_DUAL_FV) return r[0] - r[1];
         return r[0];
     }
@@ -219,9 +219,14 @@ __device__ __forceinline__ void filter_body(const FilterArgs& a, const float* __
             if (v < m && col < nb) {
                 const size_t idx = (size_t)v * nb + col;
                 float val = a.c * acc[blk][r];
-                if (a.E0) val = fmaf(a.e0, a.E0[idx], val);
+                float e0v = 0.0f;
+                if (a.E0) {
+                    e0v = a.E0[idx];
+                    val = fmaf(a.e0, e0v, val);
+                }
                 if (a.E1) val = fmaf(a.e1, a.E1[idx], val);
                 a.out[idx] = val;
+                if (a.Sout) a.Sout[idx] = a.Sw[idx] * (val - e0v);
             }
         }
     }

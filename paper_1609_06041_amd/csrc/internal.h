@@ -34,7 +34,9 @@ enum FilterMode : int {
     FILT_DUAL_FV = 3,  // s = in0 - in1                (A x - b)
 };
 
-// out = e0 * E0 + e1 * E1 + c * (D s)   (E0 / E1 may be null)
+// out = e0 * E0 + e1 * E1 + c * (D s)   (E0 / E1 may be null); when Sout is
+// set (with E0 and Sw), also Sout = Sw .* (out - E0): the dual update writes
+// the next extrapolation's filter input W^-1 (mu^{k+1} - mu^k) this way.
 struct FilterArgs {
     const float* in0;
     const float* in1;
@@ -45,6 +47,8 @@ struct FilterArgs {
     float e0, e1, c;
     int mode;
     float* out;
+    const float* Sw;
+    float* Sout;
 };
 
 // One problem of a batched solve: its geometry, its workspaces (the buffers of
@@ -164,6 +168,10 @@ hipError_t launch_pad_planes(const T* x, T* xp, T* xTp, int n, hipStream_t s);
 template <typename T>
 hipError_t launch_forward(const T* xp, const T* xTp, T* y, const ViewGeom* views, int n, int m, int nb,
                           hipStream_t s);
+// the dual-update residual straight from the projector: y = A x - rb - rw .* rm
+// (rw null: y = A x - rb), with the arithmetic of the filter prologues
+hipError_t launch_forward_resid(const float* xp, const float* xTp, float* y, const ViewGeom* views, int n, int m,
+                                int nb, const float* rb, const float* rw, const float* rm, hipStream_t s);
 // out = alpha * xin + beta * A^T (c1 * y1 + c2 * y2)   (xin, y2 may be null)
 template <typename T>
 hipError_t launch_adjoint(const T* y1, const T* y2, T c1, T c2, const T* xin, T alpha, T beta, T* out,

@@ -38,6 +38,7 @@ struct ctpd_op {
     float* mu[3] = {nullptr, nullptr, nullptr};
     float* mubar = nullptr;
     float* q = nullptr;
+    float* sx = nullptr;   // W^-1 (mu^{k+1} - mu^k), written by the dual update for the next extrapolation
     float* winv = nullptr;
     float* xbar = nullptr;   // Chambolle-Pock extrapolated image (allocated on first use)
     // filter taps for (tap_tau, tap_kappa)
@@ -186,9 +187,12 @@ struct Lanczos {
 int run_lanczos(const std::vector<Lanczos*>& chains);
 int setup_lambda_a(ctpd_op* op, int kmax, Lanczos* L, bool filt = true, const float* wgt = nullptr);
 
+// Sout (optional, with Sw and E0): also Sout = Sw .* (out - E0)
 int filter(ctpd_op* op, int mode, const float* in0, const float* in1, const float* in2, const float* in3,
-           const float* E0, float e0, const float* E1, float e1, float c, float* out);
+           const float* E0, float e0, const float* E1, float e1, float c, float* out, const float* Sw = nullptr,
+           float* Sout = nullptr);
 int project(ctpd_op* op, const float* x, float* y);
+int project_resid(ctpd_op* op, const float* x, const float* rb, const float* rw, const float* rm, float* y);
 int tv_prox(ctpd_op* op, const float* z, float lam, int n_iter, float step, float* pin, float* scratch, float* x,
             float** pout);
 

@@ -103,9 +103,13 @@ __device__ __forceinline__ void load_taps(const __amdgpu_buffer_rsrc_t& rs, unsi
 constexpr int kBufferRsrcWord3 = 0x00020000;
 constexpr int FW_BATCH = 8;
 
+// rb (optional): write the residual A x - rb - rw .* rm (rw null: A x - rb)
+// instead of A x, with the arithmetic of the filter prologues.
 template <typename T, int FB = FW_BATCH>
 __device__ __forceinline__ void forward_body(const T* __restrict__ xp, const T* __restrict__ xTp, T* __restrict__ y,
-                                             const ViewGeom* __restrict__ views, int n, int nb, int bxi, int v) {
+                                             const ViewGeom* __restrict__ views, int n, int nb, int bxi, int v,
+                                             const T* __restrict__ rb = nullptr, const T* __restrict__ rw = nullptr,
+                                             const T* __restrict__ rm = nullptr) {
     const int u = bxi * 256 + threadIdx.x;
     const ViewGeom g = views[v];
     const int P = n + 2 * FP_PAD;
@@ -166,7 +170,28 @@ __device__ __forceinline__ void forward_body(const T* __restrict__ xp, const T* 
         sfix += dfix;
         rowb += rowstride;
     }
-    if (u < nb) y[(size_t)v * nb + u] = (acc_a + acc_d * (T)2.3283064365386962890625e-10) * (T)g.len;
+    if (u < nb) {
+        const size_t idx = (size_t)v * nb + u;
+        T q = (acc_a + acc_d * (T)2.3283064365386962890625e-10) * (T)g.len;
+        if (rb) q = rw ? fma(-rw[idx], rm[idx], q - rb[idx]) : q - rb[idx];
+        y[idx] = q;
+    }
+}
+
+__global__ __launch_bounds__(256) void forward_resid_kernel(const float* __restrict__ xp,
+                                                            const float* __restrict__ xTp, float* __restrict__ y,
+                                                            const ViewGeom* __restrict__ views, int n, int nb,
+                                                            const float* __restrict__ rb,
+                                                            const float* __restrict__ rw,
+                                                            const float* __restrict__ rm) {
+    forward_body<float>(xp, xTp, y, views, n, nb, blockIdx.x, blockIdx.y, rb, rw, rm);
+}
+
+hipError_t launch_forward_resid(const float* xp, const float* xTp, float* y, const ViewGeom* views, int n, int m,
+                                int nb, const float* rb, const float* rw, const float* rm, hipStream_t s) {
+    dim3 grid((nb + 255) / 256, m);
+    forward_resid_kernel<<<grid, 256, 0, s>>>(xp, xTp, y, views, n, nb, rb, rw, rm);
+    return hipGetLastError();
 }
 
 template <typename T>
