@@ -147,7 +147,7 @@ int queue_loop(ctpd_batch* bt, int iters, int tv_iters) {
         } while (left > 0);
         // Step 3: mu^{k+1} = mu + sigma D (A x - b - W^-1 mu)
         HIP_TRY(launch_pad_planes_batched(it, bt->map[K_PAD], bt->nblk[K_PAD], s));
-        HIP_TRY(launch_forward_batched(it, bt->map[K_FWD], bt->nblk[K_FWD], bt->tiles.fwd_batch, s));
+        HIP_TRY(launch_forward_batched(it, bt->map[K_FWD], bt->nblk[K_FWD], bt->tiles.fwd_batch, rot, s));
         HIP_TRY(launch_filter_batched(it, bt->map[K_FILT], bt->nblk[K_FILT], FILT_DUAL_LD, rot, bt->max_nb, s));
     }
     HIP_TRY(launch_batch_copy_out(it, bt->map[K_COPY], bt->nblk[K_COPY], s));
@@ -311,6 +311,7 @@ int ctpd_batch_lowdose_solve(ctpd_batch* bt, const float* const* b, const float*
         it.x = op->x;
         it.z = op->z;
         it.q = op->q;
+        it.sx = op->sx;
         it.mubar = op->mubar;
         for (int j = 0; j < 3; ++j) it.mu[j] = op->mu[j];
         for (int j = 0; j < 2; ++j) it.p[j] = op->p[j];

@@ -256,8 +256,11 @@ hipError_t launch_filter_f32(const FilterArgs& a, const float* taps32, int m, in
 }
 
 // Batched filter: the solver's two uses of D per iteration, with the
-// prologue / epilogue operands taken from each problem's workspaces
-// (mu^k = mu[rot], mu^{k-1} = mu[(rot+1)%3], mu^{k+1} -> mu[(rot+2)%3]).
+// epilogue operands taken from each problem's workspaces (mu^k = mu[rot],
+// mu^{k-1} = mu[(rot+1)%3], mu^{k+1} -> mu[(rot+2)%3]).  The filter inputs are
+// written by the kernels before: the dual update's residual by the projector
+// (q), the extrapolation's W^-1 (mu^k - mu^{k-1}) by the previous dual update
+// (sx), so every launch runs the plain prologue.
 template <int MODE>
 __global__ __launch_bounds__(256) void filter_batched(const BatchItem* __restrict__ items,
                                                       const BlockRef* __restrict__ map, int rot) {
@@ -268,33 +271,30 @@ __global__ __launch_bounds__(256) void filter_batched(const BatchItem* __restric
     float* mu = it.mu[rot];
     float* mup = it.mu[(rot + 1) % 3];
     FilterArgs a{};
-    a.mode = MODE;
+    a.mode = FILT_PLAIN;
     if (MODE == FILT_PLAIN) {   // k = 0: mubar = -sigma D b
         a.in0 = it.b;
         a.c = -it.sigma;
         a.out = it.mubar;
     } else if (MODE == FILT_EXTRAP) {   // mubar = 2 mu - mu_prev - sigma D W^-1 (mu - mu_prev)
-        a.in0 = it.winv;
-        a.in1 = mu;
-        a.in2 = mup;
+        a.in0 = it.sx;
         a.E0 = mu;
         a.e0 = 2.f;
         a.E1 = mup;
         a.e1 = -1.f;
         a.c = -it.sigma;
         a.out = it.mubar;
-    } else {   // mu^{k+1} = mu + sigma D (A x - b [- W^-1 mu])
+    } else {   // mu^{k+1} = mu + sigma D (A x - b [- W^-1 mu]), and the next extrapolation's input
         a.in0 = it.q;
-        a.in1 = it.b;
-        a.in2 = it.winv;
-        a.in3 = mu;
         a.E0 = mu;
         a.e0 = 1.f;
         a.c = it.sigma;
         a.out = it.mu[(rot + 2) % 3];
+        a.Sw = it.winv;
+        a.Sout = it.sx;
     }
     const int gx = (it.nb + FBN - 1) / FBN;
-    filter_body<MODE>(a, it.taps, it.m, it.nb, smem, e.local % gx, e.local / gx);
+    filter_body<FILT_PLAIN>(a, it.taps, it.m, it.nb, smem, e.local % gx, e.local / gx);
 }
 
 hipError_t launch_filter_batched(const BatchItem* items, const BlockRef* map, int nblocks, int mode, int rot,

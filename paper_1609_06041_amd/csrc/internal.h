@@ -63,7 +63,8 @@ struct BatchItem {
     const float* winv;
     float* x;
     float* z;
-    float* q;
+    float* q;        // the dual update's residual A x - b - W^-1 mu (written by the projector)
+    float* sx;       // W^-1 (mu^{k+1} - mu^k) for the next extrapolation (written by the dual update)
     float* mubar;
     float* mu[3];
     float* p[2];
@@ -181,7 +182,8 @@ hipError_t launch_adjoint(const T* y1, const T* y2, T c1, T c2, const T* xin, T 
 //   pad planes of x, q = A x, z = x - tau A^T mubar (two: z = x - tau A^T (2 mu^k - mu^{k-1}))
 hipError_t launch_pad_planes_batched(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s);
 // fb: taps in flight per lane (4 or 8), a tuning choice of the batch
-hipError_t launch_forward_batched(const BatchItem* items, const BlockRef* map, int nblocks, int fb,
+// (the batch's projector writes the residual A x - b - W^-1 mu[rot] into q)
+hipError_t launch_forward_batched(const BatchItem* items, const BlockRef* map, int nblocks, int fb, int rot,
                                   hipStream_t s);
 hipError_t launch_adjoint_batched(const BatchItem* items, const BlockRef* map, int nblocks, bool two, int rot,
                                   hipStream_t s);

@@ -430,12 +430,13 @@ __global__ __launch_bounds__(256) void pad_planes_batched(const BatchItem* __res
 
 template <int FB>
 __global__ __launch_bounds__(256) void forward_batched(const BatchItem* __restrict__ items,
-                                                       const BlockRef* __restrict__ map) {
+                                                       const BlockRef* __restrict__ map, int rot) {
     const BlockRef e = map[blockIdx.x];
     if (e.prob < 0) return;
     const BatchItem& it = items[e.prob];
     const int gx = (it.nb + 255) / 256;
-    forward_body<float, FB>(it.xp, it.xTp, it.q, it.views, it.n, it.nb, e.local % gx, e.local / gx);
+    forward_body<float, FB>(it.xp, it.xTp, it.q, it.views, it.n, it.nb, e.local % gx, e.local / gx, it.b,
+                            it.lowdose ? it.winv : nullptr, it.mu[rot]);
 }
 
 // z = x - tau A^T mubar  (mode 0), or z = x - tau A^T (2 mu - mu_prev)  (mode 1, few-view k >= 1)
@@ -457,12 +458,12 @@ hipError_t launch_pad_planes_batched(const BatchItem* items, const BlockRef* map
     return hipGetLastError();
 }
 
-hipError_t launch_forward_batched(const BatchItem* items, const BlockRef* map, int nblocks, int fb,
+hipError_t launch_forward_batched(const BatchItem* items, const BlockRef* map, int nblocks, int fb, int rot,
                                   hipStream_t s) {
     if (fb == 4)
-        forward_batched<4><<<nblocks, 256, 0, s>>>(items, map);
+        forward_batched<4><<<nblocks, 256, 0, s>>>(items, map, rot);
     else
-        forward_batched<8><<<nblocks, 256, 0, s>>>(items, map);
+        forward_batched<8><<<nblocks, 256, 0, s>>>(items, map, rot);
     return hipGetLastError();
 }
 
