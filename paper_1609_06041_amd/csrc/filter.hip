@@ -402,15 +402,18 @@ int filter_blocks_y(int m) { return (m + FBM - 1) / FBM; }
 // ---------------------------------------------------------------------------
 // float64 filter on the matrix cores (v_mfma_f64_16x16x4_f64), for the
 // operator norms: out = post .* D (pre .* in)  (pre / post optional).
-// Same tiling as the float32 kernel (32 views x 64 bins per workgroup, wave w
-// owns rows 16*(w/2), columns 32*(w%2)); per 64-bin stage of the input the
+// DBM views x DBN bins per workgroup cut into 16 x 16 MFMA tiles, wave w owns
+// DACC consecutive tiles of one tile row; per 64-bin stage of the input the
 // workgroup keeps only the 127 taps that stage touches, and the next stage is
 // loaded into registers while the current one runs.  The A and B operand
 // layouts match the f32 instruction; the result differs: D[i][j] sits in lane
 // j + 16*(i%4), element i/4.
 typedef double v4d __attribute__((ext_vector_type(4)));
-constexpr int DBM = 32;    // views per workgroup (float64 filter)
+constexpr int DBM = 16;    // views per workgroup (float64 filter)
 constexpr int DBN = 64;    // output bins per workgroup (float64 filter)
+constexpr int DTPR = DBN / 16;            // 16 x 16 output tiles per tile row
+constexpr int DACC = DBM * DBN / 1024;    // accumulators per wave (4 waves)
+static_assert(DACC >= 1 && DTPR % DACC == 0, "a wave's tiles lie in one tile row");
 constexpr int DBK = 64;
 constexpr int DSTRIDE = DBK + 1;     // odd pitch: 16 lanes x 8 bytes cover all 32 banks
 constexpr int DTW = DBN + DBK - 1;   // taps per stage
@@ -425,7 +428,7 @@ __device__ __forceinline__ void filter_f64_body(const double* __restrict__ in, d
     __shared__ double hw[DTW + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n0 = bxi * DBN, v0 = byi * DBM;
-    const int wr = (wave >> 1) * 16, wc = (wave & 1) * 32;
+    const int wr = (wave * DACC / DTPR) * 16, wc = (wave * DACC % DTPR) * 16;
     const int li = lane & 15, lk = lane >> 4;
     double stg[DPER], stp[DPER];
     double tstg = 0.0;
@@ -446,7 +449,9 @@ __device__ __forceinline__ void filter_f64_body(const double* __restrict__ in, d
         const double tv = taps[tok ? nb - 1 + d : 0];
         tstg = tok ? tv : 0.0;
     };
-    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    v4d acc[DACC];
+#pragma unroll
+    for (int q = 0; q < DACC; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
     fetch(0);
     for (int k0 = 0; k0 < nb; k0 += DBK) {
         __syncthreads();
@@ -464,22 +469,20 @@ __device__ __forceinline__ void filter_f64_body(const double* __restrict__ in, d
 #pragma unroll 4
         for (int kk = 0; kk < DBK; kk += 4) {
             const double av = stile[(wr + li) * DSTRIDE + kk + lk];
-            const double b0 = hw[hb - kk];
-            const double b1 = hw[hb - kk + 16];
-            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, acc1, 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < DACC; ++q)
+                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, hw[hb - kk + 16 * q], acc[q], 0, 0, 0);
         }
     }
 #pragma unroll
-    for (int blk = 0; blk < 2; ++blk) {
-        const v4d acc = blk ? acc1 : acc0;
+    for (int blk = 0; blk < DACC; ++blk) {
         const int col = n0 + wc + 16 * blk + li;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int v = v0 + wr + lk + 4 * r;   // f64 16x16x4: D[i][j] in lane j + 16*(i%4), element i/4
             if (v < m && col < nb) {
                 const size_t idx = (size_t)v * nb + col;
-                double val = acc[r];
+                double val = acc[blk][r];
                 if (POST) val *= post[idx];
                 out[idx] = val;
             }
