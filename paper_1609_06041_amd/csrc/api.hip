@@ -79,6 +79,33 @@ int ensure_taps(ctpd_op* op, double tau, double kappa) {
     return CTPD_OK;
 }
 
+int ensure_sym(ctpd_op* op) {
+    if (!op->hv_sym) ALLOC(op->hv_sym, 1 + kSymBlocks);
+    return CTPD_OK;
+}
+
+int ensure_taps_default(ctpd_op* op, double kappa) {
+    const double tau = kTauMultLowdose * M_PI * kappa / (2.0 * op->m);
+    if (op->tap_tau == tau && op->tap_kappa == kappa) return CTPD_OK;
+    const int ntap = 2 * op->nb - 1;
+    if (!op->taps1) {
+        ALLOC(op->taps1, ntap);
+        ALLOC(op->sym1, 1 + kSymBlocks);
+        // taps32 is overwritten below
+        HIP_TRY(launch_taps(op->taps1, op->taps32, op->nb, op->m, kTauMultLowdose * M_PI / (2.0 * op->m), 1.0,
+                            op->stream));
+        HIP_TRY(launch_symbol_max(op->taps1, op->nb, op->sym1, op->stream));
+    }
+    int r;
+    if ((r = ensure_sym(op))) return r;
+    HIP_TRY(launch_taps_scale(op->taps1, ntap, kappa, op->taps64, op->taps32, op->sym1, op->hv_sym, op->stream));
+    op->tap_tau = tau;
+    op->tap_kappa = kappa;
+    op->hv_sym_tau = tau;
+    op->hv_sym_kappa = kappa;
+    return CTPD_OK;
+}
+
 int ensure_f64(ctpd_op* op) {
     if (op->img64[0]) return CTPD_OK;
     for (auto& p : op->img64) ALLOC(p, op->J);
@@ -340,7 +367,8 @@ int ensure_hv(ctpd_op* op, int kmax) {
         ALLOC(op->hv_theta, op->m);
         ALLOC(op->hv_done, op->m);
         ALLOC(op->hv_maxinv, op->m);
-        ALLOC(op->hv_sym, 1 + kSymBlocks);
+        int r = ensure_sym(op);
+        if (r) return r;
     }
     if (op->hv_cap < kmax) {
         if (op->hv_al) (void)hipFree(op->hv_al);
@@ -388,10 +416,13 @@ int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, cons
     }
     HIP_TRY(hipMemcpyAsync(items, items_host, sizeof(NormItem) * P, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_rows_start(items, rows, nrows, 2, s));
+    // The first check comes after one step: the Ritz values are then the start
+    // vectors' Rayleigh quotients, already close enough to lambda_h for the
+    // eigenvalue bounds to stop most views; later checks every kRound steps.
     constexpr int kRound = 8;
     int j = 0;
     for (bool running = true; running && j < kmax;) {
-        const int j1 = std::min(kmax, j + kRound);
+        const int j1 = std::min(kmax, j + (j == 0 ? 1 : kRound));
         for (; j < j1; ++j) {
             const int rot = (3 - j % 3) % 3;
             HIP_TRY(launch_norm_filter_batched(items, filt, nfilt, rot, s));
@@ -427,7 +458,7 @@ int lowdose_setup_begin(ctpd_op* op, const float* b, const float* w, const Knobs
     S->kappa = op->red_host[0] / (double)I;
     S->tau = k.tau > 0 ? k.tau : kTauMultLowdose * M_PI * S->kappa / (2.0 * op->m);
     HIP_TRY(launch_inverse_f32(op->winv, w, I, op->stream));
-    if ((r = ensure_taps(op, S->tau, S->kappa))) return r;
+    if ((r = k.tau > 0 ? ensure_taps(op, S->tau, S->kappa) : ensure_taps_default(op, S->kappa))) return r;
     S->sigma = k.sigma;
     S->norms = !(S->sigma > 0);
     if (S->norms) {
@@ -543,8 +574,8 @@ void ctpd_op_destroy(ctpd_op* op) {
     }
     if (op->fork) (void)hipEventDestroy(op->fork);
     free_unrolled(op->uw);
-    void* hv[] = {op->hv_al,   op->hv_b2,   op->hv_b0,  op->hv_theta,  op->hv_done, op->hv_item,
-                  op->hv_rows, op->hv_filt, op->hv_sum, op->hv_maxinv, op->hv_sym};
+    void* hv[] = {op->hv_al,   op->hv_b2,   op->hv_b0,  op->hv_theta,  op->hv_done, op->hv_item, op->hv_rows,
+                  op->hv_filt, op->hv_sum, op->hv_maxinv, op->hv_sym,   op->taps1,   op->sym1};
     for (void* p : hv)
         if (p) (void)hipFree(p);
     if (op->hv_item_host) (void)hipHostFree(op->hv_item_host);

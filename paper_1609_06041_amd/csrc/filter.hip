@@ -386,6 +386,25 @@ __global__ __launch_bounds__(256) void symbol_final_kernel(const double* __restr
     }
 }
 
+__global__ __launch_bounds__(256) void taps_scale_kernel(const double* __restrict__ taps1, int ntap, double kappa,
+                                                         double* __restrict__ taps64, float* __restrict__ taps32,
+                                                         const double* __restrict__ sym1,
+                                                         double* __restrict__ sym_out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < ntap) {
+        const double t = taps1[i] / kappa;
+        taps64[i] = t;
+        taps32[i] = (float)t;
+    }
+    if (i == 0 && sym_out) sym_out[0] = sym1[0] / kappa;
+}
+
+hipError_t launch_taps_scale(const double* taps1, int ntap, double kappa, double* taps64, float* taps32,
+                             const double* sym1, double* sym_out, hipStream_t s) {
+    taps_scale_kernel<<<(ntap + 255) / 256, 256, 0, s>>>(taps1, ntap, kappa, taps64, taps32, sym1, sym_out);
+    return hipGetLastError();
+}
+
 hipError_t launch_symbol_max(const double* taps64, int nb, double* out, hipStream_t s) {
     symbol_grid_kernel<<<kSymBlocks, 256, 0, s>>>(taps64, nb, out + 1);
     hipError_t e = hipGetLastError();

@@ -286,6 +286,9 @@ hipError_t launch_rows_step(const NormItem* it, const RowRef* rows, int nrows, i
 // launch_taps writes them) into out[0]; out[1 ..] is scratch (kSymBlocks doubles)
 constexpr int kSymBlocks = 64;
 hipError_t launch_symbol_max(const double* taps64, int nb, double* out, hipStream_t s);
+// taps64 = taps1 / kappa (and taps32 = float of it); sym_out[0] = sym1[0] / kappa when sym_out is set
+hipError_t launch_taps_scale(const double* taps1, int ntap, double kappa, double* taps64, float* taps32,
+                             const double* sym1, double* sym_out, hipStream_t s);
 hipError_t launch_rows_ritz(const NormItem* it, const RowRef* rows, int nrows, int count, int steps, double tol,
                             hipStream_t s);
 // workgroups of a float64 reduction over len elements

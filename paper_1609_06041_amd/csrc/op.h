@@ -45,6 +45,10 @@ struct ctpd_op {
     double* taps64 = nullptr;
     float* taps32 = nullptr;
     double tap_tau = -1.0, tap_kappa = -1.0;
+    // at the default low-dose tau the taps are taps1 / kappa, taps1 those at
+    // kappa = 1 (a property of the geometry), and so is the symbol bound
+    double* taps1 = nullptr;   // 2 nb - 1 doubles
+    double* sym1 = nullptr;    // 1 + kSymBlocks doubles (bound of the symbol of taps1 in [0])
     // reductions
     double* partials = nullptr;
     double* red = nullptr;        // device, 3 * kRedSlots doubles
@@ -113,6 +117,10 @@ int einval(const char* msg);
 std::vector<ViewGeom> make_views(int n, int m, int nb);
 int sync(ctpd_op* op);
 int ensure_taps(ctpd_op* op, double tau, double kappa);
+// the taps at the default low-dose tau for this kappa (and the symbol bound
+// when the per-view lambda_h buffers exist), scaled from the cached kappa = 1 set
+int ensure_taps_default(ctpd_op* op, double kappa);
+int ensure_sym(ctpd_op* op);
 int ensure_f64(ctpd_op* op);
 int reduce(ctpd_op* op, int kind, const void* a, const void* b, const void* c, size_t len, int slot);
 int read_red(ctpd_op* op);

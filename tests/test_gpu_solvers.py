@@ -192,3 +192,22 @@ def test_lambda_h_equals_the_largest_per_view_eigenvalue(gpu):
     lam = max(eigh(rs[v][:, None] * T * rs[v][None, :], eigvals_only=True, subset_by_index=[nb - 1, nb - 1])[0]
               for v in range(m))
     assert info["lambda_h"] == pytest.approx(lam, rel=1e-6)
+
+
+@pytest.mark.parametrize("algo", ["lowdose", "fewview"])
+def test_fused_filter_inputs_equal_the_prologue_path(gpu, algo):
+    # without the cost monitor the projector writes the dual-update residual
+    # and the dual update writes the next extrapolation's input; with it, the
+    # filters form them in their prologues -- the same arithmetic, so the
+    # iterates agree bit for bit
+    n, m, nb = 64, 90, 96
+    b, w = lowdose_inputs(n, m, nb, seed=31)
+    with ctpd.Operator(n, m, nb) as op:
+        if algo == "lowdose":
+            x0, i0 = op.lowdose_solve(dev(b), dev(w), 0.01, 12)
+            x1, i1 = op.lowdose_solve(dev(b), dev(w), 0.01, 12, record_cost=True)
+        else:
+            x0, i0 = op.fewview_solve(dev(b), 12)
+            x1, i1 = op.fewview_solve(dev(b), 12, record_cost=True)
+        assert i0["sigma"] == i1["sigma"] and i0["tau"] == i1["tau"]
+        np.testing.assert_array_equal(host(x0), host(x1))
