@@ -416,13 +416,10 @@ int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, cons
     }
     HIP_TRY(hipMemcpyAsync(items, items_host, sizeof(NormItem) * P, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_rows_start(items, rows, nrows, 2, s));
-    // The first check comes after one step: the Ritz values are then the start
-    // vectors' Rayleigh quotients, already close enough to lambda_h for the
-    // eigenvalue bounds to stop most views; later checks every kRound steps.
     constexpr int kRound = 8;
     int j = 0;
     for (bool running = true; running && j < kmax;) {
-        const int j1 = std::min(kmax, j + (j == 0 ? 1 : kRound));
+        const int j1 = std::min(kmax, j + kRound);
         for (; j < j1; ++j) {
             const int rot = (3 - j % 3) % 3;
             HIP_TRY(launch_norm_filter_batched(items, filt, nfilt, rot, s));
