@@ -258,7 +258,9 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
     __shared__ long long colt[AT_G][AT_VC][AT_T];
     __shared__ long long rowt[AT_G][AT_VC][9];
     __shared__ T plen[AT_G][AT_VC], plen2[AT_G][AT_VC];
-    const int tid = threadIdx.x, h = tid >> 8, l = tid & 255;
+    // h is the same on every lane of a wave: keep it (and the LDS bases built
+    // from it) in scalar registers
+    const int tid = threadIdx.x, h = __builtin_amdgcn_readfirstlane(tid >> 8), l = tid & 255;
     const int tx = l & 31, ty = l >> 5;
     const int x0 = bxi * AT_T, y0 = byi * AT_T;
     const double c = 0.5 * (double)(n - 1);
