@@ -169,7 +169,8 @@ def cpu_baseline(b64, w64, beta, n, m, nb, tau, sigma, stride: int = 4) -> dict:
 
 def compare(dev) -> int:
     """Iterations of the preconditioned solvers needed to match 1000 iterations of
-    the unpreconditioned comparators (the paper's Sec. 4 comparison)."""
+    the unpreconditioned comparators (the paper's Sec. 4 comparison), and the
+    same iteration without its preconditioner (D = I) as an ablation."""
     import numpy as np
     import torch
 
@@ -191,7 +192,10 @@ def compare(dev) -> int:
         xg = xg.cpu().numpy()
         _, ig_t = op.gist_lowdose_solve(b, w, beta, 1000)
         _, ia_t = op.lowdose_solve(b, w, beta, 20)
-    fa, fg = ia["cost"], ig["cost"]
+        log("Algorithm 1 with D = I (no preconditioner), 1000 iterations, cost recorded")
+        xi, ii = op.app_identity_lowdose_solve(b, w, beta, 1000, record_cost=True)
+        xi = xi.cpu().numpy()
+    fa, fg, fi = ia["cost"], ig["cost"], ii["cost"]
     k_match = next((k + 1 for k in range(len(fa)) if fa[k] <= fg[-1]), None)
     out["lowdose_512"] = {
         "algorithm1_cost": [float(v) for v in fa],
@@ -201,6 +205,12 @@ def compare(dev) -> int:
         "rmse_algorithm1_20": float(np.sqrt(((xa - xt) ** 2).mean())),
         "rmse_gist_1000": float(np.sqrt(((xg - xt) ** 2).mean())),
         "rel_diff_algorithm1_20_vs_gist_1000": float(np.linalg.norm(xa - xg) / np.linalg.norm(xg)),
+        "identity_cost_at": {str(k): float(fi[k - 1]) for k in (1, 10, 100, 300, 1000)},
+        "identity_iters_to_reach_algorithm1_k10_cost": next((k + 1 for k in range(len(fi)) if fi[k] <= fa[9]),
+                                                            None),
+        "rmse_identity_1000": float(np.sqrt(((xi - xt) ** 2).mean())),
+        "identity_steps": {"tau": ii["tau"], "sigma": ii["sigma"], "lambda_a": ii["lambda_a"],
+                           "lambda_h": ii["lambda_h"]},
         "gist_step": ig_t["tau"], "gist_lipschitz": ig_t["lambda_a"],
         "ms": {"algorithm1_20_loop": ia_t["loop_ms"], "algorithm1_setup": ia_t["setup_ms"],
                "gist_1000_loop": ig_t["loop_ms"], "gist_setup": ig_t["setup_ms"]},

@@ -249,6 +249,17 @@ int ctpd_batch_get_tiles(const ctpd_batch* batch, ctpd_batch_tiles* tiles);
  * same values.  CTPD_EINVAL before the first solve. */
 int ctpd_batch_time_loop(ctpd_batch* batch, int32_t iters, int32_t tv_iters, int32_t reps, double* ms);
 
+/* Ablation of Algorithm 1 without its preconditioner (Sec. 3 derives D as the
+ * FBP filter; here D = I): the same iteration, Eqs. 18-20, with D replaced by
+ * the identity.  Step sizes from Eq. 16 with D = I: lambda_A = lambda_max(A^T A)
+ * (a property of the geometry, cached per handle as for the Chambolle-Pock
+ * comparator), lambda_h = lambda_max(W^-1) = max 1/w; default tau =
+ * lambda_h / (2 lambda_A), where the two bounds on sigma coincide, and sigma =
+ * rho min(2 / lambda_h, 1 / (tau lambda_A)).  Arguments, knobs and report as
+ * ctpd_pd_lowdose_solve (norm_steps_h = 0). */
+int ctpd_app_identity_lowdose_solve(ctpd_op* op, const float* b, const float* w, double beta, int32_t iters,
+                                    const ctpd_params* p, float* x_out, ctpd_report* rep);
+
 /* Comparator for the low-dose problem of Eq. 1 (Sec. 4 compares Algorithm 1
  * with it; Table 1 lists it): GIST, the Loris-Verhoeven iteration -- a
  * gradient step on the weighted data term, a projection step on the dual of

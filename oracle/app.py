@@ -195,6 +195,42 @@ def fewview_solve(b, n, iters, tau=None, sigma=None, n_tv=10, tau_c=0.125, rho=0
     return res, st
 
 
+def identity_taps(nb):
+    """Taps of D = I (1 at offset 0): Algorithm 1 without its preconditioner."""
+    h = np.zeros(2 * nb - 1)
+    h[nb - 1] = 1.0
+    return h
+
+
+def steps_lowdose_identity(w, n, tau=None, rho=0.95):
+    """Eq. 16 with D = I: lambda_A = lambda_max(A^T A), lambda_h = lambda_max(W^-1)
+    = max 1/w (W^-1 is diagonal); default tau = lambda_h / (2 lambda_A), where
+    the two bounds on sigma coincide."""
+    w = np.asarray(w, dtype=np.float64)
+    m, nb = w.shape
+    winv = 1.0 / w
+    la = lambda_a(n, m, nb, identity_taps(nb))
+    lh = float(winv.max())
+    if tau is None:
+        tau = lh / (2.0 * la)
+    sigma = rho * min(2.0 / lh, 1.0 / (tau * la))
+    return Steps(tau=tau, sigma=sigma, kappa=float(winv.mean()), lambda_a=la, lambda_h=lh)
+
+
+def lowdose_identity_solve(b, w, beta, n, iters, tau=None, sigma=None, n_tv=10, tau_c=0.125, rho=0.95,
+                           record_cost=False):
+    """Algorithm 1 with D = I (the ablation without the preconditioner).  Returns (Result, Steps)."""
+    w = np.asarray(w, dtype=np.float64)
+    m, nb = w.shape
+    st = steps_lowdose_identity(w, n, tau, rho)
+    if sigma is not None:
+        st.sigma = sigma
+    mon = (lambda x, mu: cost_lowdose(x, b, w, beta)) if record_cost else None
+    res = app_solve(b, n, iters, st.tau, st.sigma, identity_taps(nb), beta=beta, winv=1.0 / w, n_tv=n_tv,
+                    tau_c=tau_c, monitor=mon)
+    return res, st
+
+
 def cost_lowdose(x, b, w, beta):
     """f(x) of Eq. 1: beta psi(x) + 1/2 sum_i w_i ((A x)_i - b_i)^2."""
     m, nb = np.shape(b)

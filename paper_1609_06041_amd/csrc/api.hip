@@ -287,6 +287,74 @@ int tv_prox(ctpd_op* op, const float* z, float lam, int n_iter, float step, floa
 }
 
 
+// Algorithm 1's iterations (Eqs. 18-20) from zero with the handle's taps as D
+// and the given steps, queued on the handle's stream; *p_final receives the
+// buffer holding the final dual field of the TV prox.
+int lowdose_loop(ctpd_op* op, const float* b, const float* w, double beta, int iters, const Knobs& k, double tau,
+                 double sigma, float** p_final) {
+    int r = CTPD_OK;
+    const size_t I = op->I, J = op->J;
+    hipStream_t s = op->stream;
+    if (k.record && (r = ensure_cost(op, iters))) return r;
+    // x^0 = 0, mu^0 = 0, p = 0
+    HIP_TRY(launch_fill_f32(op->x, 0.f, J, s));
+    HIP_TRY(launch_fill_f32(op->p[0], 0.f, 2 * J, s));
+    HIP_TRY(launch_fill_f32(op->mu[0], 0.f, I, s));
+    HIP_TRY(launch_fill_f32(op->mu[1], 0.f, I, s));
+    float *mu = op->mu[0], *mup = op->mu[1], *mun = op->mu[2];
+    float* pcur = op->p[0];
+    const float fs = (float)sigma, ft = (float)tau, lam = (float)(tau * beta);
+    const float tvstep = lam > 0 ? (float)(k.tv_step / (tau * beta)) : 0.f;
+    // Without the cost monitor the two filters run on inputs written by the
+    // kernels before them (same arithmetic as the fused prologues): the
+    // projector writes r = A x - b - W^-1 mu, and the dual update writes
+    // W^-1 (mu^{k+1} - mu^k) for the next extrapolation.
+    const bool fused = !k.record;
+    for (int it = 0; it < iters; ++it) {
+        // Step 1: extrapolation (Eq. 18 / Algorithm 1)
+        if (it == 0)
+            r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, -fs, op->mubar);
+        else if (fused)
+            r = filter(op, FILT_PLAIN, op->sx, nullptr, nullptr, nullptr, mu, 2.f, mup, -1.f, -fs, op->mubar);
+        else
+            r = filter(op, FILT_EXTRAP, op->winv, mu, mup, nullptr, mu, 2.f, mup, -1.f, -fs, op->mubar);
+        if (r) return r;
+        // Step 2: z = x - tau A^T mubar, x = prox(z; tau beta)
+        HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, op->x, 1.f, -ft, op->z, op->views, op->n,
+                                      op->m, op->nb, s));
+        float* pnew = nullptr;
+        if ((r = tv_prox(op, op->z, lam, k.tv_iters, tvstep, pcur, pcur == op->p[0] ? op->p[1] : op->p[0], op->x,
+                         &pnew)))
+            return r;
+        pcur = pnew;
+        // Step 3: mu^{k+1} = mu^k + sigma D (A x^{k+1} - b - W^-1 mu^k)
+        if (fused) {
+            if ((r = project_resid(op, op->x, b, op->winv, mu, op->q))) return r;
+            if ((r = filter(op, FILT_PLAIN, op->q, nullptr, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun,
+                            op->winv, op->sx)))
+                return r;
+        } else {
+            if ((r = project(op, op->x, op->q))) return r;
+            if ((r = filter(op, FILT_DUAL_LD, op->q, b, op->winv, mu, mu, 1.f, nullptr, 0.f, fs, mun))) return r;
+        }
+        if (k.record) {
+            if ((r = reduce(op, RED_WRES_F32, op->q, b, w, I, 0))) return r;
+            HIP_TRY(launch_tv_norm(op->x, op->n, op->partials, op->cost_dev + 6 * it, s));
+            HIP_TRY(hipMemcpyAsync(op->cost_dev + 6 * it + 3, op->red, sizeof(double) * 3,
+                                   hipMemcpyDeviceToDevice, s));
+        }
+        float* t = mup;
+        mup = mu;
+        mu = mun;
+        mun = t;
+    }
+    op->mu[0] = mu;
+    op->mu[1] = mup;
+    op->mu[2] = mun;
+    *p_final = pcur;
+    return CTPD_OK;
+}
+
 int read_params(const ctpd_params* p, Knobs* k) {
     k->tau = 0.0;
     k->sigma = 0.0;
@@ -652,8 +720,6 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
     int r = read_params(p, &k);
     if (r) return r;
     const auto t0 = std::chrono::steady_clock::now();
-    const size_t I = op->I, J = op->J;
-    hipStream_t s = op->stream;
     LowdoseSetup S;
     if ((r = lowdose_setup_begin(op, b, w, k, &S))) return r;
     if (S.norms) {
@@ -683,62 +749,8 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
     if ((r = sync(op))) return r;
     const double setup_ms = ms_since(t0);
     const auto t1 = std::chrono::steady_clock::now();
-    if (k.record && (r = ensure_cost(op, iters))) return r;
-    // x^0 = 0, mu^0 = 0, p = 0
-    HIP_TRY(launch_fill_f32(op->x, 0.f, J, s));
-    HIP_TRY(launch_fill_f32(op->p[0], 0.f, 2 * J, s));
-    HIP_TRY(launch_fill_f32(op->mu[0], 0.f, I, s));
-    HIP_TRY(launch_fill_f32(op->mu[1], 0.f, I, s));
-    float *mu = op->mu[0], *mup = op->mu[1], *mun = op->mu[2];
-    float* pcur = op->p[0];
-    const float fs = (float)sigma, ft = (float)tau, lam = (float)(tau * beta);
-    const float tvstep = lam > 0 ? (float)(k.tv_step / (tau * beta)) : 0.f;
-    // Without the cost monitor the two filters run on inputs written by the
-    // kernels before them (same arithmetic as the fused prologues): the
-    // projector writes r = A x - b - W^-1 mu, and the dual update writes
-    // W^-1 (mu^{k+1} - mu^k) for the next extrapolation.
-    const bool fused = !k.record;
-    for (int it = 0; it < iters; ++it) {
-        // Step 1: extrapolation (Eq. 18 / Algorithm 1)
-        if (it == 0)
-            r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, -fs, op->mubar);
-        else if (fused)
-            r = filter(op, FILT_PLAIN, op->sx, nullptr, nullptr, nullptr, mu, 2.f, mup, -1.f, -fs, op->mubar);
-        else
-            r = filter(op, FILT_EXTRAP, op->winv, mu, mup, nullptr, mu, 2.f, mup, -1.f, -fs, op->mubar);
-        if (r) return r;
-        // Step 2: z = x - tau A^T mubar, x = prox(z; tau beta)
-        HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, op->x, 1.f, -ft, op->z, op->views, op->n,
-                                      op->m, op->nb, s));
-        float* pnew = nullptr;
-        if ((r = tv_prox(op, op->z, lam, k.tv_iters, tvstep, pcur, pcur == op->p[0] ? op->p[1] : op->p[0], op->x,
-                         &pnew)))
-            return r;
-        pcur = pnew;
-        // Step 3: mu^{k+1} = mu^k + sigma D (A x^{k+1} - b - W^-1 mu^k)
-        if (fused) {
-            if ((r = project_resid(op, op->x, b, op->winv, mu, op->q))) return r;
-            if ((r = filter(op, FILT_PLAIN, op->q, nullptr, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun,
-                            op->winv, op->sx)))
-                return r;
-        } else {
-            if ((r = project(op, op->x, op->q))) return r;
-            if ((r = filter(op, FILT_DUAL_LD, op->q, b, op->winv, mu, mu, 1.f, nullptr, 0.f, fs, mun))) return r;
-        }
-        if (k.record) {
-            if ((r = reduce(op, RED_WRES_F32, op->q, b, w, I, 0))) return r;
-            HIP_TRY(launch_tv_norm(op->x, op->n, op->partials, op->cost_dev + 6 * it, s));
-            HIP_TRY(hipMemcpyAsync(op->cost_dev + 6 * it + 3, op->red, sizeof(double) * 3,
-                                   hipMemcpyDeviceToDevice, s));
-        }
-        float* t = mup;
-        mup = mu;
-        mu = mun;
-        mun = t;
-    }
-    op->mu[0] = mu;
-    op->mu[1] = mup;
-    op->mu[2] = mun;
+    float* pcur = nullptr;
+    if ((r = lowdose_loop(op, b, w, beta, iters, k, tau, sigma, &pcur))) return r;
     if ((r = finish(op, iters, true, beta, pcur, rep, x_out, k.record != 0))) return r;
     if (rep) {
         rep->tau = tau;
@@ -748,6 +760,69 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
         rep->lambda_h = lam_h;
         rep->norm_steps_a = steps_a;
         rep->norm_steps_h = steps_h;
+        rep->iters_done = iters;
+        rep->setup_ms = setup_ms;
+        rep->loop_ms = ms_since(t1);
+    }
+    return CTPD_OK;
+}
+
+int ctpd_app_identity_lowdose_solve(ctpd_op* op, const float* b, const float* w, double beta, int32_t iters,
+                                    const ctpd_params* p, float* x_out, ctpd_report* rep) {
+    g_errmsg[0] = 0;
+    if (!op || !b || !w || !x_out) return einval("null pointer");
+    if (!(beta >= 0.0) || !std::isfinite(beta)) return einval("beta must be finite and >= 0");
+    if (iters < 0) return einval("iters < 0");
+    Knobs k;
+    int r = read_params(p, &k);
+    if (r) return r;
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = op->stream;
+    // validity scan and kappa (reported), W^-1, lambda_h = max 1/w, D = I
+    if ((r = reduce(op, RED_INVW_CHECK, w, b, nullptr, op->I, 0))) return r;
+    HIP_TRY(launch_max_inv(w, op->I, op->partials, op->red + 3, s));
+    if ((r = read_red(op))) return r;
+    if (op->red_host[1] > 0 || op->red_host[2] > 0) {
+        snprintf(g_errmsg, sizeof g_errmsg, "%.0f weights <= 0 or non-finite, %.0f non-finite data",
+                 op->red_host[1], op->red_host[2]);
+        return CTPD_EDOMAIN;
+    }
+    const double kappa = op->red_host[0] / (double)op->I, lam_h = op->red_host[3];
+    HIP_TRY(launch_inverse_f32(op->winv, w, op->I, s));
+    HIP_TRY(launch_identity_taps(op->taps64, op->taps32, op->nb, s));
+    op->tap_tau = op->tap_kappa = -2.0;   // not the taps of any (tau, kappa)
+    double tau = k.tau, sigma = k.sigma, lam_a = 0.0;
+    int steps_a = 0;
+    if (!(tau > 0) || !(sigma > 0)) {
+        if (op->norm_ata > 0.0 && op->norm_ata_kmax == k.norm_steps) {   // a property of the geometry
+            lam_a = op->norm_ata;
+        } else {
+            Lanczos L;
+            if ((r = setup_lambda_a(op, k.norm_steps, &L, false, nullptr))) return r;
+            if ((r = run_lanczos({&L}))) return r;
+            lam_a = L.theta;
+            steps_a = L.steps;
+            op->norm_ata = lam_a;
+            op->norm_ata_kmax = k.norm_steps;
+        }
+        // default tau balances the two bounds of sigma: 1 / (tau lambda_A) = 2 / lambda_h
+        if (!(tau > 0)) tau = lam_h / (2.0 * lam_a);
+        if (!(sigma > 0)) sigma = k.rho * std::min(2.0 / lam_h, 1.0 / (tau * lam_a));
+    }
+    if ((r = sync(op))) return r;
+    const double setup_ms = ms_since(t0);
+    const auto t1 = std::chrono::steady_clock::now();
+    float* pcur = nullptr;
+    if ((r = lowdose_loop(op, b, w, beta, iters, k, tau, sigma, &pcur))) return r;
+    if ((r = finish(op, iters, true, beta, pcur, rep, x_out, k.record != 0))) return r;
+    if (rep) {
+        rep->tau = tau;
+        rep->sigma = sigma;
+        rep->kappa = kappa;
+        rep->lambda_a = lam_a;
+        rep->lambda_h = lam_h;
+        rep->norm_steps_a = steps_a;
+        rep->norm_steps_h = 0;
         rep->iters_done = iters;
         rep->setup_ms = setup_ms;
         rep->loop_ms = ms_since(t1);

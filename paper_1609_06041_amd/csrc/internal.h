@@ -295,6 +295,10 @@ hipError_t launch_rows_ritz(const NormItem* it, const RowRef* rows, int nrows, i
 int reduce_blocks_for(size_t len);
 // out[i] = 1/w[i] (float) or sqrt(1/w[i]) (double), computed in float64
 hipError_t launch_inverse_f32(float* out, const float* w, size_t len, hipStream_t s);
+// dev_out[0] = max of 1/w (float64); partials: reduce_blocks_for(len) doubles
+hipError_t launch_max_inv(const float* w, size_t len, double* partials, double* dev_out, hipStream_t s);
+// the taps of the identity (D = I): 1 at offset 0
+hipError_t launch_identity_taps(double* taps64, float* taps32, int nb, hipStream_t s);
 hipError_t launch_rsqrt_f64(double* out, const float* w, size_t len, hipStream_t s);
 hipError_t launch_copy_f32(float* dst, const float* src, size_t len, hipStream_t s);
 hipError_t launch_fill_f32(float* dst, float v, size_t len, hipStream_t s);

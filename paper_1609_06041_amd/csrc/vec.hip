@@ -681,4 +681,54 @@ hipError_t launch_step_vec(int kind, const UStep* steps, const BlockRef* map, in
     return hipGetLastError();
 }
 
+// out[0] = max over i of 1/w[i] (float64), two passes of fixed order.
+__global__ __launch_bounds__(256) void max_inv_partial_kernel(const float* __restrict__ w, size_t len,
+                                                              double* __restrict__ partial) {
+    __shared__ double red[4];
+    double mx = 0.0;
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < len; i += stride) mx = fmax(mx, 1.0 / (double)w[i]);
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void max_final_kernel(const double* __restrict__ partial, int n,
+                                                        double* __restrict__ out) {
+    __shared__ double red[4];
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) mx = fmax(mx, partial[i]);
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+hipError_t launch_max_inv(const float* w, size_t len, double* partials, double* dev_out, hipStream_t s) {
+    const int nb = reduce_blocks(len);
+    max_inv_partial_kernel<<<nb, 256, 0, s>>>(w, len, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    max_final_kernel<<<1, 256, 0, s>>>(partials, nb, dev_out);
+    return hipGetLastError();
+}
+
+// taps of D = I: 1 at offset 0, 0 elsewhere
+__global__ __launch_bounds__(256) void identity_taps_kernel(double* __restrict__ taps64, float* __restrict__ taps32,
+                                                            int ntap) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < ntap) {
+        const double v = (i == ntap / 2) ? 1.0 : 0.0;
+        taps64[i] = v;
+        taps32[i] = (float)v;
+    }
+}
+
+hipError_t launch_identity_taps(double* taps64, float* taps32, int nb, hipStream_t s) {
+    const int ntap = 2 * nb - 1;
+    identity_taps_kernel<<<(ntap + 255) / 256, 256, 0, s>>>(taps64, taps32, ntap);
+    return hipGetLastError();
+}
+
 }  // namespace ctpd

@@ -32,6 +32,8 @@ _SIGNATURES = {
     "ctpd_pd_lowdose_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p,
                                       c_void_p]),
     "ctpd_pd_fewview_solve": (c_int, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "ctpd_app_identity_lowdose_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p,
+                                                c_void_p, c_void_p]),
     "ctpd_gist_lowdose_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p,
                                         c_void_p]),
     "ctpd_cp_fewview_solve": (c_int, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
@@ -249,6 +251,18 @@ class Operator:
         _check(load().ctpd_pd_lowdose_solve(self._h, _ptr(b, (self.m, self.nb), "b"),
                                             _ptr(w, (self.m, self.nb), "w"), float(beta), int(iters),
                                             byref(prm), _ptr(out, (self.n, self.n), "out"), byref(rep)))
+        return out, self._info(rep, cost, state)
+
+    def app_identity_lowdose_solve(self, b: torch.Tensor, w: torch.Tensor, beta: float, iters: int, *, tau=None,
+                                   sigma=None, tv_iters=10, tv_step=0.125, safety=0.95, norm_steps=100,
+                                   record_cost=False, return_state=False, out: torch.Tensor | None = None):
+        """Algorithm 1 with D = I (the unpreconditioned ablation).  Returns (x, info)."""
+        out = self._img() if out is None else out
+        prm = _params(tau, sigma, tv_iters, tv_step, safety, norm_steps, record_cost)
+        rep, cost, state = self._report(iters, record_cost, return_state)
+        _check(load().ctpd_app_identity_lowdose_solve(self._h, _ptr(b, (self.m, self.nb), "b"),
+                                                      _ptr(w, (self.m, self.nb), "w"), float(beta), int(iters),
+                                                      byref(prm), _ptr(out, (self.n, self.n), "out"), byref(rep)))
         return out, self._info(rep, cost, state)
 
     def fewview_solve(self, b: torch.Tensor, iters: int, *, tau=None, sigma=None, tv_iters=10, tv_step=0.125,

@@ -112,3 +112,22 @@ def test_gist_rejects_bad_dual_step(gpu):
         with pytest.raises(ctpd.CtpdError) as e:
             op.gist_lowdose_solve(dev(b), dev(w_bad), 0.1, 3)
         assert e.value.code == ctpd.CTPD_EDOMAIN
+
+
+@pytest.mark.parametrize("n,m,nb,beta,iters", [(64, 90, 96, 0.01, 40), (45, 30, 70, 0.0, 25)])
+def test_app_identity_matches_oracle(gpu, n, m, nb, beta, iters):
+    # Algorithm 1 with D = I (the ablation without the preconditioner)
+    b, w = lowdose_inputs(n, m, nb, seed=2 * n + m)
+    ref, st = OA.lowdose_identity_solve(b, w, beta, n, iters, record_cost=True)
+    with ctpd.Operator(n, m, nb) as op:
+        x, info = op.app_identity_lowdose_solve(dev(b), dev(w), beta, iters, record_cost=True)
+        x = host(x)
+        x2, _ = op.app_identity_lowdose_solve(dev(b), dev(w), beta, iters)   # fused filter inputs
+        x2 = host(x2)
+    assert info["lambda_a"] == pytest.approx(st.lambda_a, rel=1e-6)
+    assert info["lambda_h"] == pytest.approx(st.lambda_h, rel=1e-12)
+    assert info["tau"] == pytest.approx(st.tau, rel=1e-6)
+    assert info["sigma"] == pytest.approx(st.sigma, rel=1e-6)
+    assert rel(x, ref.x) <= 1e-4, rel(x, ref.x)
+    np.testing.assert_allclose(info["cost"], ref.history, rtol=3e-5)
+    np.testing.assert_array_equal(x2, x)

@@ -166,3 +166,38 @@ def test_step_sizes_satisfy_the_bounds():
     sf = AP.steps_fewview(b, n)
     d1 = np.kron(np.eye(m), F.toeplitz_matrix(F.ramp_taps(nb, m, sf.tau)))
     assert sf.sigma * sf.tau * np.linalg.eigvalsh(a.T @ d1 @ a)[-1] == pytest.approx(0.95, rel=1e-9)
+
+
+def test_identity_taps_apply_the_identity():
+    rng = np.random.default_rng(7)
+    s = rng.standard_normal((5, 9))
+    np.testing.assert_array_equal(F.apply_filter(s, AP.identity_taps(9)), s)
+
+
+def test_identity_steps_closed_forms():
+    # lambda_h of W^-1/2 I W^-1/2 by the generic eigen-solver equals max 1/w;
+    # lambda_A equals the dense largest eigenvalue of A^T A; the default tau
+    # makes both bounds on sigma equal
+    n, m, nb = 8, 12, 12
+    _, b, w = _small_problem(3, n, m, nb)
+    st = AP.steps_lowdose_identity(w, n)
+    assert AP.lambda_h(1.0 / w, AP.identity_taps(nb)) == pytest.approx(st.lambda_h, rel=1e-10)
+    a = P.dense_matrix(n, m, nb)
+    assert st.lambda_a == pytest.approx(np.linalg.eigvalsh(a.T @ a)[-1], rel=1e-10)
+    assert 2.0 / st.lambda_h == pytest.approx(1.0 / (st.tau * st.lambda_a), rel=1e-12)
+    assert st.sigma == pytest.approx(0.95 * 2.0 / st.lambda_h, rel=1e-12)
+
+
+def test_identity_solve_converges_to_nnls():
+    # without the preconditioner the same iteration still solves Eq. 1 (beta = 0:
+    # weighted NNLS), only more slowly: 4e-5 after 20000 iterations (1e-10 after
+    # 50000) where Algorithm 1' is within 1e-9 after 1500
+    n, m, nb = 8, 12, 12
+    _, b, w = _small_problem(5, n, m, nb)
+    a = P.dense_matrix(n, m, nb)
+    sw = np.sqrt(w).ravel()
+    ref, _ = nnls(sw[:, None] * a, sw * b.ravel())
+    res, st = AP.lowdose_identity_solve(b, w, 0.0, n, 20000)
+    np.testing.assert_allclose(res.x.ravel(), ref, atol=1e-4)
+    res2, _ = AP.lowdose_identity_solve(b, w, 0.0, n, 10000)
+    assert np.abs(res.x.ravel() - ref).max() < 0.1 * np.abs(res2.x.ravel() - ref).max()
