@@ -139,3 +139,19 @@ def test_every_tile_choice_gives_the_same_result(gpu):
         assert bt.time_loop(5, 10, 2) > 0.0
         with pytest.raises(ctpd.CtpdError):
             bt.set_tiles(placement=0, tv_threads=256, fwd_batch=8)
+
+
+def test_batch_with_chunked_inner_steps(gpu):
+    # 12 inner TV steps (two prox chunks per iteration)
+    geoms = SMALL[:3]
+    data = _inputs(geoms, 50)
+    betas = [0.02, 0.0, 0.04]
+    ref = []
+    for (n, m, nb), (b, w), beta in zip(geoms, data, betas):
+        with ctpd.Operator(n, m, nb) as op:
+            x, _ = op.lowdose_solve(dev(b), dev(w), beta, 6, tv_iters=12)
+            ref.append(host(x))
+    with ctpd.Batch(geoms) as bt:
+        xs, _ = bt.lowdose_solve([dev(b) for b, _ in data], [dev(w) for _, w in data], betas, 6, tv_iters=12)
+        for x, r in zip(xs, ref):
+            np.testing.assert_array_equal(host(x), r)

@@ -132,3 +132,23 @@ def test_many_problem_calls_reject_a_repeated_operator(gpu):
         with pytest.raises(ctpd.CtpdError) as e:
             ctpd.unrolled_forward_many([op, op], [dev(b)] * 2, [dev(w)] * 2, [0.1] * 2, [0.1] * 2, [0.5] * 2, 2, cks)
         assert e.value.code == ctpd.CTPD_EINVAL
+
+
+def test_more_inner_tv_steps_than_one_launch_holds(gpu):
+    # 12 inner steps: the forward pass runs the prox in two chunks and the
+    # reverse pass recomputes the inner fields one step per launch
+    n, m, nb, iters, nt = 24, 20, 36, 3, 12
+    xt, b, w = _instance(7, n, m, nb)
+    st = OA.steps_lowdose(w, n)
+    beta = 0.03
+    fd = OU.fd_gradients(b, w, beta, st.tau, st.sigma, n, iters, xt, n_tv=nt)
+    with ctpd.Operator(n, m, nb) as op:
+        x_s, _ = op.lowdose_solve(dev(b), dev(w), beta, iters, tau=st.tau, sigma=st.sigma, tv_iters=nt)
+        pb = torch.tensor(beta, dtype=torch.float64, requires_grad=True)
+        pt = torch.tensor(st.tau, dtype=torch.float64, requires_grad=True)
+        ps = torch.tensor(st.sigma, dtype=torch.float64, requires_grad=True)
+        x = unrolled_lowdose(op, dev(b), dev(w), pb, pt, ps, iters, tv_iters=nt)
+        np.testing.assert_array_equal(host(x), host(x_s))
+        ((x - dev(xt)) ** 2).sum().backward()
+    for name, g in (("beta", pb.grad), ("tau", pt.grad), ("sigma", ps.grad)):
+        assert float(g) == pytest.approx(fd[name], rel=1e-3), (name, float(g), fd[name])
