@@ -38,9 +38,31 @@ constexpr int kTvTile = 32;
 constexpr int kTvChunk = 10;
 constexpr int kTvMaxW = kTvTile + 2 * (kTvChunk + 1);
 
-// One workgroup = 16 waves (four per SIMD, to hide the LDS latency of the
-// dependent stencil reads); a wave sweeps one 64-wide LDS row at a time.
+// One workgroup = 16 waves.  Lane c of every wave is window column c (the
+// window is at most 64 columns wide) and wave w owns the window rows
+// [w R, w R + R): a thread keeps z and p of its R rows in registers.  The
+// left neighbour of p1 and the right neighbour of x~ come from the adjacent
+// lane (DPP wave shifts), vertical neighbours from the thread's own rows;
+// only the edge rows of a strip pass through LDS.  Every step each wave
+// publishes the first row of its p (p1, p2) and the last row of its p2, one
+// barrier later reads its neighbours' rows, evaluates x~ on its rows and on
+// the row below the strip, and updates its p.  The exchange buffer has two
+// parities, so step t + 1 can publish while a slower wave still reads step t.
+// Cells outside the image or outside the shrinking valid region are updated
+// too (a kept cell never reads them: the image-edge masks drop neighbours
+// outside the image, and the halo covers the window edge); a wave whose rows
+// all lie outside the valid region of a step skips that step's arithmetic.
 constexpr int kTvThreads = 1024;
+
+// Lane c receives lane c - 1 (lane 0 receives 0), and lane c + 1 (lane 63
+// receives 0): DPP wave_shr:1 and wave_shl:1.  Every lane of the wave must be
+// active at the call.
+__device__ __forceinline__ float from_left_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float from_right_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
 
 // ps_store (optional): the dual field after every step t = 1..steps is also
 // written to ps_store + (t - 1) * 2 n^2 (the interior stays valid: the halo
@@ -50,80 +72,118 @@ __device__ __forceinline__ void tv_prox_body(const float* __restrict__ z, const 
                                              float* __restrict__ p_out, float* __restrict__ x, int n, float lam,
                                              float step, int steps, int bxi, int byi,
                                              float* __restrict__ ps_store = nullptr) {
-    __shared__ float sz[kTvMaxW * kTvMaxW], sx[kTvMaxW * kTvMaxW];
-    __shared__ float s1[kTvMaxW * kTvMaxW], s2[kTvMaxW * kTvMaxW];
+    constexpr int NW = THREADS / 64;
+    constexpr int R = (kTvMaxW + NW - 1) / NW;
+    // [parity][first-row p1, first-row p2, last-row p2][slot][lane]: wave w
+    // writes slot w of the first rows and slot w + 1 of the last row, so slot
+    // NW of the first rows and slot 0 of the last row stay zero.
+    __shared__ float ex[2][3][NW + 1][64];
     const int H = steps + 1, W = kTvTile + 2 * H;
     const int i0 = byi * kTvTile - H, j0 = bxi * kTvTile - H;
-    const int c = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const size_t nn = (size_t)n * n;
+    const int c = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int rb = w * R;
+    const bool active = rb < W;
     const int j = j0 + c;
-    const bool colin = c < W;
-    const bool jin = colin && j >= 0 && j < n;
-    for (int r = ty; r < W; r += (THREADS / 64)) {
-        const int i = i0 + r;
-        if (!colin) continue;
-        const int o = r * W + c;
-        float zz = 0.f, a1 = 0.f, a2 = 0.f;
-        if (jin && i >= 0 && i < n) {
-            const size_t g = (size_t)i * n + j;
-            zz = z[g];
-            a1 = p_in[g];
-            a2 = p_in[nn + g];
+    const bool jin = c < W && j >= 0 && j < n;
+    const bool right = j < n - 1, left = j > 0;
+    const bool cout = jin && c >= H && c < H + kTvTile;
+    const size_t nn = (size_t)n * n;
+
+    float zr[R + 1], p1[R], p2[R];
+#pragma unroll
+    for (int k = 0; k <= R; ++k) {
+        const int r = rb + k, i = i0 + r;
+        const bool in = active && jin && r < W && i >= 0 && i < n;
+        const size_t g = in ? (size_t)i * n + j : 0;
+        zr[k] = in ? z[g] : 0.f;
+        if (k < R) {
+            p1[k] = in ? p_in[g] : 0.f;
+            p2[k] = in ? p_in[nn + g] : 0.f;
         }
-        sz[o] = zz;
-        s1[o] = a1;
-        s2[o] = a2;
     }
-    __syncthreads();
-    // x~ at LDS cell (r, c) with the masked divergence of the global pixel (i, j)
-    auto xt_at = [&](int r, int i) -> float {
-        const int o = r * W + c;
-        float d = 0.f;
-        if (j < n - 1) d += s1[o];
-        if (j > 0 && c > 0) d -= s1[o - 1];
-        if (i < n - 1) d += s2[o];
-        if (i > 0 && r > 0) d -= s2[o - W];
-        return fmaxf(0.f, sz[o] - lam * d);
+    for (int q = 0; q < 2; ++q) {
+        if (w == 0) ex[q][2][0][c] = 0.f;
+        if (w == NW - 1) {
+            ex[q][0][NW][c] = 0.f;
+            ex[q][1][NW][c] = 0.f;
+        }
+        if (!active) {
+            ex[q][0][w][c] = 0.f;
+            ex[q][1][w][c] = 0.f;
+            ex[q][2][w + 1][c] = 0.f;
+        }
+    }
+
+    // x~ on the strip's rows and the row below it, from p and the rows the
+    // neighbouring waves published (pb1/pb2: first row below, pa2: last p2 above)
+    auto xtilde_rows = [&](float pb1, float pb2, float pa2, float (&xt)[R + 1]) {
+#pragma unroll
+        for (int k = 0; k <= R; ++k) {
+            const float a1 = k < R ? p1[k] : pb1, a2 = k < R ? p2[k] : pb2;
+            const float up2 = k == 0 ? pa2 : p2[k - 1];
+            const float l1 = from_left_lane(a1);
+            const int r = rb + k, i = i0 + r;
+            const float d = ((right ? a1 : 0.f) - (left ? l1 : 0.f)) + (i < n - 1 ? a2 : 0.f) -
+                            (i > 0 && r > 0 ? up2 : 0.f);
+            xt[k] = fmaxf(0.f, zr[k] - lam * d);
+        }
     };
+
     for (int t = 1; t <= steps; ++t) {
-        // cells whose new p is still needed: rows / columns [t, W - t)
-        for (int r = t - 1 + ty; r < W - t + 1; r += (THREADS / 64)) {
-            if (!colin) continue;
-            sx[r * W + c] = xt_at(r, i0 + r);
+        const int par = t & 1;
+        if (active) {
+            ex[par][0][w][c] = p1[0];
+            ex[par][1][w][c] = p2[0];
+            ex[par][2][w + 1][c] = p2[R - 1];
         }
         __syncthreads();
-        for (int r = t + ty; r < W - t; r += (THREADS / 64)) {
-            const int i = i0 + r;
-            if (!(jin && c >= t && c < W - t && i >= 0 && i < n)) continue;
-            const int o = r * W + c;
-            const float xc = sx[o];
-            const float g1 = (j < n - 1) ? sx[o + 1] - xc : 0.f;
-            const float g2 = (i < n - 1) ? sx[o + W] - xc : 0.f;
-            const float q1 = s1[o] - step * g1, q2 = s2[o] - step * g2;
-            const float sc = fmaxf(1.f, sqrtf(q1 * q1 + q2 * q2));
-            s1[o] = q1 / sc;
-            s2[o] = q2 / sc;
-        }
-        __syncthreads();
-        if (ps_store) {
-            float* dst = ps_store + (size_t)(t - 1) * 2 * nn;
-            for (int r = H + ty; r < H + kTvTile; r += (THREADS / 64)) {
-                const int i = i0 + r;
-                if (!(jin && c >= H && c < H + kTvTile && i < n)) continue;
-                const size_t g = (size_t)i * n + j;
-                dst[g] = s1[r * W + c];
-                dst[nn + g] = s2[r * W + c];
+        // rows whose p is still needed after step t: [t, W - t)
+        if (active && rb + R > t && rb < W - t) {
+            float xt[R + 1];
+            xtilde_rows(ex[par][0][w + 1][c], ex[par][1][w + 1][c], ex[par][2][w][c], xt);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int i = i0 + rb + k;
+                const float xr = from_right_lane(xt[k]);
+                const float g1 = right ? xr - xt[k] : 0.f;
+                const float g2 = (i < n - 1) ? xt[k + 1] - xt[k] : 0.f;
+                const float q1 = p1[k] - step * g1, q2 = p2[k] - step * g2;
+                const float s2 = q1 * q1 + q2 * q2;
+                const float f = s2 > 1.f ? __builtin_amdgcn_rsqf(s2) : 1.f;
+                p1[k] = q1 * f;
+                p2[k] = q2 * f;
+            }
+            if (ps_store) {
+                float* dst = ps_store + (size_t)(t - 1) * 2 * nn;
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const int r = rb + k, i = i0 + r;
+                    if (cout && r >= H && r < H + kTvTile && i < n) {
+                        const size_t g = (size_t)i * n + j;
+                        dst[g] = p1[k];
+                        dst[nn + g] = p2[k];
+                    }
+                }
             }
         }
     }
-    for (int r = H + ty; r < H + kTvTile; r += (THREADS / 64)) {
-        const int i = i0 + r;
-        if (!(jin && c >= H && c < H + kTvTile && i < n)) continue;
-        const int o = r * W + c;
-        const size_t g = (size_t)i * n + j;
-        p_out[g] = s1[o];
-        p_out[nn + g] = s2[o];
-        if (x) x[g] = xt_at(r, i);
+    const int par = (steps + 1) & 1;
+    if (active) ex[par][2][w + 1][c] = p2[R - 1];
+    __syncthreads();
+    if (active && rb + R > H && rb < H + kTvTile) {
+        float xt[R + 1];
+        if (x) xtilde_rows(0.f, 0.f, ex[par][2][w][c], xt);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int r = rb + k, i = i0 + r;
+            if (cout && r >= H && r < H + kTvTile && i < n) {
+                const size_t g = (size_t)i * n + j;
+                p_out[g] = p1[k];
+                p_out[nn + g] = p2[k];
+                if (x) x[g] = xt[k];
+            }
+        }
     }
 }
 
