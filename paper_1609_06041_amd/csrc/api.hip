@@ -484,10 +484,19 @@ int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, cons
     }
     HIP_TRY(hipMemcpyAsync(items, items_host, sizeof(NormItem) * P, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_rows_start(items, rows, nrows, 2, s));
+    int max_nb = 0;
+    for (ctpd_op* op : ops) max_nb = std::max(max_nb, op->nb);
+    // up to 1024 bins a round is one launch (the view's product and recurrence
+    // in one workgroup); beyond, a batched FP64 MFMA filter and a step kernel per step
+    const bool fused = rows_round_fits(max_nb);
     constexpr int kRound = 8;
     int j = 0;
     for (bool running = true; running && j < kmax;) {
         const int j1 = std::min(kmax, j + kRound);
+        if (fused) {
+            HIP_TRY(launch_rows_round(items, rows, nrows, j, j1, max_nb, s));
+            j = j1;
+        }
         for (; j < j1; ++j) {
             const int rot = (3 - j % 3) % 3;
             HIP_TRY(launch_norm_filter_batched(items, filt, nfilt, rot, s));

@@ -360,6 +360,191 @@ __global__ __launch_bounds__(256) void rows_step_kernel(const NormItem* __restri
     }
 }
 
+// A round of steps j0 .. j1-1 of every running view's chain in one launch,
+// one 512-thread workgroup per view (nb <= kRoundMaxBins).  The view's
+// operator S D S (S = W^-1/2 on the view's bins, D the nb x nb Toeplitz
+// section) is applied as a dense product in float64: the mirrored taps,
+// zero-extended, and u = S q sit in LDS; the eight waves split the bins k, and
+// lane l accumulates the 12 consecutive outputs 12 l .. 12 l + 11 of a
+// 768-output chunk, holding the 12 taps h[i - k] those outputs need in
+// registers.  Going from k to k + 1 moves that window by one tap, so each k
+// costs one tap read, one broadcast read of u_k and 12 FMAs.  The taps are
+// stored with one unused double after every 12, which turns the lanes' stride
+// of 12 doubles into 13, a stride the LDS banks serve without conflicts.  The
+// wave partials are added in a fixed order (w and w + 4, then the four sums).
+// The recurrence is the per-step kernel's: alpha = q.Mq, w = Mq - alpha q -
+// beta qp, beta'^2 = |w|^2, q <- w / beta', with al and b2 written per step
+// for the Ritz kernel.  On entry q is in v[0] and the previous q in v[1] (not
+// read when j0 = 0); on exit likewise.
+constexpr int kRoundWaves = 8, kRoundThreads = 64 * kRoundWaves, kRoundR = 12, kRoundChunk = 64 * kRoundR;
+constexpr int kRoundMaxBins = 1024, kRoundNpt = kRoundMaxBins / kRoundThreads;
+
+struct RoundDims {
+    int Q;      // bins k per wave (a multiple of kRoundR)
+    int KP;     // kRoundWaves * Q >= nb: k beyond nb meets u = 0
+    int OUTP;   // outputs, a multiple of kRoundChunk
+    int TP;     // LDS doubles of the padded tap array
+};
+
+__host__ __device__ inline RoundDims round_dims(int nb) {
+    RoundDims d;
+    d.Q = kRoundR * ((nb + kRoundWaves * kRoundR - 1) / (kRoundWaves * kRoundR));
+    d.KP = kRoundWaves * d.Q;
+    d.OUTP = kRoundChunk * ((nb + kRoundChunk - 1) / kRoundChunk);
+    const int e = d.KP + d.OUTP;
+    d.TP = e + e / kRoundR + 1;
+    return d;
+}
+
+// doubles of LDS: taps, u, four wave partials of a chunk, M q, the block sums
+__host__ __device__ inline size_t round_lds_doubles(int nb) {
+    const RoundDims d = round_dims(nb);
+    return (size_t)d.TP + d.KP + 4 * kRoundChunk + nb + kRoundWaves;
+}
+
+__device__ __forceinline__ double block_allsum8(double v, double* red8) {
+    v = wave_sum_all(v);
+    __syncthreads();   // red8 free from any previous use
+    if ((threadIdx.x & 63) == 0) red8[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return ((red8[0] + red8[1]) + (red8[2] + red8[3])) + ((red8[4] + red8[5]) + (red8[6] + red8[7]));
+}
+
+// acc[r] = sum over k in [kb0, kb0 + Q) of h[i_r - k] u_k for the lane's
+// outputs i_r = ob + 12 lane + r.  Tap element e (0 <= e < KP + OUTP) is
+// h[e - KP] at sT[e + e / 12]; output i and bin k meet element KP + i - k.
+__device__ __forceinline__ void round_matvec(const double* __restrict__ sT, const double* __restrict__ su, int KP,
+                                             int Q, int ob, int kb0, int lane, double (&acc)[kRoundR]) {
+    const int l13 = (kRoundR + 1) * lane;
+    double buf[kRoundR];   // at sub-step s the tap of output r is buf[(r - s) mod 12]
+    const int c0 = KP + ob - kb0;
+#pragma unroll
+    for (int r = 0; r < kRoundR; ++r) {
+        const int e = c0 + r;
+        buf[r] = sT[e + e / kRoundR + l13];
+    }
+    for (int kb = kb0; kb < kb0 + Q; kb += kRoundR) {
+        const int c = KP + ob - kb;
+#pragma unroll
+        for (int s = 0; s < kRoundR; ++s) {
+            const double uk = su[kb + s];
+#pragma unroll
+            for (int r = 0; r < kRoundR; ++r) acc[r] = fma(buf[(r - s + kRoundR) % kRoundR], uk, acc[r]);
+            // the tap entering the window at k + 1 (element c - s - 1 + 12 lane >= 0)
+            const int e = c - s - 1;
+            buf[(kRoundR - 1 - s) % kRoundR] = sT[e + e / kRoundR + l13];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kRoundThreads) void rows_round_kernel(const NormItem* __restrict__ items,
+                                                                   const RowRef* __restrict__ rows, int nrows,
+                                                                   int j0, int j1) {
+    extern __shared__ double rsm[];
+    const int row = blockIdx.x;
+    if (row >= nrows) return;
+    const RowRef rr = rows[row];
+    const NormItem& it = items[rr.prob];
+    const int m = it.m, nb = it.nb, v = rr.view;
+    if (it.done[v] || nb > kRoundMaxBins) return;
+    const RoundDims d = round_dims(nb);
+    double* sT = rsm;
+    double* su = sT + d.TP;
+    double* sp = su + d.KP;
+    double* sy = sp + 4 * kRoundChunk;
+    double* red8 = sy + nb;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const size_t base = (size_t)v * nb;
+    for (int e = tid; e < d.KP + d.OUTP; e += kRoundThreads) {
+        const int o = e - d.KP;
+        sT[e + e / kRoundR] = (o > -nb && o < nb) ? it.taps64[nb - 1 + o] : 0.0;
+    }
+    for (int k = nb + tid; k < d.KP; k += kRoundThreads) su[k] = 0.0;
+    double q[kRoundNpt], qp[kRoundNpt], sc[kRoundNpt];
+#pragma unroll
+    for (int r = 0; r < kRoundNpt; ++r) {
+        const int i = tid + kRoundThreads * r;
+        const bool in = i < nb;
+        q[r] = in ? it.v[0][base + i] : 0.0;
+        qp[r] = (in && j0 > 0) ? it.v[1][base + i] : 0.0;
+        sc[r] = in ? it.rs[base + i] : 0.0;
+    }
+    double bprev = j0 > 0 ? it.b2[(size_t)(j0 - 1) * m + v] : 0.0;
+    for (int j = j0; j < j1; ++j) {
+#pragma unroll
+        for (int r = 0; r < kRoundNpt; ++r) {
+            const int i = tid + kRoundThreads * r;
+            if (i < nb) su[i] = sc[r] * q[r];
+        }
+        __syncthreads();   // u (and on the first step the taps) complete; the previous step's sy read
+        for (int ob = 0; ob < nb; ob += kRoundChunk) {
+            double acc[kRoundR];
+#pragma unroll
+            for (int r = 0; r < kRoundR; ++r) acc[r] = 0.0;
+            round_matvec(sT, su, d.KP, d.Q, ob, wv * d.Q, lane, acc);
+            if (wv >= 4) {
+#pragma unroll
+                for (int r = 0; r < kRoundR; ++r) sp[(wv - 4) * kRoundChunk + r * 64 + lane] = acc[r];
+            }
+            __syncthreads();
+            if (wv < 4) {
+#pragma unroll
+                for (int r = 0; r < kRoundR; ++r) {
+                    double* p = sp + wv * kRoundChunk + r * 64 + lane;
+                    *p = acc[r] + *p;
+                }
+            }
+            __syncthreads();
+            // slot r * 64 + l holds output ob + 12 l + r
+            for (int t = tid; t < kRoundChunk; t += kRoundThreads) {
+                const int i = ob + kRoundR * (t & 63) + (t >> 6);
+                if (i < nb)
+                    sy[i] = (sp[t] + sp[kRoundChunk + t]) + (sp[2 * kRoundChunk + t] + sp[3 * kRoundChunk + t]);
+            }
+            __syncthreads();   // sy complete; sp free for the next chunk
+        }
+        double y[kRoundNpt];
+        double a = 0.0;
+#pragma unroll
+        for (int r = 0; r < kRoundNpt; ++r) {
+            const int i = tid + kRoundThreads * r;
+            y[r] = i < nb ? sc[r] * sy[i] : 0.0;
+            a = fma(q[r], y[r], a);
+        }
+        a = block_allsum8(a, red8);
+        const double b = j ? sqrt(bprev) : 0.0;
+        double ss = 0.0;
+#pragma unroll
+        for (int r = 0; r < kRoundNpt; ++r) {
+            double t = y[r] - a * q[r];
+            if (j) t -= b * qp[r];
+            y[r] = t;
+            ss = fma(t, t, ss);
+        }
+        ss = block_allsum8(ss, red8);
+        const double inv = ss > 0.0 ? 1.0 / sqrt(ss) : 1.0;
+#pragma unroll
+        for (int r = 0; r < kRoundNpt; ++r) {
+            qp[r] = q[r];
+            q[r] = ss > 0.0 ? y[r] * inv : y[r];
+        }
+        if (tid == 0) {
+            it.al[(size_t)j * m + v] = a;
+            it.b2[(size_t)j * m + v] = ss;
+        }
+        bprev = ss;
+    }
+#pragma unroll
+    for (int r = 0; r < kRoundNpt; ++r) {
+        const int i = tid + kRoundThreads * r;
+        if (i < nb) {
+            it.v[0][base + i] = q[r];
+            it.v[1][base + i] = qp[r];
+        }
+    }
+}
+
 // Largest eigenvalue of the k x k tridiagonal matrix (alpha_i, sqrt(b2_i)) of
 // view v by multisection over one wave: each round every lane counts (Sturm
 // sequence) the eigenvalues below its own shift of the bracket, and the
@@ -487,6 +672,18 @@ hipError_t launch_rows_start(const NormItem* it, const RowRef* rows, int nrows, 
 
 hipError_t launch_rows_step(const NormItem* it, const RowRef* rows, int nrows, int rot, int j, hipStream_t s) {
     rows_step_kernel<<<nrows, 256, 0, s>>>(it, rows, nrows, rot, j);
+    return hipGetLastError();
+}
+
+bool rows_round_fits(int max_nb) {
+    return max_nb <= kRoundMaxBins && round_lds_doubles(max_nb) * sizeof(double) <= 65536;
+}
+
+hipError_t launch_rows_round(const NormItem* it, const RowRef* rows, int nrows, int j0, int j1, int max_nb,
+                             hipStream_t s) {
+    if (!rows_round_fits(max_nb)) return hipErrorInvalidValue;
+    rows_round_kernel<<<nrows, kRoundThreads, round_lds_doubles(max_nb) * sizeof(double), s>>>(it, rows, nrows, j0,
+                                                                                                j1);
     return hipGetLastError();
 }
 

@@ -175,14 +175,16 @@ def test_invalid_weights_and_data_are_rejected(gpu):
         assert e.value.code == ctpd.CTPD_EINVAL
 
 
-def test_lambda_h_equals_the_largest_per_view_eigenvalue(gpu):
+@pytest.mark.parametrize("n,m,nb", [(128, 180, 184), (48, 10, 1100)])
+def test_lambda_h_equals_the_largest_per_view_eigenvalue(gpu, n, m, nb):
     # W^-1/2 D W^-1/2 is block diagonal over views: lambda_h is the largest
     # eigenvalue of the m dense nb x nb blocks (brute force here).  The GPU
     # stops the chains of views whose bound (symbol maximum x max 1/w) falls
-    # below the best Ritz value, which must not change the result.
+    # below the best Ritz value, which must not change the result.  Up to 1024
+    # bins a round of a chain is one launch; 1100 bins take the per-step path
+    # (batched FP64 MFMA filter, then the recurrence kernel).
     from scipy.linalg import eigh, toeplitz
     from oracle.filters import smoothed_ramp_taps
-    n, m, nb = 128, 180, 184
     b, w = lowdose_inputs(n, m, nb, seed=21, n_ell=12, i0=2e4)
     with ctpd.Operator(n, m, nb) as op:
         _, info = op.lowdose_solve(dev(b), dev(w), 0.01, 1)
