@@ -420,7 +420,8 @@ int ensure_hv(ctpd_op* op, int kmax) {
         ALLOC(op->hv_item, 1);
         HIP_TRY(hipHostMalloc((void**)&op->hv_item_host, sizeof(NormItem), hipHostMallocDefault));
         ALLOC(op->hv_sum, 3);
-        HIP_TRY(hipHostMalloc((void**)&op->hv_sum_host, sizeof(double) * 3, hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&op->hv_sum_host, sizeof(double) * 6, hipHostMallocDefault));
+        for (auto& e : op->hv_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         std::vector<RowRef> rows(op->m);
         for (int v = 0; v < op->m; ++v) rows[v] = RowRef{0, v};
         ALLOC(op->hv_rows, op->m);
@@ -452,8 +453,8 @@ int ensure_hv(ctpd_op* op, int kmax) {
 
 int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, const double* kappa, int kmax,
                    hipStream_t s, NormItem* items, NormItem* items_host, const RowRef* rows, int nrows,
-                   const BlockRef* filt, int nfilt, double* summary, double* summary_host, double* lam,
-                   int* steps) {
+                   const BlockRef* filt, int nfilt, double* summary, double* summary_host, const hipEvent_t* ev,
+                   double* lam, int* steps) {
     const int P = (int)ops.size();
     for (int i = 0; i < P; ++i) {
         ctpd_op* op = ops[i];
@@ -490,27 +491,43 @@ int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, cons
     // in one workgroup); beyond, a batched FP64 MFMA filter and a step kernel per step
     const bool fused = rows_round_fits(max_nb);
     constexpr int kRound = 8;
-    int j = 0;
-    for (bool running = true; running && j < kmax;) {
-        const int j1 = std::min(kmax, j + kRound);
-        if (fused) {
-            HIP_TRY(launch_rows_round(items, rows, nrows, j, j1, max_nb, s));
-            j = j1;
-        }
-        for (; j < j1; ++j) {
-            const int rot = (3 - j % 3) % 3;
-            HIP_TRY(launch_norm_filter_batched(items, filt, nfilt, rot, s));
-            HIP_TRY(launch_rows_step(items, rows, nrows, rot, j, s));
-        }
-        HIP_TRY(launch_rows_ritz(items, rows, nrows, P, j, 1e-9, s));
-        HIP_TRY(hipMemcpyAsync(summary_host, summary, sizeof(double) * 3 * P, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        running = false;
-        for (int i = 0; i < P; ++i) running = running || summary_host[3 * i + 1] > 0.0;
+    // steps j0 .. j1-1, the Ritz values and the summary, copied to a pinned
+    // slot of 3 P doubles with an event behind it
+    auto enqueue = [&](int j0, int j1, int slot) -> int {
+        if (fused) HIP_TRY(launch_rows_round(items, rows, nrows, j0, j1, max_nb, s));
+        else
+            for (int j = j0; j < j1; ++j) {
+                const int rot = (3 - j % 3) % 3;
+                HIP_TRY(launch_norm_filter_batched(items, filt, nfilt, rot, s));
+                HIP_TRY(launch_rows_step(items, rows, nrows, rot, j, s));
+            }
+        HIP_TRY(launch_rows_ritz(items, rows, nrows, P, j1, 1e-9, s));
+        HIP_TRY(hipMemcpyAsync(summary_host + (size_t)3 * P * slot, summary, sizeof(double) * 3 * P,
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(ev[slot], s));
+        return CTPD_OK;
+    };
+    // Rounds are queued one ahead: round r + 1 runs while the host reads round
+    // r's summary.  It sees the stops that summary made, so when no chain was
+    // left running it does nothing and its summary repeats round r's.
+    int j = std::min(kmax, kRound), slot = 0, r;
+    if ((r = enqueue(0, j, 0))) return r;
+    const double* res = summary_host;
+    for (;;) {
+        const int jn = std::min(kmax, j + kRound);
+        const bool ahead = jn > j;
+        if (ahead && (r = enqueue(j, jn, 1 - slot))) return r;
+        HIP_TRY(hipEventSynchronize(ev[slot]));
+        res = summary_host + (size_t)3 * P * slot;
+        bool running = false;
+        for (int i = 0; i < P; ++i) running = running || res[3 * i + 1] > 0.0;
+        if (!running || !ahead) break;
+        j = jn;
+        slot = 1 - slot;
     }
     for (int i = 0; i < P; ++i) {
-        lam[i] = summary_host[3 * i + 0];
-        steps[i] = summary_host[3 * i + 1] > 0.0 ? j : (int)summary_host[3 * i + 2];
+        lam[i] = res[3 * i + 0];
+        steps[i] = res[3 * i + 1] > 0.0 ? j : (int)res[3 * i + 2];
     }
     return CTPD_OK;
 }
@@ -632,6 +649,7 @@ int ctpd_op_create(const ctpd_geometry* g, void* stream, ctpd_op** out) {
 void ctpd_op_destroy(ctpd_op* op) {
     if (!op) return;
     if (op->stream || op->views) (void)hipStreamSynchronize(op->stream);
+    if (op->aux) (void)hipStreamSynchronize(op->aux);   // a lambda_h round queued ahead may still run there
     void* ptrs[] = {op->views, op->xp, op->xTp, op->x, op->z, op->p[0], op->p[1], op->mu[0], op->mu[1], op->mu[2],
                     op->mubar, op->q, op->sx, op->winv, op->taps64, op->taps32, op->partials, op->red, op->cost_dev,
                     op->img64[0], op->img64[1], op->img64[2], op->pad64[0], op->pad64[1], op->sino64[0], op->sino64[1],
@@ -654,6 +672,8 @@ void ctpd_op_destroy(ctpd_op* op) {
         if (p) (void)hipFree(p);
     if (op->hv_item_host) (void)hipHostFree(op->hv_item_host);
     if (op->hv_sum_host) (void)hipHostFree(op->hv_sum_host);
+    for (auto e : op->hv_ev)
+        if (e) (void)hipEventDestroy(e);
     delete op;
 }
 
@@ -744,7 +764,7 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
         const float* wp[1] = {w};
         if ((r = lambda_h_views({op}, wp, &S.kappa, k.norm_steps, op->aux, op->hv_item, op->hv_item_host,
                                 op->hv_rows, op->m, op->hv_filt, op->hv_nfilt, op->hv_sum, op->hv_sum_host,
-                                &S.lam_h, &S.steps_h)))
+                                op->hv_ev, &S.lam_h, &S.steps_h)))
             return r;
         if (S.run_a) {
             HIP_TRY(hipStreamSynchronize(op->stream));

@@ -78,7 +78,8 @@ struct ctpd_batch {
     RowRef* rows = nullptr;             // every (problem, view)
     int nrows = 0;
     double* hsum = nullptr;             // lambda_h chain summaries, 3 per problem (device)
-    double* hsum_host = nullptr;        // pinned mirror
+    double* hsum_host = nullptr;        // pinned, two slots of 3 per problem
+    hipEvent_t hev[2] = {nullptr, nullptr};   // behind the copies into the two slots
     BlockRef* map[K_COUNT] = {};
     int nblk[K_COUNT] = {};
     hipGraph_t graph = nullptr;
@@ -212,7 +213,8 @@ int ctpd_batch_create(const ctpd_geometry* geoms, int32_t count, void* stream, c
         ALLOC(bt->rows, rows.size());
         HIP_TRY(hipMemcpy(bt->rows, rows.data(), sizeof(RowRef) * rows.size(), hipMemcpyHostToDevice));
         ALLOC(bt->hsum, 3 * count);
-        HIP_TRY(hipHostMalloc((void**)&bt->hsum_host, sizeof(double) * 3 * count, hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&bt->hsum_host, sizeof(double) * 6 * count, hipHostMallocDefault));
+        for (auto& e : bt->hev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         return build_maps(bt);
     };
     const int r = init();
@@ -240,6 +242,8 @@ void ctpd_batch_destroy(ctpd_batch* bt) {
     if (bt->rows) (void)hipFree(bt->rows);
     if (bt->hsum) (void)hipFree(bt->hsum);
     if (bt->hsum_host) (void)hipHostFree(bt->hsum_host);
+    for (auto e : bt->hev)
+        if (e) (void)hipEventDestroy(e);
     if (bt->ev) (void)hipEventDestroy(bt->ev);
     if (bt->gs) (void)hipStreamDestroy(bt->gs);
     delete bt;
@@ -282,8 +286,8 @@ int ctpd_batch_lowdose_solve(ctpd_batch* bt, const float* const* b, const float*
         std::vector<int> st(P);
         for (int i = 0; i < P; ++i) kap[i] = S[i].kappa;
         if ((r = lambda_h_views(bt->ops, w, kap.data(), k.norm_steps, bt->gs, bt->nitems, bt->nitems_host, bt->rows,
-                                bt->nrows, bt->map[K_NFILT], bt->nblk[K_NFILT], bt->hsum, bt->hsum_host, lam.data(),
-                                st.data())))
+                                bt->nrows, bt->map[K_NFILT], bt->nblk[K_NFILT], bt->hsum, bt->hsum_host, bt->hev,
+                                lam.data(), st.data())))
             return r;
         for (int i = 0; i < P; ++i) {
             S[i].lam_h = lam[i];

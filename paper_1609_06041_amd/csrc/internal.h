@@ -283,7 +283,8 @@ hipError_t launch_batch_copy_out(const BatchItem* items, const BlockRef* map, in
 hipError_t launch_rows_start(const NormItem* it, const RowRef* rows, int nrows, uint64_t seed, hipStream_t s);
 hipError_t launch_rows_step(const NormItem* it, const RowRef* rows, int nrows, int rot, int j, hipStream_t s);
 // steps j0 .. j1-1 of every running chain in one launch (q in v[0], previous q
-// in v[1] on entry and exit); only when rows_round_fits(the largest nb of the table)
+// in v[1] on entry and exit); only when rows_round_fits(the largest nb of the
+// table), which holds up to 1024 bins
 bool rows_round_fits(int max_nb);
 hipError_t launch_rows_round(const NormItem* it, const RowRef* rows, int nrows, int j0, int j1, int max_nb,
                              hipStream_t s);

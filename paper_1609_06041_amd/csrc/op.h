@@ -86,7 +86,8 @@ struct ctpd_op {
     ctpd::BlockRef* hv_filt = nullptr;        // device, filter tiles
     int hv_nfilt = 0;
     double* hv_sum = nullptr;                 // device, 3 doubles
-    double* hv_sum_host = nullptr;            // pinned
+    double* hv_sum_host = nullptr;            // pinned, two slots of 3 doubles
+    hipEvent_t hv_ev[2] = {nullptr, nullptr}; // behind the copies into the two slots
     // workspaces of the unrolled solve's reverse pass (allocated on first use)
     ctpd_host::UnrolledWs* uw = nullptr;
 };
@@ -231,13 +232,15 @@ int lowdose_setup_begin(ctpd_op* op, const float* b, const float* w, const Knobs
 // lambda_max(W^-1/2 D W^-1/2) of each handle by per-view Lanczos chains run in
 // lockstep on stream s (needs op->sino64[3] = sqrt(1/w) and the taps).  items:
 // device / pinned tables of ops.size() entries; rows: every (problem, view);
-// filt: the filter tiles of all problems; summary: 3 doubles per problem
-// (device and pinned).  lam[i], steps[i] receive the results.
+// filt: the filter tiles of all problems; summary: 3 doubles per problem on
+// the device, two slots of 3 per problem pinned, with an event for each slot.
+// lam[i], steps[i] receive the results.  A round may still run on s after the
+// return (one queued ahead that found every chain stopped: it changes nothing).
 int ensure_hv(ctpd_op* op, int kmax);
 int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, const double* kappa, int kmax,
                    hipStream_t s, ctpd::NormItem* items, ctpd::NormItem* items_host, const ctpd::RowRef* rows,
                    int nrows, const ctpd::BlockRef* filt, int nfilt, double* summary, double* summary_host,
-                   double* lam, int* steps);
+                   const hipEvent_t* ev, double* lam, int* steps);
 void lowdose_setup_end(ctpd_op* op, const Knobs& k, LowdoseSetup* S);
 
 // Workgroup placement of batched launches: problems go to XCDs by work

@@ -545,38 +545,96 @@ __global__ __launch_bounds__(kRoundThreads) void rows_round_kernel(const NormIte
     }
 }
 
-// Largest eigenvalue of the k x k tridiagonal matrix (alpha_i, sqrt(b2_i)) of
-// view v by multisection over one wave: each round every lane counts (Sturm
-// sequence) the eigenvalues below its own shift of the bracket, and the
-// bracket shrinks to the interval between the last shift with fewer than k
-// eigenvalues below and the first with all k (65x per round).
-__device__ double rows_tridiag_max(const double* __restrict__ al, const double* __restrict__ bb, int k, int lane) {
+// b / d for the Sturm recurrence: the reciprocal instruction refined by one
+// Newton step (a few dependent instructions instead of the division's
+// sequence; the counts only need the sign of each pivot)
+__device__ __forceinline__ double sturm_quot(double b, double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return b * r;
+}
+
+// Largest eigenvalues of the leading k x k and (k-1) x (k-1) sections of the
+// tridiagonal matrix (alpha_i, sqrt(b2_i)) of a view, by multisection over one
+// wave: each round every lane counts (Sturm sequence) the eigenvalues below its
+// own shift of each bracket, and each bracket shrinks to the interval between
+// the last shift with fewer eigenvalues below than the section's size and the
+// first with all of them (65x per round).  The two sections' sequences are
+// interleaved in one loop, so their dependent chains overlap.  th1 is NaN for k = 1.
+__device__ void rows_tridiag_max2(const double* __restrict__ al, const double* __restrict__ bb, int k, int lane,
+                                  double* th, double* th1) {
     // al[i]: alpha_i; bb[i]: beta_{i+1}^2 (couples i and i+1); both in LDS
-    double lo = al[0], hi = al[0];
+    const int k1 = k - 1;
+    double lo = al[0], hi = al[0], lo1 = al[0], hi1 = al[0];
     for (int i = 0; i < k; ++i) {
-        const double r = (i > 0 ? sqrt(bb[i - 1]) : 0.0) + (i < k - 1 ? sqrt(bb[i]) : 0.0);
+        const double left = i > 0 ? sqrt(bb[i - 1]) : 0.0;
+        const double r = left + (i < k - 1 ? sqrt(bb[i]) : 0.0);
         lo = fmin(lo, al[i] - r);
         hi = fmax(hi, al[i] + r);
+        if (i < k1) {
+            const double r1 = left + (i < k1 - 1 ? sqrt(bb[i]) : 0.0);
+            lo1 = fmin(lo1, al[i] - r1);
+            hi1 = fmax(hi1, al[i] + r1);
+        }
     }
-    if (!isfinite(lo) || !isfinite(hi)) return hi;
-    for (int round = 0; round < 40 && hi - lo > 1e-15 * fmax(fabs(lo), fabs(hi)); ++round) {
-        const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
-        int cnt = 0;
-        double d = 1.0;
-        for (int i = 0; i < k; ++i) {
-            d = al[i] - x - (i > 0 ? bb[i - 1] / d : 0.0);
-            if (d == 0.0) d = -1e-300;
-            if (d < 0.0) ++cnt;
+    if (!isfinite(lo) || !isfinite(hi)) {
+        *th = hi;
+        *th1 = k1 > 0 ? hi1 : NAN;
+        return;
+    }
+    auto open = [](double l, double h) { return h - l > 1e-15 * fmax(fabs(l), fabs(h)); };
+    // shift j (1 .. 64) of the bracket [l, h]; the bracket update reuses the
+    // same expression, so its new ends are shifts that were tested
+    auto shift = [](double l, double h, int j) { return l + (h - l) * ((double)j * (1.0 / 65.0)); };
+    bool go = open(lo, hi), go1 = k1 > 0 && isfinite(lo1) && isfinite(hi1) && open(lo1, hi1);
+    for (int round = 0; round < 40 && (go || go1); ++round) {
+        const double x = shift(lo, hi, lane + 1), x1 = shift(lo1, hi1, lane + 1);
+        int cnt = 0, cnt1 = 0;
+        double d = 1.0, d1 = 1.0;
+        // the recurrence scalars of 8 steps are read ahead of their dependent chain
+        for (int i0 = 0; i0 < k; i0 += 8) {
+            double A[8], B[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + u;
+                A[u] = i < k ? al[i] : 0.0;
+                B[u] = (i > 0 && i < k) ? bb[i - 1] : 0.0;
+            }
+            // branch-free (selects), so the two chains interleave; B = 0 at i = 0
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + u;
+                const double dn = A[u] - x - sturm_quot(B[u], d);
+                const double dn1 = A[u] - x1 - sturm_quot(B[u], d1);
+                const bool on = i < k, on1 = i < k1;
+                d = on ? (dn == 0.0 ? -1e-300 : dn) : d;
+                d1 = on1 ? (dn1 == 0.0 ? -1e-300 : dn1) : d1;
+                cnt += (on && d < 0.0) ? 1 : 0;
+                cnt1 += (on1 && d1 < 0.0) ? 1 : 0;
+            }
         }
         // first lane whose shift lies above every eigenvalue
-        const unsigned long long above = __ballot(cnt == k);
-        const int f = above ? __ffsll((long long)above) - 1 : 64;
-        const double nhi = f < 64 ? lo + (hi - lo) * (double)(f + 1) / 65.0 : hi;
-        const double nlo = f > 0 ? lo + (hi - lo) * (double)f / 65.0 : lo;
-        lo = nlo;
-        hi = nhi;
+        if (go) {
+            const unsigned long long above = __ballot(cnt == k);
+            const int f = above ? __ffsll((long long)above) - 1 : 64;
+            const double nhi = f < 64 ? shift(lo, hi, f + 1) : hi;
+            const double nlo = f > 0 ? shift(lo, hi, f) : lo;
+            lo = nlo;
+            hi = nhi;
+            go = open(lo, hi);
+        }
+        if (go1) {
+            const unsigned long long above = __ballot(cnt1 == k1);
+            const int f = above ? __ffsll((long long)above) - 1 : 64;
+            const double nhi = f < 64 ? shift(lo1, hi1, f + 1) : hi1;
+            const double nlo = f > 0 ? shift(lo1, hi1, f) : lo1;
+            lo1 = nlo;
+            hi1 = nhi;
+            go1 = open(lo1, hi1);
+        }
     }
-    return hi;
+    *th = hi;
+    *th1 = k1 > 0 ? hi1 : NAN;
 }
 
 constexpr int kRitzMax = CTPD_MAX_NORM_STEPS;   // steps a per-view chain can take
@@ -604,13 +662,11 @@ __global__ __launch_bounds__(256) void rows_ritz_kernel(const NormItem* __restri
     // the wave's own LDS writes are complete and visible to its lanes before the reads
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
-    const double th = rows_tridiag_max(sal[wv], sbb[wv], steps, lane);
+    double th, th1;
+    rows_tridiag_max2(sal[wv], sbb[wv], steps, lane, &th, &th1);
     const double bn = sqrt(fmax(sbb[wv][steps - 1], 0.0));
     bool stop = !(bn > 1e-300 * fmax(1.0, fabs(th))) || !isfinite(th);
-    if (!stop && steps > 1) {
-        const double th1 = rows_tridiag_max(sal[wv], sbb[wv], steps - 1, lane);
-        stop = fabs(th - th1) <= tol * fabs(th);
-    }
+    if (!stop && steps > 1) stop = fabs(th - th1) <= tol * fabs(th);
     if (lane == 0) {
         it.theta[v] = th;
         if (stop) it.done[v] = steps;
