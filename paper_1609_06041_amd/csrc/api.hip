@@ -262,14 +262,29 @@ int filter(ctpd_op* op, int mode, const float* in0, const float* in1, const floa
 // written by the projector itself
 int project_resid(ctpd_op* op, const float* x, const float* rb, const float* rw, const float* rm, float* y) {
     HIP_TRY(launch_pad_planes<float>(x, op->xp, op->xTp, op->n, op->stream));
-    HIP_TRY(launch_forward_resid(op->xp, op->xTp, y, op->views, op->n, op->m, op->nb, rb, rw, rm, op->stream));
+    HIP_TRY(launch_forward_slab(op->xp, op->xTp, y, op->views, op->fwd_tasks, op->fwd_groups, op->n, op->nb, rb, rw,
+                                rm, op->stream));
     return CTPD_OK;
 }
 
 int project(ctpd_op* op, const float* x, float* y) {
-    HIP_TRY(launch_pad_planes<float>(x, op->xp, op->xTp, op->n, op->stream));
-    HIP_TRY(launch_forward<float>(op->xp, op->xTp, y, op->views, op->n, op->m, op->nb, op->stream));
-    return CTPD_OK;
+    return project_resid(op, x, nullptr, nullptr, nullptr, y);
+}
+
+// Task groups of the slab projector: for each orientation (row views, then
+// column views) the (view, 64-bin block) pairs in view order, cut into groups
+// of forward_slab_tasks_per_group(), the last group of each padded with -1.
+std::vector<int> slab_tasks(const std::vector<ViewGeom>& hv, int nb) {
+    const int G = forward_slab_tasks_per_group(), nblk = (nb + 63) / 64;
+    std::vector<int> out;
+    for (int row = 1; row >= 0; --row) {
+        const size_t start = out.size();
+        for (int v = 0; v < (int)hv.size(); ++v)
+            if (hv[v].row == row)
+                for (int b = 0; b < nblk; ++b) out.push_back(v * 64 + b);
+        while ((out.size() - start) % G) out.push_back(-1);
+    }
+    return out;
 }
 
 // n_iter dual steps on p (warm start in pin; result pointer returned in *pout,
@@ -618,6 +633,10 @@ int ctpd_op_create(const ctpd_geometry* g, void* stream, ctpd_op** out) {
         ALLOC(op->views, op->m);
         std::vector<ViewGeom> hv = make_views(op->n, op->m, op->nb);
         HIP_TRY(hipMemcpy(op->views, hv.data(), sizeof(ViewGeom) * op->m, hipMemcpyHostToDevice));
+        const std::vector<int> tasks = slab_tasks(hv, op->nb);
+        ALLOC(op->fwd_tasks, tasks.size());
+        HIP_TRY(hipMemcpy(op->fwd_tasks, tasks.data(), sizeof(int) * tasks.size(), hipMemcpyHostToDevice));
+        op->fwd_groups = (int)(tasks.size() / forward_slab_tasks_per_group());
         ALLOC(op->xp, op->Jp);
         ALLOC(op->xTp, op->Jp);
         ALLOC(op->x, op->J);
@@ -650,7 +669,7 @@ void ctpd_op_destroy(ctpd_op* op) {
     if (!op) return;
     if (op->stream || op->views) (void)hipStreamSynchronize(op->stream);
     if (op->aux) (void)hipStreamSynchronize(op->aux);   // a lambda_h round queued ahead may still run there
-    void* ptrs[] = {op->views, op->xp, op->xTp, op->x, op->z, op->p[0], op->p[1], op->mu[0], op->mu[1], op->mu[2],
+    void* ptrs[] = {op->views, op->fwd_tasks, op->xp, op->xTp, op->x, op->z, op->p[0], op->p[1], op->mu[0], op->mu[1], op->mu[2],
                     op->mubar, op->q, op->sx, op->winv, op->taps64, op->taps32, op->partials, op->red, op->cost_dev,
                     op->img64[0], op->img64[1], op->img64[2], op->pad64[0], op->pad64[1], op->sino64[0], op->sino64[1],
                     op->sino64[2], op->sino64[3], op->sino64[4], op->sino64[5], op->lz[0], op->lz[1],

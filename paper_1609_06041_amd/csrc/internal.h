@@ -173,6 +173,16 @@ hipError_t launch_forward(const T* xp, const T* xTp, T* y, const ViewGeom* views
 // (rw null: y = A x - rb), with the arithmetic of the filter prologues
 hipError_t launch_forward_resid(const float* xp, const float* xTp, float* y, const ViewGeom* views, int n, int m,
                                 int nb, const float* rb, const float* rw, const float* rm, hipStream_t s);
+// The same projection (and optional residual epilogue) in slab form, for one
+// float32 problem: tasks holds ngroups groups of forward_slab_tasks_per_group()
+// entries view * 64 + (64-bin block), each group of one orientation, -1 for
+// none, the first entry of a group never -1.  Bit-identical to launch_forward /
+// launch_forward_resid.
+hipError_t launch_forward_slab(const float* xp, const float* xTp, float* y, const ViewGeom* views, const int* tasks,
+                               int ngroups, int n, int nb, const float* rb, const float* rw, const float* rm,
+                               hipStream_t s);
+int forward_slab_rows(int n);
+int forward_slab_tasks_per_group();
 // out = alpha * xin + beta * A^T (c1 * y1 + c2 * y2)   (xin, y2 may be null)
 template <typename T>
 hipError_t launch_adjoint(const T* y1, const T* y2, T c1, T c2, const T* xin, T alpha, T beta, T* out,

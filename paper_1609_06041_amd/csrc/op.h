@@ -29,6 +29,8 @@ struct ctpd_op {
     size_t J = 0, I = 0;   // image / sinogram sizes
     size_t Jp = 0;         // padded plane size n * (n + 6)
     ViewGeom* views = nullptr;
+    int* fwd_tasks = nullptr;   // the slab projector's task groups (device)
+    int fwd_groups = 0;
     // float32 iteration state
     float* xp = nullptr;    // padded image planes for the forward projector, [n][n+6] each
     float* xTp = nullptr;

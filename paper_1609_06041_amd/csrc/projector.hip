@@ -7,6 +7,8 @@
 // pixels carries ~3e-5 pixel of rounding, which alone would exceed a 1e-5
 // relative error on non-smooth images; the float64 position costs a few
 // full-rate DP instructions per sample on CDNA.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace ctpd {
@@ -105,17 +107,15 @@ constexpr int FW_BATCH = 8;
 
 // rb (optional): write the residual A x - rb - rw .* rm (rw null: A x - rb)
 // instead of A x, with the arithmetic of the filter prologues.
-template <typename T, int FB = FW_BATCH>
-__device__ __forceinline__ void forward_body(const T* __restrict__ xp, const T* __restrict__ xTp, T* __restrict__ y,
-                                             const ViewGeom* __restrict__ views, int n, int nb, int bxi, int v,
-                                             const T* __restrict__ rb = nullptr, const T* __restrict__ rw = nullptr,
-                                             const T* __restrict__ rm = nullptr) {
-    const int u = bxi * 256 + threadIdx.x;
-    const ViewGeom g = views[v];
-    const int P = n + 2 * FP_PAD;
-    const double base = fma((double)min(u, nb - 1), g.su, g.s0);
-    // this ray's steps whose sample lies within one step of (-1, n)
-    int t0 = n, t1 = -1;
+// Ray u of view g: its sample position at step 0 (base; rays past the last
+// bin reuse the last bin's) and the steps [t0, t1] whose sample lies within
+// one step of (-1, n), as the union over the wave (wave-uniform; empty when
+// t0 > t1).
+__device__ __forceinline__ void wave_ray_span(const ViewGeom& g, int u, int n, int nb, double& base, int& t0,
+                                              int& t1) {
+    base = fma((double)min(u, nb - 1), g.su, g.s0);
+    t0 = n;
+    t1 = -1;
     if (u < nb) {
         if (g.st != 0.0) {
             const double ta = (-1.0 - base) / g.st, tb = ((double)n - base) / g.st;
@@ -134,6 +134,19 @@ __device__ __forceinline__ void forward_body(const T* __restrict__ xp, const T* 
     }
     t0 = __builtin_amdgcn_readfirstlane(t0);
     t1 = __builtin_amdgcn_readfirstlane(t1);
+}
+
+template <typename T, int FB = FW_BATCH>
+__device__ __forceinline__ void forward_body(const T* __restrict__ xp, const T* __restrict__ xTp, T* __restrict__ y,
+                                             const ViewGeom* __restrict__ views, int n, int nb, int bxi, int v,
+                                             const T* __restrict__ rb = nullptr, const T* __restrict__ rw = nullptr,
+                                             const T* __restrict__ rm = nullptr) {
+    const int u = bxi * 256 + threadIdx.x;
+    const ViewGeom g = views[v];
+    const int P = n + 2 * FP_PAD;
+    double base;
+    int t0, t1;
+    wave_ray_span(g, u, n, nb, base, t0, t1);
     const double two32 = 4294967296.0;
     unsigned long long sfix = (unsigned long long)llrint((fma((double)t0, g.st, base) + FP_PAD) * two32);
     const unsigned long long dfix = (unsigned long long)llrint(g.st * two32);
@@ -191,6 +204,142 @@ hipError_t launch_forward_resid(const float* xp, const float* xTp, float* y, con
                                 int nb, const float* rb, const float* rw, const float* rm, hipStream_t s) {
     dim3 grid((nb + 255) / 256, m);
     forward_resid_kernel<<<grid, 256, 0, s>>>(xp, xTp, y, views, n, nb, rb, rw, rm);
+    return hipGetLastError();
+}
+
+// Slab form of the forward projector (float32, one problem).  A workgroup of
+// 12 waves takes 36 (view, 64-bin block) tasks of views of one orientation,
+// three per wave, and streams that orientation's padded plane through LDS in
+// slabs of R rows, the next slab prefetched into registers while the current
+// one is used.  A ray's steps, positions and sums are forward_body's, taken in
+// the same order, so the results are the same bit for bit; the taps come from
+// LDS instead of one gather per step through the texture-address unit, and the
+// plane passes through L2 once per three views.  tasks: per workgroup 36
+// entries view * 64 + block (-1 for none; the first entry is never -1).
+constexpr int kSlabWaves = 12, kSlabThreads = 64 * kSlabWaves, kSlabTPW = 3, kSlabTasks = kSlabWaves * kSlabTPW;
+constexpr int kSlabFB = 4, kSlabPre = 24;
+
+int forward_slab_rows(int n) {
+    // the slab (R rows of n + 6 floats) within 64 KB of LDS and 24 prefetched floats a thread
+    const int P = n + 2 * FP_PAD;
+    return std::max(1, std::min({31, 16384 / P, kSlabPre * kSlabThreads / P}));
+}
+
+int forward_slab_tasks_per_group() { return kSlabTasks; }
+
+__global__ __launch_bounds__(kSlabThreads) void forward_slab_kernel(const float* __restrict__ xp,
+                                                                    const float* __restrict__ xTp,
+                                                                    float* __restrict__ y,
+                                                                    const ViewGeom* __restrict__ views,
+                                                                    const int* __restrict__ tasks, int n, int nb,
+                                                                    int R, const float* __restrict__ rb,
+                                                                    const float* __restrict__ rw,
+                                                                    const float* __restrict__ rm) {
+    extern __shared__ float slab[];
+    const int P = n + 2 * FP_PAD;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int* tk = tasks + (size_t)blockIdx.x * kSlabTasks;
+    const float* plane = views[tk[0] >> 6].row ? xp : xTp;
+    const unsigned cmax = (unsigned)(P - 2);
+    const double two32 = 4294967296.0;
+    unsigned long long sfix[kSlabTPW], dfix[kSlabTPW];
+    float acc_a[kSlabTPW], acc_d[kSlabTPW];
+    int t0w[kSlabTPW], t1w[kSlabTPW], vv[kSlabTPW], uu[kSlabTPW];
+#pragma unroll
+    for (int j = 0; j < kSlabTPW; ++j) {
+        const int e = tk[wv + kSlabWaves * j];
+        const int v = e >= 0 ? e >> 6 : -1;
+        const int u = e >= 0 ? (e & 63) * 64 + lane : nb;
+        vv[j] = v;
+        uu[j] = u;
+        acc_a[j] = 0.f;
+        acc_d[j] = 0.f;
+        double base = 0.0, st = 0.0;
+        int t0 = n, t1 = -1;
+        if (v >= 0) {
+            const ViewGeom g = views[v];
+            st = g.st;
+            wave_ray_span(g, u, n, nb, base, t0, t1);
+        }
+        t0w[j] = t0;
+        t1w[j] = t1;
+        sfix[j] = (unsigned long long)llrint((fma((double)t0, st, base) + FP_PAD) * two32);
+        dfix[j] = (unsigned long long)llrint(st * two32);
+    }
+    const int slab_elems = R * P;
+    const int per = (slab_elems + kSlabThreads - 1) / kSlabThreads;   // <= kSlabPre
+    float pre[kSlabPre];
+    auto fetch = [&](int r0) {
+        const int cnt = min(R, n - r0) * P;
+        const float* src = plane + (size_t)r0 * P;
+#pragma unroll
+        for (int k = 0; k < kSlabPre; ++k) {
+            const int e = threadIdx.x + kSlabThreads * k;
+            pre[k] = (k < per && e < cnt) ? src[e] : 0.f;
+        }
+    };
+    fetch(0);
+    for (int r0 = 0; r0 < n; r0 += R) {
+        __syncthreads();   // the previous slab has been read
+#pragma unroll
+        for (int k = 0; k < kSlabPre; ++k) {
+            const int e = threadIdx.x + kSlabThreads * k;
+            if (k < per && e < slab_elems) slab[e] = pre[k];
+        }
+        __syncthreads();
+        if (r0 + R < n) fetch(r0 + R);
+        const int r1 = min(n, r0 + R) - 1;
+#pragma unroll
+        for (int j = 0; j < kSlabTPW; ++j) {
+            const int ta = max(t0w[j], r0), tb = min(t1w[j], r1);
+            int t = ta;
+            for (; t + kSlabFB - 1 <= tb; t += kSlabFB) {
+                unsigned off[kSlabFB];
+                float lf[kSlabFB], a[kSlabFB], b[kSlabFB];
+#pragma unroll
+                for (int q = 0; q < kSlabFB; ++q) {
+                    off[q] = min((unsigned)(sfix[j] >> 32), cmax) + (unsigned)((t - r0 + q) * P);
+                    lf[q] = (float)(unsigned)sfix[j];
+                    sfix[j] += dfix[j];
+                }
+#pragma unroll
+                for (int q = 0; q < kSlabFB; ++q) {
+                    a[q] = slab[off[q]];
+                    b[q] = slab[off[q] + 1];
+                }
+#pragma unroll
+                for (int q = 0; q < kSlabFB; ++q) {
+                    acc_a[j] += a[q];
+                    acc_d[j] = fma(lf[q], b[q] - a[q], acc_d[j]);
+                }
+            }
+            for (; t <= tb; ++t) {
+                const unsigned off = min((unsigned)(sfix[j] >> 32), cmax) + (unsigned)((t - r0) * P);
+                const float a = slab[off], b = slab[off + 1];
+                acc_a[j] += a;
+                acc_d[j] = fma((float)(unsigned)sfix[j], b - a, acc_d[j]);
+                sfix[j] += dfix[j];
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kSlabTPW; ++j) {
+        if (vv[j] >= 0 && uu[j] < nb) {
+            const size_t idx = (size_t)vv[j] * nb + uu[j];
+            float q = (acc_a[j] + acc_d[j] * 2.3283064365386962890625e-10f) * (float)views[vv[j]].len;
+            if (rb) q = rw ? fma(-rw[idx], rm[idx], q - rb[idx]) : q - rb[idx];
+            y[idx] = q;
+        }
+    }
+}
+
+hipError_t launch_forward_slab(const float* xp, const float* xTp, float* y, const ViewGeom* views, const int* tasks,
+                               int ngroups, int n, int nb, const float* rb, const float* rw, const float* rm,
+                               hipStream_t s) {
+    const int R = forward_slab_rows(n);
+    forward_slab_kernel<<<ngroups, kSlabThreads, sizeof(float) * R * (n + 2 * FP_PAD), s>>>(xp, xTp, y, views, tasks,
+                                                                                          n, nb, R, rb, rw, rm);
     return hipGetLastError();
 }
 
