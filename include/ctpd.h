@@ -59,6 +59,14 @@ typedef struct {
     int32_t n;        /* image side, 1 <= n <= 8192 */
     int32_t n_views;  /* m >= 1 */
     int32_t n_bins;   /* 1 <= n_bins <= CTPD_MAX_BINS */
+    int32_t reserved; /* 0 */
+    const double* angles;  /* host array of the n_views view angles in radians, any
+                              order and range (copied at creation; finite, else
+                              CTPD_EINVAL), or NULL for theta_v = v pi / m.  A view
+                              steps over image rows where |cos| >= |sin| (1 - 1e-12).
+                              D keeps Eqs. 24 / 32 with the view count m: with
+                              uneven angles it is still a valid preconditioner,
+                              no longer the FBP filter of the scan. */
 } ctpd_geometry;
 
 /* Solver knobs.  A zero / negative value selects the default. */

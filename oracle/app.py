@@ -52,9 +52,10 @@ def lambda_max(apply_op, size, dense_below=1500):
     return float(eigsh(op, k=1, which="LA", tol=1e-12, v0=v0)[0][0])
 
 
-def lambda_a(n, m, nb, h):
+def lambda_a(n, m, nb, h, theta=None):
     """lambda_max(A^T D A) = ||D^1/2 A A^T D^T/2|| for the Toeplitz filter with taps h."""
-    op = lambda v: back_project(apply_filter(forward_project(v.reshape(n, n), m, nb), h), n).ravel()
+    op = lambda v: back_project(apply_filter(forward_project(v.reshape(n, n), m, nb, theta=theta), h), n,
+                                theta=theta).ravel()
     return lambda_max(op, n * n)
 
 
@@ -79,7 +80,7 @@ class Steps:
     lambda_h: float = 0.0
 
 
-def steps_lowdose(w, n, tau=None, rho=0.95):
+def steps_lowdose(w, n, tau=None, rho=0.95, theta=None):
     w = np.asarray(w, dtype=np.float64)
     m, nb = w.shape
     winv = 1.0 / w
@@ -87,7 +88,7 @@ def steps_lowdose(w, n, tau=None, rho=0.95):
     if tau is None:
         tau = default_tau_lowdose(kappa, m)
     h = smoothed_ramp_taps(nb, m, tau, kappa)
-    la = lambda_a(n, m, nb, h)
+    la = lambda_a(n, m, nb, h, theta)
     lh = lambda_h(winv, h)
     sigma = rho * min(2.0 / lh, 1.0 / (tau * la))
     return Steps(tau=tau, sigma=sigma, kappa=kappa, lambda_a=la, lambda_h=lh)
@@ -115,7 +116,7 @@ class Result:
 
 
 def app_solve(b, n, iters, tau, sigma, h, beta=1.0, winv=None, n_tv=10, tau_c=0.125,
-              monitor=None, extrapolation="simplified"):
+              monitor=None, extrapolation="simplified", theta=None):
     """The APP iteration of Eqs. 18-20 (winv given) or Eqs. 29-31 (winv None).
 
     k = 0:  mubar = -sigma D b
@@ -126,6 +127,7 @@ def app_solve(b, n, iters, tau, sigma, h, beta=1.0, winv=None, n_tv=10, tau_c=0.
 
     ``extrapolation="direct"`` uses the unsimplified left-hand form of Eq. 18,
     mubar = mu^k + sigma D (A x^k - b - W^-1 mu^k), for checking the algebra.
+    ``theta`` (optional) gives the view angles of A.
     """
     b = np.asarray(b, dtype=np.float64)
     m, nb = b.shape
@@ -139,7 +141,7 @@ def app_solve(b, n, iters, tau, sigma, h, beta=1.0, winv=None, n_tv=10, tau_c=0.
     hist = []
     for k in range(iters):
         if extrapolation == "direct":
-            r = forward_project(x, m, nb) - b
+            r = forward_project(x, m, nb, theta=theta) - b
             if winv is not None:
                 r = r - winv * mu
             mubar = mu + sigma * D(r)
@@ -149,9 +151,9 @@ def app_solve(b, n, iters, tau, sigma, h, beta=1.0, winv=None, n_tv=10, tau_c=0.
             mubar = 2.0 * mu - mu_prev - sigma * D(winv * (mu - mu_prev))
         else:
             mubar = 2.0 * mu - mu_prev
-        z = x - tau * back_project(mubar, n)
+        z = x - tau * back_project(mubar, n, theta=theta)
         x, p1, p2 = tv_prox(z, lam, p1, p2, n_tv, tau_c)
-        r = forward_project(x, m, nb) - b
+        r = forward_project(x, m, nb, theta=theta) - b
         if winv is not None:
             r = r - winv * mu
         mu_prev, mu = mu, mu + sigma * D(r)
@@ -161,20 +163,21 @@ def app_solve(b, n, iters, tau, sigma, h, beta=1.0, winv=None, n_tv=10, tau_c=0.
 
 
 def lowdose_solve(b, w, beta, n, iters, tau=None, sigma=None, n_tv=10, tau_c=0.125, rho=0.95,
-                  record_cost=False):
-    """Algorithm 1 (beta > 0) / Algorithm 1' (beta = 0).  Returns (Result, Steps)."""
+                  record_cost=False, theta=None):
+    """Algorithm 1 (beta > 0) / Algorithm 1' (beta = 0).  Returns (Result, Steps).
+    ``theta`` (optional) gives the view angles; D keeps Eq. 24 with the view count m."""
     w = np.asarray(w, dtype=np.float64)
     m, nb = w.shape
     winv = 1.0 / w
     kappa = float(winv.mean())
     if sigma is None:
-        st = steps_lowdose(w, n, tau, rho)
+        st = steps_lowdose(w, n, tau, rho, theta)
     else:
         st = Steps(tau=default_tau_lowdose(kappa, m) if tau is None else tau, sigma=sigma, kappa=kappa)
     h = smoothed_ramp_taps(nb, m, st.tau, kappa)
-    mon = (lambda x, mu: cost_lowdose(x, b, w, beta)) if record_cost else None
+    mon = (lambda x, mu: cost_lowdose(x, b, w, beta, theta)) if record_cost else None
     res = app_solve(b, n, iters, st.tau, st.sigma, h, beta=beta, winv=winv, n_tv=n_tv, tau_c=tau_c,
-                    monitor=mon)
+                    monitor=mon, theta=theta)
     return res, st
 
 
@@ -231,10 +234,10 @@ def lowdose_identity_solve(b, w, beta, n, iters, tau=None, sigma=None, n_tv=10, 
     return res, st
 
 
-def cost_lowdose(x, b, w, beta):
+def cost_lowdose(x, b, w, beta, theta=None):
     """f(x) of Eq. 1: beta psi(x) + 1/2 sum_i w_i ((A x)_i - b_i)^2."""
     m, nb = np.shape(b)
-    r = forward_project(x, m, nb) - np.asarray(b, dtype=np.float64)
+    r = forward_project(x, m, nb, theta=theta) - np.asarray(b, dtype=np.float64)
     return beta * tv_norm(x) + 0.5 * float((np.asarray(w, dtype=np.float64) * r * r).sum())
 
 

@@ -42,17 +42,18 @@ def _pick(plane, t, k):
     return np.where(ok, plane[t, np.clip(k, 0, n - 1)], 0.0)
 
 
-def forward_project(x, m, nb, views=None):
+def forward_project(x, m, nb, views=None, theta=None):
     """y = A x, y[v, u] = sum over steps of the interpolated image times the step length.
 
     ``views`` (optional) restricts the output to those view indices of the
-    m-view scan, in that order (rows of the returned array).
+    m-view scan, in that order (rows of the returned array); ``theta``
+    (optional) gives the m view angles instead of v*pi/m.
     """
     x = np.asarray(x, dtype=np.float64)
     n = x.shape[0]
     assert x.shape == (n, n)
-    th = angles(m)
-    rows = row_branch(m)
+    th = angles(m, theta)
+    rows = row_branch(m, theta)
     views = range(m) if views is None else list(views)
     y = np.zeros((len(views), nb))
     t = np.arange(n)[:, None]
@@ -66,19 +67,20 @@ def forward_project(x, m, nb, views=None):
     return y
 
 
-def back_project(y, n, m=None, views=None):
+def back_project(y, n, m=None, views=None, theta=None):
     """x = A^T y: every weight of ``forward_project`` scattered back onto its pixel.
 
     By default y holds all m = y.shape[0] views; with ``m`` and ``views`` given,
     row i of y is view ``views[i]`` of the m-view scan and the others are zero.
+    ``theta`` (optional) gives the m view angles instead of v*pi/m.
     """
     y = np.asarray(y, dtype=np.float64)
     nb = y.shape[1]
     if views is None:
         m = y.shape[0]
         views = range(m)
-    th = angles(m)
-    rows = row_branch(m)
+    th = angles(m, theta)
+    rows = row_branch(m, theta)
     acc_rows = np.zeros(n * n)   # indexed [iy, ix]
     acc_cols = np.zeros(n * n)   # indexed [ix, iy]
     t = np.broadcast_to(np.arange(n)[:, None], (n, nb))

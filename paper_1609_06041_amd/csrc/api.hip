@@ -44,14 +44,19 @@ int einval(const char* msg) {
 }
 
 // Per-view geometry in float64 (see ViewGeom).
-std::vector<ViewGeom> make_views(int n, int m, int nb) {
+// View tables.  Default angles v pi / m take the row branch for 4v <= m or
+// 4v >= 3m (the 45-degree ties decided from the index); given angles where
+// |cos| >= |sin| (1 - 1e-12), so near-diagonal views go to the row branch
+// whichever way cos and sin round.
+std::vector<ViewGeom> make_views(int n, int m, int nb, const double* angles) {
     std::vector<ViewGeom> out(m);
     const double c = 0.5 * (n - 1), cd = 0.5 * (nb - 1);
     for (int v = 0; v < m; ++v) {
-        const double th = (double)v * M_PI / (double)m;
+        const double th = angles ? angles[v] : (double)v * M_PI / (double)m;
         const double cs = std::cos(th), sn = std::sin(th);
         ViewGeom g{};
-        g.row = (4 * v <= m || 4 * v >= 3 * m) ? 1 : 0;
+        g.row = angles ? (std::fabs(cs) >= std::fabs(sn) * (1.0 - 1e-12) ? 1 : 0)
+                       : ((4 * v <= m || 4 * v >= 3 * m) ? 1 : 0);
         g.cs = cs;
         g.sn = sn;
         // row views:    s = (r_u - Y_t sin)/cos + c,  column views: s = (r_u - X_t cos)/sin + c
@@ -619,6 +624,9 @@ int ctpd_op_create(const ctpd_geometry* g, void* stream, ctpd_op** out) {
     if (g->n < 1 || g->n > 8192) return einval("n out of range [1, 8192]");
     if (g->n_views < 1 || g->n_views > 1000000) return einval("n_views out of range");
     if (g->n_bins < 1 || g->n_bins > CTPD_MAX_BINS) return einval("n_bins out of range");
+    if (g->angles)
+        for (int v = 0; v < g->n_views; ++v)
+            if (!std::isfinite(g->angles[v])) return einval("view angles must be finite");
     *out = nullptr;
     ctpd_op* op = new ctpd_op();
     op->n = g->n;
@@ -631,7 +639,7 @@ int ctpd_op_create(const ctpd_geometry* g, void* stream, ctpd_op** out) {
     auto init = [&]() -> int {
         HIP_TRY(hipGetDevice(&op->device));
         ALLOC(op->views, op->m);
-        std::vector<ViewGeom> hv = make_views(op->n, op->m, op->nb);
+        std::vector<ViewGeom> hv = make_views(op->n, op->m, op->nb, g->angles);
         HIP_TRY(hipMemcpy(op->views, hv.data(), sizeof(ViewGeom) * op->m, hipMemcpyHostToDevice));
         const std::vector<int> tasks = slab_tasks(hv, op->nb);
         ALLOC(op->fwd_tasks, tasks.size());

@@ -117,7 +117,7 @@ int einval(const char* msg);
         if (_r != CTPD_OK) return _r;                                              \
     } while (0)
 
-std::vector<ViewGeom> make_views(int n, int m, int nb);
+std::vector<ViewGeom> make_views(int n, int m, int nb, const double* angles);
 int sync(ctpd_op* op);
 int ensure_taps(ctpd_op* op, double tau, double kappa);
 // the taps at the default low-dose tau for this kappa (and the symbol bound

@@ -52,6 +52,8 @@ constexpr int kTvMaxW = kTvTile + 2 * (kTvChunk + 1);
 // too (a kept cell never reads them: the image-edge masks drop neighbours
 // outside the image, and the halo covers the window edge); a wave whose rows
 // all lie outside the valid region of a step skips that step's arithmetic.
+// Every multiply-add is an explicit fmaf, so the 512- and 1024-thread forms
+// (and every caller) round alike.
 constexpr int kTvThreads = 1024;
 
 // Lane c receives lane c - 1 (lane 0 receives 0), and lane c + 1 (lane 63
@@ -126,7 +128,7 @@ __device__ __forceinline__ void tv_prox_body(const float* __restrict__ z, const 
             const int r = rb + k, i = i0 + r;
             const float d = ((right ? a1 : 0.f) - (left ? l1 : 0.f)) + (i < n - 1 ? a2 : 0.f) -
                             (i > 0 && r > 0 ? up2 : 0.f);
-            xt[k] = fmaxf(0.f, zr[k] - lam * d);
+            xt[k] = fmaxf(0.f, fmaf(-lam, d, zr[k]));
         }
     };
 
@@ -148,8 +150,8 @@ __device__ __forceinline__ void tv_prox_body(const float* __restrict__ z, const 
                 const float xr = from_right_lane(xt[k]);
                 const float g1 = right ? xr - xt[k] : 0.f;
                 const float g2 = (i < n - 1) ? xt[k + 1] - xt[k] : 0.f;
-                const float q1 = p1[k] - step * g1, q2 = p2[k] - step * g2;
-                const float s2 = q1 * q1 + q2 * q2;
+                const float q1 = fmaf(-step, g1, p1[k]), q2 = fmaf(-step, g2, p2[k]);
+                const float s2 = fmaf(q1, q1, q2 * q2);
                 const float f = s2 > 1.f ? __builtin_amdgcn_rsqf(s2) : 1.f;
                 p1[k] = q1 * f;
                 p2[k] = q2 * f;

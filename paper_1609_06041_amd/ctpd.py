@@ -66,7 +66,18 @@ class CtpdError(RuntimeError):
 
 
 class Geometry(ctypes.Structure):
-    _fields_ = [("n", c_int32), ("n_views", c_int32), ("n_bins", c_int32)]
+    _fields_ = [("n", c_int32), ("n_views", c_int32), ("n_bins", c_int32), ("reserved", c_int32),
+                ("angles", POINTER(c_double))]
+
+
+def _geometry(n, m, nb, angles):
+    """(Geometry, keep-alive) for the C call; angles: None or m view angles in radians."""
+    if angles is None:
+        return Geometry(n, m, nb, 0, None), None
+    a = np.ascontiguousarray(np.asarray(angles, dtype=np.float64).reshape(-1))
+    if a.shape != (m,):
+        raise ValueError(f"need {m} view angles, got {a.shape}")
+    return Geometry(n, m, nb, 0, a.ctypes.data_as(POINTER(c_double))), a
 
 
 class Params(ctypes.Structure):
@@ -140,14 +151,17 @@ def _params(tau, sigma, tv_iters, tv_step, safety, norm_steps, record_cost) -> P
 class Operator:
     """A scan geometry (n x n image, n_views x n_bins sinogram) bound to a stream."""
 
-    def __init__(self, n: int, n_views: int, n_bins: int, stream: torch.cuda.Stream | None = None):
+    def __init__(self, n: int, n_views: int, n_bins: int, stream: torch.cuda.Stream | None = None,
+                 angles=None):
+        """angles: None (theta_v = v pi / n_views) or n_views view angles in radians."""
         self.n, self.m, self.nb = int(n), int(n_views), int(n_bins)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.device = self.stream.device
+        geo, keep = _geometry(self.n, self.m, self.nb, angles)
+        self.angles = None if keep is None else keep.copy()
         h = c_void_p()
         with torch.cuda.device(self.device):
-            _check(load().ctpd_op_create(byref(Geometry(self.n, self.m, self.nb)),
-                                         c_void_p(self.stream.cuda_stream), byref(h)))
+            _check(load().ctpd_op_create(byref(geo), c_void_p(self.stream.cuda_stream), byref(h)))
         self._h = h
 
     # -- lifetime --------------------------------------------------------
@@ -391,10 +405,12 @@ class Batch:
     """Independent low-dose problems of uneven sizes, solved together (Algorithm 1 on each)."""
 
     def __init__(self, geoms, stream: torch.cuda.Stream | None = None):
-        self.geoms = [(int(n), int(m), int(nb)) for n, m, nb in geoms]
+        """geoms: (n, n_views, n_bins) or (n, n_views, n_bins, angles) per problem."""
+        self.geoms = [(int(g[0]), int(g[1]), int(g[2])) for g in geoms]
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.device = self.stream.device
-        arr = (Geometry * len(self.geoms))(*[Geometry(*g) for g in self.geoms])
+        built = [_geometry(*gg, g[3] if len(g) > 3 else None) for gg, g in zip(self.geoms, geoms)]
+        arr = (Geometry * len(self.geoms))(*[b[0] for b in built])
         h = c_void_p()
         with torch.cuda.device(self.device):
             _check(load().ctpd_batch_create(arr, len(self.geoms), c_void_p(self.stream.cuda_stream), byref(h)))

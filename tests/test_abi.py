@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1609_06041_amd import ctpd
@@ -33,7 +34,7 @@ def test_library_exports_every_declared_symbol(libctpd):
 
 def test_binding_struct_layouts_match_header():
     # field order / sizes as declared (ctypes follows the C ABI layout rules)
-    assert ctypes.sizeof(ctpd.Geometry) == 12
+    assert ctypes.sizeof(ctpd.Geometry) == 4 * 4 + 8
     assert ctypes.sizeof(ctpd.Params) == 4 * 8 + 4 * 4
     assert ctypes.sizeof(ctpd.Report) == 5 * 8 + 4 * 4 + 2 * 8 + 3 * 8
     text = open(HEADER).read()
@@ -47,6 +48,17 @@ def test_op_create_rejects_bad_geometry(libctpd, n, m, nb):
     assert libctpd.ctpd_op_create(ctypes.byref(g), None, ctypes.byref(h)) == ctpd.CTPD_EINVAL
     assert not h.value
     assert b"invalid argument" in libctpd.ctpd_strerror(ctpd.CTPD_EINVAL)
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_op_create_rejects_non_finite_angles(libctpd, bad):
+    h = ctypes.c_void_p()
+    angles = np.array([0.0, 0.5, bad, 2.0])
+    g, keep = ctpd._geometry(8, 4, 12, angles)
+    assert libctpd.ctpd_op_create(ctypes.byref(g), None, ctypes.byref(h)) == ctpd.CTPD_EINVAL
+    assert not h.value
+    with pytest.raises(ValueError):
+        ctpd._geometry(8, 5, 12, angles)
 
 
 def test_null_arguments_are_rejected(libctpd):

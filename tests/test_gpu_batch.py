@@ -91,17 +91,23 @@ def test_batch_graph_replay_with_new_inputs(gpu):
 
 
 def test_batch_of_the_uneven_workload_sizes(gpu):
-    # six problems of the 64-problem uneven workload (sizes 256-512, 32-720 views), 20 iterations
+    # six problems of the 64-problem uneven workload (sizes 256-512, 32-720 views), 20 iterations,
+    # under every tile choice (the TV prox of 512- and 1024-thread workgroups, both forward
+    # projector forms) against the per-problem solver
+    from paper_1609_06041_amd import autotune
     ids = [0, 5, 11, 17, 23, 42]
     probs = [S.batch_problem(p) for p in ids]
     geoms = [(sp["n"], sp["m"], sp["nb"]) for _, sp in probs]
     data = [S.as_f32_inputs(pr) for pr, _ in probs]
     betas = [sp["beta"] for _, sp in probs]
     ref_x, _ = _singles(geoms, data, betas, 20)
+    bs, ws = [dev(b) for b, _ in data], [dev(w) for _, w in data]
     with ctpd.Batch(geoms) as bt:
-        xs, _ = bt.lowdose_solve([dev(b) for b, _ in data], [dev(w) for _, w in data], betas, 20)
-        for x, r in zip(xs, ref_x):
-            np.testing.assert_array_equal(host(x), r)
+        for cand in autotune.CANDIDATES:
+            bt.set_tiles(**cand)
+            xs, _ = bt.lowdose_solve(bs, ws, betas, 20)
+            for x, r in zip(xs, ref_x):
+                np.testing.assert_array_equal(host(x), r, err_msg=str(cand))
 
 
 def test_batch_rejects_bad_arguments(gpu):

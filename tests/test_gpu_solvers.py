@@ -213,3 +213,20 @@ def test_fused_filter_inputs_equal_the_prologue_path(gpu, algo):
             x1, i1 = op.fewview_solve(dev(b), 12, record_cost=True)
         assert i0["sigma"] == i1["sigma"] and i0["tau"] == i1["tau"]
         np.testing.assert_array_equal(host(x0), host(x1))
+
+
+def test_lowdose_with_given_angles_matches_oracle(gpu):
+    # limited-angle scan (135 degrees, irregular spacing): default step sizes
+    # from the GPU's Lanczos chains on that geometry, then 10 iterations
+    n, m, nb = 48, 30, 70
+    th = np.sort(np.random.default_rng(31).uniform(0.1, 0.1 + 0.75 * np.pi, m))
+    b, w = lowdose_inputs(n, m, nb, seed=31)
+    st = OA.steps_lowdose(w, n, theta=th)
+    ref, _ = OA.lowdose_solve(b, w, 0.02, n, 10, tau=st.tau, sigma=st.sigma, theta=th)
+    with ctpd.Operator(n, m, nb, angles=th) as op:
+        x, info = op.lowdose_solve(dev(b), dev(w), 0.02, 10)
+        x = host(x)
+    assert info["tau"] == pytest.approx(st.tau, rel=1e-12)
+    assert info["lambda_a"] == pytest.approx(st.lambda_a, rel=1e-6)
+    assert info["sigma"] == pytest.approx(st.sigma, rel=1e-6)
+    assert rel(x, ref.x) <= 1e-4, rel(x, ref.x)
