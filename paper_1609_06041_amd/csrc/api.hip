@@ -310,17 +310,21 @@ int tv_prox(ctpd_op* op, const float* z, float lam, int n_iter, float step, floa
 // Algorithm 1's iterations (Eqs. 18-20) from zero with the handle's taps as D
 // and the given steps, queued on the handle's stream; *p_final receives the
 // buffer holding the final dual field of the TV prox.
-int lowdose_loop(ctpd_op* op, const float* b, const float* w, double beta, int iters, const Knobs& k, double tau,
-                 double sigma, float** p_final) {
-    int r = CTPD_OK;
+// x^0 = 0, mu^0 = 0 (and the mu^{-1} of the first extrapolation), p = 0
+int lowdose_zero(ctpd_op* op) {
     const size_t I = op->I, J = op->J;
     hipStream_t s = op->stream;
+    HIP_TRY(launch_zero4_f32(op->x, J, op->p[0], 2 * J, op->mu[0], I, op->mu[1], I, s));
+    return CTPD_OK;
+}
+
+int lowdose_loop(ctpd_op* op, const float* b, const float* w, double beta, int iters, const Knobs& k, double tau,
+                 double sigma, float** p_final, bool zeroed = false) {
+    int r = CTPD_OK;
+    const size_t I = op->I;
+    hipStream_t s = op->stream;
     if (k.record && (r = ensure_cost(op, iters))) return r;
-    // x^0 = 0, mu^0 = 0, p = 0
-    HIP_TRY(launch_fill_f32(op->x, 0.f, J, s));
-    HIP_TRY(launch_fill_f32(op->p[0], 0.f, 2 * J, s));
-    HIP_TRY(launch_fill_f32(op->mu[0], 0.f, I, s));
-    HIP_TRY(launch_fill_f32(op->mu[1], 0.f, I, s));
+    if (!zeroed && (r = lowdose_zero(op))) return r;
     float *mu = op->mu[0], *mup = op->mu[1], *mun = op->mu[2];
     float* pcur = op->p[0];
     const float fs = (float)sigma, ft = (float)tau, lam = (float)(tau * beta);
@@ -778,6 +782,8 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
     const auto t0 = std::chrono::steady_clock::now();
     LowdoseSetup S;
     if ((r = lowdose_setup_begin(op, b, w, k, &S))) return r;
+    // the iterates' zero start runs on op->stream while the lambda_h chains run on op->aux
+    if ((r = lowdose_zero(op))) return r;
     if (S.norms) {
         // the lambda_A chain (first solve on the handle) runs on op->stream while the
         // per-view lambda_h chains run on op->aux
@@ -806,7 +812,7 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
     const double setup_ms = ms_since(t0);
     const auto t1 = std::chrono::steady_clock::now();
     float* pcur = nullptr;
-    if ((r = lowdose_loop(op, b, w, beta, iters, k, tau, sigma, &pcur))) return r;
+    if ((r = lowdose_loop(op, b, w, beta, iters, k, tau, sigma, &pcur, true))) return r;
     if ((r = finish(op, iters, true, beta, pcur, rep, x_out, k.record != 0))) return r;
     if (rep) {
         rep->tau = tau;

@@ -155,19 +155,6 @@ __device__ __forceinline__ void filter_body(const FilterArgs& a, const float* __
     float* stile = smem + tlen;         // [FBM][FSTRIDE]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n0 = bxi * FBN, v0 = byi * FBM;
-    for (int i0 = 0; i0 < tlen; i0 += 256 * 8) {   // 8 loads in flight per thread
-        float tv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int k = i0 + tid + 256 * u - FBK;
-            tv[u] = taps[(k >= 0 && k < ntap) ? k : 0];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = i0 + tid + 256 * u, k = i - FBK;
-            if (i < tlen) htap[i] = (k >= 0 && k < ntap) ? tv[u] : 0.0f;
-        }
-    }
     const int wr = (wave * FACC / FTPR) * 16, wc = (wave * FACC % FTPR) * 16;
     const int li = lane & 15, lk = lane >> 4;
     constexpr int NIN = FilterIn<MODE>::N;
@@ -189,7 +176,21 @@ __device__ __forceinline__ void filter_body(const FilterArgs& a, const float* __
     v4f acc[FACC];
 #pragma unroll
     for (int q = 0; q < FACC; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
+    // the first stage's input is in flight while the taps are staged
     fetch(0);
+    for (int i0 = 0; i0 < tlen; i0 += 256 * 8) {   // 8 loads in flight per thread
+        float tv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = i0 + tid + 256 * u - FBK;
+            tv[u] = taps[(k >= 0 && k < ntap) ? k : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + tid + 256 * u, k = i - FBK;
+            if (i < tlen) htap[i] = (k >= 0 && k < ntap) ? tv[u] : 0.0f;
+        }
+    }
     for (int k0 = 0; k0 < nb; k0 += FBK) {
         __syncthreads();
 #pragma unroll

@@ -318,5 +318,8 @@ hipError_t launch_identity_taps(double* taps64, float* taps32, int nb, hipStream
 hipError_t launch_rsqrt_f64(double* out, const float* w, size_t len, hipStream_t s);
 hipError_t launch_copy_f32(float* dst, const float* src, size_t len, hipStream_t s);
 hipError_t launch_fill_f32(float* dst, float v, size_t len, hipStream_t s);
+// a[0..na) = b[0..nb) = c[0..nc) = d[0..nd) = 0 in one launch
+hipError_t launch_zero4_f32(float* a, size_t na, float* b, size_t nb, float* c, size_t nc, float* d, size_t nd,
+                            hipStream_t s);
 
 }  // namespace ctpd

@@ -874,6 +874,41 @@ hipError_t launch_fill_f32(float* dst, float v, size_t len, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Zero four buffers in one launch.  Buffer q owns the index span span[q]
+// (its length rounded up to a multiple of 4, spans laid end to end); a thread
+// clears 4 consecutive elements of one buffer, never past its length n[q].
+struct Zero4 {
+    float* p[4];
+    size_t n[4], span[4];
+};
+
+__global__ __launch_bounds__(256) void zero4_kernel(Zero4 z) {
+    size_t i = ((size_t)blockIdx.x * 256 + threadIdx.x) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (i < z.span[q]) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (i + e < z.n[q]) z.p[q][i + e] = 0.f;
+            return;
+        }
+        i -= z.span[q];
+    }
+}
+
+hipError_t launch_zero4_f32(float* a, size_t na, float* b, size_t nb, float* c, size_t nc, float* d, size_t nd,
+                            hipStream_t s) {
+    Zero4 z{{a, b, c, d}, {na, nb, nc, nd}, {}};
+    size_t total = 0;
+    for (int q = 0; q < 4; ++q) {
+        z.span[q] = (z.n[q] + 3) / 4 * 4;
+        total += z.span[q];
+    }
+    if (total == 0) return hipSuccess;
+    zero4_kernel<<<(unsigned)((total / 4 + 255) / 256), 256, 0, s>>>(z);
+    return hipGetLastError();
+}
+
 // Recorded elementwise / reduction steps (one table entry per problem).
 // Elementwise kinds: 256 elements per workgroup.  SK_DOT: the problem's
 // reduce_blocks(len) workgroups stride over len, as launch_dot_partials.
