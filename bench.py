@@ -553,7 +553,7 @@ def main() -> int:
         "op_ms": {"A": t_a, "AT": t_at, "D": t_d, "tv_step": t_tv10 / 10.0},
         "filter_mfma_tflops": 2.0 * m * nb * nb / (t_d * 1e-3) / 1e12,
         "tv_step_gbs": 20.0 * n * n / (t_tv10 / 10.0 * 1e-3) / 1e9,
-        "roofline": {"kernel": "forward_slab_kernel (A, one launch per ctpd_project)", "bound": "alu",
+        "roofline": {"kernel": "forward_slab_kernel (A; timed per ctpd_project call, which also pads the image planes)", "bound": "alu",
                      "achieved": a_tflops, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": a_tflops / PEAK_FP32_VECTOR_TFLOPS, "traffic": read_traffic("forward"),
                      "work_per_launch": f"{ray_steps:.4g} in-image ray steps x {A_FLOP_PER_STEP:.0f} FLOP",
