@@ -265,8 +265,9 @@ int filter(ctpd_op* op, int mode, const float* in0, const float* in1, const floa
 
 // y = A x - rb - rw .* rm (rw null: A x - rb): the dual update's filter input
 // written by the projector itself
-int project_resid(ctpd_op* op, const float* x, const float* rb, const float* rw, const float* rm, float* y) {
-    HIP_TRY(launch_pad_planes<float>(x, op->xp, op->xTp, op->n, op->stream));
+int project_resid(ctpd_op* op, const float* x, const float* rb, const float* rw, const float* rm, float* y,
+                  bool padded) {
+    if (!padded) HIP_TRY(launch_pad_planes<float>(x, op->xp, op->xTp, op->n, op->stream));
     HIP_TRY(launch_forward_slab(op->xp, op->xTp, y, op->views, op->fwd_tasks, op->fwd_groups, op->n, op->nb, rb, rw,
                                 rm, op->stream));
     return CTPD_OK;
@@ -296,10 +297,11 @@ std::vector<int> slab_tasks(const std::vector<ViewGeom>& hv, int nb) {
 // which is either pin or scratch, both used as ping-pong buffers), then
 // x = max(0, z - lam div p).  lam == 0 gives x = max(0, z) and leaves p alone.
 int tv_prox(ctpd_op* op, const float* z, float lam, int n_iter, float step, float* pin, float* scratch, float* x,
-            float** pout) {
+            float** pout, bool planes) {
     float* pf = pin;
     if (lam > 0.0f)
-        HIP_TRY(launch_tv_prox(z, pin, scratch, x, op->n, lam, step, n_iter, &pf, op->stream));
+        HIP_TRY(launch_tv_prox(z, pin, scratch, x, op->n, lam, step, n_iter, &pf, op->stream,
+                               planes ? op->xp : nullptr, planes ? op->xTp : nullptr));
     else
         HIP_TRY(launch_tv_finalize(z, pin, x, op->n, 0.0f, op->stream));
     if (pout) *pout = pf;
@@ -347,18 +349,20 @@ int lowdose_loop(ctpd_op* op, const float* b, const float* w, double beta, int i
         HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, op->x, 1.f, -ft, op->z, op->views, op->n,
                                       op->m, op->nb, s));
         float* pnew = nullptr;
+        // the prox also writes the projector's planes of x (not the beta = 0 clamp)
+        const bool padded = lam > 0.f;
         if ((r = tv_prox(op, op->z, lam, k.tv_iters, tvstep, pcur, pcur == op->p[0] ? op->p[1] : op->p[0], op->x,
-                         &pnew)))
+                         &pnew, true)))
             return r;
         pcur = pnew;
         // Step 3: mu^{k+1} = mu^k + sigma D (A x^{k+1} - b - W^-1 mu^k)
         if (fused) {
-            if ((r = project_resid(op, op->x, b, op->winv, mu, op->q))) return r;
+            if ((r = project_resid(op, op->x, b, op->winv, mu, op->q, padded))) return r;
             if ((r = filter(op, FILT_PLAIN, op->q, nullptr, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun,
                             op->winv, op->sx)))
                 return r;
         } else {
-            if ((r = project(op, op->x, op->q))) return r;
+            if ((r = project_resid(op, op->x, nullptr, nullptr, nullptr, op->q, padded))) return r;
             if ((r = filter(op, FILT_DUAL_LD, op->q, b, op->winv, mu, mu, 1.f, nullptr, 0.f, fs, mun))) return r;
         }
         if (k.record) {
@@ -651,6 +655,9 @@ int ctpd_op_create(const ctpd_geometry* g, void* stream, ctpd_op** out) {
         op->fwd_groups = (int)(tasks.size() / forward_slab_tasks_per_group());
         ALLOC(op->xp, op->Jp);
         ALLOC(op->xTp, op->Jp);
+        // the planes' pad columns stay zero for good: only interiors are written after this
+        HIP_TRY(hipMemset(op->xp, 0, sizeof(float) * op->Jp));
+        HIP_TRY(hipMemset(op->xTp, 0, sizeof(float) * op->Jp));
         ALLOC(op->x, op->J);
         ALLOC(op->z, op->J);
         for (auto& p : op->p) ALLOC(p, 2 * op->J);
@@ -968,18 +975,20 @@ int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
                                           op->nb, s));
         }
         float* pnew = nullptr;
+        // the prox also writes the projector's planes of x
+        const bool padded = lam > 0.f;
         if ((r = tv_prox(op, op->z, lam, k.tv_iters, tvstep, pcur, pcur == op->p[0] ? op->p[1] : op->p[0], op->x,
-                         &pnew)))
+                         &pnew, true)))
             return r;
         pcur = pnew;
         // Step 3: mu^{k+1} = mu^k + sigma D (A x^{k+1} - b); without the cost
         // monitor the projector writes the residual itself
         if (!k.record) {
-            if ((r = project_resid(op, op->x, b, nullptr, nullptr, op->q))) return r;
+            if ((r = project_resid(op, op->x, b, nullptr, nullptr, op->q, padded))) return r;
             if ((r = filter(op, FILT_PLAIN, op->q, nullptr, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun)))
                 return r;
         } else {
-            if ((r = project(op, op->x, op->q))) return r;
+            if ((r = project_resid(op, op->x, nullptr, nullptr, nullptr, op->q, padded))) return r;
             if ((r = filter(op, FILT_DUAL_FV, op->q, b, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun)))
                 return r;
         }

@@ -161,6 +161,8 @@ hipError_t launch_step_tv(int kind, const UStep* steps, const BlockRef* map, int
 hipError_t launch_step_vec(int kind, const UStep* steps, const BlockRef* map, int nblocks, hipStream_t s);
 
 // ---- projector.hip -------------------------------------------------------
+// pad pixels on each side of every row of the forward projector's planes
+constexpr int kPlanePad = 3;
 // xp / xTp: [n][n+6] row-major copies of x and its transpose with three zero
 // pixels on each side of every row
 template <typename T>
@@ -230,9 +232,11 @@ hipError_t launch_norm_filter_batched(const NormItem* it, const BlockRef* map, i
 // ---- tv.hip --------------------------------------------------------------
 // The TV prox: n_iter dual steps on p starting from p_a (warm start), then
 // x = max(0, z - lam div p).  lam > 0.  p_a and p_b are both overwritten as
-// ping-pong buffers; *p_final receives the one holding the final p.
+// ping-pong buffers; *p_final receives the one holding the final p.  With xp
+// and xTp the padded planes of x that the forward projector reads (see
+// launch_pad_planes; their pad columns must already be zero) are written too.
 hipError_t launch_tv_prox(const float* z, float* p_a, float* p_b, float* x, int n, float lam, float step,
-                          int n_iter, float** p_final, hipStream_t s);
+                          int n_iter, float** p_final, hipStream_t s, float* xp = nullptr, float* xTp = nullptr);
 // p <- projection of (p + s grad xb) onto the unit ball, pointwise (the dual
 // step of Chambolle-Pock on the TV term).
 hipError_t launch_grad_ball(const float* xb, float* p, int n, float s, hipStream_t st);

@@ -203,9 +203,12 @@ int filter(ctpd_op* op, int mode, const float* in0, const float* in1, const floa
            const float* E0, float e0, const float* E1, float e1, float c, float* out, const float* Sw = nullptr,
            float* Sout = nullptr);
 int project(ctpd_op* op, const float* x, float* y);
-int project_resid(ctpd_op* op, const float* x, const float* rb, const float* rw, const float* rm, float* y);
+// y = A x - rb - rw .* rm (rb null: y = A x); padded: the planes of x are current
+// (the TV prox wrote them), so they are not padded again
+int project_resid(ctpd_op* op, const float* x, const float* rb, const float* rw, const float* rm, float* y,
+                  bool padded = false);
 int tv_prox(ctpd_op* op, const float* z, float lam, int n_iter, float step, float* pin, float* scratch, float* x,
-            float** pout);
+            float** pout, bool planes = false);
 
 struct Knobs {
     double tau, sigma, tv_step, rho;

@@ -19,7 +19,7 @@ namespace ctpd {
 // zero pixels on each side of every row, so taps outside the image need no
 // test:  xp[t][k + FP_PAD] = x[t][k],  xTp[t][k + FP_PAD] = x[k][t],
 // pitch n + 2 FP_PAD.
-constexpr int FP_PAD = 3;
+constexpr int FP_PAD = kPlanePad;
 
 // Kernel bodies take their block coordinates as arguments so that the single
 // launches and the batched launches (one flattened grid over many problems)

@@ -73,7 +73,8 @@ template <int THREADS>
 __device__ __forceinline__ void tv_prox_body(const float* __restrict__ z, const float* __restrict__ p_in,
                                              float* __restrict__ p_out, float* __restrict__ x, int n, float lam,
                                              float step, int steps, int bxi, int byi,
-                                             float* __restrict__ ps_store = nullptr) {
+                                             float* __restrict__ ps_store = nullptr, float* __restrict__ xp = nullptr,
+                                             float* __restrict__ xTp = nullptr) {
     constexpr int NW = THREADS / 64;
     constexpr int R = (kTvMaxW + NW - 1) / NW;
     // [parity][first-row p1, first-row p2, last-row p2][slot][lane]: wave w
@@ -173,6 +174,12 @@ __device__ __forceinline__ void tv_prox_body(const float* __restrict__ z, const 
     const int par = (steps + 1) & 1;
     if (active) ex[par][2][w + 1][c] = p2[R - 1];
     __syncthreads();
+    // with xp / xTp the forward projector's padded planes of x are written too
+    // (pitch n + 6, three pixels of pad on each side, pads left alone): xp
+    // straight, xTp through a tile in LDS so that its rows are stored whole
+    __shared__ float tileT[kTvTile][kTvTile + 1];
+    const bool planes = x && xp;
+    const int P = n + 2 * kPlanePad;
     if (active && rb + R > H && rb < H + kTvTile) {
         float xt[R + 1];
         if (x) xtilde_rows(0.f, 0.f, ex[par][2][w][c], xt);
@@ -184,7 +191,20 @@ __device__ __forceinline__ void tv_prox_body(const float* __restrict__ z, const 
                 p_out[g] = p1[k];
                 p_out[nn + g] = p2[k];
                 if (x) x[g] = xt[k];
+                if (planes) {
+                    xp[(size_t)i * P + j + kPlanePad] = xt[k];
+                    tileT[c - H][r - H] = xt[k];
+                }
             }
+        }
+    }
+    if (planes) {
+        __syncthreads();
+        // xTp row j0 + a holds column j0 + a of x: tile element (a, b) is x[i0 + b][j0 + a]
+        for (int e = threadIdx.x; e < kTvTile * kTvTile; e += THREADS) {
+            const int a = e / kTvTile, b = e % kTvTile;
+            const int jj = bxi * kTvTile + a, ii = byi * kTvTile + b;
+            if (jj < n && ii < n) xTp[(size_t)jj * P + ii + kPlanePad] = tileT[a][b];
         }
     }
 }
@@ -202,8 +222,9 @@ __global__ __launch_bounds__(256) void tv_finalize_kernel(const float* z, const 
 __global__ __launch_bounds__(kTvThreads) void tv_prox_kernel(const float* __restrict__ z,
                                                              const float* __restrict__ p_in,
                                                              float* __restrict__ p_out, float* __restrict__ x, int n,
-                                                             float lam, float step, int steps) {
-    tv_prox_body<kTvThreads>(z, p_in, p_out, x, n, lam, step, steps, blockIdx.x, blockIdx.y);
+                                                             float lam, float step, int steps,
+                                                             float* __restrict__ xp, float* __restrict__ xTp) {
+    tv_prox_body<kTvThreads>(z, p_in, p_out, x, n, lam, step, steps, blockIdx.x, blockIdx.y, nullptr, xp, xTp);
 }
 
 // Batched TV prox chunk: p[src] -> p[1 - src] for every problem, x written on
@@ -459,7 +480,7 @@ hipError_t launch_step_tv(int kind, const UStep* steps, const BlockRef* map, int
 int tv_bwd_blocks(int n) { return ((n + 63) / 64) * ((n + 3) / 4); }
 
 hipError_t launch_tv_prox(const float* z, float* p_a, float* p_b, float* x, int n, float lam, float step,
-                          int n_iter, float** p_final, hipStream_t s) {
+                          int n_iter, float** p_final, hipStream_t s, float* xp, float* xTp) {
     dim3 grid((n + kTvTile - 1) / kTvTile, (n + kTvTile - 1) / kTvTile);
     float* src = p_a;
     float* dst = p_b;
@@ -467,7 +488,7 @@ hipError_t launch_tv_prox(const float* z, float* p_a, float* p_b, float* x, int 
     do {
         const int k = left < kTvChunk ? left : kTvChunk;
         left -= k;
-        tv_prox_kernel<<<grid, kTvThreads, 0, s>>>(z, src, dst, left == 0 ? x : nullptr, n, lam, step, k);
+        tv_prox_kernel<<<grid, kTvThreads, 0, s>>>(z, src, dst, left == 0 ? x : nullptr, n, lam, step, k, xp, xTp);
         std::swap(src, dst);
     } while (left > 0);
     *p_final = src;
