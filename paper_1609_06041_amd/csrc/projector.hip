@@ -366,27 +366,40 @@ hipError_t launch_forward(const T* xp, const T* xTp, T* y, const ViewGeom* views
 // or |sin| (column views) <= 1, so only bins floor(t), floor(t)+1 carry
 // weight.  out = alpha * xin + beta * A^T (c1 y1 + c2 y2).
 //
-// Workgroup: a 32 x 32 pixel tile, AT_G view streams of 256 lanes; stream h
-// takes the view chunks h, h+AT_G, ... and its lane (tx, ty) owns pixels
-// (x0 + tx, y0 + ty + 8j), j = 0..3.  For each chunk of 16 views the stream
-// stages, per view, the 48 bins starting one below the tile's lowest bin
-// coordinate (the tile spans at most 31 sqrt(2) + 2 bins), zero outside the
-// detector, so the inner loop reads LDS without bounds tests.  The next
-// chunk's bins are loaded into registers while the current chunk is used.
-// The streams are summed through LDS at the end in a fixed order
-// (deterministic).  Per view the stream also tabulates the bin positions of
-// the tile's first row and the row increments, so a lane's positions take
-// only 64-bit adds.
+// Workgroup: a 32 x 32 pixel tile, AT_G view streams of AT_SL lanes; stream
+// h takes the view chunks h, h+AT_G, ... and its lane (tx, ty) owns the
+// pixels (x0 + tx, y0 + ty + AT_RS j), j = 0..AT_PJ-1.  For each chunk of
+// views the stream stages, per view, the 48 bins starting one below the
+// tile's lowest bin coordinate (the tile spans at most 31 sqrt(2) + 2 bins),
+// zero outside the detector, so the inner loop reads LDS without bounds
+// tests.  The next chunk's bins are loaded into registers while the current
+// chunk is used.  The streams are summed through LDS at the end in a fixed
+// order (deterministic).  Per view the stream also tabulates the bin
+// positions of the tile's first row and the row increments, so a lane's
+// positions take only 64-bit adds.  The inner loop is bound by LDS reads:
+// 8 bytes of taps per (pixel, view) plus the view's 32 bytes of tables per
+// lane, which eight pixels a lane share.
 constexpr int AT_T = 32;
-constexpr int AT_VC = 16;
-constexpr int AT_G = 4;   // view streams per tile (16 waves: a 512^2 image has one tile per CU)
-constexpr int AT_THREADS = 256 * AT_G;
+constexpr int AT_G = 8;                   // view streams per tile (16 waves: a 512^2 image has one tile per CU)
+constexpr int AT_SL = 128;                // lanes per stream
+constexpr int AT_THREADS = AT_SL * AT_G;
+constexpr int AT_PJ = 8;                  // pixels per lane, one column
+constexpr int AT_RS = AT_T / AT_PJ;       // lane rows per stream
 constexpr int AT_W = 48;
-constexpr int AT_PER = AT_VC * AT_W / 256;
+static_assert(AT_SL == AT_T * AT_RS, "a stream covers the tile once");
+
+// views per chunk: the LDS tables stay within 64 KB
+template <typename T>
+constexpr int at_vc() { return sizeof(T) == 4 ? 16 : 8; }
 
 struct TileBox {
     double xlo, xhi, ylo, yhi, cd;
 };
+
+// A hat weight over len: at most 1 by construction, so clamping to [0, 1]
+// is max(0, w); in float the clamp is the fma's output modifier.
+__device__ __forceinline__ float hat_clamp(float w) { return __builtin_amdgcn_fmed3f(w, 0.f, 1.f); }
+__device__ __forceinline__ double hat_clamp(double w) { return fmax(0.0, w); }
 
 // First staged bin of view g for the tile (one below floor of the lowest t).
 __device__ __forceinline__ int window_base(const ViewGeom& g, const TileBox& b) {
@@ -399,58 +412,74 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
                                              const T* __restrict__ xin, T alpha, T beta, T* __restrict__ out,
                                              const ViewGeom* __restrict__ views, int n, int m, int nb, int bxi,
                                              int byi) {
-    __shared__ T win[AT_G][AT_VC][AT_W];
-    // per view of the staged chunk, in 32.32 fixed point relative to the
-    // window: colt[i][tx] = t of pixel (x0 + tx, y0), rowt[i][r] = r * (the
-    // per-row increment), r = 0..8 -- so a lane's four positions are
-    // colt[tx] + rowt[ty] + j rowt[8] (adds only)
-    __shared__ long long colt[AT_G][AT_VC][AT_T];
-    __shared__ long long rowt[AT_G][AT_VC][9];
-    __shared__ T plen[AT_G][AT_VC], plen2[AT_G][AT_VC];
+    constexpr int VC = at_vc<T>();
+    constexpr int PER = VC * AT_W / AT_SL;   // staged bins per lane and chunk
+    static_assert(PER * AT_SL == VC * AT_W && VC % 2 == 0, "chunk shape");
+    struct Lds {
+        // the staged bins, each already multiplied by its view's len (first,
+        // at LDS offset zero, so the per-view bases fold into the read
+        // instructions' offsets)
+        T win[AT_G][VC][AT_W];
+        // per view of the staged chunk, in 32.32 fixed point relative to the
+        // window: colt[i][tx] = t of pixel (x0 + tx, y0), rowt[i][r] = r * (the
+        // per-row increment), r = 0..AT_RS -- so a lane's positions are
+        // colt[tx] + rowt[ty] + j rowt[AT_RS] (adds only)
+        long long colt[AT_G][VC][AT_T];
+        long long rowt[AT_G][VC][AT_RS + 1];
+        // the hat weights over len: 1 - f prate (left bin) and poff + f prate
+        // (right bin), f the 32-bit fraction, prate = len2 / (len 2^32), poff = 1 - len2 / len
+        T prate[AT_G][VC], poff[AT_G][VC];
+    };
+    __shared__ Lds sh;
+    auto& win = sh.win;
+    auto& colt = sh.colt;
+    auto& rowt = sh.rowt;
+    auto& prate = sh.prate;
+    auto& poff = sh.poff;
     // h is the same on every lane of a wave: keep it (and the LDS bases built
     // from it) in scalar registers
-    const int tid = threadIdx.x, h = __builtin_amdgcn_readfirstlane(tid >> 8), l = tid & 255;
-    const int tx = l & 31, ty = l >> 5;
+    const int tid = threadIdx.x, h = __builtin_amdgcn_readfirstlane(tid / AT_SL), l = tid % AT_SL;
+    const int tx = l % AT_T, ty = l / AT_T;
     const int x0 = bxi * AT_T, y0 = byi * AT_T;
     const double c = 0.5 * (double)(n - 1);
     const TileBox box{x0 - c, x0 + (AT_T - 1) - c, y0 - c, y0 + (AT_T - 1) - c, 0.5 * (double)(nb - 1)};
-    const int nchunk = (m + AT_VC - 1) / AT_VC;
+    const int nchunk = (m + VC - 1) / VC;
     const int nsteps = (nchunk + AT_G - 1) / AT_G;
     const double two32 = 4294967296.0;
 
-    T stg[AT_PER];
+    T stg[PER];
     auto fetch = [&](int ch) {
 #pragma unroll
-        for (int r = 0; r < AT_PER; ++r) {
-            const int e = l + 256 * r;
+        for (int r = 0; r < PER; ++r) {
+            const int e = l + AT_SL * r;
             const int i = e / AT_W, k = e - i * AT_W;
-            const int v = ch * AT_VC + i;
+            const int v = ch * VC + i;
             T val = T(0);
             if (ch < nchunk && v < m) {
                 const int u = window_base(views[v], box) + k;
                 if (u >= 0 && u < nb) {
                     const size_t idx = (size_t)v * nb + u;
-                    val = TWO ? c1 * y1[idx] + c2 * y2[idx] : y1[idx];
+                    val = (TWO ? c1 * y1[idx] + c2 * y2[idx] : y1[idx]) * (T)views[v].len;
                 }
             }
             stg[r] = val;
         }
     };
     // The tables of the chunk's views (the weights absorb the 2^-32 of the
-    // fraction through plen2).  Past the last view: position 1.5 in a zero
-    // window with zero weights.
+    // fraction through prate).  Past the last view: position 1.5 in a zero
+    // window.
     auto commit = [&](int ch) {
 #pragma unroll
-        for (int r = 0; r < AT_PER; ++r) {
-            const int e = l + 256 * r;
+        for (int r = 0; r < PER; ++r) {
+            const int e = l + AT_SL * r;
             const int i = e / AT_W;
             win[h][i][e - i * AT_W] = stg[r];
         }
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int e = l + 256 * q;
-            const int i = e >> 5, cx = e & 31;
-            const int v = ch * AT_VC + i;
+        for (int q = 0; q < VC * AT_T / AT_SL; ++q) {
+            const int e = l + AT_SL * q;
+            const int i = e / AT_T, cx = e % AT_T;
+            const int v = ch * VC + i;
             long long a = 3ll << 31;
             if (ch < nchunk && v < m) {
                 const ViewGeom g = views[v];
@@ -459,20 +488,25 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
             }
             colt[h][i][cx] = a;
         }
-        if (l < AT_VC * 9) {
-            const int i = l / 9, r = l - 9 * i;
-            const int v = ch * AT_VC + i;
-            rowt[h][i][r] = (ch < nchunk && v < m) ? (long long)r * llrint(views[v].sn * two32) : 0ll;
-        } else if (l < AT_VC * 10) {
-            const int i = l - AT_VC * 9;
-            const int v = ch * AT_VC + i;
-            const bool live = ch < nchunk && v < m;
-            plen[h][i] = live ? (T)views[v].len : T(0);
-            plen2[h][i] = live ? (T)(views[v].len2 / two32) : T(0);
+        for (int e = l; e < VC * (AT_RS + 2); e += AT_SL) {
+            if (e < VC * (AT_RS + 1)) {
+                const int i = e / (AT_RS + 1), r = e - (AT_RS + 1) * i;
+                const int v = ch * VC + i;
+                rowt[h][i][r] = (ch < nchunk && v < m) ? (long long)r * llrint(views[v].sn * two32) : 0ll;
+                continue;
+            }
+            const int i = e - VC * (AT_RS + 1);
+            const int v = ch * VC + i;
+            const bool live = ch < nchunk && v < m && views[v].len > 0.0;
+            const double q = live ? views[v].len2 / views[v].len : 0.0;
+            prate[h][i] = (T)(q / two32);
+            poff[h][i] = live ? (T)(1.0 - q) : T(0);
         }
     };
 
-    T acc[4] = {T(0), T(0), T(0), T(0)};
+    T acc[AT_PJ];
+#pragma unroll
+    for (int j = 0; j < AT_PJ; ++j) acc[j] = T(0);
     fetch(h);
     commit(h);
     __syncthreads();
@@ -480,65 +514,78 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
         const int ch = h + AT_G * st;
         fetch(ch + AT_G);
         if (ch < nchunk) {
-            // two views x four pixels per pass: all eight LDS reads are independent
+            // two views x AT_PJ pixels per pass: all 2 AT_PJ tap-pair reads are independent
 #pragma unroll 1
-            for (int i = 0; i < AT_VC; i += 2) {
-                unsigned k[2][4];
-                T f[2][4], a[2][4], b[2][4], len[2], len2[2];
+            for (int i = 0; i < VC; i += 2) {
+                unsigned k[2][AT_PJ];
+                T f[2][AT_PJ], a[2][AT_PJ], b[2][AT_PJ], rate[2], off[2];
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
                     unsigned long long tj = (unsigned long long)(colt[h][i + q][tx] + rowt[h][i + q][ty]);
-                    const unsigned long long d8 = (unsigned long long)rowt[h][i + q][8];
-                    len[q] = plen[h][i + q];
-                    len2[q] = plen2[h][i + q];
+                    const unsigned long long dr = (unsigned long long)rowt[h][i + q][AT_RS];
+                    rate[q] = prate[h][i + q];
+                    off[q] = poff[h][i + q];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
+                    for (int j = 0; j < AT_PJ; ++j) {
                         // t >= 1 - rounding > 0, so the high word is floor(t)
                         k[q][j] = (unsigned)(tj >> 32);
                         f[q][j] = (T)(unsigned)tj;
-                        tj += d8;
+                        tj += dr;
                     }
                 }
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
+                    for (int j = 0; j < AT_PJ; ++j) {
                         a[q][j] = win[h][i + q][k[q][j]];
                         b[q][j] = win[h][i + q][k[q][j] + 1];
                     }
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const T cc = len[q] - len2[q] * (T)two32;
+                for (int q = 0; q < 2; ++q)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const T w0 = fmax(T(0), len[q] - f[q][j] * len2[q]);
-                        const T w1 = fmax(T(0), cc + f[q][j] * len2[q]);
+                    for (int j = 0; j < AT_PJ; ++j) {
+                        const T w0 = hat_clamp(fma(-f[q][j], rate[q], T(1)));
+                        const T w1 = hat_clamp(fma(f[q][j], rate[q], off[q]));
                         acc[j] = fma(w0, a[q][j], fma(w1, b[q][j], acc[j]));
                     }
-                }
             }
         }
         __syncthreads();
         commit(ch + AT_G);
         __syncthreads();
     }
-    // sum the streams through LDS (reusing the staging buffer), in a fixed order
-    T* red = &win[0][0][0];
-    static_assert((AT_G - 1) * AT_T * AT_T <= AT_G * AT_VC * AT_W, "reduction buffer");
-    if (h > 0) {
+    // sum the streams through LDS (reusing the staging and position tables),
+    // in a fixed order: stream h < 4 adds stream h + 4, then stream 0 adds
+    // streams 1, 2, 3
+    T* red = reinterpret_cast<T*>(&sh);
+    constexpr int TP = AT_T * AT_T;
+    static_assert(4 * TP * sizeof(T) <= sizeof(sh.win) + sizeof(sh.colt), "reduction buffer");
+    static_assert(AT_G == 8, "two-stage stream sum");
+    const int pix0 = ty * AT_T + tx, pstep = AT_RS * AT_T;
+    if (h >= 4) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) red[(h - 1) * AT_T * AT_T + (ty + 8 * j) * AT_T + tx] = acc[j];
+        for (int j = 0; j < AT_PJ; ++j) red[(h - 4) * TP + pix0 + pstep * j] = acc[j];
+    }
+    __syncthreads();
+    if (h < 4) {
+#pragma unroll
+        for (int j = 0; j < AT_PJ; ++j) acc[j] += red[h * TP + pix0 + pstep * j];
+    }
+    __syncthreads();
+    if (h >= 1 && h < 4) {
+#pragma unroll
+        for (int j = 0; j < AT_PJ; ++j) red[(h - 1) * TP + pix0 + pstep * j] = acc[j];
     }
     __syncthreads();
     if (h == 0) {
         const int ix = x0 + tx;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int iy = y0 + ty + 8 * j;
+        for (int j = 0; j < AT_PJ; ++j) {
+            const int iy = y0 + ty + AT_RS * j;
             if (ix < n && iy < n) {
                 T sum = acc[j];
 #pragma unroll
-                for (int g = 0; g < AT_G - 1; ++g) sum += red[g * AT_T * AT_T + (ty + 8 * j) * AT_T + tx];
+                for (int g = 0; g < 3; ++g) sum += red[g * TP + pix0 + pstep * j];
                 const size_t idx = (size_t)iy * n + ix;
                 T r = beta * sum;
                 if (xin) r += alpha * xin[idx];
