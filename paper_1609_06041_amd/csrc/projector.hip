@@ -217,7 +217,7 @@ hipError_t launch_forward_resid(const float* xp, const float* xTp, float* y, con
 // plane passes through L2 once per three views.  tasks: per workgroup 36
 // entries view * 64 + block (-1 for none; the first entry is never -1).
 constexpr int kSlabWaves = 12, kSlabThreads = 64 * kSlabWaves, kSlabTPW = 3, kSlabTasks = kSlabWaves * kSlabTPW;
-constexpr int kSlabFB = 4, kSlabPre = 24;
+constexpr int kSlabFB = 6, kSlabPre = 24;
 
 int forward_slab_rows(int n) {
     // the slab (R rows of n + 6 floats) within 64 KB of LDS and 24 prefetched floats a thread
@@ -366,9 +366,9 @@ hipError_t launch_forward(const T* xp, const T* xTp, T* y, const ViewGeom* views
 // or |sin| (column views) <= 1, so only bins floor(t), floor(t)+1 carry
 // weight.  out = alpha * xin + beta * A^T (c1 y1 + c2 y2).
 //
-// Workgroup: a 32 x 32 pixel tile, AT_G view streams of AT_SL lanes; stream
-// h takes the view chunks h, h+AT_G, ... and its lane (tx, ty) owns the
-// pixels (x0 + tx, y0 + ty + AT_RS j), j = 0..AT_PJ-1.  For each chunk of
+// Workgroup: a 32 x 32 pixel tile, G view streams of SL lanes; stream h
+// takes the view chunks h, h+G, ... and its lane (tx, ty) owns the pixels
+// (x0 + tx, y0 + ty + RS j), j = 0..PJ-1.  For each chunk of
 // views the stream stages, per view, the 48 bins starting one below the
 // tile's lowest bin coordinate (the tile spans at most 31 sqrt(2) + 2 bins),
 // zero outside the detector, so the inner loop reads LDS without bounds
@@ -378,19 +378,28 @@ hipError_t launch_forward(const T* xp, const T* xTp, T* y, const ViewGeom* views
 // positions of the tile's first row and the row increments, so a lane's
 // positions take only 64-bit adds.  The inner loop is bound by LDS reads:
 // 8 bytes of taps per (pixel, view) plus the view's 32 bytes of tables per
-// lane, which eight pixels a lane share.
+// lane, which the PJ pixels of a lane share.
 constexpr int AT_T = 32;
-constexpr int AT_G = 8;                   // view streams per tile (16 waves: a 512^2 image has one tile per CU)
-constexpr int AT_SL = 128;                // lanes per stream
-constexpr int AT_THREADS = AT_SL * AT_G;
-constexpr int AT_PJ = 8;                  // pixels per lane, one column
-constexpr int AT_RS = AT_T / AT_PJ;       // lane rows per stream
+constexpr int AT_THREADS = 1024;   // 16 waves: a 512^2 image has one tile per CU
 constexpr int AT_W = 48;
-static_assert(AT_SL == AT_T * AT_RS, "a stream covers the tile once");
 
-// views per chunk: the LDS tables stay within 64 KB
+// The stream layout per element type; the LDS tables stay within 64 KB.
 template <typename T>
-constexpr int at_vc() { return sizeof(T) == 4 ? 16 : 8; }
+struct AtCfg;
+template <>
+struct AtCfg<float> {
+    static constexpr int G = 16;   // view streams per tile, one wave each
+    static constexpr int PJ = 16;  // pixels per lane, one column
+    static constexpr int VC = 8;   // views per chunk
+    static constexpr int VQ = 1;   // views per inner pass
+};
+template <>
+struct AtCfg<double> {
+    static constexpr int G = 8;
+    static constexpr int PJ = 8;
+    static constexpr int VC = 8;
+    static constexpr int VQ = 2;
+};
 
 struct TileBox {
     double xlo, xhi, ylo, yhi, cd;
@@ -412,23 +421,26 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
                                              const T* __restrict__ xin, T alpha, T beta, T* __restrict__ out,
                                              const ViewGeom* __restrict__ views, int n, int m, int nb, int bxi,
                                              int byi) {
-    constexpr int VC = at_vc<T>();
-    constexpr int PER = VC * AT_W / AT_SL;   // staged bins per lane and chunk
-    static_assert(PER * AT_SL == VC * AT_W && VC % 2 == 0, "chunk shape");
+    constexpr int G = AtCfg<T>::G, PJ = AtCfg<T>::PJ, VC = AtCfg<T>::VC, VQ = AtCfg<T>::VQ;
+    constexpr int RS = AT_T / PJ;          // lane rows per stream
+    constexpr int SL = AT_T * RS;          // lanes per stream
+    constexpr int PER = VC * AT_W / SL;    // staged bins per lane and chunk
+    static_assert(SL * G == AT_THREADS && SL % 64 == 0, "whole waves per stream");
+    static_assert(PER * SL == VC * AT_W && VC % VQ == 0 && VC * AT_T % SL == 0, "chunk shape");
     struct Lds {
         // the staged bins, each already multiplied by its view's len (first,
         // at LDS offset zero, so the per-view bases fold into the read
         // instructions' offsets)
-        T win[AT_G][VC][AT_W];
+        T win[G][VC][AT_W];
         // per view of the staged chunk, in 32.32 fixed point relative to the
         // window: colt[i][tx] = t of pixel (x0 + tx, y0), rowt[i][r] = r * (the
-        // per-row increment), r = 0..AT_RS -- so a lane's positions are
-        // colt[tx] + rowt[ty] + j rowt[AT_RS] (adds only)
-        long long colt[AT_G][VC][AT_T];
-        long long rowt[AT_G][VC][AT_RS + 1];
+        // per-row increment), r = 0..RS -- so a lane's positions are
+        // colt[tx] + rowt[ty] + j rowt[RS] (adds only)
+        long long colt[G][VC][AT_T];
+        long long rowt[G][VC][RS + 1];
         // the hat weights over len: 1 - f prate (left bin) and poff + f prate
         // (right bin), f the 32-bit fraction, prate = len2 / (len 2^32), poff = 1 - len2 / len
-        T prate[AT_G][VC], poff[AT_G][VC];
+        T prate[G][VC], poff[G][VC];
     };
     __shared__ Lds sh;
     auto& win = sh.win;
@@ -438,20 +450,20 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
     auto& poff = sh.poff;
     // h is the same on every lane of a wave: keep it (and the LDS bases built
     // from it) in scalar registers
-    const int tid = threadIdx.x, h = __builtin_amdgcn_readfirstlane(tid / AT_SL), l = tid % AT_SL;
+    const int tid = threadIdx.x, h = __builtin_amdgcn_readfirstlane(tid / SL), l = tid % SL;
     const int tx = l % AT_T, ty = l / AT_T;
     const int x0 = bxi * AT_T, y0 = byi * AT_T;
     const double c = 0.5 * (double)(n - 1);
     const TileBox box{x0 - c, x0 + (AT_T - 1) - c, y0 - c, y0 + (AT_T - 1) - c, 0.5 * (double)(nb - 1)};
     const int nchunk = (m + VC - 1) / VC;
-    const int nsteps = (nchunk + AT_G - 1) / AT_G;
+    const int nsteps = (nchunk + G - 1) / G;
     const double two32 = 4294967296.0;
 
     T stg[PER];
     auto fetch = [&](int ch) {
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
-            const int e = l + AT_SL * r;
+            const int e = l + SL * r;
             const int i = e / AT_W, k = e - i * AT_W;
             const int v = ch * VC + i;
             T val = T(0);
@@ -471,13 +483,13 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
     auto commit = [&](int ch) {
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
-            const int e = l + AT_SL * r;
+            const int e = l + SL * r;
             const int i = e / AT_W;
             win[h][i][e - i * AT_W] = stg[r];
         }
 #pragma unroll
-        for (int q = 0; q < VC * AT_T / AT_SL; ++q) {
-            const int e = l + AT_SL * q;
+        for (int q = 0; q < VC * AT_T / SL; ++q) {
+            const int e = l + SL * q;
             const int i = e / AT_T, cx = e % AT_T;
             const int v = ch * VC + i;
             long long a = 3ll << 31;
@@ -488,14 +500,14 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
             }
             colt[h][i][cx] = a;
         }
-        for (int e = l; e < VC * (AT_RS + 2); e += AT_SL) {
-            if (e < VC * (AT_RS + 1)) {
-                const int i = e / (AT_RS + 1), r = e - (AT_RS + 1) * i;
+        for (int e = l; e < VC * (RS + 2); e += SL) {
+            if (e < VC * (RS + 1)) {
+                const int i = e / (RS + 1), r = e - (RS + 1) * i;
                 const int v = ch * VC + i;
                 rowt[h][i][r] = (ch < nchunk && v < m) ? (long long)r * llrint(views[v].sn * two32) : 0ll;
                 continue;
             }
-            const int i = e - VC * (AT_RS + 1);
+            const int i = e - VC * (RS + 1);
             const int v = ch * VC + i;
             const bool live = ch < nchunk && v < m && views[v].len > 0.0;
             const double q = live ? views[v].len2 / views[v].len : 0.0;
@@ -504,29 +516,29 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
         }
     };
 
-    T acc[AT_PJ];
+    T acc[PJ];
 #pragma unroll
-    for (int j = 0; j < AT_PJ; ++j) acc[j] = T(0);
+    for (int j = 0; j < PJ; ++j) acc[j] = T(0);
     fetch(h);
     commit(h);
     __syncthreads();
     for (int st = 0; st < nsteps; ++st) {
-        const int ch = h + AT_G * st;
-        fetch(ch + AT_G);
+        const int ch = h + G * st;
+        fetch(ch + G);
         if (ch < nchunk) {
-            // two views x AT_PJ pixels per pass: all 2 AT_PJ tap-pair reads are independent
+            // VQ views x PJ pixels per pass: all VQ PJ tap-pair reads are independent
 #pragma unroll 1
-            for (int i = 0; i < VC; i += 2) {
-                unsigned k[2][AT_PJ];
-                T f[2][AT_PJ], a[2][AT_PJ], b[2][AT_PJ], rate[2], off[2];
+            for (int i = 0; i < VC; i += VQ) {
+                unsigned k[VQ][PJ];
+                T f[VQ][PJ], a[VQ][PJ], b[VQ][PJ], rate[VQ], off[VQ];
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < VQ; ++q) {
                     unsigned long long tj = (unsigned long long)(colt[h][i + q][tx] + rowt[h][i + q][ty]);
-                    const unsigned long long dr = (unsigned long long)rowt[h][i + q][AT_RS];
+                    const unsigned long long dr = (unsigned long long)rowt[h][i + q][RS];
                     rate[q] = prate[h][i + q];
                     off[q] = poff[h][i + q];
 #pragma unroll
-                    for (int j = 0; j < AT_PJ; ++j) {
+                    for (int j = 0; j < PJ; ++j) {
                         // t >= 1 - rounding > 0, so the high word is floor(t)
                         k[q][j] = (unsigned)(tj >> 32);
                         f[q][j] = (T)(unsigned)tj;
@@ -534,16 +546,16 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
                     }
                 }
 #pragma unroll
-                for (int q = 0; q < 2; ++q)
+                for (int q = 0; q < VQ; ++q)
 #pragma unroll
-                    for (int j = 0; j < AT_PJ; ++j) {
+                    for (int j = 0; j < PJ; ++j) {
                         a[q][j] = win[h][i + q][k[q][j]];
                         b[q][j] = win[h][i + q][k[q][j] + 1];
                     }
 #pragma unroll
-                for (int q = 0; q < 2; ++q)
+                for (int q = 0; q < VQ; ++q)
 #pragma unroll
-                    for (int j = 0; j < AT_PJ; ++j) {
+                    for (int j = 0; j < PJ; ++j) {
                         const T w0 = hat_clamp(fma(-f[q][j], rate[q], T(1)));
                         const T w1 = hat_clamp(fma(f[q][j], rate[q], off[q]));
                         acc[j] = fma(w0, a[q][j], fma(w1, b[q][j], acc[j]));
@@ -551,43 +563,37 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
             }
         }
         __syncthreads();
-        commit(ch + AT_G);
+        commit(ch + G);
         __syncthreads();
     }
-    // sum the streams through LDS (reusing the staging and position tables),
-    // in a fixed order: stream h < 4 adds stream h + 4, then stream 0 adds
-    // streams 1, 2, 3
+    // sum the streams through LDS (reusing the staging and position tables)
+    // as a fixed-order tree: at each level stream h < half adds stream h + half
     T* red = reinterpret_cast<T*>(&sh);
     constexpr int TP = AT_T * AT_T;
-    static_assert(4 * TP * sizeof(T) <= sizeof(sh.win) + sizeof(sh.colt), "reduction buffer");
-    static_assert(AT_G == 8, "two-stage stream sum");
-    const int pix0 = ty * AT_T + tx, pstep = AT_RS * AT_T;
-    if (h >= 4) {
+    static_assert((G / 2) * TP * sizeof(T) <= sizeof(sh.win) + sizeof(sh.colt), "reduction buffer");
+    static_assert((G & (G - 1)) == 0, "power-of-two stream count");
+    const int pix0 = ty * AT_T + tx, pstep = RS * AT_T;
 #pragma unroll
-        for (int j = 0; j < AT_PJ; ++j) red[(h - 4) * TP + pix0 + pstep * j] = acc[j];
-    }
-    __syncthreads();
-    if (h < 4) {
+    for (int half = G / 2; half >= 1; half /= 2) {
+        if (h >= half && h < 2 * half) {
 #pragma unroll
-        for (int j = 0; j < AT_PJ; ++j) acc[j] += red[h * TP + pix0 + pstep * j];
-    }
-    __syncthreads();
-    if (h >= 1 && h < 4) {
+            for (int j = 0; j < PJ; ++j) red[(h - half) * TP + pix0 + pstep * j] = acc[j];
+        }
+        __syncthreads();
+        if (h < half) {
 #pragma unroll
-        for (int j = 0; j < AT_PJ; ++j) red[(h - 1) * TP + pix0 + pstep * j] = acc[j];
+            for (int j = 0; j < PJ; ++j) acc[j] += red[h * TP + pix0 + pstep * j];
+        }
+        __syncthreads();
     }
-    __syncthreads();
     if (h == 0) {
         const int ix = x0 + tx;
 #pragma unroll
-        for (int j = 0; j < AT_PJ; ++j) {
-            const int iy = y0 + ty + AT_RS * j;
+        for (int j = 0; j < PJ; ++j) {
+            const int iy = y0 + ty + RS * j;
             if (ix < n && iy < n) {
-                T sum = acc[j];
-#pragma unroll
-                for (int g = 0; g < 3; ++g) sum += red[g * TP + pix0 + pstep * j];
                 const size_t idx = (size_t)iy * n + ix;
-                T r = beta * sum;
+                T r = beta * acc[j];
                 if (xin) r += alpha * xin[idx];
                 out[idx] = r;
             }
