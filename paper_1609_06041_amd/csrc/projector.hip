@@ -459,27 +459,52 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
     const int nsteps = (nchunk + G - 1) / G;
     const double two32 = 4294967296.0;
 
+    // Per view of a chunk, lane i < VC of every wave computes the view's
+    // values once (window base, len, the 32.32 position of the tile's first
+    // pixel, the column and row increments, the weight constants); the other
+    // lanes take them by lane shuffles.
+    const int lw = threadIdx.x & 63;
     T stg[PER];
+    long long pv_t0 = 0, pv_dc = 0, pv_dr = 0;
+    T pv_rate = T(0), pv_off = T(0);
     auto fetch = [&](int ch) {
+        int wb = 0;
+        T len = T(0);
+        pv_t0 = 3ll << 31;   // past the last view: position 1.5 in a zero window
+        pv_dc = pv_dr = 0;
+        pv_rate = pv_off = T(0);
+        const int vl = ch * VC + lw;
+        if (lw < VC && ch < nchunk && vl < m) {
+            const ViewGeom g = views[vl];
+            wb = window_base(g, box);
+            len = (T)g.len;
+            const double t0 = fma(box.xlo, g.cs, fma(box.ylo, g.sn, box.cd)) - (double)wb;
+            pv_t0 = llrint(t0 * two32);
+            pv_dc = llrint(g.cs * two32);
+            pv_dr = llrint(g.sn * two32);
+            if (g.len > 0.0) {
+                const double q = g.len2 / g.len;
+                pv_rate = (T)(q / two32);
+                pv_off = (T)(1.0 - q);
+            }
+        }
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
             const int e = l + SL * r;
             const int i = e / AT_W, k = e - i * AT_W;
             const int v = ch * VC + i;
+            const int u = __shfl(wb, i) + k;
+            const T lv = __shfl(len, i);
             T val = T(0);
-            if (ch < nchunk && v < m) {
-                const int u = window_base(views[v], box) + k;
-                if (u >= 0 && u < nb) {
-                    const size_t idx = (size_t)v * nb + u;
-                    val = (TWO ? c1 * y1[idx] + c2 * y2[idx] : y1[idx]) * (T)views[v].len;
-                }
+            if (ch < nchunk && v < m && u >= 0 && u < nb) {
+                const size_t idx = (size_t)v * nb + u;
+                val = (TWO ? c1 * y1[idx] + c2 * y2[idx] : y1[idx]) * lv;
             }
             stg[r] = val;
         }
     };
     // The tables of the chunk's views (the weights absorb the 2^-32 of the
-    // fraction through prate).  Past the last view: position 1.5 in a zero
-    // window.
+    // fraction through prate).
     auto commit = [&](int ch) {
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
@@ -491,29 +516,22 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
         for (int q = 0; q < VC * AT_T / SL; ++q) {
             const int e = l + SL * q;
             const int i = e / AT_T, cx = e % AT_T;
-            const int v = ch * VC + i;
-            long long a = 3ll << 31;
-            if (ch < nchunk && v < m) {
-                const ViewGeom g = views[v];
-                const double t0 = fma(box.xlo, g.cs, fma(box.ylo, g.sn, box.cd)) - (double)window_base(g, box);
-                a = llrint(t0 * two32) + (long long)cx * llrint(g.cs * two32);
-            }
-            colt[h][i][cx] = a;
+            colt[h][i][cx] = __shfl(pv_t0, i) + (long long)cx * __shfl(pv_dc, i);
         }
-        for (int e = l; e < VC * (RS + 2); e += SL) {
-            if (e < VC * (RS + 1)) {
-                const int i = e / (RS + 1), r = e - (RS + 1) * i;
-                const int v = ch * VC + i;
-                rowt[h][i][r] = (ch < nchunk && v < m) ? (long long)r * llrint(views[v].sn * two32) : 0ll;
-                continue;
+        for (int e0 = 0; e0 < VC * (RS + 2); e0 += SL) {
+            const int e = e0 + l;
+            // every lane of the wave takes part in the shuffles
+            const int i = e < VC * (RS + 1) ? e / (RS + 1) : min(e - VC * (RS + 1), VC - 1);
+            const long long dr = __shfl(pv_dr, i);
+            const T rate = __shfl(pv_rate, i), off = __shfl(pv_off, i);
+            if (e < VC * (RS + 1))
+                rowt[h][i][e - (RS + 1) * i] = (long long)(e - (RS + 1) * i) * dr;
+            else if (e < VC * (RS + 2)) {
+                prate[h][i] = rate;
+                poff[h][i] = off;
             }
-            const int i = e - VC * (RS + 1);
-            const int v = ch * VC + i;
-            const bool live = ch < nchunk && v < m && views[v].len > 0.0;
-            const double q = live ? views[v].len2 / views[v].len : 0.0;
-            prate[h][i] = (T)(q / two32);
-            poff[h][i] = live ? (T)(1.0 - q) : T(0);
         }
+        (void)ch;
     };
 
     T acc[PJ];
