@@ -367,9 +367,9 @@ hipError_t launch_forward(const T* xp, const T* xTp, T* y, const ViewGeom* views
 // weight.  out = alpha * xin + beta * A^T (c1 y1 + c2 y2).
 //
 // Workgroup: a 32 x 32 pixel tile, G view streams of SL lanes; stream h
-// takes the view chunks h, h+G, ... and its lane (tx, ty) owns the pixels
-// (x0 + tx, y0 + ty + RS j), j = 0..PJ-1.  For each chunk of
-// views the stream stages, per view, the 48 bins starting one below the
+// takes the views h, h+G, h+2G, ... in chunks of VC and its lane (tx, ty)
+// owns the pixels (x0 + tx, y0 + ty + RS j), j = 0..PJ-1.  For each chunk
+// of views the stream stages, per view, the 48 bins starting one below the
 // tile's lowest bin coordinate (the tile spans at most 31 sqrt(2) + 2 bins),
 // zero outside the detector, so the inner loop reads LDS without bounds
 // tests.  The next chunk's bins are loaded into registers while the current
@@ -455,8 +455,9 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
     const int x0 = bxi * AT_T, y0 = byi * AT_T;
     const double c = 0.5 * (double)(n - 1);
     const TileBox box{x0 - c, x0 + (AT_T - 1) - c, y0 - c, y0 + (AT_T - 1) - c, 0.5 * (double)(nb - 1)};
-    const int nchunk = (m + VC - 1) / VC;
-    const int nsteps = (nchunk + G - 1) / G;
+    // step st of stream h holds the views (st VC + i) G + h, i = 0..VC-1, so
+    // every stream has work even when the view count is small
+    const int nsteps = (m + VC * G - 1) / (VC * G);
     const double two32 = 4294967296.0;
 
     // Per view of a chunk, lane i < VC of every wave computes the view's
@@ -467,14 +468,14 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
     T stg[PER];
     long long pv_t0 = 0, pv_dc = 0, pv_dr = 0;
     T pv_rate = T(0), pv_off = T(0);
-    auto fetch = [&](int ch) {
+    auto fetch = [&](int st) {
         int wb = 0;
         T len = T(0);
         pv_t0 = 3ll << 31;   // past the last view: position 1.5 in a zero window
         pv_dc = pv_dr = 0;
         pv_rate = pv_off = T(0);
-        const int vl = ch * VC + lw;
-        if (lw < VC && ch < nchunk && vl < m) {
+        const int vl = (st * VC + lw) * G + h;
+        if (lw < VC && vl < m) {
             const ViewGeom g = views[vl];
             wb = window_base(g, box);
             len = (T)g.len;
@@ -492,11 +493,11 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
         for (int r = 0; r < PER; ++r) {
             const int e = l + SL * r;
             const int i = e / AT_W, k = e - i * AT_W;
-            const int v = ch * VC + i;
+            const int v = (st * VC + i) * G + h;
             const int u = __shfl(wb, i) + k;
             const T lv = __shfl(len, i);
             T val = T(0);
-            if (ch < nchunk && v < m && u >= 0 && u < nb) {
+            if (v < m && u >= 0 && u < nb) {
                 const size_t idx = (size_t)v * nb + u;
                 val = (TWO ? c1 * y1[idx] + c2 * y2[idx] : y1[idx]) * lv;
             }
@@ -505,7 +506,7 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
     };
     // The tables of the chunk's views (the weights absorb the 2^-32 of the
     // fraction through prate).
-    auto commit = [&](int ch) {
+    auto commit = [&](int st) {
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
             const int e = l + SL * r;
@@ -531,22 +532,25 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
                 poff[h][i] = off;
             }
         }
-        (void)ch;
+        (void)st;
     };
 
     T acc[PJ];
 #pragma unroll
     for (int j = 0; j < PJ; ++j) acc[j] = T(0);
-    fetch(h);
-    commit(h);
+    fetch(0);
+    commit(0);
     __syncthreads();
     for (int st = 0; st < nsteps; ++st) {
-        const int ch = h + G * st;
-        fetch(ch + G);
-        if (ch < nchunk) {
+        fetch(st + 1);
+        // the step's live views (uniform over the wave); a dead slot in the
+        // last pass has a zero window
+        const int rem = m - h - st * VC * G;
+        const int nlive = rem <= 0 ? 0 : min(VC, (rem + G - 1) / G);
+        {
             // VQ views x PJ pixels per pass: all VQ PJ tap-pair reads are independent
 #pragma unroll 1
-            for (int i = 0; i < VC; i += VQ) {
+            for (int i = 0; i < nlive; i += VQ) {
                 unsigned k[VQ][PJ];
                 T f[VQ][PJ], a[VQ][PJ], b[VQ][PJ], rate[VQ], off[VQ];
 #pragma unroll
@@ -581,7 +585,7 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
             }
         }
         __syncthreads();
-        commit(ch + G);
+        commit(st + 1);
         __syncthreads();
     }
     // sum the streams through LDS (reusing the staging and position tables)
