@@ -376,9 +376,10 @@ hipError_t launch_forward(const T* xp, const T* xTp, T* y, const ViewGeom* views
 // chunk is used.  The streams are summed through LDS at the end in a fixed
 // order (deterministic).  Per view the stream also tabulates the bin
 // positions of the tile's first row and the row increments, so a lane's
-// positions take only 64-bit adds.  The inner loop is bound by LDS reads:
-// 8 bytes of taps per (pixel, view) plus the view's 32 bytes of tables per
-// lane, which the PJ pixels of a lane share.
+// positions take only 64-bit adds.  The inner loop reads from LDS 8 bytes
+// of taps per (pixel, view) plus the view's 32 bytes of tables per lane,
+// which the PJ pixels of a lane share (with 4 pixels a lane those reads
+// bound the loop; with 16 the VALU work and latency do).
 constexpr int AT_T = 32;
 constexpr int AT_THREADS = 1024;   // 16 waves: a 512^2 image has one tile per CU
 constexpr int AT_W = 48;
