@@ -24,9 +24,14 @@
  *    order.  project / backproject / ramp_filter / tv_prox return without
  *    waiting; the solvers wait for their own results before returning.
  *  - Return value: CTPD_OK (0) or a negative error code.  On an argument
- *    error nothing is launched and no output is written.  ctpd_strerror
- *    gives a message (for CTPD_EHIP it includes the HIP error of the last
- *    failure on the calling thread).
+ *    error nothing is launched and no output is written, with one
+ *    exception: a step size given by the caller is checked against the
+ *    convergence bound of its solver (Eq. 16 and the conditions stated with
+ *    Algorithms 1 and 2) after the operator norms the bound needs have been
+ *    computed on the device; a violation returns CTPD_EINVAL before any
+ *    iteration runs or any output is written.  ctpd_strerror gives a message
+ *    (for CTPD_EHIP it includes the HIP error of the last failure on the
+ *    calling thread).
  *  - An op is not thread-safe: calls on one op must not overlap.
  */
 #ifndef CTPD_H
@@ -75,16 +80,26 @@ typedef struct {
                             mean|sigma A^T D(1) b| */
     double sigma;        /* dual step; default: rho times the bound of Eq. 16 /
                             Algorithm 1 / Algorithm 2 from the operator norms.
-                            lambda_max(A^T D A) depends on the geometry only when
-                            tau is the default (D then scales as 1/kappa; for the
-                            few-view ramp, D(tau) = D(1)/tau): the handle computes
-                            it at its first such solve and reuses it after. */
+                            A given sigma must satisfy that bound strictly:
+                            low-dose sigma < min(2/lambda_h, 1/(tau lambda_A)),
+                            few-view sigma lambda_max(A^T D(1) A) < 1; the norms
+                            are computed (or taken from the handle's cache) and a
+                            violation gives CTPD_EINVAL.
+                            kappa lambda_max(A^T D A) depends only on the geometry
+                            and a = 2 m tau / kappa (H of Eq. 24 is
+                            (1/kappa) |w| / (a + |w|)), and the few-view
+                            lambda_max(A^T D(1) A) on the geometry only: the handle
+                            keeps the last value of each and reuses it. */
     double tv_step;      /* tau_c of the TV dual iteration, default 1/8 */
     double safety;       /* rho < 1, default 0.95 */
     int32_t tv_iters;    /* inner TV steps per outer iteration, default 10 */
     int32_t norm_steps;  /* max Lanczos steps per operator norm, default 100,
                             at most CTPD_MAX_NORM_STEPS */
-    int32_t record_cost; /* 1: fill ctpd_report.cost (Eq. 1 cost, or psi for few-view) */
+    int32_t record_cost; /* 1: fill ctpd_report.cost (Eq. 1 cost, or psi for few-view).
+                            Monitors (cost, gap, resid, rmse) are computed per
+                            iteration in float64 on the device when requested; the
+                            solver then runs the filters' fused-prologue path,
+                            whose iterates equal the default path's bit for bit. */
     int32_t reserved;
 } ctpd_params;
 
@@ -102,6 +117,17 @@ typedef struct {
     double* cost;        /* host, length >= iters, or NULL */
     float* mu_out;       /* device [n_views][n_bins] receives mu^K, or NULL */
     float* p_out;        /* device [2][n][n] receives the TV dual field, or NULL */
+    /* Per-iteration convergence monitors, float64 sums on the device over the
+     * iterate after each iteration k = 1..iters (host arrays of length >= iters,
+     * each NULL when not wanted): */
+    double* gap;         /* partial primal-dual gap f(x^k) - L(x^k, mu^k)
+                            = 1/2 ||W^1/2 (A x^k - b) - W^-1/2 mu^k||^2 (Eq. 10 with the
+                            theorem after it; zero at the saddle point).  Only the
+                            low-dose APP solvers (Algorithm 1 and its D = I
+                            ablation); CTPD_EINVAL elsewhere. */
+    double* resid;       /* ||A x^k - b|| / ||b|| (the constraint of Eq. 25; all solvers) */
+    double* rmse;        /* sqrt(mean((x^k - x_ref)^2)), Eq. 34 (all solvers; needs x_ref) */
+    const float* x_ref;  /* device [n][n] reference image for rmse, or NULL */
 } ctpd_report;
 
 /* Create an operator for geometry *g bound to stream (a hipStream_t; NULL =

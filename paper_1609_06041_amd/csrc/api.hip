@@ -321,9 +321,8 @@ int lowdose_zero(ctpd_op* op) {
 }
 
 int lowdose_loop(ctpd_op* op, const float* b, const float* w, double beta, int iters, const Knobs& k, double tau,
-                 double sigma, float** p_final, bool zeroed = false) {
+                 double sigma, float** p_final, const Monitors& M, bool zeroed = false) {
     int r = CTPD_OK;
-    const size_t I = op->I;
     hipStream_t s = op->stream;
     if (k.record && (r = ensure_cost(op, iters))) return r;
     if (!zeroed && (r = lowdose_zero(op))) return r;
@@ -365,17 +364,13 @@ int lowdose_loop(ctpd_op* op, const float* b, const float* w, double beta, int i
             if ((r = project_resid(op, op->x, nullptr, nullptr, nullptr, op->q, padded))) return r;
             if ((r = filter(op, FILT_DUAL_LD, op->q, b, op->winv, mu, mu, 1.f, nullptr, 0.f, fs, mun))) return r;
         }
-        if (k.record) {
-            if ((r = reduce(op, RED_WRES_F32, op->q, b, w, I, 0))) return r;
-            HIP_TRY(launch_tv_norm(op->x, op->n, op->partials, op->cost_dev + 6 * it, s));
-            HIP_TRY(hipMemcpyAsync(op->cost_dev + 6 * it + 3, op->red, sizeof(double) * 3,
-                                   hipMemcpyDeviceToDevice, s));
-        }
+        if (k.record && (r = record_monitors(op, it, M, op->x, op->q, b, w, mun))) return r;
         float* t = mup;
         mup = mu;
         mu = mun;
         mun = t;
     }
+    (void)s;
     op->mu[0] = mu;
     op->mu[1] = mup;
     op->mu[2] = mun;
@@ -409,12 +404,57 @@ int read_params(const ctpd_params* p, Knobs* k) {
     return CTPD_OK;
 }
 
+int read_monitors(const ctpd_report* rep, bool gap_ok, Knobs* k, Monitors* M) {
+    *M = Monitors{};
+    M->cost = k->record != 0;
+    if (rep) {
+        M->gap = rep->gap != nullptr;
+        M->resid = rep->resid != nullptr;
+        M->rmse = rep->rmse != nullptr;
+        M->x_ref = rep->x_ref;
+        if (M->gap && !gap_ok) return einval("the partial gap is defined for the low-dose APP solvers only");
+        if (M->rmse && !M->x_ref) return einval("rmse needs x_ref");
+        M->cost = M->cost && rep->cost != nullptr;
+    } else {
+        M->cost = false;
+    }
+    k->record = M->any() ? 1 : 0;
+    return CTPD_OK;
+}
+
+int monitor_bnorm(ctpd_op* op, const float* b, Monitors* M) {
+    if (!M->resid) return CTPD_OK;
+    int r;
+    if ((r = reduce(op, RED_SQ_F32, b, nullptr, nullptr, op->I, 0))) return r;
+    if ((r = read_red(op))) return r;
+    M->bnorm2 = op->red_host[0];
+    return CTPD_OK;
+}
+
+// The per-iteration monitors (Eq. 1 cost or psi, partial gap, data residual,
+// Eq. 34 RMSE) as float64 sums into the iteration's slots of op->cost_dev.
+int record_monitors(ctpd_op* op, int it, const Monitors& M, const float* x, const float* q, const float* b,
+                    const float* w, const float* mu) {
+    double* slot = op->cost_dev + (size_t)3 * kMonSlots * it;
+    hipStream_t s = op->stream;
+    if (M.cost) {
+        HIP_TRY(launch_tv_norm(x, op->n, op->partials, slot + 3 * MON_TV, s));
+        HIP_TRY(launch_reduce(w ? RED_WRES_F32 : RED_SQDIFF_F32, q, b, w, op->I, op->partials, slot + 3 * MON_DATA,
+                              s));
+    }
+    if (M.gap) HIP_TRY(launch_reduce(RED_GAP_F32, q, b, w, op->I, op->partials, slot + 3 * MON_GAP, s, mu));
+    if (M.resid) HIP_TRY(launch_reduce(RED_SQDIFF_F32, q, b, nullptr, op->I, op->partials, slot + 3 * MON_RES, s));
+    if (M.rmse)
+        HIP_TRY(launch_reduce(RED_SQDIFF_F32, x, M.x_ref, nullptr, op->J, op->partials, slot + 3 * MON_RMSE, s));
+    return CTPD_OK;
+}
+
 int ensure_cost(ctpd_op* op, int iters) {
     if (op->cost_cap >= iters) return CTPD_OK;
     if (op->cost_dev) (void)hipFree(op->cost_dev);
     op->cost_dev = nullptr;
     op->cost_cap = 0;
-    ALLOC(op->cost_dev, (size_t)6 * std::max(iters, 1));
+    ALLOC(op->cost_dev, (size_t)3 * kMonSlots * std::max(iters, 1));
     op->cost_cap = iters;
     return CTPD_OK;
 }
@@ -424,20 +464,24 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 }
 
 int finish(ctpd_op* op, int iters, bool lowdose, double beta, float* p_final, ctpd_report* rep, float* x_out,
-           bool recorded) {
+           const Monitors& M) {
     const size_t J = op->J, I = op->I;
     HIP_TRY(launch_copy_f32(x_out, op->x, J, op->stream));
     if (rep && rep->mu_out) HIP_TRY(launch_copy_f32(rep->mu_out, op->mu[0], I, op->stream));
     if (rep && rep->p_out) HIP_TRY(launch_copy_f32(rep->p_out, p_final, 2 * J, op->stream));
-    if (rep && rep->cost && recorded && iters > 0) {
-        std::vector<double> h((size_t)6 * iters);
+    if (rep && M.any() && iters > 0) {
+        const size_t per = (size_t)3 * kMonSlots;
+        std::vector<double> h(per * iters);
         HIP_TRY(hipMemcpyAsync(h.data(), op->cost_dev, sizeof(double) * h.size(), hipMemcpyDeviceToHost,
                                op->stream));
         int r = sync(op);
         if (r) return r;
         for (int k = 0; k < iters; ++k) {
-            const double tv = h[6 * k + 0], res = h[6 * k + 3];
-            rep->cost[k] = lowdose ? beta * tv + 0.5 * res : tv;
+            const double* v = h.data() + per * k;
+            if (M.cost) rep->cost[k] = lowdose ? beta * v[3 * MON_TV] + 0.5 * v[3 * MON_DATA] : v[3 * MON_TV];
+            if (M.gap) rep->gap[k] = 0.5 * v[3 * MON_GAP];
+            if (M.resid) rep->resid[k] = M.bnorm2 > 0.0 ? std::sqrt(v[3 * MON_RES] / M.bnorm2) : 0.0;
+            if (M.rmse) rep->rmse[k] = std::sqrt(v[3 * MON_RMSE] / (double)J);
         }
     }
     return sync(op);
@@ -578,35 +622,45 @@ int lowdose_setup_begin(ctpd_op* op, const float* b, const float* w, const Knobs
     S->tau = k.tau > 0 ? k.tau : kTauMultLowdose * M_PI * S->kappa / (2.0 * op->m);
     HIP_TRY(launch_inverse_f32(op->winv, w, I, op->stream));
     if ((r = k.tau > 0 ? ensure_taps(op, S->tau, S->kappa) : ensure_taps_default(op, S->kappa))) return r;
-    S->sigma = k.sigma;
-    S->norms = !(S->sigma > 0);
-    if (S->norms) {
-        // with the default tau, H of Eq. 24 is |w| / (kappa (0.3 pi + |w|)), so
-        // D = D1 / kappa and kappa * lambda_max(A^T D A) depends on the geometry only
-        S->cacheable = !(k.tau > 0);
-        S->run_a = !(S->cacheable && op->norm_ld > 0.0 && op->norm_ld_kmax == k.norm_steps);
-        if ((r = ensure_f64(op))) return r;
-        HIP_TRY(launch_rsqrt_f64(op->sino64[3], w, I, op->stream));
-        if (S->run_a && (r = setup_lambda_a(op, k.norm_steps, &S->La))) return r;
-        (void)w;
-    }
+    // The two norms are computed whether sigma is given or not: they give the
+    // default sigma, and a given one is checked against the bound they set.
+    // H of Eq. 24 is (1/kappa) |w| / (a + |w|) with a = 2 m tau / kappa, so
+    // kappa * lambda_max(A^T D A) depends on the geometry and a only (a is the
+    // constant 0.3 pi at the default tau).
+    S->a = k.tau > 0 ? 2.0 * op->m * S->tau / S->kappa : kTauMultLowdose * M_PI;
+    S->run_a = !(op->norm_ld > 0.0 && op->norm_ld_a == S->a && op->norm_ld_kmax == k.norm_steps);
+    if ((r = ensure_f64(op))) return r;
+    HIP_TRY(launch_rsqrt_f64(op->sino64[3], w, I, op->stream));
+    if (S->run_a && (r = setup_lambda_a(op, k.norm_steps, &S->La))) return r;
     return CTPD_OK;
 }
 
-void lowdose_setup_end(ctpd_op* op, const Knobs& k, LowdoseSetup* S) {
-    if (!S->norms) return;
+int lowdose_setup_end(ctpd_op* op, const Knobs& k, LowdoseSetup* S) {
     if (S->run_a) {
         S->lam_a = S->La.theta;
         S->steps_a = S->La.steps;
-        if (S->cacheable) {
-            op->norm_ld = S->lam_a * S->kappa;
-            op->norm_ld_kmax = k.norm_steps;
-        }
+        op->norm_ld = S->lam_a * S->kappa;
+        op->norm_ld_a = S->a;
+        op->norm_ld_kmax = k.norm_steps;
     } else {
         S->lam_a = op->norm_ld / S->kappa;
         S->steps_a = 0;
     }
-    S->sigma = k.rho * std::min(2.0 / S->lam_h, 1.0 / (S->tau * S->lam_a));
+    // Eq. 16 with the conditions of Algorithm 1: sigma < 2 / lambda_h and sigma tau lambda_A < 1
+    const double bound = std::min(2.0 / S->lam_h, 1.0 / (S->tau * S->lam_a));
+    if (k.sigma > 0) {
+        if (!(k.sigma < bound)) {
+            snprintf(g_errmsg, sizeof g_errmsg,
+                     "invalid argument: sigma = %.6g violates the step-size bound (Eq. 16): needs sigma < "
+                     "min(2/lambda_h, 1/(tau lambda_A)) = %.6g (lambda_h = %.6g, tau = %.6g, lambda_A = %.6g)",
+                     k.sigma, bound, S->lam_h, S->tau, S->lam_a);
+            return CTPD_EINVAL;
+        }
+        S->sigma = k.sigma;
+    } else {
+        S->sigma = k.rho * bound;
+    }
+    return CTPD_OK;
 }
 
 }  // namespace ctpd_host
@@ -786,12 +840,15 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
     Knobs k;
     int r = read_params(p, &k);
     if (r) return r;
+    Monitors M;
+    if ((r = read_monitors(rep, true, &k, &M))) return r;
     const auto t0 = std::chrono::steady_clock::now();
     LowdoseSetup S;
     if ((r = lowdose_setup_begin(op, b, w, k, &S))) return r;
+    if ((r = monitor_bnorm(op, b, &M))) return r;
     // the iterates' zero start runs on op->stream while the lambda_h chains run on op->aux
     if ((r = lowdose_zero(op))) return r;
-    if (S.norms) {
+    {
         // the lambda_A chain (first solve on the handle) runs on op->stream while the
         // per-view lambda_h chains run on op->aux
         if ((r = ensure_hv(op, k.norm_steps))) return r;
@@ -812,15 +869,15 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
             if ((r = run_lanczos({&S.La}))) return r;
         }
     }
-    lowdose_setup_end(op, k, &S);
+    if ((r = lowdose_setup_end(op, k, &S))) return r;
     const double kappa = S.kappa, tau = S.tau, sigma = S.sigma, lam_a = S.lam_a, lam_h = S.lam_h;
     const int steps_a = S.steps_a, steps_h = S.steps_h;
     if ((r = sync(op))) return r;
     const double setup_ms = ms_since(t0);
     const auto t1 = std::chrono::steady_clock::now();
     float* pcur = nullptr;
-    if ((r = lowdose_loop(op, b, w, beta, iters, k, tau, sigma, &pcur, true))) return r;
-    if ((r = finish(op, iters, true, beta, pcur, rep, x_out, k.record != 0))) return r;
+    if ((r = lowdose_loop(op, b, w, beta, iters, k, tau, sigma, &pcur, M, true))) return r;
+    if ((r = finish(op, iters, true, beta, pcur, rep, x_out, M))) return r;
     if (rep) {
         rep->tau = tau;
         rep->sigma = sigma;
@@ -845,6 +902,8 @@ int ctpd_app_identity_lowdose_solve(ctpd_op* op, const float* b, const float* w,
     Knobs k;
     int r = read_params(p, &k);
     if (r) return r;
+    Monitors M;
+    if ((r = read_monitors(rep, true, &k, &M))) return r;
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = op->stream;
     // validity scan and kappa (reported), W^-1, lambda_h = max 1/w, D = I
@@ -862,28 +921,38 @@ int ctpd_app_identity_lowdose_solve(ctpd_op* op, const float* b, const float* w,
     op->tap_tau = op->tap_kappa = -2.0;   // not the taps of any (tau, kappa)
     double tau = k.tau, sigma = k.sigma, lam_a = 0.0;
     int steps_a = 0;
-    if (!(tau > 0) || !(sigma > 0)) {
-        if (op->norm_ata > 0.0 && op->norm_ata_kmax == k.norm_steps) {   // a property of the geometry
-            lam_a = op->norm_ata;
-        } else {
-            Lanczos L;
-            if ((r = setup_lambda_a(op, k.norm_steps, &L, false, nullptr))) return r;
-            if ((r = run_lanczos({&L}))) return r;
-            lam_a = L.theta;
-            steps_a = L.steps;
-            op->norm_ata = lam_a;
-            op->norm_ata_kmax = k.norm_steps;
-        }
-        // default tau balances the two bounds of sigma: 1 / (tau lambda_A) = 2 / lambda_h
-        if (!(tau > 0)) tau = lam_h / (2.0 * lam_a);
-        if (!(sigma > 0)) sigma = k.rho * std::min(2.0 / lam_h, 1.0 / (tau * lam_a));
+    if (op->norm_ata > 0.0 && op->norm_ata_kmax == k.norm_steps) {   // a property of the geometry
+        lam_a = op->norm_ata;
+    } else {
+        Lanczos L;
+        if ((r = setup_lambda_a(op, k.norm_steps, &L, false, nullptr))) return r;
+        if ((r = run_lanczos({&L}))) return r;
+        lam_a = L.theta;
+        steps_a = L.steps;
+        op->norm_ata = lam_a;
+        op->norm_ata_kmax = k.norm_steps;
     }
+    // default tau balances the two bounds of sigma: 1 / (tau lambda_A) = 2 / lambda_h
+    if (!(tau > 0)) tau = lam_h / (2.0 * lam_a);
+    const double bound = std::min(2.0 / lam_h, 1.0 / (tau * lam_a));
+    if (sigma > 0) {
+        if (!(sigma < bound)) {
+            snprintf(g_errmsg, sizeof g_errmsg,
+                     "invalid argument: sigma = %.6g violates the step-size bound (Eq. 16 with D = I): needs sigma < "
+                     "min(2/lambda_h, 1/(tau lambda_A)) = %.6g",
+                     sigma, bound);
+            return CTPD_EINVAL;
+        }
+    } else {
+        sigma = k.rho * bound;
+    }
+    if ((r = monitor_bnorm(op, b, &M))) return r;
     if ((r = sync(op))) return r;
     const double setup_ms = ms_since(t0);
     const auto t1 = std::chrono::steady_clock::now();
     float* pcur = nullptr;
-    if ((r = lowdose_loop(op, b, w, beta, iters, k, tau, sigma, &pcur))) return r;
-    if ((r = finish(op, iters, true, beta, pcur, rep, x_out, k.record != 0))) return r;
+    if ((r = lowdose_loop(op, b, w, beta, iters, k, tau, sigma, &pcur, M))) return r;
+    if ((r = finish(op, iters, true, beta, pcur, rep, x_out, M))) return r;
     if (rep) {
         rep->tau = tau;
         rep->sigma = sigma;
@@ -907,6 +976,8 @@ int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
     Knobs k;
     int r = read_params(p, &k);
     if (r) return r;
+    Monitors M;
+    if ((r = read_monitors(rep, false, &k, &M))) return r;
     const auto t0 = std::chrono::steady_clock::now();
     const size_t I = op->I, J = op->J;
     hipStream_t s = op->stream;
@@ -916,30 +987,40 @@ int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
         snprintf(g_errmsg, sizeof g_errmsg, "%.0f non-finite data values", op->red_host[1]);
         return CTPD_EDOMAIN;
     }
+    M.bnorm2 = op->red_host[0];
     // a2: sigma tau < 1/lambda_max(A^T D(tau) A) with D(tau) = D(1)/tau, so
-    // sigma = rho / lambda_max(A^T D(1) A) whatever tau is.
+    // the bound is sigma lambda_max(A^T D(1) A) < 1 whatever tau is; the
+    // default sigma is rho / lambda_max(A^T D(1) A).  The norm is a property
+    // of the geometry, computed by the first solve on the handle.
     double sigma = k.sigma, lam1 = 0.0;
     int steps_a = 0;
-    if (!(sigma > 0) || !(k.tau > 0)) {
+    if (op->norm_fv > 0.0 && op->norm_fv_kmax == k.norm_steps) {
+        lam1 = op->norm_fv;
+    } else {
         if ((r = ensure_taps(op, 1.0, 0.0))) return r;
-        if (!(sigma > 0)) {
-            if (op->norm_fv > 0.0 && op->norm_fv_kmax == k.norm_steps) {   // D(1) depends on the geometry only
-                lam1 = op->norm_fv;
-            } else {
-                Lanczos La;
-                if ((r = setup_lambda_a(op, k.norm_steps, &La))) return r;
-                if ((r = run_lanczos({&La}))) return r;
-                lam1 = La.theta;
-                steps_a = La.steps;
-                op->norm_fv = lam1;
-                op->norm_fv_kmax = k.norm_steps;
-            }
-            sigma = k.rho / lam1;
+        Lanczos La;
+        if ((r = setup_lambda_a(op, k.norm_steps, &La))) return r;
+        if ((r = run_lanczos({&La}))) return r;
+        lam1 = La.theta;
+        steps_a = La.steps;
+        op->norm_fv = lam1;
+        op->norm_fv_kmax = k.norm_steps;
+    }
+    if (sigma > 0) {
+        if (!(sigma * lam1 < 1.0)) {
+            snprintf(g_errmsg, sizeof g_errmsg,
+                     "invalid argument: sigma = %.6g violates the step-size bound of Algorithm 2: needs sigma < "
+                     "1/lambda_max(A^T D(1) A) = %.6g",
+                     sigma, 1.0 / lam1);
+            return CTPD_EINVAL;
         }
+    } else {
+        sigma = k.rho / lam1;
     }
     double tau = k.tau;
     if (!(tau > 0)) {
         // tau = mean |sigma A^T D(1) b|
+        if ((r = ensure_taps(op, 1.0, 0.0))) return r;
         if ((r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, 1.f, op->q)))
             return r;
         HIP_TRY(launch_adjoint<float>(op->q, nullptr, 1.f, 0.f, nullptr, 0.f, 1.f, op->z, op->views, op->n, op->m,
@@ -992,12 +1073,7 @@ int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
             if ((r = filter(op, FILT_DUAL_FV, op->q, b, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun)))
                 return r;
         }
-        if (k.record) {
-            if ((r = reduce(op, RED_SQDIFF_F32, op->q, b, nullptr, I, 0))) return r;
-            HIP_TRY(launch_tv_norm(op->x, op->n, op->partials, op->cost_dev + 6 * it, s));
-            HIP_TRY(hipMemcpyAsync(op->cost_dev + 6 * it + 3, op->red, sizeof(double) * 3,
-                                   hipMemcpyDeviceToDevice, s));
-        }
+        if (k.record && (r = record_monitors(op, it, M, op->x, op->q, b, nullptr, nullptr))) return r;
         float* t = mup;
         mup = mu;
         mu = mun;
@@ -1006,7 +1082,7 @@ int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
     op->mu[0] = mu;
     op->mu[1] = mup;
     op->mu[2] = mun;
-    if ((r = finish(op, iters, false, 1.0, pcur, rep, x_out, k.record != 0))) return r;
+    if ((r = finish(op, iters, false, 1.0, pcur, rep, x_out, M))) return r;
     if (rep) {
         rep->tau = tau;
         rep->sigma = sigma;
@@ -1036,6 +1112,8 @@ int ctpd_gist_lowdose_solve(ctpd_op* op, const float* b, const float* w, double 
     int r = read_params(p, &k);
     if (r) return r;
     if (k.sigma > 0.125) return einval("GIST dual step must be <= 1/8 (||grad||^2 <= 8)");
+    Monitors M;
+    if ((r = read_monitors(rep, false, &k, &M))) return r;
     const auto t0 = std::chrono::steady_clock::now();
     const size_t I = op->I, J = op->J;
     hipStream_t s = op->stream;
@@ -1047,18 +1125,30 @@ int ctpd_gist_lowdose_solve(ctpd_op* op, const float* b, const float* w, double 
         return CTPD_EDOMAIN;
     }
     const double kappa = op->red_host[0] / (double)I;
+    // the Lipschitz constant of the data term's gradient, lambda_max(A^T W A)
+    // (data-dependent): the default gamma, and the bound gamma < 2 / L a given one must meet
     double gamma = k.tau, lip = 0.0;
     int steps_a = 0;
-    if (!(gamma > 0)) {
+    {
         Lanczos L;
         if ((r = setup_lambda_a(op, k.norm_steps, &L, false, w))) return r;
         if ((r = run_lanczos({&L}))) return r;
         lip = L.theta;
         steps_a = L.steps;
+    }
+    if (gamma > 0) {
+        if (!(gamma * lip < 2.0)) {
+            snprintf(g_errmsg, sizeof g_errmsg,
+                     "invalid argument: GIST step gamma = %.6g needs gamma < 2/lambda_max(A^T W A) = %.6g", gamma,
+                     2.0 / lip);
+            return CTPD_EINVAL;
+        }
+    } else {
         gamma = k.rho * 2.0 / lip;
     }
     const double lam = k.sigma > 0 ? k.sigma : 0.125;
     const double radius = gamma * beta / lam;
+    if ((r = monitor_bnorm(op, b, &M))) return r;
     if ((r = sync(op))) return r;
     const double setup_ms = ms_since(t0);
     const auto t1 = std::chrono::steady_clock::now();
@@ -1085,15 +1175,12 @@ int ctpd_gist_lowdose_solve(ctpd_op* op, const float* b, const float* w, double 
         }
         if (k.record) {
             if ((r = project(op, op->x, op->q))) return r;
-            if ((r = reduce(op, RED_WRES_F32, op->q, b, w, I, 0))) return r;
-            HIP_TRY(launch_tv_norm(op->x, op->n, op->partials, op->cost_dev + 6 * it, s));
-            HIP_TRY(hipMemcpyAsync(op->cost_dev + 6 * it + 3, op->red, sizeof(double) * 3,
-                                   hipMemcpyDeviceToDevice, s));
+            if ((r = record_monitors(op, it, M, op->x, op->q, b, w, nullptr))) return r;
         }
     }
     if (rep && rep->p_out && radius > 0)   // report v itself
         HIP_TRY(launch_lin3_f32(pcur, pcur, (float)radius, nullptr, 0.f, nullptr, 0.f, nullptr, 2 * J, s));
-    if ((r = finish(op, iters, true, beta, pcur, rep, x_out, k.record != 0))) return r;
+    if ((r = finish(op, iters, true, beta, pcur, rep, x_out, M))) return r;
     if (rep) {
         rep->tau = gamma;
         rep->sigma = lam;
@@ -1117,6 +1204,8 @@ int ctpd_cp_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
     Knobs k;
     int r = read_params(p, &k);
     if (r) return r;
+    Monitors M;
+    if ((r = read_monitors(rep, false, &k, &M))) return r;
     const auto t0 = std::chrono::steady_clock::now();
     const size_t I = op->I, J = op->J;
     hipStream_t s = op->stream;
@@ -1126,24 +1215,34 @@ int ctpd_cp_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
         snprintf(g_errmsg, sizeof g_errmsg, "%.0f non-finite data values", op->red_host[1]);
         return CTPD_EDOMAIN;
     }
+    M.bnorm2 = op->red_host[0];
     if (!op->xbar) ALLOC(op->xbar, J);
+    // ||K||^2 <= lambda_max(A^T A) + ||grad||^2 <= lambda_max(A^T A) + 8: the defaults
+    // s = t = rho / sqrt of that, and the condition s t (lambda_max(A^T A) + 8) < 1 given steps must meet
     double t = k.tau, sg = k.sigma, lata = 0.0;
     int steps_a = 0;
-    if (!(t > 0) || !(sg > 0)) {
-        if (op->norm_ata > 0.0 && op->norm_ata_kmax == k.norm_steps) {   // a property of the geometry
-            lata = op->norm_ata;
-        } else {
-            Lanczos L;
-            if ((r = setup_lambda_a(op, k.norm_steps, &L, false, nullptr))) return r;
-            if ((r = run_lanczos({&L}))) return r;
-            lata = L.theta;
-            steps_a = L.steps;
-            op->norm_ata = lata;
-            op->norm_ata_kmax = k.norm_steps;
-        }
+    if (op->norm_ata > 0.0 && op->norm_ata_kmax == k.norm_steps) {   // a property of the geometry
+        lata = op->norm_ata;
+    } else {
+        Lanczos L;
+        if ((r = setup_lambda_a(op, k.norm_steps, &L, false, nullptr))) return r;
+        if ((r = run_lanczos({&L}))) return r;
+        lata = L.theta;
+        steps_a = L.steps;
+        op->norm_ata = lata;
+        op->norm_ata_kmax = k.norm_steps;
+    }
+    {
         const double st = k.rho / std::sqrt(lata + 8.0);
         if (!(t > 0)) t = st;
         if (!(sg > 0)) sg = st;
+        if (!(sg * t * (lata + 8.0) < 1.0)) {
+            snprintf(g_errmsg, sizeof g_errmsg,
+                     "invalid argument: Chambolle-Pock steps s = %.6g, t = %.6g need s t (lambda_max(A^T A) + 8) < 1 "
+                     "(lambda_max(A^T A) = %.6g)",
+                     sg, t, lata);
+            return CTPD_EINVAL;
+        }
     }
     if ((r = sync(op))) return r;
     const double setup_ms = ms_since(t0);
@@ -1167,15 +1266,12 @@ int ctpd_cp_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
         std::swap(x, xn);
         if (k.record) {
             if ((r = project(op, x, op->q))) return r;
-            if ((r = reduce(op, RED_SQDIFF_F32, op->q, b, nullptr, I, 0))) return r;
-            HIP_TRY(launch_tv_norm(x, op->n, op->partials, op->cost_dev + 6 * it, s));
-            HIP_TRY(hipMemcpyAsync(op->cost_dev + 6 * it + 3, op->red, sizeof(double) * 3,
-                                   hipMemcpyDeviceToDevice, s));
+            if ((r = record_monitors(op, it, M, x, op->q, b, nullptr, nullptr))) return r;
         }
     }
     op->x = x;
     op->z = xn;
-    if ((r = finish(op, iters, false, 1.0, op->p[0], rep, x_out, k.record != 0))) return r;
+    if ((r = finish(op, iters, false, 1.0, op->p[0], rep, x_out, M))) return r;
     if (rep) {
         rep->tau = t;
         rep->sigma = sg;

@@ -270,18 +270,16 @@ int ctpd_batch_lowdose_solve(ctpd_batch* bt, const float* const* b, const float*
     // a1 / a2 for every problem; the operator-norm chains of all problems run together
     std::vector<LowdoseSetup> S(P);
     std::vector<Lanczos*> chains;
-    bool norms = false;
     for (int i = 0; i < P; ++i) {
         if ((r = lowdose_setup_begin(bt->ops[i], b[i], w[i], k, &S[i]))) return r;
-        norms = norms || S[i].norms;
-        if (S[i].norms && S[i].run_a) chains.push_back(&S[i].La);
+        if (S[i].run_a) chains.push_back(&S[i].La);
     }
     // lambda_A chains (first solve on the geometry only), one stream per problem
     if ((r = run_lanczos(chains))) return r;
     // per-view lambda_h chains of all problems together, on the batch stream
     for (int i = 0; i < P; ++i)
         if ((r = sync(bt->ops[i]))) return r;
-    if (norms) {
+    {
         std::vector<double> kap(P), lam(P);
         std::vector<int> st(P);
         for (int i = 0; i < P; ++i) kap[i] = S[i].kappa;
@@ -295,7 +293,7 @@ int ctpd_batch_lowdose_solve(ctpd_batch* bt, const float* const* b, const float*
         }
     }
     for (int i = 0; i < P; ++i) {
-        lowdose_setup_end(bt->ops[i], k, &S[i]);
+        if ((r = lowdose_setup_end(bt->ops[i], k, &S[i]))) return r;
         if ((r = sync(bt->ops[i]))) return r;
     }
     const double setup_ms = ms_since(t0);

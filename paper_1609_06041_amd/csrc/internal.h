@@ -262,10 +262,11 @@ enum ReduceOp : int {
     RED_SQ_F32 = 5,        // sum b^2                           (float)
     RED_DOT_F32 = 6,       // sum a[i]*b[i]                    (float)
     RED_SUM_F32 = 7,       // sum a[i]                          (float)
+    RED_GAP_F32 = 8,       // sum (c (a - b) - d)^2 / c         (float; a = A x, b, c = w, d = mu)
 };
 // Result (3 doubles: value, count1, count2) written to dev_out[0..2].
 hipError_t launch_reduce(int op, const void* a, const void* b, const void* c, size_t len,
-                         double* partials, double* dev_out, hipStream_t s);
+                         double* partials, double* dev_out, hipStream_t s, const void* d = nullptr);
 // TV norm of x [n][n] (float), float64 sum, into dev_out[0].
 hipError_t launch_tv_norm(const float* x, int n, double* partials, double* dev_out, hipStream_t s);
 constexpr int kReduceBlocks = 512;

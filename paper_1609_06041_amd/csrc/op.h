@@ -67,12 +67,13 @@ struct ctpd_op {
     int lz_cap = 0;
     hipStream_t aux = nullptr;
     hipEvent_t fork = nullptr;
-    // per-iteration monitor values (device), 2 * cost_cap slots of 3 doubles
+    // per-iteration monitor values (device), kMonSlots slots of 3 doubles per iteration
     double* cost_dev = nullptr;
     int cost_cap = 0;
-    // geometry-only operator norms (see ctpd_params.sigma): kappa * lambda_max(A^T D A)
-    // for the default low-dose tau, lambda_max(A^T D(1) A) for few-view; 0 = not yet
-    double norm_ld = 0.0, norm_fv = 0.0, norm_ata = 0.0;   // norm_ata: lambda_max(A^T A) (Chambolle-Pock)
+    // operator norms that depend on the geometry only (see ctpd_params.sigma):
+    // kappa * lambda_max(A^T D A) at a = 2 m tau / kappa (norm_ld_a), lambda_max(A^T D(1) A)
+    // for few-view, lambda_max(A^T A) (Chambolle-Pock, D = I); 0 = not yet computed
+    double norm_ld = 0.0, norm_ld_a = 0.0, norm_fv = 0.0, norm_ata = 0.0;
     int norm_ld_kmax = 0, norm_fv_kmax = 0, norm_ata_kmax = 0;
     // per-view lambda_h chains (allocated on first use): scalars per view and
     // step, and the one-problem tables the shared routine runs on
@@ -215,21 +216,46 @@ struct Knobs {
     int tv_iters, norm_steps, record;
 };
 
+// Per-iteration monitors a report asks for (float64 sums on the device).
+// Slots of 3 doubles per iteration in op->cost_dev:
+enum MonSlot : int {
+    MON_TV = 0,      // psi(x) (Eq. 2)
+    MON_DATA = 1,    // sum w (Ax - b)^2 (low-dose) or sum (Ax - b)^2 (few-view)
+    MON_GAP = 2,     // sum (w (Ax - b) - mu)^2 / w  (twice the partial gap)
+    MON_RES = 3,     // sum (Ax - b)^2
+    MON_RMSE = 4,    // sum (x - x_ref)^2
+    kMonSlots = 5,
+};
+struct Monitors {
+    bool cost = false, gap = false, resid = false, rmse = false;
+    const float* x_ref = nullptr;
+    double bnorm2 = 0.0;   // ||b||^2, for resid
+    bool any() const { return cost || gap || resid || rmse; }
+};
+
 int read_params(const ctpd_params* p, Knobs* k);
+// the monitors rep asks for (gap_ok: the solver defines the partial gap);
+// sets k->record when any is asked for
+int read_monitors(const ctpd_report* rep, bool gap_ok, Knobs* k, Monitors* M);
+// ||b||^2 into M->bnorm2 when resid is asked for (synchronises)
+int monitor_bnorm(ctpd_op* op, const float* b, Monitors* M);
+// queue the monitors of iteration `it`: x the iterate, q = A x, mu the new dual
+// (low-dose: w given)
+int record_monitors(ctpd_op* op, int it, const Monitors& M, const float* x, const float* q, const float* b,
+                    const float* w, const float* mu);
 int ensure_cost(ctpd_op* op, int iters);
 double ms_since(std::chrono::steady_clock::time_point t0);
 int finish(ctpd_op* op, int iters, bool lowdose, double beta, float* p_final, ctpd_report* rep, float* x_out,
-           bool recorded);
+           const Monitors& M);
 
 // Set-up of Algorithm 1 (see api.hip).
 constexpr double kTauMultLowdose = 0.3;   // default tau = 0.3 pi kappa / (2m)
 
 struct LowdoseSetup {
     double kappa = 0.0, tau = 0.0, sigma = 0.0, lam_a = 0.0, lam_h = 0.0;
+    double a = 0.0;         // 2 m tau / kappa: kappa * lambda_a depends on the geometry and a only
     int steps_a = 0, steps_h = 0;
-    bool norms = false;     // sigma from the norms
     bool run_a = false;     // lambda_a from the chain (else from the handle's cache)
-    bool cacheable = false; // default tau: kappa * lambda_a is a property of the geometry
     Lanczos La;
 };
 int lowdose_setup_begin(ctpd_op* op, const float* b, const float* w, const Knobs& k, LowdoseSetup* S);
@@ -246,7 +272,9 @@ int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, cons
                    hipStream_t s, ctpd::NormItem* items, ctpd::NormItem* items_host, const ctpd::RowRef* rows,
                    int nrows, const ctpd::BlockRef* filt, int nfilt, double* summary, double* summary_host,
                    const hipEvent_t* ev, double* lam, int* steps);
-void lowdose_setup_end(ctpd_op* op, const Knobs& k, LowdoseSetup* S);
+// lambda_a from the chain or the cache, then sigma: the default, or the given
+// one checked against the bound (CTPD_EINVAL when it violates it)
+int lowdose_setup_end(ctpd_op* op, const Knobs& k, LowdoseSetup* S);
 
 // Workgroup placement of batched launches: problems go to XCDs by work
 // (largest first onto the least-loaded XCD); placement 0 interleaves the XCD

@@ -34,7 +34,8 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c) {
 template <int OP>
 __global__ __launch_bounds__(256) void reduce_partial_kernel(const void* __restrict__ pa, const void* __restrict__ pb,
                                                              const void* __restrict__ pc, size_t len,
-                                                             double* __restrict__ partials) {
+                                                             double* __restrict__ partials,
+                                                             const void* __restrict__ pd = nullptr) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     const size_t stride = (size_t)gridDim.x * 256;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < len; i += stride) {
@@ -57,6 +58,12 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(const void* __restr
             s0 = fma((double)((const float*)pa)[i], (double)((const float*)pb)[i], s0);
         } else if constexpr (OP == RED_SUM_F32) {
             s0 += (double)((const float*)pa)[i];
+        } else if constexpr (OP == RED_GAP_F32) {
+            // (w r - mu)^2 / w = (W^1/2 r - W^-1/2 mu)^2 with r = A x - b
+            const double w = (double)((const float*)pc)[i];
+            const double d = w * ((double)((const float*)pa)[i] - (double)((const float*)pb)[i]) -
+                             (double)((const float*)pd)[i];
+            s0 += d * d / w;
         } else {   // RED_SQ_F32, counting non-finite entries
             const float v = ((const float*)pa)[i];
             if (isfinite(v)) s0 = fma((double)v, (double)v, s0);
@@ -93,9 +100,12 @@ __host__ __device__ static inline int reduce_blocks(size_t len) {
 }
 
 hipError_t launch_reduce(int op, const void* a, const void* b, const void* c, size_t len, double* partials,
-                         double* dev_out, hipStream_t s) {
+                         double* dev_out, hipStream_t s, const void* d) {
     const int nb = reduce_blocks(len);
     switch (op) {
+        case RED_GAP_F32:
+            reduce_partial_kernel<RED_GAP_F32><<<nb, 256, 0, s>>>(a, b, c, len, partials, d);
+            break;
         case RED_DOT_F64: reduce_partial_kernel<RED_DOT_F64><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
         case RED_INVW_CHECK: reduce_partial_kernel<RED_INVW_CHECK><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
         case RED_ABS_F32: reduce_partial_kernel<RED_ABS_F32><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;

@@ -93,7 +93,12 @@ class Report(ctypes.Structure):
     _fields_ = [("tau", c_double), ("sigma", c_double), ("kappa", c_double), ("lambda_a", c_double),
                 ("lambda_h", c_double), ("norm_steps_a", c_int32), ("norm_steps_h", c_int32),
                 ("iters_done", c_int32), ("reserved", c_int32), ("setup_ms", c_double), ("loop_ms", c_double),
-                ("cost", POINTER(c_double)), ("mu_out", c_void_p), ("p_out", c_void_p)]
+                ("cost", POINTER(c_double)), ("mu_out", c_void_p), ("p_out", c_void_p),
+                ("gap", POINTER(c_double)), ("resid", POINTER(c_double)), ("rmse", POINTER(c_double)),
+                ("x_ref", c_void_p)]
+
+
+MONITORS = ("gap", "resid", "rmse")
 
 
 _lib = None
@@ -232,13 +237,24 @@ class Operator:
         return out, p
 
     # -- solvers -------------------------------------------------------------
-    def _report(self, iters, record_cost, return_state):
+    def _report(self, iters, record_cost, return_state, monitors=(), x_ref=None):
+        """monitors: names from MONITORS to record per iteration; x_ref: the
+        reference image of the rmse monitor."""
         rep = Report()
         cost = None
         if record_cost and iters > 0:
             cost = np.zeros(iters, dtype=np.float64)
             rep.cost = cost.ctypes.data_as(POINTER(c_double))
         state = {}
+        for name in monitors:
+            if name not in MONITORS:
+                raise ValueError(f"unknown monitor {name!r}; choose from {MONITORS}")
+            arr = np.zeros(max(iters, 1), dtype=np.float64)
+            setattr(rep, name, arr.ctypes.data_as(POINTER(c_double)))
+            state[name] = arr
+        if x_ref is not None:
+            rep.x_ref = _ptr(x_ref, (self.n, self.n), "x_ref")
+            state["_x_ref"] = x_ref   # keeps the tensor alive for the call
         if return_state:
             state["mu"] = self._sino()
             state["p"] = torch.empty((2, self.n, self.n), dtype=torch.float32, device=self.device)
@@ -252,16 +268,17 @@ class Operator:
                                             "norm_steps_h", "iters_done", "setup_ms", "loop_ms")}
         if cost is not None:
             info["cost"] = cost
-        info.update(state)
+        info.update({k: v for k, v in state.items() if not k.startswith("_")})
         return info
 
     def lowdose_solve(self, b: torch.Tensor, w: torch.Tensor, beta: float, iters: int, *, tau=None, sigma=None,
                       tv_iters=10, tv_step=0.125, safety=0.95, norm_steps=100, record_cost=False,
-                      return_state=False, out: torch.Tensor | None = None):
+                      return_state=False, monitors=(), x_ref=None,
+                      out: torch.Tensor | None = None):
         """Algorithm 1 (beta > 0) / 1' (beta = 0).  Returns (x, info)."""
         out = self._img() if out is None else out
         prm = _params(tau, sigma, tv_iters, tv_step, safety, norm_steps, record_cost)
-        rep, cost, state = self._report(iters, record_cost, return_state)
+        rep, cost, state = self._report(iters, record_cost, return_state, monitors, x_ref)
         _check(load().ctpd_pd_lowdose_solve(self._h, _ptr(b, (self.m, self.nb), "b"),
                                             _ptr(w, (self.m, self.nb), "w"), float(beta), int(iters),
                                             byref(prm), _ptr(out, (self.n, self.n), "out"), byref(rep)))
@@ -269,11 +286,12 @@ class Operator:
 
     def app_identity_lowdose_solve(self, b: torch.Tensor, w: torch.Tensor, beta: float, iters: int, *, tau=None,
                                    sigma=None, tv_iters=10, tv_step=0.125, safety=0.95, norm_steps=100,
-                                   record_cost=False, return_state=False, out: torch.Tensor | None = None):
+                                   record_cost=False, return_state=False, monitors=(), x_ref=None,
+                                   out: torch.Tensor | None = None):
         """Algorithm 1 with D = I (the unpreconditioned ablation).  Returns (x, info)."""
         out = self._img() if out is None else out
         prm = _params(tau, sigma, tv_iters, tv_step, safety, norm_steps, record_cost)
-        rep, cost, state = self._report(iters, record_cost, return_state)
+        rep, cost, state = self._report(iters, record_cost, return_state, monitors, x_ref)
         _check(load().ctpd_app_identity_lowdose_solve(self._h, _ptr(b, (self.m, self.nb), "b"),
                                                       _ptr(w, (self.m, self.nb), "w"), float(beta), int(iters),
                                                       byref(prm), _ptr(out, (self.n, self.n), "out"), byref(rep)))
@@ -281,33 +299,36 @@ class Operator:
 
     def fewview_solve(self, b: torch.Tensor, iters: int, *, tau=None, sigma=None, tv_iters=10, tv_step=0.125,
                       safety=0.95, norm_steps=100, record_cost=False, return_state=False,
+                      monitors=(), x_ref=None,
                       out: torch.Tensor | None = None):
         """Algorithm 2.  Returns (x, info)."""
         out = self._img() if out is None else out
         prm = _params(tau, sigma, tv_iters, tv_step, safety, norm_steps, record_cost)
-        rep, cost, state = self._report(iters, record_cost, return_state)
+        rep, cost, state = self._report(iters, record_cost, return_state, monitors, x_ref)
         _check(load().ctpd_pd_fewview_solve(self._h, _ptr(b, (self.m, self.nb), "b"), int(iters), byref(prm),
                                             _ptr(out, (self.n, self.n), "out"), byref(rep)))
         return out, self._info(rep, cost, state)
 
     def gist_lowdose_solve(self, b: torch.Tensor, w: torch.Tensor, beta: float, iters: int, *, gamma=None,
                            lam=None, safety=0.95, norm_steps=100, record_cost=False, return_state=False,
+                           monitors=(), x_ref=None,
                            out: torch.Tensor | None = None):
         """GIST comparator for Eq. 1 (no preconditioner).  Returns (x, info); info['tau'] is gamma."""
         out = self._img() if out is None else out
         prm = _params(gamma, lam, 0, 0, safety, norm_steps, record_cost)
-        rep, cost, state = self._report(iters, record_cost, return_state)
+        rep, cost, state = self._report(iters, record_cost, return_state, monitors, x_ref)
         _check(load().ctpd_gist_lowdose_solve(self._h, _ptr(b, (self.m, self.nb), "b"),
                                               _ptr(w, (self.m, self.nb), "w"), float(beta), int(iters),
                                               byref(prm), _ptr(out, (self.n, self.n), "out"), byref(rep)))
         return out, self._info(rep, cost, state)
 
     def cp_fewview_solve(self, b: torch.Tensor, iters: int, *, t=None, s=None, safety=0.95, norm_steps=100,
-                         record_cost=False, return_state=False, out: torch.Tensor | None = None):
+                         record_cost=False, return_state=False, monitors=(), x_ref=None,
+                         out: torch.Tensor | None = None):
         """Chambolle-Pock comparator for the few-view problem.  Returns (x, info)."""
         out = self._img() if out is None else out
         prm = _params(t, s, 0, 0, safety, norm_steps, record_cost)
-        rep, cost, state = self._report(iters, record_cost, return_state)
+        rep, cost, state = self._report(iters, record_cost, return_state, monitors, x_ref)
         _check(load().ctpd_cp_fewview_solve(self._h, _ptr(b, (self.m, self.nb), "b"), int(iters), byref(prm),
                                             _ptr(out, (self.n, self.n), "out"), byref(rep)))
         return out, self._info(rep, cost, state)
@@ -463,3 +484,4 @@ class Batch:
         ms = c_double()
         _check(load().ctpd_batch_time_loop(self._h, int(iters), int(tv_iters), int(reps), byref(ms)))
         return ms.value
+

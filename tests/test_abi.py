@@ -36,7 +36,7 @@ def test_binding_struct_layouts_match_header():
     # field order / sizes as declared (ctypes follows the C ABI layout rules)
     assert ctypes.sizeof(ctpd.Geometry) == 4 * 4 + 8
     assert ctypes.sizeof(ctpd.Params) == 4 * 8 + 4 * 4
-    assert ctypes.sizeof(ctpd.Report) == 5 * 8 + 4 * 4 + 2 * 8 + 3 * 8
+    assert ctypes.sizeof(ctpd.Report) == 5 * 8 + 4 * 4 + 2 * 8 + 3 * 8 + 4 * 8
     text = open(HEADER).read()
     assert f"#define CTPD_MAX_BINS {ctpd.MAX_BINS}" in text
 

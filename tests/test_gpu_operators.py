@@ -45,23 +45,23 @@ GEOMS = [(1, 1, 1), (7, 5, 11), (64, 90, 96), (100, 36, 143), (129, 33, 200), (6
 
 
 @pytest.mark.parametrize("n,m,nb", GEOMS)
-def test_project_matches_oracle(gpu, n, m, nb):
+def test_project_matches_oracle(gpu, parity, n, m, nb):
     rng = np.random.default_rng(n + 7 * m + 13 * nb)
     x = f32(rng.random((n, n)))
     with ctpd.Operator(n, m, nb) as op:
         y = host(op.project(dev(x)))
     ref = OP.forward_project(x, m, nb)
-    assert rel(y, ref) <= TOL, rel(y, ref)
+    parity("y", rel(y, ref), TOL)
 
 
 @pytest.mark.parametrize("n,m,nb", GEOMS)
-def test_backproject_matches_oracle(gpu, n, m, nb):
+def test_backproject_matches_oracle(gpu, parity, n, m, nb):
     rng = np.random.default_rng(3 * n + m + nb)
     y = f32(rng.standard_normal((m, nb)))
     with ctpd.Operator(n, m, nb) as op:
         x = host(op.backproject(dev(y)))
     ref = OP.back_project(y, n)
-    assert rel(x, ref) <= TOL, rel(x, ref)
+    parity("x", rel(x, ref), TOL)
 
 
 def test_gpu_adjoint_identity(gpu):
@@ -76,7 +76,7 @@ def test_gpu_adjoint_identity(gpu):
     assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(ax) * np.linalg.norm(y)
 
 
-def test_phantom_projection_and_backprojection_full_size(gpu):
+def test_phantom_projection_and_backprojection_full_size(gpu, parity):
     # the 512^2 image, 720 views x 736 bins workload, whole outputs
     n, m, nb = 512, 720, 736
     prob = S.make_problem(1, 0, n, m, nb, 20, None, with_x_true=True)
@@ -85,8 +85,8 @@ def test_phantom_projection_and_backprojection_full_size(gpu):
     with ctpd.Operator(n, m, nb) as op:
         y = host(op.project(dev(x)))
         xb = host(op.backproject(dev(b)))
-    assert rel(y, OP.forward_project(x, m, nb)) <= TOL
-    assert rel(xb, OP.back_project(b, n)) <= TOL
+    parity("y", rel(y, OP.forward_project(x, m, nb)), TOL)
+    parity("xb", rel(xb, OP.back_project(b, n)), TOL)
 
 
 @pytest.mark.parametrize("m,nb,tau,kappa", [(90, 96, 1.0, 0.0), (90, 96, 2.8e-6, 1.6e-4), (720, 736, 0.01, 0.0),
@@ -100,19 +100,19 @@ def test_filter_taps_match_oracle(gpu, m, nb, tau, kappa):
 
 @pytest.mark.parametrize("m,nb,kappa", [(90, 96, 0.0), (90, 96, 1.6e-4), (720, 736, 0.0), (720, 736, 1.5e-5),
                                         (32, 736, 0.0), (5, 37, 0.02), (33, 65, 0.0), (1, 1, 0.1), (47, 130, 0.3)])
-def test_ramp_filter_matches_oracle(gpu, m, nb, kappa):
+def test_ramp_filter_matches_oracle(gpu, parity, m, nb, kappa):
     rng = np.random.default_rng(m * nb)
     s = f32(rng.standard_normal((m, nb)))
     tau = 0.7 if kappa == 0.0 else math.pi * kappa / (2 * m)
     with ctpd.Operator(8, m, nb) as op:
         out = host(op.ramp_filter(dev(s), tau, kappa))
     ref = OF.apply_filter(s, OF.smoothed_ramp_taps(nb, m, tau, kappa))
-    assert rel(out, ref) <= TOL, rel(out, ref)
+    parity("out", rel(out, ref), TOL)
 
 
 @pytest.mark.parametrize("m,nb,kappa", [(90, 96, 1.6e-4), (720, 736, 0.0), (5, 37, 0.02), (33, 65, 0.0),
                                         (1, 1, 0.1), (47, 130, 0.3)])
-def test_ramp_filter_f64_matches_oracle(gpu, m, nb, kappa):
+def test_ramp_filter_f64_matches_oracle(gpu, parity, m, nb, kappa):
     rng = np.random.default_rng(m * nb + 1)
     s = rng.standard_normal((m, nb))
     tau = 0.7 if kappa == 0.0 else math.pi * kappa / (2 * m)
@@ -121,10 +121,10 @@ def test_ramp_filter_f64_matches_oracle(gpu, m, nb, kappa):
         torch.cuda.synchronize()
         out = out.cpu().numpy()
     ref = OF.apply_filter(s, OF.smoothed_ramp_taps(nb, m, tau, kappa))
-    assert rel(out, ref) <= 1e-12, rel(out, ref)
+    parity("out", rel(out, ref), 1e-12)
 
 
-def test_ramp_filter_on_phantom_sinogram(gpu):
+def test_ramp_filter_on_phantom_sinogram(gpu, parity):
     n, m, nb = 512, 720, 736
     prob = S.make_problem(1, 0, n, m, nb, 20, 5e4, with_x_true=False)
     b = f32(prob.b)
@@ -133,7 +133,7 @@ def test_ramp_filter_on_phantom_sinogram(gpu):
     with ctpd.Operator(n, m, nb) as op:
         out = host(op.ramp_filter(dev(b), tau, kappa))
     ref = OF.apply_filter(b, OF.smoothed_ramp_taps(nb, m, tau, kappa))
-    assert rel(out, ref) <= TOL, rel(out, ref)
+    parity("out", rel(out, ref), TOL)
 
 
 def _unit_ball_field(rng, n):
@@ -144,7 +144,7 @@ def _unit_ball_field(rng, n):
 
 @pytest.mark.parametrize("n,lam,n_iter", [(7, 0.05, 1), (64, 0.05, 10), (129, 2e-3, 10), (64, 0.0, 10),
                                           (100, 0.3, 25), (1, 0.1, 3)])
-def test_tv_prox_matches_oracle(gpu, n, lam, n_iter):
+def test_tv_prox_matches_oracle(gpu, parity, n, lam, n_iter):
     rng = np.random.default_rng(n + n_iter)
     z = np.zeros((n, n))
     z[n // 4:3 * n // 4, n // 3:2 * n // 3] = 1.0
@@ -155,8 +155,8 @@ def test_tv_prox_matches_oracle(gpu, n, lam, n_iter):
         x, pd = op.tv_prox(dev(z), lam, pd, n_iter=n_iter)
         x, p = host(x), host(pd)
     xr, p1, p2 = OT.tv_prox(z, lam, p0[0].copy(), p0[1].copy(), n_iter)
-    assert rel(x, xr) <= TOL, rel(x, xr)
-    assert rel(p, np.stack([p1, p2])) <= TOL
+    parity("x", rel(x, xr), TOL)
+    parity("p", rel(p, np.stack([p1, p2])), TOL)
     assert x.min() >= 0.0
 
 
@@ -171,7 +171,7 @@ ANGLE_SETS = {
 
 
 @pytest.mark.parametrize("name", sorted(ANGLE_SETS))
-def test_project_and_backproject_with_given_angles_match_oracle(gpu, name):
+def test_project_and_backproject_with_given_angles_match_oracle(gpu, parity, name):
     n, m, nb, th = ANGLE_SETS[name]
     rng = np.random.default_rng(m)
     x = f32(rng.random((n, n)))
@@ -179,8 +179,8 @@ def test_project_and_backproject_with_given_angles_match_oracle(gpu, name):
     with ctpd.Operator(n, m, nb, angles=th) as op:
         y = host(op.project(dev(x)))
         xb = host(op.backproject(dev(yb)))
-    assert rel(y, OP.forward_project(x, m, nb, theta=th)) <= TOL
-    assert rel(xb, OP.back_project(yb, n, theta=th)) <= TOL
+    parity("y", rel(y, OP.forward_project(x, m, nb, theta=th)), TOL)
+    parity("xb", rel(xb, OP.back_project(yb, n, theta=th)), TOL)
 
 
 def test_uniform_angles_given_equal_the_default_scan(gpu):
