@@ -23,9 +23,13 @@ readability against the paper rather than speed:
 * ``app``       - step sizes (Eq. 16, Algorithms 1 and 2) from the largest
                   eigenvalues of the preconditioned operators,
                   Algorithm 1 / 1' (low-dose) and Algorithm 2 (few-view),
-                  cost (Eq. 1), partial primal-dual gap, RMSE (Eq. 34)
+                  cost (Eq. 1), partial primal-dual gap, RMSE (Eq. 34), and
+                  the error-tolerant few-view problem the conclusions name
+                  (||Ax - b|| <= eps) by the same APP iteration on a split
+                  primal variable (x, y)
 * ``comparators`` - the unpreconditioned comparators of Sec. 4: GIST for
-                  Eq. 1 and Chambolle-Pock for the few-view problem
+                  Eq. 1 and Chambolle-Pock for the few-view problem (with
+                  Ax = b, or with ||Ax - b|| <= eps)
 * ``unrolled``  - Algorithm 1 unrolled for a fixed number of iterations as a
                   function of (b, beta, tau, sigma), and its float64
                   central-difference gradient

@@ -261,3 +261,101 @@ def rmse(x, x_true):
     """Eq. 34."""
     d = np.asarray(x, dtype=np.float64) - np.asarray(x_true, dtype=np.float64)
     return float(np.sqrt((d * d).mean()))
+
+
+# ---------------------------------------------------------------------------
+# The error-tolerant few-view problem the conclusions name (Sec. 5):
+#     min psi(x)  s.t.  ||A x - b|| <= eps,  x >= 0.
+#
+# Reading (the paper states only the problem): it is posed like Eq. 6 - Eq. 7
+# for the low-dose problem -- a variable y standing for the projection data,
+# the preconditioned equality constraint D^1/2 (A x - y) = 0, and the data term
+# on y, here the indicator of the ball B(b, eps) = {y : ||y - b|| <= eps}.  The
+# primal variable is the pair (x, y) with g(x, y) = psi(x) + i(x) + i_B(y) and
+# h(mu) = 0 (no term of mu alone remains), so APP's primal prox splits into the
+# TV prox of Eq. 17 (lambda = tau) and the Euclidean projection onto the ball,
+# and its dual gradient step is the plain ascent step.  After the variable
+# change mu <- D^T/2 mu, as in Eqs. 18-20 and 29-31:
+#     mubar^{k+1} = mu^k + sigma D (A x^k - y^k)      (= 2 mu^k - mu^{k-1} for k >= 1;
+#                                                      = -sigma D b at k = 0, with y^0 = b)
+#     x^{k+1}    = prox_{tau g}(x^k - tau A^T mubar^{k+1})
+#     y^{k+1}    = P_B(y^k + tau mubar^{k+1})
+#     mu^{k+1}   = mu^k + sigma D (A x^{k+1} - y^{k+1})
+# Convergence (Eq. 16 with K = [A, -I]): sigma tau ||D^1/2 (A A^T + I) D^T/2|| < 1.
+# D is the ramp of Eq. 32; with D(tau) = D(1)/tau the bound reads
+# sigma lambda_max(K^T D(1) K) < 1 whatever tau is.  eps = 0 keeps y = b and
+# gives Algorithm 2 exactly.
+# ---------------------------------------------------------------------------
+
+def ball_projection(v, b, eps):
+    """Euclidean projection of v onto {y : ||y - b|| <= eps}."""
+    d = v - b
+    r = float(np.sqrt((d * d).sum()))
+    return v.copy() if r <= eps else b + d * (eps / r)
+
+
+def lambda_a_split(n, m, nb, h, theta=None):
+    """lambda_max(K^T D K) for K = [A, -I] acting on (x, y): the norm of the
+    preconditioned constraint operator D^1/2 [A, -I] squared."""
+    J = n * n
+
+    def op(v):
+        x, y = v[:J].reshape(n, n), v[J:].reshape(m, nb)
+        s = apply_filter(forward_project(x, m, nb, theta=theta) - y, h)
+        return np.concatenate([back_project(s, n, theta=theta).ravel(), -s.ravel()])
+
+    return lambda_max(op, J + m * nb)
+
+
+def steps_fewview_eps(b, n, tau=None, rho=0.95):
+    """sigma = rho / lambda_max(K^T D(1) K); default tau = mean |sigma A^T D(1) b| (as Algorithm 2)."""
+    b = np.asarray(b, dtype=np.float64)
+    m, nb = b.shape
+    h1 = ramp_taps(nb, m, 1.0)
+    la1 = lambda_a_split(n, m, nb, h1)
+    sigma = rho / la1
+    if tau is None:
+        tau = TAU_MULT_FEWVIEW * float(np.abs(sigma * back_project(apply_filter(b, h1), n)).mean())
+    return Steps(tau=tau, sigma=sigma, kappa=0.0, lambda_a=la1 / tau, lambda_h=0.0)
+
+
+@dataclass
+class EpsResult:
+    x: np.ndarray
+    y: np.ndarray
+    mu: np.ndarray
+    mu_prev: np.ndarray
+    p1: np.ndarray
+    p2: np.ndarray
+    history: list = field(default_factory=list)
+
+
+def fewview_eps_solve(b, n, eps, iters, tau=None, sigma=None, n_tv=10, tau_c=0.125, rho=0.95, monitor=None):
+    """The error-tolerant few-view iteration above from x = 0, y = b, mu = 0.
+    Returns (EpsResult, Steps); monitor(x, y, mu) is recorded per iteration."""
+    b = np.asarray(b, dtype=np.float64)
+    m, nb = b.shape
+    if sigma is None or tau is None:
+        st = steps_fewview_eps(b, n, tau, rho)
+        if sigma is not None:
+            st.sigma = sigma
+    else:
+        st = Steps(tau=tau, sigma=sigma)
+    tau, sigma = st.tau, st.sigma
+    h = ramp_taps(nb, m, tau)
+    D = lambda s: apply_filter(s, h)
+    x = np.zeros((n, n))
+    y = b.copy()
+    mu = np.zeros((m, nb))
+    mu_prev = np.zeros((m, nb))
+    p1 = np.zeros((n, n))
+    p2 = np.zeros((n, n))
+    hist = []
+    for k in range(iters):
+        mubar = mu + sigma * D(forward_project(x, m, nb) - y) if k == 0 else 2.0 * mu - mu_prev
+        x, p1, p2 = tv_prox(x - tau * back_project(mubar, n), tau, p1, p2, n_tv, tau_c)
+        y = ball_projection(y + tau * mubar, b, eps)
+        mu_prev, mu = mu, mu + sigma * D(forward_project(x, m, nb) - y)
+        if monitor is not None:
+            hist.append(monitor(x, y, mu))
+    return EpsResult(x=x, y=y, mu=mu, mu_prev=mu_prev, p1=p1, p2=p2, history=hist), st

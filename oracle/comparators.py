@@ -130,3 +130,34 @@ def cp_fewview(b, n, iters, s, t, monitor=None):
         if monitor is not None:
             hist.append(monitor(x))
     return x, (y1, q1, q2), hist
+
+
+def _shrink(u, t):
+    """u max(0, 1 - t / ||u||): the prox of t ||.|| (Euclidean norm of the whole array)."""
+    r = float(np.sqrt((u * u).sum()))
+    return np.zeros_like(u) if r <= t else u * (1.0 - t / r)
+
+
+def cp_fewview_eps(b, n, eps, iters, s, t, monitor=None):
+    """Chambolle-Pock for min TV s.t. ||Ax - b|| <= eps, x >= 0: the same
+    iteration as ``cp_fewview`` with the data block's dual prox for the ball
+    indicator, prox of s (y^T b + eps ||y||) = shrink(v - s b, s eps); eps = 0
+    gives ``cp_fewview``.  Returns (x, (y1, q1, q2), history)."""
+    b = np.asarray(b, dtype=np.float64)
+    m, nb = b.shape
+    x = np.zeros((n, n))
+    xb = np.zeros((n, n))
+    y1 = np.zeros((m, nb))
+    q1 = np.zeros((n, n))
+    q2 = np.zeros((n, n))
+    hist = []
+    for _ in range(iters):
+        y1 = _shrink(y1 + s * (forward_project(xb, m, nb) - b), s * eps)
+        g1, g2 = grad(xb)
+        q1, q2 = _ball(q1 + s * g1, q2 + s * g2, 1.0)
+        xo = x
+        x = np.maximum(0.0, x - t * (back_project(y1, n) - div(q1, q2)))
+        xb = 2.0 * x - xo
+        if monitor is not None:
+            hist.append(monitor(x))
+    return x, (y1, q1, q2), hist
