@@ -15,9 +15,17 @@ per second over the whole job (20 * steps / elapsed).  Also reported: the iterat
 throughput in G(pixel, view) updates/s, the filter's matrix-core rate, the
 TV step's bandwidth, the roofline of the dominant kernel (A, the forward
 projector; A^T's is reported beside it), and the FP64 oracle timed on the host
-on a bounded sample of the same workload.
+on a bounded sample of the same workload (one BLAS thread, then all host
+cores).
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline]
+The same line carries the rest of the metric: the few-view workload (512^2,
+32 views: A, A^T and Algorithm-2 iterations/s), the batched uneven workload
+(64 problems of 256^2-512^2 and 32-720 views solved as one batch vs one after
+another) and the unrolled differentiable solve (16 x 256^2, 180 views, 10
+iterations, forward + reverse pass for all problems in one call vs one problem
+at a time, and vs 16 plain solves).
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline] [--no-extras]
 """
 from __future__ import annotations
 
@@ -120,10 +128,12 @@ def time_op(fn, stream, reps: int, warm: int = 5) -> float:
     return e0.elapsed_time(e1) / reps
 
 
-def cpu_baseline(b64, w64, beta, n, m, nb, tau, sigma, stride: int = 4) -> dict:
+def cpu_baseline(b64, w64, beta, n, m, nb, tau, sigma, stride: int = 4, threads: int = 1) -> dict:
     """The FP64 oracle, as it stands, timed for one Algorithm-1 iteration of the
     same workload on a bounded sample: A and A^T over every ``stride``-th view
-    (scaled by ``stride``), D, the TV prox and the pointwise steps in full."""
+    (scaled by ``stride``), D, the TV prox and the pointwise steps in full.
+    ``threads`` caps the BLAS thread pool; only the filter's matrix product
+    uses it (the projector and TV loops are single-threaded NumPy)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -138,7 +148,7 @@ def cpu_baseline(b64, w64, beta, n, m, nb, tau, sigma, stride: int = 4) -> dict:
     x = np.abs(rng.standard_normal((n, n))) * 1e-3
     mu = 1e-3 * rng.standard_normal((m, nb))
     mup = 1e-3 * rng.standard_normal((m, nb))
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=threads):
         t0 = time.perf_counter()
         h = OF.smoothed_ramp_taps(nb, m, tau, kappa)
         t_taps = time.perf_counter() - t0
@@ -159,10 +169,10 @@ def cpu_baseline(b64, w64, beta, n, m, nb, tau, sigma, stride: int = 4) -> dict:
         t_d2 = time.perf_counter() - t0
     it_s = t_d1 + t_at + t_tv + t_a + t_d2
     return {
-        "value": 1.0 / it_s, "unit": "PD iters/s", "cores": 1, "kind": "oracle",
-        "sample": (f"one Algorithm-1 iteration of the same 512^2/720x736 workload in float64 NumPy, one "
-                   f"thread: A and A^T on every {stride}th view ({len(views)} of {m}) scaled x{stride}, "
-                   f"D twice, 10 TV steps and the pointwise steps in full"),
+        "value": 1.0 / it_s, "unit": "PD iters/s", "cores": threads, "kind": "oracle",
+        "sample": (f"one Algorithm-1 iteration of the same 512^2/720x736 workload in float64 NumPy, "
+                   f"{threads} BLAS thread(s): A and A^T on every {stride}th view ({len(views)} of {m}) "
+                   f"scaled x{stride}, D twice, 10 TV steps and the pointwise steps in full"),
         "seconds_per_iteration": it_s,
         "parts_s": {"A": t_a, "AT": t_at, "D": t_d1 + t_d2, "tv_prox": t_tv, "taps_setup": t_taps},
         "host_cpus": os.cpu_count(),
@@ -249,6 +259,12 @@ def compare(dev) -> int:
 
 
 def batch_speedup(dev, count: int, steps: int, warmup: int) -> int:
+    out = batch_measure(dev, count, steps, warmup)
+    print(json.dumps(out), flush=True)
+    return 0 if out["results_identical_to_sequential"] else 1
+
+
+def batch_measure(dev, count: int, steps: int, warmup: int) -> dict:
     """Batched uneven workload: one batched solve (set-up of every problem, then
     the 20-iteration loop of all problems as one graph replay) against the
     per-problem solver called once per problem."""
@@ -323,11 +339,15 @@ def batch_speedup(dev, count: int, steps: int, warmup: int) -> int:
         "tiles": tuned["tiles"], "autotune_ms": tuned.get("timings_ms"),
         "results_identical_to_sequential": identical,
     }
-    print(json.dumps(out), flush=True)
-    return 0 if identical else 1
+    return out
 
 
 def unrolled_speedup(dev, steps: int) -> int:
+    print(json.dumps(unrolled_measure(dev, steps)), flush=True)
+    return 0
+
+
+def unrolled_measure(dev, steps: int) -> dict:
     """16 independent 256^2 / 180-view problems, 10 unrolled iterations: forward
     and forward + reverse pass (the many-problem calls, each problem on its own
     stream) against 16 plain solves of the same 10 iterations and against the
@@ -413,8 +433,38 @@ def unrolled_speedup(dev, steps: int) -> int:
                        "(tests/test_gpu_unrolled.py)"}
     for op in ops:
         op.close()
-    print(json.dumps(out), flush=True)
-    return 0
+    return out
+
+
+def fewview_measure(dev, reps: int) -> dict:
+    """The few-view workload (512^2, 32 views x 736 bins, noiseless): A and A^T
+    per call, and Algorithm 2's iteration rate (20 iterations, default set-up,
+    loop time from the solver's report, median of 5 solves)."""
+    import numpy as np
+    import torch
+
+    from paper_1609_06041_amd import ctpd, synth
+
+    prob, spec = synth.workload_problem("fewview_512", with_x_true=False)
+    n, m, nb = spec["n"], spec["m"], spec["nb"]
+    b = torch.from_numpy(np.asarray(prob.b, np.float32)).to(dev)
+    with ctpd.Operator(n, m, nb) as op:
+        img = torch.rand((n, n), device=dev, dtype=torch.float32)
+        sino = torch.empty((m, nb), device=dev, dtype=torch.float32)
+        img_out = torch.empty((n, n), device=dev, dtype=torch.float32)
+        t_a = time_op(lambda: op.project(img, out=sino), op.stream, reps)
+        t_at = time_op(lambda: op.backproject(b, out=img_out), op.stream, reps)
+        _, cold = op.fewview_solve(b, 20)
+        infos = [op.fewview_solve(b, 20)[1] for _ in range(5)]
+    loop_ms = float(np.median([i["loop_ms"] for i in infos]))
+    setup_ms = float(np.median([i["setup_ms"] for i in infos]))
+    updates = float(m) * n * n
+    return {"workload": "fewview_512", "image": f"{n}x{n}", "views": m, "bins": nb,
+            "A_ms": t_a, "AT_ms": t_at, "A_gupdates_per_s": updates / (t_a * 1e-3) / 1e9,
+            "AT_gupdates_per_s": updates / (t_at * 1e-3) / 1e9,
+            "algorithm2_iters": 20, "algorithm2_loop_ms": loop_ms, "algorithm2_setup_ms": setup_ms,
+            "algorithm2_setup_ms_cold": cold["setup_ms"],
+            "algorithm2_loop_iters_per_s": 20.0 / (loop_ms * 1e-3)}
 
 
 def main() -> int:
@@ -424,6 +474,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--op-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="leave out the few-view, batched and unrolled measurements of the default line")
     ap.add_argument("--compare", action="store_true",
                     help="instead of the throughput line: Algorithm 1 vs 1000 GIST iterations (lowdose_512) and "
                          "Algorithm 2 vs 1000 Chambolle-Pock iterations (fewview_512), iterations to match")
@@ -522,7 +574,8 @@ def main() -> int:
     peak_note = ("FP32 vector peak: 256 CU x 128 FMA lanes x 2.4 GHz x 2 (plain v_fma_f32 exceeds 64 lanes/CU/clock "
                  "on gfx950: a register-only FMA loop reaches 95 TFLOP/s)")
     rec = {
-        "metric": "512x512/720-view PD iters/s (Algorithm 1, set-up included) + A, A^T Gupdates/s",
+        "metric": "512x512/720-view PD iters/s (Algorithm 1, set-up included) + A, A^T Gupdates/s; "
+                  "batched & unrolled-grad speedup",
         "value": value,
         "unit": "PD iters/s",
         "n_gpus": 1,
@@ -568,12 +621,29 @@ def main() -> int:
         "paper_context": "paper (no hardware stated): ~10 Algorithm-1 iterations match GIST at 1000; "
                          "3 Algorithm-2 iterations match Chambolle-Pock at 1000",
     }
+    op.close()
+    if not args.no_extras:
+        log("few-view workload: A, A^T and Algorithm-2 iterations")
+        rec["fewview_512"] = fewview_measure(dev, reps)
+        log("batched uneven workload (64 problems): batched vs one after another")
+        rec["batched"] = batch_measure(dev, 64, 3, 1)
+        log("unrolled differentiable solve (16 x 256^2, 180 views, 10 iterations)")
+        rec["unrolled"] = unrolled_measure(dev, 3)
+        rec["speedups"] = {
+            "batched_vs_sequential_total": rec["batched"]["speedup_total"],
+            "batched_vs_sequential_loop_graph_replay": rec["batched"]["speedup_loop_graph_replay"],
+            "unrolled_fwd_bwd_concurrent_vs_sequential": rec["unrolled"]["speedup_concurrent_vs_sequential"],
+            "unrolled_fwd_bwd_over_plain_solves": rec["unrolled"]["forward_backward_over_plain"],
+        }
     if not args.no_cpu_baseline:
-        log("timing the FP64 oracle on a bounded sample (cpu_baseline)")
         b64 = b32.astype(np.float64)
         w64 = w32.astype(np.float64)
+        log("timing the FP64 oracle on a bounded sample, one thread (cpu_baseline)")
         rec["cpu_baseline"] = cpu_baseline(b64, w64, beta, n, m, nb, last["tau"], last["sigma"])
-    op.close()
+        ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        log(f"timing the FP64 oracle on the same sample with {ncpu} BLAS threads")
+        rec["cpu_baseline_all_cores"] = cpu_baseline(b64, w64, beta, n, m, nb, last["tau"], last["sigma"],
+                                                     threads=ncpu)
     print(json.dumps(rec), flush=True)
     return 0
 

@@ -268,8 +268,8 @@ int filter(ctpd_op* op, int mode, const float* in0, const float* in1, const floa
 int project_resid(ctpd_op* op, const float* x, const float* rb, const float* rw, const float* rm, float* y,
                   bool padded) {
     if (!padded) HIP_TRY(launch_pad_planes<float>(x, op->xp, op->xTp, op->n, op->stream));
-    HIP_TRY(launch_forward_slab(op->xp, op->xTp, y, op->views, op->fwd_tasks, op->fwd_groups, op->n, op->nb, rb, rw,
-                                rm, op->stream));
+    HIP_TRY(launch_forward_auto(op->xp, op->xTp, y, op->views, op->fwd_tasks, op->fwd_groups, op->n, op->m, op->nb,
+                                rb, rw, rm, op->stream));
     return CTPD_OK;
 }
 
@@ -707,11 +707,11 @@ int ctpd_op_create(const ctpd_geometry* g, void* stream, ctpd_op** out) {
         ALLOC(op->fwd_tasks, tasks.size());
         HIP_TRY(hipMemcpy(op->fwd_tasks, tasks.data(), sizeof(int) * tasks.size(), hipMemcpyHostToDevice));
         op->fwd_groups = (int)(tasks.size() / forward_slab_tasks_per_group());
-        ALLOC(op->xp, op->Jp);
-        ALLOC(op->xTp, op->Jp);
+        ALLOC(op->xp, op->Jp + kPlaneSlack);
+        ALLOC(op->xTp, op->Jp + kPlaneSlack);
         // the planes' pad columns stay zero for good: only interiors are written after this
-        HIP_TRY(hipMemset(op->xp, 0, sizeof(float) * op->Jp));
-        HIP_TRY(hipMemset(op->xTp, 0, sizeof(float) * op->Jp));
+        HIP_TRY(hipMemset(op->xp, 0, sizeof(float) * (op->Jp + kPlaneSlack)));
+        HIP_TRY(hipMemset(op->xTp, 0, sizeof(float) * (op->Jp + kPlaneSlack)));
         ALLOC(op->x, op->J);
         ALLOC(op->z, op->J);
         for (auto& p : op->p) ALLOC(p, 2 * op->J);
@@ -1019,13 +1019,14 @@ int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
     }
     double tau = k.tau;
     if (!(tau > 0)) {
-        // tau = mean |sigma A^T D(1) b|
+        // tau = mean |sigma A^T D(1) b|, a step size: formed in float64 like the norms
         if ((r = ensure_taps(op, 1.0, 0.0))) return r;
-        if ((r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, 1.f, op->q)))
-            return r;
-        HIP_TRY(launch_adjoint<float>(op->q, nullptr, 1.f, 0.f, nullptr, 0.f, 1.f, op->z, op->views, op->n, op->m,
-                                      op->nb, s));
-        if ((r = reduce(op, RED_ABS_F32, op->z, nullptr, nullptr, J, 0))) return r;
+        if ((r = ensure_f64(op))) return r;
+        HIP_TRY(launch_widen_f64(op->sino64[0], b, I, s));
+        HIP_TRY(launch_filter_f64(op->sino64[0], op->sino64[1], op->taps64, nullptr, nullptr, op->m, op->nb, s));
+        HIP_TRY(launch_adjoint<double>(op->sino64[1], nullptr, 1.0, 0.0, nullptr, 0.0, 1.0, op->img64[0], op->views,
+                                       op->n, op->m, op->nb, s));
+        if ((r = reduce(op, RED_ABS_F64, op->img64[0], nullptr, nullptr, J, 0))) return r;
         if ((r = read_red(op))) return r;
         tau = sigma * op->red_host[0] / (double)J;
         if (!(tau > 0)) tau = 1.0;   // all-zero data: any tau works

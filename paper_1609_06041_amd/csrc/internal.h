@@ -178,13 +178,21 @@ hipError_t launch_forward_resid(const float* xp, const float* xTp, float* y, con
 // The same projection (and optional residual epilogue) in slab form, for one
 // float32 problem: tasks holds ngroups groups of forward_slab_tasks_per_group()
 // entries view * 64 + (64-bin block), each group of one orientation, -1 for
-// none, the first entry of a group never -1.  Bit-identical to launch_forward /
-// launch_forward_resid.
+// none, the first entry of a group never -1.  The planes need 16 bytes of
+// slack after their end.  Bit-identical to launch_forward / launch_forward_resid.
 hipError_t launch_forward_slab(const float* xp, const float* xTp, float* y, const ViewGeom* views, const int* tasks,
                                int ngroups, int n, int nb, const float* rb, const float* rw, const float* rm,
                                hipStream_t s);
-int forward_slab_rows(int n);
+// the slab form when the geometry fills the chip with its groups (tasks may be
+// null: never), else the split form (few views), else the gather form; all
+// bit-identical
+hipError_t launch_forward_auto(const float* xp, const float* xTp, float* y, const ViewGeom* views, const int* tasks,
+                               int ngroups, int n, int m, int nb, const float* rb, const float* rw, const float* rm,
+                               hipStream_t s);
+bool forward_slab_fits(int n);
 int forward_slab_tasks_per_group();
+// floats of slack after each padded plane (the slab form copies 16-byte words)
+constexpr size_t kPlaneSlack = 4;
 // out = alpha * xin + beta * A^T (c1 * y1 + c2 * y2)   (xin, y2 may be null)
 template <typename T>
 hipError_t launch_adjoint(const T* y1, const T* y2, T c1, T c2, const T* xin, T alpha, T beta, T* out,
@@ -263,6 +271,7 @@ enum ReduceOp : int {
     RED_DOT_F32 = 6,       // sum a[i]*b[i]                    (float)
     RED_SUM_F32 = 7,       // sum a[i]                          (float)
     RED_GAP_F32 = 8,       // sum (c (a - b) - d)^2 / c         (float; a = A x, b, c = w, d = mu)
+    RED_ABS_F64 = 9,       // sum |a[i]|                        (double)
 };
 // Result (3 doubles: value, count1, count2) written to dev_out[0..2].
 hipError_t launch_reduce(int op, const void* a, const void* b, const void* c, size_t len,
@@ -290,6 +299,8 @@ hipError_t launch_scale_f64(double* y, const double* x, double a, size_t len, hi
 hipError_t launch_lin3_f32(float* out, const float* a, float c0, const float* b, float c1, const float* c, float c2,
                            const float* w, size_t len, hipStream_t s);
 hipError_t launch_mul_w_f64(double* out, const double* a, const float* w, size_t len, hipStream_t s);
+// out = (double) a
+hipError_t launch_widen_f64(double* out, const float* a, size_t len, hipStream_t s);
 // batched solve: zero x, p[0], mu[0], mu[1] of every problem / copy x to x_out
 // (2048 elements per workgroup)
 hipError_t launch_batch_init(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s);

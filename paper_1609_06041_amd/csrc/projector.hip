@@ -8,6 +8,7 @@
 // relative error on non-smooth images; the float64 position costs a few
 // full-rate DP instructions per sample on CDNA.
 #include <algorithm>
+#include <mutex>
 
 #include "internal.h"
 
@@ -70,22 +71,31 @@ hipError_t launch_pad_planes(const T* x, T* xp, T* xTp, int n, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Forward projection: one lane per ray (v, u), 256 consecutive bins of one
-// view per workgroup, so at each step a wave reads a short contiguous run of
-// one padded row (row views) or padded column (column views).
+// Forward projection: one lane per ray (v, u).  A wave holds the rays of 64
+// consecutive bins of one view and steps through the union of their step
+// ranges together (the row offset is then a scalar); a lane outside its own
+// range clamps its column into the zero pad (one unsigned min: negative
+// columns wrap to the right pad) and so adds exact zeros.
 //
-// The wave steps through the union of its rays' step ranges together (the
-// row offset is then a scalar), and each lane carries its sample position in
-// 32.32 fixed point, biased by FP_PAD so that the integer part is the padded
-// column: one 64-bit add per step, the fraction converted straight from the
-// low word.  The per-step increment is rounded to 2^-32 pixel, so after n
-// steps the position is off by at most n * 2^-33 -- far below float32
-// resolution.  A lane outside its own range clamps its column into the zero
-// pad (one unsigned min: negative columns wrap to the right pad), so it adds
-// exact zeros.  Taps are fetched with raw buffer loads: 32-bit lane offset,
-// scalar row offset, both taps in one 8-byte (16-byte for float64) load.
+// Positions are 32.32 fixed point, biased by FP_PAD so that the integer part
+// is the padded column, and are defined per segment of FW_SEG rows: at row t
+// of the segment that starts at row s0 the position is
+//     S + (t - s0) d   (mod 2^64),   S = round((s0 st + base + FP_PAD) 2^32),
+// d = round(st 2^32), with S and d from float64 -- exact integer arithmetic,
+// so every form computes the same positions whatever order it visits the rows
+// in (rounding of d adds at most FW_SEG 2^-33 pixel).  A ray's sum is formed
+// per segment in row order from zero, and the segment sums are added in
+// segment order; segments with no step of the wave's range are skipped, and
+// out-of-range steps add exact zeros.  The gather, split and slab forms below
+// all follow this, so their results are equal bit for bit.
 typedef float v2f_t __attribute__((ext_vector_type(2)));
 typedef double v2d_t __attribute__((ext_vector_type(2)));
+
+constexpr int FW_SEG = 32;
+
+__device__ __forceinline__ unsigned long long seg_position(double base, double st, int s0) {
+    return (unsigned long long)llrint((fma((double)s0, st, base) + FP_PAD) * 4294967296.0);
+}
 
 __device__ __forceinline__ void load_taps(const __amdgpu_buffer_rsrc_t& rs, unsigned voff, int soff, float& a,
                                           float& b) {
@@ -105,8 +115,6 @@ __device__ __forceinline__ void load_taps(const __amdgpu_buffer_rsrc_t& rs, unsi
 constexpr int kBufferRsrcWord3 = 0x00020000;
 constexpr int FW_BATCH = 8;
 
-// rb (optional): write the residual A x - rb - rw .* rm (rw null: A x - rb)
-// instead of A x, with the arithmetic of the filter prologues.
 // Ray u of view g: its sample position at step 0 (base; rays past the last
 // bin reuse the last bin's) and the steps [t0, t1] whose sample lies within
 // one step of (-1, n), as the union over the wave (wave-uniform; empty when
@@ -136,28 +144,15 @@ __device__ __forceinline__ void wave_ray_span(const ViewGeom& g, int u, int n, i
     t1 = __builtin_amdgcn_readfirstlane(t1);
 }
 
-template <typename T, int FB = FW_BATCH>
-__device__ __forceinline__ void forward_body(const T* __restrict__ xp, const T* __restrict__ xTp, T* __restrict__ y,
-                                             const ViewGeom* __restrict__ views, int n, int nb, int bxi, int v,
-                                             const T* __restrict__ rb = nullptr, const T* __restrict__ rw = nullptr,
-                                             const T* __restrict__ rm = nullptr) {
-    const int u = bxi * 256 + threadIdx.x;
-    const ViewGeom g = views[v];
-    const int P = n + 2 * FP_PAD;
-    double base;
-    int t0, t1;
-    wave_ray_span(g, u, n, nb, base, t0, t1);
-    const double two32 = 4294967296.0;
-    unsigned long long sfix = (unsigned long long)llrint((fma((double)t0, g.st, base) + FP_PAD) * two32);
-    const unsigned long long dfix = (unsigned long long)llrint(g.st * two32);
-    const unsigned cmax = (unsigned)(P - 2);
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)(g.row ? xp : xTp), (short)0, (int)((size_t)n * P * sizeof(T)), kBufferRsrcWord3);
-    const int rowstride = P * (int)sizeof(T);
-    int rowb = t0 * rowstride;
-    T acc_a = T(0), acc_d = T(0);   // sum of left taps, sum of low-word * (right - left)
-    int t = t0;
-    for (; t + FB - 1 <= t1; t += FB) {
+// Steps [ta, tb] of one segment through raw buffer loads of both taps (8
+// bytes, 16 for float64) of the padded plane; acc_a sums the left taps and
+// acc_d the low position word times (right - left).
+template <typename T, int FB>
+__device__ __forceinline__ void gather_segment(const __amdgpu_buffer_rsrc_t& rs, unsigned long long sfix,
+                                               unsigned long long dfix, int ta, int tb, int rowstride,
+                                               unsigned cmax, T& acc_a, T& acc_d) {
+    int rowb = ta * rowstride, t = ta;
+    for (; t + FB - 1 <= tb; t += FB) {
         unsigned off[FB];
         T lf[FB], a[FB], b[FB];
 #pragma unroll
@@ -175,7 +170,7 @@ __device__ __forceinline__ void forward_body(const T* __restrict__ xp, const T* 
         }
         rowb += FB * rowstride;
     }
-    for (; t <= t1; ++t) {
+    for (; t <= tb; ++t) {
         T a, b;
         load_taps(rs, min((unsigned)(sfix >> 32), cmax) * (unsigned)sizeof(T), rowb, a, b);
         acc_a += a;
@@ -183,11 +178,46 @@ __device__ __forceinline__ void forward_body(const T* __restrict__ xp, const T* 
         sfix += dfix;
         rowb += rowstride;
     }
+}
+
+// The ray's value len (acc_a + acc_d 2^-32), or with rb the residual
+// value - rb - rw .* rm (rw null: value - rb), the arithmetic of the filter prologues.
+template <typename T>
+__device__ __forceinline__ T ray_value(T acc_a, T acc_d, double len, size_t idx, const T* __restrict__ rb,
+                                       const T* __restrict__ rw, const T* __restrict__ rm) {
+    T q = (acc_a + acc_d * (T)2.3283064365386962890625e-10) * (T)len;
+    if (rb) q = rw ? fma(-rw[idx], rm[idx], q - rb[idx]) : q - rb[idx];
+    return q;
+}
+
+// Gather form: 256 consecutive bins of one view per workgroup.
+template <typename T, int FB = FW_BATCH>
+__device__ __forceinline__ void forward_body(const T* __restrict__ xp, const T* __restrict__ xTp, T* __restrict__ y,
+                                             const ViewGeom* __restrict__ views, int n, int nb, int bxi, int v,
+                                             const T* __restrict__ rb = nullptr, const T* __restrict__ rw = nullptr,
+                                             const T* __restrict__ rm = nullptr) {
+    const int u = bxi * 256 + threadIdx.x;
+    const ViewGeom g = views[v];
+    const int P = n + 2 * FP_PAD;
+    double base;
+    int t0, t1;
+    wave_ray_span(g, u, n, nb, base, t0, t1);
+    const unsigned long long dfix = (unsigned long long)llrint(g.st * 4294967296.0);
+    const unsigned cmax = (unsigned)(P - 2);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(g.row ? xp : xTp), (short)0, (int)((size_t)n * P * sizeof(T)), kBufferRsrcWord3);
+    T tot_a = T(0), tot_d = T(0);
+    for (int s0 = t0 - t0 % FW_SEG; s0 <= t1; s0 += FW_SEG) {
+        const int ta = max(t0, s0), tb = min(t1, s0 + FW_SEG - 1);
+        T acc_a = T(0), acc_d = T(0);
+        gather_segment<T, FB>(rs, seg_position(base, g.st, s0) + (unsigned long long)(ta - s0) * dfix, dfix, ta, tb,
+                              P * (int)sizeof(T), cmax, acc_a, acc_d);
+        tot_a += acc_a;
+        tot_d += acc_d;
+    }
     if (u < nb) {
         const size_t idx = (size_t)v * nb + u;
-        T q = (acc_a + acc_d * (T)2.3283064365386962890625e-10) * (T)g.len;
-        if (rb) q = rw ? fma(-rw[idx], rm[idx], q - rb[idx]) : q - rb[idx];
-        y[idx] = q;
+        y[idx] = ray_value<T>(tot_a, tot_d, g.len, idx, rb, rw, rm);
     }
 }
 
@@ -207,24 +237,71 @@ hipError_t launch_forward_resid(const float* xp, const float* xTp, float* y, con
     return hipGetLastError();
 }
 
-// Slab form of the forward projector (float32, one problem).  A workgroup of
-// 12 waves takes 36 (view, 64-bin block) tasks of views of one orientation,
-// three per wave, and streams that orientation's padded plane through LDS in
-// slabs of R rows, the next slab prefetched into registers while the current
-// one is used.  A ray's steps, positions and sums are forward_body's, taken in
-// the same order, so the results are the same bit for bit; the taps come from
-// LDS instead of one gather per step through the texture-address unit, and the
-// plane passes through L2 once per three views.  tasks: per workgroup 36
-// entries view * 64 + block (-1 for none; the first entry is never -1).
-constexpr int kSlabWaves = 12, kSlabThreads = 64 * kSlabWaves, kSlabTPW = 3, kSlabTasks = kSlabWaves * kSlabTPW;
-constexpr int kSlabFB = 6, kSlabPre = 24;
+// Split form, for scans with few views: a workgroup of kSplitWaves waves takes
+// one (view, 64-bin block); wave w forms the sums of segments w, w + W, ...,
+// and wave 0 adds them in segment order.  The work of a few-view scan is then
+// spread over m * nblk * W waves instead of m * nblk.
+constexpr int kSplitWaves = 16, kSplitFB = 4, kSplitMaxSeg = 64;
 
-int forward_slab_rows(int n) {
-    // the slab (R rows of n + 6 floats) within 64 KB of LDS and 24 prefetched floats a thread
+__global__ __launch_bounds__(64 * kSplitWaves) void forward_split_kernel(
+    const float* __restrict__ xp, const float* __restrict__ xTp, float* __restrict__ y,
+    const ViewGeom* __restrict__ views, int n, int nb, int nblk, const float* __restrict__ rb,
+    const float* __restrict__ rw, const float* __restrict__ rm) {
+    __shared__ float part[2][kSplitMaxSeg][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int v = blockIdx.x / nblk, blk = blockIdx.x - v * nblk;
+    const int u = blk * 64 + lane;
+    const ViewGeom g = views[v];
     const int P = n + 2 * FP_PAD;
-    return std::max(1, std::min({31, 16384 / P, kSlabPre * kSlabThreads / P}));
+    double base;
+    int t0, t1;
+    wave_ray_span(g, u, n, nb, base, t0, t1);
+    const unsigned long long dfix = (unsigned long long)llrint(g.st * 4294967296.0);
+    const unsigned cmax = (unsigned)(P - 2);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(g.row ? xp : xTp), (short)0, (int)((size_t)n * P * sizeof(float)), kBufferRsrcWord3);
+    const int ns = (n + FW_SEG - 1) / FW_SEG;
+    for (int sg = wv; sg < ns; sg += kSplitWaves) {
+        const int s0 = sg * FW_SEG;
+        const int ta = max(t0, s0), tb = min(t1, s0 + FW_SEG - 1);
+        float acc_a = 0.f, acc_d = 0.f;
+        if (ta <= tb)
+            gather_segment<float, kSplitFB>(rs, seg_position(base, g.st, s0) + (unsigned long long)(ta - s0) * dfix,
+                                            dfix, ta, tb, P * (int)sizeof(float), cmax, acc_a, acc_d);
+        part[0][sg][lane] = acc_a;
+        part[1][sg][lane] = acc_d;
+    }
+    __syncthreads();
+    if (wv == 0 && u < nb) {
+        // segments outside the range hold zeros: adding them changes no bit
+        float tot_a = 0.f, tot_d = 0.f;
+        const int sa = t0 / FW_SEG, sb = t1 < 0 ? -1 : t1 / FW_SEG;
+        for (int sg = sa; sg <= sb; ++sg) {
+            tot_a += part[0][sg][lane];
+            tot_d += part[1][sg][lane];
+        }
+        const size_t idx = (size_t)v * nb + u;
+        y[idx] = ray_value<float>(tot_a, tot_d, g.len, idx, rb, rw, rm);
+    }
 }
 
+// Slab form (float32, one problem, scans with many views).  A workgroup of
+// 12 waves takes 36 (view, 64-bin block) tasks of views of one orientation,
+// three per wave, and streams that orientation's padded plane through LDS in
+// slabs of FW_SEG rows (one segment each): the next slab is copied straight
+// from global memory into the other half of a double buffer (16 bytes a lane,
+// no registers) while the current one is read.  Each wave steps its three
+// rays together over the union of their row ranges within the slab, so every
+// step issues three independent pairs of LDS reads.  The plane needs 16 bytes
+// of slack after its end (the copy moves whole 16-byte words).
+constexpr int kSlabWaves = 12, kSlabThreads = 64 * kSlabWaves, kSlabTPW = 3, kSlabTasks = kSlabWaves * kSlabTPW;
+constexpr int kSlabFB = 2;
+constexpr size_t kSlabMaxLds = 160 * 1024;
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+size_t forward_slab_lds(int n) { return (size_t)2 * FW_SEG * (n + 2 * FP_PAD) * sizeof(float); }
+bool forward_slab_fits(int n) { return forward_slab_lds(n) <= kSlabMaxLds; }
 int forward_slab_tasks_per_group() { return kSlabTasks; }
 
 __global__ __launch_bounds__(kSlabThreads) void forward_slab_kernel(const float* __restrict__ xp,
@@ -232,104 +309,123 @@ __global__ __launch_bounds__(kSlabThreads) void forward_slab_kernel(const float*
                                                                     float* __restrict__ y,
                                                                     const ViewGeom* __restrict__ views,
                                                                     const int* __restrict__ tasks, int n, int nb,
-                                                                    int R, const float* __restrict__ rb,
+                                                                    const float* __restrict__ rb,
                                                                     const float* __restrict__ rw,
                                                                     const float* __restrict__ rm) {
-    extern __shared__ float slab[];
+    constexpr int R = FW_SEG, J = kSlabTPW, FB = kSlabFB;
+    extern __shared__ __align__(16) float slabs[];
     const int P = n + 2 * FP_PAD;
+    const int SL = R * P;   // floats per buffer, a multiple of 4
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int* tk = tasks + (size_t)blockIdx.x * kSlabTasks;
     const float* plane = views[tk[0] >> 6].row ? xp : xTp;
     const unsigned cmax = (unsigned)(P - 2);
-    const double two32 = 4294967296.0;
-    unsigned long long sfix[kSlabTPW], dfix[kSlabTPW];
-    float acc_a[kSlabTPW], acc_d[kSlabTPW];
-    int t0w[kSlabTPW], t1w[kSlabTPW], vv[kSlabTPW], uu[kSlabTPW];
+    unsigned long long dfix[J];
+    double bs[J], sts[J];
+    float tot_a[J], tot_d[J];
+    int vv[J], uu[J];
+    int tu0 = n, tu1 = -1;
 #pragma unroll
-    for (int j = 0; j < kSlabTPW; ++j) {
+    for (int j = 0; j < J; ++j) {
         const int e = tk[wv + kSlabWaves * j];
         const int v = e >= 0 ? e >> 6 : -1;
         const int u = e >= 0 ? (e & 63) * 64 + lane : nb;
         vv[j] = v;
         uu[j] = u;
-        acc_a[j] = 0.f;
-        acc_d[j] = 0.f;
-        double base = 0.0, st = 0.0;
+        tot_a[j] = tot_d[j] = 0.f;
+        double base = -1000.0, st = 0.0;   // a missing task reads the pad
         int t0 = n, t1 = -1;
         if (v >= 0) {
             const ViewGeom g = views[v];
             st = g.st;
             wave_ray_span(g, u, n, nb, base, t0, t1);
         }
-        t0w[j] = t0;
-        t1w[j] = t1;
-        sfix[j] = (unsigned long long)llrint((fma((double)t0, st, base) + FP_PAD) * two32);
-        dfix[j] = (unsigned long long)llrint(st * two32);
+        bs[j] = base;
+        sts[j] = st;
+        dfix[j] = (unsigned long long)llrint(st * 4294967296.0);
+        tu0 = min(tu0, t0);
+        tu1 = max(tu1, t1);
     }
-    const int slab_elems = R * P;
-    const int per = (slab_elems + kSlabThreads - 1) / kSlabThreads;   // <= kSlabPre
-    float pre[kSlabPre];
-    auto fetch = [&](int r0) {
-        const int cnt = min(R, n - r0) * P;
+    // rows [r0, r0 + R) of the plane into buffer b, 16 bytes a lane
+    auto copy = [&](int r0, int b) {
+        const int cnt4 = (min(R, n - r0) * P + 3) / 4;
         const float* src = plane + (size_t)r0 * P;
-#pragma unroll
-        for (int k = 0; k < kSlabPre; ++k) {
-            const int e = threadIdx.x + kSlabThreads * k;
-            pre[k] = (k < per && e < cnt) ? src[e] : 0.f;
+        for (int i0 = wv * 64; i0 < cnt4; i0 += kSlabThreads) {
+            if (i0 + lane < cnt4)
+                __builtin_amdgcn_global_load_lds((const void*)(src + 4 * (i0 + lane)),
+                                                 (lds_void_t*)(slabs + b * SL + 4 * i0), 16, 0, 0);
         }
     };
-    fetch(0);
+    copy(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    int buf = 0;
     for (int r0 = 0; r0 < n; r0 += R) {
-        __syncthreads();   // the previous slab has been read
+        if (r0 + R < n) copy(r0 + R, buf ^ 1);
+        const float* slab = slabs + buf * SL;
+        const int ta = max(tu0, r0), tb = min(tu1, min(n, r0 + R) - 1);
+        if (ta <= tb) {
+            unsigned long long sfix[J];
+            float acc_a[J], acc_d[J];
 #pragma unroll
-        for (int k = 0; k < kSlabPre; ++k) {
-            const int e = threadIdx.x + kSlabThreads * k;
-            if (k < per && e < slab_elems) slab[e] = pre[k];
-        }
-        __syncthreads();
-        if (r0 + R < n) fetch(r0 + R);
-        const int r1 = min(n, r0 + R) - 1;
-#pragma unroll
-        for (int j = 0; j < kSlabTPW; ++j) {
-            const int ta = max(t0w[j], r0), tb = min(t1w[j], r1);
+            for (int j = 0; j < J; ++j) {
+                sfix[j] = seg_position(bs[j], sts[j], r0) + (unsigned long long)(ta - r0) * dfix[j];
+                acc_a[j] = acc_d[j] = 0.f;
+            }
             int t = ta;
-            for (; t + kSlabFB - 1 <= tb; t += kSlabFB) {
-                unsigned off[kSlabFB];
-                float lf[kSlabFB], a[kSlabFB], b[kSlabFB];
+            for (; t + FB - 1 <= tb; t += FB) {
+                unsigned off[FB][J];
+                float lf[FB][J], a[FB][J], b[FB][J];
 #pragma unroll
-                for (int q = 0; q < kSlabFB; ++q) {
-                    off[q] = min((unsigned)(sfix[j] >> 32), cmax) + (unsigned)((t - r0 + q) * P);
-                    lf[q] = (float)(unsigned)sfix[j];
-                    sfix[j] += dfix[j];
-                }
+                for (int q = 0; q < FB; ++q)
 #pragma unroll
-                for (int q = 0; q < kSlabFB; ++q) {
-                    a[q] = slab[off[q]];
-                    b[q] = slab[off[q] + 1];
-                }
+                    for (int j = 0; j < J; ++j) {
+                        off[q][j] = min((unsigned)(sfix[j] >> 32), cmax) + (unsigned)((t - r0 + q) * P);
+                        lf[q][j] = (float)(unsigned)sfix[j];
+                        sfix[j] += dfix[j];
+                    }
 #pragma unroll
-                for (int q = 0; q < kSlabFB; ++q) {
-                    acc_a[j] += a[q];
-                    acc_d[j] = fma(lf[q], b[q] - a[q], acc_d[j]);
-                }
+                for (int q = 0; q < FB; ++q)
+#pragma unroll
+                    for (int j = 0; j < J; ++j) {
+                        a[q][j] = slab[off[q][j]];
+                        b[q][j] = slab[off[q][j] + 1];
+                    }
+#pragma unroll
+                for (int q = 0; q < FB; ++q)
+#pragma unroll
+                    for (int j = 0; j < J; ++j) {
+                        acc_a[j] += a[q][j];
+                        acc_d[j] = fma(lf[q][j], b[q][j] - a[q][j], acc_d[j]);
+                    }
             }
             for (; t <= tb; ++t) {
-                const unsigned off = min((unsigned)(sfix[j] >> 32), cmax) + (unsigned)((t - r0) * P);
-                const float a = slab[off], b = slab[off + 1];
-                acc_a[j] += a;
-                acc_d[j] = fma((float)(unsigned)sfix[j], b - a, acc_d[j]);
-                sfix[j] += dfix[j];
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const unsigned off = min((unsigned)(sfix[j] >> 32), cmax) + (unsigned)((t - r0) * P);
+                    const float a = slab[off], b = slab[off + 1];
+                    acc_a[j] += a;
+                    acc_d[j] = fma((float)(unsigned)sfix[j], b - a, acc_d[j]);
+                    sfix[j] += dfix[j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                tot_a[j] += acc_a[j];
+                tot_d[j] += acc_d[j];
             }
         }
+        // the next slab has landed and every wave is done with this one
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        buf ^= 1;
     }
 #pragma unroll
-    for (int j = 0; j < kSlabTPW; ++j) {
+    for (int j = 0; j < J; ++j) {
         if (vv[j] >= 0 && uu[j] < nb) {
             const size_t idx = (size_t)vv[j] * nb + uu[j];
-            float q = (acc_a[j] + acc_d[j] * 2.3283064365386962890625e-10f) * (float)views[vv[j]].len;
-            if (rb) q = rw ? fma(-rw[idx], rm[idx], q - rb[idx]) : q - rb[idx];
-            y[idx] = q;
+            y[idx] = ray_value<float>(tot_a[j], tot_d[j], views[vv[j]].len, idx, rb, rw, rm);
         }
     }
 }
@@ -337,10 +433,34 @@ __global__ __launch_bounds__(kSlabThreads) void forward_slab_kernel(const float*
 hipError_t launch_forward_slab(const float* xp, const float* xTp, float* y, const ViewGeom* views, const int* tasks,
                                int ngroups, int n, int nb, const float* rb, const float* rw, const float* rm,
                                hipStream_t s) {
-    const int R = forward_slab_rows(n);
-    forward_slab_kernel<<<ngroups, kSlabThreads, sizeof(float) * R * (n + 2 * FP_PAD), s>>>(xp, xTp, y, views, tasks,
-                                                                                          n, nb, R, rb, rw, rm);
+    static std::once_flag once;
+    static hipError_t attr = hipSuccess;
+    std::call_once(once, [] {
+        attr = hipFuncSetAttribute((const void*)forward_slab_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)kSlabMaxLds);
+    });
+    if (attr != hipSuccess) return attr;
+    forward_slab_kernel<<<ngroups, kSlabThreads, forward_slab_lds(n), s>>>(xp, xTp, y, views, tasks, n, nb, rb, rw,
+                                                                        rm);
     return hipGetLastError();
+}
+
+// The form for the geometry (all three give the same bits): the slab form
+// when its groups fill most of the chip, else the split form, else the gather
+// form (images beyond the split form's segment table).
+constexpr int kSlabMinGroups = 150;
+
+hipError_t launch_forward_auto(const float* xp, const float* xTp, float* y, const ViewGeom* views, const int* tasks,
+                               int ngroups, int n, int m, int nb, const float* rb, const float* rw, const float* rm,
+                               hipStream_t s) {
+    if (tasks && ngroups >= kSlabMinGroups && forward_slab_fits(n))
+        return launch_forward_slab(xp, xTp, y, views, tasks, ngroups, n, nb, rb, rw, rm, s);
+    if (n <= kSplitMaxSeg * FW_SEG) {
+        const int nblk = (nb + 63) / 64;
+        forward_split_kernel<<<m * nblk, 64 * kSplitWaves, 0, s>>>(xp, xTp, y, views, n, nb, nblk, rb, rw, rm);
+        return hipGetLastError();
+    }
+    return launch_forward_resid(xp, xTp, y, views, n, m, nb, rb, rw, rm, s);
 }
 
 template <typename T>

@@ -48,6 +48,8 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(const void* __restr
             if (pb && !isfinite(((const float*)pb)[i])) s2 += 1.0;
         } else if constexpr (OP == RED_ABS_F32) {
             s0 += fabs((double)((const float*)pa)[i]);
+        } else if constexpr (OP == RED_ABS_F64) {
+            s0 += fabs(((const double*)pa)[i]);
         } else if constexpr (OP == RED_WRES_F32) {
             const double r = (double)((const float*)pa)[i] - (double)((const float*)pb)[i];
             s0 = fma((double)((const float*)pc)[i] * r, r, s0);
@@ -109,6 +111,7 @@ hipError_t launch_reduce(int op, const void* a, const void* b, const void* c, si
         case RED_DOT_F64: reduce_partial_kernel<RED_DOT_F64><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
         case RED_INVW_CHECK: reduce_partial_kernel<RED_INVW_CHECK><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
         case RED_ABS_F32: reduce_partial_kernel<RED_ABS_F32><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
+        case RED_ABS_F64: reduce_partial_kernel<RED_ABS_F64><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
         case RED_WRES_F32: reduce_partial_kernel<RED_WRES_F32><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
         case RED_SQDIFF_F32: reduce_partial_kernel<RED_SQDIFF_F32><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
         case RED_DOT_F32: reduce_partial_kernel<RED_DOT_F32><<<nb, 256, 0, s>>>(a, b, c, len, partials); break;
@@ -269,6 +272,16 @@ __global__ __launch_bounds__(256) void mul_w_kernel(double* __restrict__ out, co
 
 hipError_t launch_mul_w_f64(double* out, const double* a, const float* w, size_t len, hipStream_t s) {
     mul_w_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(out, a, w, len);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void widen_kernel(double* __restrict__ out, const float* __restrict__ a, size_t len) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < len) out[i] = (double)a[i];
+}
+
+hipError_t launch_widen_f64(double* out, const float* a, size_t len, hipStream_t s) {
+    widen_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(out, a, len);
     return hipGetLastError();
 }
 
