@@ -320,6 +320,20 @@ int ctpd_gist_lowdose_solve(ctpd_op* op, const float* b, const float* w, double 
 int ctpd_cp_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd_params* p, float* x_out,
                           ctpd_report* rep);
 
+/* y = A x for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same projection as ctpd_project for the scan g with uniform angles
+ * theta_v = v pi / n_views (g->angles must be NULL), with no handle and no
+ * allocation.  Its scratch -- the view table and the two zero-padded image
+ * planes -- is one static device array of 8.7 MB that each GPU the library
+ * runs on keeps until the process ends; every call on a GPU shares it, so
+ * calls that overlap on one GPU (two streams, two threads) race and must be
+ * serialised by the caller.  Limits: 1 <= n <= 1024, 1 <= n_views <= 4096,
+ * 1 <= n_bins <= CTPD_MAX_BINS, else CTPD_EINVAL (nothing launched).
+ * stream: the hipStream_t the work is queued on (NULL = the null stream);
+ * x: [n][n], y: [n_views][n_bins], device.  Returns without waiting. */
+int ctpd_project_noalloc(const ctpd_geometry* g, void* stream, const float* x, float* y);
+
 /* Static message for an error code. */
 const char* ctpd_strerror(int code);
 

@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libctpd.so")
-SOURCES = ["projector.hip", "filter.hip", "tv.hip", "vec.hip", "api.hip", "batch.hip", "unrolled.hip"]
+SOURCES = ["projector.hip", "filter.hip", "tv.hip", "vec.hip", "api.hip", "batch.hip", "unrolled.hip", "noalloc.hip"]
 ARCH = os.environ.get("CTPD_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are kept out of every kernel (the compiler would

@@ -485,3 +485,21 @@ class Batch:
         _check(load().ctpd_batch_time_loop(self._h, int(iters), int(tv_iters), int(reps), byref(ms)))
         return ms.value
 
+
+# ---- forward projection without device allocation ---------------------------------
+_SIGNATURES["ctpd_project_noalloc"] = (c_int, [c_void_p, c_void_p, c_void_p, c_void_p])
+
+
+def project_noalloc(x: torch.Tensor, n_views: int, n_bins: int, stream: torch.cuda.Stream | None = None,
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+    """y = A x for uniform angles v pi / n_views through ctpd_project_noalloc,
+    which allocates nothing (its scratch is a static device array shared by
+    every call on the GPU: calls must not overlap).  n <= 1024, n_views <= 4096."""
+    n = int(x.shape[0]) if isinstance(x, torch.Tensor) and x.dim() == 2 else -1
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    out = torch.empty((int(n_views), int(n_bins)), dtype=torch.float32, device=stream.device) if out is None else out
+    geo = Geometry(n, int(n_views), int(n_bins), 0, None)
+    with torch.cuda.device(stream.device):
+        _check(load().ctpd_project_noalloc(byref(geo), c_void_p(stream.cuda_stream), _ptr(x, (n, n), "x"),
+                                           _ptr(out, (int(n_views), int(n_bins)), "out")))
+    return out
