@@ -268,7 +268,8 @@ int ctpd_unrolled_lowdose_backward_many(int32_t count, ctpd_op* const* ops, cons
 typedef struct {
     int32_t placement;   /* 0: each problem's workgroups on one XCD (default); 1: problem-major order */
     int32_t tv_threads;  /* threads per 32 x 32 TV tile: 512 or 1024 (default) */
-    int32_t fwd_batch;   /* taps in flight per forward-projector lane: 4 or 8 (default) */
+    int32_t fwd_form;    /* forward projector: 0 the slab form (default; every image side <= 634),
+                            1 the gather form; both give the same bits */
     int32_t reserved;
 } ctpd_batch_tiles;
 

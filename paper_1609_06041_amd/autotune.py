@@ -16,7 +16,7 @@ import torch
 
 from . import ctpd
 
-CANDIDATES = [dict(placement=p, tv_threads=t, fwd_batch=f) for p in (0, 1) for t in (1024, 512) for f in (8, 4)]
+CANDIDATES = [dict(placement=p, tv_threads=t, fwd_form=f) for p in (0, 1) for t in (1024, 512) for f in (0, 1)]
 
 
 def signature(geoms, iters: int, tv_iters: int) -> str:
@@ -39,7 +39,11 @@ def autotune(batch: ctpd.Batch, bs, ws, betas, iters: int, tv_iters: int = 10, c
     batch.lowdose_solve(bs, ws, betas, iters, tv_iters=tv_iters)   # sets the batch up for timing
     timings = []
     for cand in CANDIDATES:
-        batch.set_tiles(**cand)
+        try:
+            batch.set_tiles(**cand)
+        except ctpd.CtpdError:   # a choice the batch's geometries do not allow (an image too large for a form)
+            timings.append(float("inf"))
+            continue
         batch.time_loop(iters, tv_iters, 1)   # capture + warm
         timings.append(batch.time_loop(iters, tv_iters, reps))
     best = CANDIDATES[min(range(len(CANDIDATES)), key=timings.__getitem__)]

@@ -70,7 +70,7 @@ struct ctpd_batch {
     std::vector<ctpd_op*> ops;
     std::vector<hipStream_t> streams;   // one per problem for the set-up
     std::vector<int> xcd;               // XCD of each problem
-    int max_nb = 0;
+    int max_nb = 0, max_n = 0;
     BatchItem* items = nullptr;         // device table
     BatchItem* items_host = nullptr;    // pinned mirror
     NormItem* nitems = nullptr;         // lambda_h chains: device table
@@ -85,13 +85,14 @@ struct ctpd_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int g_iters = -1, g_tv = -1;
-    ctpd_batch_tiles tiles{0, 1024, 8, 0};
+    ctpd_batch_tiles tiles{0, 1024, 0, 0};
+    bool slab_ok = true;   // every problem's image fits the slab projector
     bool solved = false;   // items hold a valid set-up (a solve has run)
 };
 
 namespace {
 
-int blocks_of(const ctpd_op* op, int kind) {
+int blocks_of(const ctpd_op* op, int kind, int fwd_form) {
     const size_t J = op->J, I = op->I;
     switch (kind) {
         case K_INIT: return (int)((3 * J + 2 * I + 2047) / 2048);
@@ -100,7 +101,7 @@ int blocks_of(const ctpd_op* op, int kind) {
         case K_ADJ: return adjoint_tiles(op->n) * adjoint_tiles(op->n);
         case K_TV: return tv_tiles(op->n) * tv_tiles(op->n);
         case K_PAD: return pad_tiles(op->n) * pad_tiles(op->n);
-        case K_FWD: return forward_blocks_x(op->nb) * op->m;
+        case K_FWD: return fwd_form == 0 ? op->fwd_groups : forward_blocks_x(op->nb) * op->m;
         default: return (int)((J + 2047) / 2048);
     }
 }
@@ -113,7 +114,7 @@ int build_maps(ctpd_batch* bt) {
     bt->xcd = pl.xcd;
     for (int kind = 0; kind < K_COUNT; ++kind) {
         std::vector<int> counts(P);
-        for (int p = 0; p < P; ++p) counts[p] = blocks_of(bt->ops[p], kind);
+        for (int p = 0; p < P; ++p) counts[p] = blocks_of(bt->ops[p], kind, bt->tiles.fwd_form);
         const std::vector<BlockRef> flat = place_blocks(pl, counts, bt->tiles.placement);
         if (bt->map[kind]) (void)hipFree(bt->map[kind]);
         bt->map[kind] = nullptr;
@@ -148,7 +149,7 @@ int queue_loop(ctpd_batch* bt, int iters, int tv_iters) {
         } while (left > 0);
         // Step 3: mu^{k+1} = mu + sigma D (A x - b - W^-1 mu)
         HIP_TRY(launch_pad_planes_batched(it, bt->map[K_PAD], bt->nblk[K_PAD], s));
-        HIP_TRY(launch_forward_batched(it, bt->map[K_FWD], bt->nblk[K_FWD], bt->tiles.fwd_batch, rot, s));
+        HIP_TRY(launch_forward_batched(it, bt->map[K_FWD], bt->nblk[K_FWD], bt->tiles.fwd_form, bt->max_n, rot, s));
         HIP_TRY(launch_filter_batched(it, bt->map[K_FILT], bt->nblk[K_FILT], FILT_DUAL_LD, rot, bt->max_nb, s));
     }
     HIP_TRY(launch_batch_copy_out(it, bt->map[K_COPY], bt->nblk[K_COPY], s));
@@ -201,7 +202,10 @@ int ctpd_batch_create(const ctpd_geometry* geoms, int32_t count, void* stream, c
             if (r) return r;
             bt->ops.push_back(op);
             bt->max_nb = std::max(bt->max_nb, geoms[p].n_bins);
+            bt->max_n = std::max(bt->max_n, geoms[p].n);
         }
+        bt->slab_ok = forward_slab_fits(bt->max_n);
+        if (!bt->slab_ok) bt->tiles.fwd_form = 1;
         ALLOC(bt->items, count);
         HIP_TRY(hipHostMalloc((void**)&bt->items_host, sizeof(BatchItem) * count, hipHostMallocDefault));
         ALLOC(bt->nitems, count);
@@ -319,6 +323,7 @@ int ctpd_batch_lowdose_solve(ctpd_batch* bt, const float* const* b, const float*
         for (int j = 0; j < 2; ++j) it.p[j] = op->p[j];
         it.xp = op->xp;
         it.xTp = op->xTp;
+        it.tasks = op->fwd_tasks;
         it.x_out = x_out[i];
         it.sigma = (float)S[i].sigma;
         it.tau = (float)S[i].tau;
@@ -354,8 +359,9 @@ int ctpd_batch_set_tiles(ctpd_batch* bt, const ctpd_batch_tiles* t) {
     if (!bt || !t) return einval("null pointer");
     if (t->placement != 0 && t->placement != 1) return einval("placement must be 0 or 1");
     if (t->tv_threads != 512 && t->tv_threads != 1024) return einval("tv_threads must be 512 or 1024");
-    if (t->fwd_batch != 4 && t->fwd_batch != 8) return einval("fwd_batch must be 4 or 8");
-    const bool remap = t->placement != bt->tiles.placement;
+    if (t->fwd_form != 0 && t->fwd_form != 1) return einval("fwd_form must be 0 (slab) or 1 (gather)");
+    if (t->fwd_form == 0 && !bt->slab_ok) return einval("an image of the batch is too large for the slab projector");
+    const bool remap = t->placement != bt->tiles.placement || t->fwd_form != bt->tiles.fwd_form;
     bt->tiles = *t;
     bt->tiles.reserved = 0;
     bt->g_iters = -1;   // recapture the loop with the new choices

@@ -70,6 +70,7 @@ struct BatchItem {
     float* p[2];
     float* xp;
     float* xTp;
+    const int* tasks;   // the slab projector's task groups (of the problem's handle)
     float* x_out;
     float sigma, tau, lam, tvstep;
 };
@@ -201,10 +202,13 @@ hipError_t launch_adjoint(const T* y1, const T* y2, T c1, T c2, const T* xin, T 
 // batched forms (grids of nblocks workgroups described by map):
 //   pad planes of x, q = A x, z = x - tau A^T mubar (two: z = x - tau A^T (2 mu^k - mu^{k-1}))
 hipError_t launch_pad_planes_batched(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s);
-// fb: taps in flight per lane (4 or 8), a tuning choice of the batch
-// (the batch's projector writes the residual A x - b - W^-1 mu[rot] into q)
-hipError_t launch_forward_batched(const BatchItem* items, const BlockRef* map, int nblocks, int fb, int rot,
-                                  hipStream_t s);
+// form: 0 the slab form (map entries (problem, task group); every problem's
+// n must fit forward_slab_fits, max_n the largest), 1 the gather form (map
+// entries (problem, forward_blocks_x(nb) * view + block)) -- a tuning choice
+// of the batch; both give the single solve's bits.  The batch's projector
+// writes the residual A x - b - W^-1 mu[rot] into q.
+hipError_t launch_forward_batched(const BatchItem* items, const BlockRef* map, int nblocks, int form, int max_n,
+                                  int rot, hipStream_t s);
 hipError_t launch_adjoint_batched(const BatchItem* items, const BlockRef* map, int nblocks, bool two, int rot,
                                   hipStream_t s);
 

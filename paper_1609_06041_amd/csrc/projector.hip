@@ -304,21 +304,18 @@ size_t forward_slab_lds(int n) { return (size_t)2 * FW_SEG * (n + 2 * FP_PAD) * 
 bool forward_slab_fits(int n) { return forward_slab_lds(n) <= kSlabMaxLds; }
 int forward_slab_tasks_per_group() { return kSlabTasks; }
 
-__global__ __launch_bounds__(kSlabThreads) void forward_slab_kernel(const float* __restrict__ xp,
-                                                                    const float* __restrict__ xTp,
-                                                                    float* __restrict__ y,
-                                                                    const ViewGeom* __restrict__ views,
-                                                                    const int* __restrict__ tasks, int n, int nb,
-                                                                    const float* __restrict__ rb,
-                                                                    const float* __restrict__ rw,
-                                                                    const float* __restrict__ rm) {
+// tk: the group's kSlabTasks task entries
+__device__ __forceinline__ void forward_slab_body(const float* __restrict__ xp, const float* __restrict__ xTp,
+                                                  float* __restrict__ y, const ViewGeom* __restrict__ views,
+                                                  const int* __restrict__ tk, int n, int nb,
+                                                  const float* __restrict__ rb, const float* __restrict__ rw,
+                                                  const float* __restrict__ rm) {
     constexpr int R = FW_SEG, J = kSlabTPW, FB = kSlabFB;
     extern __shared__ __align__(16) float slabs[];
     const int P = n + 2 * FP_PAD;
     const int SL = R * P;   // floats per buffer, a multiple of 4
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int* tk = tasks + (size_t)blockIdx.x * kSlabTasks;
     const float* plane = views[tk[0] >> 6].row ? xp : xTp;
     const unsigned cmax = (unsigned)(P - 2);
     unsigned long long dfix[J];
@@ -430,15 +427,46 @@ __global__ __launch_bounds__(kSlabThreads) void forward_slab_kernel(const float*
     }
 }
 
-hipError_t launch_forward_slab(const float* xp, const float* xTp, float* y, const ViewGeom* views, const int* tasks,
-                               int ngroups, int n, int nb, const float* rb, const float* rw, const float* rm,
-                               hipStream_t s) {
+__global__ __launch_bounds__(kSlabThreads) void forward_slab_kernel(const float* __restrict__ xp,
+                                                                    const float* __restrict__ xTp,
+                                                                    float* __restrict__ y,
+                                                                    const ViewGeom* __restrict__ views,
+                                                                    const int* __restrict__ tasks, int n, int nb,
+                                                                    const float* __restrict__ rb,
+                                                                    const float* __restrict__ rw,
+                                                                    const float* __restrict__ rm) {
+    forward_slab_body(xp, xTp, y, views, tasks + (size_t)blockIdx.x * kSlabTasks, n, nb, rb, rw, rm);
+}
+
+// The batch's slab projector: one workgroup per (problem, task group), the
+// residual A x - b - W^-1 mu[rot] into q.
+__global__ __launch_bounds__(kSlabThreads) void forward_slab_batched(const BatchItem* __restrict__ items,
+                                                                     const BlockRef* __restrict__ map, int rot) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const BatchItem& it = items[e.prob];
+    forward_slab_body(it.xp, it.xTp, it.q, it.views, it.tasks + (size_t)e.local * kSlabTasks, it.n, it.nb, it.b,
+                      it.lowdose ? it.winv : nullptr, it.mu[rot]);
+}
+
+// lift the dynamic LDS limit of the slab kernels to the chip's 160 KB, once
+static hipError_t slab_lds_attributes() {
     static std::once_flag once;
     static hipError_t attr = hipSuccess;
     std::call_once(once, [] {
         attr = hipFuncSetAttribute((const void*)forward_slab_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)kSlabMaxLds);
+        if (attr == hipSuccess)
+            attr = hipFuncSetAttribute((const void*)forward_slab_batched, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)kSlabMaxLds);
     });
+    return attr;
+}
+
+hipError_t launch_forward_slab(const float* xp, const float* xTp, float* y, const ViewGeom* views, const int* tasks,
+                               int ngroups, int n, int nb, const float* rb, const float* rw, const float* rm,
+                               hipStream_t s) {
+    const hipError_t attr = slab_lds_attributes();
     if (attr != hipSuccess) return attr;
     forward_slab_kernel<<<ngroups, kSlabThreads, forward_slab_lds(n), s>>>(xp, xTp, y, views, tasks, n, nb, rb, rw,
                                                                         rm);
@@ -805,12 +833,15 @@ hipError_t launch_pad_planes_batched(const BatchItem* items, const BlockRef* map
     return hipGetLastError();
 }
 
-hipError_t launch_forward_batched(const BatchItem* items, const BlockRef* map, int nblocks, int fb, int rot,
-                                  hipStream_t s) {
-    if (fb == 4)
-        forward_batched<4><<<nblocks, 256, 0, s>>>(items, map, rot);
-    else
-        forward_batched<8><<<nblocks, 256, 0, s>>>(items, map, rot);
+hipError_t launch_forward_batched(const BatchItem* items, const BlockRef* map, int nblocks, int form, int max_n,
+                                  int rot, hipStream_t s) {
+    if (form == 0) {
+        const hipError_t attr = slab_lds_attributes();
+        if (attr != hipSuccess) return attr;
+        forward_slab_batched<<<nblocks, kSlabThreads, forward_slab_lds(max_n), s>>>(items, map, rot);
+    } else {
+        forward_batched<FW_BATCH><<<nblocks, 256, 0, s>>>(items, map, rot);
+    }
     return hipGetLastError();
 }
 

@@ -86,7 +86,7 @@ class Params(ctypes.Structure):
 
 
 class BatchTiles(ctypes.Structure):
-    _fields_ = [("placement", c_int32), ("tv_threads", c_int32), ("fwd_batch", c_int32), ("reserved", c_int32)]
+    _fields_ = [("placement", c_int32), ("tv_threads", c_int32), ("fwd_form", c_int32), ("reserved", c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -471,13 +471,13 @@ class Batch:
         _check(load().ctpd_batch_lowdose_solve(self._h, pb, pw, pbeta, int(iters), byref(prm), px, reps))
         return outs, [Operator._info(r, None, {}) for r in reps]
 
-    def set_tiles(self, placement: int, tv_threads: int, fwd_batch: int) -> None:
-        _check(load().ctpd_batch_set_tiles(self._h, byref(BatchTiles(placement, tv_threads, fwd_batch, 0))))
+    def set_tiles(self, placement: int, tv_threads: int, fwd_form: int) -> None:
+        _check(load().ctpd_batch_set_tiles(self._h, byref(BatchTiles(placement, tv_threads, fwd_form, 0))))
 
     def get_tiles(self) -> dict:
         t = BatchTiles()
         _check(load().ctpd_batch_get_tiles(self._h, byref(t)))
-        return {"placement": t.placement, "tv_threads": t.tv_threads, "fwd_batch": t.fwd_batch}
+        return {"placement": t.placement, "tv_threads": t.tv_threads, "fwd_form": t.fwd_form}
 
     def time_loop(self, iters: int, tv_iters: int = 10, reps: int = 3) -> float:
         """Median device ms of one replay of the loop graph (needs a previous solve)."""

@@ -92,8 +92,8 @@ def test_batch_graph_replay_with_new_inputs(gpu):
 
 def test_batch_of_the_uneven_workload_sizes(gpu):
     # six problems of the 64-problem uneven workload (sizes 256-512, 32-720 views), 20 iterations,
-    # under every tile choice (the TV prox of 512- and 1024-thread workgroups, both forward
-    # projector forms) against the per-problem solver
+    # under every tile choice (the TV prox of 512- and 1024-thread workgroups, the slab and
+    # the gather forward projector) against the per-problem solver
     from paper_1609_06041_amd import autotune
     ids = [0, 5, 11, 17, 23, 42]
     probs = [S.batch_problem(p) for p in ids]
@@ -144,7 +144,7 @@ def test_every_tile_choice_gives_the_same_result(gpu):
                 np.testing.assert_array_equal(host(x), r)
         assert bt.time_loop(5, 10, 2) > 0.0
         with pytest.raises(ctpd.CtpdError):
-            bt.set_tiles(placement=0, tv_threads=256, fwd_batch=8)
+            bt.set_tiles(placement=0, tv_threads=256, fwd_form=0)
 
 
 def test_batch_with_chunked_inner_steps(gpu):
