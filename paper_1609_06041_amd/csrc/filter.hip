@@ -115,21 +115,30 @@ hipError_t launch_taps(double* taps64, float* taps32, int nb, int m, double tau,
 
 // ---------------------------------------------------------------------------
 // float32 matrix-core filter.
+//
+// Work split: a workgroup owns one output block of 16 views x FNT*16 bins
+// (FNT 16 x 16 MFMA tiles sharing the A operand) and splits the contraction
+// over the bins j into 16-bin chunks dealt round-robin to its FKS waves, so
+// that every wave of the chip has a short, equal share of the matrix-core work
+// (the 720-view, 736-bin shape makes 720 such workgroups, all resident at
+// once).  The partial sums of the FKS waves meet in LDS and are added in a
+// fixed pairwise order, so every launch form gives the same bits.  Within a
+// chunk, MFMA step t of lane (i, q) (i = lane % 16, q = lane / 16) takes
+//     A[i][q] = s[v0 + i][k0 + 4q + t],  B[q][c] = h[n0 + c - (k0 + 4q + t)],
+// so a lane reads its 4 input values with one 16-byte load; the taps of the
+// block's range of offsets are staged once in LDS.  The next chunk's loads are
+// issued before the current chunk's MFMAs.
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int FBM = 16;    // views per workgroup
-constexpr int FBN = 64;    // output bins per workgroup
-constexpr int FTPR = FBN / 16;            // 16 x 16 output tiles per tile row
-constexpr int FACC = FBM * FBN / 1024;    // 16 x 16 accumulators per wave (4 waves)
-static_assert(FACC >= 1 && FTPR % FACC == 0, "a wave's tiles lie in one tile row");
-constexpr int FBK = 128;   // input bins per LDS stage
-constexpr int FSTRIDE = FBK + 2;   // row pitch = 2 mod 32 banks: the 32 lanes of a half-wave hit 32 banks
-constexpr int FPER = FBM * FBK / 256;
+constexpr int FNT = 3;                    // 16 x 16 output tiles per workgroup (along the bins)
+constexpr int FKS = 8;                    // waves per workgroup, each a share of the contraction
+constexpr int FTHREADS = 64 * FKS;
+constexpr int FBN = 16 * FNT;             // output bins per workgroup
+constexpr int FBM = 16;                   // views per workgroup
+static_assert((FKS & (FKS - 1)) == 0, "pairwise reduction over a power of two of waves");
 
 // Number of sinogram arrays the prologue of each mode reads, and the input of
-// D formed from their raw values (a compile-time mode, and the raw values are
-// combined only at the LDS store, so the loads of a whole stage stay in flight
-// while the previous stage runs on the matrix cores).
+// D formed from their raw values.
 template <int MODE>
 struct FilterIn {
     static constexpr int N = MODE == FILT_DUAL_LD ? 4 : MODE == FILT_EXTRAP ? 3 : MODE == FILT_DUAL_FV ? 2 : 1;
@@ -141,117 +150,159 @@ struct FilterIn {
     }
 };
 
-// Workgroup: 4 waves, an FBM x FBN output tile cut into 16 x 16 MFMA tiles;
-// wave w owns FACC consecutive tiles of one tile row.  MFMA 16x16x4 f32
-// operand layout: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k,
-// D[i][j] in lane j + 16*(i/4), element i%4.  The filter input of the next
-// 128-bin stage is loaded into registers while the current stage runs.
-template <int MODE>
-__device__ __forceinline__ void filter_body(const FilterArgs& a, const float* __restrict__ taps, int m, int nb,
-                                            float* smem, int bxi, int byi) {
-    const int ntap = 2 * nb - 1;
-    const int tlen = ntap + FBK + FBN;
-    float* htap = smem;                 // htap[FBK + k] = taps[k], zero padded
-    float* stile = smem + tlen;         // [FBM][FSTRIDE]
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n0 = bxi * FBN, v0 = byi * FBM;
-    const int wr = (wave * FACC / FTPR) * 16, wc = (wave * FACC % FTPR) * 16;
-    const int li = lane & 15, lk = lane >> 4;
+// The filter input s[v][k0 + 4q + t], t = 0..3, of one lane.  VEC: nb % 16 == 0
+// and every input 16-byte aligned, so each chunk is whole and one 16-byte load
+// per input reads it.  Otherwise scalar loads at clamped columns, masked after
+// the load (no branches: the compiler can keep the loads in flight).
+template <int MODE, bool VEC>
+__device__ __forceinline__ void filter_load_chunk(const FilterArgs& a, size_t row, int nb, int kk, float (&dst)[4]) {
     constexpr int NIN = FilterIn<MODE>::N;
     const float* src[4] = {a.in0, a.in1, a.in2, a.in3};
-    float stg[FPER][NIN];
-    bool okk[FPER];
-    auto fetch = [&](int k0) {
+    float r[NIN][4];
+    if (VEC) {
 #pragma unroll
-        for (int r = 0; r < FPER; ++r) {
-            const int e = tid + 256 * r;
-            const int row = e / FBK, cc = e - row * FBK;
-            const int v = v0 + row, j = k0 + cc;
-            okk[r] = v < m && j < nb;
-            const size_t idx = okk[r] ? (size_t)v * nb + j : 0;   // clamped, unconditional loads
-#pragma unroll
-            for (int q = 0; q < NIN; ++q) stg[r][q] = src[q][idx];
+        for (int q = 0; q < NIN; ++q) {
+            const float4 x = *reinterpret_cast<const float4*>(src[q] + row + kk);
+            r[q][0] = x.x;
+            r[q][1] = x.y;
+            r[q][2] = x.z;
+            r[q][3] = x.w;
         }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const size_t col = row + min(kk + t, nb - 1);
+#pragma unroll
+            for (int q = 0; q < NIN; ++q) r[q][t] = src[q][col];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        float rr[NIN];
+#pragma unroll
+        for (int q = 0; q < NIN; ++q) rr[q] = r[q][t];
+        dst[t] = (VEC || kk + t < nb) ? FilterIn<MODE>::combine(rr) : 0.0f;
+    }
+}
+
+// Lay-out of the dynamic LDS: the taps of the block's offsets, then the
+// waves' partial tiles.
+__host__ __device__ constexpr int filter_taps_floats(int nb) {
+    return ((((nb + 15) / 16) * 16 + FBN + 63) / 64) * 64;
+}
+
+template <int MODE, bool VEC>
+__device__ __forceinline__ void filter_tile(const FilterArgs& a, const float* __restrict__ taps, int m, int nb,
+                                            float* smem, int tile) {
+    const int tiles_x = (nb + FBN - 1) / FBN;
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const int v0 = ty * FBM, n0 = tx * FBN;
+    const int nch = (nb + 15) >> 4, kpad = nch * 16;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lq = lane >> 4;
+    float* tl = smem;                            // tl[x] = h[n0 + x - (kpad - 1)], zero outside the taps
+    float* red = smem + filter_taps_floats(nb);  // [FKS][FNT][4][64] partial tiles
+    const size_t row = (size_t)min(v0 + li, m - 1) * nb;   // rows past m only feed outputs never stored
+    float cur[4], nxt[4];
+    int c = w;
+    filter_load_chunk<MODE, VEC>(a, row, nb, 16 * min(c, nch - 1) + 4 * lq, cur);
+    const int ntl = kpad + FBN - 1;
+    for (int x = tid; x < ntl; x += FTHREADS) {
+        const int d = n0 + x - (kpad - 1);
+        tl[x] = (d > -nb && d < nb) ? taps[nb - 1 + d] : 0.0f;
+    }
+    v4f acc[FNT];
+#pragma unroll
+    for (int j = 0; j < FNT; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+    __syncthreads();
+    const int bl = li - 4 * lq + kpad - 1;
+    auto mma = [&](const float (&av)[4], int k0) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int j = 0; j < FNT; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], tl[bl + 16 * j - k0 - t], acc[j], 0, 0, 0);
     };
-    v4f acc[FACC];
+    // chunks c, c + FKS, ... in pairs; a pair's second chunk past the end
+    // counts with a zero input
+    for (; c < nch; c += 2 * FKS) {
+        const int c1 = min(c + FKS, nch - 1);
+        filter_load_chunk<MODE, VEC>(a, row, nb, 16 * c1 + 4 * lq, nxt);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(cur, 16 * c);
+        __builtin_amdgcn_sched_barrier(0);
+        filter_load_chunk<MODE, VEC>(a, row, nb, 16 * min(c + 2 * FKS, nch - 1) + 4 * lq, cur);
+        __builtin_amdgcn_sched_barrier(0);
+        const bool ok = c + FKS < nch;
 #pragma unroll
-    for (int q = 0; q < FACC; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
-    // the first stage's input is in flight while the taps are staged
-    fetch(0);
-    for (int i0 = 0; i0 < tlen; i0 += 256 * 8) {   // 8 loads in flight per thread
-        float tv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int k = i0 + tid + 256 * u - FBK;
-            tv[u] = taps[(k >= 0 && k < ntap) ? k : 0];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = i0 + tid + 256 * u, k = i - FBK;
-            if (i < tlen) htap[i] = (k >= 0 && k < ntap) ? tv[u] : 0.0f;
-        }
+        for (int t = 0; t < 4; ++t) nxt[t] = ok ? nxt[t] : 0.0f;
+        mma(nxt, 16 * c1);
     }
-    for (int k0 = 0; k0 < nb; k0 += FBK) {
-        __syncthreads();
+    // MFMA 16x16 result: D[i][c] in lane c + 16 (i / 4), element i % 4
 #pragma unroll
-        for (int r = 0; r < FPER; ++r) {
-            const int e = tid + 256 * r;
-            const int row = e / FBK;
-            stile[row * FSTRIDE + (e - row * FBK)] = okk[r] ? FilterIn<MODE>::combine(stg[r]) : 0.0f;
-        }
-        __syncthreads();
-        if (k0 + FBK < nb) fetch(k0 + FBK);
-        // T[krow][col] = h[col - krow] sits at htap[col - krow + nb - 1 + FBK].
-        const int hb = n0 + wc + li - (k0 + lk) + nb - 1 + FBK;
-#pragma unroll 8
-        for (int kk = 0; kk < FBK; kk += 4) {
-            const float av = stile[(wr + li) * FSTRIDE + kk + lk];
+    for (int j = 0; j < FNT; ++j)
 #pragma unroll
-            for (int q = 0; q < FACC; ++q)
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, htap[hb - kk + 16 * q], acc[q], 0, 0, 0);
-        }
-    }
+        for (int r = 0; r < 4; ++r) red[((w * FNT + j) * 4 + r) * 64 + lane] = acc[j][r];
+    __syncthreads();
+    for (int e = tid; e < FBM * FBN; e += FTHREADS) {
+        const int i = e / FBN, jj = e - i * FBN;
+        const int off = ((jj >> 4) * 4 + (i & 3)) * 64 + (jj & 15) + 16 * (i >> 2);
+        float p[FKS];
 #pragma unroll
-    for (int blk = 0; blk < FACC; ++blk) {
-        const int col = n0 + wc + 16 * blk + li;
+        for (int q = 0; q < FKS; ++q) p[q] = red[q * FNT * 256 + off];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int v = v0 + wr + 4 * lk + r;
-            if (v < m && col < nb) {
-                const size_t idx = (size_t)v * nb + col;
-                float val = a.c * acc[blk][r];
-                float e0v = 0.0f;
-                if (a.E0) {
-                    e0v = a.E0[idx];
-                    val = fmaf(a.e0, e0v, val);
-                }
-                if (a.E1) val = fmaf(a.e1, a.E1[idx], val);
-                a.out[idx] = val;
-                if (a.Sout) a.Sout[idx] = a.Sw[idx] * (val - e0v);
+        for (int st = 1; st < FKS; st <<= 1)
+#pragma unroll
+            for (int q = 0; q < FKS; q += 2 * st) p[q] += p[q + st];
+        const int v = v0 + i, col = n0 + jj;
+        if (v < m && col < nb) {
+            const size_t idx = (size_t)v * nb + col;
+            float val = a.c * p[0];
+            float e0v = 0.0f;
+            if (a.E0) {
+                e0v = a.E0[idx];
+                val = fmaf(a.e0, e0v, val);
             }
+            if (a.E1) val = fmaf(a.e1, a.E1[idx], val);
+            a.out[idx] = val;
+            if (a.Sout) a.Sout[idx] = a.Sw[idx] * (val - e0v);
         }
     }
 }
 
+// Both load forms give the same values and the same MFMA sequence, so the
+// choice (per workgroup, from nb and the input addresses) never changes a bit.
 template <int MODE>
-__global__ __launch_bounds__(256) void filter_mfma_kernel(FilterArgs a, const float* __restrict__ taps, int m,
-                                                          int nb) {
+__device__ __forceinline__ void filter_body(const FilterArgs& a, const float* __restrict__ taps, int m, int nb,
+                                            float* smem, int tile) {
+    constexpr int NIN = FilterIn<MODE>::N;
+    const uintptr_t bits = (uintptr_t)a.in0 | (NIN > 1 ? (uintptr_t)a.in1 : 0) | (NIN > 2 ? (uintptr_t)a.in2 : 0) |
+                           (NIN > 3 ? (uintptr_t)a.in3 : 0);
+    if ((nb & 15) == 0 && (bits & 15) == 0)
+        filter_tile<MODE, true>(a, taps, m, nb, smem, tile);
+    else
+        filter_tile<MODE, false>(a, taps, m, nb, smem, tile);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(FTHREADS) void filter_mfma_kernel(FilterArgs a, const float* __restrict__ taps, int m,
+                                                               int nb) {
     extern __shared__ float smem[];
-    filter_body<MODE>(a, taps, m, nb, smem, blockIdx.x, blockIdx.y);
+    filter_body<MODE>(a, taps, m, nb, smem, blockIdx.x);
 }
 
 size_t filter_lds_bytes(int nb) {
-    return sizeof(float) * ((size_t)(2 * nb - 1 + FBK + FBN) + FBM * FSTRIDE);
+    return sizeof(float) * ((size_t)filter_taps_floats(nb) + (size_t)FKS * FNT * 256);
 }
 
 hipError_t launch_filter_f32(const FilterArgs& a, const float* taps32, int m, int nb, hipStream_t s) {
-    dim3 grid((nb + FBN - 1) / FBN, (m + FBM - 1) / FBM);
+    const int grid = filter_blocks_x(nb) * filter_blocks_y(m);
     const size_t lds = filter_lds_bytes(nb);
     switch (a.mode) {
-        case FILT_EXTRAP: filter_mfma_kernel<FILT_EXTRAP><<<grid, 256, lds, s>>>(a, taps32, m, nb); break;
-        case FILT_DUAL_LD: filter_mfma_kernel<FILT_DUAL_LD><<<grid, 256, lds, s>>>(a, taps32, m, nb); break;
-        case FILT_DUAL_FV: filter_mfma_kernel<FILT_DUAL_FV><<<grid, 256, lds, s>>>(a, taps32, m, nb); break;
-        default: filter_mfma_kernel<FILT_PLAIN><<<grid, 256, lds, s>>>(a, taps32, m, nb); break;
+        case FILT_EXTRAP: filter_mfma_kernel<FILT_EXTRAP><<<grid, FTHREADS, lds, s>>>(a, taps32, m, nb); break;
+        case FILT_DUAL_LD: filter_mfma_kernel<FILT_DUAL_LD><<<grid, FTHREADS, lds, s>>>(a, taps32, m, nb); break;
+        case FILT_DUAL_FV: filter_mfma_kernel<FILT_DUAL_FV><<<grid, FTHREADS, lds, s>>>(a, taps32, m, nb); break;
+        default: filter_mfma_kernel<FILT_PLAIN><<<grid, FTHREADS, lds, s>>>(a, taps32, m, nb); break;
     }
     return hipGetLastError();
 }
@@ -263,7 +314,7 @@ hipError_t launch_filter_f32(const FilterArgs& a, const float* taps32, int m, in
 // (q), the extrapolation's W^-1 (mu^k - mu^{k-1}) by the previous dual update
 // (sx), so every launch runs the plain prologue.
 template <int MODE>
-__global__ __launch_bounds__(256) void filter_batched(const BatchItem* __restrict__ items,
+__global__ __launch_bounds__(FTHREADS) void filter_batched(const BatchItem* __restrict__ items,
                                                       const BlockRef* __restrict__ map, int rot) {
     extern __shared__ float smem[];
     const BlockRef e = map[blockIdx.x];
@@ -294,43 +345,41 @@ __global__ __launch_bounds__(256) void filter_batched(const BatchItem* __restric
         a.Sw = it.winv;
         a.Sout = it.sx;
     }
-    const int gx = (it.nb + FBN - 1) / FBN;
-    filter_body<FILT_PLAIN>(a, it.taps, it.m, it.nb, smem, e.local % gx, e.local / gx);
+    filter_body<FILT_PLAIN>(a, it.taps, it.m, it.nb, smem, e.local);
 }
 
 hipError_t launch_filter_batched(const BatchItem* items, const BlockRef* map, int nblocks, int mode, int rot,
                                  int max_nb, hipStream_t s) {
     const size_t lds = filter_lds_bytes(max_nb);
     switch (mode) {
-        case FILT_EXTRAP: filter_batched<FILT_EXTRAP><<<nblocks, 256, lds, s>>>(items, map, rot); break;
-        case FILT_DUAL_LD: filter_batched<FILT_DUAL_LD><<<nblocks, 256, lds, s>>>(items, map, rot); break;
-        case FILT_DUAL_FV: filter_batched<FILT_DUAL_FV><<<nblocks, 256, lds, s>>>(items, map, rot); break;
-        default: filter_batched<FILT_PLAIN><<<nblocks, 256, lds, s>>>(items, map, rot); break;
+        case FILT_EXTRAP: filter_batched<FILT_EXTRAP><<<nblocks, FTHREADS, lds, s>>>(items, map, rot); break;
+        case FILT_DUAL_LD: filter_batched<FILT_DUAL_LD><<<nblocks, FTHREADS, lds, s>>>(items, map, rot); break;
+        case FILT_DUAL_FV: filter_batched<FILT_DUAL_FV><<<nblocks, FTHREADS, lds, s>>>(items, map, rot); break;
+        default: filter_batched<FILT_PLAIN><<<nblocks, FTHREADS, lds, s>>>(items, map, rot); break;
     }
     return hipGetLastError();
 }
 
 // One recorded filter step per problem (the unrolled passes).
 template <int MODE>
-__global__ __launch_bounds__(256) void step_filter_kernel(const UStep* __restrict__ steps,
+__global__ __launch_bounds__(FTHREADS) void step_filter_kernel(const UStep* __restrict__ steps,
                                                           const BlockRef* __restrict__ map) {
     extern __shared__ float smem[];
     const BlockRef e = map[blockIdx.x];
     if (e.prob < 0) return;
     const UStep& st = steps[e.prob];
     if (!st.active) return;
-    const int gx = (st.nb + FBN - 1) / FBN;
-    filter_body<MODE>(st.fa, st.taps, st.m, st.nb, smem, e.local % gx, e.local / gx);
+    filter_body<MODE>(st.fa, st.taps, st.m, st.nb, smem, e.local);
 }
 
 hipError_t launch_step_filter(const UStep* steps, const BlockRef* map, int nblocks, int mode, int max_nb,
                               hipStream_t s) {
     const size_t lds = filter_lds_bytes(max_nb);
     switch (mode) {
-        case FILT_EXTRAP: step_filter_kernel<FILT_EXTRAP><<<nblocks, 256, lds, s>>>(steps, map); break;
-        case FILT_DUAL_LD: step_filter_kernel<FILT_DUAL_LD><<<nblocks, 256, lds, s>>>(steps, map); break;
-        case FILT_DUAL_FV: step_filter_kernel<FILT_DUAL_FV><<<nblocks, 256, lds, s>>>(steps, map); break;
-        default: step_filter_kernel<FILT_PLAIN><<<nblocks, 256, lds, s>>>(steps, map); break;
+        case FILT_EXTRAP: step_filter_kernel<FILT_EXTRAP><<<nblocks, FTHREADS, lds, s>>>(steps, map); break;
+        case FILT_DUAL_LD: step_filter_kernel<FILT_DUAL_LD><<<nblocks, FTHREADS, lds, s>>>(steps, map); break;
+        case FILT_DUAL_FV: step_filter_kernel<FILT_DUAL_FV><<<nblocks, FTHREADS, lds, s>>>(steps, map); break;
+        default: step_filter_kernel<FILT_PLAIN><<<nblocks, FTHREADS, lds, s>>>(steps, map); break;
     }
     return hipGetLastError();
 }
