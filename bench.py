@@ -57,15 +57,17 @@ A_FLOP_PER_STEP = 9.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 N_INSTANCES = 3   # independent inputs cycled through by the timed solves
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "projector_kernels_lowdose512_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lowdose512_kernels_traffic.md")
+# the source file of each kernel whose HBM traffic the counter summary records
+KERNEL_SOURCES = {"forward": "projector.hip", "adjoint": "projector.hip", "filter": "filter.hip", "tv": "tv.hip"}
 
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    src = os.path.join(ROOT, "paper_1609_06041_amd", "csrc", "projector.hip")
+def kernel_source_hash(kernel: str) -> str:
+    src = os.path.join(ROOT, "paper_1609_06041_amd", "csrc", KERNEL_SOURCES[kernel])
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
@@ -96,8 +98,9 @@ def forward_ray_steps(n: int, m: int, nb: int) -> int:
 
 
 def read_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` ("forward" or "adjoint") from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    """HBM bytes per launch of `kernel` ("forward", "adjoint", "filter", "tv") from
+    the committed rocprofv3 counter summary, if it was taken on the kernel's
+    current source file."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -105,7 +108,7 @@ def read_traffic(kernel: str):
         if ":" in line and line.strip().startswith("- "):
             k, v = line.strip()[2:].split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("source_sha256_16") != kernel_source_hash():
+    if vals.get(f"{kernel}_source_sha256_16") != kernel_source_hash(kernel):
         return None
     try:
         return float(vals[f"{kernel}_hbm_bytes_per_launch"])
@@ -487,7 +490,8 @@ def main() -> int:
                          "and reverse pass vs 16 plain solves")
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 --pmc: a plain 256 MiB device copy (counter calibration) "
-                         "followed by 5 A and 5 A^T launches on the workload; prints nothing else")
+                         "followed by 5 launches each of A, A^T, the filter D and the 10-step TV prox on the "
+                         "workload; prints nothing else")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -531,6 +535,11 @@ def main() -> int:
             op.project(img, out=sino)
         for _ in range(5):
             op.backproject(b, out=img_out)
+        for _ in range(5):
+            op.ramp_filter(b, 2.0e-8, 3.5e-5, out=sino)
+        pz = torch.zeros((2, n, n), device=dev, dtype=torch.float32)
+        for _ in range(5):
+            op.tv_prox(img, 1e-3, pz, n_iter=10, out=img_out)
         torch.cuda.synchronize()
         op.close()
         log("counter run done")
@@ -570,6 +579,8 @@ def main() -> int:
     updates = float(m) * n * n
     ray_steps = float(forward_ray_steps(n, m, nb))
     a_tflops = A_FLOP_PER_STEP * ray_steps / (t_a * 1e-3) / 1e12
+    d_tflops = 2.0 * m * nb * nb / (t_d * 1e-3) / 1e12
+    tv_gbs = 24.0 * n * n / (t_tv10 * 1e-3) / 1e9
     at_tflops = AT_FLOP_PER_UPDATE * updates / (t_at * 1e-3) / 1e12
     peak_note = ("FP32 vector peak: 256 CU x 128 FMA lanes x 2.4 GHz x 2 (plain v_fma_f32 exceeds 64 lanes/CU/clock "
                  "on gfx950: a register-only FMA loop reaches 95 TFLOP/s)")
@@ -604,7 +615,7 @@ def main() -> int:
         "A_gupdates_per_s": updates / (t_a * 1e-3) / 1e9,
         "AT_gupdates_per_s": updates / (t_at * 1e-3) / 1e9,
         "op_ms": {"A": t_a, "AT": t_at, "D": t_d, "tv_step": t_tv10 / 10.0},
-        "filter_mfma_tflops": 2.0 * m * nb * nb / (t_d * 1e-3) / 1e12,
+        "filter_mfma_tflops": d_tflops,
         "tv_step_gbs": 20.0 * n * n / (t_tv10 / 10.0 * 1e-3) / 1e9,
         "roofline": {"kernel": "forward_slab_kernel (A; timed per ctpd_project call, which also pads the image planes)", "bound": "alu",
                      "achieved": a_tflops, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
@@ -616,6 +627,14 @@ def main() -> int:
                         "frac": at_tflops / PEAK_FP32_VECTOR_TFLOPS, "traffic": read_traffic("adjoint"),
                         "work_per_launch": f"{updates:.4g} (pixel, view) updates x {AT_FLOP_PER_UPDATE:.0f} FLOP",
                         "peak_note": peak_note},
+        "roofline_filter": {"kernel": "filter_mfma_kernel (D, one launch per ctpd_filter after its taps kernel)",
+                            "bound": "mfma", "achieved": d_tflops, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                            "frac": d_tflops / PEAK_FP32_MFMA_TFLOPS, "traffic": read_traffic("filter"),
+                            "work_per_launch": f"dense Toeplitz contraction 2 x {m} x {nb} x {nb} FLOP (FP32 MFMA)"},
+        "roofline_tv": {"kernel": "tv_prox_kernel (10 dual steps fused, one launch per ctpd_tv_prox)",
+                        "bound": "alu", "achieved_gbs": tv_gbs, "hbm_frac": tv_gbs / PEAK_HBM_GBS,
+                        "traffic": read_traffic("tv"),
+                        "work_per_launch": f"algorithmic bytes 24 x {n}^2 (z, p in; p, x out; FP32)"},
         "accuracy": "parity-tested vs the FP64 oracle: A, A^T, D rel l2 <= 1e-5; x^k rel l2 <= 1e-4; "
                     "cost rel <= 1e-5 (tests/test_gpu_*.py)",
         "paper_context": "paper (no hardware stated): ~10 Algorithm-1 iterations match GIST at 1000; "

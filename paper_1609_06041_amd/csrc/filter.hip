@@ -125,7 +125,8 @@ hipError_t launch_taps(double* taps64, float* taps32, int nb, int m, double tau,
 // fixed pairwise order, so every launch form gives the same bits.  Within a
 // chunk, MFMA step t of lane (i, q) (i = lane % 16, q = lane / 16) takes
 //     A[i][q] = s[v0 + i][k0 + 4q + t],  B[q][c] = h[n0 + c - (k0 + 4q + t)],
-// so a lane reads its 4 input values with one 16-byte load; the taps of the
+// so a lane reads its 4 input values with one 16-byte load (where the row
+// length and alignment allow); the taps of the
 // block's range of offsets are staged once in LDS.  The next chunk's loads are
 // issued before the current chunk's MFMAs.
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -150,23 +151,37 @@ struct FilterIn {
     }
 };
 
-// The filter input s[v][k0 + 4q + t], t = 0..3, of one lane.  VEC: nb % 16 == 0
-// and every input 16-byte aligned, so each chunk is whole and one 16-byte load
-// per input reads it.  Otherwise scalar loads at clamped columns, masked after
-// the load (no branches: the compiler can keep the loads in flight).
-template <int MODE, bool VEC>
+// The filter input s[v][kk + t], t = 0..3, of one lane (kk = k0 + 4q).  VW is
+// the load width the row allows: 4 (nb % 4 == 0 and every input 16-byte
+// aligned: one 16-byte load per input), 2 (nb even, 8-byte aligned: two
+// 8-byte loads) or 1 (four scalar loads).  Loads past the row end are clamped
+// into it and masked after the load; there are no branches, so the compiler
+// keeps the loads in flight.
+template <int MODE, int VW>
 __device__ __forceinline__ void filter_load_chunk(const FilterArgs& a, size_t row, int nb, int kk, float (&dst)[4]) {
     constexpr int NIN = FilterIn<MODE>::N;
     const float* src[4] = {a.in0, a.in1, a.in2, a.in3};
     float r[NIN][4];
-    if (VEC) {
+    if (VW == 4) {
+        const size_t col = row + min(kk, nb - 4);
 #pragma unroll
         for (int q = 0; q < NIN; ++q) {
-            const float4 x = *reinterpret_cast<const float4*>(src[q] + row + kk);
+            const float4 x = *reinterpret_cast<const float4*>(src[q] + col);
             r[q][0] = x.x;
             r[q][1] = x.y;
             r[q][2] = x.z;
             r[q][3] = x.w;
+        }
+    } else if (VW == 2) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const size_t col = row + min(kk + 2 * h, nb - 2);
+#pragma unroll
+            for (int q = 0; q < NIN; ++q) {
+                const float2 x = *reinterpret_cast<const float2*>(src[q] + col);
+                r[q][2 * h] = x.x;
+                r[q][2 * h + 1] = x.y;
+            }
         }
     } else {
 #pragma unroll
@@ -181,7 +196,7 @@ __device__ __forceinline__ void filter_load_chunk(const FilterArgs& a, size_t ro
         float rr[NIN];
 #pragma unroll
         for (int q = 0; q < NIN; ++q) rr[q] = r[q][t];
-        dst[t] = (VEC || kk + t < nb) ? FilterIn<MODE>::combine(rr) : 0.0f;
+        dst[t] = kk + t < nb ? FilterIn<MODE>::combine(rr) : 0.0f;
     }
 }
 
@@ -191,7 +206,7 @@ __host__ __device__ constexpr int filter_taps_floats(int nb) {
     return ((((nb + 15) / 16) * 16 + FBN + 63) / 64) * 64;
 }
 
-template <int MODE, bool VEC>
+template <int MODE, int VW>
 __device__ __forceinline__ void filter_tile(const FilterArgs& a, const float* __restrict__ taps, int m, int nb,
                                             float* smem, int tile) {
     const int tiles_x = (nb + FBN - 1) / FBN;
@@ -205,7 +220,7 @@ __device__ __forceinline__ void filter_tile(const FilterArgs& a, const float* __
     const size_t row = (size_t)min(v0 + li, m - 1) * nb;   // rows past m only feed outputs never stored
     float cur[4], nxt[4];
     int c = w;
-    filter_load_chunk<MODE, VEC>(a, row, nb, 16 * min(c, nch - 1) + 4 * lq, cur);
+    filter_load_chunk<MODE, VW>(a, row, nb, 16 * min(c, nch - 1) + 4 * lq, cur);
     const int ntl = kpad + FBN - 1;
     for (int x = tid; x < ntl; x += FTHREADS) {
         const int d = n0 + x - (kpad - 1);
@@ -223,20 +238,16 @@ __device__ __forceinline__ void filter_tile(const FilterArgs& a, const float* __
             for (int j = 0; j < FNT; ++j)
                 acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], tl[bl + 16 * j - k0 - t], acc[j], 0, 0, 0);
     };
-    // chunks c, c + FKS, ... in pairs; a pair's second chunk past the end
-    // counts with a zero input
+    // chunks c, c + FKS, ... in pairs (loads clamped to the last chunk, so
+    // they are unconditional); a pair's second chunk past the end is skipped
     for (; c < nch; c += 2 * FKS) {
-        const int c1 = min(c + FKS, nch - 1);
-        filter_load_chunk<MODE, VEC>(a, row, nb, 16 * c1 + 4 * lq, nxt);
+        filter_load_chunk<MODE, VW>(a, row, nb, 16 * min(c + FKS, nch - 1) + 4 * lq, nxt);
         __builtin_amdgcn_sched_barrier(0);
         mma(cur, 16 * c);
         __builtin_amdgcn_sched_barrier(0);
-        filter_load_chunk<MODE, VEC>(a, row, nb, 16 * min(c + 2 * FKS, nch - 1) + 4 * lq, cur);
+        filter_load_chunk<MODE, VW>(a, row, nb, 16 * min(c + 2 * FKS, nch - 1) + 4 * lq, cur);
         __builtin_amdgcn_sched_barrier(0);
-        const bool ok = c + FKS < nch;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) nxt[t] = ok ? nxt[t] : 0.0f;
-        mma(nxt, 16 * c1);
+        if (c + FKS < nch) mma(nxt, 16 * (c + FKS));
     }
     // MFMA 16x16 result: D[i][c] in lane c + 16 (i / 4), element i % 4
 #pragma unroll
@@ -270,7 +281,7 @@ __device__ __forceinline__ void filter_tile(const FilterArgs& a, const float* __
     }
 }
 
-// Both load forms give the same values and the same MFMA sequence, so the
+// Every load width gives the same values and the same MFMA sequence, so the
 // choice (per workgroup, from nb and the input addresses) never changes a bit.
 template <int MODE>
 __device__ __forceinline__ void filter_body(const FilterArgs& a, const float* __restrict__ taps, int m, int nb,
@@ -278,10 +289,12 @@ __device__ __forceinline__ void filter_body(const FilterArgs& a, const float* __
     constexpr int NIN = FilterIn<MODE>::N;
     const uintptr_t bits = (uintptr_t)a.in0 | (NIN > 1 ? (uintptr_t)a.in1 : 0) | (NIN > 2 ? (uintptr_t)a.in2 : 0) |
                            (NIN > 3 ? (uintptr_t)a.in3 : 0);
-    if ((nb & 15) == 0 && (bits & 15) == 0)
-        filter_tile<MODE, true>(a, taps, m, nb, smem, tile);
+    if ((nb & 3) == 0 && (bits & 15) == 0)
+        filter_tile<MODE, 4>(a, taps, m, nb, smem, tile);
+    else if ((nb & 1) == 0 && (bits & 7) == 0)
+        filter_tile<MODE, 2>(a, taps, m, nb, smem, tile);
     else
-        filter_tile<MODE, false>(a, taps, m, nb, smem, tile);
+        filter_tile<MODE, 1>(a, taps, m, nb, smem, tile);
 }
 
 template <int MODE>
