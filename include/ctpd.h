@@ -185,6 +185,30 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
 int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd_params* p,
                           float* x_out, ctpd_report* rep);
 
+/* Error-tolerant few-view reconstruction, the extension the conclusions
+ * (Sec. 5) name for noisy few-view data:
+ *   min psi(x)  s.t.  ||A x - b|| <= eps,  x >= 0.
+ * Posed like Eqs. 6-7: a data-side variable y with the preconditioned
+ * constraint D^1/2 (A x - y) = 0 and the indicator of the ball
+ * {y : ||y - b|| <= eps} as its data term; APP on the pair (x, y) gives
+ * Eqs. 29-31 with the primal step split into the TV prox of Eq. 17 and the
+ * Euclidean projection onto the ball.  Per iteration from x = 0, y = b,
+ * mu = 0:
+ *   mubar = -sigma D b (k = 0), 2 mu^k - mu^{k-1} (k >= 1)
+ *   x = prox(x - tau A^T mubar);  y = P_ball(y + tau mubar)
+ *   mu = mu + sigma D (A x - y)       (D the ramp of Eq. 32).
+ * eps = 0 keeps y = b and gives Algorithm 2 (ctpd_pd_fewview_solve) bit for
+ * bit at the same tau and sigma.  Step sizes: sigma < 1/lambda_max(K^T D(1) K)
+ * with K = [A, -I] (Eq. 16 for the pair; D(tau) = D(1)/tau), checked when
+ * given (CTPD_EINVAL), default rho / lambda_max (computed in float64 by the
+ * first solve on the handle and cached); default tau as in
+ * ctpd_pd_fewview_solve.  The report's lambda_a is lambda_max(K^T D(tau) K).
+ * eps: finite and >= 0 (CTPD_EINVAL otherwise).  Monitors: cost (psi),
+ * resid (||A x - b|| / ||b||), rmse; not gap.  Other arguments as for
+ * ctpd_pd_fewview_solve. */
+int ctpd_pd_fewview_eps_solve(ctpd_op* op, const float* b, double eps, int32_t iters,
+                              const ctpd_params* p, float* x_out, ctpd_report* rep);
+
 /* ---- batched solves ------------------------------------------------------
  * Many independent low-dose problems (Eq. 1) of uneven image sizes and view
  * counts solved together by Algorithm 1, each with its own set-up exactly as

@@ -746,7 +746,7 @@ void ctpd_op_destroy(ctpd_op* op) {
                     op->mubar, op->q, op->sx, op->winv, op->taps64, op->taps32, op->partials, op->red, op->cost_dev,
                     op->img64[0], op->img64[1], op->img64[2], op->pad64[0], op->pad64[1], op->sino64[0], op->sino64[1],
                     op->sino64[2], op->sino64[3], op->sino64[4], op->sino64[5], op->lz[0], op->lz[1],
-                    op->lz_partials[0], op->lz_partials[1], op->xbar};
+                    op->lz_partials[0], op->lz_partials[1], op->xbar, op->ball_y, op->split64, op->ball_dev};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (op->red_host) (void)hipHostFree(op->red_host);
@@ -968,6 +968,25 @@ int ctpd_app_identity_lowdose_solve(ctpd_op* op, const float* b, const float* w,
     return CTPD_OK;
 }
 
+// The few-view default tau = mean |sigma A^T D(1) b| (a step size: formed in
+// float64 like the norms).  In Algorithm 2 tau only weighs the TV term against
+// the constraint (sigma D(tau) = sigma D(1) / tau).
+static int fewview_default_tau(ctpd_op* op, const float* b, double sigma, double* tau) {
+    int r;
+    hipStream_t s = op->stream;
+    if ((r = ensure_taps(op, 1.0, 0.0))) return r;
+    if ((r = ensure_f64(op))) return r;
+    HIP_TRY(launch_widen_f64(op->sino64[0], b, op->I, s));
+    HIP_TRY(launch_filter_f64(op->sino64[0], op->sino64[1], op->taps64, nullptr, nullptr, op->m, op->nb, s));
+    HIP_TRY(launch_adjoint<double>(op->sino64[1], nullptr, 1.0, 0.0, nullptr, 0.0, 1.0, op->img64[0], op->views,
+                                   op->n, op->m, op->nb, s));
+    if ((r = reduce(op, RED_ABS_F64, op->img64[0], nullptr, nullptr, op->J, 0))) return r;
+    if ((r = read_red(op))) return r;
+    *tau = sigma * op->red_host[0] / (double)op->J;
+    if (!(*tau > 0)) *tau = 1.0;   // all-zero data: any tau works
+    return CTPD_OK;
+}
+
 int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd_params* p, float* x_out,
                           ctpd_report* rep) {
     g_errmsg[0] = 0;
@@ -1018,19 +1037,7 @@ int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
         sigma = k.rho / lam1;
     }
     double tau = k.tau;
-    if (!(tau > 0)) {
-        // tau = mean |sigma A^T D(1) b|, a step size: formed in float64 like the norms
-        if ((r = ensure_taps(op, 1.0, 0.0))) return r;
-        if ((r = ensure_f64(op))) return r;
-        HIP_TRY(launch_widen_f64(op->sino64[0], b, I, s));
-        HIP_TRY(launch_filter_f64(op->sino64[0], op->sino64[1], op->taps64, nullptr, nullptr, op->m, op->nb, s));
-        HIP_TRY(launch_adjoint<double>(op->sino64[1], nullptr, 1.0, 0.0, nullptr, 0.0, 1.0, op->img64[0], op->views,
-                                       op->n, op->m, op->nb, s));
-        if ((r = reduce(op, RED_ABS_F64, op->img64[0], nullptr, nullptr, J, 0))) return r;
-        if ((r = read_red(op))) return r;
-        tau = sigma * op->red_host[0] / (double)J;
-        if (!(tau > 0)) tau = 1.0;   // all-zero data: any tau works
-    }
+    if (!(tau > 0) && (r = fewview_default_tau(op, b, sigma, &tau))) return r;
     if ((r = ensure_taps(op, tau, 0.0))) return r;
     if ((r = sync(op))) return r;
     const double setup_ms = ms_since(t0);
@@ -1099,6 +1106,178 @@ int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
     return CTPD_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// The error-tolerant few-view problem the conclusions (Sec. 5) name:
+//     min psi(x)  s.t.  ||A x - b|| <= eps,  x >= 0,
+// posed like Eqs. 6-7: a data-side variable y with the preconditioned
+// constraint D^1/2 (A x - y) = 0 and the indicator of the ball
+// B(b, eps) = {y : ||y - b|| <= eps} as its data term.  APP on the pair (x, y)
+// (Eqs. 29-31 with the primal prox split into the TV prox of Eq. 17 and the
+// projection onto the ball):
+//     mubar = -sigma D b (k = 0, y^0 = b), 2 mu^k - mu^{k-1} (k >= 1)
+//     x^{k+1} = prox(x^k - tau A^T mubar),   y^{k+1} = P_B(y^k + tau mubar)
+//     mu^{k+1} = mu^k + sigma D (A x^{k+1} - y^{k+1})
+// with sigma tau lambda_max(K^T D(tau) K) < 1, K = [A, -I], i.e.
+// sigma lambda_max(K^T D(1) K) < 1.  eps = 0 keeps y = b bit for bit and is
+// Algorithm 2.
+
+// lambda_max(K^T D(1) K) over the float64 pair (x, y), K (x, y) = A x - y:
+// (x, y) -> (A^T s, -s) with s = D(1) (A x - y); needs the taps at tau = 1.
+static int setup_lambda_split(ctpd_op* op, int kmax, Lanczos* L) {
+    int r = ensure_f64(op);
+    if (r) return r;
+    if ((r = ensure_lz(op, kmax))) return r;
+    const size_t J = op->J, I = op->I, len = J + I;
+    if (!op->split64) ALLOC(op->split64, 3 * len);
+    double *s1 = op->sino64[4], *s2 = op->sino64[5];
+    hipStream_t s = op->stream;
+    L->op = op;
+    L->chain = 0;
+    L->per_round = 4;
+    L->s = s;
+    L->q = op->split64;
+    L->qp = op->split64 + len;
+    L->w = op->split64 + 2 * len;
+    L->kmax = kmax;
+    L->apply = [op, s1, s2, s, J, I](const double* in, double* out) -> int {
+        HIP_TRY(launch_pad_planes<double>(in, op->pad64[0], op->pad64[1], op->n, s));
+        HIP_TRY(launch_forward<double>(op->pad64[0], op->pad64[1], s1, op->views, op->n, op->m, op->nb, s));
+        HIP_TRY(launch_axpby_f64(s1, in + J, -1.0, 1.0, nullptr, 0.0, I, s));   // A x - y
+        HIP_TRY(launch_filter_f64(s1, s2, op->taps64, nullptr, nullptr, op->m, op->nb, s));
+        HIP_TRY(launch_adjoint<double>(s2, nullptr, 1.0, 0.0, nullptr, 0.0, 1.0, out, op->views, op->n, op->m,
+                                       op->nb, s));
+        HIP_TRY(launch_scale_f64(out + J, s2, -1.0, I, s));
+        return CTPD_OK;
+    };
+    return L->start(1, (int)len, 3, nullptr, 0.0);
+}
+
+int ctpd_pd_fewview_eps_solve(ctpd_op* op, const float* b, double eps, int32_t iters, const ctpd_params* p,
+                              float* x_out, ctpd_report* rep) {
+    g_errmsg[0] = 0;
+    if (!op || !b || !x_out) return einval("null pointer");
+    if (iters < 0) return einval("iters < 0");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return einval("eps must be finite and >= 0");
+    Knobs k;
+    int r = read_params(p, &k);
+    if (r) return r;
+    Monitors M;
+    if ((r = read_monitors(rep, false, &k, &M))) return r;
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t I = op->I, J = op->J;
+    hipStream_t s = op->stream;
+    if ((r = reduce(op, RED_SQ_F32, b, nullptr, nullptr, I, 0))) return r;
+    if ((r = read_red(op))) return r;
+    if (op->red_host[1] > 0) {
+        snprintf(g_errmsg, sizeof g_errmsg, "%.0f non-finite data values", op->red_host[1]);
+        return CTPD_EDOMAIN;
+    }
+    M.bnorm2 = op->red_host[0];
+    // sigma < 1 / lambda_max(K^T D(1) K) (a property of the geometry, computed
+    // by the first solve on the handle); default rho / lambda_max
+    double sigma = k.sigma, lam1 = 0.0;
+    int steps_a = 0;
+    if (op->norm_split > 0.0 && op->norm_split_kmax == k.norm_steps) {
+        lam1 = op->norm_split;
+    } else {
+        if ((r = ensure_taps(op, 1.0, 0.0))) return r;
+        Lanczos La;
+        if ((r = setup_lambda_split(op, k.norm_steps, &La))) return r;
+        if ((r = run_lanczos({&La}))) return r;
+        lam1 = La.theta;
+        steps_a = La.steps;
+        op->norm_split = lam1;
+        op->norm_split_kmax = k.norm_steps;
+    }
+    if (sigma > 0) {
+        if (!(sigma * lam1 < 1.0)) {
+            snprintf(g_errmsg, sizeof g_errmsg,
+                     "invalid argument: sigma = %.6g violates the step-size bound of the error-tolerant few-view "
+                     "iteration: needs sigma < 1/lambda_max(K^T D(1) K) = %.6g (K = [A, -I])",
+                     sigma, 1.0 / lam1);
+            return CTPD_EINVAL;
+        }
+    } else {
+        sigma = k.rho / lam1;
+    }
+    double tau = k.tau;
+    if (!(tau > 0) && (r = fewview_default_tau(op, b, sigma, &tau))) return r;
+    if ((r = ensure_taps(op, tau, 0.0))) return r;
+    if (!op->ball_y) ALLOC(op->ball_y, I);
+    if (!op->ball_dev) ALLOC(op->ball_dev, 2);
+    if ((r = sync(op))) return r;
+    const double setup_ms = ms_since(t0);
+    const auto t1 = std::chrono::steady_clock::now();
+    if (k.record && (r = ensure_cost(op, iters))) return r;
+    float* y = op->ball_y;
+    HIP_TRY(launch_fill_f32(op->x, 0.f, J, s));
+    HIP_TRY(launch_fill_f32(op->p[0], 0.f, 2 * J, s));
+    HIP_TRY(launch_fill_f32(op->mu[0], 0.f, I, s));
+    HIP_TRY(launch_fill_f32(op->mu[1], 0.f, I, s));
+    HIP_TRY(launch_copy_f32(y, b, I, s));
+    float *mu = op->mu[0], *mup = op->mu[1], *mun = op->mu[2];
+    float* pcur = op->p[0];
+    const float fs = (float)sigma, ft = (float)tau, lam = (float)tau;
+    const float tvstep = (float)(k.tv_step / tau);
+    for (int it = 0; it < iters; ++it) {
+        // z = x - tau A^T mubar and y + tau mubar, mubar = -sigma D b (k = 0) or 2 mu - mu_prev
+        if (it == 0) {
+            if ((r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, -fs,
+                            op->mubar)))
+                return r;
+            HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, op->x, 1.f, -ft, op->z, op->views, op->n,
+                                          op->m, op->nb, s));
+        } else {
+            HIP_TRY(launch_adjoint<float>(mu, mup, 2.f, -1.f, op->x, 1.f, -ft, op->z, op->views, op->n, op->m,
+                                          op->nb, s));
+        }
+        float* pnew = nullptr;
+        const bool padded = lam > 0.f;
+        if ((r = tv_prox(op, op->z, lam, k.tv_iters, tvstep, pcur, pcur == op->p[0] ? op->p[1] : op->p[0], op->x,
+                         &pnew, true)))
+            return r;
+        pcur = pnew;
+        // y^{k+1} = P_B(y^k + tau mubar)
+        if (it == 0)
+            HIP_TRY(launch_ball_project(y, op->mubar, 1.f, nullptr, 0.f, ft, b, eps, I, op->partials, op->ball_dev,
+                                        s));
+        else
+            HIP_TRY(launch_ball_project(y, mu, 2.f, mup, -1.f, ft, b, eps, I, op->partials, op->ball_dev, s));
+        // mu^{k+1} = mu^k + sigma D (A x^{k+1} - y^{k+1})
+        if (!k.record) {
+            if ((r = project_resid(op, op->x, y, nullptr, nullptr, op->q, padded))) return r;
+            if ((r = filter(op, FILT_PLAIN, op->q, nullptr, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun)))
+                return r;
+        } else {
+            if ((r = project_resid(op, op->x, nullptr, nullptr, nullptr, op->q, padded))) return r;
+            if ((r = filter(op, FILT_DUAL_FV, op->q, y, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun)))
+                return r;
+            if ((r = record_monitors(op, it, M, op->x, op->q, b, nullptr, nullptr))) return r;
+        }
+        float* t = mup;
+        mup = mu;
+        mu = mun;
+        mun = t;
+    }
+    op->mu[0] = mu;
+    op->mu[1] = mup;
+    op->mu[2] = mun;
+    if ((r = finish(op, iters, false, 1.0, pcur, rep, x_out, M))) return r;
+    if (rep) {
+        rep->tau = tau;
+        rep->sigma = sigma;
+        rep->kappa = 0.0;
+        rep->lambda_a = lam1 / tau;
+        rep->lambda_h = 0.0;
+        rep->norm_steps_a = steps_a;
+        rep->norm_steps_h = 0;
+        rep->iters_done = iters;
+        rep->setup_ms = setup_ms;
+        rep->loop_ms = ms_since(t1);
+    }
+    return CTPD_OK;
+}
 
 // ---------------------------------------------------------------------------
 // Comparators (unpreconditioned first-order primal-dual methods of Sec. 4).

@@ -304,6 +304,12 @@ hipError_t launch_lin3_f32(float* out, const float* a, float c0, const float* b,
                            const float* w, size_t len, hipStream_t s);
 hipError_t launch_mul_w_f64(double* out, const double* a, const float* w, size_t len, hipStream_t s);
 // out = (double) a
+// Projection onto the data ball {y : ||y - b|| <= eps}: v = y + tau (c1 m1 + c2 m2)
+// (m2 may be null), ball_out[0] = ||v - b||, ball_out[1] = min(1, eps / ||v - b||)
+// (float64, on the device), then y = b + (v - b) ball_out[1] in place.
+hipError_t launch_ball_project(float* y, const float* m1, float c1, const float* m2, float c2, float tau,
+                               const float* b, double eps, size_t len, double* partials, double* ball_out,
+                               hipStream_t s);
 hipError_t launch_widen_f64(double* out, const float* a, size_t len, hipStream_t s);
 // batched solve: zero x, p[0], mu[0], mu[1] of every problem / copy x to x_out
 // (2048 elements per workgroup)

@@ -91,6 +91,14 @@ struct ctpd_op {
     double* hv_sum = nullptr;                 // device, 3 doubles
     double* hv_sum_host = nullptr;            // pinned, two slots of 3 doubles
     hipEvent_t hv_ev[2] = {nullptr, nullptr}; // behind the copies into the two slots
+    // the error-tolerant few-view solve (allocated on first use): its data-side
+    // variable y, the three float64 Lanczos vectors over the pair (x, y), and
+    // the ball projection's norm and scale (device)
+    float* ball_y = nullptr;
+    double* split64 = nullptr;   // 3 (J + I) doubles
+    double* ball_dev = nullptr;  // 2 doubles
+    double norm_split = 0.0;     // lambda_max(K^T D(1) K), K = [A, -I]; 0 = not yet computed
+    int norm_split_kmax = 0;
     // workspaces of the unrolled solve's reverse pass (allocated on first use)
     ctpd_host::UnrolledWs* uw = nullptr;
 };

@@ -124,6 +124,73 @@ hipError_t launch_reduce(int op, const void* a, const void* b, const void* c, si
     return hipGetLastError();
 }
 
+// Projection onto the data ball {y : ||y - b|| <= eps} of the error-tolerant
+// few-view problem: v = y + tau mubar with mubar = c1 m1 + c2 m2 (m2 may be
+// null), then y = b + (v - b) min(1, eps / ||v - b||).  Both passes form
+// d = v - b with the same explicit fma, so the norm is that of the d the
+// update scales; the norm and the scale are float64 and stay on the device.
+__device__ __forceinline__ float ball_d(const float* __restrict__ y, const float* __restrict__ m1, float c1,
+                                        const float* __restrict__ m2, float c2, float tau,
+                                        const float* __restrict__ b, size_t i) {
+    const float mb = m2 ? fmaf(c2, m2[i], c1 * m1[i]) : c1 * m1[i];
+    return fmaf(tau, mb, y[i]) - b[i];
+}
+
+__global__ __launch_bounds__(256) void ball_partial_kernel(const float* __restrict__ y, const float* __restrict__ m1,
+                                                           float c1, const float* __restrict__ m2, float c2,
+                                                           float tau, const float* __restrict__ b, size_t len,
+                                                           double* __restrict__ partials) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < len; i += stride) {
+        const double d = ball_d(y, m1, c1, m2, c2, tau, b, i);
+        s0 = fma(d, d, s0);
+    }
+    block_sum3(s0, s1, s2);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x + 0] = s0;
+        partials[3 * blockIdx.x + 1] = 0.0;
+        partials[3 * blockIdx.x + 2] = 0.0;
+    }
+}
+
+// out[0] = ||v - b||, out[1] = min(1, eps / ||v - b||) (1 when v lies in the ball)
+__global__ __launch_bounds__(256) void ball_scale_kernel(const double* __restrict__ partials, int nblocks, double eps,
+                                                         double* __restrict__ out) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s0 += partials[3 * b];
+    block_sum3(s0, s1, s2);
+    if (threadIdx.x == 0) {
+        const double r = sqrt(s0);
+        out[0] = r;
+        out[1] = r <= eps ? 1.0 : eps / r;
+    }
+}
+
+__global__ __launch_bounds__(256) void ball_apply_kernel(float* __restrict__ y, const float* __restrict__ m1, float c1,
+                                                         const float* __restrict__ m2, float c2, float tau,
+                                                         const float* __restrict__ b, const double* __restrict__ sc,
+                                                         size_t len) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= len) return;
+    const float scale = (float)sc[1];
+    const float d = ball_d(y, m1, c1, m2, c2, tau, b, i);
+    y[i] = fmaf(d, scale, b[i]);
+}
+
+hipError_t launch_ball_project(float* y, const float* m1, float c1, const float* m2, float c2, float tau,
+                               const float* b, double eps, size_t len, double* partials, double* ball_out,
+                               hipStream_t s) {
+    const int nb = reduce_blocks(len);
+    ball_partial_kernel<<<nb, 256, 0, s>>>(y, m1, c1, m2, c2, tau, b, len, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ball_scale_kernel<<<1, 256, 0, s>>>(partials, nb, eps, ball_out);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    ball_apply_kernel<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(y, m1, c1, m2, c2, tau, b, ball_out, len);
+    return hipGetLastError();
+}
+
 // TV norm (Eq. 2) of a float32 image in float64.
 __global__ __launch_bounds__(256) void tv_norm_partial_kernel(const float* __restrict__ x, int n,
                                                               double* __restrict__ partials) {

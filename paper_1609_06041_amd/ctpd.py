@@ -32,6 +32,7 @@ _SIGNATURES = {
     "ctpd_pd_lowdose_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p,
                                       c_void_p]),
     "ctpd_pd_fewview_solve": (c_int, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "ctpd_pd_fewview_eps_solve": (c_int, [c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p, c_void_p]),
     "ctpd_app_identity_lowdose_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p,
                                                 c_void_p, c_void_p]),
     "ctpd_gist_lowdose_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p,
@@ -307,6 +308,17 @@ class Operator:
         rep, cost, state = self._report(iters, record_cost, return_state, monitors, x_ref)
         _check(load().ctpd_pd_fewview_solve(self._h, _ptr(b, (self.m, self.nb), "b"), int(iters), byref(prm),
                                             _ptr(out, (self.n, self.n), "out"), byref(rep)))
+        return out, self._info(rep, cost, state)
+
+    def fewview_eps_solve(self, b: torch.Tensor, eps: float, iters: int, *, tau=None, sigma=None, tv_iters=10,
+                          tv_step=0.125, safety=0.95, norm_steps=100, record_cost=False, return_state=False,
+                          monitors=(), x_ref=None, out: torch.Tensor | None = None):
+        """Error-tolerant few-view solve: min psi(x) s.t. ||Ax - b|| <= eps, x >= 0.  Returns (x, info)."""
+        out = self._img() if out is None else out
+        prm = _params(tau, sigma, tv_iters, tv_step, safety, norm_steps, record_cost)
+        rep, cost, state = self._report(iters, record_cost, return_state, monitors, x_ref)
+        _check(load().ctpd_pd_fewview_eps_solve(self._h, _ptr(b, (self.m, self.nb), "b"), float(eps), int(iters),
+                                                byref(prm), _ptr(out, (self.n, self.n), "out"), byref(rep)))
         return out, self._info(rep, cost, state)
 
     def gist_lowdose_solve(self, b: torch.Tensor, w: torch.Tensor, beta: float, iters: int, *, gamma=None,

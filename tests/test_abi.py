@@ -71,6 +71,8 @@ def test_null_arguments_are_rejected(libctpd):
     assert libctpd.ctpd_tv_prox(None, None, 0.1, 1, 0.125, None, None) == ctpd.CTPD_EINVAL
     assert libctpd.ctpd_pd_lowdose_solve(None, None, None, 0.1, 1, None, None, None) == ctpd.CTPD_EINVAL
     assert libctpd.ctpd_pd_fewview_solve(None, None, 1, None, None, None) == ctpd.CTPD_EINVAL
+    assert libctpd.ctpd_pd_fewview_eps_solve(None, None, ctypes.c_double(0.5), 1, None, None,
+                                             None) == ctpd.CTPD_EINVAL
     libctpd.ctpd_op_destroy(None)   # no-op
 
 
