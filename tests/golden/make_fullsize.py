@@ -16,11 +16,19 @@ same float32 inputs the GPU receives:
   set-up of Algorithm 2 (sigma = rho / lambda_max(A^T D(1) A), tau = mean
   |sigma A^T D(1) b|), then x^3 and x^20.
 
+* fewview_eps_512 (the same data): the error-tolerant few-view iteration
+  (min psi s.t. ||Ax - b|| <= eps, x >= 0, eps = 1e-4 ||b||: with one tau for
+  both blocks y moves by about 3e-4 ||b|| in 20 iterations, so the ball binds
+  from a few iterations on only at a small eps) with its
+  default set-up (sigma = rho / lambda_max(K^T D(1) K), K = [A, -I], and the
+  default tau), then x^3 and x^20.
+
 Each iterate is stored as 2048 seeded pixel samples plus whole-image scalars
 (norm, psi of Eq. 2, the Eq. 1 cost or ||Ax - b|| / ||b||).  Run from the
 repository root:
 
-    python tests/golden/make_fullsize.py
+    python tests/golden/make_fullsize.py            # everything (about 45 minutes)
+    python tests/golden/make_fullsize.py --only eps # recompute fewview_eps_512 only
 """
 from __future__ import annotations
 
@@ -113,8 +121,44 @@ def fewview_all():
             "seconds": time.time() - t0}
 
 
+EPS_FRAC = 1e-4
+
+
+def fewview_eps_all():
+    from oracle import app as OA
+    b, _, spec, sums = inputs("fewview_512")
+    n = spec["n"]
+    idx = sample_indices(n)
+    t0 = time.time()
+    eps = EPS_FRAC * float(np.linalg.norm(b))
+    st = OA.steps_fewview_eps(b, n)
+    snaps = {}
+
+    def monitor(x, y, mu):
+        snaps[len(snaps) + 1] = (x.copy(), float(np.linalg.norm(y - b)))
+        return 0.0
+
+    OA.fewview_eps_solve(b, n, eps, 20, tau=st.tau, sigma=st.sigma, monitor=monitor)
+    cases = []
+    for k in (3, 20):
+        x, ydist = snaps[k]
+        c = describe(x, idx)
+        c.update({"iters": k, "resid": OA.data_residual(x, b), "y_dist": ydist})
+        cases.append(c)
+    return {"inputs": sums, "eps_frac": EPS_FRAC, "eps": eps, "tau": st.tau, "sigma": st.sigma,
+            "lambda_split1": st.lambda_a * st.tau, "cases": cases, "seconds": time.time() - t0}
+
+
 def main() -> int:
     t0 = time.time()
+    if "--only" in sys.argv and sys.argv[-1] == "eps":
+        with open(OUT) as f:
+            doc = json.load(f)
+        doc["fewview_eps_512"] = fewview_eps_all()
+        with open(OUT, "w") as f:
+            json.dump(doc, f, indent=1)
+        print(f"updated {OUT} in {time.time() - t0:.0f} s", flush=True)
+        return 0
     with cf.ProcessPoolExecutor(max_workers=4) as ex:
         fv = ex.submit(fewview_all)
         steps = lowdose_steps()
@@ -126,6 +170,7 @@ def main() -> int:
         (tv, x_tv), (_, x_tv0), (bench, _) = jobs["tv"].result(), jobs["tv0"].result(), jobs["bench"].result()
         tv["rel_diff_vs_beta0"] = float(np.linalg.norm(x_tv - x_tv0) / np.linalg.norm(x_tv0))
         fewview = fv.result()
+        fewview_eps = fewview_eps_all()
     doc = {
         "generator": "tests/golden/make_fullsize.py: FP64 oracle (oracle/) on the seeded float32 inputs",
         "n_samples": N_SAMPLES,
@@ -133,6 +178,7 @@ def main() -> int:
         "lowdose_512": {"steps": {k: v for k, v in steps.items() if k != "inputs"}, "inputs": steps["inputs"],
                         "cases": [tv, bench]},
         "fewview_512": fewview,
+        "fewview_eps_512": fewview_eps,
     }
     with open(OUT, "w") as f:
         json.dump(doc, f, indent=1)

@@ -14,6 +14,9 @@ iterate is 2048 seeded pixel samples plus whole-image scalars.
   benchmark times -- on the second solve, which reuses the cached lambda_A.
 * Algorithm 2 on the 512^2 / 32 x 736 noiseless workload: default sigma and
   tau, x^3 and x^20.
+* The error-tolerant few-view solve on the same data (eps = 1e-4 ||b||, the
+  ball binding after a few iterations): default sigma (the split norm
+  lambda_max(K^T D(1) K)) and tau, x^3 and x^20.
 
 Bars: step sizes 1e-6 (tau and kappa 1e-12 where they are closed forms),
 sampled x^k relative l2 1e-4, ||x^k|| 1e-4, the Eq. 1 cost (or psi) 1e-5.
@@ -103,5 +106,24 @@ def test_fewview_full_size_default_setup(gpu, parity, golden):
             parity("sigma", abs(info["sigma"] - g["sigma"]) / g["sigma"], 1e-6)
             parity("tau", abs(info["tau"] - g["tau"]) / g["tau"], 1e-6)
             compare_iterate(parity, x, case, idx, f"k={case['iters']}")
+            parity("psi", abs(info["cost"][-1] - case["psi"]) / case["psi"], 1e-5)
+            parity("||Ax-b||/||b||", abs(info["resid"][-1] - case["resid"]) / case["resid"], 1e-4)
+
+
+def test_fewview_eps_full_size_default_setup(gpu, parity, golden):
+    g = golden["fewview_eps_512"]
+    idx = np.array(golden["sample_indices"])
+    prob, spec = S.workload_problem("fewview_512", problem_id=0, with_x_true=False)
+    b32, _ = S.as_f32_inputs(prob)
+    check_inputs(b32.astype(np.float64), None, g["inputs"])
+    n, m, nb = spec["n"], spec["m"], spec["nb"]
+    b = torch.from_numpy(b32).cuda()
+    with ctpd.Operator(n, m, nb) as op:
+        for case in g["cases"]:
+            x, info = op.fewview_eps_solve(b, g["eps"], case["iters"], record_cost=True, monitors=("resid",))
+            x = x.cpu().numpy().astype(np.float64)
+            parity("sigma", abs(info["sigma"] - g["sigma"]) / g["sigma"], 1e-6)
+            parity("tau", abs(info["tau"] - g["tau"]) / g["tau"], 1e-6)
+            compare_iterate(parity, x, case, idx, f"eps k={case['iters']}")
             parity("psi", abs(info["cost"][-1] - case["psi"]) / case["psi"], 1e-5)
             parity("||Ax-b||/||b||", abs(info["resid"][-1] - case["resid"]) / case["resid"], 1e-4)
