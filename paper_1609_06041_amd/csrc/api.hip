@@ -557,6 +557,7 @@ int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, cons
     }
     HIP_TRY(hipMemcpyAsync(items, items_host, sizeof(NormItem) * P, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_rows_start(items, rows, nrows, 2, s));
+    HIP_TRY(launch_rows_prune(items, rows, nrows, P, s));
     int max_nb = 0;
     for (ctpd_op* op : ops) max_nb = std::max(max_nb, op->nb);
     // up to 1024 bins a round is one launch (the view's product and recurrence

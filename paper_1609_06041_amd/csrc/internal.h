@@ -317,6 +317,10 @@ hipError_t launch_batch_init(const BatchItem* items, const BlockRef* map, int nb
 hipError_t launch_batch_copy_out(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s);
 // per-view lambda_h chains over the rows of a NormItem table (one wave per row)
 hipError_t launch_rows_start(const NormItem* it, const RowRef* rows, int nrows, uint64_t seed, hipStream_t s);
+// before the first round: a windowed Rayleigh-quotient lower bound per view
+// (theta), then the summary's symbol-bound pruning against the largest of them
+// (count = problems of the table; a view stopped here records 1 step)
+hipError_t launch_rows_prune(const NormItem* it, const RowRef* rows, int nrows, int count, hipStream_t s);
 hipError_t launch_rows_step(const NormItem* it, const RowRef* rows, int nrows, int rot, int j, hipStream_t s);
 // steps j0 .. j1-1 of every running chain in one launch (q in v[0], previous q
 // in v[1] on entry and exit); only when rows_round_fits(the largest nb of the

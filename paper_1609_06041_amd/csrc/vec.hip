@@ -404,6 +404,55 @@ __global__ __launch_bounds__(256) void rows_start_kernel(const NormItem* __restr
     (void)m;
 }
 
+// A lower bound of each view's eigenvalue before any Lanczos step: the
+// Rayleigh quotient of W_v^-1/2 D W_v^-1/2 at a vector supported on the
+// kLowerWin bins around the view's largest 1/w, alternating in sign under a
+// sine taper (close to the top eigenvector of a short section of the
+// ramp-like Toeplitz D).  Any vector gives a valid bound; this one lands
+// within a fraction of a percent of the largest view's eigenvalue on low-dose
+// data, so the symbol bound can stop most views before the first round.  The
+// value goes to theta[v] (each chain's running lower estimate).
+constexpr int kLowerWin = 16;
+
+__global__ __launch_bounds__(256) void rows_lower_kernel(const NormItem* __restrict__ items,
+                                                         const RowRef* __restrict__ rows, int nrows) {
+    ROW_PROLOGUE
+    // the first bin of the largest 1/w (= smallest w)
+    float wmin = 3.0e38f;
+    int imin = nb;
+    for (int u = lane; u < nb; u += 64) {
+        const float wu = it.w[base + u];
+        if (wu < wmin || (wu == wmin && u < imin)) {
+            wmin = wu;
+            imin = u;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const float wo = __shfl_xor(wmin, off);
+        const int io = __shfl_xor(imin, off);
+        if (wo < wmin || (wo == wmin && io < imin)) {
+            wmin = wo;
+            imin = io;
+        }
+    }
+    const int W = min(kLowerWin, nb);
+    const int lo = min(max(imin - W / 2 + 1, 0), nb - W);
+    const double* h = it.taps64 + (nb - 1);
+    const double* rs = it.rs + base + lo;
+    double num = 0.0, den = 0.0;
+    for (int e = lane; e < W * W; e += 64) {
+        const int a = e / W, b = e - a * W;
+        const double ua = ((a & 1) ? -1.0 : 1.0) * sin(M_PI * (a + 1) / (W + 1));
+        const double ub = ((b & 1) ? -1.0 : 1.0) * sin(M_PI * (b + 1) / (W + 1));
+        num = fma(ua * rs[a], h[a > b ? a - b : b - a] * (ub * rs[b]), num);
+        if (a == b) den = fma(ua, ua, den);
+    }
+    num = wave_sum_all(num);
+    den = wave_sum_all(den);
+    if (lane == 0) it.theta[v] = num / den;
+    (void)m;
+}
+
 // Sum over the 256-thread block, returned to every thread (fixed order).
 __device__ __forceinline__ double block_allsum(double v, double* red4) {
     v = wave_sum_all(v);
@@ -813,6 +862,14 @@ __global__ __launch_bounds__(256) void rows_summary_kernel(const NormItem* __res
 
 hipError_t launch_rows_start(const NormItem* it, const RowRef* rows, int nrows, uint64_t seed, hipStream_t s) {
     rows_start_kernel<<<(nrows + 3) / 4, 256, 0, s>>>(it, rows, nrows, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_prune(const NormItem* it, const RowRef* rows, int nrows, int count, hipStream_t s) {
+    rows_lower_kernel<<<(nrows + 3) / 4, 256, 0, s>>>(it, rows, nrows);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    rows_summary_kernel<<<count, 256, 0, s>>>(it, 1);
     return hipGetLastError();
 }
 
