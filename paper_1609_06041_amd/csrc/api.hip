@@ -993,6 +993,78 @@ static int fewview_default_tau(ctpd_op* op, const float* b, double sigma, double
     return CTPD_OK;
 }
 
+// The few-view iteration from x = 0, mu = 0 (Eqs. 29-31), shared by
+// Algorithm 2 (y null: the data side is b itself) and the error-tolerant
+// solve (y: the data-side variable, starting at b, projected onto the ball
+// {||y - b|| <= eps} after each primal step).  Leaves the iterate in op->x and
+// mu^K in op->mu[0]; *p_final gets the last TV dual field.
+static int fewview_loop(ctpd_op* op, const float* b, float* y, double eps, int iters, double tau, double sigma,
+                        const Knobs& k, const Monitors& M, float** p_final) {
+    int r;
+    hipStream_t s = op->stream;
+    const size_t I = op->I, J = op->J;
+    if (k.record && (r = ensure_cost(op, iters))) return r;
+    HIP_TRY(launch_fill_f32(op->x, 0.f, J, s));
+    HIP_TRY(launch_fill_f32(op->p[0], 0.f, 2 * J, s));
+    HIP_TRY(launch_fill_f32(op->mu[0], 0.f, I, s));
+    HIP_TRY(launch_fill_f32(op->mu[1], 0.f, I, s));
+    if (y) HIP_TRY(launch_copy_f32(y, b, I, s));
+    const float* data = y ? y : b;   // the sinogram A x is driven to
+    float *mu = op->mu[0], *mup = op->mu[1], *mun = op->mu[2];
+    float* pcur = op->p[0];
+    const float fs = (float)sigma, ft = (float)tau, lam = (float)tau;
+    const float tvstep = (float)(k.tv_step / tau);
+    for (int it = 0; it < iters; ++it) {
+        // z = x - tau A^T mubar, mubar = -sigma D b (k = 0) or 2 mu - mu_prev
+        if (it == 0) {
+            if ((r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, -fs,
+                            op->mubar)))
+                return r;
+            HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, op->x, 1.f, -ft, op->z, op->views, op->n,
+                                          op->m, op->nb, s));
+        } else {
+            HIP_TRY(launch_adjoint<float>(mu, mup, 2.f, -1.f, op->x, 1.f, -ft, op->z, op->views, op->n, op->m,
+                                          op->nb, s));
+        }
+        float* pnew = nullptr;
+        // the prox also writes the projector's planes of x
+        const bool padded = lam > 0.f;
+        if ((r = tv_prox(op, op->z, lam, k.tv_iters, tvstep, pcur, pcur == op->p[0] ? op->p[1] : op->p[0], op->x,
+                         &pnew, true)))
+            return r;
+        pcur = pnew;
+        // y^{k+1} = P_ball(y^k + tau mubar)
+        if (y) {
+            if (it == 0)
+                HIP_TRY(launch_ball_project(y, op->mubar, 1.f, nullptr, 0.f, ft, b, eps, I, op->partials,
+                                            op->ball_dev, s));
+            else
+                HIP_TRY(launch_ball_project(y, mu, 2.f, mup, -1.f, ft, b, eps, I, op->partials, op->ball_dev, s));
+        }
+        // mu^{k+1} = mu^k + sigma D (A x^{k+1} - data); without the monitors
+        // the projector writes the residual itself
+        if (!k.record) {
+            if ((r = project_resid(op, op->x, data, nullptr, nullptr, op->q, padded))) return r;
+            if ((r = filter(op, FILT_PLAIN, op->q, nullptr, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun)))
+                return r;
+        } else {
+            if ((r = project_resid(op, op->x, nullptr, nullptr, nullptr, op->q, padded))) return r;
+            if ((r = filter(op, FILT_DUAL_FV, op->q, data, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun)))
+                return r;
+            if ((r = record_monitors(op, it, M, op->x, op->q, b, nullptr, nullptr))) return r;
+        }
+        float* t = mup;
+        mup = mu;
+        mu = mun;
+        mun = t;
+    }
+    op->mu[0] = mu;
+    op->mu[1] = mup;
+    op->mu[2] = mun;
+    *p_final = pcur;
+    return CTPD_OK;
+}
+
 int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd_params* p, float* x_out,
                           ctpd_report* rep) {
     g_errmsg[0] = 0;
@@ -1004,8 +1076,7 @@ int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
     Monitors M;
     if ((r = read_monitors(rep, false, &k, &M))) return r;
     const auto t0 = std::chrono::steady_clock::now();
-    const size_t I = op->I, J = op->J;
-    hipStream_t s = op->stream;
+    const size_t I = op->I;
     if ((r = reduce(op, RED_SQ_F32, b, nullptr, nullptr, I, 0))) return r;
     if ((r = read_red(op))) return r;
     if (op->red_host[1] > 0) {
@@ -1048,54 +1119,8 @@ int ctpd_pd_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
     if ((r = sync(op))) return r;
     const double setup_ms = ms_since(t0);
     const auto t1 = std::chrono::steady_clock::now();
-    if (k.record && (r = ensure_cost(op, iters))) return r;
-    HIP_TRY(launch_fill_f32(op->x, 0.f, J, s));
-    HIP_TRY(launch_fill_f32(op->p[0], 0.f, 2 * J, s));
-    HIP_TRY(launch_fill_f32(op->mu[0], 0.f, I, s));
-    HIP_TRY(launch_fill_f32(op->mu[1], 0.f, I, s));
-    float *mu = op->mu[0], *mup = op->mu[1], *mun = op->mu[2];
-    float* pcur = op->p[0];
-    const float fs = (float)sigma, ft = (float)tau, lam = (float)tau;
-    const float tvstep = (float)(k.tv_step / tau);
-    for (int it = 0; it < iters; ++it) {
-        // Steps 1-2: z = x - tau A^T mubar, mubar = -sigma D b (k = 0) or 2 mu - mu_prev
-        if (it == 0) {
-            if ((r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, -fs,
-                            op->mubar)))
-                return r;
-            HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, op->x, 1.f, -ft, op->z, op->views, op->n,
-                                          op->m, op->nb, s));
-        } else {
-            HIP_TRY(launch_adjoint<float>(mu, mup, 2.f, -1.f, op->x, 1.f, -ft, op->z, op->views, op->n, op->m,
-                                          op->nb, s));
-        }
-        float* pnew = nullptr;
-        // the prox also writes the projector's planes of x
-        const bool padded = lam > 0.f;
-        if ((r = tv_prox(op, op->z, lam, k.tv_iters, tvstep, pcur, pcur == op->p[0] ? op->p[1] : op->p[0], op->x,
-                         &pnew, true)))
-            return r;
-        pcur = pnew;
-        // Step 3: mu^{k+1} = mu^k + sigma D (A x^{k+1} - b); without the cost
-        // monitor the projector writes the residual itself
-        if (!k.record) {
-            if ((r = project_resid(op, op->x, b, nullptr, nullptr, op->q, padded))) return r;
-            if ((r = filter(op, FILT_PLAIN, op->q, nullptr, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun)))
-                return r;
-        } else {
-            if ((r = project_resid(op, op->x, nullptr, nullptr, nullptr, op->q, padded))) return r;
-            if ((r = filter(op, FILT_DUAL_FV, op->q, b, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun)))
-                return r;
-        }
-        if (k.record && (r = record_monitors(op, it, M, op->x, op->q, b, nullptr, nullptr))) return r;
-        float* t = mup;
-        mup = mu;
-        mu = mun;
-        mun = t;
-    }
-    op->mu[0] = mu;
-    op->mu[1] = mup;
-    op->mu[2] = mun;
+    float* pcur = nullptr;
+    if ((r = fewview_loop(op, b, nullptr, 0.0, iters, tau, sigma, k, M, &pcur))) return r;
     if ((r = finish(op, iters, false, 1.0, pcur, rep, x_out, M))) return r;
     if (rep) {
         rep->tau = tau;
@@ -1171,8 +1196,7 @@ int ctpd_pd_fewview_eps_solve(ctpd_op* op, const float* b, double eps, int32_t i
     Monitors M;
     if ((r = read_monitors(rep, false, &k, &M))) return r;
     const auto t0 = std::chrono::steady_clock::now();
-    const size_t I = op->I, J = op->J;
-    hipStream_t s = op->stream;
+    const size_t I = op->I;
     if ((r = reduce(op, RED_SQ_F32, b, nullptr, nullptr, I, 0))) return r;
     if ((r = read_red(op))) return r;
     if (op->red_host[1] > 0) {
@@ -1215,60 +1239,8 @@ int ctpd_pd_fewview_eps_solve(ctpd_op* op, const float* b, double eps, int32_t i
     if ((r = sync(op))) return r;
     const double setup_ms = ms_since(t0);
     const auto t1 = std::chrono::steady_clock::now();
-    if (k.record && (r = ensure_cost(op, iters))) return r;
-    float* y = op->ball_y;
-    HIP_TRY(launch_fill_f32(op->x, 0.f, J, s));
-    HIP_TRY(launch_fill_f32(op->p[0], 0.f, 2 * J, s));
-    HIP_TRY(launch_fill_f32(op->mu[0], 0.f, I, s));
-    HIP_TRY(launch_fill_f32(op->mu[1], 0.f, I, s));
-    HIP_TRY(launch_copy_f32(y, b, I, s));
-    float *mu = op->mu[0], *mup = op->mu[1], *mun = op->mu[2];
-    float* pcur = op->p[0];
-    const float fs = (float)sigma, ft = (float)tau, lam = (float)tau;
-    const float tvstep = (float)(k.tv_step / tau);
-    for (int it = 0; it < iters; ++it) {
-        // z = x - tau A^T mubar and y + tau mubar, mubar = -sigma D b (k = 0) or 2 mu - mu_prev
-        if (it == 0) {
-            if ((r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, -fs,
-                            op->mubar)))
-                return r;
-            HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, op->x, 1.f, -ft, op->z, op->views, op->n,
-                                          op->m, op->nb, s));
-        } else {
-            HIP_TRY(launch_adjoint<float>(mu, mup, 2.f, -1.f, op->x, 1.f, -ft, op->z, op->views, op->n, op->m,
-                                          op->nb, s));
-        }
-        float* pnew = nullptr;
-        const bool padded = lam > 0.f;
-        if ((r = tv_prox(op, op->z, lam, k.tv_iters, tvstep, pcur, pcur == op->p[0] ? op->p[1] : op->p[0], op->x,
-                         &pnew, true)))
-            return r;
-        pcur = pnew;
-        // y^{k+1} = P_B(y^k + tau mubar)
-        if (it == 0)
-            HIP_TRY(launch_ball_project(y, op->mubar, 1.f, nullptr, 0.f, ft, b, eps, I, op->partials, op->ball_dev,
-                                        s));
-        else
-            HIP_TRY(launch_ball_project(y, mu, 2.f, mup, -1.f, ft, b, eps, I, op->partials, op->ball_dev, s));
-        // mu^{k+1} = mu^k + sigma D (A x^{k+1} - y^{k+1})
-        if (!k.record) {
-            if ((r = project_resid(op, op->x, y, nullptr, nullptr, op->q, padded))) return r;
-            if ((r = filter(op, FILT_PLAIN, op->q, nullptr, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun)))
-                return r;
-        } else {
-            if ((r = project_resid(op, op->x, nullptr, nullptr, nullptr, op->q, padded))) return r;
-            if ((r = filter(op, FILT_DUAL_FV, op->q, y, nullptr, nullptr, mu, 1.f, nullptr, 0.f, fs, mun)))
-                return r;
-            if ((r = record_monitors(op, it, M, op->x, op->q, b, nullptr, nullptr))) return r;
-        }
-        float* t = mup;
-        mup = mu;
-        mu = mun;
-        mun = t;
-    }
-    op->mu[0] = mu;
-    op->mu[1] = mup;
-    op->mu[2] = mun;
+    float* pcur = nullptr;
+    if ((r = fewview_loop(op, b, op->ball_y, eps, iters, tau, sigma, k, M, &pcur))) return r;
     if ((r = finish(op, iters, false, 1.0, pcur, rep, x_out, M))) return r;
     if (rep) {
         rep->tau = tau;
