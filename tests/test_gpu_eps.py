@@ -137,3 +137,23 @@ def test_eps_rejections(gpu):
         assert e.value.code == ctpd.CTPD_EINVAL
         _, info = op.fewview_eps_solve(dev(b), noise, 2, tau=0.5, sigma=0.97 * bound)
         assert info["sigma"] == 0.97 * bound
+
+
+def test_eps_rmse_monitor_and_given_angles(gpu, parity):
+    # a limited-angle scan (views over 120 degrees) and the Eq. 34 RMSE monitor
+    n, m, nb = 40, 14, 60
+    theta = np.linspace(0.0, 2.0 * np.pi / 3.0, m, endpoint=False)
+    prob = S.make_problem(94, 0, n, m, nb, 8, None, with_x_true=True)
+    x_true = np.asarray(prob.x_true, np.float64)
+    from oracle import projector as OP
+    b = np.asarray(OP.forward_project(x_true, m, nb, theta=theta), np.float32).astype(np.float64)
+    eps = 0.01 * float(np.linalg.norm(b))
+    # the oracle's error-tolerant solve takes uniform angles only: the
+    # monitors are checked against the oracle's formulas (Eq. 34, Eq. 25's
+    # residual) on the returned iterate
+    with ctpd.Operator(n, m, nb, angles=theta) as op:
+        x, info = op.fewview_eps_solve(dev(b), eps, 15, monitors=("rmse", "resid"), x_ref=dev(x_true))
+        x = host(x)
+    parity("rmse(x^K) vs the returned x", abs(info["rmse"][-1] - OA.rmse(x, x_true)) / OA.rmse(x, x_true), 1e-6)
+    ref_res = float(np.linalg.norm(OP.forward_project(x, m, nb, theta=theta) - b) / np.linalg.norm(b))
+    parity("||Ax-b||/||b|| vs the returned x", abs(info["resid"][-1] - ref_res) / ref_res, 1e-4)

@@ -99,7 +99,8 @@ def test_filter_taps_match_oracle(gpu, m, nb, tau, kappa):
 
 
 @pytest.mark.parametrize("m,nb,kappa", [(90, 96, 0.0), (90, 96, 1.6e-4), (720, 736, 0.0), (720, 736, 1.5e-5),
-                                        (32, 736, 0.0), (5, 37, 0.02), (33, 65, 0.0), (1, 1, 0.1), (47, 130, 0.3)])
+                                        (32, 736, 0.0), (5, 37, 0.02), (33, 65, 0.0), (1, 1, 0.1), (47, 130, 0.3),
+                                        (90, 546, 1.6e-4), (17, 3, 0.05)])
 def test_ramp_filter_matches_oracle(gpu, parity, m, nb, kappa):
     rng = np.random.default_rng(m * nb)
     s = f32(rng.standard_normal((m, nb)))
@@ -108,6 +109,22 @@ def test_ramp_filter_matches_oracle(gpu, parity, m, nb, kappa):
         out = host(op.ramp_filter(dev(s), tau, kappa))
     ref = OF.apply_filter(s, OF.smoothed_ramp_taps(nb, m, tau, kappa))
     parity("out", rel(out, ref), TOL)
+
+
+@pytest.mark.parametrize("m,nb", [(90, 546), (40, 96), (21, 70), (33, 65)])
+def test_ramp_filter_load_widths_agree(gpu, m, nb):
+    # the filter reads its input 16, 8 or 4 bytes a lane, as the row length
+    # and the input's address allow; every width must give the same bits
+    rng = np.random.default_rng(5 * m + nb)
+    s = f32(rng.standard_normal((m, nb)))
+    tau, kappa = math.pi * 1e-4 / (2 * m), 1e-4
+    with ctpd.Operator(8, m, nb) as op:
+        aligned = host(op.ramp_filter(dev(s), tau, kappa))
+        buf = torch.zeros(m * nb + 4, device="cuda")
+        for off in (1, 2, 3):
+            view = buf[off:off + m * nb].view(m, nb)
+            view.copy_(dev(s))
+            np.testing.assert_array_equal(host(op.ramp_filter(view, tau, kappa)), aligned)
 
 
 @pytest.mark.parametrize("m,nb,kappa", [(90, 96, 1.6e-4), (720, 736, 0.0), (5, 37, 0.02), (33, 65, 0.0),
