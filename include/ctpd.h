@@ -49,7 +49,7 @@ extern "C" {
 #define CTPD_EHIP (-3)     /* a HIP runtime call failed */
 #define CTPD_ENOMEM (-4)   /* device allocation failed */
 
-/* Maximum n_bins: the filter keeps all 2*n_bins-1 taps in LDS. */
+/* Maximum n_bins (it bounds the LDS the filters stage their taps in). */
 #define CTPD_MAX_BINS 4096
 /* Maximum number of problems in one batch. */
 #define CTPD_MAX_BATCH 4096
@@ -82,14 +82,16 @@ typedef struct {
                             Algorithm 1 / Algorithm 2 from the operator norms.
                             A given sigma must satisfy that bound strictly:
                             low-dose sigma < min(2/lambda_h, 1/(tau lambda_A)),
-                            few-view sigma lambda_max(A^T D(1) A) < 1; the norms
-                            are computed (or taken from the handle's cache) and a
-                            violation gives CTPD_EINVAL.
+                            few-view sigma lambda_max(A^T D(1) A) < 1,
+                            error-tolerant few-view sigma lambda_max(K^T D(1) K) < 1
+                            (K = [A, -I]); the norms are computed (or taken from
+                            the handle's cache) and a violation gives CTPD_EINVAL.
                             kappa lambda_max(A^T D A) depends only on the geometry
                             and a = 2 m tau / kappa (H of Eq. 24 is
                             (1/kappa) |w| / (a + |w|)), and the few-view
-                            lambda_max(A^T D(1) A) on the geometry only: the handle
-                            keeps the last value of each and reuses it. */
+                            lambda_max(A^T D(1) A) and lambda_max(K^T D(1) K) on
+                            the geometry only: the handle keeps the last value of
+                            each and reuses it. */
     double tv_step;      /* tau_c of the TV dual iteration, default 1/8 */
     double safety;       /* rho < 1, default 0.95 */
     int32_t tv_iters;    /* inner TV steps per outer iteration, default 10 */
