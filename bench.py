@@ -498,6 +498,9 @@ def main() -> int:
     ap.add_argument("--unrolled", action="store_true",
                     help="instead of the throughput line: 16 unrolled 10-iteration solves (256^2, 180 views) forward "
                          "and reverse pass vs 16 plain solves")
+    ap.add_argument("--fewview", action="store_true",
+                    help="only the few-view workload (512^2, 32 views): A, A^T, Algorithm 2 and the "
+                         "error-tolerant solve")
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 --pmc: a plain 256 MiB device copy (counter calibration) "
                          "followed by 5 launches each of A, A^T, the filter D and the 10-step TV prox on the "
@@ -520,6 +523,9 @@ def main() -> int:
         return compare(dev)
     if args.batch:
         return batch_speedup(dev, args.batch, args.steps, args.warmup)
+    if args.fewview:
+        print(json.dumps(fewview_measure(dev, args.op_reps)), flush=True)
+        return 0
     if args.unrolled:
         return unrolled_speedup(dev, args.steps)
     log("generating the seeded lowdose_512 inputs (3 independent phantoms / noise draws)")
