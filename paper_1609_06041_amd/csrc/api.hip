@@ -277,22 +277,6 @@ int project(ctpd_op* op, const float* x, float* y) {
     return project_resid(op, x, nullptr, nullptr, nullptr, y);
 }
 
-// Task groups of the slab projector: for each orientation (row views, then
-// column views) the (view, 64-bin block) pairs in view order, cut into groups
-// of forward_slab_tasks_per_group(), the last group of each padded with -1.
-std::vector<int> slab_tasks(const std::vector<ViewGeom>& hv, int nb) {
-    const int G = forward_slab_tasks_per_group(), nblk = (nb + 63) / 64;
-    std::vector<int> out;
-    for (int row = 1; row >= 0; --row) {
-        const size_t start = out.size();
-        for (int v = 0; v < (int)hv.size(); ++v)
-            if (hv[v].row == row)
-                for (int b = 0; b < nblk; ++b) out.push_back(v * 64 + b);
-        while ((out.size() - start) % G) out.push_back(-1);
-    }
-    return out;
-}
-
 // n_iter dual steps on p (warm start in pin; result pointer returned in *pout,
 // which is either pin or scratch, both used as ping-pong buffers), then
 // x = max(0, z - lam div p).  lam == 0 gives x = max(0, z) and leaves p alone.
@@ -709,10 +693,23 @@ int ctpd_op_create(const ctpd_geometry* g, void* stream, ctpd_op** out) {
         ALLOC(op->views, op->m);
         std::vector<ViewGeom> hv = make_views(op->n, op->m, op->nb, g->angles);
         HIP_TRY(hipMemcpy(op->views, hv.data(), sizeof(ViewGeom) * op->m, hipMemcpyHostToDevice));
-        const std::vector<int> tasks = slab_tasks(hv, op->nb);
-        ALLOC(op->fwd_tasks, tasks.size());
-        HIP_TRY(hipMemcpy(op->fwd_tasks, tasks.data(), sizeof(int) * tasks.size(), hipMemcpyHostToDevice));
-        op->fwd_groups = (int)(tasks.size() / forward_slab_tasks_per_group());
+        {
+            // the slab projector's groups: spread over the chip's compute units for the
+            // solves, at their fullest for the batched launches
+            int cus = 0, dense = 0;
+            HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, op->device));
+            const int per = forward_slab_tasks_per_group();
+            const std::vector<int> bat = forward_slab_schedule(hv.data(), op->m, op->n, op->nb, 0, &dense);
+            ALLOC(op->bat_tasks, bat.size());
+            HIP_TRY(hipMemcpy(op->bat_tasks, bat.data(), sizeof(int) * bat.size(), hipMemcpyHostToDevice));
+            op->bat_groups = (int)(bat.size() / per);
+            if (forward_slab_preferred(dense, op->n)) {
+                const std::vector<int> one = forward_slab_schedule(hv.data(), op->m, op->n, op->nb, cus, nullptr);
+                ALLOC(op->fwd_tasks, one.size());
+                HIP_TRY(hipMemcpy(op->fwd_tasks, one.data(), sizeof(int) * one.size(), hipMemcpyHostToDevice));
+                op->fwd_groups = (int)(one.size() / per);
+            }
+        }
         ALLOC(op->xp, op->Jp + kPlaneSlack);
         ALLOC(op->xTp, op->Jp + kPlaneSlack);
         // the planes' pad columns stay zero for good: only interiors are written after this
@@ -748,8 +745,8 @@ void ctpd_op_destroy(ctpd_op* op) {
     if (!op) return;
     if (op->stream || op->views) (void)hipStreamSynchronize(op->stream);
     if (op->aux) (void)hipStreamSynchronize(op->aux);   // a lambda_h round queued ahead may still run there
-    void* ptrs[] = {op->views, op->fwd_tasks, op->xp, op->xTp, op->x, op->z, op->p[0], op->p[1], op->mu[0], op->mu[1], op->mu[2],
-                    op->mubar, op->q, op->sx, op->winv, op->taps64, op->taps32, op->partials, op->red, op->cost_dev,
+    void* ptrs[] = {op->views, op->fwd_tasks, op->bat_tasks, op->xp, op->xTp, op->x, op->z, op->p[0], op->p[1],
+                    op->mu[0], op->mu[1], op->mu[2], op->mubar, op->q, op->sx, op->winv, op->taps64, op->taps32, op->partials, op->red, op->cost_dev,
                     op->img64[0], op->img64[1], op->img64[2], op->pad64[0], op->pad64[1], op->sino64[0], op->sino64[1],
                     op->sino64[2], op->sino64[3], op->sino64[4], op->sino64[5], op->lz[0], op->lz[1],
                     op->lz_partials[0], op->lz_partials[1], op->xbar, op->ball_y, op->split64, op->ball_dev};

@@ -101,7 +101,7 @@ int blocks_of(const ctpd_op* op, int kind, int fwd_form) {
         case K_ADJ: return adjoint_tiles(op->n) * adjoint_tiles(op->n);
         case K_TV: return tv_tiles(op->n) * tv_tiles(op->n);
         case K_PAD: return pad_tiles(op->n) * pad_tiles(op->n);
-        case K_FWD: return fwd_form == 0 ? op->fwd_groups : forward_blocks_x(op->nb) * op->m;
+        case K_FWD: return fwd_form == 0 ? op->bat_groups : forward_blocks_x(op->nb) * op->m;
         default: return (int)((J + 2047) / 2048);
     }
 }
@@ -323,7 +323,7 @@ int ctpd_batch_lowdose_solve(ctpd_batch* bt, const float* const* b, const float*
         for (int j = 0; j < 2; ++j) it.p[j] = op->p[j];
         it.xp = op->xp;
         it.xTp = op->xTp;
-        it.tasks = op->fwd_tasks;
+        it.tasks = op->bat_tasks;
         it.x_out = x_out[i];
         it.sigma = (float)S[i].sigma;
         it.tau = (float)S[i].tau;

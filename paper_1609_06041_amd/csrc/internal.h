@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "ctpd.h"
 
@@ -184,14 +185,22 @@ hipError_t launch_forward_resid(const float* xp, const float* xTp, float* y, con
 hipError_t launch_forward_slab(const float* xp, const float* xTp, float* y, const ViewGeom* views, const int* tasks,
                                int ngroups, int n, int nb, const float* rb, const float* rw, const float* rm,
                                hipStream_t s);
-// the slab form when the geometry fills the chip with its groups (tasks may be
-// null: never), else the split form (few views), else the gather form; all
-// bit-identical
+// the slab form when ngroups > 0 (tasks may be null: never), else the split
+// form (few views), else the gather form; all bit-identical
 hipError_t launch_forward_auto(const float* xp, const float* xTp, float* y, const ViewGeom* views, const int* tasks,
                                int ngroups, int n, int m, int nb, const float* rb, const float* rw, const float* rm,
                                hipStream_t s);
 bool forward_slab_fits(int n);
 int forward_slab_tasks_per_group();
+// The slab form's task groups for a geometry (host): every (view, 64-bin
+// block) once, in max(min_groups, the fewest groups that hold them) groups
+// (fewer when there are too few tasks to fill them), each group of one
+// orientation and balanced over its SIMDs slab by slab; *dense (may be null)
+// receives the fewest groups that hold them.
+std::vector<int> forward_slab_schedule(const ViewGeom* hv, int m, int n, int nb, int min_groups, int* dense);
+// whether a single solve should use the slab form (enough groups at their
+// fullest to fill most of the chip, and a slab that fits the LDS)
+bool forward_slab_preferred(int dense_groups, int n);
 // floats of slack after each padded plane (the slab form copies 16-byte words)
 constexpr size_t kPlaneSlack = 4;
 // out = alpha * xin + beta * A^T (c1 * y1 + c2 * y2)   (xin, y2 may be null)

@@ -8,7 +8,11 @@
 // relative error on non-smooth images; the float64 position costs a few
 // full-rate DP instructions per sample on CDNA.
 #include <algorithm>
+#include <cmath>
 #include <mutex>
+#include <set>
+#include <tuple>
+#include <vector>
 
 #include "internal.h"
 
@@ -473,15 +477,182 @@ hipError_t launch_forward_slab(const float* xp, const float* xTp, float* y, cons
     return hipGetLastError();
 }
 
-// The form for the geometry (all three give the same bits): the slab form
-// when its groups fill most of the chip, else the split form, else the gather
-// form (images beyond the split form's segment table).
-constexpr int kSlabMinGroups = 150;
+// ---------------------------------------------------------------------------
+// Task schedule of the slab form (host).  A group's waves meet at a barrier
+// after every slab, so per slab a group takes as long as its busiest SIMD
+// (waves wv, wv + 4 and wv + 8 share SIMD wv mod 4), and a wave as long as
+// the union of its three rays' step ranges within the slab.  The tasks of
+// one orientation are sorted by step range and cut into triples of near-equal
+// ranges (one wave each); the triples are dealt, heaviest first, to the SIMD
+// slot whose per-slab load then peaks lowest (ties: the less loaded, then the
+// first), so that a SIMD holds e.g. one full-range wave beside a prefix and a
+// suffix wave of complementary lengths.  The orientations share
+// max(min_groups, the fewest groups that hold them) groups in proportion to
+// their work.  Which wave computes a ray changes none of its bits.
+constexpr int kSlabMinGroups = 150, kSlabSimds = 4, kSlabSlots = kSlabWaves / kSlabSimds;
+static_assert(kSlabWaves % kSlabSimds == 0, "waves per SIMD");
 
+// host copy of wave_ray_span over the 64 rays of block b (a cost estimate
+// only).  With st != 0 both ends of a ray's range are monotone in u, so the
+// first and last ray of the block bound the union.
+static void slab_task_span(const ViewGeom& g, int b, int n, int nb, int& t0, int& t1) {
+    t0 = n;
+    t1 = -1;
+    auto ray = [&](int u) {
+        const double base = std::fma((double)u, g.su, g.s0);
+        if (g.st != 0.0) {
+            const double ta = (-1.0 - base) / g.st, tb = ((double)n - base) / g.st;
+            const double lo = std::fmin(std::fmax(std::fmin(ta, tb), -1.0), (double)n);
+            const double hi = std::fmin(std::fmax(std::fmax(ta, tb), -1.0), (double)n);
+            t0 = std::min(t0, std::max(0, (int)std::floor(lo)));
+            t1 = std::max(t1, std::min(n - 1, (int)std::ceil(hi)));
+        } else if (base > -1.0 && base < (double)n) {
+            t0 = 0;
+            t1 = n - 1;
+        }
+    };
+    const int ua = b * 64, ue = std::min(b * 64 + 63, nb - 1);
+    if (g.st != 0.0) {
+        ray(ua);
+        ray(ue);
+    } else {
+        for (int u = ua; u <= ue; ++u) ray(u);
+    }
+}
+
+std::vector<int> forward_slab_schedule(const ViewGeom* hv, int m, int n, int nb, int min_groups, int* dense) {
+    constexpr int W = kSlabWaves, J = kSlabTPW;
+    const int nblk = (nb + 63) / 64, ns = (n + FW_SEG - 1) / FW_SEG;
+    struct Job {
+        int task[J];
+        long total;
+        std::vector<int> load;   // steps per slab, times J
+    };
+    std::vector<Job> jobs[2];
+    double work[2] = {0.0, 0.0};
+    for (int o = 0; o < 2; ++o) {
+        struct Span { int id, t0, t1; };
+        std::vector<Span> ts;
+        for (int v = 0; v < m; ++v)
+            if (hv[v].row == 1 - o)   // row views first
+                for (int b = 0; b < nblk; ++b) {
+                    Span sp{v * 64 + b, 0, 0};
+                    slab_task_span(hv[v], b, n, nb, sp.t0, sp.t1);
+                    ts.push_back(sp);
+                }
+        std::stable_sort(ts.begin(), ts.end(), [](const Span& a, const Span& b) {
+            const bool ea = a.t1 < a.t0, eb = b.t1 < b.t0;
+            if (ea != eb) return eb;
+            return a.t0 != b.t0 ? a.t0 < b.t0 : a.t1 < b.t1;
+        });
+        for (size_t i = 0; i < ts.size(); i += J) {
+            Job jb;
+            int t0 = n, t1 = -1;
+            for (int j = 0; j < J; ++j) {
+                const bool has = i + j < ts.size();
+                jb.task[j] = has ? ts[i + j].id : -1;
+                if (has && ts[i + j].t1 >= ts[i + j].t0) {
+                    t0 = std::min(t0, ts[i + j].t0);
+                    t1 = std::max(t1, ts[i + j].t1);
+                }
+            }
+            jb.load.assign(ns, 0);
+            jb.total = 0;
+            for (int s = 0; s < ns; ++s) {
+                const int a = std::max(t0, s * FW_SEG), b = std::min(t1, s * FW_SEG + FW_SEG - 1);
+                jb.load[s] = b >= a ? J * (b - a + 1) : 0;
+                jb.total += jb.load[s];
+            }
+            work[o] += (double)jb.total;
+            jobs[o].push_back(std::move(jb));
+        }
+    }
+    int need[2], G[2];
+    for (int o = 0; o < 2; ++o) need[o] = ((int)jobs[o].size() + W - 1) / W;
+    if (dense) *dense = need[0] + need[1];
+    const int total = std::max(min_groups, need[0] + need[1]);
+    if (!need[0] || !need[1]) {
+        G[0] = need[0] ? total : 0;
+        G[1] = need[1] ? total : 0;
+    } else {
+        const double share = work[0] + work[1] > 0.0 ? work[0] / (work[0] + work[1]) : 0.5;
+        G[0] = std::min(std::max((int)std::lround(share * total), need[0]), total - need[1]);
+        G[1] = total - G[0];
+    }
+    std::vector<int> out;
+    for (int o = 0; o < 2; ++o) {
+        if (!G[o]) continue;
+        const int B = G[o] * kSlabSimds;
+        std::vector<int> order(jobs[o].size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return jobs[o][a].total > jobs[o][b].total; });
+        std::vector<int> load((size_t)B * ns, 0), cnt(B, 0), slot((size_t)B * kSlabSlots, -1), peak(B, 0);
+        std::vector<long> tot(B, 0);
+        // open bins ordered by (own peak, total, index): a bin's new peak is at least
+        // its own, so the scan stops at the first bin whose own peak exceeds the best
+        std::set<std::tuple<int, long, int>> open;
+        int next_empty = 0;
+        for (int q : order) {
+            const Job& jb = jobs[o][q];
+            int best = -1;
+            if (next_empty < B) {
+                best = next_empty++;   // an empty bin: the lowest possible peak and total
+            } else {
+                int best_peak = 0;
+                long best_tot = 0;
+                for (const auto& e : open) {
+                    const int k = std::get<2>(e);
+                    if (best >= 0 && std::get<0>(e) > best_peak) break;
+                    int pk = 0;
+                    for (int s = 0; s < ns; ++s) pk = std::max(pk, load[(size_t)k * ns + s] + jb.load[s]);
+                    if (best < 0 || pk < best_peak || (pk == best_peak && (tot[k] < best_tot ||
+                                                                           (tot[k] == best_tot && k < best)))) {
+                        best = k;
+                        best_peak = pk;
+                        best_tot = tot[k];
+                    }
+                }
+                open.erase({peak[best], tot[best], best});
+            }
+            for (int s = 0; s < ns; ++s) {
+                load[(size_t)best * ns + s] += jb.load[s];
+                peak[best] = std::max(peak[best], load[(size_t)best * ns + s]);
+            }
+            tot[best] += jb.total;
+            slot[(size_t)best * kSlabSlots + cnt[best]++] = q;
+            if (cnt[best] < kSlabSlots) open.insert({peak[best], tot[best], best});
+        }
+        // SIMD slot c of SIMD k is wave k + 4 c; an empty bin takes the next
+        // job before any other bin does, so a group is empty exactly when its
+        // SIMD 0 bin is, and then so are the groups after it
+        for (int g = 0; g < G[o]; ++g) {
+            if (cnt[g * kSlabSimds] == 0) break;
+            const size_t base = out.size();
+            out.resize(base + (size_t)W * J, -1);
+            for (int k = 0; k < kSlabSimds; ++k)
+                for (int c = 0; c < kSlabSlots; ++c) {
+                    const int q = slot[(size_t)(g * kSlabSimds + k) * kSlabSlots + c];
+                    if (q < 0) continue;
+                    const int wv = k + kSlabSimds * c;
+                    for (int j = 0; j < J; ++j) out[base + wv + (size_t)W * j] = jobs[o][q].task[j];
+                }
+        }
+    }
+    return out;
+}
+
+bool forward_slab_preferred(int dense_groups, int n) {
+    return dense_groups >= kSlabMinGroups && forward_slab_fits(n);
+}
+
+// The form for the geometry (all three give the same bits): the slab form
+// when it was preferred for the geometry (ngroups > 0), else the split form,
+// else the gather form (images beyond the split form's segment table).
 hipError_t launch_forward_auto(const float* xp, const float* xTp, float* y, const ViewGeom* views, const int* tasks,
                                int ngroups, int n, int m, int nb, const float* rb, const float* rw, const float* rm,
                                hipStream_t s) {
-    if (tasks && ngroups >= kSlabMinGroups && forward_slab_fits(n))
+    if (tasks && ngroups > 0)
         return launch_forward_slab(xp, xTp, y, views, tasks, ngroups, n, nb, rb, rw, rm, s);
     if (n <= kSplitMaxSeg * FW_SEG) {
         const int nblk = (nb + 63) / 64;
