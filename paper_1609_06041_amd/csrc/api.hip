@@ -703,12 +703,12 @@ int ctpd_op_create(const ctpd_geometry* g, void* stream, ctpd_op** out) {
             ALLOC(op->bat_tasks, bat.size());
             HIP_TRY(hipMemcpy(op->bat_tasks, bat.data(), sizeof(int) * bat.size(), hipMemcpyHostToDevice));
             op->bat_groups = (int)(bat.size() / per);
-            if (forward_slab_preferred(dense, op->n)) {
-                const std::vector<int> one = forward_slab_schedule(hv.data(), op->m, op->n, op->nb, cus, nullptr);
-                ALLOC(op->fwd_tasks, one.size());
-                HIP_TRY(hipMemcpy(op->fwd_tasks, one.data(), sizeof(int) * one.size(), hipMemcpyHostToDevice));
-                op->fwd_groups = (int)(one.size() / per);
-            }
+            const bool slab = forward_slab_preferred(dense, op->n);
+            const std::vector<int> one = slab ? forward_slab_schedule(hv.data(), op->m, op->n, op->nb, cus, nullptr)
+                                              : forward_split_order(hv.data(), op->m, op->n, op->nb);
+            ALLOC(op->fwd_tasks, one.size());
+            HIP_TRY(hipMemcpy(op->fwd_tasks, one.data(), sizeof(int) * one.size(), hipMemcpyHostToDevice));
+            op->fwd_groups = slab ? (int)(one.size() / per) : 0;
         }
         ALLOC(op->xp, op->Jp + kPlaneSlack);
         ALLOC(op->xTp, op->Jp + kPlaneSlack);

@@ -185,8 +185,9 @@ hipError_t launch_forward_resid(const float* xp, const float* xTp, float* y, con
 hipError_t launch_forward_slab(const float* xp, const float* xTp, float* y, const ViewGeom* views, const int* tasks,
                                int ngroups, int n, int nb, const float* rb, const float* rw, const float* rm,
                                hipStream_t s);
-// the slab form when ngroups > 0 (tasks may be null: never), else the split
-// form (few views), else the gather form; all bit-identical
+// the slab form when ngroups > 0 (tasks: its groups), else the split form (few
+// views; tasks, when not null, its workgroup order from forward_split_order),
+// else the gather form; all bit-identical
 hipError_t launch_forward_auto(const float* xp, const float* xTp, float* y, const ViewGeom* views, const int* tasks,
                                int ngroups, int n, int m, int nb, const float* rb, const float* rw, const float* rm,
                                hipStream_t s);
@@ -201,6 +202,9 @@ std::vector<int> forward_slab_schedule(const ViewGeom* hv, int m, int n, int nb,
 // whether a single solve should use the slab form (enough groups at their
 // fullest to fill most of the chip, and a slab that fits the LDS)
 bool forward_slab_preferred(int dense_groups, int n);
+// the split form's workgroup order for a geometry (host): every view * nblk +
+// block once, heaviest first
+std::vector<int> forward_split_order(const ViewGeom* hv, int m, int n, int nb);
 // floats of slack after each padded plane (the slab form copies 16-byte words)
 constexpr size_t kPlaneSlack = 4;
 // out = alpha * xin + beta * A^T (c1 * y1 + c2 * y2)   (xin, y2 may be null)

@@ -29,8 +29,8 @@ struct ctpd_op {
     size_t J = 0, I = 0;   // image / sinogram sizes
     size_t Jp = 0;         // padded plane size n * (n + 6)
     ViewGeom* views = nullptr;
-    int* fwd_tasks = nullptr;   // the slab projector's task groups (device), spread over the chip
-    int fwd_groups = 0;         // 0: the solves use the split or gather form
+    int* fwd_tasks = nullptr;   // the slab projector's task groups (device), spread over the chip,
+    int fwd_groups = 0;         // or with fwd_groups = 0 the split form's workgroup order
     int* bat_tasks = nullptr;   // the same tasks in the fewest groups, for batched launches
     int bat_groups = 0;
     // float32 iteration state

@@ -12,6 +12,7 @@
 #include <mutex>
 #include <set>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -249,12 +250,13 @@ constexpr int kSplitWaves = 16, kSplitFB = 4, kSplitMaxSeg = 64;
 
 __global__ __launch_bounds__(64 * kSplitWaves) void forward_split_kernel(
     const float* __restrict__ xp, const float* __restrict__ xTp, float* __restrict__ y,
-    const ViewGeom* __restrict__ views, int n, int nb, int nblk, const float* __restrict__ rb,
-    const float* __restrict__ rw, const float* __restrict__ rm) {
+    const ViewGeom* __restrict__ views, const int* __restrict__ order, int n, int nb, int nblk,
+    const float* __restrict__ rb, const float* __restrict__ rw, const float* __restrict__ rm) {
     __shared__ float part[2][kSplitMaxSeg][64];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int v = blockIdx.x / nblk, blk = blockIdx.x - v * nblk;
+    const int task = order ? order[blockIdx.x] : (int)blockIdx.x;
+    const int v = task / nblk, blk = task - v * nblk;
     const int u = blk * 64 + lane;
     const ViewGeom g = views[v];
     const int P = n + 2 * FP_PAD;
@@ -642,6 +644,26 @@ std::vector<int> forward_slab_schedule(const ViewGeom* hv, int m, int n, int nb,
     return out;
 }
 
+// The split form's workgroup order: the (view, block) tasks by decreasing step
+// range.  The first workgroups of a launch take one compute unit each and the
+// rest double up behind them, so the heavy tasks go first and the light ones
+// (blocks at the detector's edges) share compute units with them.
+std::vector<int> forward_split_order(const ViewGeom* hv, int m, int n, int nb) {
+    const int nblk = (nb + 63) / 64;
+    std::vector<std::pair<int, int>> w;
+    w.reserve((size_t)m * nblk);
+    for (int v = 0; v < m; ++v)
+        for (int b = 0; b < nblk; ++b) {
+            int t0, t1;
+            slab_task_span(hv[v], b, n, nb, t0, t1);
+            w.push_back({-std::max(0, t1 - t0 + 1), v * nblk + b});
+        }
+    std::stable_sort(w.begin(), w.end());
+    std::vector<int> out(w.size());
+    for (size_t i = 0; i < w.size(); ++i) out[i] = w[i].second;
+    return out;
+}
+
 bool forward_slab_preferred(int dense_groups, int n) {
     return dense_groups >= kSlabMinGroups && forward_slab_fits(n);
 }
@@ -656,7 +678,8 @@ hipError_t launch_forward_auto(const float* xp, const float* xTp, float* y, cons
         return launch_forward_slab(xp, xTp, y, views, tasks, ngroups, n, nb, rb, rw, rm, s);
     if (n <= kSplitMaxSeg * FW_SEG) {
         const int nblk = (nb + 63) / 64;
-        forward_split_kernel<<<m * nblk, 64 * kSplitWaves, 0, s>>>(xp, xTp, y, views, n, nb, nblk, rb, rw, rm);
+        forward_split_kernel<<<m * nblk, 64 * kSplitWaves, 0, s>>>(xp, xTp, y, views, tasks, n, nb, nblk, rb, rw,
+                                                                 rm);
         return hipGetLastError();
     }
     return launch_forward_resid(xp, xTp, y, views, n, m, nb, rb, rw, rm, s);
