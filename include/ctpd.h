@@ -74,6 +74,8 @@ typedef struct {
                               no longer the FBP filter of the scan. */
 } ctpd_geometry;
 
+struct ctpd_state; /* below */
+
 /* Solver knobs.  A zero / negative value selects the default. */
 typedef struct {
     double tau;          /* primal step; default: low-dose 0.3*pi*kappa/(2m), few-view
@@ -103,7 +105,31 @@ typedef struct {
                             solver then runs the filters' fused-prologue path,
                             whose iterates equal the default path's bit for bit. */
     int32_t reserved;
+    struct ctpd_state* state; /* NULL, or the checkpoint the solve starts from and
+                            writes its end state into (ctpd_pd_lowdose_solve,
+                            ctpd_pd_fewview_solve, ctpd_pd_fewview_eps_solve;
+                            CTPD_EINVAL for the other solvers) */
 } ctpd_params;
+
+/* Checkpoint of an APP solve (Algorithms 1, 1', 2 and the error-tolerant
+ * few-view solve): the iterates an iteration reads, so that K1 iterations
+ * followed by K2 more from the checkpoint give the K1 + K2 iterations of one
+ * solve bit for bit.  The arrays are the caller's device memory, read at the
+ * start of a solve and overwritten with the state after its last iteration.
+ * k == 0 starts from x = 0, mu = mu_prev = 0, p = 0 (y = b) with the step
+ * sizes of the params (the arrays are not read); k > 0 resumes with the
+ * state's tau and sigma (both > 0, checked against the step-size bound like
+ * given ones), and the iteration after k uses the extrapolation of k >= 1. */
+typedef struct ctpd_state {
+    float* x;        /* [n][n] x^k */
+    float* mu;       /* [n_views][n_bins] mu^k */
+    float* mu_prev;  /* [n_views][n_bins] mu^{k-1} */
+    float* p;        /* [2][n][n] the TV dual field (the next prox's warm start) */
+    float* y;        /* [n_views][n_bins] the error-tolerant solve's y^k, else NULL */
+    int32_t k;       /* iterations behind the state; the solve adds its iters */
+    int32_t reserved;
+    double tau, sigma;  /* the step sizes of those iterations (written by the solve) */
+} ctpd_state;
 
 /* Solver report (host struct filled by the solvers). */
 typedef struct {

@@ -320,10 +320,11 @@ int lowdose_loop(ctpd_op* op, const float* b, const float* w, double beta, int i
     // W^-1 (mu^{k+1} - mu^k) for the next extrapolation.
     const bool fused = !k.record;
     for (int it = 0; it < iters; ++it) {
-        // Step 1: extrapolation (Eq. 18 / Algorithm 1)
-        if (it == 0)
+        // Step 1: extrapolation (Eq. 18 / Algorithm 1); a resumed state's first
+        // iteration forms W^-1 (mu^k - mu^{k-1}) in the filter's prologue
+        if (it == 0 && !k.resumed())
             r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, -fs, op->mubar);
-        else if (fused)
+        else if (fused && it > 0)
             r = filter(op, FILT_PLAIN, op->sx, nullptr, nullptr, nullptr, mu, 2.f, mup, -1.f, -fs, op->mubar);
         else
             r = filter(op, FILT_EXTRAP, op->winv, mu, mup, nullptr, mu, 2.f, mup, -1.f, -fs, op->mubar);
@@ -370,6 +371,7 @@ int read_params(const ctpd_params* p, Knobs* k) {
     k->tv_iters = 10;
     k->norm_steps = 100;
     k->record = 0;
+    k->state = nullptr;
     if (!p) return CTPD_OK;
     if (!(std::isfinite(p->tau) && std::isfinite(p->sigma) && std::isfinite(p->tv_step) &&
           std::isfinite(p->safety)))
@@ -385,6 +387,53 @@ int read_params(const ctpd_params* p, Knobs* k) {
     if (p->norm_steps > CTPD_MAX_NORM_STEPS) return einval("norm_steps above CTPD_MAX_NORM_STEPS");
     if (p->norm_steps > 0) k->norm_steps = p->norm_steps;
     k->record = p->record_cost ? 1 : 0;
+    if (ctpd_state* st = p->state) {
+        if (st->k < 0) return einval("state k < 0");
+        if (!st->x || !st->mu || !st->mu_prev || !st->p) return einval("null pointer in the state");
+        if (st->k > 0) {
+            if (!(st->tau > 0 && std::isfinite(st->tau) && st->sigma > 0 && std::isfinite(st->sigma)))
+                return einval("a resumed state needs its tau and sigma (finite, > 0)");
+            k->tau = st->tau;   // the state's step sizes (checked like given ones)
+            k->sigma = st->sigma;
+        }
+        k->state = st;
+    }
+    return CTPD_OK;
+}
+
+// For the solvers without checkpoints.
+int no_state(const Knobs& k) {
+    return k.state ? einval("a checkpoint state is taken by the APP solvers only (low-dose, few-view, "
+                            "error-tolerant few-view)")
+                   : CTPD_OK;
+}
+
+// The iterates of a resumed state into the handle's buffers the loops start
+// from (x, p[0], mu[0] = mu^k, mu[1] = mu^{k-1}, and y).
+int load_state(ctpd_op* op, const ctpd_state* st, float* y) {
+    const size_t I = op->I, J = op->J;
+    hipStream_t s = op->stream;
+    HIP_TRY(launch_copy_f32(op->x, st->x, J, s));
+    HIP_TRY(launch_copy_f32(op->p[0], st->p, 2 * J, s));
+    HIP_TRY(launch_copy_f32(op->mu[0], st->mu, I, s));
+    HIP_TRY(launch_copy_f32(op->mu[1], st->mu_prev, I, s));
+    if (y) HIP_TRY(launch_copy_f32(y, st->y, I, s));
+    return CTPD_OK;
+}
+
+// The state after a loop (mu^K in op->mu[0], mu^{K-1} in op->mu[1]).
+int save_state(ctpd_op* op, ctpd_state* st, const float* p_final, const float* y, int iters, double tau,
+               double sigma) {
+    const size_t I = op->I, J = op->J;
+    hipStream_t s = op->stream;
+    HIP_TRY(launch_copy_f32(st->x, op->x, J, s));
+    HIP_TRY(launch_copy_f32(st->p, p_final, 2 * J, s));
+    HIP_TRY(launch_copy_f32(st->mu, op->mu[0], I, s));
+    HIP_TRY(launch_copy_f32(st->mu_prev, op->mu[1], I, s));
+    if (y) HIP_TRY(launch_copy_f32(st->y, y, I, s));
+    st->k += iters;
+    st->tau = tau;
+    st->sigma = sigma;
     return CTPD_OK;
 }
 
@@ -609,15 +658,19 @@ int lowdose_setup_begin(ctpd_op* op, const float* b, const float* w, const Knobs
         return CTPD_EDOMAIN;
     }
     S->kappa = op->red_host[0] / (double)I;
-    S->tau = k.tau > 0 ? k.tau : kTauMultLowdose * M_PI * S->kappa / (2.0 * op->m);
+    // a given tau equal to the default (a resumed state's) takes the default's
+    // taps, so that a resumed solve repeats the same filter bit for bit
+    const double tau_def = kTauMultLowdose * M_PI * S->kappa / (2.0 * op->m);
+    const bool given = k.tau > 0 && k.tau != tau_def;
+    S->tau = given ? k.tau : tau_def;
     HIP_TRY(launch_inverse_f32(op->winv, w, I, op->stream));
-    if ((r = k.tau > 0 ? ensure_taps(op, S->tau, S->kappa) : ensure_taps_default(op, S->kappa))) return r;
+    if ((r = given ? ensure_taps(op, S->tau, S->kappa) : ensure_taps_default(op, S->kappa))) return r;
     // The two norms are computed whether sigma is given or not: they give the
     // default sigma, and a given one is checked against the bound they set.
     // H of Eq. 24 is (1/kappa) |w| / (a + |w|) with a = 2 m tau / kappa, so
     // kappa * lambda_max(A^T D A) depends on the geometry and a only (a is the
     // constant 0.3 pi at the default tau).
-    S->a = k.tau > 0 ? 2.0 * op->m * S->tau / S->kappa : kTauMultLowdose * M_PI;
+    S->a = given ? 2.0 * op->m * S->tau / S->kappa : kTauMultLowdose * M_PI;
     S->run_a = !(op->norm_ld > 0.0 && op->norm_ld_a == S->a && op->norm_ld_kmax == k.norm_steps);
     if ((r = ensure_f64(op))) return r;
     HIP_TRY(launch_rsqrt_f64(op->sino64[3], w, I, op->stream));
@@ -849,8 +902,8 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
     LowdoseSetup S;
     if ((r = lowdose_setup_begin(op, b, w, k, &S))) return r;
     if ((r = monitor_bnorm(op, b, &M))) return r;
-    // the iterates' zero start runs on op->stream while the lambda_h chains run on op->aux
-    if ((r = lowdose_zero(op))) return r;
+    // the iterates' start (zero or the state) runs on op->stream while the lambda_h chains run on op->aux
+    if ((r = k.resumed() ? load_state(op, k.state, nullptr) : lowdose_zero(op))) return r;
     {
         // the lambda_A chain (first solve on the handle) runs on op->stream while the
         // per-view lambda_h chains run on op->aux
@@ -880,6 +933,7 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
     const auto t1 = std::chrono::steady_clock::now();
     float* pcur = nullptr;
     if ((r = lowdose_loop(op, b, w, beta, iters, k, tau, sigma, &pcur, M, true))) return r;
+    if (k.state && (r = save_state(op, k.state, pcur, nullptr, iters, tau, sigma))) return r;
     if ((r = finish(op, iters, true, beta, pcur, rep, x_out, M))) return r;
     if (rep) {
         rep->tau = tau;
@@ -905,6 +959,7 @@ int ctpd_app_identity_lowdose_solve(ctpd_op* op, const float* b, const float* w,
     Knobs k;
     int r = read_params(p, &k);
     if (r) return r;
+    if ((r = no_state(k))) return r;
     Monitors M;
     if ((r = read_monitors(rep, true, &k, &M))) return r;
     const auto t0 = std::chrono::steady_clock::now();
@@ -1001,11 +1056,16 @@ static int fewview_loop(ctpd_op* op, const float* b, float* y, double eps, int i
     hipStream_t s = op->stream;
     const size_t I = op->I, J = op->J;
     if (k.record && (r = ensure_cost(op, iters))) return r;
-    HIP_TRY(launch_fill_f32(op->x, 0.f, J, s));
-    HIP_TRY(launch_fill_f32(op->p[0], 0.f, 2 * J, s));
-    HIP_TRY(launch_fill_f32(op->mu[0], 0.f, I, s));
-    HIP_TRY(launch_fill_f32(op->mu[1], 0.f, I, s));
-    if (y) HIP_TRY(launch_copy_f32(y, b, I, s));
+    const bool resumed = k.resumed();
+    if (resumed) {
+        if ((r = load_state(op, k.state, y))) return r;
+    } else {
+        HIP_TRY(launch_fill_f32(op->x, 0.f, J, s));
+        HIP_TRY(launch_fill_f32(op->p[0], 0.f, 2 * J, s));
+        HIP_TRY(launch_fill_f32(op->mu[0], 0.f, I, s));
+        HIP_TRY(launch_fill_f32(op->mu[1], 0.f, I, s));
+        if (y) HIP_TRY(launch_copy_f32(y, b, I, s));
+    }
     const float* data = y ? y : b;   // the sinogram A x is driven to
     float *mu = op->mu[0], *mup = op->mu[1], *mun = op->mu[2];
     float* pcur = op->p[0];
@@ -1013,7 +1073,8 @@ static int fewview_loop(ctpd_op* op, const float* b, float* y, double eps, int i
     const float tvstep = (float)(k.tv_step / tau);
     for (int it = 0; it < iters; ++it) {
         // z = x - tau A^T mubar, mubar = -sigma D b (k = 0) or 2 mu - mu_prev
-        if (it == 0) {
+        const bool first = it == 0 && !resumed;
+        if (first) {
             if ((r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, -fs,
                             op->mubar)))
                 return r;
@@ -1032,7 +1093,7 @@ static int fewview_loop(ctpd_op* op, const float* b, float* y, double eps, int i
         pcur = pnew;
         // y^{k+1} = P_ball(y^k + tau mubar)
         if (y) {
-            if (it == 0)
+            if (first)
                 HIP_TRY(launch_ball_project(y, op->mubar, 1.f, nullptr, 0.f, ft, b, eps, I, op->partials,
                                             op->ball_dev, s));
             else
@@ -1059,6 +1120,7 @@ static int fewview_loop(ctpd_op* op, const float* b, float* y, double eps, int i
     op->mu[1] = mup;
     op->mu[2] = mun;
     *p_final = pcur;
+    if (k.state && (r = save_state(op, k.state, pcur, y, iters, tau, sigma))) return r;
     return CTPD_OK;
 }
 
@@ -1190,6 +1252,7 @@ int ctpd_pd_fewview_eps_solve(ctpd_op* op, const float* b, double eps, int32_t i
     Knobs k;
     int r = read_params(p, &k);
     if (r) return r;
+    if (k.state && !k.state->y) return einval("the error-tolerant solve's state needs y");
     Monitors M;
     if ((r = read_monitors(rep, false, &k, &M))) return r;
     const auto t0 = std::chrono::steady_clock::now();
@@ -1266,6 +1329,7 @@ int ctpd_gist_lowdose_solve(ctpd_op* op, const float* b, const float* w, double 
     Knobs k;
     int r = read_params(p, &k);
     if (r) return r;
+    if ((r = no_state(k))) return r;
     if (k.sigma > 0.125) return einval("GIST dual step must be <= 1/8 (||grad||^2 <= 8)");
     Monitors M;
     if ((r = read_monitors(rep, false, &k, &M))) return r;
@@ -1359,6 +1423,7 @@ int ctpd_cp_fewview_solve(ctpd_op* op, const float* b, int32_t iters, const ctpd
     Knobs k;
     int r = read_params(p, &k);
     if (r) return r;
+    if ((r = no_state(k))) return r;
     Monitors M;
     if ((r = read_monitors(rep, false, &k, &M))) return r;
     const auto t0 = std::chrono::steady_clock::now();

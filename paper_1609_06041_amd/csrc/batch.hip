@@ -266,6 +266,7 @@ int ctpd_batch_lowdose_solve(ctpd_batch* bt, const float* const* b, const float*
     Knobs k;
     int r = read_params(p, &k);
     if (r) return r;
+    if ((r = no_state(k))) return r;
     const auto t0 = std::chrono::steady_clock::now();
     // inputs are ready on the caller's stream: every problem stream waits for it
     HIP_TRY(hipEventRecord(bt->ev, bt->user));

@@ -224,6 +224,8 @@ int tv_prox(ctpd_op* op, const float* z, float lam, int n_iter, float step, floa
 struct Knobs {
     double tau, sigma, tv_step, rho;
     int tv_iters, norm_steps, record;
+    ctpd_state* state;   // the checkpoint to start from and write back, or null
+    bool resumed() const { return state && state->k > 0; }
 };
 
 // Per-iteration monitors a report asks for (float64 sums on the device).
@@ -244,6 +246,8 @@ struct Monitors {
 };
 
 int read_params(const ctpd_params* p, Knobs* k);
+// CTPD_EINVAL when a checkpoint state was given (the solvers without one)
+int no_state(const Knobs& k);
 // the monitors rep asks for (gap_ok: the solver defines the partial gap);
 // sets k->record when any is asked for
 int read_monitors(const ctpd_report* rep, bool gap_ok, Knobs* k, Monitors* M);

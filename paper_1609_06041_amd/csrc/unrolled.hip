@@ -597,6 +597,7 @@ int ctpd_unrolled_lowdose_forward_many(int32_t count, ctpd_op* const* ops, const
     Knobs k;
     int r;
     if ((r = read_params(p, &k))) return r;
+    if ((r = no_state(k))) return r;
     std::vector<double> kappa;
     if ((r = begin_call(count, ops, b, w, beta, tau, sigma, iters, kappa))) return r;
     hipStream_t s = ops[0]->stream;
@@ -626,6 +627,7 @@ int ctpd_unrolled_lowdose_backward_many(int32_t count, ctpd_op* const* ops, cons
     Knobs k;
     int r;
     if ((r = read_params(p, &k))) return r;
+    if ((r = no_state(k))) return r;
     std::vector<double> kappa;
     if ((r = begin_call(count, ops, b, w, beta, tau, sigma, iters, kappa))) return r;
     hipStream_t s = ops[0]->stream;

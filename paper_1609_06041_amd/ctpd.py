@@ -83,7 +83,41 @@ def _geometry(n, m, nb, angles):
 
 class Params(ctypes.Structure):
     _fields_ = [("tau", c_double), ("sigma", c_double), ("tv_step", c_double), ("safety", c_double),
-                ("tv_iters", c_int32), ("norm_steps", c_int32), ("record_cost", c_int32), ("reserved", c_int32)]
+                ("tv_iters", c_int32), ("norm_steps", c_int32), ("record_cost", c_int32), ("reserved", c_int32),
+                ("state", c_void_p)]
+
+
+class State(ctypes.Structure):
+    _fields_ = [("x", c_void_p), ("mu", c_void_p), ("mu_prev", c_void_p), ("p", c_void_p), ("y", c_void_p),
+                ("k", c_int32), ("reserved", c_int32), ("tau", c_double), ("sigma", c_double)]
+
+
+class Checkpoint:
+    """The iterate state (x^k, mu^k, mu^{k-1}, p^k[, y^k]) of an APP solve in
+    device tensors.  Passed as ``state=`` to ``lowdose_solve``, ``fewview_solve``
+    or ``fewview_eps_solve``, the solve starts from it (the zero start while
+    ``k == 0``) and writes its end state back, so K1 iterations followed by K2
+    more equal K1 + K2 iterations of one solve bit for bit."""
+
+    def __init__(self, op: "Operator", with_y: bool = False):
+        z = lambda *shape: torch.zeros(shape, dtype=torch.float32, device=op.device)
+        self.shape = (op.n, op.m, op.nb)
+        self.x = z(op.n, op.n)
+        self.mu = z(op.m, op.nb)
+        self.mu_prev = z(op.m, op.nb)
+        self.p = z(2, op.n, op.n)
+        self.y = z(op.m, op.nb) if with_y else None
+        self.k, self.tau, self.sigma = 0, 0.0, 0.0
+
+    def _struct(self, op: "Operator") -> State:
+        if self.shape != (op.n, op.m, op.nb):
+            raise ValueError(f"checkpoint of shape {self.shape} for an operator of {(op.n, op.m, op.nb)}")
+        ptr = lambda t: None if t is None else c_void_p(t.data_ptr())
+        return State(x=ptr(self.x), mu=ptr(self.mu), mu_prev=ptr(self.mu_prev), p=ptr(self.p), y=ptr(self.y),
+                     k=int(self.k), reserved=0, tau=float(self.tau), sigma=float(self.sigma))
+
+    def _absorb(self, st: State) -> None:
+        self.k, self.tau, self.sigma = int(st.k), float(st.tau), float(st.sigma)
 
 
 class BatchTiles(ctypes.Structure):
@@ -151,7 +185,7 @@ def _ptr64(t: torch.Tensor, shape, name: str) -> c_void_p:
 def _params(tau, sigma, tv_iters, tv_step, safety, norm_steps, record_cost) -> Params:
     return Params(tau=float(tau or 0.0), sigma=float(sigma or 0.0), tv_step=float(tv_step or 0.0),
                   safety=float(safety or 0.0), tv_iters=int(tv_iters or 0), norm_steps=int(norm_steps or 0),
-                  record_cost=1 if record_cost else 0, reserved=0)
+                  record_cost=1 if record_cost else 0, reserved=0, state=None)
 
 
 class Operator:
@@ -263,6 +297,17 @@ class Operator:
             rep.p_out = c_void_p(state["p"].data_ptr())
         return rep, cost, state
 
+    def checkpoint(self, with_y: bool = False) -> Checkpoint:
+        """A zero-start checkpoint for this geometry (with_y: for fewview_eps_solve)."""
+        return Checkpoint(self, with_y)
+
+    def _attach(self, prm: Params, state: "Checkpoint | None"):
+        if state is None:
+            return None
+        cst = state._struct(self)
+        prm.state = ctypes.cast(ctypes.pointer(cst), c_void_p)
+        return cst
+
     @staticmethod
     def _info(rep: Report, cost, state) -> dict:
         info = {k: getattr(rep, k) for k in ("tau", "sigma", "kappa", "lambda_a", "lambda_h", "norm_steps_a",
@@ -275,15 +320,18 @@ class Operator:
     def lowdose_solve(self, b: torch.Tensor, w: torch.Tensor, beta: float, iters: int, *, tau=None, sigma=None,
                       tv_iters=10, tv_step=0.125, safety=0.95, norm_steps=100, record_cost=False,
                       return_state=False, monitors=(), x_ref=None,
-                      out: torch.Tensor | None = None):
+                      state: Checkpoint | None = None, out: torch.Tensor | None = None):
         """Algorithm 1 (beta > 0) / 1' (beta = 0).  Returns (x, info)."""
         out = self._img() if out is None else out
         prm = _params(tau, sigma, tv_iters, tv_step, safety, norm_steps, record_cost)
-        rep, cost, state = self._report(iters, record_cost, return_state, monitors, x_ref)
+        rep, cost, extra = self._report(iters, record_cost, return_state, monitors, x_ref)
+        cst = self._attach(prm, state)
         _check(load().ctpd_pd_lowdose_solve(self._h, _ptr(b, (self.m, self.nb), "b"),
                                             _ptr(w, (self.m, self.nb), "w"), float(beta), int(iters),
                                             byref(prm), _ptr(out, (self.n, self.n), "out"), byref(rep)))
-        return out, self._info(rep, cost, state)
+        if state is not None:
+            state._absorb(cst)
+        return out, self._info(rep, cost, extra)
 
     def app_identity_lowdose_solve(self, b: torch.Tensor, w: torch.Tensor, beta: float, iters: int, *, tau=None,
                                    sigma=None, tv_iters=10, tv_step=0.125, safety=0.95, norm_steps=100,
@@ -301,25 +349,31 @@ class Operator:
     def fewview_solve(self, b: torch.Tensor, iters: int, *, tau=None, sigma=None, tv_iters=10, tv_step=0.125,
                       safety=0.95, norm_steps=100, record_cost=False, return_state=False,
                       monitors=(), x_ref=None,
-                      out: torch.Tensor | None = None):
+                      state: Checkpoint | None = None, out: torch.Tensor | None = None):
         """Algorithm 2.  Returns (x, info)."""
         out = self._img() if out is None else out
         prm = _params(tau, sigma, tv_iters, tv_step, safety, norm_steps, record_cost)
-        rep, cost, state = self._report(iters, record_cost, return_state, monitors, x_ref)
+        rep, cost, extra = self._report(iters, record_cost, return_state, monitors, x_ref)
+        cst = self._attach(prm, state)
         _check(load().ctpd_pd_fewview_solve(self._h, _ptr(b, (self.m, self.nb), "b"), int(iters), byref(prm),
                                             _ptr(out, (self.n, self.n), "out"), byref(rep)))
-        return out, self._info(rep, cost, state)
+        if state is not None:
+            state._absorb(cst)
+        return out, self._info(rep, cost, extra)
 
     def fewview_eps_solve(self, b: torch.Tensor, eps: float, iters: int, *, tau=None, sigma=None, tv_iters=10,
                           tv_step=0.125, safety=0.95, norm_steps=100, record_cost=False, return_state=False,
-                          monitors=(), x_ref=None, out: torch.Tensor | None = None):
+                          monitors=(), x_ref=None, state: Checkpoint | None = None, out: torch.Tensor | None = None):
         """Error-tolerant few-view solve: min psi(x) s.t. ||Ax - b|| <= eps, x >= 0.  Returns (x, info)."""
         out = self._img() if out is None else out
         prm = _params(tau, sigma, tv_iters, tv_step, safety, norm_steps, record_cost)
-        rep, cost, state = self._report(iters, record_cost, return_state, monitors, x_ref)
+        rep, cost, extra = self._report(iters, record_cost, return_state, monitors, x_ref)
+        cst = self._attach(prm, state)
         _check(load().ctpd_pd_fewview_eps_solve(self._h, _ptr(b, (self.m, self.nb), "b"), float(eps), int(iters),
                                                 byref(prm), _ptr(out, (self.n, self.n), "out"), byref(rep)))
-        return out, self._info(rep, cost, state)
+        if state is not None:
+            state._absorb(cst)
+        return out, self._info(rep, cost, extra)
 
     def gist_lowdose_solve(self, b: torch.Tensor, w: torch.Tensor, beta: float, iters: int, *, gamma=None,
                            lam=None, safety=0.95, norm_steps=100, record_cost=False, return_state=False,

@@ -3,6 +3,8 @@ rejects bad arguments before touching the GPU (no compute calls here)."""
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import numpy as np
 import pytest
@@ -32,11 +34,31 @@ def test_library_exports_every_declared_symbol(libctpd):
         assert name in ctpd._SIGNATURES, f"binding lacks a signature for {name}"
 
 
-def test_binding_struct_layouts_match_header():
-    # field order / sizes as declared (ctypes follows the C ABI layout rules)
-    assert ctypes.sizeof(ctpd.Geometry) == 4 * 4 + 8
-    assert ctypes.sizeof(ctpd.Params) == 4 * 8 + 4 * 4
-    assert ctypes.sizeof(ctpd.Report) == 5 * 8 + 4 * 4 + 2 * 8 + 3 * 8 + 4 * 8
+# the binding's ctypes mirrors and the header's structs they stand for
+MIRRORS = [(ctpd.Geometry, "ctpd_geometry"), (ctpd.Params, "ctpd_params"), (ctpd.State, "ctpd_state"),
+           (ctpd.Report, "ctpd_report"), (ctpd.BatchTiles, "ctpd_batch_tiles")]
+
+
+def test_binding_struct_layouts_match_header(tmp_path):
+    # the C compiler's sizeof / offsetof of every field against the ctypes mirrors
+    gcc = shutil.which("gcc") or shutil.which("cc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "ctpd.h"', "int main(void) {"]
+    for cls, cname in MIRRORS:
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in cls._fields_:
+            lines.append(f'    printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["    return 0;", "}"]
+    src, exe = tmp_path / "layout.c", tmp_path / "layout"
+    src.write_text("\n".join(lines) + "\n")
+    subprocess.run([gcc, "-std=c99", "-Wall", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                          check=True).stdout.splitlines())
+    for cls, cname in MIRRORS:
+        assert int(got[f"{cname} size"]) == ctypes.sizeof(cls), cname
+        for field, _ in cls._fields_:
+            assert int(got[f"{cname} {field}"]) == getattr(cls, field).offset, (cname, field)
     text = open(HEADER).read()
     assert f"#define CTPD_MAX_BINS {ctpd.MAX_BINS}" in text
 
