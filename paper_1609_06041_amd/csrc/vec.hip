@@ -358,8 +358,8 @@ hipError_t launch_widen_f64(double* out, const float* a, size_t len, hipStream_t
 // and its largest eigenvalue is the largest over views: every view runs its
 // own chain on its nb-vector, all views (of all problems of a table) in
 // lockstep.  One workgroup per row for the Lanczos step (fixed-order
-// reductions), one wave per row for the Ritz values (Sturm-sequence
-// multisection on the view's tridiagonal matrix, scalars staged in LDS).  A
+// reductions) and for the Ritz values (Sturm-sequence multisection on the
+// view's tridiagonal matrix over four waves, scalars staged in LDS).  A
 // stopped view's vectors are left untouched.
 __device__ __forceinline__ double wave_sum_all(double v) {
 #pragma unroll
@@ -694,16 +694,22 @@ __device__ __forceinline__ double sturm_quot(double b, double d) {
 }
 
 // Largest eigenvalues of the leading k x k and (k-1) x (k-1) sections of the
-// tridiagonal matrix (alpha_i, sqrt(b2_i)) of a view, by multisection over one
-// wave: each round every lane counts (Sturm sequence) the eigenvalues below its
-// own shift of each bracket, and each bracket shrinks to the interval between
-// the last shift with fewer eigenvalues below than the section's size and the
-// first with all of them (65x per round).  The two sections' sequences are
-// interleaved in one loop, so their dependent chains overlap.  th1 is NaN for k = 1.
-__device__ void rows_tridiag_max2(const double* __restrict__ al, const double* __restrict__ bb, int k, int lane,
-                                  double* th, double* th1) {
+// tridiagonal matrix (alpha_i, sqrt(b2_i)) of a view, by multisection over the
+// kRitzWaves waves of a workgroup: each round every lane counts (Sturm
+// sequence) the eigenvalues below its own shift of each bracket (256 shifts),
+// and each bracket shrinks to the interval between the last shift with fewer
+// eigenvalues below than the section's size and the first with all of them
+// (257x per round), until its width is 1e-12 of its magnitude -- far below
+// the 1e-7 change that stops a chain.  The two sections' sequences are
+// interleaved in one loop, so their dependent chains overlap.  th1 is NaN for
+// k = 1.  Every thread of the workgroup calls it and gets the same results.
+constexpr int kRitzWaves = 4, kRitzThreads = 64 * kRitzWaves, kRitzShifts = kRitzThreads;
+
+__device__ void rows_tridiag_max2(const double* __restrict__ al, const double* __restrict__ bb, int k,
+                                  int* __restrict__ sfirst, double* th, double* th1) {
     // al[i]: alpha_i; bb[i]: beta_{i+1}^2 (couples i and i+1); both in LDS
     const int k1 = k - 1;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     double lo = al[0], hi = al[0], lo1 = al[0], hi1 = al[0];
     for (int i = 0; i < k; ++i) {
         const double left = i > 0 ? sqrt(bb[i - 1]) : 0.0;
@@ -721,13 +727,15 @@ __device__ void rows_tridiag_max2(const double* __restrict__ al, const double* _
         *th1 = k1 > 0 ? hi1 : NAN;
         return;
     }
-    auto open = [](double l, double h) { return h - l > 1e-15 * fmax(fabs(l), fabs(h)); };
-    // shift j (1 .. 64) of the bracket [l, h]; the bracket update reuses the
+    auto open = [](double l, double h) { return h - l > 1e-12 * fmax(fabs(l), fabs(h)); };
+    // shift j (1 .. 256) of the bracket [l, h]; the bracket update reuses the
     // same expression, so its new ends are shifts that were tested
-    auto shift = [](double l, double h, int j) { return l + (h - l) * ((double)j * (1.0 / 65.0)); };
+    auto shift = [](double l, double h, int j) {
+        return l + (h - l) * ((double)j * (1.0 / (double)(kRitzShifts + 1)));
+    };
     bool go = open(lo, hi), go1 = k1 > 0 && isfinite(lo1) && isfinite(hi1) && open(lo1, hi1);
     for (int round = 0; round < 40 && (go || go1); ++round) {
-        const double x = shift(lo, hi, lane + 1), x1 = shift(lo1, hi1, lane + 1);
+        const double x = shift(lo, hi, t + 1), x1 = shift(lo1, hi1, t + 1);
         int cnt = 0, cnt1 = 0;
         double d = 1.0, d1 = 1.0;
         // the recurrence scalars of 8 steps are read ahead of their dependent chain
@@ -752,21 +760,30 @@ __device__ void rows_tridiag_max2(const double* __restrict__ al, const double* _
                 cnt1 += (on1 && d1 < 0.0) ? 1 : 0;
             }
         }
-        // first lane whose shift lies above every eigenvalue
+        // the first shift (over the workgroup) that lies above every eigenvalue
+        const unsigned long long above = __ballot(cnt == k), above1 = __ballot(cnt1 == k1);
+        if (lane == 0) {
+            sfirst[wv] = above ? wv * 64 + __ffsll((long long)above) - 1 : kRitzShifts;
+            sfirst[kRitzWaves + wv] = above1 ? wv * 64 + __ffsll((long long)above1) - 1 : kRitzShifts;
+        }
+        __syncthreads();
+        int f = kRitzShifts, f1 = kRitzShifts;
+#pragma unroll
+        for (int w = 0; w < kRitzWaves; ++w) {
+            f = min(f, sfirst[w]);
+            f1 = min(f1, sfirst[kRitzWaves + w]);
+        }
+        __syncthreads();   // sfirst free for the next round
         if (go) {
-            const unsigned long long above = __ballot(cnt == k);
-            const int f = above ? __ffsll((long long)above) - 1 : 64;
-            const double nhi = f < 64 ? shift(lo, hi, f + 1) : hi;
+            const double nhi = f < kRitzShifts ? shift(lo, hi, f + 1) : hi;
             const double nlo = f > 0 ? shift(lo, hi, f) : lo;
             lo = nlo;
             hi = nhi;
             go = open(lo, hi);
         }
         if (go1) {
-            const unsigned long long above = __ballot(cnt1 == k1);
-            const int f = above ? __ffsll((long long)above) - 1 : 64;
-            const double nhi = f < 64 ? shift(lo1, hi1, f + 1) : hi1;
-            const double nlo = f > 0 ? shift(lo1, hi1, f) : lo1;
+            const double nhi = f1 < kRitzShifts ? shift(lo1, hi1, f1 + 1) : hi1;
+            const double nlo = f1 > 0 ? shift(lo1, hi1, f1) : lo1;
             lo1 = nlo;
             hi1 = nhi;
             go1 = open(lo1, hi1);
@@ -778,35 +795,32 @@ __device__ void rows_tridiag_max2(const double* __restrict__ al, const double* _
 
 constexpr int kRitzMax = CTPD_MAX_NORM_STEPS;   // steps a per-view chain can take
 
-// After `steps` steps: each running view's top Ritz value (one wave per view);
-// the view stops when it changed by <= tol relative over the last step or its
-// Krylov space is exhausted (beta ~ 0).
-__global__ __launch_bounds__(256) void rows_ritz_kernel(const NormItem* __restrict__ items,
-                                                        const RowRef* __restrict__ rows, int nrows, int steps,
-                                                        double tol) {
-    __shared__ double sal[4][kRitzMax], sbb[4][kRitzMax];
-    const int wv = threadIdx.x >> 6;
-    const int row = blockIdx.x * 4 + wv;
-    const int lane = threadIdx.x & 63;
+// After `steps` steps: each running view's top Ritz value (one workgroup of
+// kRitzWaves waves per view); the view stops when it changed by <= tol
+// relative over the last step or its Krylov space is exhausted (beta ~ 0).
+__global__ __launch_bounds__(kRitzThreads) void rows_ritz_kernel(const NormItem* __restrict__ items,
+                                                                 const RowRef* __restrict__ rows, int nrows,
+                                                                 int steps, double tol) {
+    __shared__ double sal[kRitzMax], sbb[kRitzMax];
+    __shared__ int sfirst[2 * kRitzWaves];
+    const int row = blockIdx.x;
     if (row >= nrows) return;
     const RowRef rr = rows[row];
     const NormItem& it = items[rr.prob];
     const int v = rr.view, m = it.m;
-    if (it.done[v]) return;
+    if (it.done[v]) return;   // uniform over the workgroup
     // the view's recurrence scalars into LDS (strided by m in HBM; read once)
-    for (int i = lane; i < steps; i += 64) {
-        sal[wv][i] = it.al[(size_t)i * m + v];
-        sbb[wv][i] = it.b2[(size_t)i * m + v];
+    for (int i = threadIdx.x; i < steps; i += kRitzThreads) {
+        sal[i] = it.al[(size_t)i * m + v];
+        sbb[i] = it.b2[(size_t)i * m + v];
     }
-    // the wave's own LDS writes are complete and visible to its lanes before the reads
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
+    __syncthreads();
     double th, th1;
-    rows_tridiag_max2(sal[wv], sbb[wv], steps, lane, &th, &th1);
-    const double bn = sqrt(fmax(sbb[wv][steps - 1], 0.0));
+    rows_tridiag_max2(sal, sbb, steps, sfirst, &th, &th1);
+    const double bn = sqrt(fmax(sbb[steps - 1], 0.0));
     bool stop = !(bn > 1e-300 * fmax(1.0, fabs(th))) || !isfinite(th);
     if (!stop && steps > 1) stop = fabs(th - th1) <= tol * fabs(th);
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
         it.theta[v] = th;
         if (stop) it.done[v] = steps;
     }
@@ -892,7 +906,7 @@ hipError_t launch_rows_round(const NormItem* it, const RowRef* rows, int nrows, 
 
 hipError_t launch_rows_ritz(const NormItem* it, const RowRef* rows, int nrows, int count, int steps, double tol,
                             hipStream_t s) {
-    rows_ritz_kernel<<<(nrows + 3) / 4, 256, 0, s>>>(it, rows, nrows, steps, tol);
+    rows_ritz_kernel<<<nrows, kRitzThreads, 0, s>>>(it, rows, nrows, steps, tol);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     rows_summary_kernel<<<count, 256, 0, s>>>(it, steps);
