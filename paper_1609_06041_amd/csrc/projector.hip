@@ -726,23 +726,56 @@ constexpr int AT_T = 32;
 constexpr int AT_THREADS = 1024;   // 16 waves: a 512^2 image has one tile per CU
 constexpr int AT_W = 48;
 
-// The stream layout per element type; the LDS tables stay within 64 KB.
-template <typename T>
-struct AtCfg;
-template <>
-struct AtCfg<float> {
+// Stream layouts.  Stream h takes every G-th view, so with few views the
+// sixteen streams of the float layout hold a view or two each and the
+// per-tile costs (staging the windows, the stream reduction) dominate: float
+// scans with fewer than kAtFewViews views use eight streams of eight pixels
+// a lane (32 views at 512^2: 10.0 -> 7.4 us per call; 720 views keep the
+// sixteen streams, 62 against 67 us).  Every launch (single, batched, the
+// unrolled steps) picks the layout by the same rule, so their results stay
+// equal bit for bit.
+struct AtF16 {
     static constexpr int G = 16;   // view streams per tile, one wave each
     static constexpr int PJ = 16;  // pixels per lane, one column
     static constexpr int VC = 8;   // views per chunk
     static constexpr int VQ = 1;   // views per inner pass
 };
-template <>
-struct AtCfg<double> {
+struct AtF8 {
+    static constexpr int G = 8;
+    static constexpr int PJ = 8;
+    static constexpr int VC = 8;
+    static constexpr int VQ = 1;
+};
+struct AtD8 {
     static constexpr int G = 8;
     static constexpr int PJ = 8;
     static constexpr int VC = 8;
     static constexpr int VQ = 2;
 };
+constexpr int kAtFewViews = 128;
+__host__ __device__ inline bool at_few_views(int m) { return m < kAtFewViews; }
+
+template <typename T, typename CFG>
+struct AtLds {
+    static constexpr int RS = AT_T / CFG::PJ;
+    // the staged bins, each already multiplied by its view's len (first, at
+    // LDS offset zero, so the per-view bases fold into the read instructions'
+    // offsets)
+    T win[CFG::G][CFG::VC][AT_W];
+    // per view of the staged chunk, in 32.32 fixed point relative to the
+    // window: colt[i][tx] = t of pixel (x0 + tx, y0), rowt[i][r] = r * (the
+    // per-row increment), r = 0..RS -- so a lane's positions are
+    // colt[tx] + rowt[ty] + j rowt[RS] (adds only)
+    long long colt[CFG::G][CFG::VC][AT_T];
+    long long rowt[CFG::G][CFG::VC][RS + 1];
+    // the hat weights over len: 1 - f prate (left bin) and poff + f prate
+    // (right bin), f the 32-bit fraction, prate = len2 / (len 2^32), poff = 1 - len2 / len
+    T prate[CFG::G][CFG::VC], poff[CFG::G][CFG::VC];
+};
+// LDS of a float launch that may take either layout
+constexpr size_t kAtFloatLds = sizeof(AtLds<float, AtF16>) > sizeof(AtLds<float, AtF8>)
+                                   ? sizeof(AtLds<float, AtF16>)
+                                   : sizeof(AtLds<float, AtF8>);
 
 struct TileBox {
     double xlo, xhi, ylo, yhi, cd;
@@ -759,33 +792,20 @@ __device__ __forceinline__ int window_base(const ViewGeom& g, const TileBox& b) 
     return (int)floor(tmin) - 1;
 }
 
-template <typename T, bool TWO>
+// smem: the launch's LDS block for the layout's tables (AtLds<T, CFG>)
+template <typename T, bool TWO, typename CFG>
 __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* __restrict__ y2, T c1, T c2,
                                              const T* __restrict__ xin, T alpha, T beta, T* __restrict__ out,
                                              const ViewGeom* __restrict__ views, int n, int m, int nb, int bxi,
-                                             int byi) {
-    constexpr int G = AtCfg<T>::G, PJ = AtCfg<T>::PJ, VC = AtCfg<T>::VC, VQ = AtCfg<T>::VQ;
+                                             int byi, void* smem) {
+    constexpr int G = CFG::G, PJ = CFG::PJ, VC = CFG::VC, VQ = CFG::VQ;
     constexpr int RS = AT_T / PJ;          // lane rows per stream
     constexpr int SL = AT_T * RS;          // lanes per stream
     constexpr int PER = VC * AT_W / SL;    // staged bins per lane and chunk
     static_assert(SL * G == AT_THREADS && SL % 64 == 0, "whole waves per stream");
     static_assert(PER * SL == VC * AT_W && VC % VQ == 0 && VC * AT_T % SL == 0, "chunk shape");
-    struct Lds {
-        // the staged bins, each already multiplied by its view's len (first,
-        // at LDS offset zero, so the per-view bases fold into the read
-        // instructions' offsets)
-        T win[G][VC][AT_W];
-        // per view of the staged chunk, in 32.32 fixed point relative to the
-        // window: colt[i][tx] = t of pixel (x0 + tx, y0), rowt[i][r] = r * (the
-        // per-row increment), r = 0..RS -- so a lane's positions are
-        // colt[tx] + rowt[ty] + j rowt[RS] (adds only)
-        long long colt[G][VC][AT_T];
-        long long rowt[G][VC][RS + 1];
-        // the hat weights over len: 1 - f prate (left bin) and poff + f prate
-        // (right bin), f the 32-bit fraction, prate = len2 / (len 2^32), poff = 1 - len2 / len
-        T prate[G][VC], poff[G][VC];
-    };
-    __shared__ Lds sh;
+    using Lds = AtLds<T, CFG>;
+    Lds& sh = *reinterpret_cast<Lds*>(smem);
     auto& win = sh.win;
     auto& colt = sh.colt;
     auto& rowt = sh.rowt;
@@ -966,23 +986,49 @@ __device__ __forceinline__ void adjoint_body(const T* __restrict__ y1, const T* 
     }
 }
 
-template <typename T, bool TWO>
+template <typename T, bool TWO, typename CFG>
 __global__ __launch_bounds__(AT_THREADS) void adjoint_kernel(const T* __restrict__ y1, const T* __restrict__ y2, T c1,
                                                       T c2, const T* __restrict__ xin, T alpha, T beta,
                                                       T* __restrict__ out, const ViewGeom* __restrict__ views,
                                                       int n, int m, int nb) {
-    adjoint_body<T, TWO>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb, blockIdx.x, blockIdx.y);
+    __shared__ __align__(16) unsigned char smem[sizeof(AtLds<T, CFG>)];
+    adjoint_body<T, TWO, CFG>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb, blockIdx.x, blockIdx.y, smem);
+}
+
+template <typename T, typename CFG>
+static void launch_adjoint_cfg(const T* y1, const T* y2, T c1, T c2, const T* xin, T alpha, T beta, T* out,
+                               const ViewGeom* views, int n, int m, int nb, hipStream_t s) {
+    dim3 grid((n + AT_T - 1) / AT_T, (n + AT_T - 1) / AT_T);
+    if (y2)
+        adjoint_kernel<T, true, CFG><<<grid, AT_THREADS, 0, s>>>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m,
+                                                                 nb);
+    else
+        adjoint_kernel<T, false, CFG><<<grid, AT_THREADS, 0, s>>>(y1, y2, c1, c2, xin, alpha, beta, out, views, n,
+                                                                  m, nb);
 }
 
 template <typename T>
 hipError_t launch_adjoint(const T* y1, const T* y2, T c1, T c2, const T* xin, T alpha, T beta, T* out,
                           const ViewGeom* views, int n, int m, int nb, hipStream_t s) {
-    dim3 grid((n + AT_T - 1) / AT_T, (n + AT_T - 1) / AT_T);
-    if (y2)
-        adjoint_kernel<T, true><<<grid, AT_THREADS, 0, s>>>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb);
+    if constexpr (sizeof(T) == 8)
+        launch_adjoint_cfg<T, AtD8>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb, s);
+    else if (at_few_views(m))
+        launch_adjoint_cfg<T, AtF8>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb, s);
     else
-        adjoint_kernel<T, false><<<grid, AT_THREADS, 0, s>>>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb);
+        launch_adjoint_cfg<T, AtF16>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb, s);
     return hipGetLastError();
+}
+
+// the float body in the layout the view count picks (batched and step launches)
+template <bool TWO>
+__device__ __forceinline__ void adjoint_body_f32(const float* __restrict__ y1, const float* __restrict__ y2, float c1,
+                                                 float c2, const float* __restrict__ xin, float alpha, float beta,
+                                                 float* __restrict__ out, const ViewGeom* __restrict__ views, int n,
+                                                 int m, int nb, int bxi, int byi, void* smem) {
+    if (at_few_views(m))
+        adjoint_body<float, TWO, AtF8>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb, bxi, byi, smem);
+    else
+        adjoint_body<float, TWO, AtF16>(y1, y2, c1, c2, xin, alpha, beta, out, views, n, m, nb, bxi, byi, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1018,8 +1064,9 @@ __global__ __launch_bounds__(AT_THREADS) void adjoint_batched(const BatchItem* _
     const int gx = (it.n + AT_T - 1) / AT_T;
     const float* y1 = TWO ? it.mu[rot] : it.mubar;
     const float* y2 = TWO ? it.mu[(rot + 1) % 3] : nullptr;
-    adjoint_body<float, TWO>(y1, y2, 2.f, -1.f, it.x, 1.f, -it.tau, it.z, it.views, it.n, it.m, it.nb,
-                             e.local % gx, e.local / gx);
+    __shared__ __align__(16) unsigned char smem[kAtFloatLds];
+    adjoint_body_f32<TWO>(y1, y2, 2.f, -1.f, it.x, 1.f, -it.tau, it.z, it.views, it.n, it.m, it.nb, e.local % gx,
+                          e.local / gx, smem);
 }
 
 hipError_t launch_pad_planes_batched(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s) {
@@ -1076,8 +1123,9 @@ __global__ __launch_bounds__(AT_THREADS) void step_adjoint_kernel(const UStep* _
     const UStep& st = steps[e.prob];
     if (!st.active) return;
     const int gx = (st.n + AT_T - 1) / AT_T;
-    adjoint_body<float, false>(st.in[0], nullptr, 1.f, 0.f, st.in[1], 1.f, st.c0, st.out[0], st.views, st.n, st.m,
-                               st.nb, e.local % gx, e.local / gx);
+    __shared__ __align__(16) unsigned char smem[kAtFloatLds];
+    adjoint_body_f32<false>(st.in[0], nullptr, 1.f, 0.f, st.in[1], 1.f, st.c0, st.out[0], st.views, st.n, st.m, st.nb,
+                            e.local % gx, e.local / gx, smem);
 }
 
 hipError_t launch_step_projector(int kind, const UStep* steps, const BlockRef* map, int nblocks, hipStream_t s) {
