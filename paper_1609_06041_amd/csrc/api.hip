@@ -304,8 +304,10 @@ int lowdose_zero(ctpd_op* op) {
     return CTPD_OK;
 }
 
+// z_ready: op->z holds x - tau A^T D b at x = 0 (the first iteration's z is
+// -sigma times it); else the first iteration forms it
 int lowdose_loop(ctpd_op* op, const float* b, const float* w, double beta, int iters, const Knobs& k, double tau,
-                 double sigma, float** p_final, const Monitors& M, bool zeroed = false) {
+                 double sigma, float** p_final, const Monitors& M, bool zeroed = false, bool z_ready = false) {
     int r = CTPD_OK;
     hipStream_t s = op->stream;
     if (k.record && (r = ensure_cost(op, iters))) return r;
@@ -321,17 +323,27 @@ int lowdose_loop(ctpd_op* op, const float* b, const float* w, double beta, int i
     const bool fused = !k.record;
     for (int it = 0; it < iters; ++it) {
         // Step 1: extrapolation (Eq. 18 / Algorithm 1); a resumed state's first
-        // iteration forms W^-1 (mu^k - mu^{k-1}) in the filter's prologue
-        if (it == 0 && !k.resumed())
-            r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, -fs, op->mubar);
-        else if (fused && it > 0)
-            r = filter(op, FILT_PLAIN, op->sx, nullptr, nullptr, nullptr, mu, 2.f, mup, -1.f, -fs, op->mubar);
-        else
-            r = filter(op, FILT_EXTRAP, op->winv, mu, mup, nullptr, mu, 2.f, mup, -1.f, -fs, op->mubar);
-        if (r) return r;
+        // iteration forms W^-1 (mu^k - mu^{k-1}) in the filter's prologue.
         // Step 2: z = x - tau A^T mubar, x = prox(z; tau beta)
-        HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, op->x, 1.f, -ft, op->z, op->views, op->n,
-                                      op->m, op->nb, s));
+        if (it == 0 && !k.resumed()) {
+            // x = 0, mubar = -sigma D b: z = -sigma (x - tau A^T D b)
+            if (!z_ready) {
+                if ((r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, 1.f,
+                                op->mubar)))
+                    return r;
+                HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, op->x, 1.f, -ft, op->z, op->views,
+                                              op->n, op->m, op->nb, s));
+            }
+            HIP_TRY(launch_lin3_f32(op->z, op->z, -fs, nullptr, 0.f, nullptr, 0.f, nullptr, op->J, s));
+        } else {
+            if (fused && it > 0)
+                r = filter(op, FILT_PLAIN, op->sx, nullptr, nullptr, nullptr, mu, 2.f, mup, -1.f, -fs, op->mubar);
+            else
+                r = filter(op, FILT_EXTRAP, op->winv, mu, mup, nullptr, mu, 2.f, mup, -1.f, -fs, op->mubar);
+            if (r) return r;
+            HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, op->x, 1.f, -ft, op->z, op->views, op->n,
+                                          op->m, op->nb, s));
+        }
         float* pnew = nullptr;
         // the prox also writes the projector's planes of x (not the beta = 0 clamp)
         const bool padded = lam > 0.f;
@@ -914,6 +926,17 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
             for (int q = 0; q < 4 && !S.La.finished(); ++q)   // queue the first rounds before the h chains block
                 if ((r = S.La.enqueue(S.La.per_round))) return r;
         }
+        // From the zero start the first iteration's z is -sigma (x - tau A^T D b)
+        // with x = 0 (the order of operations every solver of Algorithm 1 uses
+        // for it), and the bracket needs no sigma: it runs on op->stream beside
+        // the lambda_h chains on op->aux.
+        if (!k.resumed()) {
+            if ((r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, 1.f,
+                            op->mubar)))
+                return r;
+            HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, op->x, 1.f, -(float)S.tau, op->z,
+                                          op->views, op->n, op->m, op->nb, op->stream));
+        }
         const float* wp[1] = {w};
         if ((r = lambda_h_views({op}, wp, &S.kappa, k.norm_steps, op->aux, op->hv_item, op->hv_item_host,
                                 op->hv_rows, op->m, op->hv_filt, op->hv_nfilt, op->hv_sum, op->hv_sum_host,
@@ -932,7 +955,7 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
     const double setup_ms = ms_since(t0);
     const auto t1 = std::chrono::steady_clock::now();
     float* pcur = nullptr;
-    if ((r = lowdose_loop(op, b, w, beta, iters, k, tau, sigma, &pcur, M, true))) return r;
+    if ((r = lowdose_loop(op, b, w, beta, iters, k, tau, sigma, &pcur, M, true, !k.resumed()))) return r;
     if (k.state && (r = save_state(op, k.state, pcur, nullptr, iters, tau, sigma))) return r;
     if ((r = finish(op, iters, true, beta, pcur, rep, x_out, M))) return r;
     if (rep) {

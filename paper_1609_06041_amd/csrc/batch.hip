@@ -134,11 +134,13 @@ int queue_loop(ctpd_batch* bt, int iters, int tv_iters) {
     const int chunk = tv_chunk_max();
     for (int k = 0; k < iters; ++k) {
         const int rot = (3 - k % 3) % 3;
-        // Step 1: mubar = -sigma D b (k = 0) / 2 mu - mu_prev - sigma D W^-1 (mu - mu_prev)
+        // Step 1: mubar = 2 mu - mu_prev - sigma D W^-1 (mu - mu_prev) (k >= 1)
+        // Step 2: z = x - tau A^T mubar; x = prox(z).  At k = 0 (x = 0, mubar =
+        // -sigma D b) z = -sigma (x - tau A^T D b), the single solve's order.
         HIP_TRY(launch_filter_batched(it, bt->map[K_FILT], bt->nblk[K_FILT], k == 0 ? FILT_PLAIN : FILT_EXTRAP,
                                       rot, bt->max_nb, s));
-        // Step 2: z = x - tau A^T mubar; x = prox(z)
         HIP_TRY(launch_adjoint_batched(it, bt->map[K_ADJ], bt->nblk[K_ADJ], false, rot, s));
+        if (k == 0) HIP_TRY(launch_batch_scale_z(it, bt->map[K_COPY], bt->nblk[K_COPY], s));
         int left = tv_iters;
         do {
             const int st = std::min(left, chunk);

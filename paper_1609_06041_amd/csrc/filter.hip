@@ -337,9 +337,9 @@ __global__ __launch_bounds__(FTHREADS) void filter_batched(const BatchItem* __re
     float* mup = it.mu[(rot + 1) % 3];
     FilterArgs a{};
     a.mode = FILT_PLAIN;
-    if (MODE == FILT_PLAIN) {   // k = 0: mubar = -sigma D b
+    if (MODE == FILT_PLAIN) {   // k = 0: D b (z = -sigma (x - tau A^T D b) follows)
         a.in0 = it.b;
-        a.c = -it.sigma;
+        a.c = 1.f;
         a.out = it.mubar;
     } else if (MODE == FILT_EXTRAP) {   // mubar = 2 mu - mu_prev - sigma D W^-1 (mu - mu_prev)
         a.in0 = it.sx;

@@ -328,6 +328,8 @@ hipError_t launch_widen_f64(double* out, const float* a, size_t len, hipStream_t
 // (2048 elements per workgroup)
 hipError_t launch_batch_init(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s);
 hipError_t launch_batch_copy_out(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s);
+// z = -sigma z per problem (the copy-out map), the first iteration's last step
+hipError_t launch_batch_scale_z(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s);
 // per-view lambda_h chains over the rows of a NormItem table (one wave per row)
 hipError_t launch_rows_start(const NormItem* it, const RowRef* rows, int nrows, uint64_t seed, hipStream_t s);
 // before the first round: a windowed Rayleigh-quotient lower bound per view

@@ -424,11 +424,15 @@ void record_forward(Rec& R, const float* b, const float* w, double beta, double 
     R.fill(MC_CK, L.stride, ckpt, 0.f);
     for (int it = 0; it < iters; ++it) {
         float *x = X(it), *mu = MU(it), *mup = MU(it > 0 ? it - 1 : 0);
-        if (it == 0)
-            R.plain(taps, b, -fs, op->mubar);
-        else
+        if (it == 0) {
+            // x = 0, mubar = -sigma D b: z = -sigma (x - tau A^T D b), the solver's order
+            R.plain(taps, b, 1.f, op->mubar);
+            R.adjoint(op->mubar, x, -ft, op->z);
+            R.vec(SK_LIN3, MC_J, J, op->z, op->z, -fs);
+        } else {
             R.filter(FILT_EXTRAP, taps, op->winv, mu, mup, nullptr, mu, 2.f, mup, -1.f, -fs, op->mubar);
-        R.adjoint(op->mubar, x, -ft, op->z);
+            R.adjoint(op->mubar, x, -ft, op->z);
+        }
         R.copy(MC_2J, 2 * J, op->p[0], P(it));
         // the prox: chunks of dual steps ping-ponging p[0] / p[1], x on the last
         // (lam == 0: x = max(0, z) and p stays)
@@ -493,13 +497,17 @@ void record_backward(Rec& R, const float* b, const float* w, double beta, double
         // recompute the extrapolated dual variable, z and the inner dual fields
         const float* e = b;
         if (it == 0) {
-            R.plain(taps, b, -fs, op->mubar);
+            // the forward pass's z (u->e holds D b), and mubar = -sigma D b for the tau term below
+            R.plain(taps, b, 1.f, u->e);
+            R.adjoint(u->e, x, -ft, op->z);
+            R.vec(SK_LIN3, MC_J, J, op->z, op->z, -fs);
+            R.vec(SK_LIN3, MC_I, I, op->mubar, u->e, -fs);
         } else {
             R.vec(SK_LIN3, MC_I, I, u->e, mu, 1.f, mup, -1.f, nullptr, op->winv, 0.f);
             e = u->e;
             R.filter(FILT_EXTRAP, taps, op->winv, mu, mup, nullptr, mu, 2.f, mup, -1.f, -fs, op->mubar);
+            R.adjoint(op->mubar, x, -ft, op->z);
         }
-        R.adjoint(op->mubar, x, -ft, op->z);
         // PS(i): dual field after inner step i (PS(0) = p^k from the checkpoint)
         auto PS = [&](int i) -> const float* { return i == 0 ? P(it) : u->ps + (size_t)(i - 1) * 2 * J; };
         if (nt > 0) {

@@ -954,6 +954,25 @@ __global__ __launch_bounds__(256) void batch_copy_out_kernel(const BatchItem* __
     }
 }
 
+// the first iteration's z = -sigma (x - tau A^T D b), in place (the copy-out map)
+__global__ __launch_bounds__(256) void batch_scale_z_kernel(const BatchItem* __restrict__ items,
+                                                            const BlockRef* __restrict__ map) {
+    const BlockRef e = map[blockIdx.x];
+    if (e.prob < 0) return;
+    const BatchItem& it = items[e.prob];
+    const size_t J = (size_t)it.n * it.n;
+    const float c = -it.sigma;
+    for (int r = 0; r < 8; ++r) {
+        const size_t i = (size_t)e.local * 2048 + r * 256 + threadIdx.x;
+        if (i < J) it.z[i] = c * it.z[i];
+    }
+}
+
+hipError_t launch_batch_scale_z(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s) {
+    batch_scale_z_kernel<<<nblocks, 256, 0, s>>>(items, map);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_init(const BatchItem* items, const BlockRef* map, int nblocks, hipStream_t s) {
     batch_init_kernel<<<nblocks, 256, 0, s>>>(items, map);
     return hipGetLastError();
