@@ -539,6 +539,7 @@ int ensure_hv(ctpd_op* op, int kmax) {
         ALLOC(op->hv_sum, 3);
         HIP_TRY(hipHostMalloc((void**)&op->hv_sum_host, sizeof(double) * 6, hipHostMallocDefault));
         for (auto& e : op->hv_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&op->hv_start_ev, hipEventDisableTiming));
         std::vector<RowRef> rows(op->m);
         for (int v = 0; v < op->m; ++v) rows[v] = RowRef{0, v};
         ALLOC(op->hv_rows, op->m);
@@ -571,7 +572,7 @@ int ensure_hv(ctpd_op* op, int kmax) {
 int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, const double* kappa, int kmax,
                    hipStream_t s, NormItem* items, NormItem* items_host, const RowRef* rows, int nrows,
                    const BlockRef* filt, int nfilt, double* summary, double* summary_host, const hipEvent_t* ev,
-                   double* lam, int* steps) {
+                   double* lam, int* steps, const std::function<int(hipEvent_t)>& side, hipEvent_t side_ev) {
     const int P = (int)ops.size();
     for (int i = 0; i < P; ++i) {
         ctpd_op* op = ops[i];
@@ -603,6 +604,11 @@ int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, cons
     HIP_TRY(hipMemcpyAsync(items, items_host, sizeof(NormItem) * P, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_rows_start(items, rows, nrows, 2, s));
     HIP_TRY(launch_rows_prune(items, rows, nrows, P, s));
+    if (side && side_ev) {
+        HIP_TRY(hipEventRecord(side_ev, s));
+        const int rs = side(side_ev);
+        if (rs) return rs;
+    }
     int max_nb = 0;
     for (ctpd_op* op : ops) max_nb = std::max(max_nb, op->nb);
     // up to 1024 bins a round is one launch (the view's product and recurrence
@@ -834,6 +840,7 @@ void ctpd_op_destroy(ctpd_op* op) {
     if (op->hv_sum_host) (void)hipHostFree(op->hv_sum_host);
     for (auto e : op->hv_ev)
         if (e) (void)hipEventDestroy(e);
+    if (op->hv_start_ev) (void)hipEventDestroy(op->hv_start_ev);
     delete op;
 }
 
@@ -929,18 +936,22 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
         // From the zero start the first iteration's z is -sigma (x - tau A^T D b)
         // with x = 0 (the order of operations every solver of Algorithm 1 uses
         // for it), and the bracket needs no sigma: it runs on op->stream beside
-        // the lambda_h chains on op->aux.
-        if (!k.resumed()) {
-            if ((r = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, 1.f,
-                            op->mubar)))
-                return r;
-            HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, op->x, 1.f, -(float)S.tau, op->z,
-                                          op->views, op->n, op->m, op->nb, op->stream));
-        }
+        // the lambda_h chains on op->aux, made ready together with their first
+        // round so that the round's few workgroups find their compute units.
+        auto zstart = [&](hipEvent_t ev) -> int {
+            HIP_TRY(hipStreamWaitEvent(op->stream, ev, 0));
+            const int rf = filter(op, FILT_PLAIN, b, nullptr, nullptr, nullptr, nullptr, 0.f, nullptr, 0.f, 1.f,
+                                  op->mubar);
+            if (rf) return rf;
+            HIP_TRY(launch_adjoint<float>(op->mubar, nullptr, 1.f, 0.f, op->x, 1.f, -(float)S.tau, op->z, op->views,
+                                          op->n, op->m, op->nb, op->stream));
+            return CTPD_OK;
+        };
         const float* wp[1] = {w};
         if ((r = lambda_h_views({op}, wp, &S.kappa, k.norm_steps, op->aux, op->hv_item, op->hv_item_host,
                                 op->hv_rows, op->m, op->hv_filt, op->hv_nfilt, op->hv_sum, op->hv_sum_host,
-                                op->hv_ev, &S.lam_h, &S.steps_h)))
+                                op->hv_ev, &S.lam_h, &S.steps_h,
+                                k.resumed() ? std::function<int(hipEvent_t)>() : zstart, op->hv_start_ev)))
             return r;
         if (S.run_a) {
             HIP_TRY(hipStreamSynchronize(op->stream));

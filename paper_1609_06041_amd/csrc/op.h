@@ -93,6 +93,7 @@ struct ctpd_op {
     double* hv_sum = nullptr;                 // device, 3 doubles
     double* hv_sum_host = nullptr;            // pinned, two slots of 3 doubles
     hipEvent_t hv_ev[2] = {nullptr, nullptr}; // behind the copies into the two slots
+    hipEvent_t hv_start_ev = nullptr;           // behind the lambda_h chains' start
     // the error-tolerant few-view solve (allocated on first use): its data-side
     // variable y, the three float64 Lanczos vectors over the pair (x, y), and
     // the ball projection's norm and scale (device)
@@ -282,10 +283,14 @@ int lowdose_setup_begin(ctpd_op* op, const float* b, const float* w, const Knobs
 // lam[i], steps[i] receive the results.  A round may still run on s after the
 // return (one queued ahead that found every chain stopped: it changes nothing).
 int ensure_hv(ctpd_op* op, int kmax);
+// side (optional) is called before the first round is queued, with an event
+// recorded on s behind the chains' start: work queued behind that event
+// becomes ready together with the first round.
 int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, const double* kappa, int kmax,
                    hipStream_t s, ctpd::NormItem* items, ctpd::NormItem* items_host, const ctpd::RowRef* rows,
                    int nrows, const ctpd::BlockRef* filt, int nfilt, double* summary, double* summary_host,
-                   const hipEvent_t* ev, double* lam, int* steps);
+                   const hipEvent_t* ev, double* lam, int* steps,
+                   const std::function<int(hipEvent_t)>& side = nullptr, hipEvent_t side_ev = nullptr);
 // lambda_a from the chain or the cache, then sigma: the default, or the given
 // one checked against the bound (CTPD_EINVAL when it violates it)
 int lowdose_setup_end(ctpd_op* op, const Knobs& k, LowdoseSetup* S);
