@@ -604,11 +604,7 @@ int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, cons
     HIP_TRY(hipMemcpyAsync(items, items_host, sizeof(NormItem) * P, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_rows_start(items, rows, nrows, 2, s));
     HIP_TRY(launch_rows_prune(items, rows, nrows, P, s));
-    if (side && side_ev) {
-        HIP_TRY(hipEventRecord(side_ev, s));
-        const int rs = side(side_ev);
-        if (rs) return rs;
-    }
+    if (side && side_ev) HIP_TRY(hipEventRecord(side_ev, s));
     int max_nb = 0;
     for (ctpd_op* op : ops) max_nb = std::max(max_nb, op->nb);
     // up to 1024 bins a round is one launch (the view's product and recurrence
@@ -641,6 +637,9 @@ int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, cons
     // left running it does nothing and its summary repeats round r's.
     int j = std::min(kmax, kRound), slot = 0, r;
     if ((r = enqueue(0, j, 0))) return r;
+    // the side work is queued after the first round, so that the round is
+    // dispatched first and keeps its compute units
+    if (side && side_ev && (r = side(side_ev))) return r;
     const double* res = summary_host;
     for (;;) {
         const int jn = std::min(kmax, j + kRound);
@@ -669,6 +668,10 @@ int lowdose_setup_begin(ctpd_op* op, const float* b, const float* w, const Knobs
     const size_t I = op->I;
     int r;
     if ((r = reduce(op, RED_INVW_CHECK, w, b, nullptr, I, 0))) return r;
+    // W^-1 and W^-1/2 need no kappa: they run while the host reads it
+    HIP_TRY(launch_inverse_f32(op->winv, w, I, op->stream));
+    if ((r = ensure_f64(op))) return r;
+    HIP_TRY(launch_rsqrt_f64(op->sino64[3], w, I, op->stream));
     if ((r = read_red(op))) return r;
     if (op->red_host[1] > 0 || op->red_host[2] > 0) {
         snprintf(g_errmsg, sizeof g_errmsg, "%.0f weights <= 0 or non-finite, %.0f non-finite data",
@@ -681,7 +684,6 @@ int lowdose_setup_begin(ctpd_op* op, const float* b, const float* w, const Knobs
     const double tau_def = kTauMultLowdose * M_PI * S->kappa / (2.0 * op->m);
     const bool given = k.tau > 0 && k.tau != tau_def;
     S->tau = given ? k.tau : tau_def;
-    HIP_TRY(launch_inverse_f32(op->winv, w, I, op->stream));
     if ((r = given ? ensure_taps(op, S->tau, S->kappa) : ensure_taps_default(op, S->kappa))) return r;
     // The two norms are computed whether sigma is given or not: they give the
     // default sigma, and a given one is checked against the bound they set.
@@ -690,8 +692,6 @@ int lowdose_setup_begin(ctpd_op* op, const float* b, const float* w, const Knobs
     // constant 0.3 pi at the default tau).
     S->a = given ? 2.0 * op->m * S->tau / S->kappa : kTauMultLowdose * M_PI;
     S->run_a = !(op->norm_ld > 0.0 && op->norm_ld_a == S->a && op->norm_ld_kmax == k.norm_steps);
-    if ((r = ensure_f64(op))) return r;
-    HIP_TRY(launch_rsqrt_f64(op->sino64[3], w, I, op->stream));
     if (S->run_a && (r = setup_lambda_a(op, k.norm_steps, &S->La))) return r;
     return CTPD_OK;
 }
@@ -919,10 +919,10 @@ int ctpd_pd_lowdose_solve(ctpd_op* op, const float* b, const float* w, double be
     if ((r = read_monitors(rep, true, &k, &M))) return r;
     const auto t0 = std::chrono::steady_clock::now();
     LowdoseSetup S;
+    // the iterates' start (zero or the state) needs nothing of the set-up: it runs first
+    if ((r = k.resumed() ? load_state(op, k.state, nullptr) : lowdose_zero(op))) return r;
     if ((r = lowdose_setup_begin(op, b, w, k, &S))) return r;
     if ((r = monitor_bnorm(op, b, &M))) return r;
-    // the iterates' start (zero or the state) runs on op->stream while the lambda_h chains run on op->aux
-    if ((r = k.resumed() ? load_state(op, k.state, nullptr) : lowdose_zero(op))) return r;
     {
         // the lambda_A chain (first solve on the handle) runs on op->stream while the
         // per-view lambda_h chains run on op->aux

@@ -283,9 +283,9 @@ int lowdose_setup_begin(ctpd_op* op, const float* b, const float* w, const Knobs
 // lam[i], steps[i] receive the results.  A round may still run on s after the
 // return (one queued ahead that found every chain stopped: it changes nothing).
 int ensure_hv(ctpd_op* op, int kmax);
-// side (optional) is called before the first round is queued, with an event
-// recorded on s behind the chains' start: work queued behind that event
-// becomes ready together with the first round.
+// side (optional) is called once the first round is queued, with an event
+// recorded on s behind the chains' start (before that round): work queued
+// behind it runs beside the first round, which was dispatched first.
 int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, const double* kappa, int kmax,
                    hipStream_t s, ctpd::NormItem* items, ctpd::NormItem* items_host, const ctpd::RowRef* rows,
                    int nrows, const ctpd::BlockRef* filt, int nfilt, double* summary, double* summary_host,
