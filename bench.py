@@ -25,7 +25,7 @@ another) and the unrolled differentiable solve (16 x 256^2, 180 views, 10
 iterations, forward + reverse pass for all problems in one call vs one problem
 at a time, and vs 16 plain solves).
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline] [--no-extras]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline] [--no-extras]
 """
 from __future__ import annotations
 
