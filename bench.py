@@ -508,7 +508,7 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (independent problems "
+        print("bench.py measures one GPU only: the library has no multi-GPU path (independent problems "
               "would shard one per GPU with no exchange). Run with --gpus 1.", file=sys.stderr)
         return 2
 
