@@ -554,6 +554,7 @@ int ensure_hv(ctpd_op* op, int kmax) {
         ALLOC(op->hv_theta, op->m);
         ALLOC(op->hv_done, op->m);
         ALLOC(op->hv_maxinv, op->m);
+        ALLOC(op->hv_ubound, op->m);
         int r = ensure_sym(op);
         if (r) return r;
     }
@@ -593,6 +594,7 @@ int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, cons
         it.theta = op->hv_theta;
         it.done = op->hv_done;
         it.maxinv = op->hv_maxinv;
+        it.ubound = op->hv_ubound;
         it.fsym = op->hv_sym;
         if (op->hv_sym_tau != op->tap_tau || op->hv_sym_kappa != op->tap_kappa) {
             HIP_TRY(launch_symbol_max(op->taps64, op->nb, op->hv_sym, s));
@@ -833,7 +835,7 @@ void ctpd_op_destroy(ctpd_op* op) {
     if (op->fork) (void)hipEventDestroy(op->fork);
     free_unrolled(op->uw);
     void* hv[] = {op->hv_al,   op->hv_b2,   op->hv_b0,  op->hv_theta,  op->hv_done, op->hv_item, op->hv_rows,
-                  op->hv_filt, op->hv_sum, op->hv_maxinv, op->hv_sym,   op->taps1,   op->sym1};
+                  op->hv_filt, op->hv_sum, op->hv_maxinv, op->hv_ubound, op->hv_sym, op->taps1,  op->sym1};
     for (void* p : hv)
         if (p) (void)hipFree(p);
     if (op->hv_item_host) (void)hipHostFree(op->hv_item_host);

@@ -98,6 +98,7 @@ struct NormItem {
     double* b2;
     double* b0;
     double* theta;
+    double* ubound;   // theta + the residual norm of the top Ritz pair (+inf before the first round)
     int* done;
     double* summary;
     const double* fsym;

@@ -82,6 +82,7 @@ struct ctpd_op {
     double *hv_al = nullptr, *hv_b2 = nullptr, *hv_b0 = nullptr, *hv_theta = nullptr;
     int* hv_done = nullptr;
     double* hv_maxinv = nullptr;               // device, m doubles: max 1/w per view
+    double* hv_ubound = nullptr;               // device, m doubles: Ritz value + residual norm per view
     double* hv_sym = nullptr;                  // device, 1 + kSymBlocks doubles: bound of the filter's symbol
     double hv_sym_tau = -1.0, hv_sym_kappa = -1.0;   // the taps hv_sym was computed for
     int hv_cap = 0;

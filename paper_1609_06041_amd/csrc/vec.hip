@@ -399,6 +399,7 @@ __global__ __launch_bounds__(256) void rows_start_kernel(const NormItem* __restr
         it.b0[v] = ss;
         it.done[v] = 0;
         it.theta[v] = 0.0;
+        it.ubound[v] = HUGE_VAL;
         it.maxinv[v] = mi;
     }
     (void)m;
@@ -795,13 +796,46 @@ __device__ void rows_tridiag_max2(const double* __restrict__ al, const double* _
 
 constexpr int kRitzMax = CTPD_MAX_NORM_STEPS;   // steps a per-view chain can take
 
-// After `steps` steps: each running view's top Ritz value (one workgroup of
-// kRitzWaves waves per view); the view stops when it changed by <= tol
-// relative over the last step or its Krylov space is exhausted (beta ~ 0).
+// Residual norm ||B q - th q|| of the Ritz pair (th, q = Q_k x / ||x||) of a
+// chain after k steps, x the eigenvector of the tridiagonal T_k for th.  x is
+// taken by the three-term recurrence of T_k x = th x run upwards from
+// x_{k-1} = 1 (for the top Ritz value the components grow upwards, so the
+// recurrence is stable in that direction); what the first row then misses,
+// d0 = (th - alpha_0) x_0 - beta_1 x_1, is the error of th.  From
+// B Q_k = Q_k T_k + beta_k q_k e_{k-1}^T, B q - th q = (d0 Q_k e_0 +
+// beta_k x_{k-1} q_k) / ||x||, so the norm is at most (|d0| + beta_k) / ||x||,
+// and B has an eigenvalue within that distance of th.  sb[i] = sqrt(bb[i]),
+// sib[i] = 1 / sb[i]; bn = beta_k.  +inf when the recurrence does not stay
+// finite.
+__device__ double ritz_residual(const double* __restrict__ sal, const double* __restrict__ sb,
+                                const double* __restrict__ sib, int k, double th, double bn) {
+    double x = 1.0, xn = 0.0, nrm = 1.0, last = 1.0;   // x_i, x_{i+1}, sum x^2, x_{k-1}
+    for (int i = k - 1; i >= 1; --i) {
+        const double xp = ((th - sal[i]) * x - (i + 1 < k ? sb[i] * xn : 0.0)) * sib[i - 1];
+        xn = x;
+        x = xp;
+        nrm = fma(xp, xp, nrm);
+        if (fabs(x) > 1e100) {   // rescale, exactly (a power of two)
+            const double f = 0x1p-332;
+            x *= f;
+            xn *= f;
+            last *= f;
+            nrm *= f * f;
+        }
+    }
+    const double d0 = (th - sal[0]) * x - (k > 1 ? sb[0] * xn : 0.0);
+    const double r = (fabs(d0) + bn * last) / sqrt(nrm);
+    return isfinite(r) ? r : HUGE_VAL;
+}
+
+// After `steps` steps: each running view's top Ritz value and that value plus
+// its residual norm (one workgroup of kRitzWaves waves per view); the view
+// stops when the Ritz value changed by <= tol relative over the last step or
+// its Krylov space is exhausted (beta ~ 0).
 __global__ __launch_bounds__(kRitzThreads) void rows_ritz_kernel(const NormItem* __restrict__ items,
                                                                  const RowRef* __restrict__ rows, int nrows,
                                                                  int steps, double tol) {
-    __shared__ double sal[kRitzMax], sbb[kRitzMax];
+    __shared__ double sal[kRitzMax], sbb[kRitzMax], sb[kRitzMax], sib[kRitzMax];
     __shared__ int sfirst[2 * kRitzWaves];
     const int row = blockIdx.x;
     if (row >= nrows) return;
@@ -812,24 +846,31 @@ __global__ __launch_bounds__(kRitzThreads) void rows_ritz_kernel(const NormItem*
     // the view's recurrence scalars into LDS (strided by m in HBM; read once)
     for (int i = threadIdx.x; i < steps; i += kRitzThreads) {
         sal[i] = it.al[(size_t)i * m + v];
-        sbb[i] = it.b2[(size_t)i * m + v];
+        const double b2 = it.b2[(size_t)i * m + v];
+        sbb[i] = b2;
+        sb[i] = sqrt(fmax(b2, 0.0));
+        sib[i] = 1.0 / sb[i];
     }
     __syncthreads();
     double th, th1;
     rows_tridiag_max2(sal, sbb, steps, sfirst, &th, &th1);
-    const double bn = sqrt(fmax(sbb[steps - 1], 0.0));
+    const double bn = sb[steps - 1];
     bool stop = !(bn > 1e-300 * fmax(1.0, fabs(th))) || !isfinite(th);
     if (!stop && steps > 1) stop = fabs(th - th1) <= tol * fabs(th);
     if (threadIdx.x == 0) {
         it.theta[v] = th;
+        it.ubound[v] = stop ? HUGE_VAL : th + ritz_residual(sal, sb, sib, steps, th, bn);
         if (stop) it.done[v] = steps;
     }
 }
 
 // one workgroup per problem: {max theta, running views, max steps}, after
-// stopping the views whose eigenvalue bound is below the largest Ritz value
-// (a lower bound of the problem's lambda_h; the margin covers the rounding of
-// the Ritz values)
+// stopping the views whose eigenvalue lies below the largest Ritz value (a
+// lower bound of the problem's lambda_h; the margin covers the rounding of
+// the Ritz values): those whose symbol bound is below it, and those whose Ritz
+// value plus residual norm is -- B_v then has an eigenvalue below it next to
+// the Ritz value, and that eigenvalue is taken for the top one, the reading
+// the stopping rule of a converged chain rests on as well.
 __global__ __launch_bounds__(256) void rows_summary_kernel(const NormItem* __restrict__ items, int steps) {
     const NormItem& it = items[blockIdx.x];
     __shared__ double r0[256], r1[256], r2[256];
@@ -849,7 +890,7 @@ __global__ __launch_bounds__(256) void rows_summary_kernel(const NormItem* __res
     const double cut = it.fsym ? mx * (1.0 - 1e-9) : -1e300;
     double run = 0.0, st = 0.0;
     for (int v = threadIdx.x; v < it.m; v += 256) {
-        if (!it.done[v] && it.fsym && it.fsym[0] * it.maxinv[v] < cut) it.done[v] = steps;
+        if (!it.done[v] && it.fsym && (it.fsym[0] * it.maxinv[v] < cut || it.ubound[v] < cut)) it.done[v] = steps;
         if (!it.done[v]) run += 1.0;
         st = fmax(st, (double)it.done[v]);
     }
