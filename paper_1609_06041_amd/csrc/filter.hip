@@ -226,6 +226,23 @@ __device__ __forceinline__ void filter_tile(const FilterArgs& a, const float* __
         const int d = n0 + x - (kpad - 1);
         tl[x] = (d > -nb && d < nb) ? taps[nb - 1 + d] : 0.0f;
     }
+    // the epilogue's operands, loaded now so that their round trip overlaps
+    // the contraction instead of following the reduction
+    constexpr int NE = (FBM * FBN + FTHREADS - 1) / FTHREADS;
+    size_t eidx[NE];
+    bool eon[NE];
+    float ee0[NE], ee1[NE], esw[NE];
+#pragma unroll
+    for (int r = 0; r < NE; ++r) {
+        const int e = tid + r * FTHREADS;
+        const int i = e / FBN, jj = e - i * FBN;
+        const int v = v0 + i, col = n0 + jj;
+        eon[r] = e < FBM * FBN && v < m && col < nb;
+        eidx[r] = eon[r] ? (size_t)v * nb + col : 0;
+        ee0[r] = (eon[r] && a.E0) ? a.E0[eidx[r]] : 0.0f;
+        ee1[r] = (eon[r] && a.E1) ? a.E1[eidx[r]] : 0.0f;
+        esw[r] = (eon[r] && a.Sout) ? a.Sw[eidx[r]] : 0.0f;
+    }
     v4f acc[FNT];
 #pragma unroll
     for (int j = 0; j < FNT; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -255,7 +272,10 @@ __device__ __forceinline__ void filter_tile(const FilterArgs& a, const float* __
 #pragma unroll
         for (int r = 0; r < 4; ++r) red[((w * FNT + j) * 4 + r) * 64 + lane] = acc[j][r];
     __syncthreads();
-    for (int e = tid; e < FBM * FBN; e += FTHREADS) {
+#pragma unroll
+    for (int r = 0; r < NE; ++r) {
+        const int e = tid + r * FTHREADS;
+        if (!eon[r]) continue;
         const int i = e / FBN, jj = e - i * FBN;
         const int off = ((jj >> 4) * 4 + (i & 3)) * 64 + (jj & 15) + 16 * (i >> 2);
         float p[FKS];
@@ -265,19 +285,16 @@ __device__ __forceinline__ void filter_tile(const FilterArgs& a, const float* __
         for (int st = 1; st < FKS; st <<= 1)
 #pragma unroll
             for (int q = 0; q < FKS; q += 2 * st) p[q] += p[q + st];
-        const int v = v0 + i, col = n0 + jj;
-        if (v < m && col < nb) {
-            const size_t idx = (size_t)v * nb + col;
-            float val = a.c * p[0];
-            float e0v = 0.0f;
-            if (a.E0) {
-                e0v = a.E0[idx];
-                val = fmaf(a.e0, e0v, val);
-            }
-            if (a.E1) val = fmaf(a.e1, a.E1[idx], val);
-            a.out[idx] = val;
-            if (a.Sout) a.Sout[idx] = a.Sw[idx] * (val - e0v);
+        const size_t idx = eidx[r];
+        float val = a.c * p[0];
+        float e0v = 0.0f;
+        if (a.E0) {
+            e0v = ee0[r];
+            val = fmaf(a.e0, e0v, val);
         }
+        if (a.E1) val = fmaf(a.e1, ee1[r], val);
+        a.out[idx] = val;
+        if (a.Sout) a.Sout[idx] = esw[r] * (val - e0v);
     }
 }
 
