@@ -11,6 +11,8 @@
 // sinograms while staging it in LDS, the epilogue combines the result with up
 // to two sinograms.  A float64 variant (v_mfma_f64_16x16x4_f64) serves the
 // operator-norm computation.
+#include <mutex>
+
 #include "internal.h"
 
 namespace ctpd {
@@ -118,21 +120,21 @@ hipError_t launch_taps(double* taps64, float* taps32, int nb, int m, double tau,
 //
 // Work split: a workgroup owns one output block of 16 views x FNT*16 bins
 // (FNT 16 x 16 MFMA tiles sharing the A operand) and splits the contraction
-// over the bins j into 16-bin chunks dealt round-robin to its FKS waves, so
+// over the bins j into 32-bin steps dealt round-robin to its FKS waves, so
 // that every wave of the chip has a short, equal share of the matrix-core work
 // (the 720-view, 736-bin shape makes 720 such workgroups, all resident at
 // once).  The partial sums of the FKS waves meet in LDS and are added in a
-// fixed pairwise order, so every launch form gives the same bits.  Within a
-// chunk, MFMA step t of lane (i, q) (i = lane % 16, q = lane / 16) takes
-//     A[i][q] = s[v0 + i][k0 + 4q + t],  B[q][c] = h[n0 + c - (k0 + 4q + t)],
-// so a lane reads its 4 input values with one 16-byte load (where the row
-// length and alignment allow); the taps of the
-// block's range of offsets are staged once in LDS.  The next chunk's loads are
-// issued before the current chunk's MFMAs.
+// fixed pairwise order, so every launch form gives the same bits.  In step s
+// lane (i, g) (i = lane % 16, g = lane / 16) holds
+//     A[i][u] = s[v0 + i][32 s + 8 g + u],  B[u][c] = h[n0 + c - (32 s + 8 g + u)],
+// u = 0..7, so a lane reads its 8 input values with two 16-byte loads (where
+// the row length and alignment allow) and its taps as four aligned words of
+// LDS, where the taps of the block's range of offsets are staged once.  The
+// next step's loads are issued before the current step's MFMAs.
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int FNT = 3;                    // 16 x 16 output tiles per workgroup (along the bins)
-constexpr int FKS = 8;                    // waves per workgroup, each a share of the contraction
+constexpr int FKS = 4;                    // waves per workgroup, each a share of the contraction
 constexpr int FTHREADS = 64 * FKS;
 constexpr int FBN = 16 * FNT;             // output bins per workgroup
 constexpr int FBM = 16;                   // views per workgroup
@@ -144,6 +146,7 @@ template <int MODE>
 struct FilterIn {
     static constexpr int N = MODE == FILT_DUAL_LD ? 4 : MODE == FILT_EXTRAP ? 3 : MODE == FILT_DUAL_FV ? 2 : 1;
     __device__ static __forceinline__ float combine(const float* r) {
+#pragma clang fp contract(off)
         if (MODE == FILT_EXTRAP) return r[0] * (r[1] - r[2]);
         if (MODE == FILT_DUAL_LD) return fmaf(-r[2], r[3], r[0] - r[1]);
         if (MODE == FILT_DUAL_FV) return r[0] - r[1];
@@ -200,71 +203,241 @@ __device__ __forceinline__ void filter_load_chunk(const FilterArgs& a, size_t ro
     }
 }
 
-// Lay-out of the dynamic LDS: the taps of the block's offsets, then the
-// waves' partial tiles.
-__host__ __device__ constexpr int filter_taps_floats(int nb) {
-    return ((((nb + 15) / 16) * 16 + FBN + 63) / 64) * 64;
+// FP32 on the bf16 matrix cores.  Every operand x is split exactly into
+// three bf16 terms, x = x1 + x2 + x3 + e with |e| <= 2^-27 |x| (x1 = bf16(x),
+// x2 = bf16(x - x1), x3 = bf16(x - x1 - x2); both differences are exact in
+// FP32), and a product s h is formed from the six term products whose order
+// is at most 2^-16 of it (s1 h1, s1 h2, s2 h1, s1 h3, s3 h1, s2 h2); the
+// dropped ones are below 2^-23 of it.  A bf16 term product is exact in FP32
+// and the matrix core accumulates in FP32, so the contraction carries the
+// FP32 error of the products' accumulation, as with FP32 matrix instructions,
+// at 6 v_mfma_f32_16x16x32_bf16 (16 cycles each) per 32 x 16 x 16 block
+// instead of 8 v_mfma_f32_16x16x4_f32 (32 cycles each).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split3(float x, __bf16& t1, __bf16& t2, __bf16& t3) {
+    // x must be the rounded float: a product that forms x may not fuse with
+    // the subtraction below (the same input, formed in a prologue or read
+    // from memory, must split the same)
+#pragma clang fp contract(off)
+    t1 = (__bf16)x;
+    const float r1 = x - (float)t1;
+    t2 = (__bf16)r1;
+    t3 = (__bf16)(r1 - (float)t2);
 }
 
+// The inputs s[v][kk + t], t = 0..3, as filter_load_chunk reads them, but for
+// a single-input mode unmasked (past the row end they are values of the row,
+// zeroed by the caller where it uses them), so that nothing consumes the
+// loads until then and they stay in flight.
 template <int MODE, int VW>
+__device__ __forceinline__ void filter_load_raw(const FilterArgs& a, size_t row, int nb, int kk, float (&dst)[4]) {
+    if constexpr (FilterIn<MODE>::N > 1) {
+        filter_load_chunk<MODE, VW>(a, row, nb, kk, dst);
+    } else if constexpr (VW == 4) {
+        const float4 x = *reinterpret_cast<const float4*>(a.in0 + row + min(kk, nb - 4));
+        dst[0] = x.x;
+        dst[1] = x.y;
+        dst[2] = x.z;
+        dst[3] = x.w;
+    } else if constexpr (VW == 2) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float2 x = *reinterpret_cast<const float2*>(a.in0 + row + min(kk + 2 * h, nb - 2));
+            dst[2 * h] = x.x;
+            dst[2 * h + 1] = x.y;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) dst[t] = a.in0[row + min(kk + t, nb - 1)];
+    }
+}
+
+// Lay-out of the dynamic LDS: the block's taps, reversed (R[y] = h[n0 + FBN -
+// 1 - y]) and split into three bf16 terms, each term stored twice as bf16
+// pairs (copy e, word q = (R[2q + e], R[2q + e + 1])) so that every lane's
+// eight taps are four aligned words of one copy.
+__host__ __device__ constexpr int filter_tap_words(int nb) {
+    // ntl = kpad + FBN - 1 taps (kpad: nb rounded up to 32), one spare word
+    return ((((nb + 31) / 32) * 32 + FBN + 2) / 2 + 3) & ~3;
+}
+__host__ __device__ constexpr int filter_taps_floats(int nb) {
+    return ((6 * filter_tap_words(nb) + 63) / 64) * 64;
+}
+
+// LDS: the taps in the dynamic allocation (smem, its size set by the row
+// length), the waves' partial tiles in a static array of the kernel (red).
+constexpr int FRED = FKS * FNT * 256;   // [FKS][FNT][4][64] partial tiles
+
+// SPW > 0: every wave has at most SPW steps (nb <= 32 FKS SPW), which run
+// unrolled, so that the compiler tracks each load on its own and the loads
+// stay in flight across steps; SPW = 0: any row length, a loop over steps.
+template <int MODE, int VW, int SPW>
 __device__ __forceinline__ void filter_tile(const FilterArgs& a, const float* __restrict__ taps, int m, int nb,
-                                            float* smem, int tile) {
+                                            float* smem, float* red, int tile) {
     const int tiles_x = (nb + FBN - 1) / FBN;
     const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
     const int v0 = ty * FBM, n0 = tx * FBN;
-    const int nch = (nb + 15) >> 4, kpad = nch * 16;
+    const int nst = (nb + 31) >> 5, kpad = nst * 32;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int li = lane & 15, lq = lane >> 4;
-    float* tl = smem;                            // tl[x] = h[n0 + x - (kpad - 1)], zero outside the taps
-    float* red = smem + filter_taps_floats(nb);  // [FKS][FNT][4][64] partial tiles
+    const int TQ = filter_tap_words(nb);
+    unsigned int* tb = reinterpret_cast<unsigned int*>(smem);   // [term][copy][TQ]
     const size_t row = (size_t)min(v0 + li, m - 1) * nb;   // rows past m only feed outputs never stored
-    float cur[4], nxt[4];
-    int c = w;
-    filter_load_chunk<MODE, VW>(a, row, nb, 16 * min(c, nch - 1) + 4 * lq, cur);
-    const int ntl = kpad + FBN - 1;
-    for (int x = tid; x < ntl; x += FTHREADS) {
-        const int d = n0 + x - (kpad - 1);
-        tl[x] = (d > -nb && d < nb) ? taps[nb - 1 + d] : 0.0f;
-    }
-    // the epilogue's operands, loaded now so that their round trip overlaps
-    // the contraction instead of following the reduction
-    constexpr int NE = (FBM * FBN + FTHREADS - 1) / FTHREADS;
-    size_t eidx[NE];
-    bool eon[NE];
-    float ee0[NE], ee1[NE], esw[NE];
+    // step s (bins 32 s .. 32 s + 31) of lane (i, g): A[i][u] = s[v0 + i][32 s + 8 g + u]
+    auto load_step = [&](int st, float (&dst)[8]) {
+        float lo4[4], hi4[4];
+        filter_load_raw<MODE, VW>(a, row, nb, 32 * st + 8 * lq, lo4);
+        filter_load_raw<MODE, VW>(a, row, nb, 32 * st + 8 * lq + 4, hi4);
 #pragma unroll
-    for (int r = 0; r < NE; ++r) {
-        const int e = tid + r * FTHREADS;
-        const int i = e / FBN, jj = e - i * FBN;
-        const int v = v0 + i, col = n0 + jj;
-        eon[r] = e < FBM * FBN && v < m && col < nb;
-        eidx[r] = eon[r] ? (size_t)v * nb + col : 0;
-        ee0[r] = (eon[r] && a.E0) ? a.E0[eidx[r]] : 0.0f;
-        ee1[r] = (eon[r] && a.E1) ? a.E1[eidx[r]] : 0.0f;
-        esw[r] = (eon[r] && a.Sout) ? a.Sw[eidx[r]] : 0.0f;
+        for (int t = 0; t < 4; ++t) {
+            dst[t] = lo4[t];
+            dst[4 + t] = hi4[t];
+        }
+    };
+    // two steps in flight: this wave's first two steps now, each later one as
+    // soon as a buffer is split
+    float cur[8], nxt[8];
+    int c = w;
+    if (SPW > 0 || c < nst) load_step(min(c, nst - 1), cur);
+    if (SPW > 0 || c + FKS < nst) load_step(min(c + FKS, nst - 1), nxt);
+    // the taps, split and laid out as above (R[y] = 0 outside the filter):
+    // thread q forms word q of both copies from R[2q], R[2q + 1], R[2q + 2]
+    // (loads from clamped indices, so that they carry no branch and are
+    // issued together; the unrolled form knows how many words a thread has)
+    const int ntl = kpad + FBN - 1;
+    auto stage = [&](int q) {
+        // a thread past the last word stores the last word again: it, like
+        // every word from TQ - 1 on, holds only taps past the window (zeros),
+        // so the store needs no branch
+        q = min(q, TQ - 1);
+        float v[3];
+#pragma unroll
+        for (int h = 0; h < 3; ++h) {
+            const int y = 2 * q + h;
+            const int d = n0 + FBN - 1 - y;
+            // (a product, not a select: the compiler may not skip the load of
+            // a value that could be a NaN, so the load carries no branch)
+            const float t = taps[min(max(nb - 1 + d, 0), 2 * nb - 2)];
+            v[h] = t * ((y < ntl && d > -nb && d < nb) ? 1.0f : 0.0f);
+        }
+        unsigned int t[3][3];
+#pragma unroll
+        for (int h = 0; h < 3; ++h) {
+            __bf16 t1, t2, t3;
+            split3(v[h], t1, t2, t3);
+            t[0][h] = __builtin_bit_cast(unsigned short, t1);
+            t[1][h] = __builtin_bit_cast(unsigned short, t2);
+            t[2][h] = __builtin_bit_cast(unsigned short, t3);
+        }
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            tb[(2 * p) * TQ + q] = t[p][0] | (t[p][1] << 16);
+            tb[(2 * p + 1) * TQ + q] = t[p][1] | (t[p][2] << 16);
+        }
+    };
+    if constexpr (SPW > 0) {
+        constexpr int NQ = (filter_tap_words(32 * FKS * SPW) + FTHREADS - 1) / FTHREADS;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) stage(tid + k * FTHREADS);
+    } else {
+        for (int q = tid; q < TQ; q += FTHREADS) stage(q);
     }
+    // the epilogue's operands (element e = tid + r FTHREADS of the block),
+    // loaded by each wave with its last step, into the registers its input
+    // buffers free, so that their round trip overlaps that step's MFMAs
+    constexpr int NE = (FBM * FBN + FTHREADS - 1) / FTHREADS;
+    float ee0[NE], ee1[NE], esw[NE];
+    // (unconditional loads: an operand the launch lacks is read from the
+    // input in its place, an element outside the block from the block's
+    // first, and neither is used; branches here would make the compiler wait
+    // for every load in flight)
+    const float* pe0 = a.E0 ? a.E0 : a.in0;
+    const float* pe1 = a.E1 ? a.E1 : a.in0;
+    const float* psw = a.Sout ? a.Sw : a.in0;
+    auto epi_load = [&]() {
+#pragma unroll
+        for (int r = 0; r < NE; ++r) {
+            const int e = tid + r * FTHREADS;
+            const int i = e / FBN, jj = e - i * FBN;
+            const int v = v0 + i, col = n0 + jj;
+            const bool on = e < FBM * FBN && v < m && col < nb;
+            const size_t idx = on ? (size_t)v * nb + col : (size_t)v0 * nb + n0;
+            ee0[r] = pe0[idx];
+            ee1[r] = pe1[idx];
+            esw[r] = psw[idx];
+        }
+    };
     v4f acc[FNT];
 #pragma unroll
     for (int j = 0; j < FNT; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
-    __syncthreads();
-    const int bl = li - 4 * lq + kpad - 1;
-    auto mma = [&](const float (&av)[4], int k0) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int j = 0; j < FNT; ++j)
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], tl[bl + 16 * j - k0 - t], acc[j], 0, 0, 0);
+    // the taps are in LDS once every wave's LDS writes are done; the global
+    // loads issued so far stay in flight across this barrier (a
+    // __syncthreads would wait for them too)
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    // B[u][ci] = h[n0 + 16 j + ci - 32 s - 8 g - u] = R[yb + u] with
+    // yb = FBN - 1 - ci - 16 j + 32 s + 8 g, whose parity is that of FBN - 1 - ci
+    const int ecp = (FBN - 1 - li) & 1;
+    const int qb = (FBN - 1 - li - ecp) / 2 + 4 * lq;
+    const unsigned int* tc = tb + ecp * TQ;
+    auto bterm = [&](int p, int q0) {
+        const unsigned int* src = tc + 2 * p * TQ + q0;
+        const u32x4 wv = u32x4{src[0], src[1], src[2], src[3]};
+        return __builtin_bit_cast(bf16x8, wv);
     };
-    // chunks c, c + FKS, ... in pairs (loads clamped to the last chunk, so
-    // they are unconditional); a pair's second chunk past the end is skipped
-    for (; c < nch; c += 2 * FKS) {
-        filter_load_chunk<MODE, VW>(a, row, nb, 16 * min(c + FKS, nch - 1) + 4 * lq, nxt);
+    // step st: its inputs (buf) are split into their bf16 terms, then (ahead)
+    // the step two further on is loaded into the freed registers, or (epi)
+    // the epilogue's operands, then the MFMAs run.  A step past the row end
+    // (st >= nst: the even step count of the unrolled form) has its inputs
+    // zeroed and adds exact zeros.
+    auto step = [&](float (&buf)[8], int st, bool ahead, bool epi) {
+        bf16x8 a1, a2, a3;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            __bf16 t1, t2, t3;
+            split3(32 * st + 8 * lq + u < nb ? buf[u] : 0.0f, t1, t2, t3);
+            a1[u] = t1;
+            a2[u] = t2;
+            a3[u] = t3;
+        }
+        if (ahead)
+            load_step(min(st + 2 * FKS, nst - 1), buf);
+        else if (epi)
+            epi_load();
         __builtin_amdgcn_sched_barrier(0);
-        mma(cur, 16 * c);
-        __builtin_amdgcn_sched_barrier(0);
-        filter_load_chunk<MODE, VW>(a, row, nb, 16 * min(c + 2 * FKS, nch - 1) + 4 * lq, cur);
-        __builtin_amdgcn_sched_barrier(0);
-        if (c + FKS < nch) mma(nxt, 16 * (c + FKS));
+        const int sb = min(st, nst - 1);   // keeps the tap reads in the staged range
+#pragma unroll
+        for (int j = 0; j < FNT; ++j) {
+            const int q0 = qb - 8 * j + 16 * sb;
+            const bf16x8 b1 = bterm(0, q0), b2 = bterm(1, q0), b3 = bterm(2, q0);
+            // smallest terms first
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, b1, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b3, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b2, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b1, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b2, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[j], 0, 0, 0);
+        }
+    };
+    if constexpr (SPW > 0) {
+        // exactly SPW steps per wave, no branches: every load is tracked on
+        // its own and stays in flight until its step
+#pragma unroll
+        for (int k = 0; k < SPW; ++k) {
+            if (k & 1)
+                step(nxt, c + k * FKS, k + 2 < SPW, k == SPW - 1);
+            else
+                step(cur, c + k * FKS, k + 2 < SPW, k == SPW - 1);
+        }
+    } else {
+        // steps c, c + FKS, ... (the two buffers alternate)
+        for (; c < nst; c += 2 * FKS) {
+            const bool last0 = c + FKS >= nst, last1 = c + 2 * FKS >= nst;
+            step(cur, c, c + 2 * FKS < nst, last0);
+            if (c + FKS < nst) step(nxt, c + FKS, c + 3 * FKS < nst, last1);
+        }
+        if (w >= nst) epi_load();   // a wave without steps
     }
     // MFMA 16x16 result: D[i][c] in lane c + 16 (i / 4), element i % 4
 #pragma unroll
@@ -275,8 +448,9 @@ __device__ __forceinline__ void filter_tile(const FilterArgs& a, const float* __
 #pragma unroll
     for (int r = 0; r < NE; ++r) {
         const int e = tid + r * FTHREADS;
-        if (!eon[r]) continue;
         const int i = e / FBN, jj = e - i * FBN;
+        const int v = v0 + i, col = n0 + jj;
+        if (!(e < FBM * FBN && v < m && col < nb)) continue;
         const int off = ((jj >> 4) * 4 + (i & 3)) * 64 + (jj & 15) + 16 * (i >> 2);
         float p[FKS];
 #pragma unroll
@@ -285,16 +459,23 @@ __device__ __forceinline__ void filter_tile(const FilterArgs& a, const float* __
         for (int st = 1; st < FKS; st <<= 1)
 #pragma unroll
             for (int q = 0; q < FKS; q += 2 * st) p[q] += p[q + st];
-        const size_t idx = eidx[r];
-        float val = a.c * p[0];
-        float e0v = 0.0f;
-        if (a.E0) {
-            e0v = ee0[r];
-            val = fmaf(a.e0, e0v, val);
+        const size_t idx = (size_t)v * nb + col;
+        {
+            // no contraction here: where a launch form fixes e0 = 1 at
+            // compile time the fmaf below folds to an add, which would fuse
+            // with this product, and that form would round once where the
+            // others round twice
+#pragma clang fp contract(off)
+            float val = a.c * p[0];
+            float e0v = 0.0f;
+            if (a.E0) {
+                e0v = ee0[r];
+                val = fmaf(a.e0, e0v, val);
+            }
+            if (a.E1) val = fmaf(a.e1, ee1[r], val);
+            a.out[idx] = val;
+            if (a.Sout) a.Sout[idx] = esw[r] * (val - e0v);
         }
-        if (a.E1) val = fmaf(a.e1, ee1[r], val);
-        a.out[idx] = val;
-        if (a.Sout) a.Sout[idx] = esw[r] * (val - e0v);
     }
 }
 
@@ -302,32 +483,51 @@ __device__ __forceinline__ void filter_tile(const FilterArgs& a, const float* __
 // choice (per workgroup, from nb and the input addresses) never changes a bit.
 template <int MODE>
 __device__ __forceinline__ void filter_body(const FilterArgs& a, const float* __restrict__ taps, int m, int nb,
-                                            float* smem, int tile) {
+                                            float* smem, float* red, int tile) {
     constexpr int NIN = FilterIn<MODE>::N;
     const uintptr_t bits = (uintptr_t)a.in0 | (NIN > 1 ? (uintptr_t)a.in1 : 0) | (NIN > 2 ? (uintptr_t)a.in2 : 0) |
                            (NIN > 3 ? (uintptr_t)a.in3 : 0);
-    if ((nb & 3) == 0 && (bits & 15) == 0)
-        filter_tile<MODE, 4>(a, taps, m, nb, smem, tile);
-    else if ((nb & 1) == 0 && (bits & 7) == 0)
-        filter_tile<MODE, 2>(a, taps, m, nb, smem, tile);
-    else
-        filter_tile<MODE, 1>(a, taps, m, nb, smem, tile);
+    if ((nb & 3) == 0 && (bits & 15) == 0) {
+        const int spw = ((nb + 31) / 32 + FKS - 1) / FKS;
+        if (spw <= 2)
+            filter_tile<MODE, 4, 2>(a, taps, m, nb, smem, red, tile);
+        else if (spw <= 4)
+            filter_tile<MODE, 4, 4>(a, taps, m, nb, smem, red, tile);
+        else if (spw <= 6)
+            filter_tile<MODE, 4, 6>(a, taps, m, nb, smem, red, tile);
+        else if (spw <= 8)
+            filter_tile<MODE, 4, 8>(a, taps, m, nb, smem, red, tile);
+        else
+            filter_tile<MODE, 4, 0>(a, taps, m, nb, smem, red, tile);
+    } else if ((nb & 1) == 0 && (bits & 7) == 0) {
+        filter_tile<MODE, 2, 0>(a, taps, m, nb, smem, red, tile);
+    } else {
+        filter_tile<MODE, 1, 0>(a, taps, m, nb, smem, red, tile);
+    }
 }
 
 template <int MODE>
-__global__ __launch_bounds__(FTHREADS) void filter_mfma_kernel(FilterArgs a, const float* __restrict__ taps, int m,
+__global__ __launch_bounds__(FTHREADS) __attribute__((amdgpu_waves_per_eu(3))) void filter_mfma_kernel(FilterArgs a, const float* __restrict__ taps, int m,
                                                                int nb) {
     extern __shared__ float smem[];
-    filter_body<MODE>(a, taps, m, nb, smem, blockIdx.x);
+    __shared__ float red[FRED];
+    filter_body<MODE>(a, taps, m, nb, smem, red, blockIdx.x);
 }
 
-size_t filter_lds_bytes(int nb) {
-    return sizeof(float) * ((size_t)filter_taps_floats(nb) + (size_t)FKS * FNT * 256);
-}
+// the dynamic part (the taps); the partial tiles are static
+size_t filter_lds_bytes(int nb) { return sizeof(float) * (size_t)filter_taps_floats(nb); }
+
+// past 64 KB of LDS in all (rows of more than ~3400 bins) the limit of the
+// filter kernels is lifted, once, to what the longest row needs
+static hipError_t filter_lds_lift();
 
 hipError_t launch_filter_f32(const FilterArgs& a, const float* taps32, int m, int nb, hipStream_t s) {
     const int grid = filter_blocks_x(nb) * filter_blocks_y(m);
     const size_t lds = filter_lds_bytes(nb);
+    if (lds + sizeof(float) * FRED > 65536) {
+        const hipError_t e = filter_lds_lift();
+        if (e != hipSuccess) return e;
+    }
     switch (a.mode) {
         case FILT_EXTRAP: filter_mfma_kernel<FILT_EXTRAP><<<grid, FTHREADS, lds, s>>>(a, taps32, m, nb); break;
         case FILT_DUAL_LD: filter_mfma_kernel<FILT_DUAL_LD><<<grid, FTHREADS, lds, s>>>(a, taps32, m, nb); break;
@@ -344,9 +544,10 @@ hipError_t launch_filter_f32(const FilterArgs& a, const float* taps32, int m, in
 // (q), the extrapolation's W^-1 (mu^k - mu^{k-1}) by the previous dual update
 // (sx), so every launch runs the plain prologue.
 template <int MODE>
-__global__ __launch_bounds__(FTHREADS) void filter_batched(const BatchItem* __restrict__ items,
+__global__ __launch_bounds__(FTHREADS) __attribute__((amdgpu_waves_per_eu(3))) void filter_batched(const BatchItem* __restrict__ items,
                                                       const BlockRef* __restrict__ map, int rot) {
     extern __shared__ float smem[];
+    __shared__ float red[FRED];
     const BlockRef e = map[blockIdx.x];
     if (e.prob < 0) return;
     const BatchItem& it = items[e.prob];
@@ -375,12 +576,16 @@ __global__ __launch_bounds__(FTHREADS) void filter_batched(const BatchItem* __re
         a.Sw = it.winv;
         a.Sout = it.sx;
     }
-    filter_body<FILT_PLAIN>(a, it.taps, it.m, it.nb, smem, e.local);
+    filter_body<FILT_PLAIN>(a, it.taps, it.m, it.nb, smem, red, e.local);
 }
 
 hipError_t launch_filter_batched(const BatchItem* items, const BlockRef* map, int nblocks, int mode, int rot,
                                  int max_nb, hipStream_t s) {
     const size_t lds = filter_lds_bytes(max_nb);
+    if (lds + sizeof(float) * FRED > 65536) {
+        const hipError_t e = filter_lds_lift();
+        if (e != hipSuccess) return e;
+    }
     switch (mode) {
         case FILT_EXTRAP: filter_batched<FILT_EXTRAP><<<nblocks, FTHREADS, lds, s>>>(items, map, rot); break;
         case FILT_DUAL_LD: filter_batched<FILT_DUAL_LD><<<nblocks, FTHREADS, lds, s>>>(items, map, rot); break;
@@ -392,19 +597,24 @@ hipError_t launch_filter_batched(const BatchItem* items, const BlockRef* map, in
 
 // One recorded filter step per problem (the unrolled passes).
 template <int MODE>
-__global__ __launch_bounds__(FTHREADS) void step_filter_kernel(const UStep* __restrict__ steps,
+__global__ __launch_bounds__(FTHREADS) __attribute__((amdgpu_waves_per_eu(3))) void step_filter_kernel(const UStep* __restrict__ steps,
                                                           const BlockRef* __restrict__ map) {
     extern __shared__ float smem[];
+    __shared__ float red[FRED];
     const BlockRef e = map[blockIdx.x];
     if (e.prob < 0) return;
     const UStep& st = steps[e.prob];
     if (!st.active) return;
-    filter_body<MODE>(st.fa, st.taps, st.m, st.nb, smem, e.local);
+    filter_body<MODE>(st.fa, st.taps, st.m, st.nb, smem, red, e.local);
 }
 
 hipError_t launch_step_filter(const UStep* steps, const BlockRef* map, int nblocks, int mode, int max_nb,
                               hipStream_t s) {
     const size_t lds = filter_lds_bytes(max_nb);
+    if (lds + sizeof(float) * FRED > 65536) {
+        const hipError_t e = filter_lds_lift();
+        if (e != hipSuccess) return e;
+    }
     switch (mode) {
         case FILT_EXTRAP: step_filter_kernel<FILT_EXTRAP><<<nblocks, FTHREADS, lds, s>>>(steps, map); break;
         case FILT_DUAL_LD: step_filter_kernel<FILT_DUAL_LD><<<nblocks, FTHREADS, lds, s>>>(steps, map); break;
@@ -412,6 +622,25 @@ hipError_t launch_step_filter(const UStep* steps, const BlockRef* map, int nbloc
         default: step_filter_kernel<FILT_PLAIN><<<nblocks, FTHREADS, lds, s>>>(steps, map); break;
     }
     return hipGetLastError();
+}
+
+static hipError_t filter_lds_lift() {
+    static std::once_flag once;
+    static hipError_t attr = hipSuccess;
+    std::call_once(once, [] {
+        const void* k[] = {
+            (const void*)filter_mfma_kernel<FILT_PLAIN>,  (const void*)filter_mfma_kernel<FILT_EXTRAP>,
+            (const void*)filter_mfma_kernel<FILT_DUAL_LD>, (const void*)filter_mfma_kernel<FILT_DUAL_FV>,
+            (const void*)filter_batched<FILT_PLAIN>,      (const void*)filter_batched<FILT_EXTRAP>,
+            (const void*)filter_batched<FILT_DUAL_LD>,    (const void*)filter_batched<FILT_DUAL_FV>,
+            (const void*)step_filter_kernel<FILT_PLAIN>,  (const void*)step_filter_kernel<FILT_EXTRAP>,
+            (const void*)step_filter_kernel<FILT_DUAL_LD>, (const void*)step_filter_kernel<FILT_DUAL_FV>};
+        for (const void* f : k)
+            if (attr == hipSuccess)
+                attr = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)filter_lds_bytes(CTPD_MAX_BINS));
+    });
+    return attr;
 }
 
 // Upper bound of the largest eigenvalue of the nb x nb Toeplitz section of

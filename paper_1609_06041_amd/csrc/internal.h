@@ -9,6 +9,9 @@
 
 #include "ctpd.h"
 
+// the LDS operand of the global-to-LDS copy builtin
+typedef __attribute__((address_space(3))) void lds_void_t;
+
 namespace ctpd {
 
 // Per-view geometry, built on the host in float64 (see make_views in api.hip).

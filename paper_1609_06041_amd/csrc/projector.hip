@@ -304,7 +304,6 @@ __global__ __launch_bounds__(64 * kSplitWaves) void forward_split_kernel(
 constexpr int kSlabWaves = 12, kSlabThreads = 64 * kSlabWaves, kSlabTPW = 3, kSlabTasks = kSlabWaves * kSlabTPW;
 constexpr int kSlabFB = 2;
 constexpr size_t kSlabMaxLds = 160 * 1024;
-typedef __attribute__((address_space(3))) void lds_void_t;
 
 size_t forward_slab_lds(int n) { return (size_t)2 * FW_SEG * (n + 2 * FP_PAD) * sizeof(float); }
 bool forward_slab_fits(int n) { return forward_slab_lds(n) <= kSlabMaxLds; }
