@@ -111,7 +111,20 @@ def test_ramp_filter_matches_oracle(gpu, parity, m, nb, kappa):
     parity("out", rel(out, ref), TOL)
 
 
-@pytest.mark.parametrize("m,nb", [(90, 546), (40, 96), (21, 70), (33, 65)])
+@pytest.mark.parametrize("m,nb", [(17, 1024), (5, 1056), (3, ctpd.MAX_BINS)])
+def test_ramp_filter_long_rows_match_oracle(gpu, parity, m, nb):
+    # 1024 bins: the longest row of the unrolled step form (8 steps of 32 bins
+    # per wave); 1056: the first of the looped form; the maximum row length
+    rng = np.random.default_rng(nb + m)
+    s = f32(rng.standard_normal((m, nb)))
+    tau, kappa = math.pi * 2e-4 / (2 * m), 2e-4
+    with ctpd.Operator(8, m, nb) as op:
+        out = host(op.ramp_filter(dev(s), tau, kappa))
+    ref = OF.apply_filter(s, OF.smoothed_ramp_taps(nb, m, tau, kappa))
+    parity("out", rel(out, ref), TOL)
+
+
+@pytest.mark.parametrize("m,nb", [(90, 546), (40, 96), (21, 70), (33, 65), (7, 1056)])
 def test_ramp_filter_load_widths_agree(gpu, m, nb):
     # the filter reads its input 16, 8 or 4 bytes a lane, as the row length
     # and the input's address allow; every width must give the same bits
