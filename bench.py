@@ -55,6 +55,12 @@ AT_FLOP_PER_UPDATE = 15.0
 # a + f (b - a) (sub + FMA = 3), the accumulation (1).
 A_FLOP_PER_STEP = 9.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
+# The filter forms each FP32 product from 6 bf16 term products on the bf16
+# matrix cores (dense peak 2500 TFLOP/s), so its FP32-equivalent peak is
+# 2500 / 6.
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+FILTER_TERM_PRODUCTS = 6
+PEAK_FILTER_TFLOPS = PEAK_BF16_MFMA_TFLOPS / FILTER_TERM_PRODUCTS
 PEAK_HBM_GBS = 8000.0
 N_INSTANCES = 3   # independent inputs cycled through by the timed solves
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lowdose512_kernels_traffic.md")
@@ -644,9 +650,13 @@ def main() -> int:
                         "work_per_launch": f"{updates:.4g} (pixel, view) updates x {AT_FLOP_PER_UPDATE:.0f} FLOP",
                         "peak_note": peak_note},
         "roofline_filter": {"kernel": "filter_mfma_kernel (D, one launch per ctpd_filter after its taps kernel)",
-                            "bound": "mfma", "achieved": d_tflops, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                            "frac": d_tflops / PEAK_FP32_MFMA_TFLOPS, "traffic": read_traffic("filter"),
-                            "work_per_launch": f"dense Toeplitz contraction 2 x {m} x {nb} x {nb} FLOP (FP32 MFMA)"},
+                            "bound": "mfma", "achieved": d_tflops, "peak": PEAK_FILTER_TFLOPS, "unit": "TFLOP/s",
+                            "frac": d_tflops / PEAK_FILTER_TFLOPS, "traffic": read_traffic("filter"),
+                            "work_per_launch": f"dense Toeplitz contraction 2 x {m} x {nb} x {nb} FP32 FLOP",
+                            "peak_note": f"each FP32 product is {FILTER_TERM_PRODUCTS} bf16 term products "
+                                         f"(exact three-term splits, FP32 accumulation): bf16 dense "
+                                         f"{PEAK_BF16_MFMA_TFLOPS:.0f} / {FILTER_TERM_PRODUCTS}; the FP32 MFMA "
+                                         f"peak is {PEAK_FP32_MFMA_TFLOPS}"},
         "roofline_tv": {"kernel": "tv_prox_kernel (10 dual steps fused, one launch per ctpd_tv_prox)",
                         "bound": "alu", "achieved_gbs": tv_gbs, "hbm_frac": tv_gbs / PEAK_HBM_GBS,
                         "traffic": read_traffic("tv"),

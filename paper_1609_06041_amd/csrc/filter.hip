@@ -511,7 +511,13 @@ __global__ __launch_bounds__(FTHREADS) __attribute__((amdgpu_waves_per_eu(3))) v
                                                                int nb) {
     extern __shared__ float smem[];
     __shared__ float red[FRED];
-    filter_body<MODE>(a, taps, m, nb, smem, red, blockIdx.x);
+    // Workgroups are dealt to the 8 XCDs round-robin (workgroup b to XCD
+    // b mod 8); XCD x takes the x-th contiguous run of tiles (view-block
+    // major), so the rows of a view block are fetched into one or two XCDs'
+    // L2 instead of all eight.  A permutation of the tiles: same bits.
+    const int G = gridDim.x, per = G >> 3, rem = G & 7, x = blockIdx.x & 7;
+    const int tile = x * per + min(x, rem) + (blockIdx.x >> 3);
+    filter_body<MODE>(a, taps, m, nb, smem, red, tile);
 }
 
 // the dynamic part (the taps); the partial tiles are static

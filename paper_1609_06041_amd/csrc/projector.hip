@@ -581,6 +581,7 @@ std::vector<int> forward_slab_schedule(const ViewGeom* hv, int m, int n, int nb,
         G[1] = total - G[0];
     }
     std::vector<int> out;
+    int ng[2] = {0, 0};   // groups emitted per orientation
     for (int o = 0; o < 2; ++o) {
         if (!G[o]) continue;
         const int B = G[o] * kSlabSimds;
@@ -638,9 +639,23 @@ std::vector<int> forward_slab_schedule(const ViewGeom* hv, int m, int n, int nb,
                     const int wv = k + kSlabSimds * c;
                     for (int j = 0; j < J; ++j) out[base + wv + (size_t)W * j] = jobs[o][q].task[j];
                 }
+            ++ng[o];
         }
     }
-    return out;
+    // Workgroup b runs on XCD b mod 8: groups of orientation 0 go to
+    // positions b mod 8 < 4 and those of orientation 1 to the others (either
+    // taking the other's positions once it has none left), so each padded
+    // plane is pulled into four XCDs' L2 instead of all eight.  Which
+    // workgroup runs a group changes no ray's sum.
+    const size_t GS = (size_t)W * J;
+    std::vector<int> xcd(out.size());
+    int i0 = 0, i1 = 0;
+    for (int b = 0; b < ng[0] + ng[1]; ++b) {
+        const bool first = (b & 7) < 4;
+        const int g = ((first && i0 < ng[0]) || i1 >= ng[1]) ? i0++ : ng[0] + i1++;
+        std::copy(out.begin() + (size_t)g * GS, out.begin() + (size_t)(g + 1) * GS, xcd.begin() + (size_t)b * GS);
+    }
+    return xcd;
 }
 
 // The split form's workgroup order: the (view, block) tasks by decreasing step
