@@ -621,14 +621,16 @@ int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, cons
     // steps j0 .. j1-1, the Ritz values and the summary, copied to a pinned
     // slot of 3 P doubles with an event behind it
     auto enqueue = [&](int j0, int j1, int slot) -> int {
-        if (fused) HIP_TRY(launch_rows_round(items, rows, nrows, j0, j1, max_nb, s));
-        else
+        if (fused) {
+            HIP_TRY(launch_rows_round(items, rows, nrows, P, j0, j1, max_nb, kRowsTol, s));
+        } else {
             for (int j = j0; j < j1; ++j) {
                 const int rot = (3 - j % 3) % 3;
                 HIP_TRY(launch_norm_filter_batched(items, filt, nfilt, rot, s));
                 HIP_TRY(launch_rows_step(items, rows, nrows, rot, j, s));
             }
-        HIP_TRY(launch_rows_ritz(items, rows, nrows, P, j1, kRowsTol, s));
+            HIP_TRY(launch_rows_ritz(items, rows, nrows, P, j1, kRowsTol, s));
+        }
         HIP_TRY(hipMemcpyAsync(summary_host + (size_t)3 * P * slot, summary, sizeof(double) * 3 * P,
                                hipMemcpyDeviceToHost, s));
         HIP_TRY(hipEventRecord(ev[slot], s));

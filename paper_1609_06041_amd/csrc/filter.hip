@@ -507,8 +507,8 @@ __device__ __forceinline__ void filter_body(const FilterArgs& a, const float* __
 }
 
 template <int MODE>
-__global__ __launch_bounds__(FTHREADS) __attribute__((amdgpu_waves_per_eu(3))) void filter_mfma_kernel(FilterArgs a, const float* __restrict__ taps, int m,
-                                                               int nb) {
+__global__ __launch_bounds__(FTHREADS) __attribute__((amdgpu_waves_per_eu(3))) void filter_mfma_kernel(
+    FilterArgs a, const float* __restrict__ taps, int m, int nb) {
     extern __shared__ float smem[];
     __shared__ float red[FRED];
     // Workgroups are dealt to the 8 XCDs round-robin (workgroup b to XCD
@@ -550,8 +550,8 @@ hipError_t launch_filter_f32(const FilterArgs& a, const float* taps32, int m, in
 // (q), the extrapolation's W^-1 (mu^k - mu^{k-1}) by the previous dual update
 // (sx), so every launch runs the plain prologue.
 template <int MODE>
-__global__ __launch_bounds__(FTHREADS) __attribute__((amdgpu_waves_per_eu(3))) void filter_batched(const BatchItem* __restrict__ items,
-                                                      const BlockRef* __restrict__ map, int rot) {
+__global__ __launch_bounds__(FTHREADS) __attribute__((amdgpu_waves_per_eu(3))) void filter_batched(
+    const BatchItem* __restrict__ items, const BlockRef* __restrict__ map, int rot) {
     extern __shared__ float smem[];
     __shared__ float red[FRED];
     const BlockRef e = map[blockIdx.x];
@@ -603,8 +603,8 @@ hipError_t launch_filter_batched(const BatchItem* items, const BlockRef* map, in
 
 // One recorded filter step per problem (the unrolled passes).
 template <int MODE>
-__global__ __launch_bounds__(FTHREADS) __attribute__((amdgpu_waves_per_eu(3))) void step_filter_kernel(const UStep* __restrict__ steps,
-                                                          const BlockRef* __restrict__ map) {
+__global__ __launch_bounds__(FTHREADS) __attribute__((amdgpu_waves_per_eu(3))) void step_filter_kernel(
+    const UStep* __restrict__ steps, const BlockRef* __restrict__ map) {
     extern __shared__ float smem[];
     __shared__ float red[FRED];
     const BlockRef e = map[blockIdx.x];

@@ -342,11 +342,13 @@ hipError_t launch_rows_start(const NormItem* it, const RowRef* rows, int nrows, 
 hipError_t launch_rows_prune(const NormItem* it, const RowRef* rows, int nrows, int count, hipStream_t s);
 hipError_t launch_rows_step(const NormItem* it, const RowRef* rows, int nrows, int rot, int j, hipStream_t s);
 // steps j0 .. j1-1 of every running chain in one launch (q in v[0], previous q
-// in v[1] on entry and exit); only when rows_round_fits(the largest nb of the
-// table), which holds up to 1024 bins
+// in v[1] on entry and exit), each chain's Ritz step after them (as
+// launch_rows_ritz: the same arithmetic) and the summary (count = problems);
+// only when rows_round_fits(the largest nb of the table), which holds up to
+// 1024 bins
 bool rows_round_fits(int max_nb);
-hipError_t launch_rows_round(const NormItem* it, const RowRef* rows, int nrows, int j0, int j1, int max_nb,
-                             hipStream_t s);
+hipError_t launch_rows_round(const NormItem* it, const RowRef* rows, int nrows, int count, int j0, int j1,
+                             int max_nb, double tol, hipStream_t s);
 // upper bound of max over omega of h0 + 2 sum_k h_k cos(k omega) (taps64 as
 // launch_taps writes them) into out[0]; out[1 ..] is scratch (kSymBlocks doubles)
 constexpr int kSymBlocks = 64;

@@ -577,9 +577,19 @@ __device__ __forceinline__ void round_matvec(const double* __restrict__ sT, cons
     }
 }
 
+__device__ __forceinline__ void rows_ritz_view(const NormItem& it, int v, int steps, double tol,
+                                               const double* __restrict__ sal, const double* __restrict__ sbb,
+                                               double* __restrict__ sb, double* __restrict__ sib,
+                                               int* __restrict__ sfirst);
+constexpr int kRitzMaxSteps = CTPD_MAX_NORM_STEPS;
+static_assert(4 * kRitzMaxSteps <= 4 * kRoundChunk, "the Ritz step's arrays fit in the wave partials' LDS");
+
+// Steps j0 .. j1 - 1 of a running view's chain, then its Ritz step (the
+// round's workgroup computes the Ritz value, the residual norm and the stop
+// of its own chain, in the LDS of the wave partials, free by then).
 __global__ __launch_bounds__(kRoundThreads) void rows_round_kernel(const NormItem* __restrict__ items,
                                                                    const RowRef* __restrict__ rows, int nrows,
-                                                                   int j0, int j1) {
+                                                                   int j0, int j1, double tol) {
     extern __shared__ double rsm[];
     const int row = blockIdx.x;
     if (row >= nrows) return;
@@ -683,6 +693,18 @@ __global__ __launch_bounds__(kRoundThreads) void rows_round_kernel(const NormIte
             it.v[1][base + i] = qp[r];
         }
     }
+    // the Ritz step after j1 steps (thread 0's scalars of this round are
+    // visible to the workgroup after the barrier)
+    __syncthreads();
+    double* sal = sp;
+    double* sbb = sp + kRitzMaxSteps;
+    for (int i = tid; i < j1; i += kRoundThreads) {
+        sal[i] = it.al[(size_t)i * m + v];
+        sbb[i] = it.b2[(size_t)i * m + v];
+    }
+    __syncthreads();
+    rows_ritz_view(it, v, j1, tol, sal, sbb, sp + 2 * kRitzMaxSteps, sp + 3 * kRitzMaxSteps,
+                   reinterpret_cast<int*>(red8));
 }
 
 // b / d for the Sturm recurrence: the reciprocal instruction refined by one
@@ -703,7 +725,9 @@ __device__ __forceinline__ double sturm_quot(double b, double d) {
 // (257x per round), until its width is 1e-12 of its magnitude -- far below
 // the 1e-7 change that stops a chain.  The two sections' sequences are
 // interleaved in one loop, so their dependent chains overlap.  th1 is NaN for
-// k = 1.  Every thread of the workgroup calls it and gets the same results.
+// k = 1.  Every thread of the workgroup calls it and gets the same results; a
+// workgroup of more than kRitzWaves waves gives the same results too (its
+// further waves only join the barriers).
 constexpr int kRitzWaves = 4, kRitzThreads = 64 * kRitzWaves, kRitzShifts = kRitzThreads;
 
 __device__ void rows_tridiag_max2(const double* __restrict__ al, const double* __restrict__ bb, int k,
@@ -740,7 +764,7 @@ __device__ void rows_tridiag_max2(const double* __restrict__ al, const double* _
         int cnt = 0, cnt1 = 0;
         double d = 1.0, d1 = 1.0;
         // the recurrence scalars of 8 steps are read ahead of their dependent chain
-        for (int i0 = 0; i0 < k; i0 += 8) {
+        for (int i0 = 0; i0 < (wv < kRitzWaves ? k : 0); i0 += 8) {
             double A[8], B[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
@@ -763,7 +787,7 @@ __device__ void rows_tridiag_max2(const double* __restrict__ al, const double* _
         }
         // the first shift (over the workgroup) that lies above every eigenvalue
         const unsigned long long above = __ballot(cnt == k), above1 = __ballot(cnt1 == k1);
-        if (lane == 0) {
+        if (lane == 0 && wv < kRitzWaves) {
             sfirst[wv] = above ? wv * 64 + __ffsll((long long)above) - 1 : kRitzShifts;
             sfirst[kRitzWaves + wv] = above1 ? wv * 64 + __ffsll((long long)above1) - 1 : kRitzShifts;
         }
@@ -828,10 +852,34 @@ __device__ double ritz_residual(const double* __restrict__ sal, const double* __
     return isfinite(r) ? r : HUGE_VAL;
 }
 
-// After `steps` steps: each running view's top Ritz value and that value plus
-// its residual norm (one workgroup of kRitzWaves waves per view); the view
-// stops when the Ritz value changed by <= tol relative over the last step or
-// its Krylov space is exhausted (beta ~ 0).
+// After `steps` steps: a running view's top Ritz value and that value plus
+// its residual norm; the view stops when the Ritz value changed by <= tol
+// relative over the last step or its Krylov space is exhausted (beta ~ 0).
+// sal / sbb hold the view's recurrence scalars (steps of each), sb / sib room
+// for as many; every thread of the workgroup calls it.
+__device__ __forceinline__ void rows_ritz_view(const NormItem& it, int v, int steps, double tol,
+                                               const double* __restrict__ sal, const double* __restrict__ sbb,
+                                               double* __restrict__ sb, double* __restrict__ sib,
+                                               int* __restrict__ sfirst) {
+    for (int i = threadIdx.x; i < steps; i += blockDim.x) {
+        sb[i] = sqrt(fmax(sbb[i], 0.0));
+        sib[i] = 1.0 / sb[i];
+    }
+    __syncthreads();
+    double th, th1;
+    rows_tridiag_max2(sal, sbb, steps, sfirst, &th, &th1);
+    const double bn = sb[steps - 1];
+    bool stop = !(bn > 1e-300 * fmax(1.0, fabs(th))) || !isfinite(th);
+    if (!stop && steps > 1) stop = fabs(th - th1) <= tol * fabs(th);
+    if (threadIdx.x == 0) {
+        it.theta[v] = th;
+        it.ubound[v] = stop ? HUGE_VAL : th + ritz_residual(sal, sb, sib, steps, th, bn);
+        if (stop) it.done[v] = steps;
+    }
+}
+
+// The Ritz step of the per-step form (rows past the round kernel's size):
+// one workgroup of kRitzWaves waves per view.
 __global__ __launch_bounds__(kRitzThreads) void rows_ritz_kernel(const NormItem* __restrict__ items,
                                                                  const RowRef* __restrict__ rows, int nrows,
                                                                  int steps, double tol) {
@@ -846,22 +894,10 @@ __global__ __launch_bounds__(kRitzThreads) void rows_ritz_kernel(const NormItem*
     // the view's recurrence scalars into LDS (strided by m in HBM; read once)
     for (int i = threadIdx.x; i < steps; i += kRitzThreads) {
         sal[i] = it.al[(size_t)i * m + v];
-        const double b2 = it.b2[(size_t)i * m + v];
-        sbb[i] = b2;
-        sb[i] = sqrt(fmax(b2, 0.0));
-        sib[i] = 1.0 / sb[i];
+        sbb[i] = it.b2[(size_t)i * m + v];
     }
     __syncthreads();
-    double th, th1;
-    rows_tridiag_max2(sal, sbb, steps, sfirst, &th, &th1);
-    const double bn = sb[steps - 1];
-    bool stop = !(bn > 1e-300 * fmax(1.0, fabs(th))) || !isfinite(th);
-    if (!stop && steps > 1) stop = fabs(th - th1) <= tol * fabs(th);
-    if (threadIdx.x == 0) {
-        it.theta[v] = th;
-        it.ubound[v] = stop ? HUGE_VAL : th + ritz_residual(sal, sb, sib, steps, th, bn);
-        if (stop) it.done[v] = steps;
-    }
+    rows_ritz_view(it, v, steps, tol, sal, sbb, sb, sib, sfirst);
 }
 
 // one workgroup per problem: {max theta, running views, max steps}, after
@@ -937,11 +973,14 @@ bool rows_round_fits(int max_nb) {
     return max_nb <= kRoundMaxBins && round_lds_doubles(max_nb) * sizeof(double) <= 65536;
 }
 
-hipError_t launch_rows_round(const NormItem* it, const RowRef* rows, int nrows, int j0, int j1, int max_nb,
-                             hipStream_t s) {
+hipError_t launch_rows_round(const NormItem* it, const RowRef* rows, int nrows, int count, int j0, int j1,
+                             int max_nb, double tol, hipStream_t s) {
     if (!rows_round_fits(max_nb)) return hipErrorInvalidValue;
     rows_round_kernel<<<nrows, kRoundThreads, round_lds_doubles(max_nb) * sizeof(double), s>>>(it, rows, nrows, j0,
-                                                                                                j1);
+                                                                                                j1, tol);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    rows_summary_kernel<<<count, 256, 0, s>>>(it, j1);
     return hipGetLastError();
 }
 
