@@ -654,7 +654,7 @@ def main() -> int:
                             "frac": d_tflops / PEAK_FILTER_TFLOPS, "traffic": read_traffic("filter"),
                             "work_per_launch": f"dense Toeplitz contraction 2 x {m} x {nb} x {nb} FP32 FLOP",
                             "peak_note": f"each FP32 product is {FILTER_TERM_PRODUCTS} bf16 term products "
-                                         f"(exact three-term splits, FP32 accumulation): bf16 dense "
+                                         f"(three-term bf16 splits, FP32 accumulation): bf16 dense "
                                          f"{PEAK_BF16_MFMA_TFLOPS:.0f} / {FILTER_TERM_PRODUCTS}; the FP32 MFMA "
                                          f"peak is {PEAK_FP32_MFMA_TFLOPS}"},
         "roofline_tv": {"kernel": "tv_prox_kernel (10 dual steps fused, one launch per ctpd_tv_prox)",

@@ -203,16 +203,20 @@ __device__ __forceinline__ void filter_load_chunk(const FilterArgs& a, size_t ro
     }
 }
 
-// FP32 on the bf16 matrix cores.  Every operand x is split exactly into
-// three bf16 terms, x = x1 + x2 + x3 + e with |e| <= 2^-27 |x| (x1 = bf16(x),
-// x2 = bf16(x - x1), x3 = bf16(x - x1 - x2); both differences are exact in
-// FP32), and a product s h is formed from the six term products whose order
-// is at most 2^-16 of it (s1 h1, s1 h2, s2 h1, s1 h3, s3 h1, s2 h2); the
-// dropped ones are below 2^-23 of it.  A bf16 term product is exact in FP32
-// and the matrix core accumulates in FP32, so the contraction carries the
-// FP32 error of the products' accumulation, as with FP32 matrix instructions,
-// at 6 v_mfma_f32_16x16x32_bf16 (16 cycles each) per 32 x 16 x 16 block
-// instead of 8 v_mfma_f32_16x16x4_f32 (32 cycles each).
+// FP32 on the bf16 matrix cores.  Every operand x is split into three bf16
+// terms, x = x1 + x2 + x3 + e (x1 = bf16(x), x2 = bf16(x - x1),
+// x3 = bf16(x - x1 - x2), rounded to nearest; both differences are exact in
+// FP32): each rounding loses at most 2^-8 of what it rounds, so |x2| <= 2^-8
+// |x|, |x3| <= 2^-16 |x| and |e| <= 2^-24 |x|.  A product s h is formed from
+// the six term products of order 2^-16 of it or more (s1 h1, s1 h2, s2 h1,
+// s1 h3, s3 h1, s2 h2); the dropped ones are at most 2^-23 of it together,
+// so a product errs by at most about 2^-22 relative, a few times the FP32
+// rounding of one product.  A bf16 term product is exact in FP32 and the
+// matrix core accumulates in FP32, so beyond that the contraction carries the
+// rounding of an FP32 accumulation, as with FP32 matrix instructions (the
+// accumulation's rounding dominates the error measured against float64), at
+// 6 v_mfma_f32_16x16x32_bf16 (16 cycles each) per 32 x 16 x 16 block instead
+// of 8 v_mfma_f32_16x16x4_f32 (32 cycles each).
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
