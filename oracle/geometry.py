@@ -1,5 +1,6 @@
-"""Parallel-beam geometry (Sec. 2.1: standard parallel-beam geometry, data as
-uniform samples of p(r, theta); Eq. 24 counts m views over [0, pi)).
+"""Parallel-beam geometry (Sec. 2.1: standard parallel-beam geometry, the
+sinogram sampling p(r, theta) on a regular grid; Eq. 24 counts m views over
+[0, pi)).
 
 Readings (the paper fixes none of these): unit pixels and unit detector
 spacing, grids centred on the rotation axis, theta_v = v*pi/m unless view

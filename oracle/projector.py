@@ -1,7 +1,7 @@
 """Forward projector A and its transpose (Sec. 2.1, the system matrix A = {a_ij}).
 
-The paper only states that b holds uniform samples of parallel-beam line
-integrals.  This oracle reads A as Joseph's ray-driven model:
+The paper only states that b samples the parallel-beam line integrals on a
+regular grid.  This oracle reads A as Joseph's ray-driven model:
 
 * a view whose rays are closer to vertical (|cos theta| >= |sin theta|) steps
   over the N image rows; at row centre y the ray ``x cos + y sin = r`` crosses
