@@ -612,7 +612,9 @@ int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, cons
     // up to 1024 bins a round is one launch (the view's product and recurrence
     // in one workgroup); beyond, a batched FP64 MFMA filter and a step kernel per step
     const bool fused = rows_round_fits(max_nb);
-    constexpr int kRound = 8;
+    // the first round takes 16 steps (by then the residual bounds stop every
+    // view but those near the top), the later ones 8
+    constexpr int kRound = 8, kFirstRound = 16;
     // a chain stops when its top Ritz value moved by <= 1e-7 relative over the
     // last step: then it is within ~1e-8 of the view's eigenvalue (the Ritz
     // values converge geometrically), far inside what sigma = rho 2 / lambda_h
@@ -639,7 +641,7 @@ int lambda_h_views(const std::vector<ctpd_op*>& ops, const float* const* w, cons
     // Rounds are queued one ahead: round r + 1 runs while the host reads round
     // r's summary.  It sees the stops that summary made, so when no chain was
     // left running it does nothing and its summary repeats round r's.
-    int j = std::min(kmax, kRound), slot = 0, r;
+    int j = std::min(kmax, kFirstRound), slot = 0, r;
     if ((r = enqueue(0, j, 0))) return r;
     // the side work is queued after the first round, so that the round is
     // dispatched first and keeps its compute units
