@@ -730,19 +730,20 @@ __device__ __forceinline__ double sturm_quot(double b, double d) {
 // further waves only join the barriers).
 constexpr int kRitzWaves = 4, kRitzThreads = 64 * kRitzWaves, kRitzShifts = kRitzThreads;
 
-__device__ void rows_tridiag_max2(const double* __restrict__ al, const double* __restrict__ bb, int k,
-                                  int* __restrict__ sfirst, double* th, double* th1) {
-    // al[i]: alpha_i; bb[i]: beta_{i+1}^2 (couples i and i+1); both in LDS
+__device__ void rows_tridiag_max2(const double* __restrict__ al, const double* __restrict__ bb,
+                                  const double* __restrict__ sb, int k, int* __restrict__ sfirst, double* th,
+                                  double* th1) {
+    // al[i]: alpha_i; bb[i]: beta_{i+1}^2 (couples i and i+1); sb[i] = sqrt(bb[i]); all in LDS
     const int k1 = k - 1;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     double lo = al[0], hi = al[0], lo1 = al[0], hi1 = al[0];
     for (int i = 0; i < k; ++i) {
-        const double left = i > 0 ? sqrt(bb[i - 1]) : 0.0;
-        const double r = left + (i < k - 1 ? sqrt(bb[i]) : 0.0);
+        const double left = i > 0 ? sb[i - 1] : 0.0;
+        const double r = left + (i < k - 1 ? sb[i] : 0.0);
         lo = fmin(lo, al[i] - r);
         hi = fmax(hi, al[i] + r);
         if (i < k1) {
-            const double r1 = left + (i < k1 - 1 ? sqrt(bb[i]) : 0.0);
+            const double r1 = left + (i < k1 - 1 ? sb[i] : 0.0);
             lo1 = fmin(lo1, al[i] - r1);
             hi1 = fmax(hi1, al[i] + r1);
         }
@@ -867,7 +868,7 @@ __device__ __forceinline__ void rows_ritz_view(const NormItem& it, int v, int st
     }
     __syncthreads();
     double th, th1;
-    rows_tridiag_max2(sal, sbb, steps, sfirst, &th, &th1);
+    rows_tridiag_max2(sal, sbb, sb, steps, sfirst, &th, &th1);
     const double bn = sb[steps - 1];
     bool stop = !(bn > 1e-300 * fmax(1.0, fabs(th))) || !isfinite(th);
     if (!stop && steps > 1) stop = fabs(th - th1) <= tol * fabs(th);
